@@ -1,0 +1,88 @@
+"""Seeded synthetic workloads (plain data; none of the method's arithmetic lives here).
+
+Each preset is a plain dict consumed both by the GPU library binding and by the
+test oracle.  The transport and rate data are synthetic air-like stand-ins for the
+BOLSIG+/SIGLO tables the paper uses (which are not available):
+    mu(E) = 0.0372 (E / 1e6 V/m)^-0.25 m^2/(V s),  D = 0.1 m^2/s,
+    alpha(E) = 4.332e5 exp(-1.91e7 / E) 1/m,        eta = 2000 1/m,
+    k_gamma = 0.06 k_alpha (photo-emission, self-consistent presets only),
+    photon absorption length log-uniform in [30 um, 2 mm].
+Random parameters of ensemble presets are drawn here with numpy's generator; they
+are inputs, not part of the method.
+"""
+import copy
+import math
+
+import numpy as np
+
+AIR = dict(mu_a=0.0372, mu_E0=1.0e6, mu_b=-0.25, E_floor=1.0e4, D=0.1,
+           alpha_A=4.332e5, alpha_B=1.91e7, eta=2000.0, kgamma_ratio=0.0,
+           photon_l1=30e-6, photon_l2=2e-3)
+
+# Plain avalanche: 32^3 grid, dx = 10 um, uniform 10 MV/m along z, 1e4 electrons of
+# weight 1 in a Gaussian blob (sigma = 50 um) at the centre, dt = 1 ps, 200 steps,
+# NGP deposit, hybrid KMC for ionization and attachment, seed 1, FP64.
+AVALANCHE_32 = dict(
+    name="avalanche_32", grid=(32, 32, 32), dx=10e-6, field="uniform", E=(0.0, 0.0, 1.0e7),
+    coeffs=dict(AIR), kmc="hybrid", n_ppc=0, n_new=64, seed=1, realization=0,
+    precision="fp64", dt=1e-12, steps=200,
+    seed_kind="gaussian", seed_n0=10000, seed_centre=(160e-6, 160e-6, 160e-6), seed_sigma=50e-6,
+)
+
+# Self-consistent positive streamer: 1 mm plane-plane gap, 256^3 cells, 18 kV on
+# z = L, neutral Gaussian plasma seed (sigma = 40 um, peak 1e20 m^-3) centred
+# 100 um below the anode, semi-implicit Poisson each step, photo-emission at 0.06 x
+# ionization, merge/split to 32 particles per cell, FP32 particle state, dt = 0.5 ps.
+STREAMER_256 = dict(
+    name="streamer_256", grid=(256, 256, 256), dx=1e-3 / 256, field="poisson", V_anode=18e3,
+    coeffs=dict(AIR, kgamma_ratio=0.06), kmc="hybrid", n_ppc=32, n_new=64, seed=1,
+    realization=0, precision="fp32", dt=0.5e-12, steps=4000, max_particles=50_000_000,
+    seed_kind="neutral", seed_peak=1e20, seed_centre=(0.5e-3, 0.5e-3, 0.9e-3), seed_sigma=40e-6,
+    gmg_rtol=1e-10,
+)
+
+# The same gap at 64^3 (dx = 15.6 um), 200 steps: precision study size.
+STREAMER_64 = dict(STREAMER_256, name="streamer_64", grid=(64, 64, 64), dx=1e-3 / 64,
+                   steps=200, max_particles=4_000_000)
+
+
+def preset(name, **overrides):
+    base = {"avalanche_32": AVALANCHE_32, "streamer_256": STREAMER_256,
+            "streamer_64": STREAMER_64}[name]
+    cfg = copy.deepcopy(base)
+    for k, v in overrides.items():
+        if k == "coeffs":
+            cfg["coeffs"].update(v)
+        else:
+            cfg[k] = v
+    return cfg
+
+
+def ensemble_realizations(n=256, seed=1):
+    """Batched-avalanche realizations: grid edge uniform in {32, 48, 64, 96} (dx = 5 um),
+    initial electrons log-uniform in [1e3, 1e5], uniform field log-uniform in
+    [3, 12] MV/m, 500 steps of 1 ps or until 1e6 particles, FP32 state."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n):
+        edge = int(rng.choice([32, 48, 64, 96]))
+        n0 = int(round(10 ** rng.uniform(3, 5)))
+        E = float(10 ** rng.uniform(math.log10(3e6), math.log10(1.2e7)))
+        L = edge * 5e-6
+        out.append(dict(
+            name=f"ens_{r}", grid=(edge, edge, edge), dx=5e-6, field="uniform", E=(0.0, 0.0, E),
+            coeffs=dict(AIR), kmc="hybrid", n_ppc=0, n_new=64, seed=seed, realization=r,
+            precision="fp32", dt=1e-12, steps=500, max_particles=1_000_000,
+            seed_kind="gaussian", seed_n0=n0, seed_centre=(L / 2, L / 2, L / 2),
+            seed_sigma=0.156 * L))
+    return out
+
+
+def random_particles(rng, grid, n, wmax=1, id_base=0):
+    """Uniform random particles in grid units with integer weights in [1, wmax] and
+    distinct ids (for unit-level parity tests)."""
+    g = np.asarray(grid, dtype=np.float64)
+    xi = rng.random((n, 3)) * g
+    w = rng.integers(1, wmax + 1, size=n).astype(np.uint64)
+    ids = (np.uint64(id_base) + rng.permutation(np.arange(n, dtype=np.uint64) * np.uint64(7) + np.uint64(3)))
+    return xi, w, ids

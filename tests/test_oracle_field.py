@@ -1,0 +1,75 @@
+"""Pins of the oracle's field solve: the vacuum gap (linear potential, uniform field
+V/L), second-order convergence to a manufactured solution that satisfies the
+Dirichlet/Neumann boundary conditions, scaling by a constant coefficient, and the
+exact two-layer dielectric solution (pins the harmonic-mean face coefficient)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2307_01797_amd import workloads
+
+EPS0 = 8.8541878128e-12
+
+
+def _cfg(n, V=1000.0, nxy=None):
+    nxy = nxy or n
+    return workloads.preset("streamer_64", grid=(nxy, nxy, n), dx=1e-3 / n, V_anode=V)
+
+
+def test_vacuum_gap_linear(orc):
+    cfg = _cfg(16)
+    n = 16**3
+    phi, it, rr = orc.solve_poisson(cfg, np.zeros(n), np.ones(n))
+    assert rr < 1e-12
+    k = np.arange(16)
+    exact = 1000.0 * (k + 0.5) / 16
+    assert np.allclose(phi.reshape(16, 16, 16), exact[:, None, None], rtol=1e-10, atol=1e-9)
+    Ex, Ey, Ez = orc.efield(cfg, phi)
+    assert np.allclose(Ez, -1000.0 / 1e-3, rtol=1e-9)
+    assert np.allclose(Ex, 0, atol=1e-3) and np.allclose(Ey, 0, atol=1e-3)
+
+
+def _manufactured(orc, n):
+    L, V, A = 1e-3, 500.0, 200.0
+    cfg = _cfg(n, V)
+    h = L / n
+    c = (np.arange(n) + 0.5) * h
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    kx, ky, kz = math.pi / L, 2 * math.pi / L, math.pi / L
+    phi_e = V * z / L + A * np.sin(kz * z) * np.cos(kx * x) * np.cos(ky * y)
+    lap = -A * (kx**2 + ky**2 + kz**2) * np.sin(kz * z) * np.cos(kx * x) * np.cos(ky * y)
+    rho = -EPS0 * lap
+    phi, it, rr = orc.solve_poisson(cfg, rho.ravel(), np.ones(n**3))
+    return np.abs(phi - phi_e.ravel()).max()
+
+
+def test_manufactured_second_order(orc):
+    e8, e16 = _manufactured(orc, 8), _manufactured(orc, 16)
+    assert 3.3 < e8 / e16 < 4.8  # O(dx^2)
+    assert e16 < 2.0
+
+
+def test_constant_coefficient_scaling(orc):
+    cfg = _cfg(12, V=0.0)
+    rng = np.random.default_rng(1)
+    rho = rng.standard_normal(12**3) * 1e-3
+    p1, _, _ = orc.solve_poisson(cfg, rho, np.ones(12**3))
+    p3, _, _ = orc.solve_poisson(cfg, rho, 3.0 * np.ones(12**3))
+    assert np.allclose(p3, p1 / 3.0, rtol=1e-9, atol=1e-12 * np.abs(p1).max())
+
+
+def test_two_layer_dielectric(orc):
+    """eps = 1 in the lower half, 4 in the upper half, no charge: the flux eps E is
+    continuous, so E_low = 4 E_high and E_low L/2 + E_high L/2 = V."""
+    n, V, L = 16, 1000.0, 1e-3
+    cfg = _cfg(n, V, nxy=4)
+    eps = np.ones((n, 4, 4))
+    eps[n // 2:] = 4.0
+    phi, _, rr = orc.solve_poisson(cfg, np.zeros(n * 16), eps.ravel())
+    Eh = V / (L / 2 * 4 + L / 2)
+    El = 4 * Eh
+    h = L / n
+    z = (np.arange(n) + 0.5) * h
+    exact = np.where(z < L / 2, El * z, El * L / 2 + Eh * (z - L / 2))
+    assert np.allclose(phi.reshape(n, 4, 4)[:, 0, 0], exact, rtol=1e-9)
