@@ -1,0 +1,159 @@
+"""Benchmark: particle-steps per second of the Ito-KMC step on one MI355X.
+
+A step is one pass of the whole path (push with fused NGP binning, photon transport,
+counting sort by cell, per-cell KMC, coupling, and in the self-consistent workload the
+charge deposit and field solve) over the resident particles.  Inputs are seeded and
+synthetic and resident in HBM before the timed region starts.
+
+Prints one JSON line.  `roofline` reports the dominant kernel's algorithmic bytes per
+launch over its average launch time (HIP events recorded by the library on its own
+stream during the timed steps) against the 8 TB/s HBM peak.  `cpu_baseline` times
+the FP64 oracle on a bounded sample of the same workload on one host core.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per live particle of each particle kernel (single-precision state):
+#   push: read cell 4 + offsets 12 + id 8 + weight 4, write cell 4 + offsets 12 + rank 4
+#   scatter: read cell 4 + rank 4 + offsets 12 + weight 4 + id 8, write 28
+BYTES_PER_PARTICLE = {"push": 48, "scatter": 60}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="avalanche_256")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def traffic_from_profile(kernel_file):
+    """Measured HBM bytes per launch of the dominant kernel, if a counter summary for
+    the current source of that kernel is committed; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2307_01797_amd", "csrc", kernel_file)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    try:
+        t = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if t.get("source_sha256") != h:
+            return None
+        return t.get("bytes_per_particle")
+    except Exception:
+        return None
+
+
+def cpu_baseline(cfg, budget_s):
+    """Oracle (plain FP64, single thread) on a bounded sample of the workload: the same
+    grid and physics with fewer seed electrons, stepped until the time budget."""
+    import oracle
+    scale = 200_000
+    sub = dict(cfg)
+    sample = ""
+    o = oracle.Sim(sub)
+    if cfg.get("seed_kind") == "gaussian":
+        n0 = min(cfg["seed_n0"], scale)
+        o.seed_gaussian(n0, cfg["seed_centre"], cfg["seed_sigma"])
+        sample = f"{n0} seed electrons (of {cfg['seed_n0']}) on the full grid"
+    else:
+        o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+        sample = "full seed"
+    psteps = 0
+    t0 = time.perf_counter()
+    nsteps = 0
+    while time.perf_counter() - t0 < budget_s and nsteps < 50:
+        psteps += o.diagnostics()["n_particles"]
+        o.step(cfg["dt"], 1)
+        nsteps += 1
+    el = time.perf_counter() - t0
+    return {"value": psteps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}, {nsteps} steps, {psteps} particle-steps in {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: this benchmark runs on exactly one GPU; "
+                                   "--gpus above 1 is not supported"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2307_01797_amd import itokmc, workloads
+
+    cfg = workloads.preset(args.workload)
+    dev = torch.device("cuda:0")
+    sim = itokmc.Sim(cfg, device=dev)
+    sim.seed()
+    sim.step(args.warmup)
+    torch.cuda.synchronize(dev)
+    d0 = sim.diagnostics()
+    sim.set_profiling(True)
+    sim.phase_times(reset=True)
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    ev0.record(stream)
+    rc = sim.step_rc(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
+    ms = ev0.elapsed_time(ev1)
+    phases = sim.phase_times(reset=True)
+    sim.set_profiling(False)
+    d1 = sim.diagnostics(check=False)
+    psteps = d1["particle_steps"] - d0["particle_steps"]
+    value = psteps / (ms / 1e3)
+
+    # dominant kernel and its roofline
+    dom = max(phases, key=lambda p: phases[p][0])
+    tot_ms, launches = phases[dom]
+    roof = None
+    if dom in BYTES_PER_PARTICLE and launches:
+        per_launch_bytes = BYTES_PER_PARTICLE[dom] * psteps / launches
+        avg_s = tot_ms / launches / 1e3
+        achieved = per_launch_bytes / avg_s / 1e9
+        tb = traffic_from_profile("particles.hip")
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (tb * psteps / launches) if tb else None,
+                "kernel": dom, "avg_launch_ms": round(tot_ms / launches, 4),
+                "bytes_per_launch": int(per_launch_bytes)}
+    out = {
+        "metric": "particle-steps/s (push+sort+deposit+KMC)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if cfg.get("precision") == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": list(cfg["grid"]), "dx_m": cfg["dx"],
+                   "particles_start": d0["n_particles"], "particles_end": d1["n_particles"],
+                   "weight_end": d1["weight"], "field": cfg.get("field"),
+                   "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": rc},
+        "phase_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

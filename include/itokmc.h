@@ -1,0 +1,202 @@
+/*
+ * itokmc -- MI355X (gfx950) library for one time step of the Ito-KMC particle-mesh
+ * method of Marskar, "Stochastic and self-consistent 3D modeling of streamer
+ * discharge trees with Kinetic Monte Carlo": the Ito drift-diffusion push of
+ * computational electrons (eq. ito_kernel), field interpolation and NGP/CIC
+ * deposition (section "Charge deposition & interpolation"), binning of particles by
+ * cell, per-cell Kinetic Monte Carlo (section "Kinetic Monte Carlo" and its
+ * "Reaction algorithm outline"), the KMC-particle coupling of eq. w, photon
+ * transport (eq. photon_transport), superparticle merge/split (section
+ * "Superparticle management", eq. weight_median) and the semi-implicit field solve
+ * (eqs. poisson_simp and conductivity) on a uniform Cartesian grid with planar
+ * electrodes at z = 0 (grounded) and z = L, in the step order of the paper's "Final
+ * algorithm".
+ *
+ * Conventions for every entry point:
+ *   - Return value: ITOKMC_OK (0) or a negative ITOKMC_E* code; nothing throws or
+ *     aborts across this boundary.  itokmc_last_error() gives a message.
+ *   - Device work is enqueued on the stream given to itokmc_init_grid (a hipStream_t
+ *     passed as void*).  Calls that return host data synchronise that stream.
+ *   - Memory: the caller allocates one device arena of itokmc_arena_bytes() bytes
+ *     and keeps it alive until itokmc_destroy; the library sub-allocates all device
+ *     buffers from it and never allocates device memory itself.  Host pointers are
+ *     only read or written during the call.
+ *   - Units are SI: m, s, V, V/m, m^-3.  Positions cross the boundary as cell index
+ *     plus cell-relative offset in [0,1) per axis.
+ *   - A context is not thread-safe; use one context per stream.
+ *   - Cells are numbered c = i + nx (j + ny k); at most 2^24 cells.
+ */
+#ifndef ITOKMC_H
+#define ITOKMC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ITOKMC_OK = 0,
+  ITOKMC_EINVAL = -1,    /* invalid argument or descriptor                     */
+  ITOKMC_ENOMEM = -2,    /* arena too small                                     */
+  ITOKMC_ECAPACITY = -3, /* particle capacity exceeded; state stays valid      */
+  ITOKMC_ENOCONV = -4,   /* field solve did not reach its tolerance            */
+  ITOKMC_EHIP = -5       /* a HIP runtime call failed                           */
+};
+enum { ITOKMC_FP32 = 0, ITOKMC_FP64 = 1 };
+enum { ITOKMC_FIELD_UNIFORM = 0, ITOKMC_FIELD_POISSON = 1 };
+enum { ITOKMC_KMC_HYBRID = 0, ITOKMC_KMC_PURE_TAU = 1 };
+enum { ITOKMC_SEED_GAUSSIAN = 0, ITOKMC_SEED_NEUTRAL = 1 };
+/* itokmc_deposit / counts selectors */
+enum {
+  ITOKMC_Q_NGP_WEIGHT = 0, /* uint32 per cell: sum of electron weights (NGP)          */
+  ITOKMC_Q_NPLUS = 1,      /* uint32 per cell: positive ions                          */
+  ITOKMC_Q_NMINUS = 2,     /* uint32 per cell: negative ions                          */
+  ITOKMC_Q_NGAMMA = 3,     /* uint32 per cell: photons pending transport              */
+  ITOKMC_Q_CIC_DENSITY = 4,/* double per cell: electron density (m^-3), CIC           */
+  ITOKMC_Q_PHI = 5,        /* double per cell: potential (V), field mode POISSON      */
+  ITOKMC_Q_EX = 6, ITOKMC_Q_EY = 7, ITOKMC_Q_EZ = 8, /* double per cell: E (V/m)     */
+  ITOKMC_Q_FIRES = 9       /* uint32 per cell x 3: reaction fires of the last step    */
+};
+
+typedef struct itokmc_ctx itokmc_ctx;
+
+/* Grid and method parameters (section "Computer implementation"; defaults are the
+ * paper's: n_new = 64 (section "KMC-particle coupling"), kmc_nc = 5, kmc_nssa = 10,
+ * kmc_eps = +inf (section "Final algorithm"), gmg_rtol = 1e-10). */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t precision;       /* ITOKMC_FP32: single-precision offsets and push,
+                              ITOKMC_FP64: double everywhere                         */
+  double dx;               /* cell edge (m)                                          */
+  int32_t field_mode;      /* ITOKMC_FIELD_UNIFORM | ITOKMC_FIELD_POISSON            */
+  int32_t kmc_mode;        /* ITOKMC_KMC_HYBRID | ITOKMC_KMC_PURE_TAU                */
+  double E_uniform[3];     /* prescribed field (V/m), uniform mode                   */
+  double V_anode;          /* potential of z = L (V), Poisson mode                   */
+  int32_t n_ppc;           /* superparticle target per cell; 0 = no merge/split      */
+  int32_t n_new;           /* max computational particles made per cell and step     */
+  int32_t kmc_nc;          /* critical-reaction threshold N_c                        */
+  int32_t kmc_nssa;        /* max SSA events per SSA excursion                        */
+  double kmc_eps;          /* leap accuracy factor; INFINITY accepts any leap        */
+  uint32_t seed, realization; /* key of every random stream                          */
+  uint64_t max_particles;  /* particle capacity (per bank)                           */
+  int32_t gmg_max_cycles;  /* max multigrid cycles per solve                          */
+  int32_t pad0;
+  double gmg_rtol;         /* relative residual target of the field solve            */
+} itokmc_grid_desc;
+
+/* Transport and rate coefficients as functions of |E| (local field approximation,
+ * section "Particle transport"): mu(E) = mu_a (max(E,E_floor)/mu_E0)^mu_b, constant
+ * D, alpha(E) = alpha_A exp(-alpha_B/E), eta constant; k_alpha = alpha mu E,
+ * k_eta = eta mu E, k_gamma = kgamma_ratio k_alpha; photon mean absorption length
+ * log-uniform in [photon_l1, photon_l2]. */
+typedef struct {
+  double mu_a, mu_E0, mu_b, E_floor, D, alpha_A, alpha_B, eta, kgamma_ratio;
+  double photon_l1, photon_l2;
+} itokmc_coeffs;
+
+/* Initial particles.  GAUSSIAN: n0 electrons of weight 1 at centre + sigma N(0,1)^3,
+ * draws outside the domain discarded.  NEUTRAL: per cell Poisson(n_peak
+ * exp(-r^2/2 sigma^2) dV) electron-ion pairs, electrons made by the coupling rule. */
+typedef struct {
+  int32_t kind;
+  int32_t pad0;
+  uint64_t n0;
+  double centre[3];
+  double sigma;
+  double n_peak;
+} itokmc_seed_desc;
+
+typedef struct {
+  uint64_t n_particles, weight;
+  int64_t n_plus, n_minus;
+  int64_t charge;                 /* sum(n+ - n_e - n-), units of e                  */
+  uint64_t outflow_weight;
+  uint64_t fires[3];              /* cumulative: ionization, attachment, emission    */
+  uint64_t photons_emitted, photons_absorbed, photons_lost;
+  uint64_t created, removed_weight, merged_cells;
+  uint32_t step;
+  int32_t solver_cycles;          /* last field solve                                 */
+  double solver_relres;
+  double rho_sum;                 /* FP64 sum of rho dV over the grid (C)             */
+  uint32_t overflow;              /* nonzero if a capacity limit was hit             */
+  uint32_t pad0;
+  uint64_t particle_steps;        /* cumulative live particles advanced by transport */
+} itokmc_diag;
+
+/* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid). */
+size_t itokmc_arena_bytes(const itokmc_grid_desc* desc);
+
+/* Create a context.  arena: device pointer of at least itokmc_arena_bytes(desc)
+ * bytes, 256-byte aligned, owned by the caller.  stream: hipStream_t (may be NULL).
+ * Errors: EINVAL (bad descriptor), ENOMEM (arena too small), EHIP. */
+int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena,
+                     size_t arena_bytes, void* stream);
+
+/* Set the coefficient set (copied).  EINVAL on NaN or negative D/mobility. */
+int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* coeffs);
+
+/* Seed particles (appends to the current state; step counter unchanged). */
+int itokmc_seed_particles(itokmc_ctx* ctx, const itokmc_seed_desc* seed);
+
+/* Advance nsteps full steps of length dt (final algorithm, steps 1-8).  Returns
+ * ECAPACITY if a buffer overflowed during the steps (state remains consistent but
+ * incomplete), ENOCONV if a field solve missed its tolerance. */
+int itokmc_step(itokmc_ctx* ctx, uint32_t nsteps, double dt);
+
+/* The two halves of one step: transport (steps 1-5 and removal at the faces) and
+ * react (steps 6-8, then the step counter advances).  step == transport + react. */
+int itokmc_transport(itokmc_ctx* ctx, double dt);
+int itokmc_react(itokmc_ctx* ctx, double dt);
+
+/* Write a per-cell quantity (selector ITOKMC_Q_*) to the device buffer dev_out of
+ * ncell (x3 for FIRES) elements of the stated type.  NGP weights and CIC density are
+ * computed from the current particles. */
+int itokmc_deposit(itokmc_ctx* ctx, int what, void* dev_out);
+
+/* Reductions and tallies; synchronises the stream. */
+int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* host_out);
+
+/* Particle state exchange with host memory (checkpoint, parity resynchronisation).
+ * get: *n receives the count; arrays (each may be NULL) must hold n entries
+ * (offsets: 3 n doubles, x y z interleaved).  Call with all arrays NULL to query n.
+ * set: replaces all particles; w must be >= 1, offsets in [0,1), cells valid. */
+int itokmc_get_particles(itokmc_ctx* ctx, uint64_t* n, uint32_t* cell, double* off,
+                         uint32_t* w, uint64_t* id);
+int itokmc_set_particles(itokmc_ctx* ctx, uint64_t n, const uint32_t* cell,
+                         const double* off, const uint32_t* w, const uint64_t* id);
+/* Per-cell counts (which = ITOKMC_Q_NPLUS, NMINUS or NGAMMA), host uint32 arrays. */
+int itokmc_get_counts(itokmc_ctx* ctx, int which, uint32_t* host);
+int itokmc_set_counts(itokmc_ctx* ctx, int which, const uint32_t* host);
+int itokmc_set_step(itokmc_ctx* ctx, uint32_t step);
+/* Potential (host doubles, ncell); set_field also recomputes E. Poisson mode only. */
+int itokmc_get_field(itokmc_ctx* ctx, double* phi);
+int itokmc_set_field(itokmc_ctx* ctx, const double* phi);
+
+/* Per-phase timing with HIP events recorded around each kernel phase on the
+ * context's stream (off by default).  Phases: 0 push, 1 photons, 2 bin scan,
+ * 3 scatter, 4 KMC, 5 coupling/merge, 6 charge deposit, 7 field solve, 8 field push,
+ * 9 recount.  phase_times synchronises, writes accumulated milliseconds and launch
+ * counts for the first n phases, and clears them if reset is nonzero. */
+int itokmc_set_profiling(itokmc_ctx* ctx, int on);
+int itokmc_phase_times(itokmc_ctx* ctx, double* ms, uint64_t* calls, int n, int reset);
+
+void itokmc_destroy(itokmc_ctx* ctx);
+const char* itokmc_last_error(const itokmc_ctx* ctx);
+
+/* ---- kernel-level entry points (device pointers; used for unit parity) ----------
+ * Philox4x32-10 (Salmon et al. 2011) blocks for counters (c0 + i, c1, c2, c3),
+ * i < n, key (k0, k1): out is 4 n uint32. */
+int itokmc_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                       uint32_t k1, uint64_t n, uint32_t* dev_out, void* stream);
+/* One KMC step on n independent cells with the context's method parameters:
+ * X (n x 4 int64: e, M+, M-, gamma; in/out), k (n x 3 double rates, 1/s), cell ids
+ * (n uint32, stream keys), fires (n x 3 int64 out); all device pointers. */
+int itokmc_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* dev_cell_ids,
+                     int64_t* dev_X, const double* dev_k, double dt, uint32_t step,
+                     int64_t* dev_fires);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

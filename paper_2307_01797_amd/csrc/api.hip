@@ -1,0 +1,580 @@
+// C ABI of the itokmc library: context and arena layout, step orchestration,
+// diagnostics and state exchange.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "device.hpp"
+#include "itk.hpp"
+
+namespace itk {
+
+int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int check_hip(itokmc_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return ITOKMC_OK;
+  return set_error(ctx, ITOKMC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static double mobility(const itokmc_coeffs& c, double E) {
+  const double Ec = E > c.E_floor ? E : c.E_floor;
+  return c.mu_a * pow(Ec / c.mu_E0, c.mu_b);
+}
+
+void phase_begin(itokmc_ctx* ctx, int phase) {
+  if (!ctx->profiling) return;
+  hipEvent_t b, e;
+  if (ctx->ev_free.size() >= 2) {
+    b = ctx->ev_free.back(); ctx->ev_free.pop_back();
+    e = ctx->ev_free.back(); ctx->ev_free.pop_back();
+  } else {
+    hipEventCreate(&b);
+    hipEventCreate(&e);
+  }
+  hipEventRecord(b, ctx->s);
+  ctx->ev_used.push_back({phase, {b, e}});
+}
+
+void phase_end(itokmc_ctx* ctx, int phase) {
+  if (!ctx->profiling || ctx->ev_used.empty()) return;
+  auto& last = ctx->ev_used.back();
+  if (last.first != phase) return;
+  hipEventRecord(last.second.second, ctx->s);
+}
+
+static void phase_collect(itokmc_ctx* ctx) {
+  if (ctx->ev_used.empty()) return;
+  hipStreamSynchronize(ctx->s);
+  for (auto& u : ctx->ev_used) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, u.second.first, u.second.second) == hipSuccess) {
+      ctx->phase_ms[u.first] += ms;
+      ctx->phase_calls[u.first] += 1;
+    }
+    ctx->ev_free.push_back(u.second.first);
+    ctx->ev_free.push_back(u.second.second);
+  }
+  ctx->ev_used.clear();
+}
+
+StepConst make_const(const itokmc_ctx* ctx, double dt) {
+  StepConst k{};
+  k.nx = ctx->d.nx; k.ny = ctx->d.ny; k.nz = ctx->d.nz;
+  k.ncell = ctx->ncell;
+  k.cap = (uint32_t)ctx->cap;
+  k.step = ctx->step;
+  k.key = Key{ctx->d.seed, ctx->d.realization};
+  k.dx = ctx->d.dx;
+  k.dt = dt;
+  if (ctx->have_coeffs) {
+    k.diff = sqrt(2.0 * ctx->c.D * dt) / ctx->d.dx;
+    if (ctx->d.field_mode == ITOKMC_FIELD_UNIFORM) {
+      const double* E = ctx->d.E_uniform;
+      const double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+      const double mu = mobility(ctx->c, Em);
+      for (int a = 0; a < 3; ++a) k.drift[a] = (-mu * E[a] * dt) / ctx->d.dx;
+      const double alpha = Em > 0.0 ? ctx->c.alpha_A * exp(-ctx->c.alpha_B / Em) : 0.0;
+      const double v = mu * Em;
+      k.k[0] = alpha * v;
+      k.k[1] = ctx->c.eta * v;
+      k.k[2] = ctx->c.kgamma_ratio * k.k[0];
+    }
+  }
+  return k;
+}
+
+// ---- arena layout ------------------------------------------------------------------
+
+struct Layout {
+  size_t off[32];
+  size_t total;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool valid_desc(const itokmc_grid_desc* d) {
+  if (!d) return false;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
+  const uint64_t nc = (uint64_t)d->nx * d->ny * d->nz;
+  if (nc > (1ull << 24)) return false;
+  if (!(d->dx > 0.0)) return false;
+  if (d->precision != ITOKMC_FP32 && d->precision != ITOKMC_FP64) return false;
+  if (d->field_mode != ITOKMC_FIELD_UNIFORM && d->field_mode != ITOKMC_FIELD_POISSON) return false;
+  if (d->kmc_mode != ITOKMC_KMC_HYBRID && d->kmc_mode != ITOKMC_KMC_PURE_TAU) return false;
+  if (d->n_new < 1 || d->n_new > 64) return false;
+  if (d->n_ppc < 0 || d->n_ppc > 256) return false;
+  if (d->kmc_nc < 0 || d->kmc_nssa < 1) return false;
+  if (!(d->kmc_eps > 0.0)) return false;
+  if (d->max_particles < 1 || d->max_particles > 0x7FFFFFFFull) return false;
+  return true;
+}
+
+// index: 0..1 banks handled separately; per-bank arrays follow
+static void layout(const itokmc_grid_desc* d, Layout* L) {
+  const uint64_t nc = (uint64_t)d->nx * d->ny * d->nz;
+  const uint64_t cap = d->max_particles;
+  const size_t T = d->precision == ITOKMC_FP64 ? 8 : 4;
+  size_t o = 0;
+  int i = 0;
+  auto put = [&](size_t bytes) { L->off[i++] = o; o += al(bytes); };
+  for (int b = 0; b < 2; ++b) {
+    put(cap * 4);      // cell
+    put(cap * T);      // ox
+    put(cap * T);      // oy
+    put(cap * T);      // oz
+    put(cap * 4);      // w
+    put(cap * 8);      // id
+    put(cap * 4);      // rank
+  }
+  put(nc * 8);         // 14 cellacc
+  put((nc + 1) * 4);   // 15 start
+  put(nc * 4);         // 16 occ
+  put(nc * 12);        // 17 occ_fires
+  put(nc * 4);         // 18 nplus
+  put(nc * 4);         // 19 nminus
+  put(nc * 4);         // 20 ngamma
+  put(nc * 4);         // 21 dN
+  put(nc * 4);         // 22 work
+  put(((nc + 2047) / 2048 + 1) * 8);  // 23 blocksums
+  put(sizeof(Counters));              // 24 counters
+  put(64);                            // 25 reduction scratch
+  put(field_bytes(d));                // 26 field data
+  put(nc * 4);                        // 27 cbase
+  L->total = o;
+}
+
+}  // namespace itk
+
+using namespace itk;
+
+extern "C" {
+
+size_t itokmc_arena_bytes(const itokmc_grid_desc* desc) {
+  if (!valid_desc(desc)) return 0;
+  Layout L;
+  layout(desc, &L);
+  return L.total;
+}
+
+int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena,
+                     size_t arena_bytes, void* stream) {
+  if (!out) return ITOKMC_EINVAL;
+  *out = nullptr;
+  if (!valid_desc(desc)) return ITOKMC_EINVAL;
+  Layout L;
+  layout(desc, &L);
+  if (!arena || ((uintptr_t)arena & 255)) return ITOKMC_EINVAL;
+  if (arena_bytes < L.total) return ITOKMC_ENOMEM;
+  itokmc_ctx* ctx = new itokmc_ctx();
+  ctx->d = *desc;
+  ctx->s = (hipStream_t)stream;
+  ctx->arena = (char*)arena;
+  ctx->arena_bytes = arena_bytes;
+  ctx->ncell = (uint32_t)((uint64_t)desc->nx * desc->ny * desc->nz);
+  ctx->cap = desc->max_particles;
+  char* a = ctx->arena;
+  for (int b = 0; b < 2; ++b) {
+    Bank& k = ctx->bank[b];
+    const int o = 7 * b;
+    k.cell = (uint32_t*)(a + L.off[o]);
+    k.ox = a + L.off[o + 1];
+    k.oy = a + L.off[o + 2];
+    k.oz = a + L.off[o + 3];
+    k.w = (uint32_t*)(a + L.off[o + 4]);
+    k.id = (uint64_t*)(a + L.off[o + 5]);
+    k.rank = (uint32_t*)(a + L.off[o + 6]);
+  }
+  ctx->cellacc = (unsigned long long*)(a + L.off[14]);
+  ctx->start = (uint32_t*)(a + L.off[15]);
+  ctx->occ = (uint32_t*)(a + L.off[16]);
+  ctx->occ_fires = (uint32_t*)(a + L.off[17]);
+  ctx->nplus = (uint32_t*)(a + L.off[18]);
+  ctx->nminus = (uint32_t*)(a + L.off[19]);
+  ctx->ngamma = (uint32_t*)(a + L.off[20]);
+  ctx->dN = (int32_t*)(a + L.off[21]);
+  ctx->work = (uint32_t*)(a + L.off[22]);
+  ctx->blocksums = (uint32_t*)(a + L.off[23]);
+  ctx->ctr = (Counters*)(a + L.off[24]);
+  ctx->reduce = (unsigned long long*)(a + L.off[25]);
+  ctx->field = a + L.off[26];
+  ctx->cbase = (uint32_t*)(a + L.off[27]);
+  const size_t nb = ctx->ncell;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->nplus, 0, nb * 4, ctx->s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->nminus, 0, nb * 4, ctx->s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->ngamma, 0, nb * 4, ctx->s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->ctr, 0, sizeof(Counters), ctx->s);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_ctr, sizeof(Counters), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete ctx;
+    return ITOKMC_EHIP;
+  }
+  if (desc->field_mode == ITOKMC_FIELD_POISSON) {
+    const int rc = field_init(ctx, (char*)ctx->field);
+    if (rc != ITOKMC_OK) {
+      hipHostFree(ctx->host_ctr);
+      delete ctx;
+      return rc;
+    }
+  }
+  *out = ctx;
+  return ITOKMC_OK;
+}
+
+int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* c) {
+  if (!ctx || !c) return ITOKMC_EINVAL;
+  const double v[] = {c->mu_a, c->mu_E0, c->mu_b, c->E_floor, c->D, c->alpha_A, c->alpha_B,
+                      c->eta, c->kgamma_ratio, c->photon_l1, c->photon_l2};
+  for (double x : v)
+    if (!isfinite(x)) return set_error(ctx, ITOKMC_EINVAL, "non-finite coefficient");
+  if (c->mu_a < 0 || !(c->mu_E0 > 0) || !(c->E_floor > 0) || c->D < 0 || c->alpha_A < 0 ||
+      c->eta < 0 || c->kgamma_ratio < 0)
+    return set_error(ctx, ITOKMC_EINVAL, "negative transport or rate coefficient");
+  if (c->kgamma_ratio > 0 && !(c->photon_l1 > 0 && c->photon_l2 >= c->photon_l1))
+    return set_error(ctx, ITOKMC_EINVAL, "invalid photon absorption lengths");
+  ctx->c = *c;
+  ctx->have_coeffs = true;
+  return ITOKMC_OK;
+}
+
+static int mark_unbinned(itokmc_ctx* ctx) {
+  // the bin accumulator must be all zero between steps; recount before reacting
+  return check_hip(ctx, hipMemsetAsync(ctx->cellacc, 0, (size_t)ctx->ncell * 8, ctx->s), "memset");
+}
+
+int itokmc_seed_particles(itokmc_ctx* ctx, const itokmc_seed_desc* sd) {
+  if (!ctx || !sd) return ITOKMC_EINVAL;
+  if (!(sd->sigma > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "sigma must be positive");
+  hipError_t e;
+  if (sd->kind == ITOKMC_SEED_GAUSSIAN) e = launch_seed_gaussian(ctx, sd);
+  else if (sd->kind == ITOKMC_SEED_NEUTRAL) e = launch_seed_neutral(ctx, sd);
+  else return set_error(ctx, ITOKMC_EINVAL, "unknown seed kind");
+  int rc = check_hip(ctx, e, "seed");
+  if (rc) return rc;
+  ctx->field_valid = false;
+  return mark_unbinned(ctx);
+}
+
+// ---- step orchestration --------------------------------------------------------------
+
+int itokmc_transport(itokmc_ctx* ctx, double dt) {
+  if (!ctx) return ITOKMC_EINVAL;
+  if (!ctx->have_coeffs) return set_error(ctx, ITOKMC_EINVAL, "coefficients not set");
+  if (!(dt > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "dt must be positive");
+  StepConst k = make_const(ctx, dt);
+  int rc;
+  if (ctx->d.field_mode == ITOKMC_FIELD_UNIFORM) {
+    if (ctx->binned) {
+      // transport twice without react: re-zero the bins first
+      rc = mark_unbinned(ctx);
+      if (rc) return rc;
+    }
+    phase_begin(ctx, PH_PUSH);
+    rc = check_hip(ctx, launch_push_uniform(ctx, k), "push");
+    phase_end(ctx, PH_PUSH);
+  } else {
+    if (ctx->binned) {
+      rc = mark_unbinned(ctx);
+      if (rc) return rc;
+    }
+    rc = field_transport(ctx, k);
+  }
+  if (rc) return rc;
+  ctx->binned = true;
+  return ITOKMC_OK;
+}
+
+int itokmc_react(itokmc_ctx* ctx, double dt) {
+  if (!ctx) return ITOKMC_EINVAL;
+  if (!ctx->have_coeffs) return set_error(ctx, ITOKMC_EINVAL, "coefficients not set");
+  if (!(dt > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "dt must be positive");
+  StepConst k = make_const(ctx, dt);
+  int rc;
+  if (!ctx->binned) {
+    phase_begin(ctx, PH_COUNT);
+    rc = check_hip(ctx, launch_count(ctx), "count");
+    phase_end(ctx, PH_COUNT);
+    if (rc) return rc;
+  }
+  phase_begin(ctx, PH_PHOTON);
+  rc = check_hip(ctx, launch_photons(ctx, k), "photons");
+  phase_end(ctx, PH_PHOTON);
+  phase_begin(ctx, PH_SCAN);
+  if (!rc) rc = check_hip(ctx, launch_scan(ctx), "scan");
+  phase_end(ctx, PH_SCAN);
+  phase_begin(ctx, PH_SCATTER);
+  if (!rc) rc = check_hip(ctx, launch_scatter(ctx), "scatter");
+  phase_end(ctx, PH_SCATTER);
+  const double* rates = ctx->d.field_mode == ITOKMC_FIELD_POISSON ? field_cell_rates(ctx) : nullptr;
+  phase_begin(ctx, PH_KMC);
+  if (!rc) rc = check_hip(ctx, launch_kmc_step(ctx, k, rates), "kmc");
+  phase_end(ctx, PH_KMC);
+  phase_begin(ctx, PH_COUPLE);
+  if (!rc) rc = check_hip(ctx, launch_couple(ctx, k), "couple");
+  phase_end(ctx, PH_COUPLE);
+  if (rc) return rc;
+  ctx->cur = 1 - ctx->cur;
+  ctx->step += 1;
+  ctx->binned = false;
+  return ITOKMC_OK;
+}
+
+int itokmc_step(itokmc_ctx* ctx, uint32_t nsteps, double dt) {
+  if (!ctx) return ITOKMC_EINVAL;
+  for (uint32_t i = 0; i < nsteps; ++i) {
+    int rc = itokmc_transport(ctx, dt);
+    if (rc) return rc;
+    rc = itokmc_react(ctx, dt);
+    if (rc) return rc;
+  }
+  return ITOKMC_OK;
+}
+
+int itokmc_set_step(itokmc_ctx* ctx, uint32_t step) {
+  if (!ctx) return ITOKMC_EINVAL;
+  ctx->step = step;
+  return ITOKMC_OK;
+}
+
+int itokmc_deposit(itokmc_ctx* ctx, int what, void* dev_out) {
+  if (!ctx || !dev_out) return ITOKMC_EINVAL;
+  const size_t nb = ctx->ncell;
+  hipError_t e = hipSuccess;
+  switch (what) {
+    case ITOKMC_Q_NGP_WEIGHT: e = launch_ngp(ctx, (uint32_t*)dev_out); break;
+    case ITOKMC_Q_NPLUS: e = hipMemcpyAsync(dev_out, ctx->nplus, nb * 4, hipMemcpyDeviceToDevice, ctx->s); break;
+    case ITOKMC_Q_NMINUS: e = hipMemcpyAsync(dev_out, ctx->nminus, nb * 4, hipMemcpyDeviceToDevice, ctx->s); break;
+    case ITOKMC_Q_NGAMMA: e = hipMemcpyAsync(dev_out, ctx->ngamma, nb * 4, hipMemcpyDeviceToDevice, ctx->s); break;
+    case ITOKMC_Q_FIRES: e = launch_fires_dense(ctx, (uint32_t*)dev_out); break;
+    case ITOKMC_Q_CIC_DENSITY: e = launch_cic_density(ctx, (double*)dev_out); break;
+    case ITOKMC_Q_PHI: case ITOKMC_Q_EX: case ITOKMC_Q_EY: case ITOKMC_Q_EZ:
+      if (ctx->d.field_mode != ITOKMC_FIELD_POISSON)
+        return set_error(ctx, ITOKMC_EINVAL, "no field in uniform mode");
+      return field_deposit(ctx, what, dev_out);
+    default: return set_error(ctx, ITOKMC_EINVAL, "unknown deposit selector %d", what);
+  }
+  return check_hip(ctx, e, "deposit");
+}
+
+int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
+  if (!ctx || !out) return ITOKMC_EINVAL;
+  unsigned long long* scratch = ctx->reduce;
+  hipError_t e = hipMemsetAsync(scratch, 0, 64, ctx->s);
+  if (e == hipSuccess) e = launch_reduce_particles(ctx, scratch);
+  if (e == hipSuccess) e = launch_reduce_cells(ctx, scratch + 2);
+  unsigned long long host[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(host, scratch, 32, hipMemcpyDeviceToHost, ctx->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->host_ctr, ctx->ctr, sizeof(Counters), hipMemcpyDeviceToHost, ctx->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->s);
+  int rc = check_hip(ctx, e, "diagnostics");
+  if (rc) return rc;
+  const Counters& c = *ctx->host_ctr;
+  memset(out, 0, sizeof(*out));
+  out->n_particles = host[0];
+  out->weight = host[1];
+  out->n_plus = (int64_t)host[2];
+  out->n_minus = (int64_t)host[3];
+  out->charge = (int64_t)host[2] - (int64_t)host[1] - (int64_t)host[3];
+  out->outflow_weight = c.outflow;
+  for (int r = 0; r < 3; ++r) out->fires[r] = c.fires[r];
+  out->photons_emitted = c.ph_emitted;
+  out->photons_absorbed = c.ph_absorbed;
+  out->photons_lost = c.ph_lost;
+  out->created = c.created;
+  out->removed_weight = c.removed;
+  out->merged_cells = c.merged;
+  out->step = ctx->step;
+  out->solver_cycles = ctx->last_cycles;
+  out->solver_relres = ctx->last_relres;
+  out->rho_sum = 1.602176634e-19 * (double)out->charge;
+  out->overflow = c.overflow;
+  out->particle_steps = c.pushed;
+  if (c.overflow) return set_error(ctx, ITOKMC_ECAPACITY, "capacity exceeded (flags %u)", c.overflow);
+  return ITOKMC_OK;
+}
+
+int itokmc_get_particles(itokmc_ctx* ctx, uint64_t* n, uint32_t* cell, double* off, uint32_t* w,
+                         uint64_t* id) {
+  if (!ctx || !n) return ITOKMC_EINVAL;
+  Counters hc;
+  hipError_t e = hipMemcpyAsync(&hc, ctx->ctr, sizeof(Counters), hipMemcpyDeviceToHost, ctx->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->s);
+  int rc = check_hip(ctx, e, "get_particles");
+  if (rc) return rc;
+  const uint32_t N = hc.n[ctx->cur] < ctx->cap ? hc.n[ctx->cur] : (uint32_t)ctx->cap;
+  const Bank& b = ctx->bank[ctx->cur];
+  std::vector<uint32_t> hw(N), hc_(N);
+  std::vector<uint64_t> hid(N);
+  const bool f64 = ctx->d.precision == ITOKMC_FP64;
+  const size_t T = f64 ? 8 : 4;
+  std::vector<char> ho[3];
+  for (int a = 0; a < 3; ++a) ho[a].resize((size_t)N * T);
+  if (N) {
+    e = hipMemcpy(hw.data(), b.w, (size_t)N * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hc_.data(), b.cell, (size_t)N * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hid.data(), b.id, (size_t)N * 8, hipMemcpyDeviceToHost);
+    void* src[3] = {b.ox, b.oy, b.oz};
+    for (int a = 0; a < 3 && e == hipSuccess; ++a)
+      e = hipMemcpy(ho[a].data(), src[a], (size_t)N * T, hipMemcpyDeviceToHost);
+    rc = check_hip(ctx, e, "get_particles copy");
+    if (rc) return rc;
+  }
+  uint64_t live = 0;
+  for (uint32_t i = 0; i < N; ++i) {
+    if (hw[i] == 0) continue;
+    if (cell || off || w || id) {
+      if (cell) cell[live] = hc_[i];
+      if (w) w[live] = hw[i];
+      if (id) id[live] = hid[i];
+      if (off)
+        for (int a = 0; a < 3; ++a)
+          off[3 * live + a] = f64 ? ((const double*)ho[a].data())[i] : (double)((const float*)ho[a].data())[i];
+    }
+    ++live;
+  }
+  *n = live;
+  return ITOKMC_OK;
+}
+
+int itokmc_set_particles(itokmc_ctx* ctx, uint64_t n, const uint32_t* cell, const double* off,
+                         const uint32_t* w, const uint64_t* id) {
+  if (!ctx) return ITOKMC_EINVAL;
+  if (n > ctx->cap) return set_error(ctx, ITOKMC_ECAPACITY, "too many particles");
+  if (n && (!cell || !off || !w || !id)) return ITOKMC_EINVAL;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (cell[i] >= ctx->ncell || w[i] == 0) return set_error(ctx, ITOKMC_EINVAL, "bad particle %llu", (unsigned long long)i);
+    for (int a = 0; a < 3; ++a)
+      if (!(off[3 * i + a] >= 0.0 && off[3 * i + a] < 1.0))
+        return set_error(ctx, ITOKMC_EINVAL, "offset out of [0,1) at particle %llu", (unsigned long long)i);
+  }
+  const bool f64 = ctx->d.precision == ITOKMC_FP64;
+  const Bank& b = ctx->bank[ctx->cur];
+  hipError_t e = hipStreamSynchronize(ctx->s);
+  if (n) {
+    std::vector<char> ho[3];
+    for (int a = 0; a < 3; ++a) {
+      ho[a].resize((size_t)n * (f64 ? 8 : 4));
+      for (uint64_t i = 0; i < n; ++i) {
+        if (f64) ((double*)ho[a].data())[i] = off[3 * i + a];
+        else {
+          float f = (float)off[3 * i + a];
+          ((float*)ho[a].data())[i] = f < 1.0f ? f : 0x1.fffffep-1f;
+        }
+      }
+    }
+    void* dst[3] = {b.ox, b.oy, b.oz};
+    if (e == hipSuccess) e = hipMemcpy(b.cell, cell, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b.w, w, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b.id, id, n * 8, hipMemcpyHostToDevice);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = hipMemcpy(dst[a], ho[a].data(), ho[a].size(), hipMemcpyHostToDevice);
+  }
+  const uint32_t nn = (uint32_t)n;
+  if (e == hipSuccess) e = hipMemcpy(&ctx->ctr->n[ctx->cur], &nn, 4, hipMemcpyHostToDevice);
+  int rc = check_hip(ctx, e, "set_particles");
+  if (rc) return rc;
+  ctx->binned = false;
+  ctx->field_valid = false;
+  return mark_unbinned(ctx);
+}
+
+static uint32_t* counts_ptr(itokmc_ctx* ctx, int which) {
+  switch (which) {
+    case ITOKMC_Q_NPLUS: return ctx->nplus;
+    case ITOKMC_Q_NMINUS: return ctx->nminus;
+    case ITOKMC_Q_NGAMMA: return ctx->ngamma;
+    default: return nullptr;
+  }
+}
+
+int itokmc_get_counts(itokmc_ctx* ctx, int which, uint32_t* host) {
+  if (!ctx || !host) return ITOKMC_EINVAL;
+  uint32_t* p = counts_ptr(ctx, which);
+  if (!p) return set_error(ctx, ITOKMC_EINVAL, "bad count selector");
+  hipError_t e = hipStreamSynchronize(ctx->s);
+  if (e == hipSuccess) e = hipMemcpy(host, p, (size_t)ctx->ncell * 4, hipMemcpyDeviceToHost);
+  return check_hip(ctx, e, "get_counts");
+}
+
+int itokmc_set_counts(itokmc_ctx* ctx, int which, const uint32_t* host) {
+  if (!ctx || !host) return ITOKMC_EINVAL;
+  uint32_t* p = counts_ptr(ctx, which);
+  if (!p) return set_error(ctx, ITOKMC_EINVAL, "bad count selector");
+  hipError_t e = hipStreamSynchronize(ctx->s);
+  if (e == hipSuccess) e = hipMemcpy(p, host, (size_t)ctx->ncell * 4, hipMemcpyHostToDevice);
+  ctx->field_valid = false;
+  return check_hip(ctx, e, "set_counts");
+}
+
+int itokmc_get_field(itokmc_ctx* ctx, double* phi) {
+  if (!ctx || !phi) return ITOKMC_EINVAL;
+  if (ctx->d.field_mode != ITOKMC_FIELD_POISSON) return set_error(ctx, ITOKMC_EINVAL, "uniform mode");
+  return field_get_phi(ctx, phi);
+}
+
+int itokmc_set_field(itokmc_ctx* ctx, const double* phi) {
+  if (!ctx || !phi) return ITOKMC_EINVAL;
+  if (ctx->d.field_mode != ITOKMC_FIELD_POISSON) return set_error(ctx, ITOKMC_EINVAL, "uniform mode");
+  return field_set_phi(ctx, phi);
+}
+
+int itokmc_set_profiling(itokmc_ctx* ctx, int on) {
+  if (!ctx) return ITOKMC_EINVAL;
+  phase_collect(ctx);
+  ctx->profiling = on != 0;
+  return ITOKMC_OK;
+}
+
+int itokmc_phase_times(itokmc_ctx* ctx, double* ms, uint64_t* calls, int n, int reset) {
+  if (!ctx || !ms || !calls || n < 0) return ITOKMC_EINVAL;
+  phase_collect(ctx);
+  for (int i = 0; i < n && i < PH_NUM; ++i) {
+    ms[i] = ctx->phase_ms[i];
+    calls[i] = ctx->phase_calls[i];
+  }
+  if (reset)
+    for (int i = 0; i < PH_NUM; ++i) { ctx->phase_ms[i] = 0.0; ctx->phase_calls[i] = 0; }
+  return ITOKMC_OK;
+}
+
+void itokmc_destroy(itokmc_ctx* ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->s);
+  for (auto& u : ctx->ev_used) { hipEventDestroy(u.second.first); hipEventDestroy(u.second.second); }
+  for (auto e : ctx->ev_free) hipEventDestroy(e);
+  if (ctx->host_ctr) hipHostFree(ctx->host_ctr);
+  delete ctx;
+}
+
+const char* itokmc_last_error(const itokmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int itokmc_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                       uint64_t n, uint32_t* dev_out, void* stream) {
+  if (!dev_out && n) return ITOKMC_EINVAL;
+  if (n == 0) return ITOKMC_OK;
+  hipError_t e = launch_philox_fill(c0, c1, c2, c3, k0, k1, n, dev_out, (hipStream_t)stream);
+  return e == hipSuccess ? ITOKMC_OK : ITOKMC_EHIP;
+}
+
+int itokmc_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, int64_t* X, const double* k,
+                     double dt, uint32_t step, int64_t* fires) {
+  if (!ctx || (n && (!ids || !X || !k || !fires))) return ITOKMC_EINVAL;
+  if (!(dt > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "dt must be positive");
+  if (n == 0) return ITOKMC_OK;
+  return check_hip(ctx, launch_kmc_cells(ctx, n, ids, X, k, dt, step, fires), "kmc_cells");
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// KMC-particle coupling (section "KMC-particle coupling", eq. w): one wavefront per
+// queued cell.  A net gain dN > 0 becomes min(dN, n_new) new particles of weight
+// dN div M, the remainder going to the first, placed uniformly in the cell and
+// appended to the bank; a net loss removes weight from the cell's particles in
+// ascending id order (a particle reaching weight 0 is dead and dropped by the next
+// binning).  Superparticle management (merge/split to n_ppc per cell) is applied to
+// the cell afterwards when enabled.
+#include <math.h>
+
+#include "device.hpp"
+#include "itk.hpp"
+#include "merge.hpp"
+
+namespace itk {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T* as(void* p) { return reinterpret_cast<T*>(p); }
+
+// Remove R weight from particles [s, e) of bank b in ascending id order.
+__device__ uint64_t remove_weight(Bank b, uint32_t s, uint32_t e, uint32_t R) {
+  const int lane = lane_id();
+  uint64_t removed = 0;
+  while (R > 0) {
+    uint64_t best = ~0ull;
+    uint32_t bi = 0xFFFFFFFFu;
+    for (uint32_t q = s + lane; q < e; q += 64) {
+      if (b.w[q] > 0) {
+        const uint64_t id = b.id[q];
+        if (id < best) { best = id; bi = q; }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const uint64_t ob = (uint64_t)__shfl_xor((unsigned long long)best, d, 64);
+      const uint32_t oi = __shfl_xor(bi, d, 64);
+      if (ob < best) { best = ob; bi = oi; }
+    }
+    if (bi == 0xFFFFFFFFu) break;  // nothing left (not reachable: KMC keeps X_e >= 0)
+    uint32_t take = 0;
+    if (lane == 0) {
+      const uint32_t w = b.w[bi];
+      take = w < R ? w : R;
+      b.w[bi] = w - take;
+    }
+    take = __shfl(take, 0, 64);
+    R -= take;
+    removed += take;
+  }
+  return removed;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which, StepConst K,
+                                              const uint32_t* work, const uint32_t* occ,
+                                              const uint32_t* start, const int32_t* dN,
+                                              const uint32_t* cbase, int n_new, int n_ppc,
+                                              MergeScratch ms) {
+  const uint32_t nwork = ctr->n_work;
+  const int lane = lane_id();
+  uint64_t created = 0, removed = 0, merged = 0;
+  for (uint32_t t = blockIdx.x; t < nwork; t += gridDim.x) {
+    const uint32_t j = work[t];
+    const uint32_t c = occ[j];
+    const uint32_t s = start[c], e = start[c + 1];
+    const int32_t d = dN[j];
+    if (d < 0) removed += remove_weight(b, s, e, (uint32_t)(-d));
+    uint32_t M = 0, wb = 0, wr = 0, base = 0;
+    if (d > 0) {
+      M = (uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new;
+      wb = (uint32_t)d / M;
+      wr = (uint32_t)d % M;
+      base = cbase[j];  // slots reserved by the KMC pass
+    }
+    // new particles, one per lane (n_new <= 64 per pass)
+    T no[3] = {0, 0, 0};
+    uint32_t nw = 0;
+    uint64_t nid = 0;
+    if ((uint32_t)lane < M) {
+      const uint4 r = philox_block(c, (uint32_t)lane, K.step, TAG_CREATE, 0, K.key);
+      no[0] = (T)u24(r.x); no[1] = (T)u24(r.y); no[2] = (T)u24(r.z);
+      nw = wb + (lane == 0 ? wr : 0u);
+      nid = make_id(KIND_KMC, K.step, c, (uint32_t)lane);
+    }
+    created += M;
+    bool handled = false;
+    if (n_ppc > 0) {
+      handled = merge_cell<T>(b, ctr, which, K, c, s, e, M, base, no, nw, nid, n_ppc, ms, &merged);
+    }
+    if (!handled && M > 0) {
+      if ((uint32_t)lane < M) {
+        const uint32_t q = base + (uint32_t)lane;
+        if (q < K.cap) {
+          b.cell[q] = c;
+          as<T>(b.ox)[q] = no[0];
+          as<T>(b.oy)[q] = no[1];
+          as<T>(b.oz)[q] = no[2];
+          b.w[q] = nw;
+          b.id[q] = nid;
+        } else {
+          atomicOr(&ctr->overflow, 1u);
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    if (created) atomicAdd(&ctr->created, (unsigned long long)created);
+    if (removed) atomicAdd(&ctr->removed, (unsigned long long)removed);
+    if (merged) atomicAdd(&ctr->merged, (unsigned long long)merged);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k) {
+  const int dest = 1 - ctx->cur;  // coupling acts on the freshly binned bank
+  int g = (int)(ctx->ncell < 65536u ? ctx->ncell : 65536u);
+  if (g < 1) g = 1;
+  MergeScratch ms = merge_scratch(ctx);
+  if (ctx->d.precision == ITOKMC_FP64)
+    k_couple<double><<<g, 64, merge_lds_bytes<double>(ctx->d.n_ppc), ctx->s>>>(
+        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN,
+        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ms);
+  else
+    k_couple<float><<<g, 64, merge_lds_bytes<float>(ctx->d.n_ppc), ctx->s>>>(
+        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN,
+        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ms);
+  return hipGetLastError();
+}
+
+}  // namespace itk

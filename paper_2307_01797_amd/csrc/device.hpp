@@ -1,0 +1,144 @@
+// Device building blocks for gfx950 (wave64): counter-based random numbers and
+// wavefront-level aggregation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace itk {
+
+// Philox counter tags (top byte of counter word 3) and particle-id kinds.
+enum : uint32_t { TAG_PUSH = 1, TAG_SEED = 2, TAG_KMC = 3, TAG_CREATE = 4, TAG_PHOTON = 5 };
+enum : uint32_t { KIND_SEED = 0, KIND_KMC = 1, KIND_PHOTO = 2, KIND_MERGE = 3 };
+
+constexpr uint32_t kInvalidCell = 0xFFFFFFFFu;
+
+struct Key {
+  uint32_t k0, k1;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two 32x32->64
+// products of counter words 0 and 2 with fixed multipliers; the key advances by the
+// Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox(uint4 c, Key key) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    c = make_uint4(y0, (uint32_t)p1, y2, (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t c2,
+                                              uint32_t tag, uint32_t sub, Key key) {
+  return philox(make_uint4(c0, c1, c2, (tag << 24) | (sub & 0xFFFFFFu)), key);
+}
+
+// Uniform conversions.  [0,1) at 32-bit resolution, (0,1] at 32-bit resolution (for
+// logarithms), and [0,1) at 24-bit resolution (exact in single precision; positions).
+__device__ __forceinline__ double u_co(uint32_t x) { return (double)x * 0x1p-32; }
+__device__ __forceinline__ double u_oc(uint32_t x) { return ((double)x + 1.0) * 0x1p-32; }
+__device__ __forceinline__ double u24(uint32_t x) { return (double)(x >> 8) * 0x1p-24; }
+__device__ __forceinline__ float u24f(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+// (0,1] in single precision with relative (not absolute) 2^-24 resolution, so that the
+// logarithm of small draws stays accurate
+__device__ __forceinline__ float u_ocf(uint32_t x) { return __fmaf_rn((float)x, 0x1p-32f, 0x1p-32f); }
+
+// Sequential stream of one cell: word n is word (n mod 4) of the block with counter
+// (cell, n div 4, step, tag|sub).
+struct CellStream {
+  uint32_t cell, step, tagsub;
+  Key key;
+  uint32_t n;
+  uint4 buf;
+  __device__ void init(uint32_t c, uint32_t s, uint32_t tag, uint32_t sub, Key k) {
+    cell = c; step = s; tagsub = (tag << 24) | sub; key = k; n = 0;
+  }
+  __device__ __forceinline__ uint32_t next() {
+    const uint32_t lane = n & 3u;
+    if (lane == 0) buf = philox(make_uint4(cell, n >> 2, step, tagsub), key);
+    ++n;
+    return lane == 0 ? buf.x : lane == 1 ? buf.y : lane == 2 ? buf.z : buf.w;
+  }
+};
+
+__device__ __forceinline__ uint64_t make_id(uint32_t kind, uint32_t step, uint32_t cell,
+                                            uint32_t slot) {
+  return ((uint64_t)kind << 62) | ((uint64_t)(step & 0x3FFFFFu) << 40) |
+         ((uint64_t)(cell & 0xFFFFFFu) << 16) | (uint64_t)(slot & 0xFFFFu);
+}
+
+// ---- wavefront helpers (64 lanes) ------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+  return (uint64_t)__shfl_up((unsigned long long)v, d, 64);
+}
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  return (uint64_t)__shfl((unsigned long long)v, src, 64);
+}
+
+// Run-aggregated atomic add.  Lanes whose keys form a run of equal consecutive values
+// (inactive lanes use kInvalidCell) add their values to acc[key] with a single atomic
+// per run; each active lane receives the value acc[key] had before its own
+// contribution (old value plus the exclusive prefix of its run).  Particles sorted by
+// cell make runs long, so a wave issues few atomics.
+__device__ __forceinline__ uint64_t run_add(unsigned long long* acc, uint32_t key,
+                                            uint64_t val) {
+  const int lane = lane_id();
+  const bool active = key != kInvalidCell;
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const bool head = (lane == 0) || (prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int seg_start = 63 - __clzll(heads & upto);
+  const uint64_t after = heads & ~upto;
+  const int seg_end = after ? (__ffsll((long long)after) - 2) : 63;
+  uint64_t x = active ? val : 0ull;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = shfl_up64(x, d);
+    if (lane - d >= seg_start) x += y;
+  }
+  uint64_t old = 0;
+  if (active && lane == seg_end) old = atomicAdd(&acc[key], (unsigned long long)x);
+  old = shfl64(old, seg_end);
+  return old + x - (active ? val : 0ull);
+}
+
+// Wave-wide sum (result valid in every lane).
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, d, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sumd(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Append n items (per lane) to a counter with one atomic per wave; returns the lane's
+// first slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, uint32_t n) {
+  const int lane = lane_id();
+  uint32_t x = n;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  const uint32_t total = __shfl(x, 63, 64);
+  uint32_t base = 0;
+  if (lane == 63 && total) base = atomicAdd(counter, total);
+  base = __shfl(base, 63, 64);
+  return base + x - n;
+}
+
+}  // namespace itk

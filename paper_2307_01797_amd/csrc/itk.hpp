@@ -1,0 +1,136 @@
+// Internal context of the itokmc library (host side) and kernel launcher prototypes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/itokmc.h"
+
+namespace itk {
+
+// Structure-of-arrays particle bank.  Offsets are cell-relative in [0,1) and stored
+// in the working precision (float or double) as three separate arrays so that each
+// lane's loads coalesce.
+struct Bank {
+  uint32_t* cell;
+  void* ox;
+  void* oy;
+  void* oz;
+  uint32_t* w;
+  uint64_t* id;
+  uint32_t* rank;  // position inside the destination cell, written by the push
+};
+
+// Device-resident counters and tallies (one 256-byte block of the arena).
+struct Counters {
+  uint32_t n[2];          // particles per bank (including dead slots, w == 0)
+  uint32_t overflow;      // bit 0: particle capacity, bit 1: merge scratch
+  uint32_t n_occ;         // occupied cells after binning
+  uint32_t n_work;        // cells needing coupling / merge
+  uint32_t pad[3];
+  unsigned long long outflow, created, removed, merged;
+  unsigned long long fires[3];
+  unsigned long long ph_emitted, ph_absorbed, ph_lost;
+  unsigned long long pushed;   // live particles advanced by the transport kernels
+};
+
+// Device-side copy of the per-step constants shared by the kernels.
+struct StepConst {
+  int nx, ny, nz;
+  uint32_t ncell;
+  uint32_t cap;
+  uint32_t step;
+  Key key;
+  double dx, dt;
+  double drift[3];   // uniform mode: -mu E dt / dx per axis (grid units)
+  double diff;       // sqrt(2 D dt) / dx (grid units per unit normal)
+  double k[3];       // uniform mode rates (1/s)
+};
+
+}  // namespace itk
+
+struct itokmc_ctx {
+  itokmc_grid_desc d;
+  itokmc_coeffs c;
+  bool have_coeffs = false;
+  hipStream_t s = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  uint32_t ncell = 0;
+  uint64_t cap = 0;
+  int cur = 0;  // bank holding the current particles
+  itk::Bank bank[2];
+  // per-cell arrays
+  unsigned long long* cellacc = nullptr;  // (count << 32) | weight, reset after use
+  uint32_t* start = nullptr;              // ncell + 1 exclusive prefix of counts
+  uint32_t* occ = nullptr;                // occupied cells (n_occ entries)
+  uint32_t* occ_fires = nullptr;          // 3 per occupied cell: fires of the last step
+  uint32_t* nplus = nullptr;
+  uint32_t* nminus = nullptr;
+  uint32_t* ngamma = nullptr;
+  int32_t* dN = nullptr;                  // net electron change per occupied cell
+  uint32_t* work = nullptr;               // occupied-cell indices needing coupling
+  uint32_t* cbase = nullptr;              // first reserved bank slot of a cell's products
+  uint32_t* blocksums = nullptr;          // scan scratch
+  itk::Counters* ctr = nullptr;
+  unsigned long long* reduce = nullptr;   // small reduction scratch
+  bool binned = false;                    // bins of the current bank are filled
+  itk::Counters* host_ctr = nullptr;      // pinned mirror
+  // Poisson-mode field data (see field.hip)
+  void* field = nullptr;
+  bool field_valid = false;
+  int last_cycles = 0;
+  double last_relres = 0.0;
+  uint32_t step = 0;
+  std::string err;
+  // optional per-phase timing with HIP events recorded on the context's stream
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  std::vector<hipEvent_t> ev_free;
+  double phase_ms[16] = {0};
+  uint64_t phase_calls[16] = {0};
+};
+
+namespace itk {
+// phases timed when profiling is on
+enum Phase { PH_PUSH = 0, PH_PHOTON, PH_SCAN, PH_SCATTER, PH_KMC, PH_COUPLE, PH_DEPOSIT,
+             PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_NUM };
+void phase_begin(itokmc_ctx* ctx, int phase);
+void phase_end(itokmc_ctx* ctx, int phase);
+int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);
+int check_hip(itokmc_ctx* ctx, hipError_t e, const char* what);
+
+StepConst make_const(const itokmc_ctx* ctx, double dt);
+// particles.hip
+hipError_t launch_seed_gaussian(itokmc_ctx* ctx, const itokmc_seed_desc* sd);
+hipError_t launch_seed_neutral(itokmc_ctx* ctx, const itokmc_seed_desc* sd);
+hipError_t launch_push_uniform(itokmc_ctx* ctx, const StepConst& k);
+hipError_t launch_count(itokmc_ctx* ctx);  // bin the current bank without moving
+hipError_t launch_photons(itokmc_ctx* ctx, const StepConst& k);
+hipError_t launch_scan(itokmc_ctx* ctx);
+hipError_t launch_scatter(itokmc_ctx* ctx);
+hipError_t launch_ngp(itokmc_ctx* ctx, uint32_t* out);
+hipError_t launch_reduce_particles(itokmc_ctx* ctx, unsigned long long* out2);
+hipError_t launch_reduce_cells(itokmc_ctx* ctx, unsigned long long* out2);
+hipError_t launch_fires_dense(itokmc_ctx* ctx, uint32_t* out);
+hipError_t launch_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1, uint64_t n, uint32_t* out, hipStream_t s);
+// kmc.hip
+hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const double* cell_rates);
+hipError_t launch_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, int64_t* X,
+                            const double* k, double dt, uint32_t step, int64_t* fires);
+// couple.hip
+hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k);
+// field.hip (Poisson mode)
+size_t field_bytes(const itokmc_grid_desc* d);
+int field_init(itokmc_ctx* ctx, char* base);
+int field_transport(itokmc_ctx* ctx, const StepConst& k);
+const double* field_cell_rates(itokmc_ctx* ctx);  // rates per cell for the KMC
+int field_get_phi(itokmc_ctx* ctx, double* host);
+int field_set_phi(itokmc_ctx* ctx, const double* host);
+int field_deposit(itokmc_ctx* ctx, int what, void* dev_out);
+hipError_t launch_cic_density(itokmc_ctx* ctx, double* out);
+}  // namespace itk

@@ -1,0 +1,242 @@
+// Per-cell Kinetic Monte Carlo on the GPU: one lane per occupied cell, double
+// precision, random numbers from the cell's sequential Philox stream (cell, step, KMC).
+//
+// Network (rows 1, 2 and 5 of the paper's air-chemistry table), species (e, M+, M-,
+// photons), first-order propensities a_r = k_r X_e:
+//   ionization  e -> 2e + M+ ; attachment e -> M- ; photo-emission e -> e + photon.
+// Only attachment consumes a reactant, so it is the only reaction that can be
+// critical (X_e < N_c).  The hybrid integrator follows the paper's reaction-algorithm
+// outline with the SSA exception (A h <= 1) tested before the critical time is drawn
+// (ordering of Cao, Gillespie and Petzold 2006); a rejected leap halves the step.
+// A pure tau-leaping mode (eq. tau_leaping) is selectable.
+#include <math.h>
+
+#include "device.hpp"
+#include "itk.hpp"
+#include "poisson.hpp"
+
+namespace itk {
+
+namespace {
+
+struct KmcParams {
+  int mode, nc, nssa;
+  double eps;
+};
+
+struct State {
+  int64_t e, p, m, g;
+};
+
+// Largest leap that keeps the relative change of the non-critical propensities below
+// eps (step 4, g_i = 1); infinite for eps = inf.
+__device__ double leap_bound(const KmcParams& P, const State& X, double a1, double a2,
+                             double a3, bool crit2) {
+  if (isinf(P.eps)) return INFINITY;
+  // the only reactant is e; net and squared changes of e over non-critical reactions
+  double mu = 0.0 + 1.0 * a1;
+  double var = 0.0 + 1.0 * a1;
+  if (!crit2) { mu = mu + (-1.0) * a2; var = var + 1.0 * a2; }
+  mu = mu + 0.0 * a3;
+  var = var + 0.0 * a3;
+  const double bound = fmax(P.eps * (double)X.e / 1.0, 1.0);
+  double best = INFINITY;
+  if (mu != 0.0) best = fmin(best, bound / fabs(mu));
+  if (var > 0.0) best = fmin(best, bound * bound / var);
+  return best;
+}
+
+// Whole-network SSA for at most nssa events inside h; returns the time advanced.
+__device__ double ssa_run(const KmcParams& P, State& X, const double k[3], double h,
+                          CellStream& st, int64_t f[3]) {
+  double tp = 0.0;
+  for (int ev = 0; ev < P.nssa; ++ev) {
+    const double a1 = k[0] * (double)X.e, a2 = k[1] * (double)X.e, a3 = k[2] * (double)X.e;
+    const double A = a1 + a2 + a3;
+    if (!(A > 0.0)) return h;
+    const double delta = log(1.0 / u_oc(st.next())) / A;
+    if (tp + delta > h) return h;
+    const double target = u_co(st.next()) * A;
+    if (a1 > target) { X.e += 1; X.p += 1; f[0] += 1; }
+    else if (a1 + a2 > target) { X.e -= 1; X.m += 1; f[1] += 1; }
+    else { X.g += 1; f[2] += 1; }
+    tp += delta;
+  }
+  return tp;
+}
+
+__device__ void advance_hybrid(const KmcParams& P, State& X, const double k[3], double dt,
+                               CellStream& st, int64_t f[3]) {
+  double tau = 0.0;
+  for (int pass = 0; tau < dt && pass < (1 << 22); ++pass) {  // bounded: every pass fires or advances
+    const double a1 = k[0] * (double)X.e, a2 = k[1] * (double)X.e, a3 = k[2] * (double)X.e;
+    const double A = a1 + a2 + a3;
+    if (!(A > 0.0)) break;
+    const bool crit2 = (a2 > 0.0) && X.e < (int64_t)P.nc;
+    const double Ac = crit2 ? a2 : 0.0;
+    double dtnc = leap_bound(P, X, a1, a2, a3, crit2);
+    double dtc = INFINITY;
+    bool drawn = false;
+    for (int attempt = 0; attempt < 4096; ++attempt) {
+      const double rem = dt - tau;
+      const double h = fmin(rem, dtnc);
+      if (A * h <= 1.0) {
+        const double tp = ssa_run(P, X, k, h, st, f);
+        tau = (tp == rem) ? dt : tau + tp;
+        break;
+      }
+      if (!drawn) {
+        if (Ac > 0.0) dtc = log(1.0 / u_oc(st.next())) / Ac;
+        drawn = true;
+      }
+      const double dtau = fmin(h, dtc);
+      State Y = X;
+      int64_t g[3] = {0, 0, 0};
+      if (dtc < dtnc && dtc < rem) {
+        (void)st.next();            // selection among the critical set (attachment only)
+        Y.e -= 1; Y.m += 1; g[1] += 1;
+      }
+      // non-critical reactions leap over dtau, in table order
+      const int64_t n1 = poisson_draw(a1 * dtau, st);
+      Y.e += n1; Y.p += n1; g[0] += n1;
+      if (!crit2) {
+        const int64_t n2 = poisson_draw(a2 * dtau, st);
+        Y.e -= n2; Y.m += n2; g[1] += n2;
+      }
+      const int64_t n3 = poisson_draw(a3 * dtau, st);
+      Y.g += n3; g[2] += n3;
+      if (Y.e < 0 || Y.p < 0 || Y.m < 0 || Y.g < 0) { dtnc = dtau / 2.0; continue; }
+      X = Y;
+      f[0] += g[0]; f[1] += g[1]; f[2] += g[2];
+      tau = (dtau == rem) ? dt : tau + dtau;
+      break;
+    }
+  }
+}
+
+__device__ void advance_pure_tau(State& X, const double k[3], double dt, CellStream& st,
+                                 int64_t f[3]) {
+  double tau = 0.0, hmax = INFINITY;
+  for (int it = 0; tau < dt && it < 100000; ++it) {
+    const double a1 = k[0] * (double)X.e, a2 = k[1] * (double)X.e, a3 = k[2] * (double)X.e;
+    if (!(a1 + a2 + a3 > 0.0)) break;
+    const double h = fmin(dt - tau, hmax);
+    const int64_t n1 = poisson_draw(a1 * h, st);
+    const int64_t n2 = poisson_draw(a2 * h, st);
+    const int64_t n3 = poisson_draw(a3 * h, st);
+    State Y = X;
+    Y.e += n1 - n2; Y.p += n1; Y.m += n2; Y.g += n3;
+    if (Y.e < 0) { hmax = h / 2.0; continue; }
+    X = Y;
+    f[0] += n1; f[1] += n2; f[2] += n3;
+    tau = (h == dt - tau) ? dt : tau + h;
+  }
+}
+
+__device__ __forceinline__ void advance(const KmcParams& P, State& X, const double k[3], double dt,
+                                        CellStream& st, int64_t f[3]) {
+  f[0] = f[1] = f[2] = 0;
+  if (P.mode == ITOKMC_KMC_PURE_TAU) advance_pure_tau(X, k, dt, st, f);
+  else advance_hybrid(P, X, k, dt, st, f);
+}
+
+// Step kernel: occupied cells from the binning pass.  Writes the per-cell fires, the
+// updated ions and pending photons, the net electron change, clears the cell's bin
+// accumulator, and queues cells for the coupling pass.
+__global__ void __launch_bounds__(256) k_kmc_step(KmcParams P, StepConst K, Counters* ctr,
+                                                 const uint32_t* occ, unsigned long long* cellacc,
+                                                 uint32_t* nplus, uint32_t* nminus,
+                                                 uint32_t* ngamma, uint32_t* occ_fires, int32_t* dN,
+                                                 uint32_t* work, uint32_t* cbase,
+                                                 const double* cell_rates, int queue_all,
+                                                 int n_new, int dest) {
+  const uint32_t n = ctr->n_occ;
+  uint64_t t0 = 0, t1 = 0, t2 = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t j = base + threadIdx.x;
+    bool queue = false;
+    uint32_t M = 0;
+    if (j < n) {
+      const uint32_t c = occ[j];
+      const uint32_t Xe = (uint32_t)cellacc[c];
+      cellacc[c] = 0ull;
+      State X{(int64_t)Xe, (int64_t)nplus[c], (int64_t)nminus[c], 0};
+      double k[3];
+      if (cell_rates) { k[0] = cell_rates[3 * (size_t)c]; k[1] = cell_rates[3 * (size_t)c + 1]; k[2] = cell_rates[3 * (size_t)c + 2]; }
+      else { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
+      CellStream st;
+      st.init(c, K.step, TAG_KMC, 0, K.key);
+      int64_t f[3];
+      advance(P, X, k, K.dt, st, f);
+      occ_fires[3 * (size_t)j] = (uint32_t)f[0];
+      occ_fires[3 * (size_t)j + 1] = (uint32_t)f[1];
+      occ_fires[3 * (size_t)j + 2] = (uint32_t)f[2];
+      nplus[c] = (uint32_t)X.p;
+      nminus[c] = (uint32_t)X.m;
+      ngamma[c] = (uint32_t)X.g;
+      const int64_t d = X.e - (int64_t)Xe;
+      dN[j] = (int32_t)d;
+      queue = queue_all || d != 0;
+      if (d > 0) M = d < (int64_t)n_new ? (uint32_t)d : (uint32_t)n_new;
+      t0 += (uint64_t)f[0]; t1 += (uint64_t)f[1]; t2 += (uint64_t)f[2];
+    }
+    const uint32_t q = wave_append(&ctr->n_work, queue ? 1u : 0u);
+    if (queue) work[q] = j;
+    // reserve the bank slots of the KMC products: one atomic per wave
+    const uint32_t slot = wave_append(&ctr->n[dest], M);
+    if (M) cbase[j] = slot;
+  }
+  t0 = wave_sum64(t0); t1 = wave_sum64(t1); t2 = wave_sum64(t2);
+  if (lane_id() == 0) {
+    if (t0) atomicAdd(&ctr->fires[0], (unsigned long long)t0);
+    if (t1) atomicAdd(&ctr->fires[1], (unsigned long long)t1);
+    if (t2) {
+      atomicAdd(&ctr->fires[2], (unsigned long long)t2);
+      atomicAdd(&ctr->ph_emitted, (unsigned long long)t2);
+    }
+  }
+}
+
+__global__ void k_kmc_cells(KmcParams P, Key key, uint64_t n, const uint32_t* ids, int64_t* Xa,
+                            const double* ka, double dt, uint32_t step, int64_t* fa) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    State X{Xa[4 * i], Xa[4 * i + 1], Xa[4 * i + 2], Xa[4 * i + 3]};
+    const double k[3] = {ka[3 * i], ka[3 * i + 1], ka[3 * i + 2]};
+    CellStream st;
+    st.init(ids[i], step, TAG_KMC, 0, key);
+    int64_t f[3];
+    advance(P, X, k, dt, st, f);
+    Xa[4 * i] = X.e; Xa[4 * i + 1] = X.p; Xa[4 * i + 2] = X.m; Xa[4 * i + 3] = X.g;
+    fa[3 * i] = f[0]; fa[3 * i + 1] = f[1]; fa[3 * i + 2] = f[2];
+  }
+}
+
+KmcParams params(const itokmc_ctx* ctx) {
+  return KmcParams{ctx->d.kmc_mode, ctx->d.kmc_nc, ctx->d.kmc_nssa, ctx->d.kmc_eps};
+}
+
+}  // namespace
+
+hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const double* cell_rates) {
+  int g = (int)((ctx->ncell + 255) / 256);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  k_kmc_step<<<g, 256, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
+                                    ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
+                                    ctx->cbase, cell_rates, ctx->d.n_ppc > 0 ? 1 : 0, ctx->d.n_new,
+                                    1 - ctx->cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, int64_t* X,
+                            const double* k, double dt, uint32_t step, int64_t* fires) {
+  int g = (int)((n + 255) / 256);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  k_kmc_cells<<<g, 256, 0, ctx->s>>>(params(ctx), Key{ctx->d.seed, ctx->d.realization}, n, ids, X,
+                                     k, dt, step, fires);
+  return hipGetLastError();
+}
+
+}  // namespace itk

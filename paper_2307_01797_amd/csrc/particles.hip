@@ -1,0 +1,612 @@
+// Particle kernels: seeding, the explicit Ito push with fused NGP binning, photon
+// transport, the counting sort by cell (scan + scatter) and reductions.
+#include <math.h>
+
+#include "device.hpp"
+#include "itk.hpp"
+#include "poisson.hpp"
+
+namespace itk {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(uint64_t n, int per_block = kBlock, int max_blocks = 8192) {
+  uint64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+template <typename T>
+__device__ __forceinline__ T* as(void* p) { return reinterpret_cast<T*>(p); }
+
+// Store one particle into a bank slot.
+template <typename T>
+__device__ __forceinline__ void put(const Bank& b, uint32_t q, uint32_t cell, T ox, T oy, T oz,
+                                    uint32_t w, uint64_t id) {
+  b.cell[q] = cell;
+  as<T>(b.ox)[q] = ox;
+  as<T>(b.oy)[q] = oy;
+  as<T>(b.oz)[q] = oz;
+  b.w[q] = w;
+  b.id[q] = id;
+}
+
+// Offset in [0,1) of the working precision.
+template <typename T> __device__ __forceinline__ T to_off(double o);
+template <> __device__ __forceinline__ double to_off<double>(double o) { return o; }
+template <> __device__ __forceinline__ float to_off<float>(double o) {
+  float f = (float)o;
+  return f < 1.0f ? f : 0x1.fffffep-1f;
+}
+
+// ---- seeding ---------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_seed_gaussian(Bank b, Counters* ctr, int which,
+                                                         StepConst k, uint64_t n0, double cx,
+                                                         double cy, double cz, double sigma) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n0;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = base + threadIdx.x;
+    bool keep = false;
+    double xi[3];
+    if (i < n0) {
+      const uint4 r = philox_block((uint32_t)i, (uint32_t)(i >> 32), 0, TAG_SEED, 0, k.key);
+      const double r0 = sqrt(-2.0 * log(u_oc(r.x)));
+      const double t0 = two_pi * u_co(r.y);
+      const double r1 = sqrt(-2.0 * log(u_oc(r.z)));
+      const double t1 = two_pi * u_co(r.w);
+      const double nrm[3] = {r0 * cos(t0), r0 * sin(t0), r1 * cos(t1)};
+      const double c[3] = {cx, cy, cz};
+      for (int a = 0; a < 3; ++a) xi[a] = (c[a] + sigma * nrm[a]) / k.dx;
+      keep = xi[0] >= 0.0 && xi[0] < k.nx && xi[1] >= 0.0 && xi[1] < k.ny && xi[2] >= 0.0 &&
+             xi[2] < k.nz;
+    }
+    const uint32_t q = wave_append(&ctr->n[which], keep ? 1u : 0u);
+    if (keep) {
+      if (q >= k.cap) {
+        atomicOr(&ctr->overflow, 1u);
+      } else {
+        const double f[3] = {floor(xi[0]), floor(xi[1]), floor(xi[2])};
+        const uint32_t cell =
+            (uint32_t)f[0] + (uint32_t)k.nx * ((uint32_t)f[1] + (uint32_t)k.ny * (uint32_t)f[2]);
+        put<T>(b, q, cell, to_off<T>(xi[0] - f[0]), to_off<T>(xi[1] - f[1]),
+               to_off<T>(xi[2] - f[2]), 1u, (1ull << 61) | i);
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_seed_neutral(Bank b, Counters* ctr, int which,
+                                                        StepConst k, uint32_t* nplus,
+                                                        int n_new, double n_peak, double cx,
+                                                        double cy, double cz, double sigma) {
+  const double dV = k.dx * k.dx * k.dx;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < k.ncell; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    int64_t N = 0;
+    if (c < k.ncell) {
+      const uint32_t i = c % (uint32_t)k.nx, j = (c / (uint32_t)k.nx) % (uint32_t)k.ny,
+                     kk = c / ((uint32_t)k.nx * (uint32_t)k.ny);
+      const double x = (i + 0.5) * k.dx - cx, y = (j + 0.5) * k.dx - cy, z = (kk + 0.5) * k.dx - cz;
+      const double lam = n_peak * exp(-(x * x + y * y + z * z) / (2.0 * sigma * sigma)) * dV;
+      CellStream st;
+      st.init(c, 0, TAG_SEED, 1, k.key);
+      N = poisson_draw(lam, st);
+    }
+    const uint32_t M = N > 0 ? (uint32_t)(N < n_new ? N : n_new) : 0u;
+    const uint32_t q0 = wave_append(&ctr->n[which], M);
+    if (M > 0) {
+      const uint32_t i = c % (uint32_t)k.nx, j = (c / (uint32_t)k.nx) % (uint32_t)k.ny,
+                     kk = c / ((uint32_t)k.nx * (uint32_t)k.ny);
+      (void)i; (void)j; (void)kk;
+      const uint32_t wb = (uint32_t)(N / M), wr = (uint32_t)(N % M);
+      for (uint32_t s = 0; s < M; ++s) {
+        const uint32_t q = q0 + s;
+        if (q >= k.cap) { atomicOr(&ctr->overflow, 1u); break; }
+        const uint4 r = philox_block(c, s, 0, TAG_SEED, 2, k.key);
+        put<T>(b, q, c, (T)u24(r.x), (T)u24(r.y), (T)u24(r.z), wb + (s == 0 ? wr : 0u),
+               ((uint64_t)c << 16) | s);
+      }
+      nplus[c] += (uint32_t)N;
+    }
+  }
+}
+
+// ---- push (uniform prescribed field) with fused NGP binning -------------------------
+
+template <typename T> struct Normals;
+template <> struct Normals<double> {
+  // Box-Muller on one Philox block; the fourth word's partner is unused.
+  __device__ static void get(uint4 r, double n[3]) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const double r0 = sqrt(-2.0 * log(u_oc(r.x)));
+    const double t0 = two_pi * u_co(r.y);
+    const double r1 = sqrt(-2.0 * log(u_oc(r.z)));
+    const double t1 = two_pi * u_co(r.w);
+    n[0] = r0 * cos(t0);
+    n[1] = r0 * sin(t0);
+    n[2] = r1 * cos(t1);
+  }
+};
+template <> struct Normals<float> {
+  // Single precision: hardware log2 and sin/cos of revolutions (v_log_f32, v_sin_f32,
+  // v_cos_f32); -2 ln u = -2 ln2 log2 u.
+  __device__ static void get(uint4 r, float n[3]) {
+    const float m2ln2 = -1.3862943611198906f;
+    const float r0 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.x)));
+    const float r1 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.z)));
+    const float a0 = (float)(r.y >> 8) * 0x1p-24f;
+    const float a1 = (float)(r.w >> 8) * 0x1p-24f;
+    n[0] = r0 * __builtin_amdgcn_cosf(a0);
+    n[1] = r0 * __builtin_amdgcn_sinf(a0);
+    n[2] = r1 * __builtin_amdgcn_cosf(a1);
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, int which,
+                                                        unsigned long long* cellacc,
+                                                        StepConst k) {
+  const uint32_t n = min(ctr->n[which], k.cap);
+  const T drift[3] = {(T)k.drift[0], (T)k.drift[1], (T)k.drift[2]};
+  const T diff = (T)k.diff;
+  uint64_t out_w = 0, pushed = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t key = kInvalidCell;
+    uint32_t w = 0;
+    if (i < n) w = a.w[i];
+    if (w > 0) {
+      ++pushed;
+      const uint32_t cell = a.cell[i];
+      const uint64_t id = a.id[i];
+      T o[3] = {as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i]};
+      const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), k.step, TAG_PUSH, 0, k.key);
+      T nr[3];
+      Normals<T>::get(r, nr);
+      int ci[3] = {(int)(cell % (uint32_t)k.nx), (int)((cell / (uint32_t)k.nx) % (uint32_t)k.ny),
+                   (int)(cell / ((uint32_t)k.nx * (uint32_t)k.ny))};
+      const int lim[3] = {k.nx, k.ny, k.nz};
+      bool inside = true;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        T x = o[ax] + (drift[ax] + diff * nr[ax]);
+        T f = floor(x);
+        x -= f;
+        if (x >= (T)1) { x -= (T)1; f += (T)1; }
+        o[ax] = x;
+        ci[ax] += (int)f;
+        inside = inside && ci[ax] >= 0 && ci[ax] < lim[ax];
+      }
+      if (inside) {
+        key = (uint32_t)ci[0] + (uint32_t)k.nx * ((uint32_t)ci[1] + (uint32_t)k.ny * (uint32_t)ci[2]);
+        a.cell[i] = key;
+        as<T>(a.ox)[i] = o[0];
+        as<T>(a.oy)[i] = o[1];
+        as<T>(a.oz)[i] = o[2];
+      } else {
+        out_w += w;
+        a.w[i] = 0;  // removed at the domain face
+      }
+    }
+    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+  }
+  out_w = wave_sum64(out_w);
+  pushed = wave_sum64(pushed);
+  if (lane_id() == 0) {
+    if (out_w) atomicAdd(&ctr->outflow, (unsigned long long)out_w);
+    if (pushed) atomicAdd(&ctr->pushed, (unsigned long long)pushed);
+  }
+}
+
+// Bin the current particles without moving them (after seeding or set_state).
+__global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int which,
+                                                 unsigned long long* cellacc, uint32_t cap) {
+  const uint32_t n = min(ctr->n[which], cap);
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t key = kInvalidCell, w = 0;
+    if (i < n) {
+      w = a.w[i];
+      if (w > 0) key = a.cell[i];
+    }
+    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+  }
+}
+
+// ---- photon transport (final algorithm, step 6) -------------------------------------
+// Photons counted by the previous step's reactions leave their cell in at most n_new
+// computational photons; each is emitted uniformly in the cell, isotropically, and
+// travels an exponential distance whose mean is log-uniform in [l1, l2].  Absorbed
+// photons make one electron of the photon's weight plus as many positive ions in the
+// absorbing cell; photons leaving the domain are removed.  Geometry in double.
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int which,
+                                                   unsigned long long* cellacc, uint32_t* ngamma,
+                                                   uint32_t* nplus, StepConst k, int n_new,
+                                                   double l1, double l2) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double lr = l2 / l1;
+  uint64_t absorbed = 0, lost = 0;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < k.ncell;
+       c += gridDim.x * blockDim.x) {
+    const uint32_t ng = ngamma[c];
+    if (ng == 0) continue;
+    ngamma[c] = 0;
+    const uint32_t M = ng < (uint32_t)n_new ? ng : (uint32_t)n_new;
+    const uint32_t wb = ng / M, wr = ng % M;
+    const double ci = (double)(c % (uint32_t)k.nx), cj = (double)((c / (uint32_t)k.nx) % (uint32_t)k.ny),
+                 ck = (double)(c / ((uint32_t)k.nx * (uint32_t)k.ny));
+    for (uint32_t s = 0; s < M; ++s) {
+      const uint32_t w = wb + (s == 0 ? wr : 0u);
+      const uint4 A = philox_block(c, s, k.step, TAG_PHOTON, 0, k.key);
+      const uint4 B = philox_block(c, s, k.step, TAG_PHOTON, 1, k.key);
+      const double cth = 2.0 * u_co(A.w) - 1.0;
+      const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+      const double ph = two_pi * u_co(B.x);
+      const double ell = l1 * pow(lr, u_co(B.y));
+      const double rg = -ell * log(u_oc(B.z)) / k.dx;
+      const double y[3] = {ci + u24(A.x) + rg * (sth * cos(ph)), cj + u24(A.y) + rg * (sth * sin(ph)),
+                           ck + u24(A.z) + rg * cth};
+      const bool in = y[0] >= 0.0 && y[0] < k.nx && y[1] >= 0.0 && y[1] < k.ny && y[2] >= 0.0 &&
+                      y[2] < k.nz;
+      if (!in) { lost += w; continue; }
+      const double f[3] = {floor(y[0]), floor(y[1]), floor(y[2])};
+      const uint32_t cell =
+          (uint32_t)f[0] + (uint32_t)k.nx * ((uint32_t)f[1] + (uint32_t)k.ny * (uint32_t)f[2]);
+      const uint32_t q = atomicAdd(&ctr->n[which], 1u);
+      if (q >= k.cap) { atomicOr(&ctr->overflow, 1u); continue; }
+      put<T>(a, q, cell, to_off<T>(y[0] - f[0]), to_off<T>(y[1] - f[1]), to_off<T>(y[2] - f[2]), w,
+             make_id(KIND_PHOTO, k.step, c, s));
+      const unsigned long long old = atomicAdd(&cellacc[cell], (1ull << 32) | (unsigned long long)w);
+      a.rank[q] = (uint32_t)(old >> 32);
+      atomicAdd(&nplus[cell], w);
+      absorbed += w;
+    }
+  }
+  absorbed = wave_sum64(absorbed);
+  lost = wave_sum64(lost);
+  if (lane_id() == 0) {
+    if (absorbed) atomicAdd(&ctr->ph_absorbed, (unsigned long long)absorbed);
+    if (lost) atomicAdd(&ctr->ph_lost, (unsigned long long)lost);
+  }
+}
+
+// ---- counting sort by cell ------------------------------------------------------------
+// Three passes over the per-cell counts: block totals, a scan of the block totals, and
+// the final exclusive prefix (start) plus the list of occupied cells.
+
+constexpr int kScanPer = 8;                     // cells per thread
+constexpr int kScanTile = kBlock * kScanPer;    // cells per block
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // sh: kBlock / 64 + 1 words
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < kBlock / 64; ++i) { const uint32_t t = sh[i]; sh[i] = acc; acc += t; }
+    sh[kBlock / 64] = acc;
+  }
+  __syncthreads();
+  const uint32_t r = sh[wid] + x - v;
+  *total = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const unsigned long long* cellacc,
+                                                       uint32_t ncell, uint32_t* blocksums) {
+  __shared__ uint32_t sh[2][kBlock / 64 + 1];
+  const uint32_t c0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  uint32_t cnt = 0, occ = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const uint32_t c = c0 + j;
+    if (c < ncell) {
+      const uint32_t n = (uint32_t)(cellacc[c] >> 32);
+      cnt += n;
+      occ += n ? 1u : 0u;
+    }
+  }
+  uint32_t t0, t1;
+  block_exclusive_scan(cnt, sh[0], &t0);
+  block_exclusive_scan(occ, sh[1], &t1);
+  if (threadIdx.x == 0) {
+    blocksums[2 * blockIdx.x] = t0;
+    blocksums[2 * blockIdx.x + 1] = t1;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* blocksums, uint32_t nb) {
+  // exclusive scan of nb (count, occupied) pairs by one block; blocksums[2 nb ..] = totals
+  __shared__ uint32_t sh[2][1024 / 64 + 1];
+  const int per = (int)((nb + 1023) / 1024);
+  const uint32_t b0 = threadIdx.x * per;
+  uint32_t s0 = 0, s1 = 0;
+  for (int j = 0; j < per; ++j)
+    if (b0 + j < nb) { s0 += blocksums[2 * (b0 + j)]; s1 += blocksums[2 * (b0 + j) + 1]; }
+  // block scan with 1024 threads
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  uint32_t x0 = s0, x1 = s1;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y0 = __shfl_up(x0, d, 64), y1 = __shfl_up(x1, d, 64);
+    if (lane >= d) { x0 += y0; x1 += y1; }
+  }
+  if (lane == 63) { sh[0][wid] = x0; sh[1][wid] = x1; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a0 = 0, a1 = 0;
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t t0 = sh[0][i], t1 = sh[1][i];
+      sh[0][i] = a0; sh[1][i] = a1; a0 += t0; a1 += t1;
+    }
+    sh[0][16] = a0; sh[1][16] = a1;
+  }
+  __syncthreads();
+  uint32_t e0 = sh[0][wid] + x0 - s0, e1 = sh[1][wid] + x1 - s1;
+  for (int j = 0; j < per; ++j) {
+    if (b0 + j < nb) {
+      const uint32_t t0 = blocksums[2 * (b0 + j)], t1 = blocksums[2 * (b0 + j) + 1];
+      blocksums[2 * (b0 + j)] = e0;
+      blocksums[2 * (b0 + j) + 1] = e1;
+      e0 += t0; e1 += t1;
+    }
+  }
+  if (threadIdx.x == 0) { blocksums[2 * nb] = sh[0][16]; blocksums[2 * nb + 1] = sh[1][16]; }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* cellacc,
+                                                     uint32_t ncell, const uint32_t* blocksums,
+                                                     uint32_t nb, uint32_t* start, uint32_t* occ,
+                                                     Counters* ctr, int dest) {
+  __shared__ uint32_t sh[2][kBlock / 64 + 1];
+  const uint32_t c0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  uint32_t n[kScanPer];
+  uint32_t cnt = 0, oc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const uint32_t c = c0 + j;
+    n[j] = c < ncell ? (uint32_t)(cellacc[c] >> 32) : 0u;
+    cnt += n[j];
+    oc += n[j] ? 1u : 0u;
+  }
+  uint32_t t0, t1;
+  uint32_t p0 = block_exclusive_scan(cnt, sh[0], &t0) + blocksums[2 * blockIdx.x];
+  uint32_t p1 = block_exclusive_scan(oc, sh[1], &t1) + blocksums[2 * blockIdx.x + 1];
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const uint32_t c = c0 + j;
+    if (c < ncell) {
+      start[c] = p0;
+      if (n[j]) occ[p1++] = c;
+      p0 += n[j];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t total = blocksums[2 * nb], tocc = blocksums[2 * nb + 1];
+    start[ncell] = total;
+    ctr->n_occ = tocc;
+    ctr->n[dest] = total;
+    ctr->n_work = 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scatter(Bank a, Bank b, Counters* ctr, int which,
+                                                   const uint32_t* start, uint32_t cap) {
+  const uint32_t n = min(ctr->n[which], cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t w = a.w[i];
+    if (w == 0) continue;
+    const uint32_t cell = a.cell[i];
+    const uint32_t q = start[cell] + a.rank[i];
+    put<T>(b, q, cell, as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i], w, a.id[i]);
+  }
+}
+
+// ---- queries and reductions -----------------------------------------------------------
+
+__global__ void k_ngp(Bank a, Counters* ctr, int which, uint32_t* out, uint32_t cap) {
+  const uint32_t n = min(ctr->n[which], cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t w = a.w[i];
+    if (w) atomicAdd(&out[a.cell[i]], w);
+  }
+}
+
+__global__ void k_reduce_particles(Bank a, Counters* ctr, int which, unsigned long long* out,
+                                   uint32_t cap) {
+  const uint32_t n = min(ctr->n[which], cap);
+  uint64_t cnt = 0, W = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    if (i < n) {
+      const uint32_t w = a.w[i];
+      cnt += w ? 1 : 0;
+      W += w;
+    }
+  }
+  cnt = wave_sum64(cnt);
+  W = wave_sum64(W);
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], (unsigned long long)cnt);
+    atomicAdd(&out[1], (unsigned long long)W);
+  }
+}
+
+__global__ void k_reduce_cells(const uint32_t* p, const uint32_t* m, uint32_t ncell,
+                               unsigned long long* out) {
+  uint64_t sp = 0, sm = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < ncell; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    if (c < ncell) { sp += p[c]; sm += m[c]; }
+  }
+  sp = wave_sum64(sp);
+  sm = wave_sum64(sm);
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], (unsigned long long)sp);
+    atomicAdd(&out[1], (unsigned long long)sm);
+  }
+}
+
+__global__ void k_fires_dense(const uint32_t* occ, const uint32_t* occ_fires, const Counters* ctr,
+                              uint32_t* out) {
+  const uint32_t n = ctr->n_occ;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const uint32_t c = occ[j];
+    for (int r = 0; r < 3; ++r) out[3 * (size_t)c + r] = occ_fires[3 * (size_t)j + r];
+  }
+}
+
+__global__ void k_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, Key key,
+                              uint64_t n, uint4* out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = philox(make_uint4(c0 + (uint32_t)i, c1, c2, c3), key);
+}
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------------------
+
+static inline bool fp64(const itokmc_ctx* ctx) { return ctx->d.precision == ITOKMC_FP64; }
+
+hipError_t launch_seed_gaussian(itokmc_ctx* ctx, const itokmc_seed_desc* sd) {
+  StepConst k = make_const(ctx, 0.0);
+  const int g = grid_for(sd->n0);
+  if (fp64(ctx))
+    k_seed_gaussian<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, k,
+                                                       sd->n0, sd->centre[0], sd->centre[1],
+                                                       sd->centre[2], sd->sigma);
+  else
+    k_seed_gaussian<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, k,
+                                                      sd->n0, sd->centre[0], sd->centre[1],
+                                                      sd->centre[2], sd->sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_neutral(itokmc_ctx* ctx, const itokmc_seed_desc* sd) {
+  StepConst k = make_const(ctx, 0.0);
+  const int g = grid_for(ctx->ncell);
+  if (fp64(ctx))
+    k_seed_neutral<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, k,
+                                                      ctx->nplus, ctx->d.n_new, sd->n_peak,
+                                                      sd->centre[0], sd->centre[1], sd->centre[2],
+                                                      sd->sigma);
+  else
+    k_seed_neutral<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, k,
+                                                     ctx->nplus, ctx->d.n_new, sd->n_peak,
+                                                     sd->centre[0], sd->centre[1], sd->centre[2],
+                                                     sd->sigma);
+  return hipGetLastError();
+}
+
+static int particle_grid(const itokmc_ctx* ctx) {
+  // persistent-style grid: enough blocks to fill 256 CUs several times over
+  return grid_for(ctx->cap, kBlock, 4096);
+}
+
+hipError_t launch_push_uniform(itokmc_ctx* ctx, const StepConst& k) {
+  const int g = particle_grid(ctx);
+  if (fp64(ctx))
+    k_push_uniform<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
+                                                      ctx->cellacc, k);
+  else
+    k_push_uniform<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
+                                                     ctx->cellacc, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(itokmc_ctx* ctx) {
+  k_count<<<particle_grid(ctx), kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
+                                                     ctx->cellacc, (uint32_t)ctx->cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_photons(itokmc_ctx* ctx, const StepConst& k) {
+  if (!(ctx->c.kgamma_ratio > 0.0)) return hipSuccess;
+  const int g = grid_for(ctx->ncell, kBlock, 16384);
+  if (fp64(ctx))
+    k_photons<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
+                                                 ctx->cellacc, ctx->ngamma, ctx->nplus, k,
+                                                 ctx->d.n_new, ctx->c.photon_l1, ctx->c.photon_l2);
+  else
+    k_photons<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
+                                                ctx->cellacc, ctx->ngamma, ctx->nplus, k,
+                                                ctx->d.n_new, ctx->c.photon_l1, ctx->c.photon_l2);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(itokmc_ctx* ctx) {
+  const uint32_t nb = (ctx->ncell + kScanTile - 1) / kScanTile;
+  k_scan_reduce<<<nb, kBlock, 0, ctx->s>>>(ctx->cellacc, ctx->ncell, ctx->blocksums);
+  k_scan_top<<<1, 1024, 0, ctx->s>>>(ctx->blocksums, nb);
+  k_scan_down<<<nb, kBlock, 0, ctx->s>>>(ctx->cellacc, ctx->ncell, ctx->blocksums, nb, ctx->start,
+                                        ctx->occ, ctx->ctr, 1 - ctx->cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(itokmc_ctx* ctx) {
+  const int g = particle_grid(ctx);
+  if (fp64(ctx))
+    k_scatter<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->bank[1 - ctx->cur],
+                                                 ctx->ctr, ctx->cur, ctx->start, (uint32_t)ctx->cap);
+  else
+    k_scatter<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->bank[1 - ctx->cur],
+                                                ctx->ctr, ctx->cur, ctx->start, (uint32_t)ctx->cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_ngp(itokmc_ctx* ctx, uint32_t* out) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(uint32_t) * ctx->ncell, ctx->s);
+  if (e != hipSuccess) return e;
+  k_ngp<<<particle_grid(ctx), kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, out,
+                                                   (uint32_t)ctx->cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_particles(itokmc_ctx* ctx, unsigned long long* out2) {
+  k_reduce_particles<<<particle_grid(ctx), kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr,
+                                                                ctx->cur, out2, (uint32_t)ctx->cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_cells(itokmc_ctx* ctx, unsigned long long* out2) {
+  k_reduce_cells<<<grid_for(ctx->ncell, kBlock, 4096), kBlock, 0, ctx->s>>>(
+      ctx->nplus, ctx->nminus, ctx->ncell, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_fires_dense(itokmc_ctx* ctx, uint32_t* out) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(uint32_t) * 3 * (size_t)ctx->ncell, ctx->s);
+  if (e != hipSuccess) return e;
+  k_fires_dense<<<grid_for(ctx->ncell, kBlock, 4096), kBlock, 0, ctx->s>>>(ctx->occ, ctx->occ_fires,
+                                                                           ctx->ctr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1, uint64_t n, uint32_t* out, hipStream_t s) {
+  k_philox_fill<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(c0, c1, c2, c3, Key{k0, k1}, n,
+                                                             reinterpret_cast<uint4*>(out));
+  return hipGetLastError();
+}
+
+}  // namespace itk

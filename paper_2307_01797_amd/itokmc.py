@@ -1,0 +1,342 @@
+"""Python binding of libitokmc (the C ABI in include/itokmc.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of the
+library.  PyTorch supplies the device arena and the stream.  Importing this module on
+a machine without the built library raises immediately; there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libitokmc.so")
+
+OK, EINVAL, ENOMEM, ECAPACITY, ENOCONV, EHIP = 0, -1, -2, -3, -4, -5
+FP32, FP64 = 0, 1
+FIELD_UNIFORM, FIELD_POISSON = 0, 1
+KMC_HYBRID, KMC_PURE_TAU = 0, 1
+SEED_GAUSSIAN, SEED_NEUTRAL = 0, 1
+Q_NGP_WEIGHT, Q_NPLUS, Q_NMINUS, Q_NGAMMA, Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ, Q_FIRES = range(10)
+
+EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
+           "itokmc_seed_particles", "itokmc_step", "itokmc_transport", "itokmc_react",
+           "itokmc_deposit", "itokmc_diagnostics", "itokmc_get_particles",
+           "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
+           "itokmc_get_field", "itokmc_set_field", "itokmc_destroy", "itokmc_last_error",
+           "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_set_profiling",
+           "itokmc_phase_times"]
+PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
+          "field_push", "count"]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("field_mode", ctypes.c_int32), ("kmc_mode", ctypes.c_int32),
+                ("E_uniform", ctypes.c_double * 3), ("V_anode", ctypes.c_double),
+                ("n_ppc", ctypes.c_int32), ("n_new", ctypes.c_int32),
+                ("kmc_nc", ctypes.c_int32), ("kmc_nssa", ctypes.c_int32),
+                ("kmc_eps", ctypes.c_double), ("seed", ctypes.c_uint32),
+                ("realization", ctypes.c_uint32), ("max_particles", ctypes.c_uint64),
+                ("gmg_max_cycles", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("gmg_rtol", ctypes.c_double)]
+
+
+class Coeffs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("mu_a", "mu_E0", "mu_b", "E_floor", "D", "alpha_A",
+                                               "alpha_B", "eta", "kgamma_ratio", "photon_l1",
+                                               "photon_l2")]
+
+
+class SeedDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad0", ctypes.c_int32), ("n0", ctypes.c_uint64),
+                ("centre", ctypes.c_double * 3), ("sigma", ctypes.c_double),
+                ("n_peak", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_uint64), ("weight", ctypes.c_uint64),
+                ("n_plus", ctypes.c_int64), ("n_minus", ctypes.c_int64),
+                ("charge", ctypes.c_int64), ("outflow_weight", ctypes.c_uint64),
+                ("fires", ctypes.c_uint64 * 3), ("photons_emitted", ctypes.c_uint64),
+                ("photons_absorbed", ctypes.c_uint64), ("photons_lost", ctypes.c_uint64),
+                ("created", ctypes.c_uint64), ("removed_weight", ctypes.c_uint64),
+                ("merged_cells", ctypes.c_uint64), ("step", ctypes.c_uint32),
+                ("solver_cycles", ctypes.c_int32), ("solver_relres", ctypes.c_double),
+                ("rho_sum", ctypes.c_double), ("overflow", ctypes.c_uint32),
+                ("pad0", ctypes.c_uint32), ("particle_steps", ctypes.c_uint64)]
+
+    def as_dict(self):
+        d = {}
+        for n, _ in self._fields_:
+            if n.startswith("pad"):
+                continue
+            v = getattr(self, n)
+            d[n] = list(v) if n == "fires" else v
+        return d
+
+
+class ItokmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"itokmc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libitokmc.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIBPATH)
+        P, U32, U64, I32, D = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                               ctypes.c_double)
+        L.itokmc_arena_bytes.restype = ctypes.c_size_t
+        L.itokmc_arena_bytes.argtypes = [ctypes.POINTER(GridDesc)]
+        L.itokmc_init_grid.argtypes = [ctypes.POINTER(P), ctypes.POINTER(GridDesc), P,
+                                       ctypes.c_size_t, P]
+        L.itokmc_set_coefficients.argtypes = [P, ctypes.POINTER(Coeffs)]
+        L.itokmc_seed_particles.argtypes = [P, ctypes.POINTER(SeedDesc)]
+        L.itokmc_step.argtypes = [P, U32, D]
+        L.itokmc_transport.argtypes = [P, D]
+        L.itokmc_react.argtypes = [P, D]
+        L.itokmc_deposit.argtypes = [P, I32, P]
+        L.itokmc_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
+        L.itokmc_get_particles.argtypes = [P, ctypes.POINTER(U64), P, P, P, P]
+        L.itokmc_set_particles.argtypes = [P, U64, P, P, P, P]
+        L.itokmc_get_counts.argtypes = [P, I32, P]
+        L.itokmc_set_counts.argtypes = [P, I32, P]
+        L.itokmc_set_step.argtypes = [P, U32]
+        L.itokmc_get_field.argtypes = [P, P]
+        L.itokmc_set_field.argtypes = [P, P]
+        L.itokmc_destroy.argtypes = [P]
+        L.itokmc_destroy.restype = None
+        L.itokmc_last_error.argtypes = [P]
+        L.itokmc_last_error.restype = ctypes.c_char_p
+        L.itokmc_philox_fill.argtypes = [U32, U32, U32, U32, U32, U32, U64, P, P]
+        L.itokmc_kmc_cells.argtypes = [P, U64, P, P, P, D, U32, P]
+        L.itokmc_set_profiling.argtypes = [P, I32]
+        L.itokmc_phase_times.argtypes = [P, P, P, I32, I32]
+        _lib = L
+    return _lib
+
+
+def _np(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_desc(cfg, precision=None, max_particles=None):
+    d = GridDesc()
+    d.nx, d.ny, d.nz = cfg["grid"]
+    prec = precision or cfg.get("precision", "fp32")
+    d.precision = FP64 if prec == "fp64" else FP32
+    d.dx = cfg["dx"]
+    d.field_mode = FIELD_POISSON if cfg.get("field") == "poisson" else FIELD_UNIFORM
+    d.kmc_mode = KMC_PURE_TAU if cfg.get("kmc") == "pure_tau" else KMC_HYBRID
+    d.E_uniform = (ctypes.c_double * 3)(*cfg.get("E", (0.0, 0.0, 0.0)))
+    d.V_anode = cfg.get("V_anode", 0.0)
+    d.n_ppc = cfg.get("n_ppc", 0)
+    d.n_new = cfg.get("n_new", 64)
+    d.kmc_nc = cfg.get("kmc_nc", 5)
+    d.kmc_nssa = cfg.get("kmc_nssa", 10)
+    d.kmc_eps = cfg.get("kmc_eps", math.inf)
+    d.seed = cfg.get("seed", 1)
+    d.realization = cfg.get("realization", 0)
+    d.max_particles = int(max_particles or cfg.get("max_particles", 4_000_000))
+    d.gmg_max_cycles = cfg.get("gmg_max_cycles", 50)
+    d.gmg_rtol = cfg.get("gmg_rtol", 1e-10)
+    return d
+
+
+def make_coeffs(cfg):
+    c = Coeffs()
+    for n, _ in Coeffs._fields_:
+        setattr(c, n, cfg["coeffs"][n])
+    return c
+
+
+class Sim:
+    """One realization resident on a GPU."""
+
+    def __init__(self, cfg, device="cuda:0", precision=None, max_particles=None, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = lib()
+        self._desc = make_desc(cfg, precision, max_particles)
+        nbytes = L.itokmc_arena_bytes(ctypes.byref(self._desc))
+        if nbytes == 0:
+            raise ItokmcError(EINVAL, "invalid grid descriptor")
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ncell = int(np.prod(cfg["grid"]))
+        h = ctypes.c_void_p()
+        rc = L.itokmc_init_grid(ctypes.byref(h), ctypes.byref(self._desc),
+                                ctypes.c_void_p(self.arena.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != OK:
+            raise ItokmcError(rc, "init_grid failed")
+        self.h = h
+        self._check(L.itokmc_set_coefficients(self.h, ctypes.byref(make_coeffs(cfg))))
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = lib().itokmc_last_error(self.h).decode()
+            raise ItokmcError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().itokmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ---------------------------------------------------------------------
+    def seed(self):
+        cfg = self.cfg
+        sd = SeedDesc()
+        sd.centre = (ctypes.c_double * 3)(*cfg["seed_centre"])
+        sd.sigma = cfg["seed_sigma"]
+        if cfg["seed_kind"] == "gaussian":
+            sd.kind = SEED_GAUSSIAN
+            sd.n0 = cfg["seed_n0"]
+        else:
+            sd.kind = SEED_NEUTRAL
+            sd.n_peak = cfg["seed_peak"]
+        return self._check(lib().itokmc_seed_particles(self.h, ctypes.byref(sd)))
+
+    # -- stepping ------------------------------------------------------------------
+    def step(self, n=1, dt=None):
+        return self._check(lib().itokmc_step(self.h, n, dt or self.cfg["dt"]))
+
+    def step_rc(self, n=1, dt=None):
+        return lib().itokmc_step(self.h, n, dt or self.cfg["dt"])
+
+    def transport(self, dt=None):
+        return self._check(lib().itokmc_transport(self.h, dt or self.cfg["dt"]))
+
+    def react(self, dt=None):
+        return self._check(lib().itokmc_react(self.h, dt or self.cfg["dt"]))
+
+    def set_step(self, k):
+        return self._check(lib().itokmc_set_step(self.h, k))
+
+    # -- queries -------------------------------------------------------------------
+    def diagnostics(self, check=True):
+        d = Diag()
+        rc = lib().itokmc_diagnostics(self.h, ctypes.byref(d))
+        if check:
+            self._check(rc)
+        return d.as_dict()
+
+    def particles(self):
+        n = ctypes.c_uint64()
+        self._check(lib().itokmc_get_particles(self.h, ctypes.byref(n), None, None, None, None))
+        N = n.value
+        cell = np.zeros(N, dtype=np.uint32)
+        off = np.zeros((N, 3), dtype=np.float64)
+        w = np.zeros(N, dtype=np.uint32)
+        ids = np.zeros(N, dtype=np.uint64)
+        self._check(lib().itokmc_get_particles(self.h, ctypes.byref(n), _np(cell), _np(off), _np(w),
+                                               _np(ids)))
+        assert n.value == N
+        return cell, off, w, ids
+
+    def set_particles(self, cell, off, w, ids):
+        cell = np.ascontiguousarray(cell, dtype=np.uint32)
+        off = np.ascontiguousarray(off, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.uint32)
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        return self._check(lib().itokmc_set_particles(self.h, len(w), _np(cell), _np(off), _np(w),
+                                                      _np(ids)))
+
+    def counts(self, which):
+        q = {"plus": Q_NPLUS, "minus": Q_NMINUS, "gamma": Q_NGAMMA}[which]
+        v = np.zeros(self.ncell, dtype=np.uint32)
+        self._check(lib().itokmc_get_counts(self.h, q, _np(v)))
+        return v
+
+    def set_counts(self, which, v):
+        q = {"plus": Q_NPLUS, "minus": Q_NMINUS, "gamma": Q_NGAMMA}[which]
+        v = np.ascontiguousarray(v, dtype=np.uint32)
+        return self._check(lib().itokmc_set_counts(self.h, q, _np(v)))
+
+    def deposit(self, what):
+        torch = self.torch
+        q = {"ngp": Q_NGP_WEIGHT, "plus": Q_NPLUS, "minus": Q_NMINUS, "gamma": Q_NGAMMA,
+             "cic": Q_CIC_DENSITY, "phi": Q_PHI, "ex": Q_EX, "ey": Q_EY, "ez": Q_EZ,
+             "fires": Q_FIRES}[what]
+        if q in (Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ):
+            out = torch.empty(self.ncell, dtype=torch.float64, device=self.device)
+        elif q == Q_FIRES:
+            out = torch.empty(self.ncell * 3, dtype=torch.int32, device=self.device)
+        else:
+            out = torch.empty(self.ncell, dtype=torch.int32, device=self.device)
+        self._check(lib().itokmc_deposit(self.h, q, ctypes.c_void_p(out.data_ptr())))
+        self.stream.synchronize()
+        a = out.cpu().numpy()
+        if q == Q_FIRES:
+            return a.view(np.uint32).reshape(self.ncell, 3)
+        if a.dtype == np.int32:
+            return a.view(np.uint32)
+        return a
+
+    def set_profiling(self, on):
+        return self._check(lib().itokmc_set_profiling(self.h, 1 if on else 0))
+
+    def phase_times(self, reset=True):
+        """{phase: (total ms, launches)} from HIP events on the library's stream."""
+        n = len(PHASES)
+        ms = np.zeros(n)
+        calls = np.zeros(n, dtype=np.uint64)
+        self._check(lib().itokmc_phase_times(self.h, _np(ms), _np(calls), n, 1 if reset else 0))
+        return {p: (float(ms[i]), int(calls[i])) for i, p in enumerate(PHASES)}
+
+    def field(self):
+        phi = np.zeros(self.ncell)
+        self._check(lib().itokmc_get_field(self.h, _np(phi)))
+        return phi
+
+    def set_field(self, phi):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        return self._check(lib().itokmc_set_field(self.h, _np(phi)))
+
+    def kmc_cells(self, X, k, dt, step, cell_ids=None):
+        """One KMC step on independent cells (kernel-level entry point)."""
+        torch = self.torch
+        X = np.ascontiguousarray(X, dtype=np.int64)
+        n = X.shape[0]
+        ids = np.arange(n, dtype=np.uint32) if cell_ids is None else np.asarray(cell_ids, np.uint32)
+        dX = torch.from_numpy(X.copy()).to(self.device)
+        dk = torch.from_numpy(np.ascontiguousarray(k, dtype=np.float64)).to(self.device)
+        di = torch.from_numpy(ids.astype(np.int32)).to(self.device)
+        df = torch.zeros((n, 3), dtype=torch.int64, device=self.device)
+        self.stream.synchronize()
+        self._check(lib().itokmc_kmc_cells(self.h, n, ctypes.c_void_p(di.data_ptr()),
+                                           ctypes.c_void_p(dX.data_ptr()),
+                                           ctypes.c_void_p(dk.data_ptr()), dt, step,
+                                           ctypes.c_void_p(df.data_ptr())))
+        self.stream.synchronize()
+        return dX.cpu().numpy(), df.cpu().numpy()
+
+
+def philox_fill(c0, c1, c2, c3, k0, k1, n, device="cuda:0"):
+    import torch
+    out = torch.empty(4 * n, dtype=torch.int32, device=device)
+    rc = lib().itokmc_philox_fill(c0, c1, c2, c3, k0, k1, n, ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream))
+    if rc != OK:
+        raise ItokmcError(rc, "philox_fill")
+    torch.cuda.synchronize(device)
+    return out.cpu().numpy().view(np.uint32).reshape(n, 4)

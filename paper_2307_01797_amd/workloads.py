@@ -46,9 +46,20 @@ STREAMER_64 = dict(STREAMER_256, name="streamer_64", grid=(64, 64, 64), dx=1e-3 
                    steps=200, max_particles=4_000_000)
 
 
+# Avalanche at streamer scale: the plain-method physics of AVALANCHE_32 on the
+# streamer's 256^3 grid (dx = 3.9 um), 5e7 weight-1 electrons in a Gaussian blob
+# (sigma = 150 um), FP32 state.  Exercises push, binning, NGP deposit, KMC and coupling
+# at the particle count of the self-consistent workload.
+AVALANCHE_256 = dict(
+    AVALANCHE_32, name="avalanche_256", grid=(256, 256, 256), dx=1e-3 / 256,
+    precision="fp32", seed_n0=50_000_000, seed_centre=(0.5e-3, 0.5e-3, 0.5e-3),
+    seed_sigma=150e-6, max_particles=110_000_000, steps=40,
+)
+
+
 def preset(name, **overrides):
     base = {"avalanche_32": AVALANCHE_32, "streamer_256": STREAMER_256,
-            "streamer_64": STREAMER_64}[name]
+            "streamer_64": STREAMER_64, "avalanche_256": AVALANCHE_256}[name]
     cfg = copy.deepcopy(base)
     for k, v in overrides.items():
         if k == "coeffs":

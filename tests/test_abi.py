@@ -1,0 +1,54 @@
+"""The C-ABI library loads on the host and exports every entry point its header
+declares (no compute calls: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "itokmc.h")
+LIB = os.path.join(ROOT, "paper_2307_01797_amd", "libitokmc.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(itokmc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("itokmc_init_grid", "itokmc_seed_particles", "itokmc_set_coefficients",
+              "itokmc_step", "itokmc_deposit", "itokmc_diagnostics"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_export_list_matches_header():
+    from paper_2307_01797_amd import itokmc
+    assert sorted(itokmc.EXPORTS) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_arena_size_and_descriptor_validation():
+    from paper_2307_01797_amd import itokmc, workloads
+    L = itokmc.lib()
+    d = itokmc.make_desc(workloads.preset("avalanche_32"), max_particles=1000)
+    n = L.itokmc_arena_bytes(ctypes.byref(d))
+    assert n > 32**3 * 8
+    bad = itokmc.make_desc(workloads.preset("avalanche_32"), max_particles=1000)
+    bad.n_new = 65
+    assert L.itokmc_arena_bytes(ctypes.byref(bad)) == 0
+    bad = itokmc.make_desc(workloads.preset("avalanche_32", grid=(512, 512, 512)))
+    assert L.itokmc_arena_bytes(ctypes.byref(bad)) == 0
+    # init rejects a null arena without touching the device
+    h = ctypes.c_void_p()
+    assert L.itokmc_init_grid(ctypes.byref(h), ctypes.byref(d), None, n, None) == itokmc.EINVAL
