@@ -73,7 +73,7 @@ typedef struct {
   int32_t kmc_mode;        /* ITOKMC_KMC_HYBRID | ITOKMC_KMC_PURE_TAU                */
   double E_uniform[3];     /* prescribed field (V/m), uniform mode                   */
   double V_anode;          /* potential of z = L (V), Poisson mode                   */
-  int32_t n_ppc;           /* superparticle target per cell; 0 = no merge/split      */
+  int32_t n_ppc;           /* superparticle target per cell (<= 64); 0 = no merge    */
   int32_t n_new;           /* max computational particles made per cell and step     */
   int32_t kmc_nc;          /* critical-reaction threshold N_c                        */
   int32_t kmc_nssa;        /* max SSA events per SSA excursion                        */
@@ -122,6 +122,8 @@ typedef struct {
   uint32_t overflow;              /* nonzero if a capacity limit was hit             */
   uint32_t pad0;
   uint64_t particle_steps;        /* cumulative live particles advanced by transport */
+  uint32_t merge_skipped;         /* cells whose particles exceeded the merge staging */
+  uint32_t pad1;
 } itokmc_diag;
 
 /* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid). */

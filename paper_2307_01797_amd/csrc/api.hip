@@ -115,7 +115,7 @@ static bool valid_desc(const itokmc_grid_desc* d) {
   if (d->field_mode != ITOKMC_FIELD_UNIFORM && d->field_mode != ITOKMC_FIELD_POISSON) return false;
   if (d->kmc_mode != ITOKMC_KMC_HYBRID && d->kmc_mode != ITOKMC_KMC_PURE_TAU) return false;
   if (d->n_new < 1 || d->n_new > 64) return false;
-  if (d->n_ppc < 0 || d->n_ppc > 256) return false;
+  if (d->n_ppc < 0 || d->n_ppc > 64) return false;
   if (d->kmc_nc < 0 || d->kmc_nssa < 1) return false;
   if (!(d->kmc_eps > 0.0)) return false;
   if (d->max_particles < 1 || d->max_particles > 0x7FFFFFFFull) return false;
@@ -403,6 +403,7 @@ int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
   out->rho_sum = 1.602176634e-19 * (double)out->charge;
   out->overflow = c.overflow;
   out->particle_steps = c.pushed;
+  out->merge_skipped = c.merge_skipped;
   if (c.overflow) return set_error(ctx, ITOKMC_ECAPACITY, "capacity exceeded (flags %u)", c.overflow);
   return ITOKMC_OK;
 }

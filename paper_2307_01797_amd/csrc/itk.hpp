@@ -35,6 +35,8 @@ struct Counters {
   unsigned long long fires[3];
   unsigned long long ph_emitted, ph_absorbed, ph_lost;
   unsigned long long pushed;   // live particles advanced by the transport kernels
+  uint32_t merge_skipped;      // cells too large for the LDS merge (left unmerged)
+  uint32_t pad2;
 };
 
 // Device-side copy of the per-step constants shared by the kernels.

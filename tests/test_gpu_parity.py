@@ -204,3 +204,84 @@ def test_determinism(itk):
         out.append(by_id(ids, cell, off, w))
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_merge_paper_example(itk, orc, prec, tol):
+    """1000 particles uniform in one cell with weights uniform on 1..100, merged to 64
+    (the paper's superparticle example) through the react path: leaves, weights and
+    ids identical to the oracle's merge, centroids within tolerance."""
+    cfg = workloads.preset("avalanche_32", grid=(4, 4, 4), n_ppc=64, coeffs=dict(alpha_A=0.0, eta=0.0))
+    g = itk.Sim(cfg, precision=prec, max_particles=4096)
+    rng = np.random.default_rng(2023)
+    m = 1000
+    c = 1 + 4 * (2 + 4 * 3)
+    g.set_particles(np.full(m, c), rng.random((m, 3)), rng.integers(1, 101, m),
+                    rng.permutation(m).astype(np.uint64) + np.uint64(5))
+    cell, off, w, ids = g.particles()          # exactly what the GPU holds
+    lo, lw, li = orc.merge_cell(64, off, w.astype(np.uint64), ids, cell=c, step=0)
+    g.react()
+    cell2, off2, w2, ids2 = g.particles()
+    assert np.all(cell2 == c)
+    ids2, off2, w2 = by_id(ids2, off2, w2)
+    li, lo, lw = by_id(li, lo, lw)
+    assert np.array_equal(ids2, li)
+    assert np.array_equal(w2.astype(np.uint64), lw)
+    assert int(lw.max()) - int(lw.min()) <= 1
+    assert np.abs(off2 - lo).max() < tol
+
+
+def test_merge_split_small_cells(itk, orc):
+    """Cells with a few heavy particles are split up to N_ppc; cells above N_ppc merged."""
+    cfg = workloads.preset("avalanche_32", grid=(6, 6, 6), n_ppc=16, coeffs=dict(alpha_A=0.0, eta=0.0))
+    g = itk.Sim(cfg, precision="fp64", max_particles=20000)
+    rng = np.random.default_rng(9)
+    cells, offs, ws, idl = [], [], [], []
+    nid = 1
+    for c in range(216):
+        k = int(rng.choice([1, 2, 3, 16, 17, 40, 300]))
+        wmax = int(rng.choice([1, 5, 1000]))
+        for _ in range(k):
+            cells.append(c); offs.append(rng.random(3)); ws.append(int(rng.integers(1, wmax + 1)))
+            idl.append(nid); nid += 1
+    g.set_particles(np.array(cells), np.array(offs), np.array(ws), np.array(idl, dtype=np.uint64))
+    o = _oracle_from_gpu(orc, cfg, g)
+    g.react()
+    o.react(cfg["dt"])
+    assert _compare(g, o, cfg, 1e-12) == 0
+    _compare_tallies(g, o)
+
+
+def test_merge_free_running_fp64(itk, orc):
+    cfg = workloads.preset("avalanche_32", n_ppc=16, coeffs=dict(kgamma_ratio=0.06))
+    g = itk.Sim(cfg, precision="fp64", max_particles=600_000)
+    g.seed()
+    o = orc.Sim(cfg)
+    o.seed_gaussian(cfg["seed_n0"], cfg["seed_centre"], cfg["seed_sigma"])
+    for target in (1, 10, 40):
+        n = target - g.diagnostics()["step"]
+        g.step(n)
+        o.step(cfg["dt"], n)
+        assert _compare(g, o, cfg, 1e-9) == 0
+        _compare_tallies(g, o)
+    assert g.diagnostics()["merged_cells"] > 0
+
+
+def test_merge_fp32_resync(itk, orc):
+    cfg = workloads.preset("avalanche_32", precision="fp32", n_ppc=32, coeffs=dict(kgamma_ratio=0.06))
+    g = itk.Sim(cfg, precision="fp32", max_particles=600_000)
+    g.seed()
+    g.step(10)
+    for _ in range(6):
+        g.transport()
+        o = _oracle_from_gpu(orc, cfg, g)
+        g.react()
+        o.react(cfg["dt"])
+        assert _compare(g, o, cfg, 2e-6) == 0
+        _compare_tallies_react(g, o)
+
+
+def _compare_tallies_react(g, o):
+    dg, do = g.diagnostics(), o.diagnostics()
+    for key in ("n_particles", "weight", "n_plus", "n_minus"):
+        assert dg[key] == do[key], (key, dg[key], do[key])
