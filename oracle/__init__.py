@@ -353,6 +353,12 @@ class Sim:
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         lib().or_set_field(self.h, _p(phi))
 
+    def set_efield(self, Ex, Ey, Ez):
+        E = [np.ascontiguousarray(a, dtype=np.float64) for a in (Ex, Ey, Ez)]
+        L = lib()
+        L.or_set_efield.argtypes = [ctypes.c_void_p] * 4
+        L.or_set_efield(self.h, *[_p(a) for a in E])
+
 
 def photon_sample(cfg, cell, slot, step):
     d = make_desc(cfg)

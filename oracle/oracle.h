@@ -142,6 +142,8 @@ void or_efield(const or_desc* d, const double* phi, double* Ex, double* Ey, doub
 /* Access to the current field of a simulation (Poisson mode). */
 void or_get_field(const or_sim* s, double* phi, double* Ex, double* Ey, double* Ez);
 void or_set_field(or_sim* s, const double* phi);
+/* Set the cell-centred field used by the next transport (as E^k) and reactions. */
+void or_set_efield(or_sim* s, const double* Ex, const double* Ey, const double* Ez);
 
 /* CIC helpers on an arbitrary point set (grid units). */
 void or_cic_deposit(const or_desc* d, uint64_t n, const double* xi, const double* q,

@@ -270,6 +270,15 @@ void or_get_field(const or_sim* s, double* phi, double* Ex, double* Ey, double* 
   if (Ez) memcpy(Ez, s->Ez, nb);
 }
 
+void or_set_efield(or_sim* s, const double* Ex, const double* Ey, const double* Ez) {
+  if (s->d.field_mode != OR_FIELD_POISSON) return;
+  size_t nb = sizeof(double) * (size_t)s->ncell;
+  memcpy(s->Ex, Ex, nb);
+  memcpy(s->Ey, Ey, nb);
+  memcpy(s->Ez, Ez, nb);
+  s->field_valid = 1;
+}
+
 void or_set_field(or_sim* s, const double* phi) {
   if (s->d.field_mode != OR_FIELD_POISSON) return;
   memcpy(s->phi, phi, sizeof(double) * (size_t)s->ncell);

@@ -319,9 +319,10 @@ int itokmc_react(itokmc_ctx* ctx, double dt) {
   phase_begin(ctx, PH_SCATTER);
   if (!rc) rc = check_hip(ctx, launch_scatter(ctx), "scatter");
   phase_end(ctx, PH_SCATTER);
-  const double* rates = ctx->d.field_mode == ITOKMC_FIELD_POISSON ? field_cell_rates(ctx) : nullptr;
+  FieldRates fr{};
+  if (ctx->d.field_mode == ITOKMC_FIELD_POISSON) fr = field_rates(ctx);
   phase_begin(ctx, PH_KMC);
-  if (!rc) rc = check_hip(ctx, launch_kmc_step(ctx, k, rates), "kmc");
+  if (!rc) rc = check_hip(ctx, launch_kmc_step(ctx, k, fr), "kmc");
   phase_end(ctx, PH_KMC);
   phase_begin(ctx, PH_COUPLE);
   if (!rc) rc = check_hip(ctx, launch_couple(ctx, k), "couple");
@@ -556,6 +557,7 @@ void itokmc_destroy(itokmc_ctx* ctx) {
   hipStreamSynchronize(ctx->s);
   for (auto& u : ctx->ev_used) { hipEventDestroy(u.second.first); hipEventDestroy(u.second.second); }
   for (auto e : ctx->ev_free) hipEventDestroy(e);
+  field_destroy(ctx);
   if (ctx->host_ctr) hipHostFree(ctx->host_ctr);
   delete ctx;
 }

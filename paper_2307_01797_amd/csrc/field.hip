@@ -1,5 +1,28 @@
-// Field-coupled (Poisson) mode and CIC transfers.
+// Self-consistent field mode: the semi-implicit Euler-Maruyama step of the paper's
+// "Final algorithm" (steps 1-5) and its field solve.
+//
+//   1. sigma^k = e sum_p mu_p w_p W(x - X_p^k) / dV with mu_p = mu(|E^k(X_p^k)|)
+//      (eq. conductivity, electrons only; ions are immobile);
+//   2. X_dagger = X^k + sqrt(2 D dt) N, regenerated from the particle's push stream;
+//   3. rho_dagger = e (n+ - n- - CIC(X_dagger)) / dV, solve
+//      div[(1 + sigma dt / eps0) grad phi] = -rho_dagger / eps0 (eq. poisson_simp) with
+//      phi = 0 at z = 0, phi = V at z = L, homogeneous Neumann on x and y;
+//   4-5. X^{k+1} = X_dagger - mu_p E^{k+1}(X^k) dt, binned by cell as in the uniform push.
+//
+// Discretisation: cell-centred finite volumes, 7-point stencil, face coefficients the
+// harmonic mean of the two cell values, a Dirichlet face using the cell's own value
+// over half a cell; E at cell centres by central differences with ghost values from
+// the same conditions; CIC deposit/interpolation with tent weights about cell centres,
+// clouds folded into the wall cells.
+//
+// Solver: geometric multigrid V(2,2) cycles with red-black Gauss-Seidel, cell-averaged
+// restriction and piecewise-constant prolongation, run in the working precision on the
+// correction equation of an iterative-refinement loop whose residual and potential
+// are kept in double; the loop stops at ||r||_2 <= rtol ||b||_2 (the paper's relative
+// multigrid tolerance, 1e-10 by default).
 #include <math.h>
+
+#include <vector>
 
 #include "device.hpp"
 #include "itk.hpp"
@@ -8,23 +31,701 @@ namespace itk {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ const T* cas(const void* p) { return reinterpret_cast<const T*>(p); }
+constexpr double kE = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr int kMaxLevels = 12;
+constexpr int kBottomMaxCells = 4096;
 
-// Clamped tent weights along one axis about cell centres (i + 1/2): lower node and the
-// weight of the upper node; the part of a cloud beyond the outermost centres folds
-// into the wall cell.
-__device__ __forceinline__ void tent(double xi, int n, int& i0, double& f) {
-  double s = xi - 0.5;
-  s = s < 0.0 ? 0.0 : s;
-  s = s > (double)(n - 1) ? (double)(n - 1) : s;
-  if (n == 1) { i0 = 0; f = 0.0; return; }
-  int i = (int)floor(s);
-  i = i > n - 2 ? n - 2 : i;
+struct Level {
+  int nx, ny, nz;
+  uint32_t n;
+  void* u;    // correction
+  void* f;    // right-hand side (scaled by h^2)
+  void* eps;  // cell coefficient 1 + sigma dt / eps0
+};
+
+struct Coef {
+  double mu_a, mu_E0, mu_b, E_floor, D;
+};
+
+template <typename T>
+__device__ __forceinline__ T* tp(void* p) { return reinterpret_cast<T*>(p); }
+template <typename T>
+__device__ __forceinline__ const T* ctp(const void* p) { return reinterpret_cast<const T*>(p); }
+
+__device__ __forceinline__ double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
+__device__ __forceinline__ float hmean(float a, float b) { return 2.0f * a * b / (a + b); }
+
+// ---- CIC helpers ------------------------------------------------------------------
+
+// Lower tent node and weight of the upper node along one axis for a particle in cell c
+// with offset t from the cell's lower face (t may leave [0,1) for X_dagger).
+template <typename T>
+__device__ __forceinline__ void tent_axis(int c, T t, int n, int& i0, T& f) {
+  const T s = t - (T)0.5;
+  const T fl = floor(s);
+  int i = c + (int)fl;
+  T fr = s - fl;
+  if (n == 1) { i0 = 0; f = (T)0; return; }
+  if (i < 0) { i = 0; fr = (T)0; }
+  if (i > n - 2) { i = n - 2; fr = (T)1; }
   i0 = i;
-  f = s - (double)i;
+  f = fr;
 }
 
+template <typename T>
+__device__ __forceinline__ void cic_add(T* grid, const StepConst& K, int i0, int j0, int k0, T fx,
+                                        T fy, T fz, T q) {
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
+    const T wt = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
+    const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
+    if (wt == (T)0 || ii >= nx || jj >= ny || kk >= nz) continue;
+    atomicAdd(&grid[(size_t)ii + (size_t)nx * ((size_t)jj + (size_t)ny * kk)], q * wt);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T cic_get(const T* grid, const StepConst& K, int i0, int j0, int k0, T fx,
+                                     T fy, T fz) {
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
+  T acc = (T)0;
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
+    const T wt = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
+    const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
+    if (wt == (T)0 || ii >= nx || jj >= ny || kk >= nz) continue;
+    acc += grid[(size_t)ii + (size_t)nx * ((size_t)jj + (size_t)ny * kk)] * wt;
+  }
+  return acc;
+}
+
+template <typename T> struct Mob;
+template <> struct Mob<double> {
+  __device__ static double mu(const Coef& c, double E) {
+    const double Ec = E > c.E_floor ? E : c.E_floor;
+    return c.mu_a * pow(Ec / c.mu_E0, c.mu_b);
+  }
+};
+template <> struct Mob<float> {
+  // mu_a (E / E0)^b with hardware exp2/log2
+  __device__ static float mu(const Coef& c, float E) {
+    const float Ec = E > (float)c.E_floor ? E : (float)c.E_floor;
+    return (float)c.mu_a *
+           __builtin_amdgcn_exp2f((float)c.mu_b * __builtin_amdgcn_logf(Ec / (float)c.mu_E0));
+  }
+};
+
+template <typename T> struct NormalsF;
+template <> struct NormalsF<double> {
+  __device__ static void get(uint4 r, double n[3]) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const double r0 = sqrt(-2.0 * log(u_oc(r.x)));
+    const double t0 = two_pi * u_co(r.y);
+    const double r1 = sqrt(-2.0 * log(u_oc(r.z)));
+    const double t1 = two_pi * u_co(r.w);
+    n[0] = r0 * cos(t0);
+    n[1] = r0 * sin(t0);
+    n[2] = r1 * cos(t1);
+  }
+};
+template <> struct NormalsF<float> {
+  __device__ static void get(uint4 r, float n[3]) {
+    const float m2ln2 = -1.3862943611198906f;
+    const float r0 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.x)));
+    const float r1 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.z)));
+    const float a0 = (float)(r.y >> 8) * 0x1p-24f;
+    const float a1 = (float)(r.w >> 8) * 0x1p-24f;
+    n[0] = r0 * __builtin_amdgcn_cosf(a0);
+    n[1] = r0 * __builtin_amdgcn_sinf(a0);
+    n[2] = r1 * __builtin_amdgcn_cosf(a1);
+  }
+};
+
+// ---- particle passes --------------------------------------------------------------
+
+// mode 0: electron number at X^k only (initial field); mode 1: sigma at X^k and the
+// electron number at X_dagger.
+template <typename T>
+__global__ void __launch_bounds__(256) k_field_deposit(Bank a, const Counters* ctr, int which,
+                                                      StepConst K, const void* Ex, const void* Ey,
+                                                      const void* Ez, Coef co, int mode, T* sig,
+                                                      T* ne) {
+  const uint32_t n = min(ctr->n[which], K.cap);
+  const T diff = (T)K.diff;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t w = a.w[i];
+    if (!w) continue;
+    const uint32_t cell = a.cell[i];
+    const int ci = (int)(cell % (uint32_t)K.nx), cj = (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
+              ck = (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny));
+    const T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
+    int i0, j0, k0;
+    T fx, fy, fz;
+    tent_axis<T>(ci, o[0], K.nx, i0, fx);
+    tent_axis<T>(cj, o[1], K.ny, j0, fy);
+    tent_axis<T>(ck, o[2], K.nz, k0, fz);
+    if (mode == 0) {
+      cic_add<T>(ne, K, i0, j0, k0, fx, fy, fz, (T)w);
+      continue;
+    }
+    const T e[3] = {cic_get<T>(ctp<T>(Ex), K, i0, j0, k0, fx, fy, fz),
+                    cic_get<T>(ctp<T>(Ey), K, i0, j0, k0, fx, fy, fz),
+                    cic_get<T>(ctp<T>(Ez), K, i0, j0, k0, fx, fy, fz)};
+    const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    const T mu = Mob<T>::mu(co, Em);
+    cic_add<T>(sig, K, i0, j0, k0, fx, fy, fz, mu * (T)w);
+    const uint64_t id = a.id[i];
+    const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
+    T nr[3];
+    NormalsF<T>::get(r, nr);
+    tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
+    tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
+    tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
+    cic_add<T>(ne, K, i0, j0, k0, fx, fy, fz, (T)w);
+  }
+}
+
+// Semi-implicit push: X^{k+1} = X^k + sqrt(2 D dt) N - mu(|E^k(X^k)|) E^{k+1}(X^k) dt,
+// then binning exactly as the uniform push.
+template <typename T>
+__global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int which,
+                                                   unsigned long long* cellacc, StepConst K,
+                                                   const void* Eox, const void* Eoy, const void* Eoz,
+                                                   const void* Enx, const void* Eny, const void* Enz,
+                                                   Coef co) {
+  const uint32_t n = min(ctr->n[which], K.cap);
+  const T diff = (T)K.diff;
+  const T dtdx = (T)(K.dt / K.dx);
+  uint64_t out_w = 0, pushed = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t key = kInvalidCell, w = 0;
+    if (i < n) w = a.w[i];
+    if (w > 0) {
+      ++pushed;
+      const uint32_t cell = a.cell[i];
+      int ci[3] = {(int)(cell % (uint32_t)K.nx), (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
+                   (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny))};
+      T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
+      int i0, j0, k0;
+      T fx, fy, fz;
+      tent_axis<T>(ci[0], o[0], K.nx, i0, fx);
+      tent_axis<T>(ci[1], o[1], K.ny, j0, fy);
+      tent_axis<T>(ci[2], o[2], K.nz, k0, fz);
+      const T eo[3] = {cic_get<T>(ctp<T>(Eox), K, i0, j0, k0, fx, fy, fz),
+                       cic_get<T>(ctp<T>(Eoy), K, i0, j0, k0, fx, fy, fz),
+                       cic_get<T>(ctp<T>(Eoz), K, i0, j0, k0, fx, fy, fz)};
+      const T en[3] = {cic_get<T>(ctp<T>(Enx), K, i0, j0, k0, fx, fy, fz),
+                       cic_get<T>(ctp<T>(Eny), K, i0, j0, k0, fx, fy, fz),
+                       cic_get<T>(ctp<T>(Enz), K, i0, j0, k0, fx, fy, fz)};
+      const T mu = Mob<T>::mu(co, sqrt(eo[0] * eo[0] + eo[1] * eo[1] + eo[2] * eo[2]));
+      const uint64_t id = a.id[i];
+      const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
+      T nr[3];
+      NormalsF<T>::get(r, nr);
+      const int lim[3] = {K.nx, K.ny, K.nz};
+      bool inside = true;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        T x = (o[ax] + diff * nr[ax]) + (-mu * en[ax]) * dtdx;
+        T f = floor(x);
+        x -= f;
+        if (x >= (T)1) { x -= (T)1; f += (T)1; }
+        o[ax] = x;
+        ci[ax] += (int)f;
+        inside = inside && ci[ax] >= 0 && ci[ax] < lim[ax];
+      }
+      if (inside) {
+        key = (uint32_t)ci[0] + (uint32_t)K.nx * ((uint32_t)ci[1] + (uint32_t)K.ny * (uint32_t)ci[2]);
+        a.cell[i] = key;
+        tp<T>(a.ox)[i] = o[0];
+        tp<T>(a.oy)[i] = o[1];
+        tp<T>(a.oz)[i] = o[2];
+      } else {
+        out_w += w;
+        a.w[i] = 0;
+      }
+    }
+    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+  }
+  out_w = wave_sum64(out_w);
+  pushed = wave_sum64(pushed);
+  if (lane_id() == 0) {
+    if (out_w) atomicAdd(&ctr->outflow, (unsigned long long)out_w);
+    if (pushed) atomicAdd(&ctr->pushed, (unsigned long long)pushed);
+  }
+}
+
+// ---- grid passes ------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_zero(T* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = (T)0;
+}
+
+// Fine-level coefficient and right-hand side b = dx^2 rho / eps0 (+ the lift of the
+// anode potential on the top layer), both scaled by dx^2; accumulates ||b||^2.
+template <typename T>
+__global__ void k_field_prep(StepConst K, const uint32_t* nplus, const uint32_t* nminus,
+                             const T* ne, const T* sig, double sig_scale, double V, T* eps,
+                             double* b, double* norms) {
+  const uint32_t n = K.ncell;
+  const double dV = K.dx * K.dx * K.dx;
+  const double qscale = K.dx * K.dx * kE / (kEps0 * dV);
+  double acc = 0.0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    double bb = 0.0;
+    if (c < n) {
+      const double e = 1.0 + sig_scale * (double)sig[c];
+      eps[c] = (T)e;
+      const double rho_units = (double)nplus[c] - (double)nminus[c] - (double)ne[c];
+      bb = qscale * rho_units;
+      const uint32_t k = c / ((uint32_t)K.nx * (uint32_t)K.ny);
+      if (k == (uint32_t)K.nz - 1) bb += 2.0 * (double)(T)e * V;
+      b[c] = bb;
+    }
+    acc += bb * bb;
+  }
+  acc = wave_sumd(acc);
+  if (lane_id() == 0) atomicAdd(&norms[0], acc);
+}
+
+template <typename T>
+__global__ void k_eps_restrict(const T* ef, int fnx, int fny, T* ec, int cnx, int cny, int cnz) {
+  const uint32_t n = (uint32_t)cnx * cny * cnz;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int i = c % cnx, j = (c / cnx) % cny, k = c / (cnx * cny);
+    double s = 0.0;
+    for (int d = 0; d < 8; ++d) {
+      const int fi = 2 * i + (d & 1), fj = 2 * j + ((d >> 1) & 1), fk = 2 * k + (d >> 2);
+      s += (double)ef[(size_t)fi + (size_t)fnx * ((size_t)fj + (size_t)fny * fk)];
+    }
+    ec[c] = (T)(s * 0.125);
+  }
+}
+
+// Operator of the scaled system at one cell (homogeneous boundary values):
+// sum over faces of beta (u_c - u_nb) plus 2 eps_c u_c on the Dirichlet faces.
+template <typename R, typename U, typename E>
+__device__ __forceinline__ void stencil(const U* u, const E* eps, int nx, int ny, int nz, int i, int j,
+                                        int k, R& diag, R& offsum) {
+  const size_t c = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
+  const R ec = (R)eps[c];
+  R d = 0, s = 0;
+  if (i > 0) { const R b = hmean(ec, (R)eps[c - 1]); d += b; s += b * (R)u[c - 1]; }
+  if (i < nx - 1) { const R b = hmean(ec, (R)eps[c + 1]); d += b; s += b * (R)u[c + 1]; }
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  if (j > 0) { const R b = hmean(ec, (R)eps[c - sy]); d += b; s += b * (R)u[c - sy]; }
+  if (j < ny - 1) { const R b = hmean(ec, (R)eps[c + sy]); d += b; s += b * (R)u[c + sy]; }
+  if (k > 0) { const R b = hmean(ec, (R)eps[c - sz]); d += b; s += b * (R)u[c - sz]; }
+  else d += (R)2 * ec;
+  if (k < nz - 1) { const R b = hmean(ec, (R)eps[c + sz]); d += b; s += b * (R)u[c + sz]; }
+  else d += (R)2 * ec;
+  diag = d;
+  offsum = s;
+}
+
+// r = b - A phi in double with the true boundary values (the lift is in b); writes the
+// working-precision right-hand side of the correction equation and ||r||^2.
+template <typename T>
+__global__ void k_residual64(const double* phi, const double* b, const T* eps, int nx, int ny, int nz,
+                             T* f0, double* norms) {
+  const uint32_t n = (uint32_t)nx * ny * nz;
+  double acc = 0.0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    double r = 0.0;
+    if (c < n) {
+      const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+      double d, s;
+      stencil<double, double, T>(phi, eps, nx, ny, nz, i, j, k, d, s);
+      r = b[c] - (d * phi[c] - s);
+      f0[c] = (T)r;
+    }
+    acc += r * r;
+  }
+  acc = wave_sumd(acc);
+  if (lane_id() == 0) atomicAdd(&norms[1], acc);
+}
+
+template <typename T>
+__global__ void k_smooth(T* u, const T* f, const T* eps, int nx, int ny, int nz, int color) {
+  const uint32_t n = (uint32_t)nx * ny * nz;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    if (((i + j + k) & 1) != color) continue;
+    T d, s;
+    stencil<T, T, T>(u, eps, nx, ny, nz, i, j, k, d, s);
+    u[c] = (f[c] + s) / d;
+  }
+}
+
+// Coarse right-hand side from the fine residual: with both levels scaled by their own
+// h^2, f_coarse = 4 * mean of the 8 child residuals = (sum of the 8) / 2.  Also zeroes
+// the coarse correction.
+template <typename T>
+__global__ void k_resid_restrict(const T* u, const T* f, const T* eps, int nx, int ny, int nz, T* fc,
+                                 T* uc, int cnx, int cny, int cnz) {
+  const uint32_t n = (uint32_t)cnx * cny * cnz;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int ci = c % cnx, cj = (c / cnx) % cny, ck = c / (cnx * cny);
+    T s8 = 0;
+    for (int d = 0; d < 8; ++d) {
+      const int i = 2 * ci + (d & 1), j = 2 * cj + ((d >> 1) & 1), k = 2 * ck + (d >> 2);
+      T dg, sm;
+      stencil<T, T, T>(u, eps, nx, ny, nz, i, j, k, dg, sm);
+      const size_t q = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
+      s8 += f[q] - (dg * u[q] - sm);
+    }
+    fc[c] = s8 * (T)0.5;
+    uc[c] = (T)0;
+  }
+}
+
+template <typename T>
+__global__ void k_prolong(T* u, int nx, int ny, int nz, const T* uc, int cnx, int cny) {
+  const uint32_t n = (uint32_t)nx * ny * nz;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    u[c] += uc[(size_t)(i >> 1) + (size_t)cnx * ((size_t)(j >> 1) + (size_t)cny * (k >> 1))];
+  }
+}
+
+// Coarsest level: red-black sweeps from zero inside one workgroup.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                                int sweeps) {
+  const int n = nx * ny * nz;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = (T)0;
+  __syncthreads();
+  for (int s = 0; s < sweeps; ++s)
+    for (int color = 0; color < 2; ++color) {
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        if (((i + j + k) & 1) != color) continue;
+        T d, sm;
+        stencil<T, T, T>(u, eps, nx, ny, nz, i, j, k, d, sm);
+        u[c] = (f[c] + sm) / d;
+      }
+      __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_phi_update(double* phi, const T* u, uint32_t n) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    phi[c] += (double)u[c];
+}
+
+template <typename T>
+__global__ void k_efield(const double* phi, int nx, int ny, int nz, double V, double inv2h, T* Ex, T* Ey,
+                         T* Ez) {
+  const uint32_t n = (uint32_t)nx * ny * nz;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    const double pc = phi[c];
+    const double xm = i > 0 ? phi[c - 1] : pc, xp = i < nx - 1 ? phi[c + 1] : pc;
+    const double ym = j > 0 ? phi[c - sy] : pc, yp = j < ny - 1 ? phi[c + sy] : pc;
+    const double zm = k > 0 ? phi[c - sz] : -pc, zp = k < nz - 1 ? phi[c + sz] : 2.0 * V - pc;
+    Ex[c] = (T)(-(xp - xm) * inv2h);
+    Ey[c] = (T)(-(yp - ym) * inv2h);
+    Ez[c] = (T)(-(zp - zm) * inv2h);
+  }
+}
+
+template <typename T>
+__global__ void k_to_double(const T* a, double* out, uint32_t n) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+    out[c] = (double)a[c];
+}
+
+inline int blocks(uint64_t n, int max_blocks = 16384) {
+  uint64_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+}  // namespace
+
+// ---- host side ------------------------------------------------------------------------
+
+struct FieldState {
+  int nlev = 0;
+  Level lev[kMaxLevels];
+  double* phi = nullptr;
+  double* b = nullptr;
+  void* E[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  int cur = 0;        // E[cur] holds the latest field
+  void* sig = nullptr;
+  void* ne = nullptr;
+  double* norms = nullptr;   // device: ||b||^2, ||r||^2
+  double* host_norms = nullptr;
+};
+
+static int build_levels(const itokmc_grid_desc* d, int dims[kMaxLevels][3]) {
+  int nl = 0;
+  int nx = d->nx, ny = d->ny, nz = d->nz;
+  for (;;) {
+    dims[nl][0] = nx; dims[nl][1] = ny; dims[nl][2] = nz;
+    ++nl;
+    const int mn = nx < ny ? (nx < nz ? nx : nz) : (ny < nz ? ny : nz);
+    if (nl == kMaxLevels || mn < 8 || (nx | ny | nz) & 1) break;
+    nx /= 2; ny /= 2; nz /= 2;
+  }
+  return nl;
+}
+
+size_t field_bytes(const itokmc_grid_desc* d) {
+  if (d->field_mode != ITOKMC_FIELD_POISSON) return 0;
+  const size_t T = d->precision == ITOKMC_FP64 ? 8 : 4;
+  const size_t n = (size_t)d->nx * d->ny * d->nz;
+  int dims[kMaxLevels][3];
+  const int nl = build_levels(d, dims);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t total = al(n * 8) * 2 + al(n * T) * 6 + al(n * T) * 2 + al(64);
+  for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
+  return total;
+}
+
+static FieldState* fs(itokmc_ctx* ctx) { return reinterpret_cast<FieldState*>(ctx->field_state); }
+
+int field_init(itokmc_ctx* ctx, char* base) {
+  const itokmc_grid_desc* d = &ctx->d;
+  int dims[kMaxLevels][3];
+  const int nl = build_levels(d, dims);
+  const uint64_t bottom = (uint64_t)dims[nl - 1][0] * dims[nl - 1][1] * dims[nl - 1][2];
+  if (bottom > (uint64_t)kBottomMaxCells)
+    return set_error(ctx, ITOKMC_EINVAL, "grid cannot be coarsened to <= %d cells (dims must be even)",
+                     kBottomMaxCells);
+  FieldState* F = new FieldState();
+  const size_t T = d->precision == ITOKMC_FP64 ? 8 : 4;
+  const size_t n = ctx->ncell;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char* p = base;
+  F->phi = (double*)p; p += al(n * 8);
+  F->b = (double*)p; p += al(n * 8);
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < 3; ++a) { F->E[s][a] = p; p += al(n * T); }
+  F->sig = p; p += al(n * T);
+  F->ne = p; p += al(n * T);
+  F->norms = (double*)p; p += al(64);
+  F->nlev = nl;
+  for (int l = 0; l < nl; ++l) {
+    Level& L = F->lev[l];
+    L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
+    L.n = (uint32_t)((size_t)L.nx * L.ny * L.nz);
+    L.u = p; p += al(L.n * T);
+    L.f = p; p += al(L.n * T);
+    L.eps = p; p += al(L.n * T);
+  }
+  hipError_t e = hipHostMalloc((void**)&F->host_norms, 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(F->phi, 0, n * 8, ctx->s);
+  for (int s = 0; s < 2 && e == hipSuccess; ++s)
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = hipMemsetAsync(F->E[s][a], 0, n * T, ctx->s);
+  if (e != hipSuccess) {
+    delete F;
+    return check_hip(ctx, e, "field init");
+  }
+  ctx->field_state = F;
+  return ITOKMC_OK;
+}
+
+void field_destroy(itokmc_ctx* ctx) {
+  FieldState* F = fs(ctx);
+  if (!F) return;
+  if (F->host_norms) hipHostFree(F->host_norms);
+  delete F;
+  ctx->field_state = nullptr;
+}
+
+static Coef coef(const itokmc_ctx* ctx) {
+  return Coef{ctx->c.mu_a, ctx->c.mu_E0, ctx->c.mu_b, ctx->c.E_floor, ctx->c.D};
+}
+
+template <typename T>
+static void vcycle(itokmc_ctx* ctx, FieldState* F, int l) {
+  Level& L = F->lev[l];
+  hipStream_t s = ctx->s;
+  T* u = (T*)L.u;
+  const T* f = (const T*)L.f;
+  const T* ep = (const T*)L.eps;
+  if (l == F->nlev - 1) {
+    int mx = L.nx > L.ny ? L.nx : L.ny;
+    mx = mx > L.nz ? mx : L.nz;
+    k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 8 * mx + 40);
+    return;
+  }
+  Level& C = F->lev[l + 1];
+  const int g = blocks(L.n);
+  for (int it = 0; it < 2; ++it) {
+    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
+    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
+  }
+  k_resid_restrict<T><<<blocks(C.n), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx,
+                                                  C.ny, C.nz);
+  vcycle<T>(ctx, F, l + 1);
+  k_prolong<T><<<g, 256, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny);
+  for (int it = 0; it < 2; ++it) {
+    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
+    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
+  }
+}
+
+// Solve with the current right-hand side b and fine coefficient lev[0].eps.
+template <typename T>
+static int solve(itokmc_ctx* ctx, FieldState* F) {
+  hipStream_t s = ctx->s;
+  Level& L0 = F->lev[0];
+  for (int l = 1; l < F->nlev; ++l) {
+    Level& Fl = F->lev[l - 1];
+    Level& Cl = F->lev[l];
+    k_eps_restrict<T><<<blocks(Cl.n), 256, 0, s>>>((const T*)Fl.eps, Fl.nx, Fl.ny, (T*)Cl.eps, Cl.nx,
+                                                   Cl.ny, Cl.nz);
+  }
+  const int maxc = ctx->d.gmg_max_cycles > 0 ? ctx->d.gmg_max_cycles : 50;
+  double bn2 = 0.0, rn2 = 0.0;
+  int cyc = 0;
+  for (;; ++cyc) {
+    hipError_t e = hipMemsetAsync(F->norms + 1, 0, 8, s);
+    if (e != hipSuccess) return check_hip(ctx, e, "solve");
+    k_residual64<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
+                                                 (T*)L0.f, F->norms);
+    e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return check_hip(ctx, e, "solve residual");
+    bn2 = F->host_norms[0];
+    rn2 = F->host_norms[1];
+    const double bn = bn2 > 0.0 ? sqrt(bn2) : 1.0;
+    ctx->last_relres = sqrt(rn2) / bn;
+    ctx->last_cycles = cyc;
+    if (sqrt(rn2) <= ctx->d.gmg_rtol * bn) break;
+    if (cyc >= maxc) return set_error(ctx, ITOKMC_ENOCONV, "field solve: relres %.3e after %d cycles",
+                                      ctx->last_relres, cyc);
+    k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
+    vcycle<T>(ctx, F, 0);
+    k_phi_update<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, (const T*)L0.u, L0.n);
+  }
+  return check_hip(ctx, hipGetLastError(), "solve");
+}
+
+// Deposit (mode 0 initial / 1 semi-implicit), right-hand side, solve, E into E[next].
+template <typename T>
+static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K, int mode) {
+  hipStream_t s = ctx->s;
+  const uint32_t n = ctx->ncell;
+  phase_begin(ctx, PH_DEPOSIT);
+  k_zero<T><<<blocks(n), 256, 0, s>>>((T*)F->sig, n);
+  k_zero<T><<<blocks(n), 256, 0, s>>>((T*)F->ne, n);
+  void* const* Eo = F->E[F->cur];
+  k_field_deposit<T><<<blocks(ctx->cap, 8192), 256, 0, s>>>(
+      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1], Eo[2], coef(ctx), mode, (T*)F->sig,
+      (T*)F->ne);
+  hipError_t e = hipMemsetAsync(F->norms, 0, 16, s);
+  if (e != hipSuccess) return check_hip(ctx, e, "deposit");
+  const double sig_scale = mode == 1 ? kE * K.dt / (kEps0 * K.dx * K.dx * K.dx) : 0.0;
+  k_field_prep<T><<<blocks(n), 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const T*)F->ne,
+                                            (const T*)F->sig, sig_scale, ctx->d.V_anode,
+                                            (T*)F->lev[0].eps, F->b, F->norms);
+  phase_end(ctx, PH_DEPOSIT);
+  phase_begin(ctx, PH_SOLVE);
+  const int rc = solve<T>(ctx, F);
+  const int nxt = 1 - F->cur;
+  k_efield<T><<<blocks(n), 256, 0, s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz, ctx->d.V_anode,
+                                        1.0 / (2.0 * ctx->d.dx), (T*)F->E[nxt][0], (T*)F->E[nxt][1],
+                                        (T*)F->E[nxt][2]);
+  phase_end(ctx, PH_SOLVE);
+  return rc ? rc : check_hip(ctx, hipGetLastError(), "field");
+}
+
+template <typename T>
+static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
+  FieldState* F = fs(ctx);
+  if (!ctx->field_valid) {
+    // initial field: the solution for the present charge with sigma = 0
+    const int rc = deposit_and_solve<T>(ctx, F, K, 0);
+    if (rc) return rc;
+    F->cur = 1 - F->cur;
+    ctx->field_valid = true;
+  }
+  const int rc = deposit_and_solve<T>(ctx, F, K, 1);
+  if (rc) return rc;
+  const int nxt = 1 - F->cur;
+  phase_begin(ctx, PH_FIELD_PUSH);
+  k_push_field<T><<<blocks(ctx->cap, 4096), 256, 0, ctx->s>>>(
+      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, K, F->E[F->cur][0], F->E[F->cur][1],
+      F->E[F->cur][2], F->E[nxt][0], F->E[nxt][1], F->E[nxt][2], coef(ctx));
+  phase_end(ctx, PH_FIELD_PUSH);
+  F->cur = nxt;  // E^{k+1} becomes the field of the next step
+  return check_hip(ctx, hipGetLastError(), "field push");
+}
+
+int field_transport(itokmc_ctx* ctx, const StepConst& K) {
+  return ctx->d.precision == ITOKMC_FP64 ? transport_t<double>(ctx, K) : transport_t<float>(ctx, K);
+}
+
+FieldRates field_rates(itokmc_ctx* ctx) {
+  FieldState* F = fs(ctx);
+  FieldRates r{};
+  if (!F) return r;
+  for (int a = 0; a < 3; ++a) r.E[a] = F->E[F->cur][a];
+  r.is_double = ctx->d.precision == ITOKMC_FP64 ? 1 : 0;
+  r.mu_a = ctx->c.mu_a; r.mu_E0 = ctx->c.mu_E0; r.mu_b = ctx->c.mu_b; r.E_floor = ctx->c.E_floor;
+  r.alpha_A = ctx->c.alpha_A; r.alpha_B = ctx->c.alpha_B; r.eta = ctx->c.eta;
+  r.kgamma_ratio = ctx->c.kgamma_ratio;
+  return r;
+}
+
+int field_get_phi(itokmc_ctx* ctx, double* host) {
+  FieldState* F = fs(ctx);
+  hipError_t e = hipStreamSynchronize(ctx->s);
+  if (e == hipSuccess) e = hipMemcpy(host, F->phi, (size_t)ctx->ncell * 8, hipMemcpyDeviceToHost);
+  return check_hip(ctx, e, "get_field");
+}
+
+int field_set_phi(itokmc_ctx* ctx, const double* host) {
+  FieldState* F = fs(ctx);
+  hipError_t e = hipStreamSynchronize(ctx->s);
+  if (e == hipSuccess) e = hipMemcpy(F->phi, host, (size_t)ctx->ncell * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return check_hip(ctx, e, "set_field");
+  const uint32_t n = ctx->ncell;
+  if (ctx->d.precision == ITOKMC_FP64)
+    k_efield<double><<<blocks(n), 256, 0, ctx->s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz,
+                                                    ctx->d.V_anode, 1.0 / (2.0 * ctx->d.dx),
+                                                    (double*)F->E[F->cur][0], (double*)F->E[F->cur][1],
+                                                    (double*)F->E[F->cur][2]);
+  else
+    k_efield<float><<<blocks(n), 256, 0, ctx->s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz,
+                                                   ctx->d.V_anode, 1.0 / (2.0 * ctx->d.dx),
+                                                   (float*)F->E[F->cur][0], (float*)F->E[F->cur][1],
+                                                   (float*)F->E[F->cur][2]);
+  ctx->field_valid = true;
+  return check_hip(ctx, hipGetLastError(), "set_field");
+}
+
+int field_deposit(itokmc_ctx* ctx, int what, void* dev_out) {
+  FieldState* F = fs(ctx);
+  const uint32_t n = ctx->ncell;
+  if (what == ITOKMC_Q_PHI)
+    return check_hip(ctx, hipMemcpyAsync(dev_out, F->phi, (size_t)n * 8, hipMemcpyDeviceToDevice, ctx->s),
+                     "deposit phi");
+  const int a = what - ITOKMC_Q_EX;
+  if (ctx->d.precision == ITOKMC_FP64)
+    k_to_double<double><<<blocks(n), 256, 0, ctx->s>>>((const double*)F->E[F->cur][a], (double*)dev_out, n);
+  else
+    k_to_double<float><<<blocks(n), 256, 0, ctx->s>>>((const float*)F->E[F->cur][a], (double*)dev_out, n);
+  return check_hip(ctx, hipGetLastError(), "deposit E");
+}
+
+// CIC electron density of the current particles (diagnostic query), double atomics.
+namespace {
 template <typename T>
 __global__ void k_cic_density(Bank a, const Counters* ctr, int which, StepConst K, double inv_dV,
                               double* out) {
@@ -32,27 +733,15 @@ __global__ void k_cic_density(Bank a, const Counters* ctr, int which, StepConst 
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t w = a.w[i];
     if (!w) continue;
-    const uint32_t c = a.cell[i];
-    const double xi[3] = {(double)(c % (uint32_t)K.nx) + (double)cas<T>(a.ox)[i],
-                          (double)((c / (uint32_t)K.nx) % (uint32_t)K.ny) + (double)cas<T>(a.oy)[i],
-                          (double)(c / ((uint32_t)K.nx * (uint32_t)K.ny)) + (double)cas<T>(a.oz)[i]};
+    const uint32_t cell = a.cell[i];
     int i0, j0, k0;
     double fx, fy, fz;
-    tent(xi[0], K.nx, i0, fx);
-    tent(xi[1], K.ny, j0, fy);
-    tent(xi[2], K.nz, k0, fz);
-    const double q = (double)w * inv_dV;
-    for (int cc = 0; cc < 8; ++cc) {
-      const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
-      const double wt = (di ? fx : 1.0 - fx) * (dj ? fy : 1.0 - fy) * (dk ? fz : 1.0 - fz);
-      if (wt == 0.0) continue;
-      const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
-      if (ii >= K.nx || jj >= K.ny || kk >= K.nz) continue;
-      atomicAdd(&out[(size_t)ii + (size_t)K.nx * ((size_t)jj + (size_t)K.ny * kk)], q * wt);
-    }
+    tent_axis<double>((int)(cell % (uint32_t)K.nx), (double)ctp<T>(a.ox)[i], K.nx, i0, fx);
+    tent_axis<double>((int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny), (double)ctp<T>(a.oy)[i], K.ny, j0, fy);
+    tent_axis<double>((int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny)), (double)ctp<T>(a.oz)[i], K.nz, k0, fz);
+    cic_add<double>(out, K, i0, j0, k0, fx, fy, fz, (double)w * inv_dV);
   }
 }
-
 }  // namespace
 
 hipError_t launch_cic_density(itokmc_ctx* ctx, double* out) {
@@ -66,21 +755,5 @@ hipError_t launch_cic_density(itokmc_ctx* ctx, double* out) {
     k_cic_density<float><<<2048, 256, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, inv_dV, out);
   return hipGetLastError();
 }
-
-size_t field_bytes(const itokmc_grid_desc* d) {
-  if (d->field_mode != ITOKMC_FIELD_POISSON) return 0;
-  return 256;
-}
-
-int field_init(itokmc_ctx* ctx, char*) {
-  return set_error(ctx, ITOKMC_EINVAL, "Poisson field mode is not available in this build");
-}
-int field_transport(itokmc_ctx* ctx, const StepConst&) {
-  return set_error(ctx, ITOKMC_EINVAL, "Poisson field mode is not available in this build");
-}
-const double* field_cell_rates(itokmc_ctx*) { return nullptr; }
-int field_get_phi(itokmc_ctx* ctx, double*) { return set_error(ctx, ITOKMC_EINVAL, "no field"); }
-int field_set_phi(itokmc_ctx* ctx, const double*) { return set_error(ctx, ITOKMC_EINVAL, "no field"); }
-int field_deposit(itokmc_ctx* ctx, int, void*) { return set_error(ctx, ITOKMC_EINVAL, "no field"); }
 
 }  // namespace itk

@@ -52,6 +52,14 @@ struct StepConst {
   double k[3];       // uniform mode rates (1/s)
 };
 
+// Field view for per-cell KMC rates (Poisson mode): E at cell centres and the
+// coefficient forms; E[0] == nullptr means the prescribed uniform field.
+struct FieldRates {
+  const void* E[3];
+  int is_double;
+  double mu_a, mu_E0, mu_b, E_floor, alpha_A, alpha_B, eta, kgamma_ratio;
+};
+
 }  // namespace itk
 
 struct itokmc_ctx {
@@ -82,7 +90,8 @@ struct itokmc_ctx {
   bool binned = false;                    // bins of the current bank are filled
   itk::Counters* host_ctr = nullptr;      // pinned mirror
   // Poisson-mode field data (see field.hip)
-  void* field = nullptr;
+  void* field = nullptr;        // arena region
+  void* field_state = nullptr;  // host-side bookkeeping (FieldState)
   bool field_valid = false;
   int last_cycles = 0;
   double last_relres = 0.0;
@@ -121,7 +130,7 @@ hipError_t launch_fires_dense(itokmc_ctx* ctx, uint32_t* out);
 hipError_t launch_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                               uint32_t k1, uint64_t n, uint32_t* out, hipStream_t s);
 // kmc.hip
-hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const double* cell_rates);
+hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates& fr);
 hipError_t launch_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, int64_t* X,
                             const double* k, double dt, uint32_t step, int64_t* fires);
 // couple.hip
@@ -130,7 +139,8 @@ hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k);
 size_t field_bytes(const itokmc_grid_desc* d);
 int field_init(itokmc_ctx* ctx, char* base);
 int field_transport(itokmc_ctx* ctx, const StepConst& k);
-const double* field_cell_rates(itokmc_ctx* ctx);  // rates per cell for the KMC
+FieldRates field_rates(itokmc_ctx* ctx);  // E view for the KMC rates
+void field_destroy(itokmc_ctx* ctx);
 int field_get_phi(itokmc_ctx* ctx, double* host);
 int field_set_phi(itokmc_ctx* ctx, const double* host);
 int field_deposit(itokmc_ctx* ctx, int what, void* dev_out);

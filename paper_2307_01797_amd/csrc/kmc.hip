@@ -140,6 +140,22 @@ __device__ __forceinline__ void advance(const KmcParams& P, State& X, const doub
   else advance_hybrid(P, X, k, dt, st, f);
 }
 
+// Rates from |E| at the cell centre (local field approximation).
+__device__ void rates_at(const FieldRates& fr, uint32_t c, double k[3]) {
+  double e[3];
+  for (int a = 0; a < 3; ++a)
+    e[a] = fr.is_double ? reinterpret_cast<const double*>(fr.E[a])[c]
+                        : (double)reinterpret_cast<const float*>(fr.E[a])[c];
+  const double Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  const double Ec = Em > fr.E_floor ? Em : fr.E_floor;
+  const double mu = fr.mu_a * pow(Ec / fr.mu_E0, fr.mu_b);
+  const double alpha = Em > 0.0 ? fr.alpha_A * exp(-fr.alpha_B / Em) : 0.0;
+  const double v = mu * Em;
+  k[0] = alpha * v;
+  k[1] = fr.eta * v;
+  k[2] = fr.kgamma_ratio * k[0];
+}
+
 // Step kernel: occupied cells from the binning pass.  Writes the per-cell fires, the
 // updated ions and pending photons, the net electron change, clears the cell's bin
 // accumulator, and queues cells for the coupling pass.
@@ -148,8 +164,8 @@ __global__ void __launch_bounds__(256) k_kmc_step(KmcParams P, StepConst K, Coun
                                                  uint32_t* nplus, uint32_t* nminus,
                                                  uint32_t* ngamma, uint32_t* occ_fires, int32_t* dN,
                                                  uint32_t* work, uint32_t* cbase,
-                                                 const double* cell_rates, int queue_all,
-                                                 int n_new, int dest) {
+                                                 FieldRates fr, int queue_all, int n_new,
+                                                 int dest) {
   const uint32_t n = ctr->n_occ;
   uint64_t t0 = 0, t1 = 0, t2 = 0;
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
@@ -162,7 +178,7 @@ __global__ void __launch_bounds__(256) k_kmc_step(KmcParams P, StepConst K, Coun
       cellacc[c] = 0ull;
       State X{(int64_t)Xe, (int64_t)nplus[c], (int64_t)nminus[c], 0};
       double k[3];
-      if (cell_rates) { k[0] = cell_rates[3 * (size_t)c]; k[1] = cell_rates[3 * (size_t)c + 1]; k[2] = cell_rates[3 * (size_t)c + 2]; }
+      if (fr.E[0]) rates_at(fr, c, k);
       else { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
       CellStream st;
       st.init(c, K.step, TAG_KMC, 0, K.key);
@@ -218,13 +234,13 @@ KmcParams params(const itokmc_ctx* ctx) {
 
 }  // namespace
 
-hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const double* cell_rates) {
+hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates& fr) {
   int g = (int)((ctx->ncell + 255) / 256);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   k_kmc_step<<<g, 256, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
                                     ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
-                                    ctx->cbase, cell_rates, ctx->d.n_ppc > 0 ? 1 : 0, ctx->d.n_new,
+                                    ctx->cbase, fr, ctx->d.n_ppc > 0 ? 1 : 0, ctx->d.n_new,
                                     1 - ctx->cur);
   return hipGetLastError();
 }

@@ -285,3 +285,86 @@ def _compare_tallies_react(g, o):
     dg, do = g.diagnostics(), o.diagnostics()
     for key in ("n_particles", "weight", "n_plus", "n_minus"):
         assert dg[key] == do[key], (key, dg[key], do[key])
+
+
+# ---- self-consistent field mode -------------------------------------------------------
+
+def _streamer_small(**kw):
+    base = dict(grid=(16, 16, 16), dx=1e-3 / 64, seed_centre=(125e-6, 125e-6, 125e-6),
+                seed_sigma=30e-6, V_anode=18e3 * 0.25, gmg_rtol=1e-12, max_particles=400_000)
+    base.update(kw)
+    return workloads.preset("streamer_64", **base)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 2e-6)])
+def test_field_vacuum_gap(itk, prec, tol):
+    cfg = _streamer_small(grid=(8, 8, 32), V_anode=1000.0, dx=1e-3 / 32)
+    g = itk.Sim(cfg, precision=prec, max_particles=1000)
+    g.set_particles(np.zeros(0), np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.uint64))
+    g.transport()
+    ez = g.deposit("ez")
+    assert np.allclose(ez, -1000.0 / 1e-3, rtol=tol)
+    assert g.diagnostics()["solver_relres"] <= 1e-12
+
+
+def test_field_solve_matches_oracle(itk, orc):
+    """Semi-implicit solve after two steps of a neutral-plasma seed, both sides starting
+    from the same E^k: the potential agrees with the oracle's conjugate-gradient
+    solution to 1e-9 of its range."""
+    cfg = _streamer_small()
+    g = itk.Sim(cfg, precision="fp64")
+    g.seed()
+    g.step(2)
+    o = _oracle_from_gpu(orc, cfg, g)
+    o.set_field(g.field())   # E^k of both sides from the same potential
+    g.transport()
+    o.transport(cfg["dt"])
+    phi_g = g.field()
+    phi_o = o.field()[0]
+    assert np.abs(phi_g - phi_o).max() < 1e-9 * np.abs(phi_o).max()
+    assert _compare(g, o, cfg, 1e-9) == 0
+
+
+def test_streamer_fp64_free_running(itk, orc):
+    """Self-consistent streamer seed (16^3, neutral plasma, semi-implicit field, photons,
+    merge/split to 32 per cell), free-running FP64: every integer agrees."""
+    cfg = _streamer_small()
+    g = itk.Sim(cfg, precision="fp64")
+    g.seed()
+    o = orc.Sim(cfg)
+    o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+    assert _compare(g, o, cfg, 1e-12) == 0
+    for target in (1, 3, 6):
+        n = target - g.diagnostics()["step"]
+        g.step(n)
+        o.step(cfg["dt"], n)
+        assert _compare(g, o, cfg, 1e-9) == 0
+        _compare_tallies(g, o)
+    assert g.diagnostics()["merged_cells"] > 0
+
+
+def test_streamer_fp32_resync(itk, orc):
+    """FP32 state, single-precision multigrid with double residual refinement.
+    Transport from an identical state: potential within 1e-6 of its range, positions
+    within 1e-5 cells outside the tie band.  React with the GPU's E given to the oracle:
+    every integer agrees."""
+    cfg = _streamer_small(precision="fp32", gmg_rtol=1e-10)
+    g = itk.Sim(cfg, precision="fp32")
+    g.seed()
+    g.step(3)
+    nband = 0
+    for _ in range(3):
+        o = _oracle_from_gpu(orc, cfg, g)
+        o.set_field(g.field())
+        o.set_efield(g.deposit("ex"), g.deposit("ey"), g.deposit("ez"))
+        g.transport()
+        o.transport(cfg["dt"])
+        phi_g, phi_o = g.field(), o.field()[0]
+        assert np.abs(phi_g - phi_o).max() < 1e-6 * np.abs(phi_o).max()
+        nband += _compare(g, o, cfg, 1e-5, band=1e-5)
+        o = _oracle_from_gpu(orc, cfg, g)
+        o.set_efield(g.deposit("ex"), g.deposit("ey"), g.deposit("ez"))
+        g.react()
+        o.react(cfg["dt"])
+        assert _compare(g, o, cfg, 2e-6) == 0
+    assert nband <= 2
