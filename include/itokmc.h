@@ -124,6 +124,8 @@ typedef struct {
   uint64_t particle_steps;        /* cumulative live particles advanced by transport */
   uint32_t merge_skipped;         /* cells whose particles exceeded the merge staging */
   uint32_t pad1;
+  uint64_t solver_cycles_total;   /* multigrid cycles over all field solves          */
+  uint64_t solves_total;          /* field solves performed                           */
 } itokmc_diag;
 
 /* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid). */

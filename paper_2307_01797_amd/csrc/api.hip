@@ -405,6 +405,8 @@ int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
   out->overflow = c.overflow;
   out->particle_steps = c.pushed;
   out->merge_skipped = c.merge_skipped;
+  out->solver_cycles_total = ctx->total_cycles;
+  out->solves_total = ctx->total_solves;
   if (c.overflow) return set_error(ctx, ITOKMC_ECAPACITY, "capacity exceeded (flags %u)", c.overflow);
   return ITOKMC_OK;
 }

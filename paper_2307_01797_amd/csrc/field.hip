@@ -591,6 +591,7 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
                                                    Cl.ny, Cl.nz);
   }
   const int maxc = ctx->d.gmg_max_cycles > 0 ? ctx->d.gmg_max_cycles : 50;
+  ctx->total_solves += 1;
   double bn2 = 0.0, rn2 = 0.0;
   int cyc = 0;
   for (;; ++cyc) {
@@ -607,6 +608,7 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
     ctx->last_relres = sqrt(rn2) / bn;
     ctx->last_cycles = cyc;
     if (sqrt(rn2) <= ctx->d.gmg_rtol * bn) break;
+    ctx->total_cycles += 1;
     if (cyc >= maxc) return set_error(ctx, ITOKMC_ENOCONV, "field solve: relres %.3e after %d cycles",
                                       ctx->last_relres, cyc);
     k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);

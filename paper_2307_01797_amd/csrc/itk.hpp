@@ -94,6 +94,8 @@ struct itokmc_ctx {
   void* field_state = nullptr;  // host-side bookkeeping (FieldState)
   bool field_valid = false;
   int last_cycles = 0;
+  uint64_t total_cycles = 0;   // multigrid cycles over all solves
+  uint64_t total_solves = 0;
   double last_relres = 0.0;
   uint32_t step = 0;
   std::string err;

@@ -67,7 +67,8 @@ class Diag(ctypes.Structure):
                 ("solver_cycles", ctypes.c_int32), ("solver_relres", ctypes.c_double),
                 ("rho_sum", ctypes.c_double), ("overflow", ctypes.c_uint32),
                 ("pad0", ctypes.c_uint32), ("particle_steps", ctypes.c_uint64),
-                ("merge_skipped", ctypes.c_uint32), ("pad1", ctypes.c_uint32)]
+                ("merge_skipped", ctypes.c_uint32), ("pad1", ctypes.c_uint32),
+                ("solver_cycles_total", ctypes.c_uint64), ("solves_total", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {}
