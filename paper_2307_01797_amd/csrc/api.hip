@@ -153,6 +153,7 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(64);                            // 25 reduction scratch
   put(field_bytes(d));                // 26 field data
   put(nc * 4);                        // 27 cbase
+  put(nc * 4);                        // 28 big
   L->total = o;
 }
 
@@ -211,6 +212,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->reduce = (unsigned long long*)(a + L.off[25]);
   ctx->field = a + L.off[26];
   ctx->cbase = (uint32_t*)(a + L.off[27]);
+  ctx->big = (uint32_t*)(a + L.off[28]);
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);
@@ -226,7 +228,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   if (desc->field_mode == ITOKMC_FIELD_POISSON) {
     const int rc = field_init(ctx, (char*)ctx->field);
     if (rc != ITOKMC_OK) {
-      hipHostFree(ctx->host_ctr);
+      (void)hipHostFree(ctx->host_ctr);
       delete ctx;
       return rc;
     }
@@ -560,7 +562,7 @@ void itokmc_destroy(itokmc_ctx* ctx) {
   for (auto& u : ctx->ev_used) { hipEventDestroy(u.second.first); hipEventDestroy(u.second.second); }
   for (auto e : ctx->ev_free) hipEventDestroy(e);
   field_destroy(ctx);
-  if (ctx->host_ctr) hipHostFree(ctx->host_ctr);
+  if (ctx->host_ctr) (void)hipHostFree(ctx->host_ctr);
   delete ctx;
 }
 

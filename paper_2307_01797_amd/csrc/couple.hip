@@ -45,6 +45,9 @@ __device__ uint64_t remove_weight(Bank b, uint32_t s, uint32_t e, uint32_t R) {
       b.w[bi] = w - take;
     }
     take = __shfl(take, 0, 64);
+    // make lane 0's store visible to the whole wavefront before the next search
+    __syncthreads();
+    if (take == 0) break;  // no progress possible (cannot happen with consistent weights)
     R -= take;
     removed += take;
   }
@@ -56,7 +59,7 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
                                               const uint32_t* work, const uint32_t* occ,
                                               const uint32_t* start, const int32_t* dN,
                                               const uint32_t* cbase, int n_new, int n_ppc,
-                                              MergeScratch ms) {
+                                              uint32_t* big) {
   const uint32_t nwork = ctr->n_work;
   const int lane = lane_id();
   uint64_t created = 0, removed = 0, merged = 0;
@@ -73,35 +76,26 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
       wr = (uint32_t)d % M;
       base = cbase[j];  // slots reserved by the KMC pass
     }
-    // new particles, one per lane (n_new <= 64 per pass)
-    T no[3] = {0, 0, 0};
-    uint32_t nw = 0;
-    uint64_t nid = 0;
+    // new particles, one per lane (n_new <= 64), into the reserved slots
     if ((uint32_t)lane < M) {
       const uint4 r = philox_block(c, (uint32_t)lane, K.step, TAG_CREATE, 0, K.key);
-      no[0] = (T)u24(r.x); no[1] = (T)u24(r.y); no[2] = (T)u24(r.z);
-      nw = wb + (lane == 0 ? wr : 0u);
-      nid = make_id(KIND_KMC, K.step, c, (uint32_t)lane);
+      const uint32_t q = base + (uint32_t)lane;
+      if (q < K.cap) {
+        b.cell[q] = c;
+        as<T>(b.ox)[q] = (T)u24(r.x);
+        as<T>(b.oy)[q] = (T)u24(r.y);
+        as<T>(b.oz)[q] = (T)u24(r.z);
+        b.w[q] = wb + (lane == 0 ? wr : 0u);
+        b.id[q] = make_id(KIND_KMC, K.step, c, (uint32_t)lane);
+      } else {
+        atomicOr(&ctr->overflow, 1u);
+      }
     }
     created += M;
-    bool handled = false;
     if (n_ppc > 0) {
-      handled = merge_cell<T>(b, ctr, which, K, c, s, e, M, base, no, nw, nid, n_ppc, ms, &merged);
-    }
-    if (!handled && M > 0) {
-      if ((uint32_t)lane < M) {
-        const uint32_t q = base + (uint32_t)lane;
-        if (q < K.cap) {
-          b.cell[q] = c;
-          as<T>(b.ox)[q] = no[0];
-          as<T>(b.oy)[q] = no[1];
-          as<T>(b.oz)[q] = no[2];
-          b.w[q] = nw;
-          b.id[q] = nid;
-        } else {
-          atomicOr(&ctr->overflow, 1u);
-        }
-      }
+      __syncthreads();  // removal and product stores visible before the merge gathers them
+      const int r = merge_cell<T, kMergeSmall>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
+      if (r == 2 && lane == 0) big[atomicAdd(&ctr->n_big, 1u)] = j;
     }
   }
   if (lane == 0) {
@@ -111,21 +105,56 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
   }
 }
 
+// Cells whose particles exceed the small staging area, merged with the large one.
+template <typename T>
+__global__ void __launch_bounds__(64) k_merge_big(Bank b, Counters* ctr, int which, StepConst K,
+                                                 const uint32_t* big, const uint32_t* occ,
+                                                 const uint32_t* start, const int32_t* dN,
+                                                 const uint32_t* cbase, int n_new, int n_ppc) {
+  const uint32_t nbig = ctr->n_big;
+  uint64_t merged = 0;
+  for (uint32_t t = blockIdx.x; t < nbig; t += gridDim.x) {
+    const uint32_t j = big[t];
+    const uint32_t c = occ[j];
+    const int32_t d = dN[j];
+    const uint32_t M = d > 0 ? ((uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new) : 0u;
+    const uint32_t base = M ? cbase[j] : 0u;
+    const int r = merge_cell<T, MergeBig<T>::value>(b, ctr, which, K, c, start[c], start[c + 1], base,
+                                                     M, n_ppc, &merged);
+    if (r == 2 && lane_id() == 0) atomicAdd(&ctr->merge_skipped, 1u);
+  }
+  if (lane_id() == 0 && merged) atomicAdd(&ctr->merged, (unsigned long long)merged);
+}
+
 }  // namespace
 
 hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k) {
   const int dest = 1 - ctx->cur;  // coupling acts on the freshly binned bank
   int g = (int)(ctx->ncell < 65536u ? ctx->ncell : 65536u);
   if (g < 1) g = 1;
-  MergeScratch ms = merge_scratch(ctx);
-  if (ctx->d.precision == ITOKMC_FP64)
+  const bool f64 = ctx->d.precision == ITOKMC_FP64;
+  if (f64)
     k_couple<double><<<g, 64, merge_lds_bytes<double>(ctx->d.n_ppc), ctx->s>>>(
-        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN,
-        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ms);
+        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN, ctx->cbase,
+        ctx->d.n_new, ctx->d.n_ppc, ctx->big);
   else
     k_couple<float><<<g, 64, merge_lds_bytes<float>(ctx->d.n_ppc), ctx->s>>>(
-        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN,
-        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ms);
+        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN, ctx->cbase,
+        ctx->d.n_new, ctx->d.n_ppc, ctx->big);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ctx->d.n_ppc == 0) return e;
+  const int gb = 1024;
+  if (f64) {
+    const size_t lds = merge_lds_bytes_c<double, MergeBig<double>::value>();
+    k_merge_big<double><<<gb, 64, lds, ctx->s>>>(ctx->bank[dest], ctx->ctr, dest, k, ctx->big, ctx->occ,
+                                                  ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
+                                                  ctx->d.n_ppc);
+  } else {
+    const size_t lds = merge_lds_bytes_c<float, MergeBig<float>::value>();
+    k_merge_big<float><<<gb, 64, lds, ctx->s>>>(ctx->bank[dest], ctx->ctr, dest, k, ctx->big, ctx->occ,
+                                                 ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
+                                                 ctx->d.n_ppc);
+  }
   return hipGetLastError();
 }
 

@@ -56,6 +56,34 @@ __device__ __forceinline__ const T* ctp(const void* p) { return reinterpret_cast
 __device__ __forceinline__ double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
 __device__ __forceinline__ float hmean(float a, float b) { return 2.0f * a * b / (a + b); }
 
+constexpr int kRedBlocks = 1024;  // fixed grid of the norm kernels: one partial per block
+
+// Block-wide sum of a double (256 threads), valid in thread 0.
+__device__ __forceinline__ double block_sumd(double v) {
+  __shared__ double sh[4];
+  v = wave_sumd(v);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return s;
+}
+
+// Sum of the per-block partials in a fixed order (deterministic).
+__global__ void __launch_bounds__(1024) k_sum_partials(const double* part, int n, double* out) {
+  __shared__ double sh[16];
+  double v = threadIdx.x < (unsigned)n ? part[threadIdx.x] : 0.0;
+  v = wave_sumd(v);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += sh[i];
+    *out = s;
+  }
+}
+
 // ---- CIC helpers ------------------------------------------------------------------
 
 // Lower tent node and weight of the upper node along one axis for a particle in cell c
@@ -189,6 +217,117 @@ __global__ void __launch_bounds__(256) k_field_deposit(Bank a, const Counters* c
   }
 }
 
+// LDS-staged form of k_field_deposit.  A workgroup takes a chunk of kDepChunk
+// consecutive (cell-sorted, hence spatially compact) particles and accumulates their
+// 8-node CIC contributions in an LDS hash table keyed by grid node (linear probing,
+// at most kDepProbes probes, then a direct global atomic); the table is flushed with
+// one global atomic per touched node and field.  Same arithmetic as k_field_deposit.
+constexpr int kDepChunk = 2048;
+constexpr int kDepProbes = 8;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+template <typename T> struct DepTbl;
+template <> struct DepTbl<float> { static constexpr int log2n = 12; };
+template <> struct DepTbl<double> { static constexpr int log2n = 11; };
+
+template <typename T>
+__device__ __forceinline__ void tbl_add(uint32_t* keys, T* v0, T* v1, uint32_t node, T a, T b,
+                                        T* g0, T* g1) {
+  constexpr int L2 = DepTbl<T>::log2n;
+  constexpr uint32_t mask = (1u << L2) - 1u;
+  uint32_t h = (node * 2654435761u) >> (32 - L2);
+  for (int probe = 0; probe < kDepProbes; ++probe) {
+    uint32_t k = keys[h];
+    if (k == kEmptyKey) {
+      const uint32_t prev = atomicCAS(&keys[h], kEmptyKey, node);
+      k = prev == kEmptyKey ? node : prev;
+    }
+    if (k == node) {
+      if (a != (T)0) atomicAdd(&v0[h], a);
+      if (b != (T)0) atomicAdd(&v1[h], b);
+      return;
+    }
+    h = (h + 1u) & mask;
+  }
+  if (a != (T)0) atomicAdd(&g0[node], a);
+  if (b != (T)0) atomicAdd(&g1[node], b);
+}
+
+template <typename T>
+__device__ __forceinline__ void tbl_cic(uint32_t* keys, T* v0, T* v1, const StepConst& K, int i0,
+                                        int j0, int k0, T fx, T fy, T fz, T qa, T qb, T* g0, T* g1) {
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) {
+    const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
+    const T wt = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
+    const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
+    if (wt == (T)0 || ii >= K.nx || jj >= K.ny || kk >= K.nz) continue;
+    const uint32_t node = (uint32_t)ii + (uint32_t)K.nx * ((uint32_t)jj + (uint32_t)K.ny * (uint32_t)kk);
+    tbl_add<T>(keys, v0, v1, node, qa * wt, qb * wt, g0, g1);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
+                                                          StepConst K, const void* Ex,
+                                                          const void* Ey, const void* Ez, Coef co,
+                                                          int mode, T* sig, T* ne) {
+  constexpr int TBL = 1 << DepTbl<T>::log2n;
+  extern __shared__ __align__(16) char smem[];
+  uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
+  T* v0 = reinterpret_cast<T*>(smem + TBL * 4);
+  T* v1 = v0 + TBL;
+  const uint32_t n = min(ctr->n[which], K.cap);
+  const T diff = (T)K.diff;
+  for (uint32_t c0 = blockIdx.x * (uint32_t)kDepChunk; c0 < n; c0 += gridDim.x * (uint32_t)kDepChunk) {
+    for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
+      keys[t] = kEmptyKey;
+      v0[t] = (T)0;
+      v1[t] = (T)0;
+    }
+    __syncthreads();
+    const uint32_t c1 = min(c0 + (uint32_t)kDepChunk, n);
+    for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+      const uint32_t w = a.w[i];
+      if (!w) continue;
+      const uint32_t cell = a.cell[i];
+      const int ci = (int)(cell % (uint32_t)K.nx), cj = (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
+                ck = (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny));
+      const T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
+      int i0, j0, k0;
+      T fx, fy, fz;
+      tent_axis<T>(ci, o[0], K.nx, i0, fx);
+      tent_axis<T>(cj, o[1], K.ny, j0, fy);
+      tent_axis<T>(ck, o[2], K.nz, k0, fz);
+      if (mode == 0) {
+        tbl_cic<T>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
+        continue;
+      }
+      const T e[3] = {cic_get<T>(ctp<T>(Ex), K, i0, j0, k0, fx, fy, fz),
+                      cic_get<T>(ctp<T>(Ey), K, i0, j0, k0, fx, fy, fz),
+                      cic_get<T>(ctp<T>(Ez), K, i0, j0, k0, fx, fy, fz)};
+      const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+      const T mu = Mob<T>::mu(co, Em);
+      tbl_cic<T>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, mu * (T)w, (T)0, sig, ne);
+      const uint64_t id = a.id[i];
+      const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
+      T nr[3];
+      NormalsF<T>::get(r, nr);
+      tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
+      tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
+      tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
+      tbl_cic<T>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
+      const uint32_t k = keys[t];
+      if (k == kEmptyKey) continue;
+      if (v0[t] != (T)0) atomicAdd(&sig[k], v0[t]);
+      if (v1[t] != (T)0) atomicAdd(&ne[k], v1[t]);
+    }
+    __syncthreads();
+  }
+}
+
 // Semi-implicit push: X^{k+1} = X^k + sqrt(2 D dt) N - mu(|E^k(X^k)|) E^{k+1}(X^k) dt,
 // then binning exactly as the uniform push.
 template <typename T>
@@ -271,9 +410,10 @@ __global__ void k_zero(T* p, uint32_t n) {
 // Fine-level coefficient and right-hand side b = dx^2 rho / eps0 (+ the lift of the
 // anode potential on the top layer), both scaled by dx^2; accumulates ||b||^2.
 template <typename T>
-__global__ void k_field_prep(StepConst K, const uint32_t* nplus, const uint32_t* nminus,
-                             const T* ne, const T* sig, double sig_scale, double V, T* eps,
-                             double* b, double* norms) {
+__global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t* nplus,
+                                                   const uint32_t* nminus, const T* ne, const T* sig,
+                                                   double sig_scale, double V, T* eps, double* b,
+                                                   double* partial) {
   const uint32_t n = K.ncell;
   const double dV = K.dx * K.dx * K.dx;
   const double qscale = K.dx * K.dx * kE / (kEps0 * dV);
@@ -292,8 +432,8 @@ __global__ void k_field_prep(StepConst K, const uint32_t* nplus, const uint32_t*
     }
     acc += bb * bb;
   }
-  acc = wave_sumd(acc);
-  if (lane_id() == 0) atomicAdd(&norms[0], acc);
+  acc = block_sumd(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 template <typename T>
@@ -334,8 +474,8 @@ __device__ __forceinline__ void stencil(const U* u, const E* eps, int nx, int ny
 // r = b - A phi in double with the true boundary values (the lift is in b); writes the
 // working-precision right-hand side of the correction equation and ||r||^2.
 template <typename T>
-__global__ void k_residual64(const double* phi, const double* b, const T* eps, int nx, int ny, int nz,
-                             T* f0, double* norms) {
+__global__ void __launch_bounds__(256) k_residual64(const double* phi, const double* b, const T* eps,
+                                                   int nx, int ny, int nz, T* f0, double* partial) {
   const uint32_t n = (uint32_t)nx * ny * nz;
   double acc = 0.0;
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
@@ -350,8 +490,8 @@ __global__ void k_residual64(const double* phi, const double* b, const T* eps, i
     }
     acc += r * r;
   }
-  acc = wave_sumd(acc);
-  if (lane_id() == 0) atomicAdd(&norms[1], acc);
+  acc = block_sumd(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 template <typename T>
@@ -466,7 +606,7 @@ struct FieldState {
   int cur = 0;        // E[cur] holds the latest field
   void* sig = nullptr;
   void* ne = nullptr;
-  double* norms = nullptr;   // device: ||b||^2, ||r||^2
+  double* norms = nullptr;   // device: ||b||^2, ||r||^2, then per-block partials
   double* host_norms = nullptr;
 };
 
@@ -490,7 +630,7 @@ size_t field_bytes(const itokmc_grid_desc* d) {
   int dims[kMaxLevels][3];
   const int nl = build_levels(d, dims);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  size_t total = al(n * 8) * 2 + al(n * T) * 6 + al(n * T) * 2 + al(64);
+  size_t total = al(n * 8) * 2 + al(n * T) * 6 + al(n * T) * 2 + al(8 * (8 + kRedBlocks));
   for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
   return total;
 }
@@ -516,7 +656,7 @@ int field_init(itokmc_ctx* ctx, char* base) {
     for (int a = 0; a < 3; ++a) { F->E[s][a] = p; p += al(n * T); }
   F->sig = p; p += al(n * T);
   F->ne = p; p += al(n * T);
-  F->norms = (double*)p; p += al(64);
+  F->norms = (double*)p; p += al(8 * (8 + kRedBlocks));
   F->nlev = nl;
   for (int l = 0; l < nl; ++l) {
     Level& L = F->lev[l];
@@ -541,7 +681,7 @@ int field_init(itokmc_ctx* ctx, char* base) {
 void field_destroy(itokmc_ctx* ctx) {
   FieldState* F = fs(ctx);
   if (!F) return;
-  if (F->host_norms) hipHostFree(F->host_norms);
+  if (F->host_norms) (void)hipHostFree(F->host_norms);
   delete F;
   ctx->field_state = nullptr;
 }
@@ -595,11 +735,10 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
   double bn2 = 0.0, rn2 = 0.0;
   int cyc = 0;
   for (;; ++cyc) {
-    hipError_t e = hipMemsetAsync(F->norms + 1, 0, 8, s);
-    if (e != hipSuccess) return check_hip(ctx, e, "solve");
-    k_residual64<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
-                                                 (T*)L0.f, F->norms);
-    e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
+    k_residual64<T><<<kRedBlocks, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
+                                               (T*)L0.f, F->norms + 8);
+    k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms + 1);
+    hipError_t e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return check_hip(ctx, e, "solve residual");
     bn2 = F->host_norms[0];
@@ -627,15 +766,19 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   k_zero<T><<<blocks(n), 256, 0, s>>>((T*)F->sig, n);
   k_zero<T><<<blocks(n), 256, 0, s>>>((T*)F->ne, n);
   void* const* Eo = F->E[F->cur];
-  k_field_deposit<T><<<blocks(ctx->cap, 8192), 256, 0, s>>>(
-      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1], Eo[2], coef(ctx), mode, (T*)F->sig,
-      (T*)F->ne);
-  hipError_t e = hipMemsetAsync(F->norms, 0, 16, s);
-  if (e != hipSuccess) return check_hip(ctx, e, "deposit");
+  {
+    constexpr int TBL = 1 << DepTbl<T>::log2n;
+    const size_t lds = (size_t)TBL * (4 + 2 * sizeof(T));
+    int g = (int)((ctx->cap + kDepChunk - 1) / kDepChunk);
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    k_field_deposit_lds<T><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1],
+                                               Eo[2], coef(ctx), mode, (T*)F->sig, (T*)F->ne);
+  }
   const double sig_scale = mode == 1 ? kE * K.dt / (kEps0 * K.dx * K.dx * K.dx) : 0.0;
-  k_field_prep<T><<<blocks(n), 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const T*)F->ne,
-                                            (const T*)F->sig, sig_scale, ctx->d.V_anode,
-                                            (T*)F->lev[0].eps, F->b, F->norms);
+  k_field_prep<T><<<kRedBlocks, 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const T*)F->ne,
+                                             (const T*)F->sig, sig_scale, ctx->d.V_anode,
+                                             (T*)F->lev[0].eps, F->b, F->norms + 8);
+  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms);
   phase_end(ctx, PH_DEPOSIT);
   phase_begin(ctx, PH_SOLVE);
   const int rc = solve<T>(ctx, F);

@@ -36,7 +36,7 @@ struct Counters {
   unsigned long long ph_emitted, ph_absorbed, ph_lost;
   unsigned long long pushed;   // live particles advanced by the transport kernels
   uint32_t merge_skipped;      // cells too large for the LDS merge (left unmerged)
-  uint32_t pad2;
+  uint32_t n_big;              // cells deferred to the large-staging merge pass
 };
 
 // Device-side copy of the per-step constants shared by the kernels.
@@ -84,6 +84,7 @@ struct itokmc_ctx {
   int32_t* dN = nullptr;                  // net electron change per occupied cell
   uint32_t* work = nullptr;               // occupied-cell indices needing coupling
   uint32_t* cbase = nullptr;              // first reserved bank slot of a cell's products
+  uint32_t* big = nullptr;                // occupied-cell indices for the large merge pass
   uint32_t* blocksums = nullptr;          // scan scratch
   itk::Counters* ctr = nullptr;
   unsigned long long* reduce = nullptr;   // small reduction scratch

@@ -1,119 +1,130 @@
 // Superparticle merge/split of one cell by one wavefront (section "Superparticle
 // management", eq. weight_median).
 //
-// The cell's live particles plus its new KMC products are staged in LDS as pieces
-// (offset, weight, id).  A bounding-volume tree is grown breadth-first: a leaf splits
-// along the axis of largest extent (single-precision extents, ties to the lower
-// axis), its pieces ordered by (coordinate, id); the weight median is the first sorted
-// piece p with 2 (weight up to and including p) > leaf weight; a median of weight one
-// joins the lighter side (ties left), a heavier median is cut into floor(T/2) - W_left
-// (left, omitted if zero) and the rest (right).  Leaves of weight one are terminal;
-// when a level would overshoot n_ppc leaves the heaviest split first (ties to the
-// lower index).  Each final leaf becomes one particle at its weighted centroid with
-// id (MERGE, step, cell, leaf).
+// The cell's live particles (its bank segment plus the slots holding its new KMC
+// products) are staged in LDS as pieces (offset, weight, id) in a store addressed
+// through two index buffers; a leaf is a contiguous range of an index buffer.  The
+// bounding-volume tree grows breadth-first and every leaf of a level is processed at
+// once: a leaf splits along the axis of largest extent (single-precision extents, ties
+// to the lower axis), its pieces ordered by (coordinate, id); the weight median is the
+// first ordered piece p with 2 (weight up to and including p) > leaf weight; a median
+// of weight one joins the lighter side (ties left), a heavier median is cut into
+// floor(T/2) - W_left (left, omitted if zero) and the rest (right, kept in a spare slot
+// at the end of the leaf's region).  Leaves of weight one are terminal; when a level
+// would overshoot n_ppc leaves the heaviest split first (ties to the lower index).
+// Each final leaf becomes one particle at its weighted centroid with id
+// (MERGE, step, cell, leaf).
 //
-// Leaves are written back into the cell's own bank slots, then into the slots the KMC
-// pass reserved for the products, then (splits of small cells only) into slots
-// appended with one atomic; slots left over are marked dead (weight 0).
+// Leaves are written back into the cell's segment slots, then into its product slots,
+// then (splits of small cells only) into slots appended with one atomic; slots left
+// over are marked dead (weight 0).
 #pragma once
 #include "device.hpp"
 #include "itk.hpp"
 
 namespace itk {
 
-template <typename T> struct MergeCap;
-template <> struct MergeCap<float> { static constexpr int value = 1536; };
-template <> struct MergeCap<double> { static constexpr int value = 1024; };
 constexpr int kMaxMergePpc = 64;
+constexpr int kMergeSmall = 256;  // pieces staged by the common (small-LDS) path
+template <typename T> struct MergeBig;
+template <> struct MergeBig<float> { static constexpr int value = 1536; };
+template <> struct MergeBig<double> { static constexpr int value = 1024; };
 
-struct MergeScratch {
-  int n_ppc;
+// Bit pattern whose unsigned order is the order of non-negative values.
+template <typename T> struct Bits;
+template <> struct Bits<float> {
+  using U = uint32_t;
+  __device__ static U of(float x) { return __float_as_uint(x); }
+  __device__ static float val(U u) { return __uint_as_float(u); }
+  static constexpr U lo_init = 0xFFFFFFFFu;
+};
+template <> struct Bits<double> {
+  using U = unsigned long long;
+  __device__ static U of(double x) { return (U)__double_as_longlong(x); }
+  __device__ static double val(U u) { return __longlong_as_double((long long)u); }
+  static constexpr U lo_init = ~0ull;
 };
 
-inline MergeScratch merge_scratch(itokmc_ctx* ctx) { return MergeScratch{ctx->d.n_ppc}; }
-
+template <typename T, int CAP>
+constexpr size_t merge_lds_bytes_c() {
+  constexpr size_t S = (size_t)CAP + kMaxMergePpc;
+  constexpr size_t NL = kMaxMergePpc;
+  constexpr size_t U = sizeof(typename Bits<T>::U);
+  return S * (8 + 3 * sizeof(T) + 4 + 2 * 2 + 3)  // store, two index buffers, three tag arrays
+         + NL * (6 * 4 + 3 * 4 + 6 * U + 1)        // leaf records, per-leaf scratch, extents, axis
+         + 64;
+}
 template <typename T>
 inline size_t merge_lds_bytes(int n_ppc) {
-  if (n_ppc <= 0) return 0;
-  const size_t cap2 = (size_t)MergeCap<T>::value + (size_t)n_ppc;
-  return cap2 * (8 + 3 * sizeof(T) + 4) + 2 * cap2 * 2 + 2 * 3 * 4 * (size_t)kMaxMergePpc + 64;
+  return n_ppc > 0 ? merge_lds_bytes_c<T, kMergeSmall>() : 0;
 }
-
-// Piece store (each piece once) plus two index buffers whose ranges are the leaves.
-template <typename T>
-struct Pieces {
-  uint64_t* id;
-  T* o[3];
-  uint32_t* w;
-};
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-template <typename T>
-__device__ bool merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, uint32_t c,
-                           uint32_t s, uint32_t e, uint32_t M, uint32_t base, const T no[3],
-                           uint32_t nw, uint64_t nid, int n_ppc, const MergeScratch&,
-                           uint64_t* merged) {
+// Returns 0 if the cell needs no merge, 1 if it was merged, 2 if it holds more than CAP
+// pieces (nothing written; the caller defers it to a larger staging area).
+template <typename T, int CAP>
+__device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, uint32_t c,
+                          uint32_t s, uint32_t e, uint32_t base, uint32_t M, int n_ppc,
+                          uint64_t* merged) {
+  using U = typename Bits<T>::U;
+  constexpr int S = CAP + kMaxMergePpc;
+  constexpr int NL = kMaxMergePpc;
+  constexpr uint8_t kNone = 0xFF;
   extern __shared__ __align__(16) char smem[];
-  constexpr int CAP = MergeCap<T>::value;
-  const int cap2 = CAP + n_ppc;
   const int lane = lane_id();
-  Pieces<T> S;
   char* p = smem;
-  S.id = (uint64_t*)p; p += (size_t)cap2 * 8;
-  for (int a = 0; a < 3; ++a) { S.o[a] = (T*)p; p += (size_t)cap2 * sizeof(T); }
-  S.w = (uint32_t*)p; p += (size_t)cap2 * 4;
-  uint16_t* I[2];
-  for (int k = 0; k < 2; ++k) { I[k] = (uint16_t*)p; p += (size_t)cap2 * 2; }
-  uint32_t* Lst[2];
-  uint32_t* Lcn[2];
-  uint32_t* LW[2];
+  uint64_t* sid = (uint64_t*)p; p += (size_t)S * 8;
+  U* lo = (U*)p; p += (size_t)NL * 3 * sizeof(U);
+  U* hi = (U*)p; p += (size_t)NL * 3 * sizeof(U);
+  T* so[3];
+  for (int a = 0; a < 3; ++a) { so[a] = (T*)p; p += (size_t)S * sizeof(T); }
+  uint32_t* sw = (uint32_t*)p; p += (size_t)S * 4;
+  uint32_t* Lst[2]; uint32_t* Lcn[2]; uint32_t* LW[2];
   for (int k = 0; k < 2; ++k) {
-    Lst[k] = (uint32_t*)p; p += kMaxMergePpc * 4;
-    Lcn[k] = (uint32_t*)p; p += kMaxMergePpc * 4;
-    LW[k] = (uint32_t*)p; p += kMaxMergePpc * 4;
+    Lst[k] = (uint32_t*)p; p += NL * 4;
+    Lcn[k] = (uint32_t*)p; p += NL * 4;
+    LW[k] = (uint32_t*)p; p += NL * 4;
   }
+  uint32_t* Rg = (uint32_t*)p; p += NL * 4;     // region of each old leaf in the new buffer
+  uint32_t* medp = (uint32_t*)p; p += NL * 4;   // median position inside the ordered leaf
+  uint32_t* medWl = (uint32_t*)p; p += NL * 4;  // weight ordered before the median
+  uint16_t* I[2];
+  for (int k = 0; k < 2; ++k) { I[k] = (uint16_t*)p; p += (size_t)S * 2; }
+  uint8_t* tag[2];                               // leaf of each slot of I[k]
+  for (int k = 0; k < 2; ++k) { tag[k] = (uint8_t*)p; p += (size_t)S; }
+  uint8_t* otag = (uint8_t*)p; p += (size_t)S;   // splitting leaf owning an ordered slot
+  uint8_t* axis = (uint8_t*)p; p += NL;
 
-  // ---- gather live particles and the new products ----
+  // ---- gather: segment [s, e) then product slots [base, base + M) ----
   uint32_t m = 0, wmax = 0;
   uint64_t Wtot = 0;
-  for (uint32_t q0 = s; q0 < e; q0 += 64) {
-    const uint32_t q = q0 + (uint32_t)lane;
-    const uint32_t w = q < e ? b.w[q] : 0u;
+  const uint32_t nseg = e - s;
+  for (uint32_t q0 = 0; q0 < nseg + M; q0 += 64) {
+    const uint32_t qi = q0 + (uint32_t)lane;
+    const uint32_t q = qi < nseg ? s + qi : base + (qi - nseg);
+    const uint32_t w = qi < nseg + M ? b.w[q] : 0u;
     const bool alive = w > 0;
     const uint64_t mask = __ballot(alive);
     const uint32_t pos = m + (uint32_t)__popcll(mask & lanemask_lt());
     if (alive) {
       if (pos < (uint32_t)CAP) {
-        S.id[pos] = b.id[q];
-        S.o[0][pos] = reinterpret_cast<const T*>(b.ox)[q];
-        S.o[1][pos] = reinterpret_cast<const T*>(b.oy)[q];
-        S.o[2][pos] = reinterpret_cast<const T*>(b.oz)[q];
-        S.w[pos] = w;
+        sid[pos] = b.id[q];
+        so[0][pos] = reinterpret_cast<const T*>(b.ox)[q];
+        so[1][pos] = reinterpret_cast<const T*>(b.oy)[q];
+        so[2][pos] = reinterpret_cast<const T*>(b.oz)[q];
+        sw[pos] = w;
         I[0][pos] = (uint16_t)pos;
+        tag[0][pos] = 0;
       }
       wmax = w > wmax ? w : wmax;
       Wtot += w;
     }
     m += (uint32_t)__popcll(mask);
   }
-  if ((uint32_t)lane < M) {
-    const uint32_t pos = m + (uint32_t)lane;
-    if (pos < (uint32_t)CAP) {
-      S.id[pos] = nid;
-      S.o[0][pos] = no[0];
-      S.o[1][pos] = no[1];
-      S.o[2][pos] = no[2];
-      S.w[pos] = nw;
-      I[0][pos] = (uint16_t)pos;
-    }
-    wmax = nw > wmax ? nw : wmax;
-    Wtot += nw;
-  }
-  m += M;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const uint32_t o = __shfl_xor(wmax, d, 64);
@@ -121,20 +132,19 @@ __device__ bool merge_cell(Bank b, Counters* ctr, int which, const StepConst& K,
   }
   Wtot = wave_sum64(Wtot);
   const bool trigger = m > (uint32_t)n_ppc || (m < (uint32_t)n_ppc && wmax >= 2);
-  if (!trigger || m == 0) return false;
-  if (m > (uint32_t)CAP) {
-    if (lane == 0) atomicAdd(&ctr->merge_skipped, 1u);
-    return false;
-  }
-  __syncthreads();
-
-  // ---- breadth-first tree growth ----
-  int cb = 0, cl = 0, nl = 1;
-  uint32_t nstore = m;  // next free piece in the store (split superparticle pieces)
+  if (!trigger || m == 0) return 0;
+  if (m > (uint32_t)CAP) return 2;
   if (lane == 0) { Lst[0][0] = 0; Lcn[0][0] = m; LW[0][0] = (uint32_t)Wtot; }
   __syncthreads();
+
+  // ---- breadth-first growth, all leaves of a level at once ----
+  int cb = 0, nl = 1;
+  uint32_t extent = m;   // slots in use in I[cb]
+  uint32_t nstore = m;   // next free store entry
   for (int level = 0; level < 64 && nl < n_ppc; ++level) {
-    const uint32_t Wi = lane < nl ? LW[cl][lane] : 0u;
+    const int ncb = 1 - cb;
+    // leaves to split this level
+    const uint32_t Wi = lane < nl ? LW[cb][lane] : 0u;
     const bool cand = lane < nl && Wi >= 2;
     const uint64_t cmask = __ballot(cand);
     const int ncand = __popcll(cmask);
@@ -145,167 +155,208 @@ __device__ bool merge_cell(Bank b, Counters* ctr, int which, const StepConst& K,
       int rank = 0;
       for (int j = 0; j < nl; ++j) {
         const uint32_t Wj = __shfl(Wi, j, 64);
-        const bool cj = (cmask >> j) & 1ull;
-        if (cj && (Wj > Wi || (Wj == Wi && j < lane))) ++rank;
+        if (((cmask >> j) & 1ull) && (Wj > Wi || (Wj == Wi && j < lane))) ++rank;
       }
       chosen = cand && rank < budget;
     }
-    const uint64_t chmask = __ballot(chosen);
-    // new leaf index and new piece-region start of each old leaf
-    const uint32_t cnt_i = lane < nl ? Lcn[cl][lane] : 0u;
-    uint32_t widx = lane < nl ? (chosen ? 2u : 1u) : 0u;
-    uint32_t wreg = cnt_i + (chosen ? 1u : 0u);
+    const uint64_t chm = __ballot(chosen);
+    const uint32_t n_i = lane < nl ? Lcn[cb][lane] : 0u;
+    // new leaf index and region of each old leaf (a splitting leaf gets a spare slot)
+    const uint32_t widx = lane < nl ? (chosen ? 2u : 1u) : 0u;
+    const uint32_t wreg = n_i + (chosen ? 1u : 0u);
     uint32_t xi = widx, xr = wreg;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t yi = __shfl_up(xi, d, 64), yr = __shfl_up(xr, d, 64);
       if (lane >= d) { xi += yi; xr += yr; }
     }
-    const uint32_t newidx = xi - widx, region = xr - wreg;
+    const uint32_t newidx = xi - widx, R = xr - wreg;
     const int nl_new = (int)__shfl(xi, 63, 64);
-    const int ncb = 1 - cb, ncl = 1 - cl;
-    for (int L = 0; L < nl; ++L) {
-      const uint32_t st = Lst[cl][L], n = Lcn[cl][L], WL = LW[cl][L];
-      const uint32_t R = __shfl(region, L, 64), ni = __shfl(newidx, L, 64);
-      if (!((chmask >> L) & 1ull)) {
-        for (uint32_t q = (uint32_t)lane; q < n; q += 64) I[ncb][R + q] = I[cb][st + q];
-        if (lane == 0) { Lst[ncl][ni] = R; Lcn[ncl][ni] = n; LW[ncl][ni] = WL; }
-        continue;
+    const uint32_t new_extent = __shfl(xr, 63, 64);
+    if (lane < nl) {
+      Rg[lane] = R;
+      if (chosen) {
+        for (int a = 0; a < 3; ++a) { lo[3 * lane + a] = Bits<T>::lo_init; hi[3 * lane + a] = 0; }
+      } else {
+        Lst[ncb][newidx] = R; Lcn[ncb][newidx] = n_i; LW[ncb][newidx] = Wi;
       }
-      // (i) axis of largest extent
-      T lo[3], hi[3];
-      for (int a = 0; a < 3; ++a) { lo[a] = S.o[a][I[cb][st]]; hi[a] = lo[a]; }
-      for (uint32_t q = (uint32_t)lane; q < n; q += 64)
-        for (int a = 0; a < 3; ++a) {
-          const T v = S.o[a][I[cb][st + q]];
-          lo[a] = v < lo[a] ? v : lo[a];
-          hi[a] = v > hi[a] ? v : hi[a];
-        }
-      float ext[3];
+    }
+    for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) { tag[ncb][q] = kNone; otag[q] = kNone; }
+    __syncthreads();
+    // (i) extents of the splitting leaves
+    for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
+      const uint8_t L = tag[cb][q];
+      if (L == kNone || !((chm >> L) & 1ull)) continue;
+      const uint16_t pq = I[cb][q];
       for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          const T ol = __shfl_xor(lo[a], d, 64), oh = __shfl_xor(hi[a], d, 64);
-          lo[a] = ol < lo[a] ? ol : lo[a];
-          hi[a] = oh > hi[a] ? oh : hi[a];
-        }
-        ext[a] = (float)((double)hi[a] - (double)lo[a]);
+        const U v = Bits<T>::of(so[a][pq]);
+        atomicMin(&lo[3 * L + a], v);
+        atomicMax(&hi[3 * L + a], v);
       }
+    }
+    __syncthreads();
+    if (lane < nl && chosen) {
+      float ext[3];
+      for (int a = 0; a < 3; ++a)
+        ext[a] = (float)((double)Bits<T>::val(hi[3 * lane + a]) - (double)Bits<T>::val(lo[3 * lane + a]));
       int ax = 0;
       if (ext[1] > ext[ax]) ax = 1;
       if (ext[2] > ext[ax]) ax = 2;
-      // (ii) order by (coordinate, id): rank of each piece, written to the new region
-      for (uint32_t q = (uint32_t)lane; q < n; q += 64) {
-        const uint16_t pq = I[cb][st + q];
-        const T kq = S.o[ax][pq];
-        const uint64_t iq = S.id[pq];
-        uint32_t rank = 0;
-        for (uint32_t r = 0; r < n; ++r) {
-          const uint16_t pr = I[cb][st + r];
-          const T kr = S.o[ax][pr];
-          const uint64_t ir = S.id[pr];
-          rank += (kr < kq || (kr == kq && ir < iq)) ? 1u : 0u;
-        }
-        I[ncb][R + rank] = pq;
+      axis[lane] = (uint8_t)ax;
+    }
+    __syncthreads();
+    // (ii) order each splitting leaf by (coordinate, id); copy the other leaves
+    for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
+      const uint8_t L = tag[cb][q];
+      if (L == kNone) continue;
+      const uint32_t Ls = Lst[cb][L], Ln = Lcn[cb][L], RL = Rg[L];
+      const uint16_t pq = I[cb][q];
+      if (!((chm >> L) & 1ull)) {
+        const uint32_t ni = (uint32_t)L + (uint32_t)__popcll(chm & ((1ull << L) - 1ull));
+        I[ncb][RL + (q - Ls)] = pq;
+        tag[ncb][RL + (q - Ls)] = (uint8_t)ni;
+        continue;
       }
-      __syncthreads();
-      // (iii) weight median: first sorted piece with 2 * inclusive weight > leaf weight
-      uint64_t run = 0;
-      int med = -1;
-      uint64_t Wl = 0;
-      for (uint32_t q0 = 0; q0 < n && med < 0; q0 += 64) {
-        const uint32_t q = q0 + (uint32_t)lane;
-        const uint64_t w = q < n ? (uint64_t)S.w[I[ncb][R + q]] : 0ull;
-        uint64_t x = w;
+      const int ax = axis[L];
+      const T kq = so[ax][pq];
+      const uint64_t iq = sid[pq];
+      uint32_t rank = 0;
+      for (uint32_t r = Ls; r < Ls + Ln; ++r) {
+        const uint16_t pr = I[cb][r];
+        const T kr = so[ax][pr];
+        rank += (kr < kq || (kr == kq && sid[pr] < iq)) ? 1u : 0u;
+      }
+      I[ncb][RL + rank] = pq;
+      otag[RL + rank] = L;
+    }
+    __syncthreads();
+    // (iii) weight median of every splitting leaf: one segmented scan over the buffer
+    uint64_t carry = 0;
+    uint32_t carry_key = 0xFFFFFFFFu;
+    bool carry_hit = false;
+    for (uint32_t q0 = 0; q0 < new_extent; q0 += 64) {
+      const uint32_t q = q0 + (uint32_t)lane;
+      const uint8_t t8 = q < new_extent ? otag[q] : kNone;
+      const bool valid = t8 != kNone;
+      const uint32_t vkey = valid ? (uint32_t)t8 : 0xFFFFFFFFu;
+      const uint64_t w = valid ? (uint64_t)sw[I[ncb][q]] : 0ull;
+      const uint32_t prev = __shfl_up(vkey, 1, 64);
+      const bool head = lane == 0 || prev != vkey;
+      const uint64_t heads = __ballot(head);
+      const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const int seg_start = 63 - __clzll(heads & upto);
+      uint64_t x = w;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const uint64_t y = shfl_up64(x, d);
-          if (lane >= d) x += y;
-        }
-        const bool hit = q < n && 2ull * (run + x) > (uint64_t)WL;
-        const uint64_t hm = __ballot(hit);
-        if (hm) {
-          const int first = __ffsll((long long)hm) - 1;
-          med = (int)q0 + first;
-          Wl = run + shfl64(x - w, first);
-        }
-        run += shfl64(x, 63);
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = shfl_up64(x, d);
+        if (lane - d >= seg_start) x += y;
       }
-      const uint32_t mu = (uint32_t)med;
-      const uint16_t pm = I[ncb][R + mu];
-      const uint32_t wm = S.w[pm];
-      const uint64_t Wr = (uint64_t)WL - Wl - wm;
-      // (iv)-(v) children.  The region holds n + 1 slots: a split superparticle median
-      // keeps its left piece in place and puts its right piece in the spare last slot.
-      uint32_t lcnt, rst, rcnt;
-      uint64_t WLn, WRn;
+      if (seg_start == 0 && vkey == carry_key) x += carry;
+      const bool hit = valid && 2ull * x > (uint64_t)LW[cb][vkey & 63u];
+      const bool up_hit = __shfl_up(hit ? 1 : 0, 1, 64) != 0;
+      const bool prev_same = lane > 0 ? prev == vkey : vkey == carry_key;
+      const bool prev_hit = lane > 0 ? up_hit : carry_hit;
+      if (hit && !(prev_same && prev_hit)) {
+        medp[vkey] = q - Rg[vkey];
+        medWl[vkey] = (uint32_t)(x - w);
+      }
+      carry = shfl64(x, 63);
+      carry_key = __shfl(vkey, 63, 64);
+      carry_hit = __shfl(hit ? 1 : 0, 63, 64) != 0;
+    }
+    __syncthreads();
+    // (iv)-(v) children of every splitting leaf, one lane per leaf
+    uint32_t lcnt = 0, rst = 0, rcnt = 0, WLn = 0, WRn = 0, wl = 0, pm = 0, mu = 0;
+    bool super = false;
+    if (lane < nl && chosen) {
+      mu = medp[lane];
+      const uint32_t Wl = medWl[lane];
+      pm = I[ncb][R + mu];
+      const uint32_t wm = sw[pm];
+      const uint32_t Wr = Wi - Wl - wm;
       if (wm == 1) {
-        if (Wl <= Wr) {  // median joins the left side
-          lcnt = mu + 1; rst = mu + 1; rcnt = n - mu - 1;
-          WLn = Wl + 1; WRn = Wr;
-        } else {         // median joins the right side
-          lcnt = mu; rst = mu; rcnt = n - mu;
-          WLn = Wl; WRn = Wr + 1;
-        }
+        if (Wl <= Wr) { lcnt = mu + 1; rst = mu + 1; rcnt = n_i - mu - 1; WLn = Wl + 1; WRn = Wr; }
+        else { lcnt = mu; rst = mu; rcnt = n_i - mu; WLn = Wl; WRn = Wr + 1; }
       } else {
-        const uint64_t Ttot = Wl + wm + Wr;
-        const uint32_t wl = (uint32_t)(Ttot / 2 - Wl);
-        const uint32_t wr = wm - wl;
-        if (lane == 0) {
-          const uint32_t np = nstore;
-          S.id[np] = S.id[pm];
-          for (int a = 0; a < 3; ++a) S.o[a][np] = S.o[a][pm];
-          S.w[np] = wr;
-          S.w[pm] = wl;
-          I[ncb][R + n] = (uint16_t)np;
-        }
-        ++nstore;
+        super = true;
+        wl = (Wl + wm + Wr) / 2 - Wl;
         lcnt = wl > 0 ? mu + 1 : mu;
-        rst = mu + 1; rcnt = n - mu;
-        WLn = Wl + wl; WRn = Wr + wr;
+        rst = mu + 1; rcnt = n_i - mu;
+        WLn = Wl + wl; WRn = Wr + (wm - wl);
       }
-      if (lane == 0) {
-        Lst[ncl][ni] = R; Lcn[ncl][ni] = lcnt; LW[ncl][ni] = (uint32_t)WLn;
-        Lst[ncl][ni + 1] = R + rst; Lcn[ncl][ni + 1] = rcnt; LW[ncl][ni + 1] = (uint32_t)WRn;
+    }
+    // store entries for the right pieces of split superparticle medians
+    const uint32_t sx = super ? 1u : 0u;
+    uint32_t sp = sx;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(sp, d, 64);
+      if (lane >= d) sp += y;
+    }
+    const uint32_t np = nstore + sp - sx;
+    nstore += __shfl(sp, 63, 64);
+    if (lane < nl && chosen) {
+      if (super) {
+        const uint32_t wm = sw[pm];
+        sid[np] = sid[pm];
+        for (int a = 0; a < 3; ++a) so[a][np] = so[a][pm];
+        sw[np] = wm - wl;
+        sw[pm] = wl;
+        I[ncb][R + n_i] = (uint16_t)np;
       }
-      __syncthreads();
+      Lst[ncb][newidx] = R; Lcn[ncb][newidx] = lcnt; LW[ncb][newidx] = WLn;
+      Lst[ncb][newidx + 1] = R + rst; Lcn[ncb][newidx + 1] = rcnt; LW[ncb][newidx + 1] = WRn;
+    }
+    __syncthreads();
+    // leaf tags of the split regions (ordered slots plus the spare slot)
+    for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) {
+      uint8_t L = otag[q];
+      if (L == kNone) {
+        if (q == 0 || otag[q - 1] == kNone) continue;
+        const uint8_t Lp = otag[q - 1];
+        if (q != Rg[Lp] + Lcn[cb][Lp]) continue;
+        L = Lp;  // the spare slot that follows an ordered range
+      }
+      const uint32_t ni = (uint32_t)L + (uint32_t)__popcll(chm & ((1ull << L) - 1ull));
+      const uint32_t off = q - Rg[L];
+      const uint32_t lc = Lcn[ncb][ni], rs = Lst[ncb][ni + 1] - Rg[L], rc = Lcn[ncb][ni + 1];
+      uint8_t t = kNone;
+      if (off < lc) t = (uint8_t)ni;
+      else if (off >= rs && off < rs + rc) t = (uint8_t)(ni + 1);
+      tag[ncb][q] = t;
     }
     __syncthreads();
     cb = ncb;
-    cl = ncl;
     nl = nl_new;
+    extent = new_extent;
   }
 
   // ---- leaves -> particles ----
   double my_o[3] = {0.0, 0.0, 0.0};
   uint32_t my_w = 0;
-  for (int L = 0; L < nl; ++L) {
-    const uint32_t st = Lst[cl][L], n = Lcn[cl][L];
+  if (lane < nl) {
+    const uint32_t st = Lst[cb][lane], n = Lcn[cb][lane];
     double acc[3] = {0.0, 0.0, 0.0};
-    for (uint32_t q = (uint32_t)lane; q < n; q += 64) {
-      const uint16_t pq = I[cb][st + q];
-      const double w = (double)S.w[pq];
-      for (int a = 0; a < 3; ++a) acc[a] += w * (double)S.o[a][pq];
+    for (uint32_t q = st; q < st + n; ++q) {
+      const uint16_t pq = I[cb][q];
+      const double w = (double)sw[pq];
+      for (int a = 0; a < 3; ++a) acc[a] += w * (double)so[a][pq];
     }
-    for (int a = 0; a < 3; ++a) acc[a] = wave_sumd(acc[a]);
-    if (lane == L) {
-      my_w = LW[cl][L];
-      for (int a = 0; a < 3; ++a) my_o[a] = acc[a] / (double)my_w;
-    }
+    my_w = LW[cb][lane];
+    for (int a = 0; a < 3; ++a) my_o[a] = acc[a] / (double)my_w;
   }
-  const uint32_t seg_n = e - s;
   uint32_t extra_base = 0;
-  const int extra = nl - (int)seg_n - (int)M;
+  const int extra = nl - (int)nseg - (int)M;
   if (extra > 0) {
     if (lane == 0) extra_base = atomicAdd(&ctr->n[which], (uint32_t)extra);
     extra_base = __shfl(extra_base, 0, 64);
   }
   if (lane < nl) {
-    uint32_t q;
     const uint32_t i = (uint32_t)lane;
-    if (i < seg_n) q = s + i;
-    else if (i < seg_n + M) q = base + (i - seg_n);
-    else q = extra_base + (i - seg_n - M);
+    uint32_t q;
+    if (i < nseg) q = s + i;
+    else if (i < nseg + M) q = base + (i - nseg);
+    else q = extra_base + (i - nseg - M);
     if (q < K.cap) {
       T o3[3];
       for (int a = 0; a < 3; ++a) {
@@ -326,15 +377,13 @@ __device__ bool merge_cell(Bank b, Counters* ctr, int which, const StepConst& K,
     }
   }
   // retire the cell's remaining slots
-  for (uint32_t i = (uint32_t)nl + (uint32_t)lane; i < seg_n; i += 64) b.w[s + i] = 0;
-  const uint32_t used_res = nl > (int)seg_n ? (uint32_t)(nl - (int)seg_n) : 0u;
-  for (uint32_t i = used_res + (uint32_t)lane; i < M; i += 64) {
-    const uint32_t q = base + i;
+  for (uint32_t i = (uint32_t)nl + (uint32_t)lane; i < nseg + M; i += 64) {
+    const uint32_t q = i < nseg ? s + i : base + (i - nseg);
     if (q < K.cap) b.w[q] = 0;
   }
   if (lane == 0) *merged += 1;
   __syncthreads();
-  return true;
+  return 1;
 }
 
 }  // namespace itk

@@ -405,6 +405,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* 
     ctr->n_occ = tocc;
     ctr->n[dest] = total;
     ctr->n_work = 0;
+    ctr->n_big = 0;
   }
 }
 
