@@ -177,6 +177,17 @@ int itokmc_set_step(itokmc_ctx* ctx, uint32_t step);
 int itokmc_get_field(itokmc_ctx* ctx, double* phi);
 int itokmc_set_field(itokmc_ctx* ctx, const double* phi);
 
+/* Performance parameters (results do not depend on them beyond the solver
+ * tolerance): multigrid pre/post red-black sweeps per level (default 2/2, each 0..8,
+ * sum >= 1), bottom-level sweeps (0 = automatic), capture of the refinement cycle in
+ * a HIP graph (default on), linear-in-time extrapolation of the potential as the
+ * initial guess (default on).  set_tuning copies the struct; EINVAL if out of range. */
+typedef struct {
+  int32_t mg_pre, mg_post, bottom_sweeps, use_graph, extrapolate, pad0;
+} itokmc_tuning;
+int itokmc_set_tuning(itokmc_ctx* ctx, const itokmc_tuning* tuning);
+int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
+
 /* Per-phase timing with HIP events recorded around each kernel phase on the
  * context's stream (off by default).  Phases: 0 push, 1 photons, 2 bin scan,
  * 3 scatter, 4 KMC, 5 coupling/merge, 6 charge deposit, 7 field solve, 8 field push,

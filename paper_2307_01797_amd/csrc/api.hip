@@ -537,6 +537,22 @@ int itokmc_set_field(itokmc_ctx* ctx, const double* phi) {
   return field_set_phi(ctx, phi);
 }
 
+int itokmc_set_tuning(itokmc_ctx* ctx, const itokmc_tuning* t) {
+  if (!ctx || !t) return ITOKMC_EINVAL;
+  if (t->mg_pre < 0 || t->mg_pre > 8 || t->mg_post < 0 || t->mg_post > 8 || t->mg_pre + t->mg_post < 1 ||
+      t->bottom_sweeps < 0 || t->bottom_sweeps > 4096)
+    return set_error(ctx, ITOKMC_EINVAL, "invalid tuning");
+  ctx->tune = *t;
+  field_reset_graph(ctx);
+  return ITOKMC_OK;
+}
+
+int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* t) {
+  if (!ctx || !t) return ITOKMC_EINVAL;
+  *t = ctx->tune;
+  return ITOKMC_OK;
+}
+
 int itokmc_set_profiling(itokmc_ctx* ctx, int on) {
   if (!ctx) return ITOKMC_EINVAL;
   phase_collect(ctx);

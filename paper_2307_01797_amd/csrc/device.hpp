@@ -73,6 +73,17 @@ __device__ __forceinline__ uint64_t make_id(uint32_t kind, uint32_t step, uint32
          ((uint64_t)(cell & 0xFFFFFFu) << 16) | (uint64_t)(slot & 0xFFFFu);
 }
 
+// ---- XCD-aware workgroup order --------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  This
+// remaps the dispatch index so XCD x processes one contiguous range of logical blocks:
+// neighbouring rows and planes of a stencil then share an L2.  A bijection on
+// [0, nblocks).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
+  const uint32_t per = nblocks >> 3, rem = nblocks & 7u;
+  const uint32_t x = bid & 7u, i = bid >> 3;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // ---- wavefront helpers (64 lanes) ------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }

@@ -16,7 +16,7 @@
 // clouds folded into the wall cells.
 //
 // Solver: geometric multigrid V(2,2) cycles with red-black Gauss-Seidel, cell-averaged
-// restriction and piecewise-constant prolongation, run in the working precision on the
+// restriction and trilinear prolongation, run in the working precision on the
 // correction equation of an iterative-refinement loop whose residual and potential
 // are kept in double; the loop stops at ||r||_2 <= rtol ||b||_2 (the paper's relative
 // multigrid tolerance, 1e-10 by default).
@@ -73,7 +73,8 @@ __device__ __forceinline__ double block_sumd(double v) {
 // Sum of the per-block partials in a fixed order (deterministic).
 __global__ void __launch_bounds__(1024) k_sum_partials(const double* part, int n, double* out) {
   __shared__ double sh[16];
-  double v = threadIdx.x < (unsigned)n ? part[threadIdx.x] : 0.0;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) v += part[i];
   v = wave_sumd(v);
   if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -471,70 +472,150 @@ __device__ __forceinline__ void stencil(const U* u, const E* eps, int nx, int ny
   offsum = s;
 }
 
-// r = b - A phi in double with the true boundary values (the lift is in b); writes the
-// working-precision right-hand side of the correction equation and ||r||^2.
-template <typename T>
-__global__ void __launch_bounds__(256) k_residual64(const double* phi, const double* b, const T* eps,
-                                                   int nx, int ny, int nz, T* f0, double* partial) {
-  const uint32_t n = (uint32_t)nx * ny * nz;
-  double acc = 0.0;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const uint32_t c = base + threadIdx.x;
-    double r = 0.0;
-    if (c < n) {
-      const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-      double d, s;
-      stencil<double, double, T>(phi, eps, nx, ny, nz, i, j, k, d, s);
-      r = b[c] - (d * phi[c] - s);
-      f0[c] = (T)r;
-    }
-    acc += r * r;
-  }
-  acc = block_sumd(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-}
+// Harmonic mean for the smoother: exact in double; fast reciprocal in single precision
+// (the smoother only has to reduce the error; the double residual of the refinement
+// loop defines the solution).
+__device__ __forceinline__ double hmean_s(double a, double b) { return 2.0 * a * b / (a + b); }
+__device__ __forceinline__ float hmean_s(float a, float b) { return __fdividef(2.0f * a * b, a + b); }
 
 template <typename T>
-__global__ void k_smooth(T* u, const T* f, const T* eps, int nx, int ny, int nz, int color) {
-  const uint32_t n = (uint32_t)nx * ny * nz;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-    const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-    if (((i + j + k) & 1) != color) continue;
-    T d, s;
-    stencil<T, T, T>(u, eps, nx, ny, nz, i, j, k, d, s);
-    u[c] = (f[c] + s) / d;
-  }
+__device__ __forceinline__ void stencil_s(const T* u, const T* eps, int nx, int ny, int nz, int i, int j,
+                                          int k, size_t c, T& diag, T& offsum) {
+  const T ec = eps[c];
+  T d = 0, s = 0;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  if (i > 0) { const T b = hmean_s(ec, eps[c - 1]); d += b; s += b * u[c - 1]; }
+  if (i < nx - 1) { const T b = hmean_s(ec, eps[c + 1]); d += b; s += b * u[c + 1]; }
+  if (j > 0) { const T b = hmean_s(ec, eps[c - sy]); d += b; s += b * u[c - sy]; }
+  if (j < ny - 1) { const T b = hmean_s(ec, eps[c + sy]); d += b; s += b * u[c + sy]; }
+  if (k > 0) { const T b = hmean_s(ec, eps[c - sz]); d += b; s += b * u[c - sz]; }
+  else d += (T)2 * ec;
+  if (k < nz - 1) { const T b = hmean_s(ec, eps[c + sz]); d += b; s += b * u[c + sz]; }
+  else d += (T)2 * ec;
+  diag = d;
+  offsum = s;
 }
 
-// Coarse right-hand side from the fine residual: with both levels scaled by their own
-// h^2, f_coarse = 4 * mean of the 8 child residuals = (sum of the 8) / 2.  Also zeroes
-// the coarse correction.
+// Operator row for the double residual with the face coefficients computed exactly as
+// the smoother computes them (single-precision harmonic means in FP32 mode, exact double
+// in FP64 mode), accumulated in double.
 template <typename T>
-__global__ void k_resid_restrict(const T* u, const T* f, const T* eps, int nx, int ny, int nz, T* fc,
-                                 T* uc, int cnx, int cny, int cnz) {
-  const uint32_t n = (uint32_t)cnx * cny * cnz;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-    const int ci = c % cnx, cj = (c / cnx) % cny, ck = c / (cnx * cny);
-    T s8 = 0;
-    for (int d = 0; d < 8; ++d) {
-      const int i = 2 * ci + (d & 1), j = 2 * cj + ((d >> 1) & 1), k = 2 * ck + (d >> 2);
-      T dg, sm;
-      stencil<T, T, T>(u, eps, nx, ny, nz, i, j, k, dg, sm);
-      const size_t q = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
-      s8 += f[q] - (dg * u[q] - sm);
-    }
-    fc[c] = s8 * (T)0.5;
-    uc[c] = (T)0;
-  }
+__device__ __forceinline__ void stencil_r(const double* u, const T* eps, int nx, int ny, int nz, int i,
+                                          int j, int k, size_t c, double& diag, double& offsum) {
+  const T ec = eps[c];
+  double d = 0, s = 0;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  if (i > 0) { const double b = (double)hmean_s(ec, eps[c - 1]); d += b; s += b * u[c - 1]; }
+  if (i < nx - 1) { const double b = (double)hmean_s(ec, eps[c + 1]); d += b; s += b * u[c + 1]; }
+  if (j > 0) { const double b = (double)hmean_s(ec, eps[c - sy]); d += b; s += b * u[c - sy]; }
+  if (j < ny - 1) { const double b = (double)hmean_s(ec, eps[c + sy]); d += b; s += b * u[c + sy]; }
+  if (k > 0) { const double b = (double)hmean_s(ec, eps[c - sz]); d += b; s += b * u[c - sz]; }
+  else d += 2.0 * (double)ec;
+  if (k < nz - 1) { const double b = (double)hmean_s(ec, eps[c + sz]); d += b; s += b * u[c + sz]; }
+  else d += 2.0 * (double)ec;
+  diag = d;
+  offsum = s;
 }
 
+// Logical (x, y, z) block of a 3-D grid after the XCD remap.
+__device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
+  const uint32_t nb = gridDim.x * gridDim.y * gridDim.z;
+  const uint32_t lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const uint32_t l = xcd_block(lin, nb);
+  bx = (int)(l % gridDim.x);
+  by = (int)((l / gridDim.x) % gridDim.y);
+  bz = (int)(l / (gridDim.x * gridDim.y));
+}
+
+// One colour of a red-black Gauss-Seidel sweep: grid (x: half a row, y: j, z: k),
+// every thread updates the one cell of the colour in its pair.
 template <typename T>
-__global__ void k_prolong(T* u, int nx, int ny, int nz, const T* uc, int cnx, int cny) {
+__global__ void __launch_bounds__(128) k_smooth_rb(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                                  int color) {
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int i = 2 * (int)(bx * blockDim.x + threadIdx.x) + ((j + k + color) & 1);
+  if (i >= nx) return;
+  const size_t c = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
+  T d, s;
+  stencil_s<T>(u, eps, nx, ny, nz, i, j, k, c, d, s);
+  u[c] = (f[c] + s) / d;
+}
+
+// r = b - A phi in double with the true boundary values (the lift is in b), 256 cells
+// per block; writes the working-precision right-hand side of the correction equation
+// and one partial of ||r||^2 per block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_residual_rows(const double* phi, const double* b, const T* eps,
+                                                      int nx, int ny, int nz, T* f0, double* partial) {
   const uint32_t n = (uint32_t)nx * ny * nz;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-    const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-    u[c] += uc[(size_t)(i >> 1) + (size_t)cnx * ((size_t)(j >> 1) + (size_t)cny * (k >> 1))];
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t c = blk * 256u + threadIdx.x;
+  double rr = 0.0;
+  if (c < n) {
+    const int i = (int)(c % (uint32_t)nx), j = (int)((c / (uint32_t)nx) % (uint32_t)ny),
+              k = (int)(c / ((uint32_t)nx * (uint32_t)ny));
+    double d, s;
+    stencil_r<T>(phi, eps, nx, ny, nz, i, j, k, c, d, s);
+    rr = b[c] - (d * phi[c] - s);
+    f0[c] = (T)rr;
   }
+  const double acc = block_sumd(rr * rr);
+  if (threadIdx.x == 0) partial[blk] = acc;
+}
+
+// Coarse right-hand side (sum of the 8 child residuals / 2) and zero coarse correction;
+// grid (x: coarse row, y: cj, z: ck).
+template <typename T>
+__global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const T* eps, int nx, int ny,
+                                                  int nz, T* fc, T* uc, int cnx, int cny) {
+  int bx, cj, ck;
+  xcd_block3(bx, cj, ck);
+  const int ci = bx * blockDim.x + threadIdx.x;
+  if (ci >= cnx) return;
+  T s8 = 0;
+  for (int d = 0; d < 8; ++d) {
+    const int i = 2 * ci + (d & 1), j = 2 * cj + ((d >> 1) & 1), k = 2 * ck + (d >> 2);
+    const size_t q = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
+    T dg, sm;
+    stencil_s<T>(u, eps, nx, ny, nz, i, j, k, q, dg, sm);
+    s8 += f[q] - (dg * u[q] - sm);
+  }
+  const size_t cc = (size_t)ci + (size_t)cnx * ((size_t)cj + (size_t)cny * ck);
+  fc[cc] = s8 * (T)0.5;
+  uc[cc] = (T)0;
+}
+
+// Trilinear prolongation of the coarse correction onto cell centres: along each axis
+// the nearer coarse centre weighs 3/4 and the farther 1/4; coarse ghost values mirror
+// the cell on the Neumann x and y faces and negate it on the homogeneous Dirichlet z
+// faces.  (Second-order transfer: with cell-averaged restriction the transfer orders
+// then exceed the order of the operator.)
+template <typename T>
+__global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, const T* uc, int cnx,
+                                                 int cny, int cnz) {
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int i = bx * blockDim.x + threadIdx.x;
+  if (i >= nx) return;
+  const int I = i >> 1, J = j >> 1, K = k >> 1;
+  const int ia[2] = {I, (i & 1) ? I + 1 : I - 1};
+  const int ja[2] = {J, (j & 1) ? J + 1 : J - 1};
+  const int ka[2] = {K, (k & 1) ? K + 1 : K - 1};
+  const T wt[2] = {(T)0.75, (T)0.25};
+  T acc = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    int a = ia[c & 1], b = ja[(c >> 1) & 1], z = ka[c >> 2];
+    a = a < 0 ? 0 : (a >= cnx ? cnx - 1 : a);
+    b = b < 0 ? 0 : (b >= cny ? cny - 1 : b);
+    T sg = (T)1;
+    if (z < 0) { z = 0; sg = (T)-1; }
+    if (z >= cnz) { z = cnz - 1; sg = (T)-1; }
+    acc += wt[c & 1] * wt[(c >> 1) & 1] * wt[c >> 2] * sg *
+           uc[(size_t)a + (size_t)cnx * ((size_t)b + (size_t)cny * z)];
+  }
+  u[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] += acc;
 }
 
 // Coarsest level: red-black sweeps from zero inside one workgroup.
@@ -550,11 +631,20 @@ __global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps,
         const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
         if (((i + j + k) & 1) != color) continue;
         T d, sm;
-        stencil<T, T, T>(u, eps, nx, ny, nz, i, j, k, d, sm);
+        stencil_s<T>(u, eps, nx, ny, nz, i, j, k, (size_t)c, d, sm);
         u[c] = (f[c] + sm) / d;
       }
       __syncthreads();
     }
+}
+
+// Initial guess by linear extrapolation in time: phi <- 2 phi - prev, prev <- old phi.
+__global__ void k_extrapolate(double* phi, double* prev, uint32_t n, int have_prev) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const double p = phi[c];
+    if (have_prev) phi[c] = 2.0 * p - prev[c];
+    prev[c] = p;
+  }
 }
 
 template <typename T>
@@ -608,6 +698,10 @@ struct FieldState {
   void* ne = nullptr;
   double* norms = nullptr;   // device: ||b||^2, ||r||^2, then per-block partials
   double* host_norms = nullptr;
+  double* phi_prev = nullptr;  // converged potential of the previous step
+  bool have_prev = false;
+  bool graph_failed = false;
+  hipGraphExec_t graph_exec = nullptr;
 };
 
 static int build_levels(const itokmc_grid_desc* d, int dims[kMaxLevels][3]) {
@@ -617,7 +711,7 @@ static int build_levels(const itokmc_grid_desc* d, int dims[kMaxLevels][3]) {
     dims[nl][0] = nx; dims[nl][1] = ny; dims[nl][2] = nz;
     ++nl;
     const int mn = nx < ny ? (nx < nz ? nx : nz) : (ny < nz ? ny : nz);
-    if (nl == kMaxLevels || mn < 8 || (nx | ny | nz) & 1) break;
+    if (nl == kMaxLevels || mn < 4 || (nx | ny | nz) & 1) break;
     nx /= 2; ny /= 2; nz /= 2;
   }
   return nl;
@@ -630,7 +724,8 @@ size_t field_bytes(const itokmc_grid_desc* d) {
   int dims[kMaxLevels][3];
   const int nl = build_levels(d, dims);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  size_t total = al(n * 8) * 2 + al(n * T) * 6 + al(n * T) * 2 + al(8 * (8 + kRedBlocks));
+  const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
+  size_t total = al(n * 8) * 3 + al(n * T) * 6 + al(n * T) * 2 + al(8 * (8 + npart));
   for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
   return total;
 }
@@ -652,11 +747,13 @@ int field_init(itokmc_ctx* ctx, char* base) {
   char* p = base;
   F->phi = (double*)p; p += al(n * 8);
   F->b = (double*)p; p += al(n * 8);
+  F->phi_prev = (double*)p; p += al(n * 8);
   for (int s = 0; s < 2; ++s)
     for (int a = 0; a < 3; ++a) { F->E[s][a] = p; p += al(n * T); }
   F->sig = p; p += al(n * T);
   F->ne = p; p += al(n * T);
-  F->norms = (double*)p; p += al(8 * (8 + kRedBlocks));
+  const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
+  F->norms = (double*)p; p += al(8 * (8 + npart));
   F->nlev = nl;
   for (int l = 0; l < nl; ++l) {
     Level& L = F->lev[l];
@@ -678,10 +775,20 @@ int field_init(itokmc_ctx* ctx, char* base) {
   return ITOKMC_OK;
 }
 
+// Drop the captured cycle (its launch parameters depend on the tuning).
+void field_reset_graph(itokmc_ctx* ctx) {
+  FieldState* F = fs(ctx);
+  if (!F) return;
+  if (F->graph_exec) (void)hipGraphExecDestroy(F->graph_exec);
+  F->graph_exec = nullptr;
+  F->graph_failed = false;
+}
+
 void field_destroy(itokmc_ctx* ctx) {
   FieldState* F = fs(ctx);
   if (!F) return;
   if (F->host_norms) (void)hipHostFree(F->host_norms);
+  if (F->graph_exec) (void)hipGraphExecDestroy(F->graph_exec);
   delete F;
   ctx->field_state = nullptr;
 }
@@ -690,33 +797,78 @@ static Coef coef(const itokmc_ctx* ctx) {
   return Coef{ctx->c.mu_a, ctx->c.mu_E0, ctx->c.mu_b, ctx->c.E_floor, ctx->c.D};
 }
 
+static dim3 row_grid(int half_nx, int ny, int nz) {
+  return dim3((unsigned)((half_nx + 127) / 128), (unsigned)ny, (unsigned)nz);
+}
+
 template <typename T>
-static void vcycle(itokmc_ctx* ctx, FieldState* F, int l) {
+static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   Level& L = F->lev[l];
-  hipStream_t s = ctx->s;
   T* u = (T*)L.u;
   const T* f = (const T*)L.f;
   const T* ep = (const T*)L.eps;
   if (l == F->nlev - 1) {
     int mx = L.nx > L.ny ? L.nx : L.ny;
     mx = mx > L.nz ? mx : L.nz;
-    k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 8 * mx + 40);
+    const int bs = ctx->tune.bottom_sweeps > 0 ? ctx->tune.bottom_sweeps : 4 * mx + 16;
+    k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, bs);
     return;
   }
   Level& C = F->lev[l + 1];
-  const int g = blocks(L.n);
-  for (int it = 0; it < 2; ++it) {
-    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
-    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
+  const dim3 gs = row_grid((L.nx + 1) / 2, L.ny, L.nz);
+  for (int it = 0; it < ctx->tune.mg_pre; ++it) {
+    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
+    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
   }
-  k_resid_restrict<T><<<blocks(C.n), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx,
-                                                  C.ny, C.nz);
-  vcycle<T>(ctx, F, l + 1);
-  k_prolong<T><<<g, 256, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny);
-  for (int it = 0; it < 2; ++it) {
-    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
-    k_smooth<T><<<g, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
+  k_restrict3<T><<<row_grid(C.nx, C.ny, C.nz), 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u,
+                                                             C.nx, C.ny);
+  vcycle<T>(ctx, F, l + 1, s);
+  k_prolong3<T><<<row_grid(L.nx, L.ny, L.nz), 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny,
+                                                            C.nz);
+  for (int it = 0; it < ctx->tune.mg_post; ++it) {
+    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
+    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
   }
+}
+
+// One refinement cycle: correction V-cycle from zero, potential update, new double
+// residual and its norm.
+template <typename T>
+static void refine_cycle(itokmc_ctx* ctx, FieldState* F, hipStream_t s) {
+  Level& L0 = F->lev[0];
+  k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
+  vcycle<T>(ctx, F, 0, s);
+  k_phi_update<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, (const T*)L0.u, L0.n);
+  const int rb = (int)((L0.n + 255) / 256);
+  k_residual_rows<T><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz, (T*)L0.f,
+                                        F->norms + 8);
+  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+}
+
+// Capture one refinement cycle into a HIP graph (on a private stream: the caller's
+// stream may be the legacy default stream, which cannot be captured).  The graph holds
+// kernel nodes only.  Returns false if capture is unavailable; the caller then runs the
+// cycle eagerly.
+template <typename T>
+static bool capture_cycle(itokmc_ctx* ctx, FieldState* F) {
+  if (F->graph_exec) return true;
+  if (F->graph_failed) return false;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { F->graph_failed = true; return false; }
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    refine_cycle<T>(ctx, F, cs);
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess && g != nullptr;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  (void)hipGetLastError();
+  if (!ok) { F->graph_failed = true; return false; }
+  F->graph_exec = ex;
+  return true;
 }
 
 // Solve with the current right-hand side b and fine coefficient lev[0].eps.
@@ -732,27 +884,29 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
   }
   const int maxc = ctx->d.gmg_max_cycles > 0 ? ctx->d.gmg_max_cycles : 50;
   ctx->total_solves += 1;
-  double bn2 = 0.0, rn2 = 0.0;
-  int cyc = 0;
-  for (;; ++cyc) {
-    k_residual64<T><<<kRedBlocks, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
-                                               (T*)L0.f, F->norms + 8);
-    k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms + 1);
+  const int rb = (int)((L0.n + 255) / 256);
+  k_residual_rows<T><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz, (T*)L0.f,
+                                        F->norms + 8);
+  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+  const bool graph = ctx->tune.use_graph && capture_cycle<T>(ctx, F);
+  for (int cyc = 0;; ++cyc) {
     hipError_t e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return check_hip(ctx, e, "solve residual");
-    bn2 = F->host_norms[0];
-    rn2 = F->host_norms[1];
+    const double bn2 = F->host_norms[0], rn2 = F->host_norms[1];
     const double bn = bn2 > 0.0 ? sqrt(bn2) : 1.0;
     ctx->last_relres = sqrt(rn2) / bn;
     ctx->last_cycles = cyc;
     if (sqrt(rn2) <= ctx->d.gmg_rtol * bn) break;
+    if (cyc >= maxc)
+      return set_error(ctx, ITOKMC_ENOCONV, "field solve: relres %.3e after %d cycles", ctx->last_relres, cyc);
     ctx->total_cycles += 1;
-    if (cyc >= maxc) return set_error(ctx, ITOKMC_ENOCONV, "field solve: relres %.3e after %d cycles",
-                                      ctx->last_relres, cyc);
-    k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
-    vcycle<T>(ctx, F, 0);
-    k_phi_update<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, (const T*)L0.u, L0.n);
+    if (graph) {
+      e = hipGraphLaunch(F->graph_exec, s);
+      if (e != hipSuccess) return check_hip(ctx, e, "solve graph");
+    } else {
+      refine_cycle<T>(ctx, F, s);
+    }
   }
   return check_hip(ctx, hipGetLastError(), "solve");
 }
@@ -775,6 +929,13 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
                                                Eo[2], coef(ctx), mode, (T*)F->sig, (T*)F->ne);
   }
   const double sig_scale = mode == 1 ? kE * K.dt / (kEps0 * K.dx * K.dx * K.dx) : 0.0;
+  if (mode == 1) {
+    k_extrapolate<<<blocks(n), 256, 0, s>>>(F->phi, F->phi_prev, n,
+                                           (F->have_prev && ctx->tune.extrapolate) ? 1 : 0);
+    F->have_prev = true;
+  } else {
+    F->have_prev = false;
+  }
   k_field_prep<T><<<kRedBlocks, 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const T*)F->ne,
                                              (const T*)F->sig, sig_scale, ctx->d.V_anode,
                                              (T*)F->lev[0].eps, F->b, F->norms + 8);
@@ -840,6 +1001,7 @@ int field_set_phi(itokmc_ctx* ctx, const double* host) {
   hipError_t e = hipStreamSynchronize(ctx->s);
   if (e == hipSuccess) e = hipMemcpy(F->phi, host, (size_t)ctx->ncell * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) return check_hip(ctx, e, "set_field");
+  F->have_prev = false;
   const uint32_t n = ctx->ncell;
   if (ctx->d.precision == ITOKMC_FP64)
     k_efield<double><<<blocks(n), 256, 0, ctx->s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz,

@@ -106,6 +106,7 @@ struct itokmc_ctx {
   std::vector<hipEvent_t> ev_free;
   double phase_ms[16] = {0};
   uint64_t phase_calls[16] = {0};
+  itokmc_tuning tune = {2, 2, 0, 1, 1, 0};
 };
 
 namespace itk {
@@ -144,6 +145,7 @@ int field_init(itokmc_ctx* ctx, char* base);
 int field_transport(itokmc_ctx* ctx, const StepConst& k);
 FieldRates field_rates(itokmc_ctx* ctx);  // E view for the KMC rates
 void field_destroy(itokmc_ctx* ctx);
+void field_reset_graph(itokmc_ctx* ctx);
 int field_get_phi(itokmc_ctx* ctx, double* host);
 int field_set_phi(itokmc_ctx* ctx, const double* host);
 int field_deposit(itokmc_ctx* ctx, int what, void* dev_out);

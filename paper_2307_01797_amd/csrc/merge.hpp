@@ -45,12 +45,16 @@ template <> struct Bits<double> {
   static constexpr U lo_init = ~0ull;
 };
 
+// The small path also stages the sort keys of splitting leaves contiguously.
+template <int CAP> struct MergeContig { static constexpr bool value = CAP <= kMergeSmall; };
+
 template <typename T, int CAP>
 constexpr size_t merge_lds_bytes_c() {
   constexpr size_t S = (size_t)CAP + kMaxMergePpc;
   constexpr size_t NL = kMaxMergePpc;
   constexpr size_t U = sizeof(typename Bits<T>::U);
   return S * (8 + 3 * sizeof(T) + 4 + 2 * 2 + 3)  // store, two index buffers, three tag arrays
+         + (MergeContig<CAP>::value ? S * (sizeof(T) + 8) : 0)  // contiguous keys and ids
          + NL * (6 * 4 + 3 * 4 + 6 * U + 1)        // leaf records, per-leaf scratch, extents, axis
          + 64;
 }
@@ -98,6 +102,10 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   for (int k = 0; k < 2; ++k) { tag[k] = (uint8_t*)p; p += (size_t)S; }
   uint8_t* otag = (uint8_t*)p; p += (size_t)S;   // splitting leaf owning an ordered slot
   uint8_t* axis = (uint8_t*)p; p += NL;
+  constexpr bool contig = MergeContig<CAP>::value;
+  p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+  uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id of slot q (sorting leaves)
+  T* kkey = (T*)p; p += contig ? (size_t)S * sizeof(T) : 0;        // key of slot q
 
   // ---- gather: segment [s, e) then product slots [base, base + M) ----
   uint32_t m = 0, wmax = 0;
@@ -205,6 +213,16 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       axis[lane] = (uint8_t)ax;
     }
     __syncthreads();
+    if (contig) {
+      for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
+        const uint8_t L = tag[cb][q];
+        if (L == kNone || !((chm >> L) & 1ull)) continue;
+        const uint16_t pq = I[cb][q];
+        kkey[q] = so[axis[L]][pq];
+        kid[q] = sid[pq];
+      }
+      __syncthreads();
+    }
     // (ii) order each splitting leaf by (coordinate, id); copy the other leaves
     for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
       const uint8_t L = tag[cb][q];
@@ -221,10 +239,27 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       const T kq = so[ax][pq];
       const uint64_t iq = sid[pq];
       uint32_t rank = 0;
-      for (uint32_t r = Ls; r < Ls + Ln; ++r) {
-        const uint16_t pr = I[cb][r];
-        const T kr = so[ax][pr];
-        rank += (kr < kq || (kr == kq && sid[pr] < iq)) ? 1u : 0u;
+      if (contig) {
+        uint32_t r = Ls;
+        const uint32_t rend = Ls + Ln;
+        for (; r + 4 <= rend; r += 4) {
+          const T k0 = kkey[r], k1 = kkey[r + 1], k2 = kkey[r + 2], k3 = kkey[r + 3];
+          const uint64_t i0 = kid[r], i1 = kid[r + 1], i2 = kid[r + 2], i3 = kid[r + 3];
+          rank += (k0 < kq || (k0 == kq && i0 < iq)) ? 1u : 0u;
+          rank += (k1 < kq || (k1 == kq && i1 < iq)) ? 1u : 0u;
+          rank += (k2 < kq || (k2 == kq && i2 < iq)) ? 1u : 0u;
+          rank += (k3 < kq || (k3 == kq && i3 < iq)) ? 1u : 0u;
+        }
+        for (; r < rend; ++r) {
+          const T kr = kkey[r];
+          rank += (kr < kq || (kr == kq && kid[r] < iq)) ? 1u : 0u;
+        }
+      } else {
+        for (uint32_t r = Ls; r < Ls + Ln; ++r) {
+          const uint16_t pr = I[cb][r];
+          const T kr = so[ax][pr];
+          rank += (kr < kq || (kr == kq && sid[pr] < iq)) ? 1u : 0u;
+        }
       }
       I[ncb][RL + rank] = pq;
       otag[RL + rank] = L;

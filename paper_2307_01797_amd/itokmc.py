@@ -26,7 +26,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
            "itokmc_get_field", "itokmc_set_field", "itokmc_destroy", "itokmc_last_error",
            "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_set_profiling",
-           "itokmc_phase_times"]
+           "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
           "field_push", "count"]
 
@@ -48,6 +48,11 @@ class Coeffs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("mu_a", "mu_E0", "mu_b", "E_floor", "D", "alpha_A",
                                                "alpha_B", "eta", "kgamma_ratio", "photon_l1",
                                                "photon_l2")]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("mg_pre", "mg_post", "bottom_sweeps", "use_graph",
+                                              "extrapolate", "pad0")]
 
 
 class SeedDesc(ctypes.Structure):
@@ -123,6 +128,8 @@ def lib():
         L.itokmc_philox_fill.argtypes = [U32, U32, U32, U32, U32, U32, U64, P, P]
         L.itokmc_kmc_cells.argtypes = [P, U64, P, P, P, D, U32, P]
         L.itokmc_set_profiling.argtypes = [P, I32]
+        L.itokmc_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.itokmc_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.itokmc_phase_times.argtypes = [P, P, P, I32, I32]
         _lib = L
     return _lib
@@ -293,6 +300,18 @@ class Sim:
         if a.dtype == np.int32:
             return a.view(np.uint32)
         return a
+
+    def tuning(self):
+        t = Tuning()
+        self._check(lib().itokmc_get_tuning(self.h, ctypes.byref(t)))
+        return {n: getattr(t, n) for n, _ in Tuning._fields_ if n != "pad0"}
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        self._check(lib().itokmc_get_tuning(self.h, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        return self._check(lib().itokmc_set_tuning(self.h, ctypes.byref(t)))
 
     def set_profiling(self, on):
         return self._check(lib().itokmc_set_profiling(self.h, 1 if on else 0))
