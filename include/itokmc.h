@@ -41,7 +41,8 @@ enum {
   ITOKMC_ENOMEM = -2,    /* arena too small                                     */
   ITOKMC_ECAPACITY = -3, /* particle capacity exceeded; state stays valid      */
   ITOKMC_ENOCONV = -4,   /* field solve did not reach its tolerance            */
-  ITOKMC_EHIP = -5       /* a HIP runtime call failed                           */
+  ITOKMC_EHIP = -5,      /* a HIP runtime call failed                           */
+  ITOKMC_EAGAIN = -6     /* ensemble: no free slot, cells or particle quota now  */
 };
 enum { ITOKMC_FP32 = 0, ITOKMC_FP64 = 1 };
 enum { ITOKMC_FIELD_UNIFORM = 0, ITOKMC_FIELD_POISSON = 1 };
@@ -198,6 +199,108 @@ int itokmc_phase_times(itokmc_ctx* ctx, double* ms, uint64_t* calls, int n, int 
 
 void itokmc_destroy(itokmc_ctx* ctx);
 const char* itokmc_last_error(const itokmc_ctx* ctx);
+
+/* ---- batched ensemble of independent realizations --------------------------------
+ * Many independent realizations of the method (each with its own grid, coefficients,
+ * key and run length) share one device arena and advance together: one ensemble step
+ * advances every active realization by one step of its own dt (final algorithm, steps
+ * 1-8 in the uniform-field form: push, binning, KMC, coupling of eq. w) with one
+ * sequence of pool-wide kernels, replayed as a HIP graph.  Every random stream is
+ * keyed by the realization's own (seed, realization) and local cell or particle id,
+ * so a realization's result is bit-identical whether it runs alone, in any mix, or as
+ * a single context (itokmc_init_grid + itokmc_step) with the same descriptor.
+ *
+ * Pools: realizations take grid cells in 4096-cell blocks from a cell pool and reserve
+ * a particle quota (their descriptor's max_particles) from a particle pool; admission
+ * fails with EAGAIN while either pool or the slot table is full.  Supported
+ * realizations: field_mode UNIFORM, n_ppc 0 (no merge), kgamma_ratio 0 (no photons),
+ * Gaussian electron seeds, the ensemble's precision.
+ * Conventions are those of the context API above (status codes, caller-owned arena,
+ * stream given at creation, not thread-safe). */
+typedef struct itokmc_ens itokmc_ens;
+enum { ITOKMC_SLOT_FREE = 0, ITOKMC_SLOT_ACTIVE = 1, ITOKMC_SLOT_DONE = 2,
+       ITOKMC_SLOT_CAPPED = 3 };
+
+typedef struct {
+  int32_t max_slots;       /* realizations resident at once, 1..4096                  */
+  int32_t precision;       /* ITOKMC_FP32 | ITOKMC_FP64, shared by all realizations    */
+  uint64_t max_cells;      /* cell pool (rounded up to 4096-cell blocks), <= 2^31      */
+  uint64_t max_particles;  /* particle pool per bank, <= 2^31 - 1                      */
+} itokmc_ens_desc;
+
+/* Run length of one admitted realization.  It is done after nsteps steps, or after
+ * the first step that began with at least stop_particles live particles (0: never). */
+typedef struct {
+  double dt;               /* step length (s)                                         */
+  uint32_t nsteps;
+  uint32_t pad0;
+  uint64_t stop_particles;
+  uint64_t tag;            /* caller's request id, echoed by poll                    */
+} itokmc_run_desc;
+
+typedef struct {
+  int32_t slot;
+  int32_t state;           /* ITOKMC_SLOT_DONE, or ITOKMC_SLOT_CAPPED if the
+                              realization's particle quota overflowed (its state is
+                              valid up to the dropped products; it stops there)       */
+  uint64_t tag;
+  uint32_t steps;          /* steps run                                               */
+  uint32_t pad0;
+} itokmc_slot_event;
+
+typedef struct {
+  int32_t slots_used, slots_free;
+  uint64_t cells_free;     /* unassigned pool cells                                   */
+  uint64_t particles_free; /* unreserved particle quota                               */
+  uint64_t pool_particles; /* particle slots in use in the pool bank                  */
+  uint64_t steps;          /* ensemble steps run                                      */
+} itokmc_ens_info;
+
+/* Launch shapes of the ensemble step (results do not depend on them): threads per
+ * block of the particle kernels (64..1024, multiple of 64) and their blocks per
+ * compute unit (1..64), threads per block of the KMC kernel, coupling wavefronts per
+ * compute unit (1..256), HIP graph replay (default on). */
+typedef struct {
+  int32_t push_block, push_blocks_per_cu, kmc_block, couple_per_cu, use_graph, pad0;
+} itokmc_ens_tuning;
+
+size_t itokmc_ensemble_arena_bytes(const itokmc_ens_desc* desc);
+/* arena: device pointer, 256-byte aligned, >= itokmc_ensemble_arena_bytes(desc). */
+int itokmc_ensemble_create(itokmc_ens** out, const itokmc_ens_desc* desc, void* arena,
+                           size_t arena_bytes, void* stream);
+/* Admit one realization: grid descriptor (its max_particles is the quota it
+ * reserves), coefficients, seed and run length.  Seeds its particles (enqueued) and
+ * returns its slot.  EAGAIN: no free slot, cells or quota; EINVAL: unsupported
+ * descriptor. */
+int itokmc_ensemble_admit(itokmc_ens* ens, const itokmc_grid_desc* desc,
+                          const itokmc_coeffs* coeffs, const itokmc_seed_desc* seed,
+                          const itokmc_run_desc* run, int32_t* slot);
+/* Enqueue nsteps ensemble steps (does not synchronise). */
+int itokmc_ensemble_step(itokmc_ens* ens, uint32_t nsteps);
+/* Synchronise and report realizations that finished since the last poll (at most
+ * max events; the rest are reported by later polls).  ECAPACITY if the pool bank
+ * overflowed (not reachable while quotas hold). */
+int itokmc_ensemble_poll(itokmc_ens* ens, itokmc_slot_event* events, int32_t max,
+                         int32_t* n_events);
+/* Results of a resident realization (synchronises): diagnostics as for a context,
+ * its particles (cells local to its grid; same array conventions as
+ * itokmc_get_particles) and per-cell counts (ITOKMC_Q_NGP_WEIGHT, NPLUS, NMINUS). */
+int itokmc_ensemble_result(itokmc_ens* ens, int32_t slot, itokmc_diag* out);
+int itokmc_ensemble_get_particles(itokmc_ens* ens, int32_t slot, uint64_t* n, uint32_t* cell,
+                                  double* off, uint32_t* w, uint64_t* id);
+int itokmc_ensemble_get_counts(itokmc_ens* ens, int32_t slot, int which, uint32_t* host);
+/* Free a slot with its cells and quota (its particles are dropped by the next step). */
+int itokmc_ensemble_release(itokmc_ens* ens, int32_t slot);
+int itokmc_ensemble_info(itokmc_ens* ens, itokmc_ens_info* out);
+int itokmc_ensemble_set_tuning(itokmc_ens* ens, const itokmc_ens_tuning* tuning);
+int itokmc_ensemble_get_tuning(itokmc_ens* ens, itokmc_ens_tuning* tuning);
+/* Pick the launch shapes by timing candidate shapes on the live ensemble: each trial
+ * is a real ensemble step (results are unchanged), candidates are interleaved over
+ * rounds; the fastest is kept.  best_ms: its mean step time. */
+int itokmc_ensemble_autotune(itokmc_ens* ens, uint32_t rounds, itokmc_ens_tuning* best,
+                             double* best_ms);
+void itokmc_ensemble_destroy(itokmc_ens* ens);
+const char* itokmc_ensemble_last_error(const itokmc_ens* ens);
 
 /* ---- kernel-level entry points (device pointers; used for unit parity) ----------
  * Philox4x32-10 (Salmon et al. 2011) blocks for counters (c0 + i, c1, c2, c3),

@@ -70,6 +70,20 @@ static void phase_collect(itokmc_ctx* ctx) {
   ctx->ev_used.clear();
 }
 
+void uniform_consts(const itokmc_grid_desc& d, const itokmc_coeffs& c, double dt,
+                    double drift[3], double* diff, double k[3]) {
+  *diff = sqrt(2.0 * c.D * dt) / d.dx;
+  const double* E = d.E_uniform;
+  const double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+  const double mu = mobility(c, Em);
+  for (int a = 0; a < 3; ++a) drift[a] = (-mu * E[a] * dt) / d.dx;
+  const double alpha = Em > 0.0 ? c.alpha_A * exp(-c.alpha_B / Em) : 0.0;
+  const double v = mu * Em;
+  k[0] = alpha * v;
+  k[1] = c.eta * v;
+  k[2] = c.kgamma_ratio * k[0];
+}
+
 StepConst make_const(const itokmc_ctx* ctx, double dt) {
   StepConst k{};
   k.nx = ctx->d.nx; k.ny = ctx->d.ny; k.nz = ctx->d.nz;
@@ -80,17 +94,10 @@ StepConst make_const(const itokmc_ctx* ctx, double dt) {
   k.dx = ctx->d.dx;
   k.dt = dt;
   if (ctx->have_coeffs) {
-    k.diff = sqrt(2.0 * ctx->c.D * dt) / ctx->d.dx;
     if (ctx->d.field_mode == ITOKMC_FIELD_UNIFORM) {
-      const double* E = ctx->d.E_uniform;
-      const double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
-      const double mu = mobility(ctx->c, Em);
-      for (int a = 0; a < 3; ++a) k.drift[a] = (-mu * E[a] * dt) / ctx->d.dx;
-      const double alpha = Em > 0.0 ? ctx->c.alpha_A * exp(-ctx->c.alpha_B / Em) : 0.0;
-      const double v = mu * Em;
-      k.k[0] = alpha * v;
-      k.k[1] = ctx->c.eta * v;
-      k.k[2] = ctx->c.kgamma_ratio * k.k[0];
+      uniform_consts(ctx->d, ctx->c, dt, k.drift, &k.diff, k.k);
+    } else {
+      k.diff = sqrt(2.0 * ctx->c.D * dt) / ctx->d.dx;
     }
   }
   return k;
@@ -105,7 +112,7 @@ struct Layout {
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static bool valid_desc(const itokmc_grid_desc* d) {
+bool valid_desc(const itokmc_grid_desc* d) {
   if (!d) return false;
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
   const uint64_t nc = (uint64_t)d->nx * d->ny * d->nz;
@@ -155,6 +162,23 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(nc * 4);                        // 27 cbase
   put(nc * 4);                        // 28 big
   L->total = o;
+}
+
+int check_coeffs(const itokmc_coeffs* c, std::string* why) {
+  const double v[] = {c->mu_a, c->mu_E0, c->mu_b, c->E_floor, c->D, c->alpha_A, c->alpha_B,
+                      c->eta, c->kgamma_ratio, c->photon_l1, c->photon_l2};
+  for (double x : v)
+    if (!isfinite(x)) { *why = "non-finite coefficient"; return ITOKMC_EINVAL; }
+  if (c->mu_a < 0 || !(c->mu_E0 > 0) || !(c->E_floor > 0) || c->D < 0 || c->alpha_A < 0 ||
+      c->eta < 0 || c->kgamma_ratio < 0) {
+    *why = "negative transport or rate coefficient";
+    return ITOKMC_EINVAL;
+  }
+  if (c->kgamma_ratio > 0 && !(c->photon_l1 > 0 && c->photon_l2 >= c->photon_l1)) {
+    *why = "invalid photon absorption lengths";
+    return ITOKMC_EINVAL;
+  }
+  return ITOKMC_OK;
 }
 
 }  // namespace itk
@@ -239,15 +263,8 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
 
 int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* c) {
   if (!ctx || !c) return ITOKMC_EINVAL;
-  const double v[] = {c->mu_a, c->mu_E0, c->mu_b, c->E_floor, c->D, c->alpha_A, c->alpha_B,
-                      c->eta, c->kgamma_ratio, c->photon_l1, c->photon_l2};
-  for (double x : v)
-    if (!isfinite(x)) return set_error(ctx, ITOKMC_EINVAL, "non-finite coefficient");
-  if (c->mu_a < 0 || !(c->mu_E0 > 0) || !(c->E_floor > 0) || c->D < 0 || c->alpha_A < 0 ||
-      c->eta < 0 || c->kgamma_ratio < 0)
-    return set_error(ctx, ITOKMC_EINVAL, "negative transport or rate coefficient");
-  if (c->kgamma_ratio > 0 && !(c->photon_l1 > 0 && c->photon_l2 >= c->photon_l1))
-    return set_error(ctx, ITOKMC_EINVAL, "invalid photon absorption lengths");
+  std::string why;
+  if (check_coeffs(c, &why)) return set_error(ctx, ITOKMC_EINVAL, "%s", why.c_str());
   ctx->c = *c;
   ctx->have_coeffs = true;
   return ITOKMC_OK;

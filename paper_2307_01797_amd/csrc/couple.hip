@@ -9,6 +9,7 @@
 
 #include "device.hpp"
 #include "itk.hpp"
+#include "couple_device.hpp"
 #include "merge.hpp"
 
 namespace itk {
@@ -17,42 +18,6 @@ namespace {
 
 template <typename T>
 __device__ __forceinline__ T* as(void* p) { return reinterpret_cast<T*>(p); }
-
-// Remove R weight from particles [s, e) of bank b in ascending id order.
-__device__ uint64_t remove_weight(Bank b, uint32_t s, uint32_t e, uint32_t R) {
-  const int lane = lane_id();
-  uint64_t removed = 0;
-  while (R > 0) {
-    uint64_t best = ~0ull;
-    uint32_t bi = 0xFFFFFFFFu;
-    for (uint32_t q = s + lane; q < e; q += 64) {
-      if (b.w[q] > 0) {
-        const uint64_t id = b.id[q];
-        if (id < best) { best = id; bi = q; }
-      }
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      const uint64_t ob = (uint64_t)__shfl_xor((unsigned long long)best, d, 64);
-      const uint32_t oi = __shfl_xor(bi, d, 64);
-      if (ob < best) { best = ob; bi = oi; }
-    }
-    if (bi == 0xFFFFFFFFu) break;  // nothing left (not reachable: KMC keeps X_e >= 0)
-    uint32_t take = 0;
-    if (lane == 0) {
-      const uint32_t w = b.w[bi];
-      take = w < R ? w : R;
-      b.w[bi] = w - take;
-    }
-    take = __shfl(take, 0, 64);
-    // make lane 0's store visible to the whole wavefront before the next search
-    __syncthreads();
-    if (take == 0) break;  // no progress possible (cannot happen with consistent weights)
-    R -= take;
-    removed += take;
-  }
-  return removed;
-}
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which, StepConst K,
@@ -78,18 +43,9 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
     }
     // new particles, one per lane (n_new <= 64), into the reserved slots
     if ((uint32_t)lane < M) {
-      const uint4 r = philox_block(c, (uint32_t)lane, K.step, TAG_CREATE, 0, K.key);
       const uint32_t q = base + (uint32_t)lane;
-      if (q < K.cap) {
-        b.cell[q] = c;
-        as<T>(b.ox)[q] = (T)u24(r.x);
-        as<T>(b.oy)[q] = (T)u24(r.y);
-        as<T>(b.oz)[q] = (T)u24(r.z);
-        b.w[q] = wb + (lane == 0 ? wr : 0u);
-        b.id[q] = make_id(KIND_KMC, K.step, c, (uint32_t)lane);
-      } else {
-        atomicOr(&ctr->overflow, 1u);
-      }
+      if (q < K.cap) write_product<T>(b, q, c, c, (uint32_t)lane, wb, wr, K.step, K.key);
+      else atomicOr(&ctr->overflow, 1u);
     }
     created += M;
     if (n_ppc > 0) {

@@ -1,0 +1,1164 @@
+// Batched ensemble: many independent uniform-field realizations advanced together.
+//
+// Every realization (slot) owns 4096-cell blocks of a shared cell pool and a quota of a
+// shared particle pool.  A global cell g belongs to block g >> 12; the block table gives
+// its slot and its local block, and the slot's block map gives the global block of each
+// local block, so a particle's global cell and its realization's own cell index convert
+// both ways in O(1).  One ensemble step is the single-context step over the whole pool:
+//   push + NGP binning (each particle with its slot's constants) -> counting sort over
+//   the occupied pool cells -> scatter -> per-cell KMC (slot's rates, dt, key, step)
+//   -> coupling of eq. w -> per-slot bookkeeping (step counter, stop rule).
+// Ids, random streams and product positions use the local cell and the slot's own key,
+// so each realization evolves exactly as it would alone.  The fixed kernel sequence is
+// replayed as one HIP graph per bank parity.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "couple_device.hpp"
+#include "device.hpp"
+#include "itk.hpp"
+#include "kmc_device.hpp"
+#include "push_device.hpp"
+
+namespace itk {
+namespace {
+
+constexpr int kBlkShift = 12;
+constexpr uint32_t kBlkCells = 1u << kBlkShift;
+constexpr uint32_t kBlkMask = kBlkCells - 1u;
+constexpr int kMaxSlots = 4096;
+constexpr int kListMax = 768;  // blocks per table-update launch (kernel argument space)
+constexpr int kCUs = 256;
+
+// Per-slot constants, written at admission; step and state advance on the device.
+struct SlotConst {
+  int nx, ny, nz;
+  uint32_t ncell;
+  Key key;
+  uint32_t step, nsteps;
+  uint32_t state, n_new, quota, map_off;
+  uint64_t stop;
+  KmcParams kp;
+  double dt, diff;
+  double drift[3];
+  double k[3];
+};
+
+// Per-slot tallies, structure of arrays: st[f * max_slots + slot].
+enum Stat {
+  S_LIVE = 0,  // live particles pushed this step (reset each step)
+  S_LEFT,      // of which left the grid (reset each step)
+  S_PROD,      // product slots reserved this step (reset each step)
+  S_CAPPED,    // quota overflow flag
+  S_OUTW,      // cumulative outflow weight
+  S_CREATED,   // cumulative computational particles created by the coupling
+  S_REMOVED,   // cumulative weight removed by the coupling
+  S_F0, S_F1, S_F2,
+  S_PUSHED,    // cumulative particle-steps
+  S_NUM
+};
+
+struct BlkList {
+  uint32_t n, first_local;
+  uint32_t b[kListMax];
+};
+
+template <typename T>
+__device__ __forceinline__ T* as(void* p) { return reinterpret_cast<T*>(p); }
+
+__device__ __forceinline__ uint32_t to_local(uint32_t g, const uint32_t* blk_local) {
+  return (blk_local[g >> kBlkShift] << kBlkShift) | (g & kBlkMask);
+}
+__device__ __forceinline__ uint32_t to_global(uint32_t c, const uint32_t* map, uint32_t map_off) {
+  return (map[map_off + (c >> kBlkShift)] << kBlkShift) | (c & kBlkMask);
+}
+
+// Segmented sum over runs of equal keys in the wavefront (inactive lanes: kInvalidCell);
+// true in the last lane of each active run, with *total the run's sum.
+__device__ __forceinline__ bool run_total(uint32_t key, uint64_t val, uint64_t* total) {
+  const int lane = lane_id();
+  const bool active = key != kInvalidCell;
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const bool head = (lane == 0) || (prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int seg_start = 63 - __clzll(heads & upto);
+  const uint64_t after = heads & ~upto;
+  const int seg_end = after ? (__ffsll((long long)after) - 2) : 63;
+  uint64_t x = active ? val : 0ull;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = shfl_up64(x, d);
+    if (lane - d >= seg_start) x += y;
+  }
+  *total = x;
+  return active && lane == seg_end;
+}
+
+// ---- slot table maintenance (arguments by value: no host staging) --------------------
+
+__global__ void e_set_slot(SlotConst v, int s, SlotConst* sc, unsigned long long* st,
+                           uint32_t* stat2, uint32_t ms) {
+  if (threadIdx.x == 0) {
+    sc[s] = v;
+    stat2[2 * s] = v.state;
+    stat2[2 * s + 1] = 0;
+  }
+  if (threadIdx.x < S_NUM) st[threadIdx.x * ms + s] = 0ull;
+}
+
+__global__ void e_set_blocks(BlkList L, int s, uint32_t map_off, int32_t* blk_slot,
+                             uint32_t* blk_local, uint32_t* map) {
+  for (uint32_t i = threadIdx.x; i < L.n; i += blockDim.x) {
+    const uint32_t b = L.b[i], lb = L.first_local + i;
+    blk_slot[b] = s;
+    blk_local[b] = lb;
+    map[map_off + lb] = b;
+  }
+}
+
+__global__ void e_clear_blocks(BlkList L, int s, SlotConst* sc, uint32_t* stat2,
+                               int32_t* blk_slot) {
+  for (uint32_t i = threadIdx.x; i < L.n; i += blockDim.x) blk_slot[L.b[i]] = -1;
+  if (threadIdx.x == 0 && s >= 0) {
+    sc[s].state = ITOKMC_SLOT_FREE;
+    stat2[2 * s] = ITOKMC_SLOT_FREE;
+  }
+}
+
+// Zero the ion counts of a slot's blocks (one workgroup per block).
+__global__ void e_zero_cells(BlkList L, uint32_t* nplus, uint32_t* nminus) {
+  const uint32_t b = L.b[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < kBlkCells; i += blockDim.x) {
+    nplus[(b << kBlkShift) + i] = 0u;
+    nminus[(b << kBlkShift) + i] = 0u;
+  }
+}
+
+__global__ void e_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// ---- seeding ----------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256) e_seed_gaussian(Bank b, Counters* ctr, int which,
+                                                      const SlotConst* sc, int s,
+                                                      const uint32_t* map, uint32_t cap,
+                                                      uint64_t n0, double dx, double cx,
+                                                      double cy, double cz, double sigma) {
+  const SlotConst S = sc[s];
+  const int lim[3] = {S.nx, S.ny, S.nz};
+  const double c[3] = {cx, cy, cz};
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n0;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = base + threadIdx.x;
+    bool keep = false;
+    double xi[3];
+    if (i < n0) keep = gaussian_seed_point(i, S.key, dx, lim, c, sigma, xi);
+    const uint32_t q = wave_append(&ctr->n[which], keep ? 1u : 0u);
+    if (keep) {
+      if (q >= cap) {
+        atomicOr(&ctr->overflow, 1u);
+      } else {
+        const double f[3] = {floor(xi[0]), floor(xi[1]), floor(xi[2])};
+        const uint32_t lc =
+            (uint32_t)f[0] + (uint32_t)S.nx * ((uint32_t)f[1] + (uint32_t)S.ny * (uint32_t)f[2]);
+        b.cell[q] = to_global(lc, map, S.map_off);
+        as<T>(b.ox)[q] = to_off<T>(xi[0] - f[0]);
+        as<T>(b.oy)[q] = to_off<T>(xi[1] - f[1]);
+        as<T>(b.oz)[q] = to_off<T>(xi[2] - f[2]);
+        b.w[q] = 1u;
+        b.id[q] = (1ull << 61) | i;
+      }
+    }
+  }
+}
+
+// ---- the step ---------------------------------------------------------------------------
+
+// Push with fused NGP binning over the pool.  Particles of released slots are dropped,
+// particles of finished slots stay binned where they are.
+template <typename T>
+__global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
+                                              unsigned long long* cellacc, const SlotConst* sc,
+                                              const int32_t* blk_slot, const uint32_t* blk_local,
+                                              const uint32_t* map, unsigned long long* st,
+                                              uint32_t ms, uint32_t cap) {
+  const uint32_t n = min(ctr->n[which], cap);
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t key = kInvalidCell, skey = kInvalidCell, w = 0;
+    uint64_t packed = 0;  // live (bits 0-7), left (8-15), outflow weight (16-63)
+    if (i < n) w = a.w[i];
+    if (w > 0) {
+      const uint32_t g = a.cell[i];
+      const int s = blk_slot[g >> kBlkShift];
+      if (s < 0) {
+        a.w[i] = 0;  // realization released
+      } else if (sc[s].state != ITOKMC_SLOT_ACTIVE) {
+        key = g;
+      } else {
+        const SlotConst& S = sc[s];
+        skey = (uint32_t)s;
+        const uint32_t c = to_local(g, blk_local);
+        T o[3] = {as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i]};
+        int ci[3] = {(int)(c % (uint32_t)S.nx), (int)((c / (uint32_t)S.nx) % (uint32_t)S.ny),
+                     (int)(c / ((uint32_t)S.nx * (uint32_t)S.ny))};
+        const int lim[3] = {S.nx, S.ny, S.nz};
+        const T drift[3] = {(T)S.drift[0], (T)S.drift[1], (T)S.drift[2]};
+        const bool inside = push_uniform<T>(a.id[i], S.step, S.key, drift, (T)S.diff, lim, ci, o);
+        if (inside) {
+          const uint32_t lc =
+              (uint32_t)ci[0] + (uint32_t)S.nx * ((uint32_t)ci[1] + (uint32_t)S.ny * (uint32_t)ci[2]);
+          key = to_global(lc, map, S.map_off);
+          a.cell[i] = key;
+          as<T>(a.ox)[i] = o[0];
+          as<T>(a.oy)[i] = o[1];
+          as<T>(a.oz)[i] = o[2];
+          packed = 1ull;
+        } else {
+          a.w[i] = 0;
+          packed = 1ull | (1ull << 8) | ((uint64_t)w << 16);
+        }
+      }
+    }
+    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+    uint64_t tot;
+    if (run_total(skey, packed, &tot)) {
+      atomicAdd(&st[S_LIVE * ms + skey], (unsigned long long)(tot & 0xFFull));
+      const uint64_t left = (tot >> 8) & 0xFFull;
+      if (left) {
+        atomicAdd(&st[S_LEFT * ms + skey], (unsigned long long)left);
+        atomicAdd(&st[S_OUTW * ms + skey], (unsigned long long)(tot >> 16));
+      }
+    }
+  }
+}
+
+// Per-cell KMC over the occupied pool cells; reserves product slots within each
+// realization's quota and queues cells for the coupling.
+__global__ void __launch_bounds__(256) e_kmc(Counters* ctr, const uint32_t* occ,
+                                            unsigned long long* cellacc, uint32_t* nplus,
+                                            uint32_t* nminus, int32_t* dN, uint32_t* work,
+                                            uint32_t* cbase, const SlotConst* sc,
+                                            const int32_t* blk_slot, const uint32_t* blk_local,
+                                            unsigned long long* st, uint32_t ms, int dest) {
+  const uint32_t n = ctr->n_occ;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t skey = kInvalidCell, M = 0;
+    int64_t d = 0;
+    int64_t f[3] = {0, 0, 0};
+    if (j < n) {
+      const uint32_t g = occ[j];
+      const uint32_t Xe = (uint32_t)cellacc[g];
+      cellacc[g] = 0ull;
+      const int s = blk_slot[g >> kBlkShift];
+      if (s >= 0 && sc[s].state == ITOKMC_SLOT_ACTIVE) {
+        const SlotConst& S = sc[s];
+        skey = (uint32_t)s;
+        const uint32_t c = to_local(g, blk_local);
+        State X{(int64_t)Xe, (int64_t)nplus[g], (int64_t)nminus[g], 0};
+        const double k[3] = {S.k[0], S.k[1], S.k[2]};
+        CellStream cs;
+        cs.init(c, S.step, TAG_KMC, 0, S.key);
+        advance(S.kp, X, k, S.dt, cs, f);
+        nplus[g] = (uint32_t)X.p;
+        nminus[g] = (uint32_t)X.m;
+        d = X.e - (int64_t)Xe;
+        if (d > 0) M = d < (int64_t)S.n_new ? (uint32_t)d : S.n_new;
+      }
+    }
+    // quota: live particles kept by the push plus products reserved so far
+    const uint64_t before = run_add(st + S_PROD * ms, M ? skey : kInvalidCell, M);
+    if (M) {
+      const uint64_t kept = st[S_LIVE * ms + skey] - st[S_LEFT * ms + skey];
+      if (kept + before + M > (uint64_t)sc[skey].quota) {
+        M = 0;
+        d = 0;  // products dropped: the realization is capped and stops after this step
+        atomicOr(&st[S_CAPPED * ms + skey], 1ull);
+      }
+    }
+    if (j < n) dN[j] = (int32_t)d;
+    const bool queue = d != 0;
+    const uint32_t q = wave_append(&ctr->n_work, queue ? 1u : 0u);
+    if (queue) work[q] = j;
+    const uint32_t slot = wave_append(&ctr->n[dest], M);
+    if (M) cbase[j] = slot;
+    // per-slot tallies
+    uint64_t tot;
+    if (run_total(skey, (uint64_t)f[0], &tot) && tot) atomicAdd(&st[S_F0 * ms + skey], (unsigned long long)tot);
+    if (run_total(skey, (uint64_t)f[1], &tot) && tot) atomicAdd(&st[S_F1 * ms + skey], (unsigned long long)tot);
+    if (run_total(skey, (uint64_t)f[2], &tot) && tot) atomicAdd(&st[S_F2 * ms + skey], (unsigned long long)tot);
+    if (run_total(skey, (uint64_t)M, &tot) && tot) atomicAdd(&st[S_CREATED * ms + skey], (unsigned long long)tot);
+    if (run_total(skey, d < 0 ? (uint64_t)(-d) : 0ull, &tot) && tot)
+      atomicAdd(&st[S_REMOVED * ms + skey], (unsigned long long)tot);
+  }
+}
+
+// Coupling of eq. w, one wavefront per queued cell (no merge in the ensemble).
+template <typename T>
+__global__ void __launch_bounds__(64) e_couple(Bank b, Counters* ctr, const uint32_t* work,
+                                              const uint32_t* occ, const uint32_t* start,
+                                              const int32_t* dN, const uint32_t* cbase,
+                                              const SlotConst* sc, const int32_t* blk_slot,
+                                              const uint32_t* blk_local, uint32_t cap) {
+  const uint32_t nwork = ctr->n_work;
+  const int lane = lane_id();
+  for (uint32_t t = blockIdx.x; t < nwork; t += gridDim.x) {
+    const uint32_t j = work[t];
+    const uint32_t g = occ[j];
+    const int32_t d = dN[j];
+    if (d < 0) (void)remove_weight(b, start[g], start[g + 1], (uint32_t)(-d));
+    if (d > 0) {
+      const int s = blk_slot[g >> kBlkShift];
+      const SlotConst& S = sc[s];
+      const uint32_t M = (uint32_t)d < S.n_new ? (uint32_t)d : S.n_new;
+      const uint32_t wb = (uint32_t)d / M, wr = (uint32_t)d % M;
+      if ((uint32_t)lane < M) {
+        const uint32_t q = cbase[j] + (uint32_t)lane;
+        if (q < cap)
+          write_product<T>(b, q, g, to_local(g, blk_local), (uint32_t)lane, wb, wr, S.step, S.key);
+        else
+          atomicOr(&ctr->overflow, 1u);
+      }
+    }
+  }
+}
+
+// Per-slot end of step: advance the step counter and apply the stop rule.
+__global__ void e_finish(SlotConst* sc, unsigned long long* st, uint32_t* stat2, uint32_t ms) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ms; s += gridDim.x * blockDim.x) {
+    if (sc[s].state != ITOKMC_SLOT_ACTIVE) continue;
+    const uint64_t live = st[S_LIVE * ms + s];
+    st[S_PUSHED * ms + s] += live;
+    const uint32_t step = sc[s].step + 1u;
+    sc[s].step = step;
+    uint32_t state = ITOKMC_SLOT_ACTIVE;
+    if (st[S_CAPPED * ms + s]) state = ITOKMC_SLOT_CAPPED;
+    else if (step >= sc[s].nsteps || (sc[s].stop && live >= sc[s].stop)) state = ITOKMC_SLOT_DONE;
+    sc[s].state = state;
+    st[S_LIVE * ms + s] = 0ull;
+    st[S_LEFT * ms + s] = 0ull;
+    st[S_PROD * ms + s] = 0ull;
+    stat2[2 * s] = state;
+    stat2[2 * s + 1] = step;
+  }
+}
+
+// ---- queries ------------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256) e_extract(Bank a, const Counters* ctr, int which,
+                                                uint32_t cap, int s, const int32_t* blk_slot,
+                                                const uint32_t* blk_local, Bank o,
+                                                uint32_t* count) {
+  const uint32_t n = min(ctr->n[which], cap);
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    bool mine = false;
+    if (i < n && a.w[i] > 0) mine = blk_slot[a.cell[i] >> kBlkShift] == s;
+    const uint32_t q = wave_append(count, mine ? 1u : 0u);
+    if (mine) {
+      o.cell[q] = to_local(a.cell[i], blk_local);
+      as<T>(o.ox)[q] = as<T>(a.ox)[i];
+      as<T>(o.oy)[q] = as<T>(a.oy)[i];
+      as<T>(o.oz)[q] = as<T>(a.oz)[i];
+      o.w[q] = a.w[i];
+      o.id[q] = a.id[i];
+    }
+  }
+}
+
+// Live particle count and weight of one slot, and its ion sums over its blocks.
+__global__ void __launch_bounds__(256) e_reduce_slot(Bank a, const Counters* ctr, int which,
+                                                    uint32_t cap, int s, const int32_t* blk_slot,
+                                                    unsigned long long* out) {
+  const uint32_t n = min(ctr->n[which], cap);
+  uint64_t cnt = 0, W = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t w = a.w[i];
+    if (w > 0 && blk_slot[a.cell[i] >> kBlkShift] == s) { ++cnt; W += w; }
+  }
+  cnt = wave_sum64(cnt);
+  W = wave_sum64(W);
+  if (lane_id() == 0) {
+    if (cnt) atomicAdd(&out[0], (unsigned long long)cnt);
+    if (W) atomicAdd(&out[1], (unsigned long long)W);
+  }
+}
+
+__global__ void __launch_bounds__(256) e_reduce_ions(BlkList L, const uint32_t* nplus,
+                                                    const uint32_t* nminus,
+                                                    unsigned long long* out) {
+  const uint32_t b = L.b[blockIdx.x];
+  uint64_t p = 0, m = 0;
+  for (uint32_t i = threadIdx.x; i < kBlkCells; i += blockDim.x) {
+    p += nplus[(b << kBlkShift) + i];
+    m += nminus[(b << kBlkShift) + i];
+  }
+  p = wave_sum64(p);
+  m = wave_sum64(m);
+  if (lane_id() == 0) {
+    if (p) atomicAdd(&out[2], (unsigned long long)p);
+    if (m) atomicAdd(&out[3], (unsigned long long)m);
+  }
+}
+
+// First-fit allocator of contiguous index ranges (block-map entries).
+struct RangeAlloc {
+  std::map<uint32_t, uint32_t> free_;  // start -> length
+  void init(uint32_t n) { free_.clear(); if (n) free_[0] = n; }
+  bool take(uint32_t n, uint32_t* at) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *at = it->first;
+        const uint32_t rest = it->second - n, st = it->first + n;
+        free_.erase(it);
+        if (rest) free_[st] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void give(uint32_t at, uint32_t n) {
+    if (!n) return;
+    auto it = free_.emplace(at, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct SlotHost {
+  bool used = false, reported = false;
+  std::vector<uint32_t> blocks;
+  uint32_t map_off = 0;
+  uint64_t quota = 0;
+  itokmc_grid_desc d{};
+  itokmc_coeffs c{};
+  itokmc_run_desc r{};
+};
+
+}  // namespace
+}  // namespace itk
+
+using namespace itk;
+
+struct itokmc_ens {
+  itokmc_ens_desc d{};
+  hipStream_t s = nullptr;
+  char* arena = nullptr;
+  uint32_t nblk = 0, ms = 0, max_cells = 0;
+  uint32_t cap = 0;
+  int cur = 0;
+  Bank bank[2];
+  unsigned long long* cellacc = nullptr;
+  uint32_t *start = nullptr, *occ = nullptr, *nplus = nullptr, *nminus = nullptr;
+  int32_t* dN = nullptr;
+  uint32_t *work = nullptr, *cbase = nullptr, *blocksums = nullptr;
+  Counters* ctr = nullptr;
+  uint32_t* misc = nullptr;  // [0] cells to scan, [1] extraction counter
+  unsigned long long* reduce = nullptr;
+  SlotConst* sc = nullptr;
+  unsigned long long* st = nullptr;
+  uint32_t* stat2 = nullptr;
+  int32_t* blk_slot = nullptr;
+  uint32_t *blk_local = nullptr, *map = nullptr;
+  // host bookkeeping
+  std::vector<SlotHost> slots;
+  std::set<uint32_t> free_blocks, used_blocks;
+  std::vector<uint32_t> pending_blocks;
+  std::vector<std::pair<uint32_t, uint32_t>> pending_map;
+  RangeAlloc map_alloc;
+  uint64_t quota_free = 0, pending_quota = 0;
+  uint32_t hw_blocks = 0;
+  uint64_t steps = 0;
+  itokmc_ens_tuning tune{256, 8, 256, 64, 1, 0};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_failed = false;
+  uint32_t* host_stat = nullptr;
+  Counters* host_ctr = nullptr;
+  unsigned long long* host_red = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int ens_error(itokmc_ens* e, int code, const char* fmt, ...) {
+  if (e) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    e->err = buf;
+  }
+  return code;
+}
+
+int ens_hip(itokmc_ens* e, hipError_t h, const char* what) {
+  if (h == hipSuccess) return ITOKMC_OK;
+  return ens_error(e, ITOKMC_EHIP, "%s: %s", what, hipGetErrorString(h));
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct EnsLayout {
+  size_t off[32];
+  size_t total;
+};
+
+bool valid_ens(const itokmc_ens_desc* d) {
+  if (!d) return false;
+  if (d->max_slots < 1 || d->max_slots > kMaxSlots) return false;
+  if (d->precision != ITOKMC_FP32 && d->precision != ITOKMC_FP64) return false;
+  if (d->max_cells < 1 || d->max_cells > (1ull << 31)) return false;
+  if (d->max_particles < 1 || d->max_particles > 0x7FFFFFFFull) return false;
+  return true;
+}
+
+void ens_layout(const itokmc_ens_desc* d, EnsLayout* L) {
+  const uint64_t nblk = (d->max_cells + kBlkCells - 1) / kBlkCells;
+  const uint64_t nc = nblk * kBlkCells;
+  const uint64_t cap = d->max_particles;
+  const uint64_t ms = (uint64_t)d->max_slots;
+  const size_t T = d->precision == ITOKMC_FP64 ? 8 : 4;
+  size_t o = 0;
+  int i = 0;
+  auto put = [&](size_t bytes) { L->off[i++] = o; o += al(bytes); };
+  for (int b = 0; b < 2; ++b) {
+    put(cap * 4); put(cap * T); put(cap * T); put(cap * T); put(cap * 4); put(cap * 8); put(cap * 4);
+  }
+  put(nc * 8);                         // 14 cellacc
+  put((nc + 1) * 4);                   // 15 start
+  put(nc * 4);                         // 16 occ
+  put(nc * 4);                         // 17 nplus
+  put(nc * 4);                         // 18 nminus
+  put(nc * 4);                         // 19 dN
+  put(nc * 4);                         // 20 work
+  put(nc * 4);                         // 21 cbase
+  put(((nc + 2047) / 2048 + 1) * 8);   // 22 blocksums
+  put(sizeof(Counters));               // 23 counters
+  put(64);                             // 24 misc
+  put(64);                             // 25 reduction scratch
+  put(ms * sizeof(SlotConst));         // 26 slot constants
+  put(ms * S_NUM * 8);                 // 27 tallies
+  put(ms * 8);                         // 28 state and step
+  put(nblk * 4);                       // 29 block -> slot
+  put(nblk * 4);                       // 30 block -> local block
+  put(2 * nblk * 4);                   // 31 block maps
+  L->total = o;
+}
+
+inline bool f64(const itokmc_ens* e) { return e->d.precision == ITOKMC_FP64; }
+
+int grid_particles(const itokmc_ens* e) {
+  int g = kCUs * e->tune.push_blocks_per_cu;
+  const uint64_t need = ((uint64_t)e->cap + e->tune.push_block - 1) / e->tune.push_block;
+  if ((uint64_t)g > need) g = (int)std::max<uint64_t>(need, 1);
+  return g;
+}
+
+// Enqueue one ensemble step for bank parity cur on stream s.
+hipError_t enqueue_step(itokmc_ens* e, int cur, hipStream_t s) {
+  const int dest = 1 - cur;
+  const int gp = grid_particles(e);
+  if (f64(e))
+    e_push<double><<<gp, e->tune.push_block, 0, s>>>(e->bank[cur], e->ctr, cur, e->cellacc, e->sc,
+                                                     e->blk_slot, e->blk_local, e->map, e->st, e->ms,
+                                                     e->cap);
+  else
+    e_push<float><<<gp, e->tune.push_block, 0, s>>>(e->bank[cur], e->ctr, cur, e->cellacc, e->sc,
+                                                    e->blk_slot, e->blk_local, e->map, e->st, e->ms,
+                                                    e->cap);
+  hipError_t h = hipGetLastError();
+  if (h != hipSuccess) return h;
+  h = launch_scan_raw(e->cellacc, e->max_cells, e->misc, e->blocksums, e->start, e->occ, e->ctr,
+                      dest, s);
+  if (h != hipSuccess) return h;
+  h = launch_scatter_raw(e->bank[cur], e->bank[dest], e->ctr, cur, e->start, e->cap, f64(e) ? 1 : 0,
+                         std::max(1, (int)std::min<uint64_t>((uint64_t)kCUs * 8, (e->cap + 255) / 256)), s);
+  if (h != hipSuccess) return h;
+  int gk = (int)std::min<uint64_t>((uint64_t)kCUs * 8, ((uint64_t)e->max_cells + e->tune.kmc_block - 1) /
+                                                           e->tune.kmc_block);
+  if (gk < 1) gk = 1;
+  e_kmc<<<gk, e->tune.kmc_block, 0, s>>>(e->ctr, e->occ, e->cellacc, e->nplus, e->nminus, e->dN,
+                                         e->work, e->cbase, e->sc, e->blk_slot, e->blk_local, e->st,
+                                         e->ms, dest);
+  h = hipGetLastError();
+  if (h != hipSuccess) return h;
+  const int gc = kCUs * e->tune.couple_per_cu;
+  if (f64(e))
+    e_couple<double><<<gc, 64, 0, s>>>(e->bank[dest], e->ctr, e->work, e->occ, e->start, e->dN,
+                                       e->cbase, e->sc, e->blk_slot, e->blk_local, e->cap);
+  else
+    e_couple<float><<<gc, 64, 0, s>>>(e->bank[dest], e->ctr, e->work, e->occ, e->start, e->dN,
+                                      e->cbase, e->sc, e->blk_slot, e->blk_local, e->cap);
+  h = hipGetLastError();
+  if (h != hipSuccess) return h;
+  e_finish<<<(e->ms + 255) / 256, 256, 0, s>>>(e->sc, e->st, e->stat2, e->ms);
+  return hipGetLastError();
+}
+
+void drop_graphs(itokmc_ens* e) {
+  for (int p = 0; p < 2; ++p)
+    if (e->graph[p]) { (void)hipGraphExecDestroy(e->graph[p]); e->graph[p] = nullptr; }
+  e->graph_failed = false;
+}
+
+bool capture_graphs(itokmc_ens* e) {
+  if (e->graph[0] && e->graph[1]) return true;
+  if (e->graph_failed) return false;
+  for (int p = 0; p < 2; ++p) {
+    if (e->graph[p]) continue;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { e->graph_failed = true; return false; }
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      const hipError_t h = enqueue_step(e, p, cs);
+      const bool end_ok = hipStreamEndCapture(cs, &g) == hipSuccess && g != nullptr;
+      ok = h == hipSuccess && end_ok;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+    if (!ok) { drop_graphs(e); e->graph_failed = true; return false; }
+    e->graph[p] = ex;
+  }
+  return true;
+}
+
+// Launch a block list in chunks of kListMax.
+template <typename F>
+hipError_t for_lists(const std::vector<uint32_t>& blocks, F f) {
+  BlkList L;
+  for (size_t i = 0; i < blocks.size(); i += kListMax) {
+    L.n = (uint32_t)std::min<size_t>(kListMax, blocks.size() - i);
+    L.first_local = (uint32_t)i;
+    for (uint32_t k = 0; k < L.n; ++k) L.b[k] = blocks[i + k];
+    hipError_t h = f(L);
+    if (h != hipSuccess) return h;
+  }
+  return hipSuccess;
+}
+
+hipError_t update_hw(itokmc_ens* e) {
+  const uint32_t hw = e->used_blocks.empty() ? 0u : *e->used_blocks.rbegin() + 1u;
+  if (hw == e->hw_blocks) return hipSuccess;
+  e->hw_blocks = hw;
+  e_set_u32<<<1, 1, 0, e->s>>>(e->misc, hw * kBlkCells);
+  return hipGetLastError();
+}
+
+int check_slot(itokmc_ens* e, int32_t slot) {
+  if (!e) return ITOKMC_EINVAL;
+  if (slot < 0 || slot >= (int32_t)e->ms || !e->slots[slot].used)
+    return ens_error(e, ITOKMC_EINVAL, "slot %d is not in use", slot);
+  return ITOKMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t itokmc_ensemble_arena_bytes(const itokmc_ens_desc* desc) {
+  if (!valid_ens(desc)) return 0;
+  EnsLayout L;
+  ens_layout(desc, &L);
+  return L.total;
+}
+
+int itokmc_ensemble_create(itokmc_ens** out, const itokmc_ens_desc* desc, void* arena,
+                           size_t arena_bytes, void* stream) {
+  if (!out) return ITOKMC_EINVAL;
+  *out = nullptr;
+  if (!valid_ens(desc)) return ITOKMC_EINVAL;
+  EnsLayout L;
+  ens_layout(desc, &L);
+  if (!arena || ((uintptr_t)arena & 255)) return ITOKMC_EINVAL;
+  if (arena_bytes < L.total) return ITOKMC_ENOMEM;
+  itokmc_ens* e = new itokmc_ens();
+  e->d = *desc;
+  e->s = (hipStream_t)stream;
+  e->arena = (char*)arena;
+  e->ms = (uint32_t)desc->max_slots;
+  e->nblk = (uint32_t)((desc->max_cells + kBlkCells - 1) / kBlkCells);
+  e->max_cells = e->nblk * kBlkCells;
+  e->cap = (uint32_t)desc->max_particles;
+  char* a = e->arena;
+  for (int b = 0; b < 2; ++b) {
+    Bank& k = e->bank[b];
+    const int o = 7 * b;
+    k.cell = (uint32_t*)(a + L.off[o]);
+    k.ox = a + L.off[o + 1];
+    k.oy = a + L.off[o + 2];
+    k.oz = a + L.off[o + 3];
+    k.w = (uint32_t*)(a + L.off[o + 4]);
+    k.id = (uint64_t*)(a + L.off[o + 5]);
+    k.rank = (uint32_t*)(a + L.off[o + 6]);
+  }
+  e->cellacc = (unsigned long long*)(a + L.off[14]);
+  e->start = (uint32_t*)(a + L.off[15]);
+  e->occ = (uint32_t*)(a + L.off[16]);
+  e->nplus = (uint32_t*)(a + L.off[17]);
+  e->nminus = (uint32_t*)(a + L.off[18]);
+  e->dN = (int32_t*)(a + L.off[19]);
+  e->work = (uint32_t*)(a + L.off[20]);
+  e->cbase = (uint32_t*)(a + L.off[21]);
+  e->blocksums = (uint32_t*)(a + L.off[22]);
+  e->ctr = (Counters*)(a + L.off[23]);
+  e->misc = (uint32_t*)(a + L.off[24]);
+  e->reduce = (unsigned long long*)(a + L.off[25]);
+  e->sc = (SlotConst*)(a + L.off[26]);
+  e->st = (unsigned long long*)(a + L.off[27]);
+  e->stat2 = (uint32_t*)(a + L.off[28]);
+  e->blk_slot = (int32_t*)(a + L.off[29]);
+  e->blk_local = (uint32_t*)(a + L.off[30]);
+  e->map = (uint32_t*)(a + L.off[31]);
+  hipError_t h = hipSuccess;
+  if (h == hipSuccess) h = hipMemsetAsync(e->cellacc, 0, (size_t)e->max_cells * 8, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->ctr, 0, sizeof(Counters), e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->misc, 0, 64, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->sc, 0, (size_t)e->ms * sizeof(SlotConst), e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->st, 0, (size_t)e->ms * S_NUM * 8, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->stat2, 0, (size_t)e->ms * 8, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->blk_slot, 0xFF, (size_t)e->nblk * 4, e->s);
+  if (h == hipSuccess) h = hipHostMalloc((void**)&e->host_stat, (size_t)e->ms * 8, hipHostMallocDefault);
+  if (h == hipSuccess) h = hipHostMalloc((void**)&e->host_ctr, sizeof(Counters), hipHostMallocDefault);
+  if (h == hipSuccess) h = hipHostMalloc((void**)&e->host_red, 64, hipHostMallocDefault);
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  if (h != hipSuccess) {
+    if (e->host_stat) (void)hipHostFree(e->host_stat);
+    if (e->host_ctr) (void)hipHostFree(e->host_ctr);
+    if (e->host_red) (void)hipHostFree(e->host_red);
+    delete e;
+    return ITOKMC_EHIP;
+  }
+  e->slots.resize(e->ms);
+  for (uint32_t b = 0; b < e->nblk; ++b) e->free_blocks.insert(b);
+  e->map_alloc.init(2 * e->nblk);
+  e->quota_free = e->cap;
+  *out = e;
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_admit(itokmc_ens* e, const itokmc_grid_desc* d, const itokmc_coeffs* c,
+                          const itokmc_seed_desc* sd, const itokmc_run_desc* r, int32_t* slot) {
+  if (!e || !d || !c || !sd || !r || !slot) return ITOKMC_EINVAL;
+  *slot = -1;
+  if (!valid_desc(d)) return ens_error(e, ITOKMC_EINVAL, "invalid grid descriptor");
+  if (d->field_mode != ITOKMC_FIELD_UNIFORM || d->n_ppc != 0 || d->precision != e->d.precision)
+    return ens_error(e, ITOKMC_EINVAL,
+                     "ensemble realizations need a uniform field, n_ppc 0 and the ensemble's precision");
+  std::string why;
+  if (check_coeffs(c, &why)) return ens_error(e, ITOKMC_EINVAL, "%s", why.c_str());
+  if (c->kgamma_ratio != 0.0) return ens_error(e, ITOKMC_EINVAL, "ensemble realizations carry no photons");
+  if (sd->kind != ITOKMC_SEED_GAUSSIAN || !(sd->sigma > 0.0))
+    return ens_error(e, ITOKMC_EINVAL, "ensemble seeds are Gaussian electrons with sigma > 0");
+  if (!(r->dt > 0.0) || r->nsteps < 1) return ens_error(e, ITOKMC_EINVAL, "dt > 0 and nsteps >= 1 required");
+  if (sd->n0 > d->max_particles) return ens_error(e, ITOKMC_EINVAL, "seed exceeds the particle quota");
+  const uint64_t ncell = (uint64_t)d->nx * d->ny * d->nz;
+  const uint32_t nb = (uint32_t)((ncell + kBlkCells - 1) / kBlkCells);
+  const uint64_t quota = d->max_particles;
+  if (quota > e->cap || nb > e->nblk) return ens_error(e, ITOKMC_EINVAL, "realization larger than the pools");
+  int s = -1;
+  for (uint32_t i = 0; i < e->ms; ++i)
+    if (!e->slots[i].used) { s = (int)i; break; }
+  if (s < 0 || quota > e->quota_free || nb > e->free_blocks.size()) return ITOKMC_EAGAIN;
+  uint32_t map_off = 0;
+  if (!e->map_alloc.take(nb, &map_off)) return ITOKMC_EAGAIN;
+  SlotHost& H = e->slots[s];
+  H = SlotHost();
+  H.used = true;
+  H.d = *d;
+  H.c = *c;
+  H.r = *r;
+  H.quota = quota;
+  H.map_off = map_off;
+  for (uint32_t i = 0; i < nb; ++i) {
+    const uint32_t b = *e->free_blocks.begin();
+    e->free_blocks.erase(e->free_blocks.begin());
+    e->used_blocks.insert(b);
+    H.blocks.push_back(b);
+  }
+  e->quota_free -= quota;
+  SlotConst v{};
+  v.nx = d->nx; v.ny = d->ny; v.nz = d->nz;
+  v.ncell = (uint32_t)ncell;
+  v.key = Key{d->seed, d->realization};
+  v.step = 0;
+  v.nsteps = r->nsteps;
+  v.state = ITOKMC_SLOT_ACTIVE;
+  v.n_new = (uint32_t)d->n_new;
+  v.quota = (uint32_t)quota;
+  v.map_off = map_off;
+  v.stop = r->stop_particles;
+  v.kp = KmcParams{d->kmc_mode, d->kmc_nc, d->kmc_nssa, d->kmc_eps};
+  v.dt = r->dt;
+  uniform_consts(*d, *c, r->dt, v.drift, &v.diff, v.k);
+  hipError_t h = update_hw(e);
+  if (h == hipSuccess) {
+    e_set_slot<<<1, 64, 0, e->s>>>(v, s, e->sc, e->st, e->stat2, e->ms);
+    h = hipGetLastError();
+  }
+  if (h == hipSuccess)
+    h = for_lists(H.blocks, [&](const BlkList& L) {
+      e_set_blocks<<<1, 256, 0, e->s>>>(L, s, map_off, e->blk_slot, e->blk_local, e->map);
+      e_zero_cells<<<L.n, 256, 0, e->s>>>(L, e->nplus, e->nminus);
+      return hipGetLastError();
+    });
+  if (h == hipSuccess && sd->n0 > 0) {
+    const int g = (int)std::min<uint64_t>(4096, (sd->n0 + 255) / 256);
+    if (f64(e))
+      e_seed_gaussian<double><<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->sc, s, e->map,
+                                                   e->cap, sd->n0, d->dx, sd->centre[0], sd->centre[1],
+                                                   sd->centre[2], sd->sigma);
+    else
+      e_seed_gaussian<float><<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->sc, s, e->map,
+                                                  e->cap, sd->n0, d->dx, sd->centre[0], sd->centre[1],
+                                                  sd->centre[2], sd->sigma);
+    h = hipGetLastError();
+  }
+  if (h != hipSuccess) return ens_hip(e, h, "admit");
+  *slot = s;
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_step(itokmc_ens* e, uint32_t nsteps) {
+  if (!e) return ITOKMC_EINVAL;
+  const bool graph = e->tune.use_graph && capture_graphs(e);
+  for (uint32_t i = 0; i < nsteps; ++i) {
+    hipError_t h = graph ? hipGraphLaunch(e->graph[e->cur], e->s) : enqueue_step(e, e->cur, e->s);
+    if (h != hipSuccess) return ens_hip(e, h, "ensemble step");
+    e->cur = 1 - e->cur;
+    e->steps += 1;
+  }
+  if (nsteps > 0 && (!e->pending_blocks.empty() || e->pending_quota || !e->pending_map.empty())) {
+    // the step just enqueued dropped the particles of released slots
+    for (uint32_t b : e->pending_blocks) e->free_blocks.insert(b);
+    e->pending_blocks.clear();
+    for (auto& m : e->pending_map) e->map_alloc.give(m.first, m.second);
+    e->pending_map.clear();
+    e->quota_free += e->pending_quota;
+    e->pending_quota = 0;
+    const hipError_t h = update_hw(e);
+    if (h != hipSuccess) return ens_hip(e, h, "ensemble step");
+  }
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_poll(itokmc_ens* e, itokmc_slot_event* ev, int32_t max, int32_t* n_ev) {
+  if (!e || !n_ev || (max > 0 && !ev)) return ITOKMC_EINVAL;
+  *n_ev = 0;
+  uint32_t top = 0;
+  for (uint32_t i = 0; i < e->ms; ++i)
+    if (e->slots[i].used) top = i + 1;
+  hipError_t h = hipSuccess;
+  if (top) h = hipMemcpyAsync(e->host_stat, e->stat2, (size_t)top * 8, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipMemcpyAsync(e->host_ctr, e->ctr, sizeof(Counters), hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  if (h != hipSuccess) return ens_hip(e, h, "poll");
+  int32_t k = 0;
+  for (uint32_t i = 0; i < top && k < max; ++i) {
+    SlotHost& H = e->slots[i];
+    const uint32_t state = e->host_stat[2 * i];
+    if (!H.used || H.reported || (state != ITOKMC_SLOT_DONE && state != ITOKMC_SLOT_CAPPED)) continue;
+    H.reported = true;
+    ev[k].slot = (int32_t)i;
+    ev[k].state = (int32_t)state;
+    ev[k].tag = H.r.tag;
+    ev[k].steps = e->host_stat[2 * i + 1];
+    ev[k].pad0 = 0;
+    ++k;
+  }
+  *n_ev = k;
+  if (e->host_ctr->overflow)
+    return ens_error(e, ITOKMC_ECAPACITY, "ensemble pool overflow (flags %u)", e->host_ctr->overflow);
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_result(itokmc_ens* e, int32_t slot, itokmc_diag* out) {
+  int rc = check_slot(e, slot);
+  if (rc) return rc;
+  if (!out) return ITOKMC_EINVAL;
+  SlotHost& H = e->slots[slot];
+  hipError_t h = hipMemsetAsync(e->reduce, 0, 64, e->s);
+  if (h == hipSuccess) {
+    const int g = (int)std::min<uint64_t>(4096, ((uint64_t)e->cap + 255) / 256);
+    e_reduce_slot<<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->cap, slot, e->blk_slot,
+                                       e->reduce);
+    h = hipGetLastError();
+  }
+  if (h == hipSuccess)
+    h = for_lists(H.blocks, [&](const BlkList& L) {
+      e_reduce_ions<<<L.n, 256, 0, e->s>>>(L, e->nplus, e->nminus, e->reduce);
+      return hipGetLastError();
+    });
+  unsigned long long stv[S_NUM];
+  for (int f = 0; f < S_NUM && h == hipSuccess; ++f)
+    h = hipMemcpyAsync(&stv[f], e->st + (size_t)f * e->ms + slot, 8, hipMemcpyDeviceToHost, e->s);
+  uint32_t st2[2] = {0, 0};
+  if (h == hipSuccess) h = hipMemcpyAsync(st2, e->stat2 + 2 * slot, 8, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipMemcpyAsync(e->host_red, e->reduce, 32, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  if (h != hipSuccess) return ens_hip(e, h, "result");
+  memset(out, 0, sizeof(*out));
+  out->n_particles = e->host_red[0];
+  out->weight = e->host_red[1];
+  out->n_plus = (int64_t)e->host_red[2];
+  out->n_minus = (int64_t)e->host_red[3];
+  out->charge = out->n_plus - (int64_t)out->weight - out->n_minus;
+  out->outflow_weight = stv[S_OUTW];
+  out->fires[0] = stv[S_F0];
+  out->fires[1] = stv[S_F1];
+  out->fires[2] = stv[S_F2];
+  out->created = stv[S_CREATED];
+  out->removed_weight = stv[S_REMOVED];
+  out->step = st2[1];
+  out->rho_sum = 1.602176634e-19 * (double)out->charge;
+  out->overflow = stv[S_CAPPED] ? 1u : 0u;
+  out->particle_steps = stv[S_PUSHED];
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_get_particles(itokmc_ens* e, int32_t slot, uint64_t* n, uint32_t* cell,
+                                  double* off, uint32_t* w, uint64_t* id) {
+  int rc = check_slot(e, slot);
+  if (rc) return rc;
+  if (!n) return ITOKMC_EINVAL;
+  const int o = 1 - e->cur;  // the other bank is free between steps
+  hipError_t h = hipMemsetAsync(e->misc + 1, 0, 4, e->s);
+  if (h == hipSuccess) {
+    const int g = (int)std::min<uint64_t>(4096, ((uint64_t)e->cap + 255) / 256);
+    if (f64(e))
+      e_extract<double><<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->cap, slot, e->blk_slot,
+                                             e->blk_local, e->bank[o], e->misc + 1);
+    else
+      e_extract<float><<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->cap, slot, e->blk_slot,
+                                            e->blk_local, e->bank[o], e->misc + 1);
+    h = hipGetLastError();
+  }
+  uint32_t cnt = 0;
+  if (h == hipSuccess) h = hipMemcpyAsync(&cnt, e->misc + 1, 4, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  if (h != hipSuccess) return ens_hip(e, h, "get_particles");
+  const bool want = cell || off || w || id;
+  if (want && *n < cnt) {
+    *n = cnt;
+    return ens_error(e, ITOKMC_EINVAL, "output arrays hold fewer than %u particles", cnt);
+  }
+  *n = cnt;
+  if (!want || cnt == 0) return ITOKMC_OK;
+  const Bank& B = e->bank[o];
+  if (cell) h = hipMemcpyAsync(cell, B.cell, (size_t)cnt * 4, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess && w) h = hipMemcpyAsync(w, B.w, (size_t)cnt * 4, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess && id) h = hipMemcpyAsync(id, B.id, (size_t)cnt * 8, hipMemcpyDeviceToHost, e->s);
+  std::vector<char> tmp;
+  if (h == hipSuccess && off) {
+    const size_t T = f64(e) ? 8 : 4;
+    tmp.resize((size_t)cnt * T * 3);
+    void* src[3] = {B.ox, B.oy, B.oz};
+    for (int a = 0; a < 3 && h == hipSuccess; ++a)
+      h = hipMemcpyAsync(tmp.data() + (size_t)a * cnt * T, src[a], (size_t)cnt * T, hipMemcpyDeviceToHost, e->s);
+  }
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  if (h != hipSuccess) return ens_hip(e, h, "get_particles");
+  if (off) {
+    for (uint32_t i = 0; i < cnt; ++i)
+      for (int a = 0; a < 3; ++a)
+        off[3 * (size_t)i + a] = f64(e) ? ((const double*)tmp.data())[(size_t)a * cnt + i]
+                                        : (double)((const float*)tmp.data())[(size_t)a * cnt + i];
+  }
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_get_counts(itokmc_ens* e, int32_t slot, int which, uint32_t* host) {
+  int rc = check_slot(e, slot);
+  if (rc) return rc;
+  if (!host) return ITOKMC_EINVAL;
+  const SlotHost& H = e->slots[slot];
+  const uint64_t ncell = (uint64_t)H.d.nx * H.d.ny * H.d.nz;
+  if (which == ITOKMC_Q_NGP_WEIGHT) {
+    uint64_t n = 0;
+    rc = itokmc_ensemble_get_particles(e, slot, &n, nullptr, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    std::vector<uint32_t> cell(n), w(n);
+    rc = itokmc_ensemble_get_particles(e, slot, &n, cell.data(), nullptr, w.data(), nullptr);
+    if (rc) return rc;
+    memset(host, 0, ncell * 4);
+    for (uint64_t i = 0; i < n; ++i) host[cell[i]] += w[i];
+    return ITOKMC_OK;
+  }
+  const uint32_t* src;
+  if (which == ITOKMC_Q_NPLUS) src = e->nplus;
+  else if (which == ITOKMC_Q_NMINUS) src = e->nminus;
+  else return ens_error(e, ITOKMC_EINVAL, "unsupported count selector %d", which);
+  hipError_t h = hipSuccess;
+  for (size_t lb = 0; lb < H.blocks.size() && h == hipSuccess; ++lb) {
+    const uint64_t c0 = (uint64_t)lb * kBlkCells;
+    const uint64_t len = std::min<uint64_t>(kBlkCells, ncell - c0);
+    h = hipMemcpyAsync(host + c0, src + ((size_t)H.blocks[lb] << kBlkShift), len * 4,
+                       hipMemcpyDeviceToHost, e->s);
+  }
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  return ens_hip(e, h, "get_counts");
+}
+
+int itokmc_ensemble_release(itokmc_ens* e, int32_t slot) {
+  int rc = check_slot(e, slot);
+  if (rc) return rc;
+  SlotHost& H = e->slots[slot];
+  const hipError_t h = for_lists(H.blocks, [&](const BlkList& L) {
+    e_clear_blocks<<<1, 256, 0, e->s>>>(L, L.first_local == 0 ? slot : -1, e->sc, e->stat2, e->blk_slot);
+    return hipGetLastError();
+  });
+  if (h != hipSuccess) return ens_hip(e, h, "release");
+  for (uint32_t b : H.blocks) {
+    e->used_blocks.erase(b);
+    e->pending_blocks.push_back(b);
+  }
+  e->pending_map.push_back({H.map_off, (uint32_t)H.blocks.size()});
+  e->pending_quota += H.quota;
+  H = SlotHost();
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_info(itokmc_ens* e, itokmc_ens_info* out) {
+  if (!e || !out) return ITOKMC_EINVAL;
+  hipError_t h = hipMemcpyAsync(e->host_ctr, e->ctr, sizeof(Counters), hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipStreamSynchronize(e->s);
+  if (h != hipSuccess) return ens_hip(e, h, "info");
+  memset(out, 0, sizeof(*out));
+  for (uint32_t i = 0; i < e->ms; ++i) {
+    if (e->slots[i].used) out->slots_used += 1;
+  }
+  out->slots_free = (int32_t)e->ms - out->slots_used;
+  out->cells_free = (uint64_t)e->free_blocks.size() * kBlkCells;
+  out->particles_free = e->quota_free;
+  out->pool_particles = std::min<uint64_t>(e->host_ctr->n[e->cur], e->cap);
+  out->steps = e->steps;
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_set_tuning(itokmc_ens* e, const itokmc_ens_tuning* t) {
+  if (!e || !t) return ITOKMC_EINVAL;
+  if (t->push_block < 64 || t->push_block > 1024 || t->push_block % 64 ||
+      t->push_blocks_per_cu < 1 || t->push_blocks_per_cu > 64 ||
+      (t->kmc_block != 64 && t->kmc_block != 128 && t->kmc_block != 256) ||
+      t->couple_per_cu < 1 || t->couple_per_cu > 256)
+    return ens_error(e, ITOKMC_EINVAL, "tuning out of range");
+  e->tune = *t;
+  e->tune.pad0 = 0;
+  drop_graphs(e);
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_get_tuning(itokmc_ens* e, itokmc_ens_tuning* t) {
+  if (!e || !t) return ITOKMC_EINVAL;
+  *t = e->tune;
+  return ITOKMC_OK;
+}
+
+int itokmc_ensemble_autotune(itokmc_ens* e, uint32_t rounds, itokmc_ens_tuning* best,
+                             double* best_ms) {
+  if (!e || rounds < 1) return ITOKMC_EINVAL;
+  const itokmc_ens_tuning base = e->tune;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return ens_error(e, ITOKMC_EHIP, "autotune: event creation failed");
+  // coordinate search: particle-kernel shape, then KMC block, then coupling grid
+  itokmc_ens_tuning cur = base;
+  double cur_ms = 0.0;
+  int rc = ITOKMC_OK;
+  auto measure = [&](const std::vector<itokmc_ens_tuning>& cands, size_t* arg, double* ms) -> int {
+    std::vector<double> tot(cands.size(), 0.0);
+    for (uint32_t r = 0; r < rounds; ++r) {
+      for (size_t i = 0; i < cands.size(); ++i) {
+        int q = itokmc_ensemble_set_tuning(e, &cands[i]);
+        if (q) return q;
+        if (e->tune.use_graph && !capture_graphs(e)) return ens_error(e, ITOKMC_EHIP, "autotune: capture failed");
+        if (hipEventRecord(e0, e->s) != hipSuccess) return ens_error(e, ITOKMC_EHIP, "autotune: event");
+        q = itokmc_ensemble_step(e, 1);
+        if (q) return q;
+        if (hipEventRecord(e1, e->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+          return ens_error(e, ITOKMC_EHIP, "autotune: event");
+        float m = 0.f;
+        (void)hipEventElapsedTime(&m, e0, e1);
+        tot[i] += m;
+      }
+    }
+    *arg = (size_t)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+    *ms = tot[*arg] / rounds;
+    return ITOKMC_OK;
+  };
+  std::vector<itokmc_ens_tuning> c1;
+  for (int pb : {256, 512, 1024})
+    for (int pc : {2, 4, 8, 16}) {
+      itokmc_ens_tuning t = cur;
+      t.push_block = pb;
+      t.push_blocks_per_cu = pc;
+      c1.push_back(t);
+    }
+  size_t arg = 0;
+  rc = measure(c1, &arg, &cur_ms);
+  if (!rc) {
+    cur = c1[arg];
+    std::vector<itokmc_ens_tuning> c2;
+    for (int kb : {64, 128, 256}) { itokmc_ens_tuning t = cur; t.kmc_block = kb; c2.push_back(t); }
+    rc = measure(c2, &arg, &cur_ms);
+    if (!rc) cur = c2[arg];
+  }
+  if (!rc) {
+    std::vector<itokmc_ens_tuning> c3;
+    for (int cc : {16, 64, 256}) { itokmc_ens_tuning t = cur; t.couple_per_cu = cc; c3.push_back(t); }
+    rc = measure(c3, &arg, &cur_ms);
+    if (!rc) cur = c3[arg];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    (void)itokmc_ensemble_set_tuning(e, &base);
+    return rc;
+  }
+  rc = itokmc_ensemble_set_tuning(e, &cur);
+  if (best) *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return rc;
+}
+
+void itokmc_ensemble_destroy(itokmc_ens* e) {
+  if (!e) return;
+  (void)hipStreamSynchronize(e->s);
+  drop_graphs(e);
+  if (e->host_stat) (void)hipHostFree(e->host_stat);
+  if (e->host_ctr) (void)hipHostFree(e->host_ctr);
+  if (e->host_red) (void)hipHostFree(e->host_red);
+  delete e;
+}
+
+const char* itokmc_ensemble_last_error(const itokmc_ens* e) {
+  return e ? e->err.c_str() : "null ensemble";
+}
+
+}  // extern "C"

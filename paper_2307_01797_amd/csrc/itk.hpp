@@ -119,6 +119,11 @@ int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);
 int check_hip(itokmc_ctx* ctx, hipError_t e, const char* what);
 
 StepConst make_const(const itokmc_ctx* ctx, double dt);
+// Uniform-field drift and diffusion per step (grid units) and rates (1/s).
+void uniform_consts(const itokmc_grid_desc& d, const itokmc_coeffs& c, double dt,
+                    double drift[3], double* diff, double k[3]);
+bool valid_desc(const itokmc_grid_desc* d);
+int check_coeffs(const itokmc_coeffs* c, std::string* why);
 // particles.hip
 hipError_t launch_seed_gaussian(itokmc_ctx* ctx, const itokmc_seed_desc* sd);
 hipError_t launch_seed_neutral(itokmc_ctx* ctx, const itokmc_seed_desc* sd);
@@ -127,6 +132,12 @@ hipError_t launch_count(itokmc_ctx* ctx);  // bin the current bank without movin
 hipError_t launch_photons(itokmc_ctx* ctx, const StepConst& k);
 hipError_t launch_scan(itokmc_ctx* ctx);
 hipError_t launch_scatter(itokmc_ctx* ctx);
+// pointer forms used by the ensemble (ncell_dev: device-side cell count to scan)
+hipError_t launch_scan_raw(const unsigned long long* cellacc, uint32_t max_cells,
+                           const uint32_t* ncell_dev, uint32_t* blocksums, uint32_t* start,
+                           uint32_t* occ, Counters* ctr, int dest, hipStream_t s);
+hipError_t launch_scatter_raw(Bank a, Bank b, Counters* ctr, int which, const uint32_t* start,
+                              uint32_t cap, int fp64, int grid, hipStream_t s);
 hipError_t launch_ngp(itokmc_ctx* ctx, uint32_t* out);
 hipError_t launch_reduce_particles(itokmc_ctx* ctx, unsigned long long* out2);
 hipError_t launch_reduce_cells(itokmc_ctx* ctx, unsigned long long* out2);

@@ -5,6 +5,7 @@
 #include "device.hpp"
 #include "itk.hpp"
 #include "poisson.hpp"
+#include "push_device.hpp"
 
 namespace itk {
 
@@ -34,38 +35,20 @@ __device__ __forceinline__ void put(const Bank& b, uint32_t q, uint32_t cell, T 
   b.id[q] = id;
 }
 
-// Offset in [0,1) of the working precision.
-template <typename T> __device__ __forceinline__ T to_off(double o);
-template <> __device__ __forceinline__ double to_off<double>(double o) { return o; }
-template <> __device__ __forceinline__ float to_off<float>(double o) {
-  float f = (float)o;
-  return f < 1.0f ? f : 0x1.fffffep-1f;
-}
-
 // ---- seeding ---------------------------------------------------------------------
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_seed_gaussian(Bank b, Counters* ctr, int which,
                                                          StepConst k, uint64_t n0, double cx,
                                                          double cy, double cz, double sigma) {
-  const double two_pi = 6.283185307179586476925286766559;
+  const int lim[3] = {k.nx, k.ny, k.nz};
+  const double c[3] = {cx, cy, cz};
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n0;
        base += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t i = base + threadIdx.x;
     bool keep = false;
     double xi[3];
-    if (i < n0) {
-      const uint4 r = philox_block((uint32_t)i, (uint32_t)(i >> 32), 0, TAG_SEED, 0, k.key);
-      const double r0 = sqrt(-2.0 * log(u_oc(r.x)));
-      const double t0 = two_pi * u_co(r.y);
-      const double r1 = sqrt(-2.0 * log(u_oc(r.z)));
-      const double t1 = two_pi * u_co(r.w);
-      const double nrm[3] = {r0 * cos(t0), r0 * sin(t0), r1 * cos(t1)};
-      const double c[3] = {cx, cy, cz};
-      for (int a = 0; a < 3; ++a) xi[a] = (c[a] + sigma * nrm[a]) / k.dx;
-      keep = xi[0] >= 0.0 && xi[0] < k.nx && xi[1] >= 0.0 && xi[1] < k.ny && xi[2] >= 0.0 &&
-             xi[2] < k.nz;
-    }
+    if (i < n0) keep = gaussian_seed_point(i, k.key, k.dx, lim, c, sigma, xi);
     const uint32_t q = wave_append(&ctr->n[which], keep ? 1u : 0u);
     if (keep) {
       if (q >= k.cap) {
@@ -120,35 +103,6 @@ __global__ void __launch_bounds__(kBlock) k_seed_neutral(Bank b, Counters* ctr, 
 
 // ---- push (uniform prescribed field) with fused NGP binning -------------------------
 
-template <typename T> struct Normals;
-template <> struct Normals<double> {
-  // Box-Muller on one Philox block; the fourth word's partner is unused.
-  __device__ static void get(uint4 r, double n[3]) {
-    const double two_pi = 6.283185307179586476925286766559;
-    const double r0 = sqrt(-2.0 * log(u_oc(r.x)));
-    const double t0 = two_pi * u_co(r.y);
-    const double r1 = sqrt(-2.0 * log(u_oc(r.z)));
-    const double t1 = two_pi * u_co(r.w);
-    n[0] = r0 * cos(t0);
-    n[1] = r0 * sin(t0);
-    n[2] = r1 * cos(t1);
-  }
-};
-template <> struct Normals<float> {
-  // Single precision: hardware log2 and sin/cos of revolutions (v_log_f32, v_sin_f32,
-  // v_cos_f32); -2 ln u = -2 ln2 log2 u.
-  __device__ static void get(uint4 r, float n[3]) {
-    const float m2ln2 = -1.3862943611198906f;
-    const float r0 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.x)));
-    const float r1 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.z)));
-    const float a0 = (float)(r.y >> 8) * 0x1p-24f;
-    const float a1 = (float)(r.w >> 8) * 0x1p-24f;
-    n[0] = r0 * __builtin_amdgcn_cosf(a0);
-    n[1] = r0 * __builtin_amdgcn_sinf(a0);
-    n[2] = r1 * __builtin_amdgcn_cosf(a1);
-  }
-};
-
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, int which,
                                                         unsigned long long* cellacc,
@@ -167,23 +121,10 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
       const uint32_t cell = a.cell[i];
       const uint64_t id = a.id[i];
       T o[3] = {as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i]};
-      const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), k.step, TAG_PUSH, 0, k.key);
-      T nr[3];
-      Normals<T>::get(r, nr);
       int ci[3] = {(int)(cell % (uint32_t)k.nx), (int)((cell / (uint32_t)k.nx) % (uint32_t)k.ny),
                    (int)(cell / ((uint32_t)k.nx * (uint32_t)k.ny))};
       const int lim[3] = {k.nx, k.ny, k.nz};
-      bool inside = true;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        T x = o[ax] + (drift[ax] + diff * nr[ax]);
-        T f = floor(x);
-        x -= f;
-        if (x >= (T)1) { x -= (T)1; f += (T)1; }
-        o[ax] = x;
-        ci[ax] += (int)f;
-        inside = inside && ci[ax] >= 0 && ci[ax] < lim[ax];
-      }
+      const bool inside = push_uniform<T>(id, k.step, k.key, drift, diff, lim, ci, o);
       if (inside) {
         key = (uint32_t)ci[0] + (uint32_t)k.nx * ((uint32_t)ci[1] + (uint32_t)k.ny * (uint32_t)ci[2]);
         a.cell[i] = key;
@@ -311,32 +252,46 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return r;
 }
 
+// ncell_dev (may be null) holds a device-side cell count that overrides ncell: the
+// ensemble scans only the cells its slots occupy, with a grid sized for its pool.
+__device__ __forceinline__ uint32_t scan_cells(uint32_t ncell, const uint32_t* ncell_dev) {
+  return ncell_dev ? *ncell_dev : ncell;
+}
+
 __global__ void __launch_bounds__(kBlock) k_scan_reduce(const unsigned long long* cellacc,
-                                                       uint32_t ncell, uint32_t* blocksums) {
+                                                       uint32_t ncell_arg,
+                                                       const uint32_t* ncell_dev,
+                                                       uint32_t* blocksums) {
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
-  const uint32_t c0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
-  uint32_t cnt = 0, occ = 0;
+  const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
+  const uint32_t nb = (ncell + kScanTile - 1) / kScanTile;
+  for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    const uint32_t c0 = t * kScanTile + threadIdx.x * kScanPer;
+    uint32_t cnt = 0, occ = 0;
 #pragma unroll
-  for (int j = 0; j < kScanPer; ++j) {
-    const uint32_t c = c0 + j;
-    if (c < ncell) {
-      const uint32_t n = (uint32_t)(cellacc[c] >> 32);
-      cnt += n;
-      occ += n ? 1u : 0u;
+    for (int j = 0; j < kScanPer; ++j) {
+      const uint32_t c = c0 + j;
+      if (c < ncell) {
+        const uint32_t n = (uint32_t)(cellacc[c] >> 32);
+        cnt += n;
+        occ += n ? 1u : 0u;
+      }
     }
-  }
-  uint32_t t0, t1;
-  block_exclusive_scan(cnt, sh[0], &t0);
-  block_exclusive_scan(occ, sh[1], &t1);
-  if (threadIdx.x == 0) {
-    blocksums[2 * blockIdx.x] = t0;
-    blocksums[2 * blockIdx.x + 1] = t1;
+    uint32_t t0, t1;
+    block_exclusive_scan(cnt, sh[0], &t0);
+    block_exclusive_scan(occ, sh[1], &t1);
+    if (threadIdx.x == 0) {
+      blocksums[2 * t] = t0;
+      blocksums[2 * t + 1] = t1;
+    }
   }
 }
 
-__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* blocksums, uint32_t nb) {
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* blocksums, uint32_t ncell_arg,
+                                                  const uint32_t* ncell_dev) {
   // exclusive scan of nb (count, occupied) pairs by one block; blocksums[2 nb ..] = totals
   __shared__ uint32_t sh[2][1024 / 64 + 1];
+  const uint32_t nb = (scan_cells(ncell_arg, ncell_dev) + kScanTile - 1) / kScanTile;
   const int per = (int)((nb + 1023) / 1024);
   const uint32_t b0 = threadIdx.x * per;
   uint32_t s0 = 0, s1 = 0;
@@ -373,30 +328,34 @@ __global__ void __launch_bounds__(1024) k_scan_top(uint32_t* blocksums, uint32_t
 }
 
 __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* cellacc,
-                                                     uint32_t ncell, const uint32_t* blocksums,
-                                                     uint32_t nb, uint32_t* start, uint32_t* occ,
-                                                     Counters* ctr, int dest) {
+                                                     uint32_t ncell_arg, const uint32_t* ncell_dev,
+                                                     const uint32_t* blocksums, uint32_t* start,
+                                                     uint32_t* occ, Counters* ctr, int dest) {
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
-  const uint32_t c0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
-  uint32_t n[kScanPer];
-  uint32_t cnt = 0, oc = 0;
+  const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
+  const uint32_t nb = (ncell + kScanTile - 1) / kScanTile;
+  for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    const uint32_t c0 = t * kScanTile + threadIdx.x * kScanPer;
+    uint32_t n[kScanPer];
+    uint32_t cnt = 0, oc = 0;
 #pragma unroll
-  for (int j = 0; j < kScanPer; ++j) {
-    const uint32_t c = c0 + j;
-    n[j] = c < ncell ? (uint32_t)(cellacc[c] >> 32) : 0u;
-    cnt += n[j];
-    oc += n[j] ? 1u : 0u;
-  }
-  uint32_t t0, t1;
-  uint32_t p0 = block_exclusive_scan(cnt, sh[0], &t0) + blocksums[2 * blockIdx.x];
-  uint32_t p1 = block_exclusive_scan(oc, sh[1], &t1) + blocksums[2 * blockIdx.x + 1];
+    for (int j = 0; j < kScanPer; ++j) {
+      const uint32_t c = c0 + j;
+      n[j] = c < ncell ? (uint32_t)(cellacc[c] >> 32) : 0u;
+      cnt += n[j];
+      oc += n[j] ? 1u : 0u;
+    }
+    uint32_t t0, t1;
+    uint32_t p0 = block_exclusive_scan(cnt, sh[0], &t0) + blocksums[2 * t];
+    uint32_t p1 = block_exclusive_scan(oc, sh[1], &t1) + blocksums[2 * t + 1];
 #pragma unroll
-  for (int j = 0; j < kScanPer; ++j) {
-    const uint32_t c = c0 + j;
-    if (c < ncell) {
-      start[c] = p0;
-      if (n[j]) occ[p1++] = c;
-      p0 += n[j];
+    for (int j = 0; j < kScanPer; ++j) {
+      const uint32_t c = c0 + j;
+      if (c < ncell) {
+        start[c] = p0;
+        if (n[j]) occ[p1++] = c;
+        p0 += n[j];
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -555,12 +514,29 @@ hipError_t launch_photons(itokmc_ctx* ctx, const StepConst& k) {
   return hipGetLastError();
 }
 
+hipError_t launch_scan_raw(const unsigned long long* cellacc, uint32_t max_cells,
+                           const uint32_t* ncell_dev, uint32_t* blocksums, uint32_t* start,
+                           uint32_t* occ, Counters* ctr, int dest, hipStream_t s) {
+  uint32_t nb = (max_cells + kScanTile - 1) / kScanTile;
+  if (nb < 1) nb = 1;
+  if (ncell_dev && nb > 4096) nb = 4096;  // tiles beyond the grid are looped over
+  k_scan_reduce<<<nb, kBlock, 0, s>>>(cellacc, max_cells, ncell_dev, blocksums);
+  k_scan_top<<<1, 1024, 0, s>>>(blocksums, max_cells, ncell_dev);
+  k_scan_down<<<nb, kBlock, 0, s>>>(cellacc, max_cells, ncell_dev, blocksums, start, occ, ctr, dest);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(itokmc_ctx* ctx) {
-  const uint32_t nb = (ctx->ncell + kScanTile - 1) / kScanTile;
-  k_scan_reduce<<<nb, kBlock, 0, ctx->s>>>(ctx->cellacc, ctx->ncell, ctx->blocksums);
-  k_scan_top<<<1, 1024, 0, ctx->s>>>(ctx->blocksums, nb);
-  k_scan_down<<<nb, kBlock, 0, ctx->s>>>(ctx->cellacc, ctx->ncell, ctx->blocksums, nb, ctx->start,
-                                        ctx->occ, ctx->ctr, 1 - ctx->cur);
+  return launch_scan_raw(ctx->cellacc, ctx->ncell, nullptr, ctx->blocksums, ctx->start, ctx->occ,
+                         ctx->ctr, 1 - ctx->cur, ctx->s);
+}
+
+hipError_t launch_scatter_raw(Bank a, Bank b, Counters* ctr, int which, const uint32_t* start,
+                              uint32_t cap, int fp64, int grid, hipStream_t s) {
+  if (fp64)
+    k_scatter<double><<<grid, kBlock, 0, s>>>(a, b, ctr, which, start, cap);
+  else
+    k_scatter<float><<<grid, kBlock, 0, s>>>(a, b, ctr, which, start, cap);
   return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libitokmc.so")
 
-OK, EINVAL, ENOMEM, ECAPACITY, ENOCONV, EHIP = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, ECAPACITY, ENOCONV, EHIP, EAGAIN = 0, -1, -2, -3, -4, -5, -6
+SLOT_FREE, SLOT_ACTIVE, SLOT_DONE, SLOT_CAPPED = 0, 1, 2, 3
 FP32, FP64 = 0, 1
 FIELD_UNIFORM, FIELD_POISSON = 0, 1
 KMC_HYBRID, KMC_PURE_TAU = 0, 1
@@ -26,7 +27,13 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
            "itokmc_get_field", "itokmc_set_field", "itokmc_destroy", "itokmc_last_error",
            "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_set_profiling",
-           "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning"]
+           "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning",
+           "itokmc_ensemble_arena_bytes", "itokmc_ensemble_create", "itokmc_ensemble_admit",
+           "itokmc_ensemble_step", "itokmc_ensemble_poll", "itokmc_ensemble_result",
+           "itokmc_ensemble_get_particles", "itokmc_ensemble_get_counts",
+           "itokmc_ensemble_release", "itokmc_ensemble_info", "itokmc_ensemble_set_tuning",
+           "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
+           "itokmc_ensemble_last_error"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
           "field_push", "count"]
 
@@ -85,6 +92,32 @@ class Diag(ctypes.Structure):
         return d
 
 
+class EnsDesc(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_cells", ctypes.c_uint64), ("max_particles", ctypes.c_uint64)]
+
+
+class RunDesc(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("nsteps", ctypes.c_uint32), ("pad0", ctypes.c_uint32),
+                ("stop_particles", ctypes.c_uint64), ("tag", ctypes.c_uint64)]
+
+
+class SlotEvent(ctypes.Structure):
+    _fields_ = [("slot", ctypes.c_int32), ("state", ctypes.c_int32), ("tag", ctypes.c_uint64),
+                ("steps", ctypes.c_uint32), ("pad0", ctypes.c_uint32)]
+
+
+class EnsInfo(ctypes.Structure):
+    _fields_ = [("slots_used", ctypes.c_int32), ("slots_free", ctypes.c_int32),
+                ("cells_free", ctypes.c_uint64), ("particles_free", ctypes.c_uint64),
+                ("pool_particles", ctypes.c_uint64), ("steps", ctypes.c_uint64)]
+
+
+class EnsTuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("push_block", "push_blocks_per_cu", "kmc_block",
+                                              "couple_per_cu", "use_graph", "pad0")]
+
+
 class ItokmcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"itokmc error {code}: {msg}")
@@ -131,6 +164,29 @@ def lib():
         L.itokmc_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.itokmc_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.itokmc_phase_times.argtypes = [P, P, P, I32, I32]
+        L.itokmc_ensemble_arena_bytes.restype = ctypes.c_size_t
+        L.itokmc_ensemble_arena_bytes.argtypes = [ctypes.POINTER(EnsDesc)]
+        L.itokmc_ensemble_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(EnsDesc), P,
+                                             ctypes.c_size_t, P]
+        L.itokmc_ensemble_admit.argtypes = [P, ctypes.POINTER(GridDesc), ctypes.POINTER(Coeffs),
+                                            ctypes.POINTER(SeedDesc), ctypes.POINTER(RunDesc),
+                                            ctypes.POINTER(ctypes.c_int32)]
+        L.itokmc_ensemble_step.argtypes = [P, U32]
+        L.itokmc_ensemble_poll.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.itokmc_ensemble_result.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Diag)]
+        L.itokmc_ensemble_get_particles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(U64), P, P,
+                                                    P, P]
+        L.itokmc_ensemble_get_counts.argtypes = [P, ctypes.c_int32, I32, P]
+        L.itokmc_ensemble_release.argtypes = [P, ctypes.c_int32]
+        L.itokmc_ensemble_info.argtypes = [P, ctypes.POINTER(EnsInfo)]
+        L.itokmc_ensemble_set_tuning.argtypes = [P, ctypes.POINTER(EnsTuning)]
+        L.itokmc_ensemble_get_tuning.argtypes = [P, ctypes.POINTER(EnsTuning)]
+        L.itokmc_ensemble_autotune.argtypes = [P, U32, ctypes.POINTER(EnsTuning),
+                                               ctypes.POINTER(ctypes.c_double)]
+        L.itokmc_ensemble_destroy.argtypes = [P]
+        L.itokmc_ensemble_destroy.restype = None
+        L.itokmc_ensemble_last_error.argtypes = [P]
+        L.itokmc_ensemble_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -213,17 +269,7 @@ class Sim:
 
     # -- setup ---------------------------------------------------------------------
     def seed(self):
-        cfg = self.cfg
-        sd = SeedDesc()
-        sd.centre = (ctypes.c_double * 3)(*cfg["seed_centre"])
-        sd.sigma = cfg["seed_sigma"]
-        if cfg["seed_kind"] == "gaussian":
-            sd.kind = SEED_GAUSSIAN
-            sd.n0 = cfg["seed_n0"]
-        else:
-            sd.kind = SEED_NEUTRAL
-            sd.n_peak = cfg["seed_peak"]
-        return self._check(lib().itokmc_seed_particles(self.h, ctypes.byref(sd)))
+        return self._check(lib().itokmc_seed_particles(self.h, ctypes.byref(make_seed(self.cfg))))
 
     # -- stepping ------------------------------------------------------------------
     def step(self, n=1, dt=None):
@@ -350,6 +396,159 @@ class Sim:
                                            ctypes.c_void_p(df.data_ptr())))
         self.stream.synchronize()
         return dX.cpu().numpy(), df.cpu().numpy()
+
+
+def make_seed(cfg):
+    sd = SeedDesc()
+    sd.centre = (ctypes.c_double * 3)(*cfg["seed_centre"])
+    sd.sigma = cfg["seed_sigma"]
+    if cfg["seed_kind"] == "gaussian":
+        sd.kind = SEED_GAUSSIAN
+        sd.n0 = cfg["seed_n0"]
+    else:
+        sd.kind = SEED_NEUTRAL
+        sd.n_peak = cfg["seed_peak"]
+    return sd
+
+
+def make_run(cfg, tag=0):
+    r = RunDesc()
+    r.dt = cfg["dt"]
+    r.nsteps = int(cfg["steps"])
+    r.stop_particles = int(cfg.get("stop_particles", 0))
+    r.tag = int(tag)
+    return r
+
+
+class Ensemble:
+    """Many independent uniform-field realizations advanced together on one GPU
+    (the itokmc_ensemble_* entry points)."""
+
+    def __init__(self, max_slots, max_cells, max_particles, precision="fp32", device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = lib()
+        self._desc = EnsDesc(int(max_slots), FP64 if precision == "fp64" else FP32,
+                             int(max_cells), int(max_particles))
+        nbytes = L.itokmc_ensemble_arena_bytes(ctypes.byref(self._desc))
+        if nbytes == 0:
+            raise ItokmcError(EINVAL, "invalid ensemble descriptor")
+        self.arena_bytes = nbytes
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        rc = L.itokmc_ensemble_create(ctypes.byref(h), ctypes.byref(self._desc),
+                                      ctypes.c_void_p(self.arena.data_ptr()), nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != OK:
+            raise ItokmcError(rc, "ensemble_create failed")
+        self.h = h
+        self.ncell = {}
+        self.max_slots = int(max_slots)
+        self._ev = (SlotEvent * self.max_slots)()
+
+    @staticmethod
+    def arena_bytes_for(max_slots, max_cells, max_particles, precision="fp32"):
+        d = EnsDesc(int(max_slots), FP64 if precision == "fp64" else FP32, int(max_cells),
+                    int(max_particles))
+        return lib().itokmc_ensemble_arena_bytes(ctypes.byref(d))
+
+    def _check(self, rc):
+        if rc != OK:
+            raise ItokmcError(rc, lib().itokmc_ensemble_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().itokmc_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, cfg, tag=0):
+        """Admit one realization; returns its slot, or None if the pools are full."""
+        slot = ctypes.c_int32(-1)
+        rc = lib().itokmc_ensemble_admit(self.h, ctypes.byref(make_desc(cfg)),
+                                         ctypes.byref(make_coeffs(cfg)),
+                                         ctypes.byref(make_seed(cfg)),
+                                         ctypes.byref(make_run(cfg, tag)), ctypes.byref(slot))
+        if rc == EAGAIN:
+            return None
+        self._check(rc)
+        self.ncell[slot.value] = int(np.prod(cfg["grid"]))
+        return slot.value
+
+    def step(self, n=1):
+        return self._check(lib().itokmc_ensemble_step(self.h, n))
+
+    def poll(self):
+        """[(slot, state, tag, steps)] of realizations finished since the last poll."""
+        out = []
+        while True:
+            n = ctypes.c_int32()
+            self._check(lib().itokmc_ensemble_poll(self.h, self._ev, self.max_slots,
+                                                   ctypes.byref(n)))
+            out += [(e.slot, e.state, e.tag, e.steps) for e in self._ev[:n.value]]
+            if n.value < self.max_slots:
+                return out
+
+    def result(self, slot):
+        d = Diag()
+        self._check(lib().itokmc_ensemble_result(self.h, slot, ctypes.byref(d)))
+        return d.as_dict()
+
+    def particles(self, slot):
+        n = ctypes.c_uint64()
+        self._check(lib().itokmc_ensemble_get_particles(self.h, slot, ctypes.byref(n), None, None,
+                                                        None, None))
+        N = n.value
+        cell = np.zeros(N, dtype=np.uint32)
+        off = np.zeros((N, 3), dtype=np.float64)
+        w = np.zeros(N, dtype=np.uint32)
+        ids = np.zeros(N, dtype=np.uint64)
+        self._check(lib().itokmc_ensemble_get_particles(self.h, slot, ctypes.byref(n), _np(cell),
+                                                        _np(off), _np(w), _np(ids)))
+        return cell, off, w, ids
+
+    def counts(self, slot, which):
+        q = {"ngp": Q_NGP_WEIGHT, "plus": Q_NPLUS, "minus": Q_NMINUS}[which]
+        v = np.zeros(self.ncell[slot], dtype=np.uint32)
+        self._check(lib().itokmc_ensemble_get_counts(self.h, slot, q, _np(v)))
+        return v
+
+    def release(self, slot):
+        self.ncell.pop(slot, None)
+        return self._check(lib().itokmc_ensemble_release(self.h, slot))
+
+    def info(self):
+        i = EnsInfo()
+        self._check(lib().itokmc_ensemble_info(self.h, ctypes.byref(i)))
+        return {n: getattr(i, n) for n, _ in EnsInfo._fields_}
+
+    def tuning(self):
+        t = EnsTuning()
+        self._check(lib().itokmc_ensemble_get_tuning(self.h, ctypes.byref(t)))
+        return {n: getattr(t, n) for n, _ in EnsTuning._fields_ if n != "pad0"}
+
+    def set_tuning(self, **kw):
+        t = EnsTuning()
+        self._check(lib().itokmc_ensemble_get_tuning(self.h, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        return self._check(lib().itokmc_ensemble_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, rounds=3):
+        t = EnsTuning()
+        ms = ctypes.c_double()
+        self._check(lib().itokmc_ensemble_autotune(self.h, rounds, ctypes.byref(t),
+                                                   ctypes.byref(ms)))
+        return {n: getattr(t, n) for n, _ in EnsTuning._fields_ if n != "pad0"}, ms.value
 
 
 def philox_fill(c0, c1, c2, c3, k0, k1, n, device="cuda:0"):

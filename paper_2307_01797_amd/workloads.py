@@ -72,7 +72,9 @@ def preset(name, **overrides):
 def ensemble_realizations(n=256, seed=1):
     """Batched-avalanche realizations: grid edge uniform in {32, 48, 64, 96} (dx = 5 um),
     initial electrons log-uniform in [1e3, 1e5], uniform field log-uniform in
-    [3, 12] MV/m, 500 steps of 1 ps or until 1e6 particles, FP32 state."""
+    [3, 12] MV/m, 500 steps of 1 ps or until 1e6 particles, FP32 state.  A realization
+    stops after the first step that began with at least stop_particles live particles;
+    its particle quota (max_particles) leaves room for that step's growth."""
     rng = np.random.default_rng(seed)
     out = []
     for r in range(n):
@@ -83,7 +85,8 @@ def ensemble_realizations(n=256, seed=1):
         out.append(dict(
             name=f"ens_{r}", grid=(edge, edge, edge), dx=5e-6, field="uniform", E=(0.0, 0.0, E),
             coeffs=dict(AIR), kmc="hybrid", n_ppc=0, n_new=64, seed=seed, realization=r,
-            precision="fp32", dt=1e-12, steps=500, max_particles=1_000_000,
+            precision="fp32", dt=1e-12, steps=500, stop_particles=1_000_000,
+            max_particles=1_250_000,
             seed_kind="gaussian", seed_n0=n0, seed_centre=(L / 2, L / 2, L / 2),
             seed_sigma=0.156 * L))
     return out

@@ -52,3 +52,22 @@ def test_arena_size_and_descriptor_validation():
     # init rejects a null arena without touching the device
     h = ctypes.c_void_p()
     assert L.itokmc_init_grid(ctypes.byref(h), ctypes.byref(d), None, n, None) == itokmc.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_ensemble_descriptor_validation():
+    from paper_2307_01797_amd import itokmc
+    L = itokmc.lib()
+    ok = itokmc.EnsDesc(256, itokmc.FP32, 1 << 26, 100_000_000)
+    n = L.itokmc_ensemble_arena_bytes(ctypes.byref(ok))
+    # two banks of 32 bytes per particle plus 36 bytes per pool cell, at least
+    assert n >= 2 * 32 * 100_000_000 + 36 * (1 << 26)
+    for bad in (itokmc.EnsDesc(0, itokmc.FP32, 4096, 1000),
+                itokmc.EnsDesc(5000, itokmc.FP32, 4096, 1000),
+                itokmc.EnsDesc(4, 7, 4096, 1000),
+                itokmc.EnsDesc(4, itokmc.FP32, (1 << 31) + 1, 1000),
+                itokmc.EnsDesc(4, itokmc.FP32, 4096, 1 << 31)):
+        assert L.itokmc_ensemble_arena_bytes(ctypes.byref(bad)) == 0
+    h = ctypes.c_void_p()
+    assert L.itokmc_ensemble_create(ctypes.byref(h), ctypes.byref(ok), None, n, None) == itokmc.EINVAL
+    assert L.itokmc_ensemble_step(None, 1) == itokmc.EINVAL

@@ -1,0 +1,245 @@
+"""Batched ensemble (itokmc_ensemble_*) through the C ABI.
+
+Every realization's result must be bit-identical (particles: cells, FP32/FP64
+offsets, weights, ids; ion counts; reaction tallies; steps) whether it runs alone in
+an ensemble, in a mix with others admitted and released at different times, or as a
+plain single context with the same descriptor; in FP64 it must match the oracle on
+integers exactly and on positions to 1e-9 cells.
+"""
+import numpy as np
+import pytest
+
+from helpers import by_id, gpu_xi, xi_to_cell_off
+from paper_2307_01797_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def itk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2307_01797_amd import itokmc
+    itokmc.lib()
+    return itokmc
+
+
+def _small_realizations(n, steps, seed=1, n0_max=4000, precision="fp32"):
+    """Ensemble-type realizations shrunk to test size: edges 32/48, fewer electrons."""
+    out = []
+    for cfg in workloads.ensemble_realizations(n, seed=seed):
+        edge = 32 if cfg["grid"][0] <= 48 else 48
+        L = edge * cfg["dx"]
+        cfg.update(grid=(edge, edge, edge), seed_centre=(L / 2, L / 2, L / 2),
+                   seed_sigma=0.156 * L, seed_n0=min(cfg["seed_n0"], n0_max), steps=steps,
+                   stop_particles=0, max_particles=300_000, precision=precision)
+        out.append(cfg)
+    return out
+
+
+def _state(get_particles, counts, grid):
+    cell, off, w, ids = get_particles()
+    ids, cell, off, w = by_id(ids, cell, off, w)
+    return dict(ids=ids, cell=cell, off=off, w=w, plus=counts("plus"), minus=counts("minus"))
+
+
+def _assert_same(a, b):
+    assert len(a["ids"]) == len(b["ids"])
+    for k in ("ids", "cell", "w", "plus", "minus"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["off"], b["off"])  # bit-identical offsets
+
+
+TALLIES = ("n_particles", "weight", "n_plus", "n_minus", "outflow_weight", "fires", "created",
+           "removed_weight", "particle_steps", "step")
+
+
+def _run_plain(itk, cfg):
+    """The plain form: one context, same stop rule (checked before each step)."""
+    g = itk.Sim(cfg, max_particles=cfg["max_particles"])
+    g.seed()
+    stop = cfg.get("stop_particles", 0)
+    for _ in range(cfg["steps"]):
+        live = g.diagnostics()["n_particles"]
+        g.step(1)
+        if stop and live >= stop:
+            break
+    return g
+
+
+def _plain_state(g):
+    return _state(g.particles, g.counts, g.cfg["grid"])
+
+
+def _ens_state(ens, slot, grid):
+    return _state(lambda: ens.particles(slot), lambda w: ens.counts(slot, w), grid)
+
+
+def _new_ensemble(itk, slots=16, cells=1 << 22, particles=4_000_000, precision="fp32"):
+    return itk.Ensemble(slots, cells, particles, precision=precision)
+
+
+def _drain(ens, max_steps=10_000):
+    done = {}
+    for _ in range(max_steps):
+        for slot, state, tag, steps in ens.poll():
+            done[slot] = (state, tag, steps)
+        if len(done) == len(ens.ncell):
+            return done
+        ens.step(1)
+    raise AssertionError("ensemble did not finish")
+
+
+def test_ensemble_matches_plain_contexts(itk):
+    cfgs = _small_realizations(6, steps=40)
+    ens = _new_ensemble(itk)
+    slots = [ens.admit(c, tag=100 + i) for i, c in enumerate(cfgs)]
+    done = _drain(ens)
+    for i, (cfg, s) in enumerate(zip(cfgs, slots)):
+        state, tag, steps = done[s]
+        assert state == itk.SLOT_DONE and tag == 100 + i and steps == 40
+        g = _run_plain(itk, cfg)
+        _assert_same(_ens_state(ens, s, cfg["grid"]), _plain_state(g))
+        rg, re_ = g.diagnostics(), ens.result(s)
+        for k in TALLIES:
+            assert re_[k] == rg[k], (k, re_[k], rg[k])
+        assert re_["weight"] > 0
+
+
+def test_alone_vs_in_mix_with_churn(itk):
+    """A realization alone equals the same realization admitted mid-run into a mix in
+    which other realizations finish, are released and their cells and quota reused."""
+    cfgs = _small_realizations(9, steps=30, seed=7)
+    target = cfgs[0]
+    alone = _new_ensemble(itk, slots=2)
+    s0 = alone.admit(target)
+    _drain(alone)
+    ref = _ens_state(alone, s0, target["grid"])
+    ref_t = alone.result(s0)
+
+    mix = _new_ensemble(itk, slots=4, cells=4 * 48**3 + 4096 * 8, particles=1_300_000)
+    live = {}
+    queue = list(range(1, 9))
+    # fill with others first, run a few steps, then admit the target
+    for _ in range(3):
+        i = queue.pop(0)
+        live[mix.admit(cfgs[i])] = i
+    mix.step(7)
+    st = None
+    while st is None:
+        st = mix.admit(target)
+        if st is None:  # pools full: finish someone first
+            mix.step(1)
+            for slot, *_ in mix.poll():
+                if live.get(slot) is not None:
+                    mix.release(slot)
+                    live.pop(slot)
+    live[st] = 0
+    got = None
+    for _ in range(500):
+        mix.step(1)
+        for slot, state, tag, steps in mix.poll():
+            if live[slot] == 0:
+                got = (_ens_state(mix, slot, target["grid"]), mix.result(slot))
+            mix.release(slot)
+            live.pop(slot)
+        while queue and len(live) < 4:
+            s = mix.admit(cfgs[queue[0]])
+            if s is None:
+                break
+            live[s] = queue.pop(0)
+        if got is not None and not live:
+            break
+    assert got is not None
+    _assert_same(got[0], ref)
+    for k in TALLIES:
+        assert got[1][k] == ref_t[k], k
+
+
+def test_stop_rule_matches_plain(itk):
+    """Realizations stop after the first step that began with at least stop_particles
+    live particles; the plain form applies the same rule."""
+    cfgs = _small_realizations(4, steps=200, seed=3)
+    for c in cfgs:
+        c["stop_particles"] = int(c["seed_n0"] * 1.5)
+        c["E"] = (0.0, 0.0, 1.2e7)
+    ens = _new_ensemble(itk)
+    slots = [ens.admit(c) for c in cfgs]
+    done = _drain(ens)
+    for cfg, s in zip(cfgs, slots):
+        g = _run_plain(itk, cfg)
+        assert done[s][2] == g.diagnostics()["step"] < 200
+        _assert_same(_ens_state(ens, s, cfg["grid"]), _plain_state(g))
+
+
+def test_ensemble_fp64_matches_oracle(itk, orc):
+    cfgs = _small_realizations(3, steps=25, seed=5, precision="fp64")
+    ens = _new_ensemble(itk, precision="fp64")
+    slots = [ens.admit(c) for c in cfgs]
+    _drain(ens)
+    for cfg, s in zip(cfgs, slots):
+        o = orc.Sim(cfg)
+        o.seed_gaussian(cfg["seed_n0"], cfg["seed_centre"], cfg["seed_sigma"])
+        o.step(cfg["dt"], cfg["steps"])
+        cell, off, w, ids = ens.particles(s)
+        ids, cell, off, w = by_id(ids, cell, off, w)
+        xi_o, w_o, id_o = o.particles()
+        id_o, xi_o, w_o = by_id(id_o, xi_o, w_o)
+        assert np.array_equal(ids, id_o)
+        assert np.array_equal(w.astype(np.uint64), w_o)
+        co, _ = xi_to_cell_off(xi_o, cfg["grid"])
+        assert np.array_equal(co, cell)
+        assert np.abs(gpu_xi(cell, off, cfg["grid"]) - xi_o).max(initial=0) < 1e-9
+        for which in ("plus", "minus"):
+            assert np.array_equal(ens.counts(s, which).astype(np.int64), o.counts(which))
+        r, od = ens.result(s), o.diagnostics()
+        assert r["fires"] == list(od["fires"])
+        assert r["n_plus"] == od["n_plus"] and r["n_minus"] == od["n_minus"]
+
+
+def test_admission_limits_and_release(itk):
+    cfgs = _small_realizations(3, steps=5, seed=11)
+    ens = _new_ensemble(itk, slots=2, cells=2 * 48**3, particles=700_000)
+    a = ens.admit(cfgs[0])
+    b = ens.admit(cfgs[1])
+    assert a is not None and b is not None
+    assert ens.admit(cfgs[2]) is None          # no free slot / quota
+    ens.release(a)
+    assert ens.admit(cfgs[2]) is None          # freed only after the next step
+    ens.step(1)
+    c = ens.admit(cfgs[2])
+    assert c is not None
+    info = ens.info()
+    assert info["slots_used"] == 2
+    _drain(ens)
+    g = _run_plain(itk, cfgs[2])
+    _assert_same(_ens_state(ens, c, cfgs[2]["grid"]), _plain_state(g))
+
+
+def test_capped_realization_stops(itk):
+    """A realization whose products would exceed its quota is flagged capped and
+    stops; the others are unaffected."""
+    cfgs = _small_realizations(2, steps=120, seed=13)
+    cfgs[0].update(E=(0.0, 0.0, 1.2e7), max_particles=int(cfgs[0]["seed_n0"] * 1.3) + 64)
+    ens = _new_ensemble(itk)
+    s0, s1 = ens.admit(cfgs[0]), ens.admit(cfgs[1])
+    done = _drain(ens)
+    assert done[s0][0] == itk.SLOT_CAPPED and done[s0][2] < 120
+    assert done[s1][0] == itk.SLOT_DONE
+    assert ens.result(s0)["overflow"] == 1
+    _assert_same(_ens_state(ens, s1, cfgs[1]["grid"]), _plain_state(_run_plain(itk, cfgs[1])))
+
+
+def test_autotune_keeps_results(itk):
+    cfgs = _small_realizations(5, steps=60, seed=17)
+    ens = _new_ensemble(itk)
+    slots = [ens.admit(c) for c in cfgs]
+    ens.step(2)
+    best, ms = ens.autotune(rounds=2)
+    assert ms > 0 and best["push_block"] in (256, 512, 1024)
+    ens.set_tuning(use_graph=0)
+    ens.step(3)
+    ens.set_tuning(use_graph=1)
+    _drain(ens)
+    for cfg, s in zip(cfgs, slots):
+        _assert_same(_ens_state(ens, s, cfg["grid"]), _plain_state(_run_plain(itk, cfg)))
