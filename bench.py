@@ -42,6 +42,14 @@ def parse():
     p.add_argument("--workload", default="streamer_256")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    # batched ensemble (--workload ensemble_256) and served (--workload served) forms
+    p.add_argument("--realizations", type=int, default=256)
+    p.add_argument("--rate", type=float, default=200.0)
+    p.add_argument("--duration", type=float, default=60.0)
+    p.add_argument("--poisson-frac", type=float, default=0.1)
+    p.add_argument("--budget-gb", type=float, default=200.0)
+    p.add_argument("--drain", type=float, default=60.0)
+    p.add_argument("--no-plain", action="store_true")
     return p.parse_args()
 
 
@@ -93,12 +101,139 @@ def cpu_baseline(cfg, budget_s):
             "sample": f"{sample}, {nsteps} steps, {psteps} particle-steps in {el:.1f} s"}
 
 
+def cpu_baseline_ensemble(cfgs, budget_s):
+    """Oracle on a stratified sample of the batched realizations (one per grid edge,
+    in turn), each advanced step by step until the time budget is spent."""
+    import oracle
+    by_edge = {}
+    for c in cfgs:
+        by_edge.setdefault(c["grid"][0], c)
+    sims = []
+    for c in by_edge.values():
+        o = oracle.Sim(c)
+        o.seed_gaussian(c["seed_n0"], c["seed_centre"], c["seed_sigma"])
+        sims.append([o, c, 0])
+    psteps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        progressed = False
+        for s in sims:
+            o, c, k = s
+            if k >= c["steps"]:
+                continue
+            psteps += o.diagnostics()["n_particles"]
+            o.step(c["dt"], 1)
+            s[2] += 1
+            progressed = True
+        if not progressed:
+            break
+    el = time.perf_counter() - t0
+    steps = [s[2] for s in sims]
+    return {"value": psteps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one realization per grid edge {sorted(by_edge)}, steps {steps}, "
+                      f"{psteps} particle-steps in {el:.1f} s"}
+
+
+BYTES_EXPLICIT_STEP = 48 + 60   # push with binning + scatter, per particle-step
+
+
+def bench_ensemble(args):
+    """Batched form: every realization in one ensemble, stepped together to the end,
+    against the plain form (each realization alone in a single context)."""
+    import torch
+
+    from paper_2307_01797_amd import serve, workloads
+    cfgs = workloads.ensemble_realizations(args.realizations)
+    ens = serve.ensemble_for(cfgs)
+    # warm-up pass: admit everything, run a few steps, pick launch shapes, release
+    for i, c in enumerate(cfgs):
+        ens.admit(c, tag=i)
+    ens.step(max(1, args.warmup))
+    tune, tune_ms = ens.autotune(rounds=2)
+    ens.poll()
+    for s in list(ens.ncell):
+        ens.release(s)
+    ens.step(1)
+    torch.cuda.synchronize()
+    rb = serve.run_batched(cfgs, ens=ens, steps_per_poll=4)
+    value = rb["particle_steps"] / rb["seconds"]
+    steps_run = [r["step"] for r in rb["results"]]
+    out = {
+        "metric": "particle-steps/s (batched ensemble: push+sort+KMC+coupling)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": int(max(steps_run)), "warmup": args.warmup,
+        "ms_per_step": rb["seconds"] * 1e3 / max(1, max(steps_run)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble_{len(cfgs)}", "realizations": len(cfgs),
+                   "edges": sorted({c["grid"][0] for c in cfgs}), "dx_m": 5e-6,
+                   "steps_max": 500, "stop_particles": 1_000_000,
+                   "capped": sum(1 for r in rb["results"] if r["state"] != 2),
+                   "particle_steps": rb["particle_steps"], "seconds": rb["seconds"],
+                   "tuning": tune, "autotune_step_ms": tune_ms,
+                   "arena_gb": ens.arena_bytes / 1e9},
+        "step_bandwidth": {"bytes_per_particle_step": BYTES_EXPLICIT_STEP,
+                           "achieved_gbs": BYTES_EXPLICIT_STEP * value / 1e9,
+                           "frac": BYTES_EXPLICIT_STEP * value / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_plain:
+        rp = serve.run_plain(cfgs)
+        same = sum(1 for a, b in zip(rb["results"], rp["results"])
+                   if all(a[k] == b[k] for k in ("weight", "n_particles", "fires", "n_plus",
+                                                 "n_minus", "particle_steps", "step")))
+        out["plain_form"] = {"seconds": rp["seconds"],
+                             "value": rp["particle_steps"] / rp["seconds"],
+                             "identical_results": same, "of": len(cfgs)}
+        out["speedup_vs_plain"] = rp["seconds"] / rb["seconds"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_ensemble(cfgs, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+def bench_served(args):
+    """Served form: Poisson arrivals, continuous batching, HBM-budget admission;
+    p50/p99 time-to-result beside throughput, against first-come first-served
+    single-context serving of the same request stream."""
+    import torch
+
+    from paper_2307_01797_amd import serve, workloads
+    trace = workloads.request_trace(rate=args.rate, duration=args.duration,
+                                    poisson_frac=args.poisson_frac)
+    srv = serve.Server(budget_bytes=args.budget_gb * 1e9)
+    # warm-up: a few requests through both lanes (graph capture, allocator)
+    warm = [(0.0, -1 - i, c) for i, (_, _, c) in enumerate(trace[:8])]
+    srv.run(warm)
+    torch.cuda.synchronize()
+    summary, recs = srv.run(trace, drain_limit_s=args.drain)
+    out = {
+        "metric": "served requests/s with p50/p99 time-to-result",
+        "value": summary["throughput_req_s"], "unit": "requests/s", "n_gpus": 1,
+        "steps": summary["ensemble_steps"], "warmup": len(warm),
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served", "rate_req_s": args.rate, "duration_s": args.duration,
+                   "poisson_frac": args.poisson_frac, "budget_gb": args.budget_gb,
+                   "drain_limit_s": args.drain},
+        "served": summary,
+    }
+    if not args.no_plain:
+        ps, _ = serve.serve_plain(trace, time_limit_s=summary["wall_s"])
+        out["plain_form"] = ps
+        if ps["throughput_req_s"] > 0:
+            out["throughput_ratio_vs_plain"] = summary["throughput_req_s"] / ps["throughput_req_s"]
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: this benchmark runs on exactly one GPU; "
                                    "--gpus above 1 is not supported"}))
         sys.exit(2)
+    if args.workload.startswith("ensemble"):
+        return bench_ensemble(args)
+    if args.workload == "served":
+        return bench_served(args)
     import torch
 
     from paper_2307_01797_amd import itokmc, workloads

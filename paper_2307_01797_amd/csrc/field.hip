@@ -176,63 +176,46 @@ template <> struct NormalsF<float> {
 
 // ---- particle passes --------------------------------------------------------------
 
-// mode 0: electron number at X^k only (initial field); mode 1: sigma at X^k and the
-// electron number at X_dagger.
-template <typename T>
-__global__ void __launch_bounds__(256) k_field_deposit(Bank a, const Counters* ctr, int which,
-                                                      StepConst K, const void* Ex, const void* Ey,
-                                                      const void* Ez, Coef co, int mode, T* sig,
-                                                      T* ne) {
-  const uint32_t n = min(ctr->n[which], K.cap);
-  const T diff = (T)K.diff;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t w = a.w[i];
-    if (!w) continue;
-    const uint32_t cell = a.cell[i];
-    const int ci = (int)(cell % (uint32_t)K.nx), cj = (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
-              ck = (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny));
-    const T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
-    int i0, j0, k0;
-    T fx, fy, fz;
-    tent_axis<T>(ci, o[0], K.nx, i0, fx);
-    tent_axis<T>(cj, o[1], K.ny, j0, fy);
-    tent_axis<T>(ck, o[2], K.nz, k0, fz);
-    if (mode == 0) {
-      cic_add<T>(ne, K, i0, j0, k0, fx, fy, fz, (T)w);
-      continue;
-    }
-    const T e[3] = {cic_get<T>(ctp<T>(Ex), K, i0, j0, k0, fx, fy, fz),
-                    cic_get<T>(ctp<T>(Ey), K, i0, j0, k0, fx, fy, fz),
-                    cic_get<T>(ctp<T>(Ez), K, i0, j0, k0, fx, fy, fz)};
-    const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-    const T mu = Mob<T>::mu(co, Em);
-    cic_add<T>(sig, K, i0, j0, k0, fx, fy, fz, mu * (T)w);
-    const uint64_t id = a.id[i];
-    const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
-    T nr[3];
-    NormalsF<T>::get(r, nr);
-    tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
-    tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
-    tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
-    cic_add<T>(ne, K, i0, j0, k0, fx, fy, fz, (T)w);
-  }
-}
+// Deposit accumulators.  In single precision the node sums are fixed-point integers
+// (conductivity weight mu w in units of 2^-32, electron number in units of 2^-28,
+// 64-bit), so a sum does not depend on the order of its atomic additions and the field
+// of a realization is bit-reproducible; each single-precision contribution converts
+// exactly or to within half a unit.  Ranges: 2^31 and 2^35 per node.  Double precision
+// sums doubles.
+template <typename T> struct DepAcc;
+template <> struct DepAcc<double> {
+  using S = double;
+  __device__ static S enc0(double a) { return a; }
+  __device__ static S enc1(double a) { return a; }
+  __device__ static double dec0(S v) { return v; }
+  __device__ static double dec1(S v) { return v; }
+};
+template <> struct DepAcc<float> {
+  using S = unsigned long long;
+  __device__ static S enc0(float a) { return (S)rintf(a * 0x1p32f); }
+  __device__ static S enc1(float a) { return (S)rintf(a * 0x1p28f); }
+  __device__ static double dec0(S v) { return (double)v * 0x1p-32; }
+  __device__ static double dec1(S v) { return (double)v * 0x1p-28; }
+};
 
-// LDS-staged form of k_field_deposit.  A workgroup takes a chunk of kDepChunk
+// Charge deposit for the field solve.  A workgroup takes a chunk of kDepChunk
 // consecutive (cell-sorted, hence spatially compact) particles and accumulates their
 // 8-node CIC contributions in an LDS hash table keyed by grid node (linear probing,
 // at most kDepProbes probes, then a direct global atomic); the table is flushed with
-// one global atomic per touched node and field.  Same arithmetic as k_field_deposit.
+// one global atomic per touched node and field.  Mode 0 deposits the electron number
+// at X^k only (initial field); mode 1 deposits the conductivity weight mu(|E^k|) w at
+// X^k and the electron number at X_dagger (the position after the diffusive part of
+// the step, with the normals of the push).
 constexpr int kDepChunk = 2048;
 constexpr int kDepProbes = 8;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-template <typename T> struct DepTbl;
-template <> struct DepTbl<float> { static constexpr int log2n = 12; };
-template <> struct DepTbl<double> { static constexpr int log2n = 11; };
+template <typename T> struct DepTbl { static constexpr int log2n = 11; };
 
 template <typename T>
-__device__ __forceinline__ void tbl_add(uint32_t* keys, T* v0, T* v1, uint32_t node, T a, T b,
-                                        T* g0, T* g1) {
+__device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v0,
+                                        typename DepAcc<T>::S* v1, uint32_t node, T a, T b,
+                                        typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
+  using A = DepAcc<T>;
   constexpr int L2 = DepTbl<T>::log2n;
   constexpr uint32_t mask = (1u << L2) - 1u;
   uint32_t h = (node * 2654435761u) >> (32 - L2);
@@ -243,19 +226,21 @@ __device__ __forceinline__ void tbl_add(uint32_t* keys, T* v0, T* v1, uint32_t n
       k = prev == kEmptyKey ? node : prev;
     }
     if (k == node) {
-      if (a != (T)0) atomicAdd(&v0[h], a);
-      if (b != (T)0) atomicAdd(&v1[h], b);
+      if (a != (T)0) atomicAdd(&v0[h], A::enc0(a));
+      if (b != (T)0) atomicAdd(&v1[h], A::enc1(b));
       return;
     }
     h = (h + 1u) & mask;
   }
-  if (a != (T)0) atomicAdd(&g0[node], a);
-  if (b != (T)0) atomicAdd(&g1[node], b);
+  if (a != (T)0) atomicAdd(&g0[node], A::enc0(a));
+  if (b != (T)0) atomicAdd(&g1[node], A::enc1(b));
 }
 
 template <typename T>
-__device__ __forceinline__ void tbl_cic(uint32_t* keys, T* v0, T* v1, const StepConst& K, int i0,
-                                        int j0, int k0, T fx, T fy, T fz, T qa, T qb, T* g0, T* g1) {
+__device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v0,
+                                        typename DepAcc<T>::S* v1, const StepConst& K, int i0,
+                                        int j0, int k0, T fx, T fy, T fz, T qa, T qb,
+                                        typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {
     const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
@@ -271,19 +256,21 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
                                                           StepConst K, const void* Ex,
                                                           const void* Ey, const void* Ez, Coef co,
-                                                          int mode, T* sig, T* ne) {
+                                                          int mode, typename DepAcc<T>::S* sig,
+                                                          typename DepAcc<T>::S* ne) {
+  using S = typename DepAcc<T>::S;
   constexpr int TBL = 1 << DepTbl<T>::log2n;
   extern __shared__ __align__(16) char smem[];
-  uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
-  T* v0 = reinterpret_cast<T*>(smem + TBL * 4);
-  T* v1 = v0 + TBL;
+  S* v0 = reinterpret_cast<S*>(smem);
+  S* v1 = v0 + TBL;
+  uint32_t* keys = reinterpret_cast<uint32_t*>(v1 + TBL);
   const uint32_t n = min(ctr->n[which], K.cap);
   const T diff = (T)K.diff;
   for (uint32_t c0 = blockIdx.x * (uint32_t)kDepChunk; c0 < n; c0 += gridDim.x * (uint32_t)kDepChunk) {
     for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
       keys[t] = kEmptyKey;
-      v0[t] = (T)0;
-      v1[t] = (T)0;
+      v0[t] = (S)0;
+      v1[t] = (S)0;
     }
     __syncthreads();
     const uint32_t c1 = min(c0 + (uint32_t)kDepChunk, n);
@@ -322,8 +309,8 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
     for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
       const uint32_t k = keys[t];
       if (k == kEmptyKey) continue;
-      if (v0[t] != (T)0) atomicAdd(&sig[k], v0[t]);
-      if (v1[t] != (T)0) atomicAdd(&ne[k], v1[t]);
+      if (v0[t] != (S)0) atomicAdd(&sig[k], v0[t]);
+      if (v1[t] != (S)0) atomicAdd(&ne[k], v1[t]);
     }
     __syncthreads();
   }
@@ -412,7 +399,9 @@ __global__ void k_zero(T* p, uint32_t n) {
 // anode potential on the top layer), both scaled by dx^2; accumulates ||b||^2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t* nplus,
-                                                   const uint32_t* nminus, const T* ne, const T* sig,
+                                                   const uint32_t* nminus,
+                                                   const typename DepAcc<T>::S* ne,
+                                                   const typename DepAcc<T>::S* sig,
                                                    double sig_scale, double V, T* eps, double* b,
                                                    double* partial) {
   const uint32_t n = K.ncell;
@@ -423,9 +412,9 @@ __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t*
     const uint32_t c = base + threadIdx.x;
     double bb = 0.0;
     if (c < n) {
-      const double e = 1.0 + sig_scale * (double)sig[c];
+      const double e = 1.0 + sig_scale * DepAcc<T>::dec0(sig[c]);
       eps[c] = (T)e;
-      const double rho_units = (double)nplus[c] - (double)nminus[c] - (double)ne[c];
+      const double rho_units = (double)nplus[c] - (double)nminus[c] - DepAcc<T>::dec1(ne[c]);
       bb = qscale * rho_units;
       const uint32_t k = c / ((uint32_t)K.nx * (uint32_t)K.ny);
       if (k == (uint32_t)K.nz - 1) bb += 2.0 * (double)(T)e * V;
@@ -725,7 +714,7 @@ size_t field_bytes(const itokmc_grid_desc* d) {
   const int nl = build_levels(d, dims);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
-  size_t total = al(n * 8) * 3 + al(n * T) * 6 + al(n * T) * 2 + al(8 * (8 + npart));
+  size_t total = al(n * 8) * 3 + al(n * T) * 6 + al(n * 8) * 2 + al(8 * (8 + npart));
   for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
   return total;
 }
@@ -750,8 +739,8 @@ int field_init(itokmc_ctx* ctx, char* base) {
   F->phi_prev = (double*)p; p += al(n * 8);
   for (int s = 0; s < 2; ++s)
     for (int a = 0; a < 3; ++a) { F->E[s][a] = p; p += al(n * T); }
-  F->sig = p; p += al(n * T);
-  F->ne = p; p += al(n * T);
+  F->sig = p; p += al(n * 8);  // deposit accumulators (8 bytes in either precision)
+  F->ne = p; p += al(n * 8);
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
   F->norms = (double*)p; p += al(8 * (8 + npart));
   F->nlev = nl;
@@ -917,16 +906,17 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   hipStream_t s = ctx->s;
   const uint32_t n = ctx->ncell;
   phase_begin(ctx, PH_DEPOSIT);
-  k_zero<T><<<blocks(n), 256, 0, s>>>((T*)F->sig, n);
-  k_zero<T><<<blocks(n), 256, 0, s>>>((T*)F->ne, n);
+  using S = typename DepAcc<T>::S;
+  k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->sig, n);
+  k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->ne, n);
   void* const* Eo = F->E[F->cur];
   {
     constexpr int TBL = 1 << DepTbl<T>::log2n;
-    const size_t lds = (size_t)TBL * (4 + 2 * sizeof(T));
+    const size_t lds = (size_t)TBL * (4 + 2 * sizeof(S));
     int g = (int)((ctx->cap + kDepChunk - 1) / kDepChunk);
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     k_field_deposit_lds<T><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1],
-                                               Eo[2], coef(ctx), mode, (T*)F->sig, (T*)F->ne);
+                                               Eo[2], coef(ctx), mode, (S*)F->sig, (S*)F->ne);
   }
   const double sig_scale = mode == 1 ? kE * K.dt / (kEps0 * K.dx * K.dx * K.dx) : 0.0;
   if (mode == 1) {
@@ -936,8 +926,8 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   } else {
     F->have_prev = false;
   }
-  k_field_prep<T><<<kRedBlocks, 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const T*)F->ne,
-                                             (const T*)F->sig, sig_scale, ctx->d.V_anode,
+  k_field_prep<T><<<kRedBlocks, 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const S*)F->ne,
+                                             (const S*)F->sig, sig_scale, ctx->d.V_anode,
                                              (T*)F->lev[0].eps, F->b, F->norms + 8);
   k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms);
   phase_end(ctx, PH_DEPOSIT);

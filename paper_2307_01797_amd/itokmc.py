@@ -218,6 +218,11 @@ def make_desc(cfg, precision=None, max_particles=None):
     return d
 
 
+def arena_bytes(cfg, precision=None, max_particles=None):
+    """Device bytes a single context for cfg needs (0 if the descriptor is invalid)."""
+    return lib().itokmc_arena_bytes(ctypes.byref(make_desc(cfg, precision, max_particles)))
+
+
 def make_coeffs(cfg):
     c = Coeffs()
     for n, _ in Coeffs._fields_:

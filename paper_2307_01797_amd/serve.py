@@ -1,0 +1,336 @@
+"""Batched and served forms of the method on one GPU, over the itokmc C ABI.
+
+* run_batched: a fixed set of uniform-field realizations admitted into one batched
+  ensemble and stepped together until every one is done.
+* run_plain: the same realizations one at a time, each in its own single context
+  (the plain per-realization form).
+* Server: a request loop with continuous batching.  Uniform-field requests are
+  admitted into the resident ensemble as soon as a slot, pool cells and particle quota
+  are free (the arena is sized from an HBM budget); each ensemble step advances every
+  resident request, and finished ones are reported and released between steps while
+  new ones join.  Self-consistent (Poisson) requests run in single contexts on worker
+  threads with streams of their own, admitted against the remaining budget, so their
+  kernels overlap the ensemble's on the device.
+* serve_plain: the same request stream handled first-come first-served, one request
+  at a time in single contexts.
+
+Every request's stop rule is the library's: a request is done after its step budget
+or after the first step that began with at least stop_particles live particles.
+Host code here only schedules; all arithmetic runs in the library's kernels.
+"""
+import collections
+import queue
+import threading
+import time
+
+import numpy as np
+
+from . import itokmc
+
+BANK_BYTES_FP32 = 2 * 32   # both particle banks, bytes per particle slot
+CELL_BYTES = 36            # ensemble per-cell arrays
+
+
+def _stop_rule_run(sim, cfg, cancelled=None):
+    """Step a single context under the stop rule; returns steps run, or None if
+    cancelled() became true first."""
+    stop = int(cfg.get("stop_particles", 0))
+    steps = 0
+    for _ in range(int(cfg["steps"])):
+        if cancelled is not None and cancelled():
+            return None
+        live = sim.diagnostics()["n_particles"] if stop else 0
+        sim.step(1)
+        steps += 1
+        if stop and live >= stop:
+            break
+    return steps
+
+
+def run_plain_one(cfg, device="cuda:0", stream=None, keep_particles=False, cancelled=None):
+    """One request in its own context; returns (diagnostics, particles or None), or
+    (None, None) if cancelled."""
+    sim = itokmc.Sim(cfg, device=device, max_particles=cfg["max_particles"], stream=stream)
+    try:
+        sim.seed()
+        if _stop_rule_run(sim, cfg, cancelled) is None:
+            return None, None
+        d = sim.diagnostics(check=False)
+        parts = sim.particles() if keep_particles else None
+        return d, parts
+    finally:
+        sim.close()
+
+
+def run_plain(cfgs, device="cuda:0"):
+    """Plain per-realization form: each realization alone, one after another."""
+    import torch
+    dev = torch.device(device)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    results = [run_plain_one(c, device)[0] for c in cfgs]
+    torch.cuda.synchronize(dev)
+    sec = time.perf_counter() - t0
+    return dict(seconds=sec, results=results,
+                particle_steps=sum(r["particle_steps"] for r in results))
+
+
+def ensemble_for(cfgs, max_slots=None, device="cuda:0"):
+    """An ensemble whose pools hold all of cfgs at once."""
+    blocks = sum(-(-int(np.prod(c["grid"])) // 4096) for c in cfgs)
+    quota = sum(int(c["max_particles"]) for c in cfgs)
+    return itokmc.Ensemble(max_slots or len(cfgs), blocks * 4096, quota,
+                           precision=cfgs[0].get("precision", "fp32"), device=device)
+
+
+def run_batched(cfgs, ens=None, steps_per_poll=4, device="cuda:0"):
+    """Batched form: admit every realization, step the ensemble until all are done."""
+    import torch
+    dev = torch.device(device)
+    ens = ens or ensemble_for(cfgs, device=device)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    slot_of = {}
+    for i, c in enumerate(cfgs):
+        s = ens.admit(c, tag=i)
+        if s is None:
+            raise RuntimeError("ensemble pools too small for the batch")
+        slot_of[i] = s
+    done = {}
+    while len(done) < len(cfgs):
+        ens.step(steps_per_poll)
+        for slot, state, tag, steps in ens.poll():
+            done[tag] = (slot, state, steps)
+    torch.cuda.synchronize(dev)
+    sec = time.perf_counter() - t0
+    results = []
+    for i in range(len(cfgs)):
+        slot, state, steps = done[i]
+        r = ens.result(slot)
+        r["state"] = state
+        results.append(r)
+    for i in range(len(cfgs)):
+        ens.release(done[i][0])
+    ens.step(1)  # drop the released realizations' particles
+    return dict(seconds=sec, results=results, ensemble=ens,
+                particle_steps=sum(r["particle_steps"] for r in results))
+
+
+def _percentiles(lat):
+    if not lat:
+        return None, None
+    a = np.sort(np.asarray(lat))
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+class Server:
+    """Continuous-batching request loop on one GPU (see the module docstring).
+
+    budget_bytes: device memory the service may hold; the ensemble arena takes
+    (1 - poisson_share) of it, self-consistent requests reserve their context arenas
+    from the rest.  keep: request ids whose final particles are returned."""
+
+    def __init__(self, budget_bytes=200e9, max_slots=1024, poisson_share=0.25,
+                 poisson_workers=2, slot_particles=1_250_000, slot_cells=96**3,
+                 device="cuda:0", keep=()):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        ens_budget = budget_bytes * (1.0 - poisson_share)
+        per_slot = slot_particles * BANK_BYTES_FP32 + slot_cells * CELL_BYTES
+        slots = int(max(1, min(max_slots, ens_budget // per_slot)))
+        cells = -(-slots * slot_cells // 4096) * 4096
+        particles = min(0x7FFFFFFF, slots * slot_particles)
+        self.ens = itokmc.Ensemble(slots, cells, particles, device=device)
+        self.slots = slots
+        self.budget = budget_bytes
+        self.poisson_budget = max(0.0, budget_bytes - self.ens.arena_bytes)
+        self.poisson_free = self.poisson_budget
+        self.poisson_workers = poisson_workers
+        self.keep = set(keep)
+        self.cv = threading.Condition()
+        self._cancel = threading.Event()
+
+    # -- self-consistent lane -------------------------------------------------------
+    def _poisson_worker(self, q, results, t0, stream, errors):
+        torch = self.torch
+        cancelled = self._cancel.is_set
+        try:
+            with torch.cuda.stream(stream):
+                while not cancelled():
+                    try:
+                        item = q.get(timeout=0.05)
+                    except queue.Empty:
+                        continue
+                    if item is None:
+                        return
+                    t_arr, rid, cfg = item
+                    need = itokmc.arena_bytes(cfg, max_particles=cfg["max_particles"])
+                    if need > self.poisson_budget:
+                        results[rid] = dict(kind="poisson", arrival=t_arr, rejected=True)
+                        continue
+                    with self.cv:
+                        while self.poisson_free < need and not cancelled():
+                            self.cv.wait(0.05)
+                        if cancelled():
+                            return
+                        self.poisson_free -= need
+                    t_adm = time.perf_counter() - t0
+                    try:
+                        d, parts = run_plain_one(cfg, self.device, stream, rid in self.keep,
+                                                 cancelled)
+                    finally:
+                        with self.cv:
+                            self.poisson_free += need
+                            self.cv.notify_all()
+                    if d is None:
+                        return
+                    results[rid] = dict(kind="poisson", arrival=t_arr, admitted=t_adm,
+                                        finished=time.perf_counter() - t0, diag=d,
+                                        particles=parts)
+        except Exception as e:  # reported by run()
+            errors.append(repr(e))
+
+    # -- main loop ----------------------------------------------------------------------
+    def run(self, trace, drain_limit_s=None, steps_per_poll=1):
+        """Serve a request trace [(arrival_s, id, cfg)] in real time.  Returns a summary
+        and the per-request records (arrival, admission and finish times in s)."""
+        torch = self.torch
+        ens = self.ens
+        results = {}
+        errors = []
+        pq = queue.Queue()
+        streams = [torch.cuda.Stream(self.device) for _ in range(self.poisson_workers)]
+        torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
+        workers = [threading.Thread(target=self._poisson_worker, args=(pq, results, t0, s, errors),
+                                    daemon=True) for s in streams]
+        for w in workers:
+            w.start()
+        end_arrivals = trace[-1][0] if trace else 0.0
+        i = 0
+        pending = collections.deque()
+        active = {}
+        batched_steps = 0
+        max_active = 0
+        self.admission_waits = 0
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(trace) and trace[i][0] <= now:
+                item = trace[i]
+                i += 1
+                if item[2].get("field") == "poisson":
+                    pq.put(item)
+                else:
+                    pending.append(item)
+            while pending:
+                t_arr, rid, cfg = pending[0]
+                slot = ens.admit(cfg, tag=rid)
+                if slot is None and not active:
+                    ens.step(1)  # an empty step returns released cells and quota
+                    slot = ens.admit(cfg, tag=rid)
+                    if slot is None:
+                        # larger than the whole ensemble: can never be admitted
+                        pending.popleft()
+                        results[rid] = dict(kind="batched", arrival=t_arr, rejected=True)
+                        continue
+                if slot is None:
+                    self.admission_waits += 1
+                    break
+                pending.popleft()
+                active[slot] = (rid, t_arr, now)
+            max_active = max(max_active, len(active))
+            if active:
+                ens.step(steps_per_poll)
+                batched_steps += steps_per_poll
+                events = ens.poll()
+                tf = time.perf_counter() - t0
+                for slot, state, tag, steps in events:
+                    rid, t_arr, t_adm = active.pop(slot)
+                    d = ens.result(slot)
+                    parts = ens.particles(slot) if rid in self.keep else None
+                    ens.release(slot)
+                    results[rid] = dict(kind="batched", arrival=t_arr, admitted=t_adm,
+                                        finished=tf, state=state, steps=steps, diag=d,
+                                        particles=parts)
+            elif i >= len(trace) and not pending:
+                break
+            elif i < len(trace):
+                time.sleep(max(0.0, min(0.002, trace[i][0] - now)))
+            if drain_limit_s is not None and now > end_arrivals + drain_limit_s:
+                break
+        # let the self-consistent lane finish its queue, within the drain limit
+        for _ in workers:
+            pq.put(None)
+        deadline = None if drain_limit_s is None else t0 + end_arrivals + drain_limit_s
+        for w in workers:
+            while w.is_alive():
+                w.join(0.1)
+                if deadline is not None and time.perf_counter() > deadline:
+                    self._cancel.set()
+        torch.cuda.synchronize(self.device)
+        if errors:
+            raise RuntimeError("self-consistent worker failed: " + "; ".join(errors))
+        wall = time.perf_counter() - t0
+        return self._summary(trace, results, wall, batched_steps, max_active), results
+
+    def _summary(self, trace, results, wall, batched_steps, max_active):
+        lat_all, lat_b, lat_p = [], [], []
+        psteps = 0
+        done = 0
+        unfinished_poisson = 0
+        for t, rid, cfg in trace:
+            r = results.get(rid)
+            if r is None or r.get("rejected"):
+                if cfg.get("field") == "poisson":
+                    unfinished_poisson += 1
+                continue
+            done += 1
+            lat = r["finished"] - r["arrival"]
+            lat_all.append(lat)
+            (lat_p if r["kind"] == "poisson" else lat_b).append(lat)
+            psteps += r["diag"]["particle_steps"]
+        p50, p99 = _percentiles(lat_all)
+        b50, b99 = _percentiles(lat_b)
+        q50, q99 = _percentiles(lat_p)
+        n = len(trace)
+        return dict(requests=n, completed=done, unfinished=n - done,
+                    unfinished_poisson=unfinished_poisson, wall_s=wall,
+                    throughput_req_s=done / wall if wall > 0 else 0.0,
+                    particle_steps_per_s=psteps / wall if wall > 0 else 0.0,
+                    p50_s=p50, p99_s=p99, batched_p50_s=b50, batched_p99_s=b99,
+                    poisson_p50_s=q50, poisson_p99_s=q99, slots=self.slots,
+                    max_resident=max_active, ensemble_steps=batched_steps,
+                    admission_waits=self.admission_waits,
+                    ensemble_arena_gb=self.ens.arena_bytes / 1e9)
+
+
+def serve_plain(trace, time_limit_s, device="cuda:0", keep=()):
+    """First-come first-served, one request at a time in a single context; stops
+    starting new requests after time_limit_s.  Returns (summary, records)."""
+    import torch
+    dev = torch.device(device)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    results = {}
+    psteps = 0
+    for t_arr, rid, cfg in trace:
+        now = time.perf_counter() - t0
+        if now > time_limit_s:
+            break
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        t_adm = time.perf_counter() - t0
+        d, parts = run_plain_one(cfg, device, keep_particles=rid in keep)
+        results[rid] = dict(kind=cfg.get("field", "uniform"), arrival=t_arr, admitted=t_adm,
+                            finished=time.perf_counter() - t0, diag=d, particles=parts)
+        psteps += d["particle_steps"]
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    lat = [r["finished"] - r["arrival"] for r in results.values()]
+    p50, p99 = _percentiles(lat)
+    return dict(requests=len(trace), completed=len(results),
+                unfinished=len(trace) - len(results), wall_s=wall,
+                throughput_req_s=len(results) / wall if wall > 0 else 0.0,
+                particle_steps_per_s=psteps / wall if wall > 0 else 0.0,
+                p50_s=p50, p99_s=p99), results

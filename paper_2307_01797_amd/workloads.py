@@ -69,27 +69,67 @@ def preset(name, **overrides):
     return cfg
 
 
-def ensemble_realizations(n=256, seed=1):
-    """Batched-avalanche realizations: grid edge uniform in {32, 48, 64, 96} (dx = 5 um),
+def ensemble_realization(r, seed=1):
+    """Batched-avalanche realization r: grid edge uniform in {32, 48, 64, 96} (dx = 5 um),
     initial electrons log-uniform in [1e3, 1e5], uniform field log-uniform in
     [3, 12] MV/m, 500 steps of 1 ps or until 1e6 particles, FP32 state.  A realization
     stops after the first step that began with at least stop_particles live particles;
-    its particle quota (max_particles) leaves room for that step's growth."""
-    rng = np.random.default_rng(seed)
+    its particle quota (max_particles) leaves room for that step's growth.  Parameters
+    are drawn from a generator keyed by (seed, r), so realization r is the same in any
+    batch or request stream."""
+    rng = np.random.default_rng([seed, r])
+    edge = int(rng.choice([32, 48, 64, 96]))
+    n0 = int(round(10 ** rng.uniform(3, 5)))
+    E = float(10 ** rng.uniform(math.log10(3e6), math.log10(1.2e7)))
+    L = edge * 5e-6
+    return dict(
+        name=f"ens_{r}", grid=(edge, edge, edge), dx=5e-6, field="uniform", E=(0.0, 0.0, E),
+        coeffs=dict(AIR), kmc="hybrid", n_ppc=0, n_new=64, seed=seed, realization=r,
+        precision="fp32", dt=1e-12, steps=500, stop_particles=1_000_000,
+        max_particles=1_250_000,
+        seed_kind="gaussian", seed_n0=n0, seed_centre=(L / 2, L / 2, L / 2),
+        seed_sigma=0.156 * L)
+
+
+def ensemble_realizations(n=256, seed=1):
+    """The first n batched-avalanche realizations (see ensemble_realization)."""
+    return [ensemble_realization(r, seed) for r in range(n)]
+
+
+def poisson_request(r, seed=1):
+    """Self-consistent served request r: 128^3 grid, dx = 5 um (L = 640 um), plane
+    electrodes at V = E L with E drawn as for the batched avalanches, the same Gaussian
+    electron seed, semi-implicit Poisson each step, no photons or merging, 500 steps of
+    1 ps or until 1e6 particles, FP32 state."""
+    rng = np.random.default_rng([seed, r, 128])
+    n0 = int(round(10 ** rng.uniform(3, 5)))
+    E = float(10 ** rng.uniform(math.log10(3e6), math.log10(1.2e7)))
+    L = 128 * 5e-6
+    return dict(
+        name=f"poisson_{r}", grid=(128, 128, 128), dx=5e-6, field="poisson", V_anode=E * L,
+        coeffs=dict(AIR), kmc="hybrid", n_ppc=0, n_new=64, seed=seed, realization=r,
+        precision="fp32", dt=1e-12, steps=500, stop_particles=1_000_000,
+        max_particles=1_250_000, gmg_rtol=1e-10,
+        seed_kind="gaussian", seed_n0=n0, seed_centre=(L / 2, L / 2, L / 2),
+        seed_sigma=0.156 * L)
+
+
+def request_trace(rate=200.0, duration=60.0, poisson_frac=0.1, seed=1):
+    """Served workload: Poisson arrivals at `rate` requests/s over `duration` s; each
+    request is a self-consistent 128^3 request with probability poisson_frac, else a
+    batched-avalanche realization.  Returns [(arrival_s, request_id, cfg)]."""
+    rng = np.random.default_rng([seed, 5])
     out = []
-    for r in range(n):
-        edge = int(rng.choice([32, 48, 64, 96]))
-        n0 = int(round(10 ** rng.uniform(3, 5)))
-        E = float(10 ** rng.uniform(math.log10(3e6), math.log10(1.2e7)))
-        L = edge * 5e-6
-        out.append(dict(
-            name=f"ens_{r}", grid=(edge, edge, edge), dx=5e-6, field="uniform", E=(0.0, 0.0, E),
-            coeffs=dict(AIR), kmc="hybrid", n_ppc=0, n_new=64, seed=seed, realization=r,
-            precision="fp32", dt=1e-12, steps=500, stop_particles=1_000_000,
-            max_particles=1_250_000,
-            seed_kind="gaussian", seed_n0=n0, seed_centre=(L / 2, L / 2, L / 2),
-            seed_sigma=0.156 * L))
-    return out
+    t = 0.0
+    r = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        kind = rng.random() < poisson_frac
+        cfg = poisson_request(r, seed) if kind else ensemble_realization(r, seed)
+        out.append((t, r, cfg))
+        r += 1
 
 
 def random_particles(rng, grid, n, wmax=1, id_base=0):
