@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--poisson-frac", type=float, default=0.1)
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--drain", type=float, default=60.0)
+    p.add_argument("--poisson-workers", type=int, default=4)
     p.add_argument("--no-plain", action="store_true")
     return p.parse_args()
 
@@ -99,6 +100,10 @@ def cpu_baseline(cfg, budget_s):
     el = time.perf_counter() - t0
     return {"value": psteps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample}, {nsteps} steps, {psteps} particle-steps in {el:.1f} s"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def cpu_baseline_ensemble(cfgs, budget_s):
@@ -177,7 +182,8 @@ def bench_ensemble(args):
                            "frac": BYTES_EXPLICIT_STEP * value / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_plain:
-        rp = serve.run_plain(cfgs)
+        log(f"batched form done in {rb['seconds']:.2f} s; plain form next")
+        rp = serve.run_plain(cfgs, log=log)
         same = sum(1 for a, b in zip(rb["results"], rp["results"])
                    if all(a[k] == b[k] for k in ("weight", "n_particles", "fires", "n_plus",
                                                  "n_minus", "particle_steps", "step")))
@@ -199,12 +205,12 @@ def bench_served(args):
     from paper_2307_01797_amd import serve, workloads
     trace = workloads.request_trace(rate=args.rate, duration=args.duration,
                                     poisson_frac=args.poisson_frac)
-    srv = serve.Server(budget_bytes=args.budget_gb * 1e9)
+    srv = serve.Server(budget_bytes=args.budget_gb * 1e9, poisson_workers=args.poisson_workers)
     # warm-up: a few requests through both lanes (graph capture, allocator)
     warm = [(0.0, -1 - i, c) for i, (_, _, c) in enumerate(trace[:8])]
     srv.run(warm)
     torch.cuda.synchronize()
-    summary, recs = srv.run(trace, drain_limit_s=args.drain)
+    summary, recs = srv.run(trace, drain_limit_s=args.drain, log=log)
     out = {
         "metric": "served requests/s with p50/p99 time-to-result",
         "value": summary["throughput_req_s"], "unit": "requests/s", "n_gpus": 1,
@@ -213,11 +219,12 @@ def bench_served(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "served", "rate_req_s": args.rate, "duration_s": args.duration,
                    "poisson_frac": args.poisson_frac, "budget_gb": args.budget_gb,
+                   "poisson_workers": args.poisson_workers,
                    "drain_limit_s": args.drain},
         "served": summary,
     }
     if not args.no_plain:
-        ps, _ = serve.serve_plain(trace, time_limit_s=summary["wall_s"])
+        ps, _ = serve.serve_plain(trace, time_limit_s=summary["wall_s"], log=log)
         out["plain_form"] = ps
         if ps["throughput_req_s"] > 0:
             out["throughput_ratio_vs_plain"] = summary["throughput_req_s"] / ps["throughput_req_s"]

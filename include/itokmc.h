@@ -286,6 +286,10 @@ int itokmc_ensemble_poll(itokmc_ens* ens, itokmc_slot_event* events, int32_t max
  * its particles (cells local to its grid; same array conventions as
  * itokmc_get_particles) and per-cell counts (ITOKMC_Q_NGP_WEIGHT, NPLUS, NMINUS). */
 int itokmc_ensemble_result(itokmc_ens* ens, int32_t slot, itokmc_diag* out);
+/* Diagnostics of n resident realizations at once (one pass over the pool): out[i]
+ * for slots[i]. */
+int itokmc_ensemble_results(itokmc_ens* ens, const int32_t* slots, int32_t n,
+                            itokmc_diag* out);
 int itokmc_ensemble_get_particles(itokmc_ens* ens, int32_t slot, uint64_t* n, uint32_t* cell,
                                   double* off, uint32_t* w, uint64_t* id);
 int itokmc_ensemble_get_counts(itokmc_ens* ens, int32_t slot, int which, uint32_t* host);

@@ -155,12 +155,13 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(nc * 4);         // 20 ngamma
   put(nc * 4);         // 21 dN
   put(nc * 4);         // 22 work
-  put(((nc + 2047) / 2048 + 1) * 8);  // 23 blocksums
+  put(scan_scratch_words(nc) * 4);    // 23 scan scratch
   put(sizeof(Counters));              // 24 counters
   put(64);                            // 25 reduction scratch
   put(field_bytes(d));                // 26 field data
   put(nc * 4);                        // 27 cbase
   put(nc * 4);                        // 28 big
+  put(nc / 2048 + 2);                 // 29 scan tile flags
   L->total = o;
 }
 
@@ -237,6 +238,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->field = a + L.off[26];
   ctx->cbase = (uint32_t*)(a + L.off[27]);
   ctx->big = (uint32_t*)(a + L.off[28]);
+  ctx->tiles = (uint8_t*)(a + L.off[29]);
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);
@@ -244,6 +246,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   if (e == hipSuccess) e = hipMemsetAsync(ctx->nminus, 0, nb * 4, ctx->s);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->ngamma, 0, nb * 4, ctx->s);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->ctr, 0, sizeof(Counters), ctx->s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->tiles, 0, nb / 2048 + 2, ctx->s);
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_ctr, sizeof(Counters), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete ctx;

@@ -25,13 +25,14 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
                                               const uint32_t* start, const int32_t* dN,
                                               const uint32_t* cbase, int n_new, int n_ppc,
                                               uint32_t* big) {
-  const uint32_t nwork = ctr->n_work;
+  const uint32_t nwork = ctr->n_work, n_occ = ctr->n_occ, sorted = ctr->sorted;
   const int lane = lane_id();
   uint64_t created = 0, removed = 0, merged = 0;
   for (uint32_t t = blockIdx.x; t < nwork; t += gridDim.x) {
     const uint32_t j = work[t];
     const uint32_t c = occ[j];
-    const uint32_t s = start[c], e = start[c + 1];
+    // the cell's sorted range ends where the next occupied cell's begins
+    const uint32_t s = start[c], e = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
     const int32_t d = dN[j];
     if (d < 0) removed += remove_weight(b, s, e, (uint32_t)(-d));
     uint32_t M = 0, wb = 0, wr = 0, base = 0;
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(64) k_merge_big(Bank b, Counters* ctr, int whi
                                                  const uint32_t* big, const uint32_t* occ,
                                                  const uint32_t* start, const int32_t* dN,
                                                  const uint32_t* cbase, int n_new, int n_ppc) {
-  const uint32_t nbig = ctr->n_big;
+  const uint32_t nbig = ctr->n_big, n_occ = ctr->n_occ, sorted = ctr->sorted;
   uint64_t merged = 0;
   for (uint32_t t = blockIdx.x; t < nbig; t += gridDim.x) {
     const uint32_t j = big[t];
@@ -75,8 +76,9 @@ __global__ void __launch_bounds__(64) k_merge_big(Bank b, Counters* ctr, int whi
     const int32_t d = dN[j];
     const uint32_t M = d > 0 ? ((uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new) : 0u;
     const uint32_t base = M ? cbase[j] : 0u;
-    const int r = merge_cell<T, MergeBig<T>::value>(b, ctr, which, K, c, start[c], start[c + 1], base,
-                                                     M, n_ppc, &merged);
+    const uint32_t e = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
+    const int r = merge_cell<T, MergeBig<T>::value>(b, ctr, which, K, c, start[c], e, base, M, n_ppc,
+                                                     &merged);
     if (r == 2 && lane_id() == 0) atomicAdd(&ctr->merge_skipped, 1u);
   }
   if (lane_id() == 0 && merged) atomicAdd(&ctr->merged, (unsigned long long)merged);

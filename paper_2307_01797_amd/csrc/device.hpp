@@ -123,6 +123,14 @@ __device__ __forceinline__ uint64_t run_add(unsigned long long* acc, uint32_t ke
   return old + x - (active ? val : 0ull);
 }
 
+// Scan tiles of 2048 cells.  The binning kernels flag the tile of every cell that
+// receives its first particle of the step; the counting-sort scan visits flagged tiles
+// only (and clears the flags).
+constexpr int kTileShift = 11;
+__device__ __forceinline__ void mark_tile(uint8_t* tiles, uint32_t key, uint64_t old) {
+  if (key != kInvalidCell && (old >> 32) == 0) tiles[key >> kTileShift] = 1;
+}
+
 // Wave-wide sum (result valid in every lane).
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 #pragma unroll

@@ -187,7 +187,8 @@ __global__ void __launch_bounds__(256) e_seed_gaussian(Bank b, Counters* ctr, in
 // particles of finished slots stay binned where they are.
 template <typename T>
 __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
-                                              unsigned long long* cellacc, const SlotConst* sc,
+                                              unsigned long long* cellacc, uint8_t* tiles,
+                                              const SlotConst* sc,
                                               const int32_t* blk_slot, const uint32_t* blk_local,
                                               const uint32_t* map, unsigned long long* st,
                                               uint32_t ms, uint32_t cap) {
@@ -230,6 +231,7 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
       }
     }
     const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    mark_tile(tiles, key, old);
     if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
     uint64_t tot;
     if (run_total(skey, packed, &tot)) {
@@ -311,13 +313,16 @@ __global__ void __launch_bounds__(64) e_couple(Bank b, Counters* ctr, const uint
                                               const int32_t* dN, const uint32_t* cbase,
                                               const SlotConst* sc, const int32_t* blk_slot,
                                               const uint32_t* blk_local, uint32_t cap) {
-  const uint32_t nwork = ctr->n_work;
+  const uint32_t nwork = ctr->n_work, n_occ = ctr->n_occ, sorted = ctr->sorted;
   const int lane = lane_id();
   for (uint32_t t = blockIdx.x; t < nwork; t += gridDim.x) {
     const uint32_t j = work[t];
     const uint32_t g = occ[j];
     const int32_t d = dN[j];
-    if (d < 0) (void)remove_weight(b, start[g], start[g + 1], (uint32_t)(-d));
+    if (d < 0) {
+      const uint32_t end = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
+      (void)remove_weight(b, start[g], end, (uint32_t)(-d));
+    }
     if (d > 0) {
       const int s = blk_slot[g >> kBlkShift];
       const SlotConst& S = sc[s];
@@ -378,28 +383,33 @@ __global__ void __launch_bounds__(256) e_extract(Bank a, const Counters* ctr, in
   }
 }
 
-// Live particle count and weight of one slot, and its ion sums over its blocks.
-__global__ void __launch_bounds__(256) e_reduce_slot(Bank a, const Counters* ctr, int which,
-                                                    uint32_t cap, int s, const int32_t* blk_slot,
-                                                    unsigned long long* out) {
+// Live particle count and weight of every slot in one pool pass (out: 2 per slot).
+__global__ void __launch_bounds__(256) e_reduce_all(Bank a, const Counters* ctr, int which,
+                                                   uint32_t cap, const int32_t* blk_slot,
+                                                   unsigned long long* out) {
   const uint32_t n = min(ctr->n[which], cap);
-  uint64_t cnt = 0, W = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t w = a.w[i];
-    if (w > 0 && blk_slot[a.cell[i] >> kBlkShift] == s) { ++cnt; W += w; }
-  }
-  cnt = wave_sum64(cnt);
-  W = wave_sum64(W);
-  if (lane_id() == 0) {
-    if (cnt) atomicAdd(&out[0], (unsigned long long)cnt);
-    if (W) atomicAdd(&out[1], (unsigned long long)W);
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t key = kInvalidCell, w = 0;
+    if (i < n) {
+      w = a.w[i];
+      if (w > 0) {
+        const int s = blk_slot[a.cell[i] >> kBlkShift];
+        if (s >= 0) key = (uint32_t)s;
+      }
+    }
+    uint64_t tot;
+    if (run_total(key, 1ull, &tot)) atomicAdd(&out[2 * key], (unsigned long long)tot);
+    if (run_total(key, (uint64_t)w, &tot)) atomicAdd(&out[2 * key + 1], (unsigned long long)tot);
   }
 }
 
-__global__ void __launch_bounds__(256) e_reduce_ions(BlkList L, const uint32_t* nplus,
-                                                    const uint32_t* nminus,
-                                                    unsigned long long* out) {
-  const uint32_t b = L.b[blockIdx.x];
+// Ion sums of the listed blocks into out[2 idx[i] ..] (one workgroup per block).
+__global__ void __launch_bounds__(256) e_reduce_ions_multi(BlkList L, BlkList idx,
+                                                          const uint32_t* nplus,
+                                                          const uint32_t* nminus,
+                                                          unsigned long long* out) {
+  const uint32_t b = L.b[blockIdx.x], k = idx.b[blockIdx.x];
   uint64_t p = 0, m = 0;
   for (uint32_t i = threadIdx.x; i < kBlkCells; i += blockDim.x) {
     p += nplus[(b << kBlkShift) + i];
@@ -408,8 +418,8 @@ __global__ void __launch_bounds__(256) e_reduce_ions(BlkList L, const uint32_t* 
   p = wave_sum64(p);
   m = wave_sum64(m);
   if (lane_id() == 0) {
-    if (p) atomicAdd(&out[2], (unsigned long long)p);
-    if (m) atomicAdd(&out[3], (unsigned long long)m);
+    if (p) atomicAdd(&out[2 * k], (unsigned long long)p);
+    if (m) atomicAdd(&out[2 * k + 1], (unsigned long long)m);
   }
 }
 
@@ -482,6 +492,8 @@ struct itokmc_ens {
   uint32_t* stat2 = nullptr;
   int32_t* blk_slot = nullptr;
   uint32_t *blk_local = nullptr, *map = nullptr;
+  unsigned long long* slot_red = nullptr;  // 4 per slot: count, weight (pool), n+, n-
+  uint8_t* tiles = nullptr;                // scan tile flags
   // host bookkeeping
   std::vector<SlotHost> slots;
   std::set<uint32_t> free_blocks, used_blocks;
@@ -522,7 +534,7 @@ int ens_hip(itokmc_ens* e, hipError_t h, const char* what) {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct EnsLayout {
-  size_t off[32];
+  size_t off[40];
   size_t total;
 };
 
@@ -555,7 +567,7 @@ void ens_layout(const itokmc_ens_desc* d, EnsLayout* L) {
   put(nc * 4);                         // 19 dN
   put(nc * 4);                         // 20 work
   put(nc * 4);                         // 21 cbase
-  put(((nc + 2047) / 2048 + 1) * 8);   // 22 blocksums
+  put(scan_scratch_words(nc) * 4);     // 22 scan scratch
   put(sizeof(Counters));               // 23 counters
   put(64);                             // 24 misc
   put(64);                             // 25 reduction scratch
@@ -565,6 +577,8 @@ void ens_layout(const itokmc_ens_desc* d, EnsLayout* L) {
   put(nblk * 4);                       // 29 block -> slot
   put(nblk * 4);                       // 30 block -> local block
   put(2 * nblk * 4);                   // 31 block maps
+  put(ms * 4 * 8);                     // 32 per-slot result reductions
+  put(nc / 2048 + 2);                  // 33 scan tile flags
   L->total = o;
 }
 
@@ -582,17 +596,17 @@ hipError_t enqueue_step(itokmc_ens* e, int cur, hipStream_t s) {
   const int dest = 1 - cur;
   const int gp = grid_particles(e);
   if (f64(e))
-    e_push<double><<<gp, e->tune.push_block, 0, s>>>(e->bank[cur], e->ctr, cur, e->cellacc, e->sc,
+    e_push<double><<<gp, e->tune.push_block, 0, s>>>(e->bank[cur], e->ctr, cur, e->cellacc, e->tiles, e->sc,
                                                      e->blk_slot, e->blk_local, e->map, e->st, e->ms,
                                                      e->cap);
   else
-    e_push<float><<<gp, e->tune.push_block, 0, s>>>(e->bank[cur], e->ctr, cur, e->cellacc, e->sc,
+    e_push<float><<<gp, e->tune.push_block, 0, s>>>(e->bank[cur], e->ctr, cur, e->cellacc, e->tiles, e->sc,
                                                     e->blk_slot, e->blk_local, e->map, e->st, e->ms,
                                                     e->cap);
   hipError_t h = hipGetLastError();
   if (h != hipSuccess) return h;
-  h = launch_scan_raw(e->cellacc, e->max_cells, e->misc, e->blocksums, e->start, e->occ, e->ctr,
-                      dest, s);
+  h = launch_scan_raw(e->cellacc, e->max_cells, e->misc, e->tiles, e->blocksums, e->start, e->occ,
+                      e->ctr, dest, s);
   if (h != hipSuccess) return h;
   h = launch_scatter_raw(e->bank[cur], e->bank[dest], e->ctr, cur, e->start, e->cap, f64(e) ? 1 : 0,
                          std::max(1, (int)std::min<uint64_t>((uint64_t)kCUs * 8, (e->cap + 255) / 256)), s);
@@ -736,10 +750,13 @@ int itokmc_ensemble_create(itokmc_ens** out, const itokmc_ens_desc* desc, void* 
   e->blk_slot = (int32_t*)(a + L.off[29]);
   e->blk_local = (uint32_t*)(a + L.off[30]);
   e->map = (uint32_t*)(a + L.off[31]);
+  e->slot_red = (unsigned long long*)(a + L.off[32]);
+  e->tiles = (uint8_t*)(a + L.off[33]);
   hipError_t h = hipSuccess;
   if (h == hipSuccess) h = hipMemsetAsync(e->cellacc, 0, (size_t)e->max_cells * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->ctr, 0, sizeof(Counters), e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->misc, 0, 64, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->tiles, 0, (size_t)e->max_cells / 2048 + 2, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->sc, 0, (size_t)e->ms * sizeof(SlotConst), e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->st, 0, (size_t)e->ms * S_NUM * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->stat2, 0, (size_t)e->ms * 8, e->s);
@@ -898,48 +915,67 @@ int itokmc_ensemble_poll(itokmc_ens* e, itokmc_slot_event* ev, int32_t max, int3
   return ITOKMC_OK;
 }
 
-int itokmc_ensemble_result(itokmc_ens* e, int32_t slot, itokmc_diag* out) {
-  int rc = check_slot(e, slot);
-  if (rc) return rc;
-  if (!out) return ITOKMC_EINVAL;
-  SlotHost& H = e->slots[slot];
-  hipError_t h = hipMemsetAsync(e->reduce, 0, 64, e->s);
+int itokmc_ensemble_results(itokmc_ens* e, const int32_t* slots, int32_t n, itokmc_diag* out) {
+  if (!e || n < 0 || (n > 0 && (!slots || !out))) return ITOKMC_EINVAL;
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = check_slot(e, slots[i]);
+    if (rc) return rc;
+  }
+  if (n == 0) return ITOKMC_OK;
+  const size_t ms = e->ms;
+  unsigned long long* pool = e->slot_red;           // 2 per slot (all slots)
+  unsigned long long* ions = e->slot_red + 2 * ms;  // 2 per requested index
+  hipError_t h = hipMemsetAsync(e->slot_red, 0, ms * 4 * 8, e->s);
   if (h == hipSuccess) {
     const int g = (int)std::min<uint64_t>(4096, ((uint64_t)e->cap + 255) / 256);
-    e_reduce_slot<<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->cap, slot, e->blk_slot,
-                                       e->reduce);
+    e_reduce_all<<<g, 256, 0, e->s>>>(e->bank[e->cur], e->ctr, e->cur, e->cap, e->blk_slot, pool);
     h = hipGetLastError();
   }
-  if (h == hipSuccess)
-    h = for_lists(H.blocks, [&](const BlkList& L) {
-      e_reduce_ions<<<L.n, 256, 0, e->s>>>(L, e->nplus, e->nminus, e->reduce);
-      return hipGetLastError();
-    });
-  unsigned long long stv[S_NUM];
-  for (int f = 0; f < S_NUM && h == hipSuccess; ++f)
-    h = hipMemcpyAsync(&stv[f], e->st + (size_t)f * e->ms + slot, 8, hipMemcpyDeviceToHost, e->s);
-  uint32_t st2[2] = {0, 0};
-  if (h == hipSuccess) h = hipMemcpyAsync(st2, e->stat2 + 2 * slot, 8, hipMemcpyDeviceToHost, e->s);
-  if (h == hipSuccess) h = hipMemcpyAsync(e->host_red, e->reduce, 32, hipMemcpyDeviceToHost, e->s);
+  // ion sums: every block of every requested slot, tagged with the request index
+  std::vector<uint32_t> blocks, tags;
+  for (int32_t i = 0; i < n && h == hipSuccess; ++i)
+    for (uint32_t b : e->slots[slots[i]].blocks) { blocks.push_back(b); tags.push_back((uint32_t)i); }
+  for (size_t i = 0; i < blocks.size() && h == hipSuccess; i += kListMax) {
+    BlkList L, T;
+    L.n = T.n = (uint32_t)std::min<size_t>(kListMax, blocks.size() - i);
+    L.first_local = T.first_local = 0;
+    for (uint32_t k = 0; k < L.n; ++k) { L.b[k] = blocks[i + k]; T.b[k] = tags[i + k]; }
+    e_reduce_ions_multi<<<L.n, 256, 0, e->s>>>(L, T, e->nplus, e->nminus, ions);
+    h = hipGetLastError();
+  }
+  std::vector<unsigned long long> stv((size_t)S_NUM * ms), red(4 * ms);
+  std::vector<uint32_t> st2(2 * ms);
+  if (h == hipSuccess) h = hipMemcpyAsync(stv.data(), e->st, stv.size() * 8, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipMemcpyAsync(st2.data(), e->stat2, st2.size() * 4, hipMemcpyDeviceToHost, e->s);
+  if (h == hipSuccess) h = hipMemcpyAsync(red.data(), e->slot_red, red.size() * 8, hipMemcpyDeviceToHost, e->s);
   if (h == hipSuccess) h = hipStreamSynchronize(e->s);
-  if (h != hipSuccess) return ens_hip(e, h, "result");
-  memset(out, 0, sizeof(*out));
-  out->n_particles = e->host_red[0];
-  out->weight = e->host_red[1];
-  out->n_plus = (int64_t)e->host_red[2];
-  out->n_minus = (int64_t)e->host_red[3];
-  out->charge = out->n_plus - (int64_t)out->weight - out->n_minus;
-  out->outflow_weight = stv[S_OUTW];
-  out->fires[0] = stv[S_F0];
-  out->fires[1] = stv[S_F1];
-  out->fires[2] = stv[S_F2];
-  out->created = stv[S_CREATED];
-  out->removed_weight = stv[S_REMOVED];
-  out->step = st2[1];
-  out->rho_sum = 1.602176634e-19 * (double)out->charge;
-  out->overflow = stv[S_CAPPED] ? 1u : 0u;
-  out->particle_steps = stv[S_PUSHED];
+  if (h != hipSuccess) return ens_hip(e, h, "results");
+  for (int32_t i = 0; i < n; ++i) {
+    const size_t s = (size_t)slots[i];
+    auto S = [&](int f) { return stv[(size_t)f * ms + s]; };
+    itokmc_diag* o = out + i;
+    memset(o, 0, sizeof(*o));
+    o->n_particles = red[2 * s];
+    o->weight = red[2 * s + 1];
+    o->n_plus = (int64_t)red[2 * ms + 2 * i];
+    o->n_minus = (int64_t)red[2 * ms + 2 * i + 1];
+    o->charge = o->n_plus - (int64_t)o->weight - o->n_minus;
+    o->outflow_weight = S(S_OUTW);
+    o->fires[0] = S(S_F0);
+    o->fires[1] = S(S_F1);
+    o->fires[2] = S(S_F2);
+    o->created = S(S_CREATED);
+    o->removed_weight = S(S_REMOVED);
+    o->step = st2[2 * s + 1];
+    o->rho_sum = 1.602176634e-19 * (double)o->charge;
+    o->overflow = S(S_CAPPED) ? 1u : 0u;
+    o->particle_steps = S(S_PUSHED);
+  }
   return ITOKMC_OK;
+}
+
+int itokmc_ensemble_result(itokmc_ens* e, int32_t slot, itokmc_diag* out) {
+  return itokmc_ensemble_results(e, &slot, 1, out);
 }
 
 int itokmc_ensemble_get_particles(itokmc_ens* e, int32_t slot, uint64_t* n, uint32_t* cell,

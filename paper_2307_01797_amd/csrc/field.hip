@@ -320,7 +320,8 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
 // then binning exactly as the uniform push.
 template <typename T>
 __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int which,
-                                                   unsigned long long* cellacc, StepConst K,
+                                                   unsigned long long* cellacc, uint8_t* tiles,
+                                                   StepConst K,
                                                    const void* Eox, const void* Eoy, const void* Eoz,
                                                    const void* Enx, const void* Eny, const void* Enz,
                                                    Coef co) {
@@ -378,6 +379,7 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
       }
     }
     const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    mark_tile(tiles, key, old);
     if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
   }
   out_w = wave_sum64(out_w);
@@ -956,7 +958,7 @@ static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
   const int nxt = 1 - F->cur;
   phase_begin(ctx, PH_FIELD_PUSH);
   k_push_field<T><<<blocks(ctx->cap, 4096), 256, 0, ctx->s>>>(
-      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, K, F->E[F->cur][0], F->E[F->cur][1],
+      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, F->E[F->cur][0], F->E[F->cur][1],
       F->E[F->cur][2], F->E[nxt][0], F->E[nxt][1], F->E[nxt][2], coef(ctx));
   phase_end(ctx, PH_FIELD_PUSH);
   F->cur = nxt;  // E^{k+1} becomes the field of the next step

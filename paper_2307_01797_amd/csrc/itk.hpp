@@ -30,7 +30,8 @@ struct Counters {
   uint32_t overflow;      // bit 0: particle capacity, bit 1: merge scratch
   uint32_t n_occ;         // occupied cells after binning
   uint32_t n_work;        // cells needing coupling / merge
-  uint32_t pad[3];
+  uint32_t sorted;        // particles placed by the last counting sort
+  uint32_t pad[2];
   unsigned long long outflow, created, removed, merged;
   unsigned long long fires[3];
   unsigned long long ph_emitted, ph_absorbed, ph_lost;
@@ -86,6 +87,7 @@ struct itokmc_ctx {
   uint32_t* cbase = nullptr;              // first reserved bank slot of a cell's products
   uint32_t* big = nullptr;                // occupied-cell indices for the large merge pass
   uint32_t* blocksums = nullptr;          // scan scratch
+  uint8_t* tiles = nullptr;               // per 2048-cell tile: received particles
   itk::Counters* ctr = nullptr;
   unsigned long long* reduce = nullptr;   // small reduction scratch
   bool binned = false;                    // bins of the current bank are filled
@@ -134,8 +136,10 @@ hipError_t launch_scan(itokmc_ctx* ctx);
 hipError_t launch_scatter(itokmc_ctx* ctx);
 // pointer forms used by the ensemble (ncell_dev: device-side cell count to scan)
 hipError_t launch_scan_raw(const unsigned long long* cellacc, uint32_t max_cells,
-                           const uint32_t* ncell_dev, uint32_t* blocksums, uint32_t* start,
-                           uint32_t* occ, Counters* ctr, int dest, hipStream_t s);
+                           const uint32_t* ncell_dev, uint8_t* tiles, uint32_t* blocksums,
+                           uint32_t* start, uint32_t* occ, Counters* ctr, int dest, hipStream_t s);
+// u32 words of scan scratch for a cell count
+size_t scan_scratch_words(uint64_t ncell);
 hipError_t launch_scatter_raw(Bank a, Bank b, Counters* ctr, int which, const uint32_t* start,
                               uint32_t cap, int fp64, int grid, hipStream_t s);
 hipError_t launch_ngp(itokmc_ctx* ctx, uint32_t* out);

@@ -2,6 +2,8 @@
 // transport, the counting sort by cell (scan + scatter) and reductions.
 #include <math.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "itk.hpp"
 #include "poisson.hpp"
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(kBlock) k_seed_neutral(Bank b, Counters* ctr, 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, int which,
                                                         unsigned long long* cellacc,
-                                                        StepConst k) {
+                                                        uint8_t* tiles, StepConst k) {
   const uint32_t n = min(ctr->n[which], k.cap);
   const T drift[3] = {(T)k.drift[0], (T)k.drift[1], (T)k.drift[2]};
   const T diff = (T)k.diff;
@@ -137,6 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
       }
     }
     const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    mark_tile(tiles, key, old);
     if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
   }
   out_w = wave_sum64(out_w);
@@ -149,7 +152,8 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
 
 // Bin the current particles without moving them (after seeding or set_state).
 __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int which,
-                                                 unsigned long long* cellacc, uint32_t cap) {
+                                                 unsigned long long* cellacc, uint8_t* tiles,
+                                                 uint32_t cap) {
   const uint32_t n = min(ctr->n[which], cap);
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t i = base + threadIdx.x;
@@ -159,6 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int whi
       if (w > 0) key = a.cell[i];
     }
     const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
+    mark_tile(tiles, key, old);
     if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
   }
 }
@@ -172,7 +177,8 @@ __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int whi
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int which,
-                                                   unsigned long long* cellacc, uint32_t* ngamma,
+                                                   unsigned long long* cellacc, uint8_t* tiles,
+                                                   uint32_t* ngamma,
                                                    uint32_t* nplus, StepConst k, int n_new,
                                                    double l1, double l2) {
   const double two_pi = 6.283185307179586476925286766559;
@@ -209,6 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
       put<T>(a, q, cell, to_off<T>(y[0] - f[0]), to_off<T>(y[1] - f[1]), to_off<T>(y[2] - f[2]), w,
              make_id(KIND_PHOTO, k.step, c, s));
       const unsigned long long old = atomicAdd(&cellacc[cell], (1ull << 32) | (unsigned long long)w);
+      mark_tile(tiles, cell, old);
       a.rank[q] = (uint32_t)(old >> 32);
       atomicAdd(&nplus[cell], w);
       absorbed += w;
@@ -223,14 +230,20 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
 }
 
 // ---- counting sort by cell ------------------------------------------------------------
-// Three passes over the per-cell counts: block totals, a scan of the block totals, and
-// the final exclusive prefix (start) plus the list of occupied cells.
+// Per 2048-cell tile: particle and occupied-cell counts of flagged tiles (reduce), an
+// exclusive scan of the tile counts in groups of 1024 tiles (mid) and of the group
+// totals (top), then per cell the first bank slot (start, written for occupied cells
+// only) and the ascending list of occupied cells (down).  Scratch layout (u32):
+// tile counts [2 nb] | tile prefixes within the group [2 nb] | group prefixes [2 ng + 2].
 
 constexpr int kScanPer = 8;                     // cells per thread
-constexpr int kScanTile = kBlock * kScanPer;    // cells per block
+constexpr int kScanTile = kBlock * kScanPer;    // cells per tile (1 << kTileShift)
+static_assert(kScanTile == (1 << kTileShift), "scan tile and tile flags disagree");
+constexpr int kScanGroup = 1024;                // tiles per mid-level group
 
+template <int NT>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  // sh: kBlock / 64 + 1 words
+  // sh: NT / 64 + 1 words
   const int lane = lane_id(), wid = threadIdx.x >> 6;
   uint32_t x = v;
 #pragma unroll
@@ -242,12 +255,12 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
-    for (int i = 0; i < kBlock / 64; ++i) { const uint32_t t = sh[i]; sh[i] = acc; acc += t; }
-    sh[kBlock / 64] = acc;
+    for (int i = 0; i < NT / 64; ++i) { const uint32_t t = sh[i]; sh[i] = acc; acc += t; }
+    sh[NT / 64] = acc;
   }
   __syncthreads();
   const uint32_t r = sh[wid] + x - v;
-  *total = sh[kBlock / 64];
+  *total = sh[NT / 64];
   __syncthreads();
   return r;
 }
@@ -257,110 +270,114 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 __device__ __forceinline__ uint32_t scan_cells(uint32_t ncell, const uint32_t* ncell_dev) {
   return ncell_dev ? *ncell_dev : ncell;
 }
+__device__ __forceinline__ uint32_t scan_tiles(uint32_t ncell) {
+  return (ncell + kScanTile - 1) / kScanTile;
+}
 
 __global__ void __launch_bounds__(kBlock) k_scan_reduce(const unsigned long long* cellacc,
                                                        uint32_t ncell_arg,
                                                        const uint32_t* ncell_dev,
-                                                       uint32_t* blocksums) {
+                                                       uint8_t* tiles, uint32_t* cnt) {
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
   const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
-  const uint32_t nb = (ncell + kScanTile - 1) / kScanTile;
+  const uint32_t nb = scan_tiles(ncell);
   for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    if (tiles[t] == 0) {  // no particle was binned into this tile
+      if (threadIdx.x == 0) { cnt[2 * t] = 0u; cnt[2 * t + 1] = 0u; }
+      continue;
+    }
     const uint32_t c0 = t * kScanTile + threadIdx.x * kScanPer;
-    uint32_t cnt = 0, occ = 0;
+    uint32_t n = 0, oc = 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
       const uint32_t c = c0 + j;
       if (c < ncell) {
-        const uint32_t n = (uint32_t)(cellacc[c] >> 32);
-        cnt += n;
-        occ += n ? 1u : 0u;
+        const uint32_t k = (uint32_t)(cellacc[c] >> 32);
+        n += k;
+        oc += k ? 1u : 0u;
       }
     }
     uint32_t t0, t1;
-    block_exclusive_scan(cnt, sh[0], &t0);
-    block_exclusive_scan(occ, sh[1], &t1);
+    block_exclusive_scan<kBlock>(n, sh[0], &t0);
+    block_exclusive_scan<kBlock>(oc, sh[1], &t1);
     if (threadIdx.x == 0) {
-      blocksums[2 * t] = t0;
-      blocksums[2 * t + 1] = t1;
+      cnt[2 * t] = t0;
+      cnt[2 * t + 1] = t1;
+      tiles[t] = 0;  // cleared for the next binning
     }
   }
 }
 
-__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* blocksums, uint32_t ncell_arg,
-                                                  const uint32_t* ncell_dev) {
-  // exclusive scan of nb (count, occupied) pairs by one block; blocksums[2 nb ..] = totals
-  __shared__ uint32_t sh[2][1024 / 64 + 1];
-  const uint32_t nb = (scan_cells(ncell_arg, ncell_dev) + kScanTile - 1) / kScanTile;
-  const int per = (int)((nb + 1023) / 1024);
-  const uint32_t b0 = threadIdx.x * per;
-  uint32_t s0 = 0, s1 = 0;
-  for (int j = 0; j < per; ++j)
-    if (b0 + j < nb) { s0 += blocksums[2 * (b0 + j)]; s1 += blocksums[2 * (b0 + j) + 1]; }
-  // block scan with 1024 threads
-  const int lane = lane_id(), wid = threadIdx.x >> 6;
-  uint32_t x0 = s0, x1 = s1;
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y0 = __shfl_up(x0, d, 64), y1 = __shfl_up(x1, d, 64);
-    if (lane >= d) { x0 += y0; x1 += y1; }
+__global__ void __launch_bounds__(kScanGroup) k_scan_mid(const uint32_t* cnt, uint32_t* pre,
+                                                        uint32_t* grp, uint32_t ncell_arg,
+                                                        const uint32_t* ncell_dev) {
+  __shared__ uint32_t sh[2][kScanGroup / 64 + 1];
+  const uint32_t nb = scan_tiles(scan_cells(ncell_arg, ncell_dev));
+  const uint32_t ng = (nb + kScanGroup - 1) / kScanGroup;
+  for (uint32_t g = blockIdx.x; g < ng; g += gridDim.x) {
+    const uint32_t t = g * kScanGroup + threadIdx.x;
+    const uint32_t v0 = t < nb ? cnt[2 * t] : 0u, v1 = t < nb ? cnt[2 * t + 1] : 0u;
+    uint32_t s0, s1;
+    const uint32_t e0 = block_exclusive_scan<kScanGroup>(v0, sh[0], &s0);
+    const uint32_t e1 = block_exclusive_scan<kScanGroup>(v1, sh[1], &s1);
+    if (t < nb) { pre[2 * t] = e0; pre[2 * t + 1] = e1; }
+    if (threadIdx.x == 0) { grp[2 * g] = s0; grp[2 * g + 1] = s1; }
   }
-  if (lane == 63) { sh[0][wid] = x0; sh[1][wid] = x1; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t a0 = 0, a1 = 0;
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t t0 = sh[0][i], t1 = sh[1][i];
-      sh[0][i] = a0; sh[1][i] = a1; a0 += t0; a1 += t1;
-    }
-    sh[0][16] = a0; sh[1][16] = a1;
-  }
-  __syncthreads();
-  uint32_t e0 = sh[0][wid] + x0 - s0, e1 = sh[1][wid] + x1 - s1;
-  for (int j = 0; j < per; ++j) {
-    if (b0 + j < nb) {
-      const uint32_t t0 = blocksums[2 * (b0 + j)], t1 = blocksums[2 * (b0 + j) + 1];
-      blocksums[2 * (b0 + j)] = e0;
-      blocksums[2 * (b0 + j) + 1] = e1;
-      e0 += t0; e1 += t1;
-    }
-  }
-  if (threadIdx.x == 0) { blocksums[2 * nb] = sh[0][16]; blocksums[2 * nb + 1] = sh[1][16]; }
+}
+
+__global__ void __launch_bounds__(kScanGroup) k_scan_top(uint32_t* grp, uint32_t ncell_arg,
+                                                        const uint32_t* ncell_dev) {
+  // exclusive scan of the ng <= 1024 group totals; grp[2 ng ..] = grand totals
+  __shared__ uint32_t sh[2][kScanGroup / 64 + 1];
+  const uint32_t nb = scan_tiles(scan_cells(ncell_arg, ncell_dev));
+  const uint32_t ng = (nb + kScanGroup - 1) / kScanGroup;
+  const uint32_t g = threadIdx.x;
+  const uint32_t v0 = g < ng ? grp[2 * g] : 0u, v1 = g < ng ? grp[2 * g + 1] : 0u;
+  uint32_t s0, s1;
+  const uint32_t e0 = block_exclusive_scan<kScanGroup>(v0, sh[0], &s0);
+  const uint32_t e1 = block_exclusive_scan<kScanGroup>(v1, sh[1], &s1);
+  if (g < ng) { grp[2 * g] = e0; grp[2 * g + 1] = e1; }
+  if (threadIdx.x == 0) { grp[2 * ng] = s0; grp[2 * ng + 1] = s1; }
 }
 
 __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* cellacc,
                                                      uint32_t ncell_arg, const uint32_t* ncell_dev,
-                                                     const uint32_t* blocksums, uint32_t* start,
+                                                     const uint32_t* cnt, const uint32_t* pre,
+                                                     const uint32_t* grp, uint32_t* start,
                                                      uint32_t* occ, Counters* ctr, int dest) {
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
   const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
-  const uint32_t nb = (ncell + kScanTile - 1) / kScanTile;
+  const uint32_t nb = scan_tiles(ncell);
   for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    if (cnt[2 * t] == 0u) continue;  // empty tile: no start entries, no occupied cells
     const uint32_t c0 = t * kScanTile + threadIdx.x * kScanPer;
     uint32_t n[kScanPer];
-    uint32_t cnt = 0, oc = 0;
+    uint32_t k = 0, oc = 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
       const uint32_t c = c0 + j;
       n[j] = c < ncell ? (uint32_t)(cellacc[c] >> 32) : 0u;
-      cnt += n[j];
+      k += n[j];
       oc += n[j] ? 1u : 0u;
     }
+    const uint32_t g = t / kScanGroup;
     uint32_t t0, t1;
-    uint32_t p0 = block_exclusive_scan(cnt, sh[0], &t0) + blocksums[2 * t];
-    uint32_t p1 = block_exclusive_scan(oc, sh[1], &t1) + blocksums[2 * t + 1];
+    uint32_t p0 = block_exclusive_scan<kBlock>(k, sh[0], &t0) + pre[2 * t] + grp[2 * g];
+    uint32_t p1 = block_exclusive_scan<kBlock>(oc, sh[1], &t1) + pre[2 * t + 1] + grp[2 * g + 1];
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      const uint32_t c = c0 + j;
-      if (c < ncell) {
-        start[c] = p0;
-        if (n[j]) occ[p1++] = c;
+      if (n[j]) {
+        start[c0 + j] = p0;
+        occ[p1++] = c0 + j;
         p0 += n[j];
       }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const uint32_t total = blocksums[2 * nb], tocc = blocksums[2 * nb + 1];
+    const uint32_t ng = (nb + kScanGroup - 1) / kScanGroup;
+    const uint32_t total = grp[2 * ng], tocc = grp[2 * ng + 1];
     start[ncell] = total;
+    ctr->sorted = total;
     ctr->n_occ = tocc;
     ctr->n[dest] = total;
     ctr->n_work = 0;
@@ -487,16 +504,16 @@ hipError_t launch_push_uniform(itokmc_ctx* ctx, const StepConst& k) {
   const int g = particle_grid(ctx);
   if (fp64(ctx))
     k_push_uniform<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
-                                                      ctx->cellacc, k);
+                                                      ctx->cellacc, ctx->tiles, k);
   else
     k_push_uniform<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
-                                                     ctx->cellacc, k);
+                                                     ctx->cellacc, ctx->tiles, k);
   return hipGetLastError();
 }
 
 hipError_t launch_count(itokmc_ctx* ctx) {
   k_count<<<particle_grid(ctx), kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
-                                                     ctx->cellacc, (uint32_t)ctx->cap);
+                                                     ctx->cellacc, ctx->tiles, (uint32_t)ctx->cap);
   return hipGetLastError();
 }
 
@@ -505,30 +522,40 @@ hipError_t launch_photons(itokmc_ctx* ctx, const StepConst& k) {
   const int g = grid_for(ctx->ncell, kBlock, 16384);
   if (fp64(ctx))
     k_photons<double><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
-                                                 ctx->cellacc, ctx->ngamma, ctx->nplus, k,
+                                                 ctx->cellacc, ctx->tiles, ctx->ngamma, ctx->nplus, k,
                                                  ctx->d.n_new, ctx->c.photon_l1, ctx->c.photon_l2);
   else
     k_photons<float><<<g, kBlock, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur,
-                                                ctx->cellacc, ctx->ngamma, ctx->nplus, k,
+                                                ctx->cellacc, ctx->tiles, ctx->ngamma, ctx->nplus, k,
                                                 ctx->d.n_new, ctx->c.photon_l1, ctx->c.photon_l2);
   return hipGetLastError();
 }
 
+size_t scan_scratch_words(uint64_t ncell) {
+  const uint64_t nb = (ncell + kScanTile - 1) / kScanTile + 1;
+  const uint64_t ng = (nb + kScanGroup - 1) / kScanGroup + 1;
+  return (size_t)(4 * nb + 2 * ng + 2);
+}
+
 hipError_t launch_scan_raw(const unsigned long long* cellacc, uint32_t max_cells,
-                           const uint32_t* ncell_dev, uint32_t* blocksums, uint32_t* start,
-                           uint32_t* occ, Counters* ctr, int dest, hipStream_t s) {
-  uint32_t nb = (max_cells + kScanTile - 1) / kScanTile;
-  if (nb < 1) nb = 1;
-  if (ncell_dev && nb > 4096) nb = 4096;  // tiles beyond the grid are looped over
-  k_scan_reduce<<<nb, kBlock, 0, s>>>(cellacc, max_cells, ncell_dev, blocksums);
-  k_scan_top<<<1, 1024, 0, s>>>(blocksums, max_cells, ncell_dev);
-  k_scan_down<<<nb, kBlock, 0, s>>>(cellacc, max_cells, ncell_dev, blocksums, start, occ, ctr, dest);
+                           const uint32_t* ncell_dev, uint8_t* tiles, uint32_t* scratch,
+                           uint32_t* start, uint32_t* occ, Counters* ctr, int dest, hipStream_t s) {
+  const uint32_t nb = (max_cells + kScanTile - 1) / kScanTile;
+  uint32_t* cnt = scratch;
+  uint32_t* pre = scratch + 2 * (size_t)(nb + 1);
+  uint32_t* grp = scratch + 4 * (size_t)(nb + 1);
+  const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(nb, 8192));  // tiles are looped over
+  const uint32_t ng = std::max<uint32_t>(1, (nb + kScanGroup - 1) / kScanGroup);
+  k_scan_reduce<<<gt, kBlock, 0, s>>>(cellacc, max_cells, ncell_dev, tiles, cnt);
+  k_scan_mid<<<std::min<uint32_t>(ng, 1024), kScanGroup, 0, s>>>(cnt, pre, grp, max_cells, ncell_dev);
+  k_scan_top<<<1, kScanGroup, 0, s>>>(grp, max_cells, ncell_dev);
+  k_scan_down<<<gt, kBlock, 0, s>>>(cellacc, max_cells, ncell_dev, cnt, pre, grp, start, occ, ctr, dest);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(itokmc_ctx* ctx) {
-  return launch_scan_raw(ctx->cellacc, ctx->ncell, nullptr, ctx->blocksums, ctx->start, ctx->occ,
-                         ctx->ctr, 1 - ctx->cur, ctx->s);
+  return launch_scan_raw(ctx->cellacc, ctx->ncell, nullptr, ctx->tiles, ctx->blocksums, ctx->start,
+                         ctx->occ, ctx->ctr, 1 - ctx->cur, ctx->s);
 }
 
 hipError_t launch_scatter_raw(Bank a, Bank b, Counters* ctr, int which, const uint32_t* start,

@@ -30,6 +30,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning",
            "itokmc_ensemble_arena_bytes", "itokmc_ensemble_create", "itokmc_ensemble_admit",
            "itokmc_ensemble_step", "itokmc_ensemble_poll", "itokmc_ensemble_result",
+           "itokmc_ensemble_results",
            "itokmc_ensemble_get_particles", "itokmc_ensemble_get_counts",
            "itokmc_ensemble_release", "itokmc_ensemble_info", "itokmc_ensemble_set_tuning",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
@@ -174,6 +175,7 @@ def lib():
         L.itokmc_ensemble_step.argtypes = [P, U32]
         L.itokmc_ensemble_poll.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.itokmc_ensemble_result.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Diag)]
+        L.itokmc_ensemble_results.argtypes = [P, P, ctypes.c_int32, P]
         L.itokmc_ensemble_get_particles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(U64), P, P,
                                                     P, P]
         L.itokmc_ensemble_get_counts.argtypes = [P, ctypes.c_int32, I32, P]
@@ -507,6 +509,17 @@ class Ensemble:
         d = Diag()
         self._check(lib().itokmc_ensemble_result(self.h, slot, ctypes.byref(d)))
         return d.as_dict()
+
+    def results(self, slots):
+        """Diagnostics of several resident realizations with one pass over the pool."""
+        slots = list(slots)
+        if not slots:
+            return []
+        arr = (ctypes.c_int32 * len(slots))(*slots)
+        out = (Diag * len(slots))()
+        self._check(lib().itokmc_ensemble_results(self.h, ctypes.cast(arr, ctypes.c_void_p),
+                                                  len(slots), ctypes.cast(out, ctypes.c_void_p)))
+        return [d.as_dict() for d in out]
 
     def particles(self, slot):
         n = ctypes.c_uint64()

@@ -62,13 +62,18 @@ def run_plain_one(cfg, device="cuda:0", stream=None, keep_particles=False, cance
         sim.close()
 
 
-def run_plain(cfgs, device="cuda:0"):
-    """Plain per-realization form: each realization alone, one after another."""
+def run_plain(cfgs, device="cuda:0", log=None):
+    """Plain per-realization form: each realization alone, one after another.
+    log: optional callable receiving a progress line now and then."""
     import torch
     dev = torch.device(device)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    results = [run_plain_one(c, device)[0] for c in cfgs]
+    results = []
+    for i, c in enumerate(cfgs):
+        results.append(run_plain_one(c, device)[0])
+        if log and (i + 1) % 32 == 0:
+            log(f"plain form: {i + 1}/{len(cfgs)} realizations, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize(dev)
     sec = time.perf_counter() - t0
     return dict(seconds=sec, results=results,
@@ -83,35 +88,33 @@ def ensemble_for(cfgs, max_slots=None, device="cuda:0"):
                            precision=cfgs[0].get("precision", "fp32"), device=device)
 
 
-def run_batched(cfgs, ens=None, steps_per_poll=4, device="cuda:0"):
-    """Batched form: admit every realization, step the ensemble until all are done."""
+def run_batched(cfgs, ens=None, steps_per_poll=2, device="cuda:0"):
+    """Batched form: admit every realization, step the ensemble, and collect and
+    release realizations as they finish (their particles leave the pool at the next
+    step) until all are done."""
     import torch
     dev = torch.device(device)
     ens = ens or ensemble_for(cfgs, device=device)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    slot_of = {}
     for i, c in enumerate(cfgs):
-        s = ens.admit(c, tag=i)
-        if s is None:
+        if ens.admit(c, tag=i) is None:
             raise RuntimeError("ensemble pools too small for the batch")
-        slot_of[i] = s
-    done = {}
-    while len(done) < len(cfgs):
+    results = [None] * len(cfgs)
+    left = len(cfgs)
+    while left:
         ens.step(steps_per_poll)
-        for slot, state, tag, steps in ens.poll():
-            done[tag] = (slot, state, steps)
+        events = ens.poll()
+        if events:
+            diags = ens.results([e[0] for e in events])
+            for (slot, state, tag, steps), d in zip(events, diags):
+                d["state"] = state
+                results[tag] = d
+                ens.release(slot)
+            left -= len(events)
     torch.cuda.synchronize(dev)
     sec = time.perf_counter() - t0
-    results = []
-    for i in range(len(cfgs)):
-        slot, state, steps = done[i]
-        r = ens.result(slot)
-        r["state"] = state
-        results.append(r)
-    for i in range(len(cfgs)):
-        ens.release(done[i][0])
-    ens.step(1)  # drop the released realizations' particles
+    ens.step(1)  # drop the last released realizations' particles
     return dict(seconds=sec, results=results, ensemble=ens,
                 particle_steps=sum(r["particle_steps"] for r in results))
 
@@ -192,9 +195,10 @@ class Server:
             errors.append(repr(e))
 
     # -- main loop ----------------------------------------------------------------------
-    def run(self, trace, drain_limit_s=None, steps_per_poll=1):
+    def run(self, trace, drain_limit_s=None, steps_per_poll=1, log=None):
         """Serve a request trace [(arrival_s, id, cfg)] in real time.  Returns a summary
-        and the per-request records (arrival, admission and finish times in s)."""
+        and the per-request records (arrival, admission and finish times in s).
+        log: optional callable receiving a progress line every 10 s."""
         torch = self.torch
         ens = self.ens
         results = {}
@@ -214,8 +218,13 @@ class Server:
         batched_steps = 0
         max_active = 0
         self.admission_waits = 0
+        next_log = 10.0
         while True:
             now = time.perf_counter() - t0
+            if log and now >= next_log:
+                next_log += 10.0
+                log(f"served: t={now:.0f} s arrived {i}/{len(trace)} resident {len(active)} "
+                    f"queued {len(pending)} done {len(results)}")
             while i < len(trace) and trace[i][0] <= now:
                 item = trace[i]
                 i += 1
@@ -245,9 +254,9 @@ class Server:
                 batched_steps += steps_per_poll
                 events = ens.poll()
                 tf = time.perf_counter() - t0
-                for slot, state, tag, steps in events:
+                diags = ens.results([e[0] for e in events]) if events else []
+                for (slot, state, tag, steps), d in zip(events, diags):
                     rid, t_arr, t_adm = active.pop(slot)
-                    d = ens.result(slot)
                     parts = ens.particles(slot) if rid in self.keep else None
                     ens.release(slot)
                     results[rid] = dict(kind="batched", arrival=t_arr, admitted=t_adm,
@@ -263,11 +272,15 @@ class Server:
         for _ in workers:
             pq.put(None)
         deadline = None if drain_limit_s is None else t0 + end_arrivals + drain_limit_s
+        last = time.perf_counter()
         for w in workers:
             while w.is_alive():
                 w.join(0.1)
                 if deadline is not None and time.perf_counter() > deadline:
                     self._cancel.set()
+                if log and time.perf_counter() - last > 10.0:
+                    last = time.perf_counter()
+                    log(f"served: draining self-consistent lane, done {len(results)}")
         torch.cuda.synchronize(self.device)
         if errors:
             raise RuntimeError("self-consistent worker failed: " + "; ".join(errors))
@@ -305,7 +318,7 @@ class Server:
                     ensemble_arena_gb=self.ens.arena_bytes / 1e9)
 
 
-def serve_plain(trace, time_limit_s, device="cuda:0", keep=()):
+def serve_plain(trace, time_limit_s, device="cuda:0", keep=(), log=None):
     """First-come first-served, one request at a time in a single context; stops
     starting new requests after time_limit_s.  Returns (summary, records)."""
     import torch
@@ -314,10 +327,14 @@ def serve_plain(trace, time_limit_s, device="cuda:0", keep=()):
     t0 = time.perf_counter()
     results = {}
     psteps = 0
+    next_log = 10.0
     for t_arr, rid, cfg in trace:
         now = time.perf_counter() - t0
         if now > time_limit_s:
             break
+        if log and now >= next_log:
+            next_log += 10.0
+            log(f"plain serving: t={now:.0f} s done {len(results)}")
         if t_arr > now:
             time.sleep(t_arr - now)
         t_adm = time.perf_counter() - t0
