@@ -20,18 +20,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per live particle of each particle phase (single-precision state):
-#   push / field_push: read cell 4 + offsets 12 + id 8 + weight 4,
-#                      write cell 4 + offsets 12 + rank 4
-#   deposit: read cell 4 + offsets 12 + id 8 + weight 4
-#   scatter: read cell 4 + rank 4 + offsets 12 + weight 4 + id 8, write 28
-BYTES_PER_PARTICLE = {"push": 48, "field_push": 48, "deposit": 28, "scatter": 60}
-# Algorithmic bytes per fine cell of one refinement cycle of the field solve
-# (single precision): 4 red-black sweeps reading u, eps, f and writing u (96), residual
-# and restriction (13), prolongation (8.5), double-precision residual reading phi, b,
-# eps and writing f (24), potential update (20), correction reset (4); coarser levels
-# add 1/7.
-BYTES_PER_CELL_CYCLE = (96 + 13 + 8.5 + 24 + 20 + 4) * 8.0 / 7.0
+# Single-kernel phases timed with HIP events (library profiling mode), the kernel each
+# one is, and its algorithmic HBM bytes per unit (S = 4 in single, 8 in double precision):
+#   push / field_push (per live particle): read cell 4 + offsets 3S + id 8 + weight 4,
+#                      write cell 4 + offsets 3S + rank 4
+#   deposit (per particle): read cell 4 + offsets 3S + id 8 + weight 4
+#   scatter (per particle): read cell 4 + rank 4 + offsets 3S + weight 4 + id 8, write
+#                      cell 4 + offsets 3S + weight 4 + id 8
+#   couple (per particle of a queued cell, merging on): read and write cell, offsets,
+#                      weight and id
+#   smooth_fine (per finest-level cell and launch of one colour): read u and eps of every
+#                      cell, f of the cells of the colour, write u of those cells: 3S
+KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k_field_deposit_lds",
+           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_rb<fine>"}
+
+
+def bytes_per_unit(phase, S):
+    return {"push": 24 + 6 * S, "field_push": 24 + 6 * S, "deposit": 16 + 3 * S,
+            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 3 * S}[phase]
 
 
 def parse():
@@ -251,10 +257,9 @@ def main():
     sim.seed()
     sim.step(args.warmup)
     torch.cuda.synchronize(dev)
-    d0 = sim.diagnostics()
-    sim.set_profiling(True)
-    sim.phase_times(reset=True)
     stream = sim.stream
+    # timed window: K steps, HIP events on the library's stream
+    d0 = sim.diagnostics()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize(dev)
@@ -263,37 +268,51 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize(dev)
     ms = ev0.elapsed_time(ev1)
-    phases = sim.phase_times(reset=True)
-    sim.set_profiling(False)
     d1 = sim.diagnostics(check=False)
     psteps = d1["particle_steps"] - d0["particle_steps"]
     value = psteps / (ms / 1e3)
+    # profiled window: the next K steps with HIP events around every kernel phase (and
+    # around each finest-level smoother launch, whose cycles then run without the graph)
+    sim.set_profiling(True)
+    sim.phase_times(reset=True)
+    ev0.record(stream)
+    rc_p = sim.step_rc(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
+    ms_p = ev0.elapsed_time(ev1)
+    phases = sim.phase_times(reset=True)
+    sim.set_profiling(False)
+    d2 = sim.diagnostics(check=False)
+    psteps_p = d2["particle_steps"] - d1["particle_steps"]
 
-    # dominant phase and its roofline (algorithmic bytes per launch / average launch)
+    # roofline of the dominant kernel: algorithmic bytes per launch / average launch
     ncell = 1
     for v in cfg["grid"]:
         ncell *= v
+    S = 8 if cfg.get("precision") == "fp64" else 4
     cycles = d1.get("solver_cycles_total", 0) - d0.get("solver_cycles_total", 0)
     roofs = {}
-    for ph, (tot_ms, launches) in phases.items():
+    psteps_r = psteps_p
+    for ph, kname in KERNELS.items():
+        tot_ms, launches = phases.get(ph, (0.0, 0))
         if not launches or tot_ms <= 0:
             continue
-        if ph in BYTES_PER_PARTICLE:
-            total_bytes = BYTES_PER_PARTICLE[ph] * psteps
-        elif ph == "solve" and cycles:
-            total_bytes = BYTES_PER_CELL_CYCLE * ncell * cycles
+        if ph == "smooth_fine":
+            units = ncell * launches
+        elif ph == "couple":
+            if not cfg.get("n_ppc"):
+                continue  # without merging only some cells are visited
+            units = psteps_r
         else:
-            continue
-        per_launch = total_bytes / launches
+            units = psteps_r
+        per_launch = bytes_per_unit(ph, S) * units / launches
         achieved = per_launch / (tot_ms / launches / 1e3) / 1e9
         roofs[ph] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": ph, "avg_launch_ms": round(tot_ms / launches, 4),
-                     "bytes_per_launch": int(per_launch)}
-    dom = max(phases, key=lambda p: phases[p][0])
-    roof = roofs.get(dom)
-    if roof is None and roofs:
-        roof = max(roofs.values(), key=lambda r: phases[r["kernel"]][0])
+                     "kernel": kname, "avg_launch_ms": round(tot_ms / launches, 4),
+                     "launches": launches, "bytes_per_launch": int(per_launch),
+                     "total_ms": round(tot_ms, 3)}
+    roof = max(roofs.values(), key=lambda r: r["total_ms"]) if roofs else None
     out = {
         "metric": "particle-steps/s (push+sort+deposit+KMC)",
         "value": value,
@@ -311,10 +330,12 @@ def main():
                    "particles_start": d0["n_particles"], "particles_end": d1["n_particles"],
                    "weight_end": d1["weight"], "field": cfg.get("field"),
                    "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": rc},
+        "profiled_window": {"ms_per_step": ms_p / args.steps, "status": rc_p,
+                            "particle_steps": psteps_p},
         "phase_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
         "solver_cycles_per_step": cycles / args.steps,
         "roofline": roof,
-        "roofline_by_phase": roofs,
+        "roofline_by_kernel": roofs,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

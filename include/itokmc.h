@@ -191,9 +191,12 @@ int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
 
 /* Per-phase timing with HIP events recorded around each kernel phase on the
  * context's stream (off by default).  Phases: 0 push, 1 photons, 2 bin scan,
- * 3 scatter, 4 KMC, 5 coupling/merge, 6 charge deposit, 7 field solve, 8 field push,
- * 9 recount.  phase_times synchronises, writes accumulated milliseconds and launch
- * counts for the first n phases, and clears them if reset is nonzero. */
+ * 3 scatter, 4 KMC, 5 coupling kernel, 6 charge-deposit kernel, 7 field solve (with
+ * the field from the potential), 8 field push, 9 recount, 10 larger merge tiers,
+ * 11 deposit clearing and right-hand side, 12 finest-level smoother launches (inside
+ * the solve; one count per launch).  phase_times synchronises, writes accumulated
+ * milliseconds and launch counts for the first n phases, and clears them if reset is
+ * nonzero. */
 int itokmc_set_profiling(itokmc_ctx* ctx, int on);
 int itokmc_phase_times(itokmc_ctx* ctx, double* ms, uint64_t* calls, int n, int reset);
 

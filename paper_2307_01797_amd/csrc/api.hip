@@ -106,7 +106,7 @@ StepConst make_const(const itokmc_ctx* ctx, double dt) {
 // ---- arena layout ------------------------------------------------------------------
 
 struct Layout {
-  size_t off[32];
+  size_t off[40];
   size_t total;
 };
 
@@ -161,7 +161,10 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(field_bytes(d));                // 26 field data
   put(nc * 4);                        // 27 cbase
   put(nc * 4);                        // 28 big
-  put(nc / 2048 + 2);                 // 29 scan tile flags
+  put((nc / 2048 + 2) * 4);           // 29 scan tile flags
+  put(nc * 4);                        // 30 cells for the full KMC pass
+  put(d->field_mode == ITOKMC_FIELD_POISSON ? nc * 24 : 64);  // 31 rates for the full pass
+  put(nc * 4);                        // 32 huge (large merge list)
   L->total = o;
 }
 
@@ -238,7 +241,10 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->field = a + L.off[26];
   ctx->cbase = (uint32_t*)(a + L.off[27]);
   ctx->big = (uint32_t*)(a + L.off[28]);
-  ctx->tiles = (uint8_t*)(a + L.off[29]);
+  ctx->tiles = (uint32_t*)(a + L.off[29]);
+  ctx->heavy = (uint32_t*)(a + L.off[30]);
+  ctx->rates = (double*)(a + L.off[31]);
+  ctx->huge = (uint32_t*)(a + L.off[32]);
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);
@@ -246,7 +252,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   if (e == hipSuccess) e = hipMemsetAsync(ctx->nminus, 0, nb * 4, ctx->s);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->ngamma, 0, nb * 4, ctx->s);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->ctr, 0, sizeof(Counters), ctx->s);
-  if (e == hipSuccess) e = hipMemsetAsync(ctx->tiles, 0, nb / 2048 + 2, ctx->s);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->tiles, 0, (nb / 2048 + 2) * 4, ctx->s);
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_ctr, sizeof(Counters), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete ctx;
@@ -346,9 +352,8 @@ int itokmc_react(itokmc_ctx* ctx, double dt) {
   phase_begin(ctx, PH_KMC);
   if (!rc) rc = check_hip(ctx, launch_kmc_step(ctx, k, fr), "kmc");
   phase_end(ctx, PH_KMC);
-  phase_begin(ctx, PH_COUPLE);
+  phase_begin(ctx, PH_COUPLE);  // ended inside: coupling kernel, then the merge tiers
   if (!rc) rc = check_hip(ctx, launch_couple(ctx, k), "couple");
-  phase_end(ctx, PH_COUPLE);
   if (rc) return rc;
   ctx->cur = 1 - ctx->cur;
   ctx->step += 1;
@@ -577,6 +582,7 @@ int itokmc_set_profiling(itokmc_ctx* ctx, int on) {
   if (!ctx) return ITOKMC_EINVAL;
   phase_collect(ctx);
   ctx->profiling = on != 0;
+  if (ctx->d.field_mode == ITOKMC_FIELD_POISSON) field_set_timing(ctx, ctx->profiling);
   return ITOKMC_OK;
 }
 

@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
     created += M;
     if (n_ppc > 0) {
       __syncthreads();  // removal and product stores visible before the merge gathers them
-      const int r = merge_cell<T, kMergeSmall>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
+      const int r = merge_cell<T, kMergeTiny>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
       if (r == 2 && lane == 0) big[atomicAdd(&ctr->n_big, 1u)] = j;
     }
   }
@@ -62,24 +62,30 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
   }
 }
 
-// Cells whose particles exceed the small staging area, merged with the large one.
-template <typename T>
-__global__ void __launch_bounds__(64) k_merge_big(Bank b, Counters* ctr, int which, StepConst K,
-                                                 const uint32_t* big, const uint32_t* occ,
-                                                 const uint32_t* start, const int32_t* dN,
-                                                 const uint32_t* cbase, int n_new, int n_ppc) {
-  const uint32_t nbig = ctr->n_big, n_occ = ctr->n_occ, sorted = ctr->sorted;
+// Cells whose particles exceed a staging area, merged with the next larger one:
+// tier CAP reads its cells from list `in` (count *n_in); cells exceeding CAP go to
+// list `out` (count *n_out) or, from the largest tier, are left unmerged and counted.
+template <typename T, int CAP>
+__global__ void __launch_bounds__(64) k_merge_tier(Bank b, Counters* ctr, int which, StepConst K,
+                                                  const uint32_t* in, const uint32_t* n_in,
+                                                  uint32_t* out, uint32_t* n_out,
+                                                  const uint32_t* occ, const uint32_t* start,
+                                                  const int32_t* dN, const uint32_t* cbase,
+                                                  int n_new, int n_ppc) {
+  const uint32_t nin = *n_in, n_occ = ctr->n_occ, sorted = ctr->sorted;
   uint64_t merged = 0;
-  for (uint32_t t = blockIdx.x; t < nbig; t += gridDim.x) {
-    const uint32_t j = big[t];
+  for (uint32_t t = blockIdx.x; t < nin; t += gridDim.x) {
+    const uint32_t j = in[t];
     const uint32_t c = occ[j];
     const int32_t d = dN[j];
     const uint32_t M = d > 0 ? ((uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new) : 0u;
     const uint32_t base = M ? cbase[j] : 0u;
     const uint32_t e = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
-    const int r = merge_cell<T, MergeBig<T>::value>(b, ctr, which, K, c, start[c], e, base, M, n_ppc,
-                                                     &merged);
-    if (r == 2 && lane_id() == 0) atomicAdd(&ctr->merge_skipped, 1u);
+    const int r = merge_cell<T, CAP>(b, ctr, which, K, c, start[c], e, base, M, n_ppc, &merged);
+    if (r == 2 && lane_id() == 0) {
+      if (out) out[atomicAdd(n_out, 1u)] = j;
+      else atomicAdd(&ctr->merge_skipped, 1u);
+    }
   }
   if (lane_id() == 0 && merged) atomicAdd(&ctr->merged, (unsigned long long)merged);
 }
@@ -100,19 +106,28 @@ hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k) {
         ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN, ctx->cbase,
         ctx->d.n_new, ctx->d.n_ppc, ctx->big);
   hipError_t e = hipGetLastError();
+  phase_end(ctx, PH_COUPLE);
   if (e != hipSuccess || ctx->d.n_ppc == 0) return e;
-  const int gb = 1024;
+  phase_begin(ctx, PH_MERGE);  // the larger merge tiers
+  Counters* C = ctx->ctr;
   if (f64) {
-    const size_t lds = merge_lds_bytes_c<double, MergeBig<double>::value>();
-    k_merge_big<double><<<gb, 64, lds, ctx->s>>>(ctx->bank[dest], ctx->ctr, dest, k, ctx->big, ctx->occ,
-                                                  ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
-                                                  ctx->d.n_ppc);
+    k_merge_tier<double, kMergeSmall><<<2048, 64, merge_lds_bytes_c<double, kMergeSmall>(), ctx->s>>>(
+        ctx->bank[dest], C, dest, k, ctx->big, &C->n_big, ctx->huge, &C->n_huge, ctx->occ, ctx->start,
+        ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
+    k_merge_tier<double, MergeBig<double>::value>
+        <<<1024, 64, merge_lds_bytes_c<double, MergeBig<double>::value>(), ctx->s>>>(
+            ctx->bank[dest], C, dest, k, ctx->huge, &C->n_huge, nullptr, nullptr, ctx->occ, ctx->start,
+            ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
   } else {
-    const size_t lds = merge_lds_bytes_c<float, MergeBig<float>::value>();
-    k_merge_big<float><<<gb, 64, lds, ctx->s>>>(ctx->bank[dest], ctx->ctr, dest, k, ctx->big, ctx->occ,
-                                                 ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
-                                                 ctx->d.n_ppc);
+    k_merge_tier<float, kMergeSmall><<<2048, 64, merge_lds_bytes_c<float, kMergeSmall>(), ctx->s>>>(
+        ctx->bank[dest], C, dest, k, ctx->big, &C->n_big, ctx->huge, &C->n_huge, ctx->occ, ctx->start,
+        ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
+    k_merge_tier<float, MergeBig<float>::value>
+        <<<1024, 64, merge_lds_bytes_c<float, MergeBig<float>::value>(), ctx->s>>>(
+            ctx->bank[dest], C, dest, k, ctx->huge, &C->n_huge, nullptr, nullptr, ctx->occ, ctx->start,
+            ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
   }
+  phase_end(ctx, PH_MERGE);
   return hipGetLastError();
 }
 

@@ -127,8 +127,12 @@ __device__ __forceinline__ uint64_t run_add(unsigned long long* acc, uint32_t ke
 // receives its first particle of the step; the counting-sort scan visits flagged tiles
 // only (and clears the flags).
 constexpr int kTileShift = 11;
-__device__ __forceinline__ void mark_tile(uint8_t* tiles, uint32_t key, uint64_t old) {
-  if (key != kInvalidCell && (old >> 32) == 0) tiles[key >> kTileShift] = 1;
+__device__ __forceinline__ void mark_tile(uint32_t* tiles, uint32_t key, uint64_t old) {
+  if (key != kInvalidCell && (old >> 32) == 0) {
+    uint32_t* f = tiles + (key >> kTileShift);
+    // device-coherent read: store only while the tile is still unflagged
+    if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) *f = 1u;
+  }
 }
 
 // Wave-wide sum (result valid in every lane).
@@ -141,6 +145,30 @@ __device__ __forceinline__ double wave_sumd(double v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
   return v;
+}
+
+// Append n items (per thread) to a counter with one atomic per workgroup; returns the
+// thread's first slot.  Every thread of the workgroup must call it (it synchronises);
+// sh: 18 words of LDS.
+__device__ __forceinline__ uint32_t block_append(uint32_t* counter, uint32_t n, uint32_t* sh) {
+  const int lane = lane_id(), wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  uint32_t x = n;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < nw; ++i) { const uint32_t t = sh[i]; sh[i] = acc; acc += t; }
+    sh[17] = acc ? atomicAdd(counter, acc) : 0u;
+  }
+  __syncthreads();
+  const uint32_t r = sh[17] + sh[wid] + x - n;
+  __syncthreads();
+  return r;
 }
 
 // Append n items (per lane) to a counter with one atomic per wave; returns the lane's

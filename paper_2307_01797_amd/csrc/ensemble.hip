@@ -184,20 +184,26 @@ __global__ void __launch_bounds__(256) e_seed_gaussian(Bank b, Counters* ctr, in
 // ---- the step ---------------------------------------------------------------------------
 
 // Push with fused NGP binning over the pool.  Particles of released slots are dropped,
-// particles of finished slots stay binned where they are.
+// particles of finished slots stay binned where they are.  A workgroup takes one
+// contiguous chunk of the bank (whose particles mostly share a realization), and each
+// thread keeps its realization's tallies in registers, flushing them when it moves to
+// another realization and, wave-aggregated, at the end.
 template <typename T>
 __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
-                                              unsigned long long* cellacc, uint8_t* tiles,
+                                              unsigned long long* cellacc, uint32_t* tiles,
                                               const SlotConst* sc,
                                               const int32_t* blk_slot, const uint32_t* blk_local,
                                               const uint32_t* map, unsigned long long* st,
                                               uint32_t ms, uint32_t cap) {
   const uint32_t n = min(ctr->n[which], cap);
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+  const uint32_t per = ((n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const uint32_t b0 = blockIdx.x * per, b1 = min(n, b0 + per);
+  uint32_t cur = kInvalidCell;
+  uint64_t live = 0, left = 0, outw = 0;
+  for (uint32_t base = b0; base < b1; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
-    uint32_t key = kInvalidCell, skey = kInvalidCell, w = 0;
-    uint64_t packed = 0;  // live (bits 0-7), left (8-15), outflow weight (16-63)
-    if (i < n) w = a.w[i];
+    uint32_t key = kInvalidCell, w = 0;
+    if (i < b1) w = a.w[i];
     if (w > 0) {
       const uint32_t g = a.cell[i];
       const int s = blk_slot[g >> kBlkShift];
@@ -207,7 +213,15 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
         key = g;
       } else {
         const SlotConst& S = sc[s];
-        skey = (uint32_t)s;
+        if ((uint32_t)s != cur) {
+          if (cur != kInvalidCell) {
+            if (live) atomicAdd(&st[S_LIVE * ms + cur], (unsigned long long)live);
+            if (left) atomicAdd(&st[S_LEFT * ms + cur], (unsigned long long)left);
+            if (outw) atomicAdd(&st[S_OUTW * ms + cur], (unsigned long long)outw);
+          }
+          cur = (uint32_t)s;
+          live = left = outw = 0;
+        }
         const uint32_t c = to_local(g, blk_local);
         T o[3] = {as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i]};
         int ci[3] = {(int)(c % (uint32_t)S.nx), (int)((c / (uint32_t)S.nx) % (uint32_t)S.ny),
@@ -215,6 +229,7 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
         const int lim[3] = {S.nx, S.ny, S.nz};
         const T drift[3] = {(T)S.drift[0], (T)S.drift[1], (T)S.drift[2]};
         const bool inside = push_uniform<T>(a.id[i], S.step, S.key, drift, (T)S.diff, lim, ci, o);
+        ++live;
         if (inside) {
           const uint32_t lc =
               (uint32_t)ci[0] + (uint32_t)S.nx * ((uint32_t)ci[1] + (uint32_t)S.ny * (uint32_t)ci[2]);
@@ -223,87 +238,137 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
           as<T>(a.ox)[i] = o[0];
           as<T>(a.oy)[i] = o[1];
           as<T>(a.oz)[i] = o[2];
-          packed = 1ull;
         } else {
           a.w[i] = 0;
-          packed = 1ull | (1ull << 8) | ((uint64_t)w << 16);
+          ++left;
+          outw += w;
         }
       }
     }
     const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
     mark_tile(tiles, key, old);
     if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
-    uint64_t tot;
-    if (run_total(skey, packed, &tot)) {
-      atomicAdd(&st[S_LIVE * ms + skey], (unsigned long long)(tot & 0xFFull));
-      const uint64_t left = (tot >> 8) & 0xFFull;
-      if (left) {
-        atomicAdd(&st[S_LEFT * ms + skey], (unsigned long long)left);
-        atomicAdd(&st[S_OUTW * ms + skey], (unsigned long long)(tot >> 16));
-      }
-    }
   }
+  uint64_t tot;
+  if (run_total(cur, live, &tot) && tot) atomicAdd(&st[S_LIVE * ms + cur], (unsigned long long)tot);
+  if (run_total(cur, left, &tot) && tot) atomicAdd(&st[S_LEFT * ms + cur], (unsigned long long)tot);
+  if (run_total(cur, outw, &tot) && tot) atomicAdd(&st[S_OUTW * ms + cur], (unsigned long long)tot);
 }
 
-// Per-cell KMC over the occupied pool cells; reserves product slots within each
-// realization's quota and queues cells for the coupling.
-__global__ void __launch_bounds__(256) e_kmc(Counters* ctr, const uint32_t* occ,
-                                            unsigned long long* cellacc, uint32_t* nplus,
-                                            uint32_t* nminus, int32_t* dN, uint32_t* work,
-                                            uint32_t* cbase, const SlotConst* sc,
-                                            const int32_t* blk_slot, const uint32_t* blk_local,
-                                            unsigned long long* st, uint32_t ms, int dest) {
-  const uint32_t n = ctr->n_occ;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const uint32_t j = base + threadIdx.x;
-    uint32_t skey = kInvalidCell, M = 0;
-    int64_t d = 0;
-    int64_t f[3] = {0, 0, 0};
-    if (j < n) {
-      const uint32_t g = occ[j];
-      const uint32_t Xe = (uint32_t)cellacc[g];
-      cellacc[g] = 0ull;
-      const int s = blk_slot[g >> kBlkShift];
-      if (s >= 0 && sc[s].state == ITOKMC_SLOT_ACTIVE) {
-        const SlotConst& S = sc[s];
-        skey = (uint32_t)s;
-        const uint32_t c = to_local(g, blk_local);
-        State X{(int64_t)Xe, (int64_t)nplus[g], (int64_t)nminus[g], 0};
-        const double k[3] = {S.k[0], S.k[1], S.k[2]};
-        CellStream cs;
-        cs.init(c, S.step, TAG_KMC, 0, S.key);
-        advance(S.kp, X, k, S.dt, cs, f);
-        nplus[g] = (uint32_t)X.p;
-        nminus[g] = (uint32_t)X.m;
-        d = X.e - (int64_t)Xe;
-        if (d > 0) M = d < (int64_t)S.n_new ? (uint32_t)d : S.n_new;
-      }
-    }
-    // quota: live particles kept by the push plus products reserved so far
-    const uint64_t before = run_add(st + S_PROD * ms, M ? skey : kInvalidCell, M);
-    if (M) {
-      const uint64_t kept = st[S_LIVE * ms + skey] - st[S_LEFT * ms + skey];
-      if (kept + before + M > (uint64_t)sc[skey].quota) {
-        M = 0;
-        d = 0;  // products dropped: the realization is capped and stops after this step
-        atomicOr(&st[S_CAPPED * ms + skey], 1ull);
-      }
-    }
-    if (j < n) dN[j] = (int32_t)d;
-    const bool queue = d != 0;
-    const uint32_t q = wave_append(&ctr->n_work, queue ? 1u : 0u);
-    if (queue) work[q] = j;
-    const uint32_t slot = wave_append(&ctr->n[dest], M);
-    if (M) cbase[j] = slot;
-    // per-slot tallies
-    uint64_t tot;
-    if (run_total(skey, (uint64_t)f[0], &tot) && tot) atomicAdd(&st[S_F0 * ms + skey], (unsigned long long)tot);
-    if (run_total(skey, (uint64_t)f[1], &tot) && tot) atomicAdd(&st[S_F1 * ms + skey], (unsigned long long)tot);
-    if (run_total(skey, (uint64_t)f[2], &tot) && tot) atomicAdd(&st[S_F2 * ms + skey], (unsigned long long)tot);
-    if (run_total(skey, (uint64_t)M, &tot) && tot) atomicAdd(&st[S_CREATED * ms + skey], (unsigned long long)tot);
-    if (run_total(skey, d < 0 ? (uint64_t)(-d) : 0ull, &tot) && tot)
-      atomicAdd(&st[S_REMOVED * ms + skey], (unsigned long long)tot);
+// Per-slot tallies of one thread, flushed to the slot's counters when the thread moves
+// to another slot and, wave-aggregated, at the end.
+struct SlotTally {
+  uint32_t slot = kInvalidCell;
+  uint64_t v[5] = {0, 0, 0, 0, 0};  // fires x3, created, removed weight
+  static constexpr int kField[5] = {S_F0, S_F1, S_F2, S_CREATED, S_REMOVED};
+  __device__ void flush(unsigned long long* st, uint32_t ms) {
+    if (slot != kInvalidCell)
+      for (int i = 0; i < 5; ++i)
+        if (v[i]) atomicAdd(&st[kField[i] * ms + slot], (unsigned long long)v[i]);
+    for (int i = 0; i < 5; ++i) v[i] = 0;
   }
+  __device__ void add(uint32_t s, const uint64_t x[5], unsigned long long* st, uint32_t ms) {
+    if (s != slot) { flush(st, ms); slot = s; }
+    for (int i = 0; i < 5; ++i) v[i] += x[i];
+  }
+  // all lanes call: one atomic per run of equal slots in the wavefront
+  __device__ void flush_wave(unsigned long long* st, uint32_t ms) {
+    for (int i = 0; i < 5; ++i) {
+      uint64_t tot;
+      if (run_total(slot, v[i], &tot) && tot) atomicAdd(&st[kField[i] * ms + slot], (unsigned long long)tot);
+      v[i] = 0;
+    }
+  }
+};
+
+// Per-cell KMC over the occupied pool cells; reserves product slots within each
+// realization's quota and queues cells for the coupling.  As in the single-context
+// step, a fast pass settles cells whose step is one SSA excursion and queues the rest,
+// untouched, for the full pass; a thread takes kEnsKmcPer cells between the
+// workgroup-aggregated appends.
+constexpr int kEnsKmcPer = 4;
+
+template <bool kFast>
+__global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
+    Counters* ctr, const uint32_t* occ, unsigned long long* cellacc, uint32_t* nplus,
+    uint32_t* nminus, int32_t* dN, uint32_t* work, uint32_t* cbase, uint32_t* heavy,
+    const SlotConst* sc, const int32_t* blk_slot, const uint32_t* blk_local,
+    unsigned long long* st, uint32_t ms, int dest) {
+  __shared__ uint32_t sh[18];
+  const uint32_t n = kFast ? ctr->n_occ : ctr->n_heavy;
+  const uint32_t span = blockDim.x * kEnsKmcPer;
+  SlotTally tally;
+  for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+    uint32_t js[kEnsKmcPer], Ms[kEnsKmcPer], fl[kEnsKmcPer];  // fl: 1 queue, 2 defer
+    uint32_t nq = 0, nd = 0, nm = 0;
+#pragma unroll
+    for (int r = 0; r < kEnsKmcPer; ++r) {
+      const uint32_t jj = base + (uint32_t)r * blockDim.x + threadIdx.x;
+      js[r] = 0; Ms[r] = 0; fl[r] = 0;
+      uint32_t skey = kInvalidCell, M = 0, j = 0;
+      int64_t d = 0;
+      int64_t f[3] = {0, 0, 0};
+      bool defer = false;
+      if (jj < n) {
+        j = kFast ? jj : heavy[jj];
+        const uint32_t g = occ[j];
+        const uint32_t Xe = (uint32_t)cellacc[g];
+        const int s = blk_slot[g >> kBlkShift];
+        if (s >= 0 && sc[s].state == ITOKMC_SLOT_ACTIVE) {
+          const SlotConst& S = sc[s];
+          const uint32_t c = to_local(g, blk_local);
+          State X{(int64_t)Xe, (int64_t)nplus[g], (int64_t)nminus[g], 0};
+          const double k[3] = {S.k[0], S.k[1], S.k[2]};
+          CellStream cs;
+          cs.init(c, S.step, TAG_KMC, 0, S.key);
+          if (kFast) defer = !advance_fast(S.kp, X, k, S.dt, cs, f);
+          else advance(S.kp, X, k, S.dt, cs, f);
+          if (!defer) {
+            skey = (uint32_t)s;
+            nplus[g] = (uint32_t)X.p;
+            nminus[g] = (uint32_t)X.m;
+            d = X.e - (int64_t)Xe;
+            if (d > 0) M = d < (int64_t)S.n_new ? (uint32_t)d : S.n_new;
+          }
+        }
+        if (!defer) cellacc[g] = 0ull;
+      }
+      // quota: live particles kept by the push plus products reserved so far
+      const uint64_t before = run_add(st + S_PROD * ms, M ? skey : kInvalidCell, M);
+      if (M) {
+        const uint64_t kept = st[S_LIVE * ms + skey] - st[S_LEFT * ms + skey];
+        if (kept + before + M > (uint64_t)sc[skey].quota) {
+          M = 0;
+          d = 0;  // products dropped: the realization is capped and stops after this step
+          atomicOr(&st[S_CAPPED * ms + skey], 1ull);
+        }
+      }
+      if (jj < n && !defer) {
+        dN[j] = (int32_t)d;
+        js[r] = j;
+        if (d != 0) { fl[r] = 1; ++nq; }
+        Ms[r] = M;
+        nm += M;
+        if (skey != kInvalidCell) {
+          const uint64_t x[5] = {(uint64_t)f[0], (uint64_t)f[1], (uint64_t)f[2], (uint64_t)M,
+                                 d < 0 ? (uint64_t)(-d) : 0ull};
+          tally.add(skey, x, st, ms);
+        }
+      } else if (defer) {
+        js[r] = j; fl[r] = 2; ++nd;
+      }
+    }
+    uint32_t hb = kFast ? block_append(&ctr->n_heavy, nd, sh) : 0u;
+    uint32_t qb = block_append(&ctr->n_work, nq, sh);
+    uint32_t mb = block_append(&ctr->n[dest], nm, sh);
+#pragma unroll
+    for (int r = 0; r < kEnsKmcPer; ++r) {
+      if (fl[r] == 2) heavy[hb++] = js[r];
+      if (fl[r] == 1) work[qb++] = js[r];
+      if (Ms[r]) { cbase[js[r]] = mb; mb += Ms[r]; }
+    }
+  }
+  tally.flush_wave(st, ms);
 }
 
 // Coupling of eq. w, one wavefront per queued cell (no merge in the ensemble).
@@ -493,7 +558,8 @@ struct itokmc_ens {
   int32_t* blk_slot = nullptr;
   uint32_t *blk_local = nullptr, *map = nullptr;
   unsigned long long* slot_red = nullptr;  // 4 per slot: count, weight (pool), n+, n-
-  uint8_t* tiles = nullptr;                // scan tile flags
+  uint32_t* tiles = nullptr;                // scan tile flags
+  uint32_t* heavy = nullptr;                // cells for the full KMC pass
   // host bookkeeping
   std::vector<SlotHost> slots;
   std::set<uint32_t> free_blocks, used_blocks;
@@ -578,7 +644,8 @@ void ens_layout(const itokmc_ens_desc* d, EnsLayout* L) {
   put(nblk * 4);                       // 30 block -> local block
   put(2 * nblk * 4);                   // 31 block maps
   put(ms * 4 * 8);                     // 32 per-slot result reductions
-  put(nc / 2048 + 2);                  // 33 scan tile flags
+  put((nc / 2048 + 2) * 4);            // 33 scan tile flags
+  put(nc * 4);                         // 34 cells for the full KMC pass
   L->total = o;
 }
 
@@ -611,12 +678,17 @@ hipError_t enqueue_step(itokmc_ens* e, int cur, hipStream_t s) {
   h = launch_scatter_raw(e->bank[cur], e->bank[dest], e->ctr, cur, e->start, e->cap, f64(e) ? 1 : 0,
                          std::max(1, (int)std::min<uint64_t>((uint64_t)kCUs * 8, (e->cap + 255) / 256)), s);
   if (h != hipSuccess) return h;
-  int gk = (int)std::min<uint64_t>((uint64_t)kCUs * 8, ((uint64_t)e->max_cells + e->tune.kmc_block - 1) /
-                                                           e->tune.kmc_block);
+  const uint64_t span = (uint64_t)e->tune.kmc_block * kEnsKmcPer;
+  int gk = (int)std::min<uint64_t>((uint64_t)kCUs * 16, ((uint64_t)e->max_cells + span - 1) / span);
   if (gk < 1) gk = 1;
-  e_kmc<<<gk, e->tune.kmc_block, 0, s>>>(e->ctr, e->occ, e->cellacc, e->nplus, e->nminus, e->dN,
-                                         e->work, e->cbase, e->sc, e->blk_slot, e->blk_local, e->st,
-                                         e->ms, dest);
+  e_kmc<true><<<gk, e->tune.kmc_block, 0, s>>>(e->ctr, e->occ, e->cellacc, e->nplus, e->nminus, e->dN,
+                                               e->work, e->cbase, e->heavy, e->sc, e->blk_slot,
+                                               e->blk_local, e->st, e->ms, dest);
+  h = hipGetLastError();
+  if (h != hipSuccess) return h;
+  e_kmc<false><<<kCUs * 4, 64, 0, s>>>(e->ctr, e->occ, e->cellacc, e->nplus, e->nminus, e->dN, e->work,
+                                       e->cbase, e->heavy, e->sc, e->blk_slot, e->blk_local, e->st,
+                                       e->ms, dest);
   h = hipGetLastError();
   if (h != hipSuccess) return h;
   const int gc = kCUs * e->tune.couple_per_cu;
@@ -751,12 +823,13 @@ int itokmc_ensemble_create(itokmc_ens** out, const itokmc_ens_desc* desc, void* 
   e->blk_local = (uint32_t*)(a + L.off[30]);
   e->map = (uint32_t*)(a + L.off[31]);
   e->slot_red = (unsigned long long*)(a + L.off[32]);
-  e->tiles = (uint8_t*)(a + L.off[33]);
+  e->tiles = (uint32_t*)(a + L.off[33]);
+  e->heavy = (uint32_t*)(a + L.off[34]);
   hipError_t h = hipSuccess;
   if (h == hipSuccess) h = hipMemsetAsync(e->cellacc, 0, (size_t)e->max_cells * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->ctr, 0, sizeof(Counters), e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->misc, 0, 64, e->s);
-  if (h == hipSuccess) h = hipMemsetAsync(e->tiles, 0, (size_t)e->max_cells / 2048 + 2, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->tiles, 0, ((size_t)e->max_cells / 2048 + 2) * 4, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->sc, 0, (size_t)e->ms * sizeof(SlotConst), e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->st, 0, (size_t)e->ms * S_NUM * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->stat2, 0, (size_t)e->ms * 8, e->s);

@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
 // then binning exactly as the uniform push.
 template <typename T>
 __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int which,
-                                                   unsigned long long* cellacc, uint8_t* tiles,
+                                                   unsigned long long* cellacc, uint32_t* tiles,
                                                    StepConst K,
                                                    const void* Eox, const void* Eoy, const void* Eoz,
                                                    const void* Enx, const void* Eny, const void* Enz,
@@ -520,7 +520,8 @@ __device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
 
 // One colour of a red-black Gauss-Seidel sweep: grid (x: half a row, y: j, z: k),
 // every thread updates the one cell of the colour in its pair.
-template <typename T>
+// kFine marks the finest level's instantiation, so that kernel traces report it apart.
+template <typename T, bool kFine>
 __global__ void __launch_bounds__(128) k_smooth_rb(T* u, const T* f, const T* eps, int nx, int ny, int nz,
                                                   int color) {
   int bx, j, k;
@@ -693,6 +694,13 @@ struct FieldState {
   bool have_prev = false;
   bool graph_failed = false;
   hipGraphExec_t graph_exec = nullptr;
+  // optional timing of the finest-level smoother launches: event pairs recorded around
+  // each launch; while timing is on the cycle runs eagerly (not from the graph)
+  static constexpr int kMaxTimed = 64;
+  hipEvent_t sm_ev[2 * kMaxTimed] = {};
+  int sm_n = 0;              // event pairs recorded by the cycle being enqueued
+  int sm_pending = 0;        // pairs recorded by the last enqueued cycle, unread
+  bool timing = false;
 };
 
 static int build_levels(const itokmc_grid_desc* d, int dims[kMaxLevels][3]) {
@@ -775,9 +783,22 @@ void field_reset_graph(itokmc_ctx* ctx) {
   F->graph_failed = false;
 }
 
+// Turn timing of the finest-level smoother on or off (the cycle graph is rebuilt).
+void field_set_timing(itokmc_ctx* ctx, bool on) {
+  FieldState* F = fs(ctx);
+  if (!F || F->timing == on) return;
+  (void)hipStreamSynchronize(ctx->s);
+  if (on && !F->sm_ev[0])
+    for (int i = 0; i < 2 * FieldState::kMaxTimed; ++i) (void)hipEventCreate(&F->sm_ev[i]);
+  F->timing = on;
+  F->sm_pending = 0;
+}
+
 void field_destroy(itokmc_ctx* ctx) {
   FieldState* F = fs(ctx);
   if (!F) return;
+  for (int i = 0; i < 2 * FieldState::kMaxTimed; ++i)
+    if (F->sm_ev[i]) (void)hipEventDestroy(F->sm_ev[i]);
   if (F->host_norms) (void)hipHostFree(F->host_norms);
   if (F->graph_exec) (void)hipGraphExecDestroy(F->graph_exec);
   delete F;
@@ -790,6 +811,26 @@ static Coef coef(const itokmc_ctx* ctx) {
 
 static dim3 row_grid(int half_nx, int ny, int nz) {
   return dim3((unsigned)((half_nx + 127) / 128), (unsigned)ny, (unsigned)nz);
+}
+
+// One colour sweep at level l; the finest level's launches are bracketed by event
+// pairs when timing is on.
+template <typename T>
+static void smooth(FieldState* F, int l, hipStream_t s, int color) {
+  Level& L = F->lev[l];
+  const dim3 gs = row_grid((L.nx + 1) / 2, L.ny, L.nz);
+  T* u = (T*)L.u;
+  const T* f = (const T*)L.f;
+  const T* ep = (const T*)L.eps;
+  if (l > 0) {
+    k_smooth_rb<T, false><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+    return;
+  }
+  const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
+  if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
+  k_smooth_rb<T, true><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n + 1], s);
+  if (timed) ++F->sm_n;
 }
 
 template <typename T>
@@ -806,10 +847,9 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
     return;
   }
   Level& C = F->lev[l + 1];
-  const dim3 gs = row_grid((L.nx + 1) / 2, L.ny, L.nz);
   for (int it = 0; it < ctx->tune.mg_pre; ++it) {
-    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
-    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
+    smooth<T>(F, l, s, 0);
+    smooth<T>(F, l, s, 1);
   }
   k_restrict3<T><<<row_grid(C.nx, C.ny, C.nz), 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u,
                                                              C.nx, C.ny);
@@ -817,9 +857,22 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   k_prolong3<T><<<row_grid(L.nx, L.ny, L.nz), 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny,
                                                             C.nz);
   for (int it = 0; it < ctx->tune.mg_post; ++it) {
-    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 0);
-    k_smooth_rb<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, 1);
+    smooth<T>(F, l, s, 0);
+    smooth<T>(F, l, s, 1);
   }
+}
+
+// Accumulate the timed finest-level smoother launches of the last cycle (the stream
+// has been synchronised).
+static void collect_smooth(itokmc_ctx* ctx, FieldState* F) {
+  for (int i = 0; i < F->sm_pending; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, F->sm_ev[2 * i], F->sm_ev[2 * i + 1]) == hipSuccess) {
+      ctx->phase_ms[PH_SMOOTH_FINE] += ms;
+      ctx->phase_calls[PH_SMOOTH_FINE] += 1;
+    }
+  }
+  F->sm_pending = 0;
 }
 
 // One refinement cycle: correction V-cycle from zero, potential update, new double
@@ -827,6 +880,7 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
 template <typename T>
 static void refine_cycle(itokmc_ctx* ctx, FieldState* F, hipStream_t s) {
   Level& L0 = F->lev[0];
+  F->sm_n = 0;
   k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
   vcycle<T>(ctx, F, 0, s);
   k_phi_update<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, (const T*)L0.u, L0.n);
@@ -879,11 +933,12 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
   k_residual_rows<T><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz, (T*)L0.f,
                                         F->norms + 8);
   k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
-  const bool graph = ctx->tune.use_graph && capture_cycle<T>(ctx, F);
+  const bool graph = ctx->tune.use_graph && !F->timing && capture_cycle<T>(ctx, F);
   for (int cyc = 0;; ++cyc) {
     hipError_t e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return check_hip(ctx, e, "solve residual");
+    collect_smooth(ctx, F);
     const double bn2 = F->host_norms[0], rn2 = F->host_norms[1];
     const double bn = bn2 > 0.0 ? sqrt(bn2) : 1.0;
     ctx->last_relres = sqrt(rn2) / bn;
@@ -895,8 +950,10 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
     if (graph) {
       e = hipGraphLaunch(F->graph_exec, s);
       if (e != hipSuccess) return check_hip(ctx, e, "solve graph");
+      F->sm_pending = 0;
     } else {
       refine_cycle<T>(ctx, F, s);
+      F->sm_pending = F->sm_n;
     }
   }
   return check_hip(ctx, hipGetLastError(), "solve");
@@ -907,11 +964,13 @@ template <typename T>
 static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K, int mode) {
   hipStream_t s = ctx->s;
   const uint32_t n = ctx->ncell;
-  phase_begin(ctx, PH_DEPOSIT);
+  phase_begin(ctx, PH_FIELD_PREP);
   using S = typename DepAcc<T>::S;
   k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->sig, n);
   k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->ne, n);
+  phase_end(ctx, PH_FIELD_PREP);
   void* const* Eo = F->E[F->cur];
+  phase_begin(ctx, PH_DEPOSIT);  // the deposit kernel alone
   {
     constexpr int TBL = 1 << DepTbl<T>::log2n;
     const size_t lds = (size_t)TBL * (4 + 2 * sizeof(S));
@@ -920,6 +979,8 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
     k_field_deposit_lds<T><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1],
                                                Eo[2], coef(ctx), mode, (S*)F->sig, (S*)F->ne);
   }
+  phase_end(ctx, PH_DEPOSIT);
+  phase_begin(ctx, PH_FIELD_PREP);
   const double sig_scale = mode == 1 ? kE * K.dt / (kEps0 * K.dx * K.dx * K.dx) : 0.0;
   if (mode == 1) {
     k_extrapolate<<<blocks(n), 256, 0, s>>>(F->phi, F->phi_prev, n,
@@ -932,7 +993,7 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
                                              (const S*)F->sig, sig_scale, ctx->d.V_anode,
                                              (T*)F->lev[0].eps, F->b, F->norms + 8);
   k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms);
-  phase_end(ctx, PH_DEPOSIT);
+  phase_end(ctx, PH_FIELD_PREP);
   phase_begin(ctx, PH_SOLVE);
   const int rc = solve<T>(ctx, F);
   const int nxt = 1 - F->cur;

@@ -31,13 +31,14 @@ struct Counters {
   uint32_t n_occ;         // occupied cells after binning
   uint32_t n_work;        // cells needing coupling / merge
   uint32_t sorted;        // particles placed by the last counting sort
-  uint32_t pad[2];
+  uint32_t n_heavy;       // occupied cells left to the full KMC pass
+  uint32_t n_huge;        // cells deferred past the mid-size merge staging
   unsigned long long outflow, created, removed, merged;
   unsigned long long fires[3];
   unsigned long long ph_emitted, ph_absorbed, ph_lost;
   unsigned long long pushed;   // live particles advanced by the transport kernels
   uint32_t merge_skipped;      // cells too large for the LDS merge (left unmerged)
-  uint32_t n_big;              // cells deferred to the large-staging merge pass
+  uint32_t n_big;              // cells deferred to the mid-size merge staging
 };
 
 // Device-side copy of the per-step constants shared by the kernels.
@@ -85,9 +86,12 @@ struct itokmc_ctx {
   int32_t* dN = nullptr;                  // net electron change per occupied cell
   uint32_t* work = nullptr;               // occupied-cell indices needing coupling
   uint32_t* cbase = nullptr;              // first reserved bank slot of a cell's products
-  uint32_t* big = nullptr;                // occupied-cell indices for the large merge pass
+  uint32_t* big = nullptr;                // occupied-cell indices for the mid-size merge pass
+  uint32_t* huge = nullptr;               // occupied-cell indices for the large merge pass
+  uint32_t* heavy = nullptr;              // occupied-cell indices for the full KMC pass
+  double* rates = nullptr;                // 3 per occupied cell: rates handed to the full pass
   uint32_t* blocksums = nullptr;          // scan scratch
-  uint8_t* tiles = nullptr;               // per 2048-cell tile: received particles
+  uint32_t* tiles = nullptr;               // per 2048-cell tile: received particles
   itk::Counters* ctr = nullptr;
   unsigned long long* reduce = nullptr;   // small reduction scratch
   bool binned = false;                    // bins of the current bank are filled
@@ -106,7 +110,7 @@ struct itokmc_ctx {
   bool profiling = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   std::vector<hipEvent_t> ev_free;
-  double phase_ms[16] = {0};
+  double phase_ms[16] = {0};      // indexed by itk::Phase (< 16)
   uint64_t phase_calls[16] = {0};
   itokmc_tuning tune = {2, 2, 0, 1, 1, 0};
 };
@@ -114,7 +118,7 @@ struct itokmc_ctx {
 namespace itk {
 // phases timed when profiling is on
 enum Phase { PH_PUSH = 0, PH_PHOTON, PH_SCAN, PH_SCATTER, PH_KMC, PH_COUPLE, PH_DEPOSIT,
-             PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_NUM };
+             PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_MERGE, PH_FIELD_PREP, PH_SMOOTH_FINE, PH_NUM };
 void phase_begin(itokmc_ctx* ctx, int phase);
 void phase_end(itokmc_ctx* ctx, int phase);
 int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);
@@ -136,7 +140,7 @@ hipError_t launch_scan(itokmc_ctx* ctx);
 hipError_t launch_scatter(itokmc_ctx* ctx);
 // pointer forms used by the ensemble (ncell_dev: device-side cell count to scan)
 hipError_t launch_scan_raw(const unsigned long long* cellacc, uint32_t max_cells,
-                           const uint32_t* ncell_dev, uint8_t* tiles, uint32_t* blocksums,
+                           const uint32_t* ncell_dev, uint32_t* tiles, uint32_t* blocksums,
                            uint32_t* start, uint32_t* occ, Counters* ctr, int dest, hipStream_t s);
 // u32 words of scan scratch for a cell count
 size_t scan_scratch_words(uint64_t ncell);
@@ -161,6 +165,7 @@ int field_transport(itokmc_ctx* ctx, const StepConst& k);
 FieldRates field_rates(itokmc_ctx* ctx);  // E view for the KMC rates
 void field_destroy(itokmc_ctx* ctx);
 void field_reset_graph(itokmc_ctx* ctx);
+void field_set_timing(itokmc_ctx* ctx, bool on);
 int field_get_phi(itokmc_ctx* ctx, double* host);
 int field_set_phi(itokmc_ctx* ctx, const double* host);
 int field_deposit(itokmc_ctx* ctx, int what, void* dev_out);

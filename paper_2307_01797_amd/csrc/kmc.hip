@@ -36,34 +36,58 @@ __device__ void rates_at(const FieldRates& fr, uint32_t c, double k[3]) {
   k[2] = fr.kgamma_ratio * k[0];
 }
 
-// Step kernel: occupied cells from the binning pass.  Writes the per-cell fires, the
-// updated ions and pending photons, the net electron change, clears the cell's bin
-// accumulator, and queues cells for the coupling pass.
-__global__ void __launch_bounds__(256) k_kmc_step(KmcParams P, StepConst K, Counters* ctr,
-                                                 const uint32_t* occ, unsigned long long* cellacc,
-                                                 uint32_t* nplus, uint32_t* nminus,
-                                                 uint32_t* ngamma, uint32_t* occ_fires, int32_t* dN,
-                                                 uint32_t* work, uint32_t* cbase,
-                                                 FieldRates fr, int queue_all, int n_new,
-                                                 int dest) {
-  const uint32_t n = ctr->n_occ;
+// Step kernels: occupied cells from the binning pass.  Each writes the per-cell
+// fires, the updated ions and pending photons, the net electron change, clears the
+// cell's bin accumulator, queues cells for the coupling pass and reserves the bank
+// slots of their products.  The fast pass (kFast) takes every occupied cell and
+// settles those whose step is a single SSA excursion with a small register footprint;
+// it queues the rest, untouched, for the full pass (!kFast), which runs the complete
+// method from the same state and stream (with the rates the fast pass computed).
+// A thread takes kKmcPer cells between the workgroup-aggregated appends to the queues.
+constexpr int kKmcPer = 4;
+
+template <bool kFast>
+__global__ void __launch_bounds__(kFast ? 256 : 64) k_kmc_step(
+    KmcParams P, StepConst K, Counters* ctr, const uint32_t* occ, unsigned long long* cellacc,
+    uint32_t* nplus, uint32_t* nminus, uint32_t* ngamma, uint32_t* occ_fires, int32_t* dN,
+    uint32_t* work, uint32_t* cbase, uint32_t* heavy, double* rates, FieldRates fr,
+    int queue_all, int n_new, int dest) {
+  __shared__ uint32_t sh[18];
+  const uint32_t n = kFast ? ctr->n_occ : ctr->n_heavy;
+  const uint32_t span = blockDim.x * kKmcPer;
   uint64_t t0 = 0, t1 = 0, t2 = 0;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const uint32_t j = base + threadIdx.x;
-    bool queue = false;
-    uint32_t M = 0;
-    if (j < n) {
+  for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+    uint32_t js[kKmcPer], Ms[kKmcPer], fl[kKmcPer];  // fl: 1 queue, 2 defer
+    uint32_t nq = 0, nd = 0, nm = 0;
+#pragma unroll
+    for (int r = 0; r < kKmcPer; ++r) {
+      const uint32_t jj = base + (uint32_t)r * blockDim.x + threadIdx.x;
+      js[r] = 0; Ms[r] = 0; fl[r] = 0;
+      if (jj >= n) continue;
+      const uint32_t j = kFast ? jj : heavy[jj];
+      js[r] = j;
       const uint32_t c = occ[j];
       const uint32_t Xe = (uint32_t)cellacc[c];
-      cellacc[c] = 0ull;
       State X{(int64_t)Xe, (int64_t)nplus[c], (int64_t)nminus[c], 0};
       double k[3];
-      if (fr.E[0]) rates_at(fr, c, k);
-      else { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
+      if (!fr.E[0]) { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
+      else if (kFast) rates_at(fr, c, k);
+      else { k[0] = rates[3 * (size_t)j]; k[1] = rates[3 * (size_t)j + 1]; k[2] = rates[3 * (size_t)j + 2]; }
       CellStream st;
       st.init(c, K.step, TAG_KMC, 0, K.key);
       int64_t f[3];
-      advance(P, X, k, K.dt, st, f);
+      if (kFast) {
+        if (!advance_fast(P, X, k, K.dt, st, f)) {
+          fl[r] = 2; ++nd;
+          if (fr.E[0]) {
+            rates[3 * (size_t)j] = k[0]; rates[3 * (size_t)j + 1] = k[1]; rates[3 * (size_t)j + 2] = k[2];
+          }
+          continue;
+        }
+      } else {
+        advance(P, X, k, K.dt, st, f);
+      }
+      cellacc[c] = 0ull;
       occ_fires[3 * (size_t)j] = (uint32_t)f[0];
       occ_fires[3 * (size_t)j + 1] = (uint32_t)f[1];
       occ_fires[3 * (size_t)j + 2] = (uint32_t)f[2];
@@ -72,15 +96,19 @@ __global__ void __launch_bounds__(256) k_kmc_step(KmcParams P, StepConst K, Coun
       ngamma[c] = (uint32_t)X.g;
       const int64_t d = X.e - (int64_t)Xe;
       dN[j] = (int32_t)d;
-      queue = queue_all || d != 0;
-      if (d > 0) M = d < (int64_t)n_new ? (uint32_t)d : (uint32_t)n_new;
+      if (queue_all || d != 0) { fl[r] = 1; ++nq; }
+      if (d > 0) { Ms[r] = d < (int64_t)n_new ? (uint32_t)d : (uint32_t)n_new; nm += Ms[r]; }
       t0 += (uint64_t)f[0]; t1 += (uint64_t)f[1]; t2 += (uint64_t)f[2];
     }
-    const uint32_t q = wave_append(&ctr->n_work, queue ? 1u : 0u);
-    if (queue) work[q] = j;
-    // reserve the bank slots of the KMC products: one atomic per wave
-    const uint32_t slot = wave_append(&ctr->n[dest], M);
-    if (M) cbase[j] = slot;
+    uint32_t hb = kFast ? block_append(&ctr->n_heavy, nd, sh) : 0u;
+    uint32_t qb = block_append(&ctr->n_work, nq, sh);
+    uint32_t mb = block_append(&ctr->n[dest], nm, sh);  // bank slots of the products
+#pragma unroll
+    for (int r = 0; r < kKmcPer; ++r) {
+      if (fl[r] == 2) heavy[hb++] = js[r];
+      if (fl[r] == 1) work[qb++] = js[r];
+      if (Ms[r]) { cbase[js[r]] = mb; mb += Ms[r]; }
+    }
   }
   t0 = wave_sum64(t0); t1 = wave_sum64(t1); t2 = wave_sum64(t2);
   if (lane_id() == 0) {
@@ -115,13 +143,21 @@ KmcParams params(const itokmc_ctx* ctx) {
 }  // namespace
 
 hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates& fr) {
-  int g = (int)((ctx->ncell + 255) / 256);
-  if (g > 8192) g = 8192;
+  int g = (int)((ctx->ncell + 256 * kKmcPer - 1) / (256 * kKmcPer));
+  if (g > 4096) g = 4096;
   if (g < 1) g = 1;
-  k_kmc_step<<<g, 256, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
-                                    ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
-                                    ctx->cbase, fr, ctx->d.n_ppc > 0 ? 1 : 0, ctx->d.n_new,
-                                    1 - ctx->cur);
+  const int qa = ctx->d.n_ppc > 0 ? 1 : 0, dest = 1 - ctx->cur;
+  k_kmc_step<true><<<g, 256, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
+                                          ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
+                                          ctx->cbase, ctx->heavy, ctx->rates, fr, qa, ctx->d.n_new, dest);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int gh = (int)((ctx->ncell + 64 * kKmcPer - 1) / (64 * kKmcPer));
+  if (gh > 4096) gh = 4096;
+  if (gh < 1) gh = 1;
+  k_kmc_step<false><<<gh, 64, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
+                                           ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
+                                           ctx->cbase, ctx->heavy, ctx->rates, fr, qa, ctx->d.n_new, dest);
   return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ __device__ inline double leap_bound(const KmcParams& P, const State& X, double a
 __device__ inline double ssa_run(const KmcParams& P, State& X, const double k[3], double h,
                           CellStream& st, int64_t f[3]) {
   double tp = 0.0;
+#pragma unroll 1
   for (int ev = 0; ev < P.nssa; ++ev) {
     const double a1 = k[0] * (double)X.e, a2 = k[1] * (double)X.e, a3 = k[2] * (double)X.e;
     const double A = a1 + a2 + a3;
@@ -120,6 +121,24 @@ __device__ inline void advance_pure_tau(State& X, const double k[3], double dt, 
     f[0] += n1; f[1] += n2; f[2] += n3;
     tau = (h == dt - tau) ? dt : tau + h;
   }
+}
+
+// The common case of the hybrid method, with a small register footprint: the whole step
+// is one SSA excursion (A h <= 1 for h = dt, i.e. no leap bound below dt) that ends at
+// dt within nssa events, or nothing can fire (A = 0).  Then X, f and the stream are
+// exactly what advance() produces and the result is true.  Otherwise false: the caller
+// discards X, f and the stream and runs advance() from the original state.
+__device__ __forceinline__ bool advance_fast(const KmcParams& P, State& X, const double k[3],
+                                             double dt, CellStream& st, int64_t f[3]) {
+  f[0] = f[1] = f[2] = 0;
+  if (P.mode != ITOKMC_KMC_HYBRID) return false;
+  const double a1 = k[0] * (double)X.e, a2 = k[1] * (double)X.e, a3 = k[2] * (double)X.e;
+  const double A = a1 + a2 + a3;
+  if (!(A > 0.0)) return true;
+  const bool crit2 = (a2 > 0.0) && X.e < (int64_t)P.nc;
+  const double h = fmin(dt, leap_bound(P, X, a1, a2, a3, crit2));
+  if (h != dt || !(A * h <= 1.0)) return false;
+  return ssa_run(P, X, k, h, st, f) == dt;
 }
 
 __device__ __forceinline__ void advance(const KmcParams& P, State& X, const double k[3], double dt,

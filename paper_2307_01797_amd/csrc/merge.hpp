@@ -25,7 +25,8 @@
 namespace itk {
 
 constexpr int kMaxMergePpc = 64;
-constexpr int kMergeSmall = 256;  // pieces staged by the common (small-LDS) path
+constexpr int kMergeTiny = 96;    // pieces staged by the common path (smallest LDS)
+constexpr int kMergeSmall = 256;  // pieces staged by the mid-size path
 template <typename T> struct MergeBig;
 template <> struct MergeBig<float> { static constexpr int value = 1536; };
 template <> struct MergeBig<double> { static constexpr int value = 1024; };
@@ -60,7 +61,7 @@ constexpr size_t merge_lds_bytes_c() {
 }
 template <typename T>
 inline size_t merge_lds_bytes(int n_ppc) {
-  return n_ppc > 0 ? merge_lds_bytes_c<T, kMergeSmall>() : 0;
+  return n_ppc > 0 ? merge_lds_bytes_c<T, kMergeTiny>() : 0;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kBlock) k_seed_neutral(Bank b, Counters* ctr, 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, int which,
                                                         unsigned long long* cellacc,
-                                                        uint8_t* tiles, StepConst k) {
+                                                        uint32_t* tiles, StepConst k) {
   const uint32_t n = min(ctr->n[which], k.cap);
   const T drift[3] = {(T)k.drift[0], (T)k.drift[1], (T)k.drift[2]};
   const T diff = (T)k.diff;
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
 
 // Bin the current particles without moving them (after seeding or set_state).
 __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int which,
-                                                 unsigned long long* cellacc, uint8_t* tiles,
+                                                 unsigned long long* cellacc, uint32_t* tiles,
                                                  uint32_t cap) {
   const uint32_t n = min(ctr->n[which], cap);
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int whi
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int which,
-                                                   unsigned long long* cellacc, uint8_t* tiles,
+                                                   unsigned long long* cellacc, uint32_t* tiles,
                                                    uint32_t* ngamma,
                                                    uint32_t* nplus, StepConst k, int n_new,
                                                    double l1, double l2) {
@@ -277,7 +277,7 @@ __device__ __forceinline__ uint32_t scan_tiles(uint32_t ncell) {
 __global__ void __launch_bounds__(kBlock) k_scan_reduce(const unsigned long long* cellacc,
                                                        uint32_t ncell_arg,
                                                        const uint32_t* ncell_dev,
-                                                       uint8_t* tiles, uint32_t* cnt) {
+                                                       uint32_t* tiles, uint32_t* cnt) {
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
   const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
   const uint32_t nb = scan_tiles(ncell);
@@ -382,6 +382,8 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* 
     ctr->n[dest] = total;
     ctr->n_work = 0;
     ctr->n_big = 0;
+    ctr->n_heavy = 0;
+    ctr->n_huge = 0;
   }
 }
 
@@ -538,7 +540,7 @@ size_t scan_scratch_words(uint64_t ncell) {
 }
 
 hipError_t launch_scan_raw(const unsigned long long* cellacc, uint32_t max_cells,
-                           const uint32_t* ncell_dev, uint8_t* tiles, uint32_t* scratch,
+                           const uint32_t* ncell_dev, uint32_t* tiles, uint32_t* scratch,
                            uint32_t* start, uint32_t* occ, Counters* ctr, int dest, hipStream_t s) {
   const uint32_t nb = (max_cells + kScanTile - 1) / kScanTile;
   uint32_t* cnt = scratch;

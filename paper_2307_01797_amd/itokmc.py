@@ -36,7 +36,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
            "itokmc_ensemble_last_error"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
-          "field_push", "count"]
+          "field_push", "count", "merge", "field_prep", "smooth_fine"]
 
 
 class GridDesc(ctypes.Structure):
