@@ -31,13 +31,17 @@ HBM_PEAK_GBS = 8000.0
 #                      weight and id
 #   smooth_fine (per finest-level cell and launch of one colour): read u and eps of every
 #                      cell, f of the cells of the colour, write u of those cells: 3S
+#   sweep_fine (per finest-level cell and fused launch, one full red-black sweep): read
+#                      u, eps and f, write u: 4S
 KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k_field_deposit_lds",
-           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_rb<fine>"}
+           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_rb<fine>",
+           "sweep_fine": "k_smooth_fused<fine>"}
 
 
 def bytes_per_unit(phase, S):
     return {"push": 24 + 6 * S, "field_push": 24 + 6 * S, "deposit": 16 + 3 * S,
-            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 3 * S}[phase]
+            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 3 * S,
+            "sweep_fine": 4 * S}[phase]
 
 
 def parse():
@@ -56,6 +60,9 @@ def parse():
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--drain", type=float, default=60.0)
     p.add_argument("--poisson-workers", type=int, default=4)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="first copy 1 GiB device to device (a known-size kernel for "
+                        "scaling hardware traffic counters)")
     p.add_argument("--no-plain", action="store_true")
     return p.parse_args()
 
@@ -253,6 +260,12 @@ def main():
 
     cfg = workloads.preset(args.workload)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
     sim = itokmc.Sim(cfg, device=dev)
     sim.seed()
     sim.step(args.warmup)
@@ -297,7 +310,7 @@ def main():
         tot_ms, launches = phases.get(ph, (0.0, 0))
         if not launches or tot_ms <= 0:
             continue
-        if ph == "smooth_fine":
+        if ph in ("smooth_fine", "sweep_fine"):
             units = ncell * launches
         elif ph == "couple":
             if not cfg.get("n_ppc"):
@@ -329,7 +342,9 @@ def main():
         "config": {"workload": cfg["name"], "grid": list(cfg["grid"]), "dx_m": cfg["dx"],
                    "particles_start": d0["n_particles"], "particles_end": d1["n_particles"],
                    "weight_end": d1["weight"], "field": cfg.get("field"),
-                   "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": rc},
+                   "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": rc,
+                   "occupied_cells_end": d2.get("occupied_cells"),
+                   "queued_cells_end": d2.get("queued_cells")},
         "profiled_window": {"ms_per_step": ms_p / args.steps, "status": rc_p,
                             "particle_steps": psteps_p},
         "phase_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},

@@ -121,10 +121,10 @@ typedef struct {
   double solver_relres;
   double rho_sum;                 /* FP64 sum of rho dV over the grid (C)             */
   uint32_t overflow;              /* nonzero if a capacity limit was hit             */
-  uint32_t pad0;
+  uint32_t occupied_cells;        /* cells holding particles at the last binning     */
   uint64_t particle_steps;        /* cumulative live particles advanced by transport */
   uint32_t merge_skipped;         /* cells whose particles exceeded the merge staging */
-  uint32_t pad1;
+  uint32_t queued_cells;          /* cells coupled (and merged) by the last step      */
   uint64_t solver_cycles_total;   /* multigrid cycles over all field solves          */
   uint64_t solves_total;          /* field solves performed                           */
 } itokmc_diag;
@@ -145,8 +145,9 @@ int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* coeffs);
 int itokmc_seed_particles(itokmc_ctx* ctx, const itokmc_seed_desc* seed);
 
 /* Advance nsteps full steps of length dt (final algorithm, steps 1-8).  Returns
- * ECAPACITY if a buffer overflowed during the steps (state remains consistent but
- * incomplete), ENOCONV if a field solve missed its tolerance. */
+ * ENOCONV if a field solve missed its tolerance.  A particle-capacity overflow drops
+ * the particles that do not fit, sets a device flag and is reported as ECAPACITY by
+ * itokmc_diagnostics (the state stays consistent but incomplete). */
 int itokmc_step(itokmc_ctx* ctx, uint32_t nsteps, double dt);
 
 /* The two halves of one step: transport (steps 1-5 and removal at the faces) and
@@ -182,9 +183,12 @@ int itokmc_set_field(itokmc_ctx* ctx, const double* phi);
  * tolerance): multigrid pre/post red-black sweeps per level (default 2/2, each 0..8,
  * sum >= 1), bottom-level sweeps (0 = automatic), capture of the refinement cycle in
  * a HIP graph (default on), linear-in-time extrapolation of the potential as the
- * initial guess (default on).  set_tuning copies the struct; EINVAL if out of range. */
+ * initial guess (default on), fused sweeps (0 default: one launch per colour; 1 or 2:
+ * levels at least 128 cells wide smooth pairs of sweeps with one out-of-place launch
+ * per sweep on 8- or 4-row tiles, giving results identical to single-colour launches).
+ * set_tuning copies the struct; EINVAL if out of range. */
 typedef struct {
-  int32_t mg_pre, mg_post, bottom_sweeps, use_graph, extrapolate, pad0;
+  int32_t mg_pre, mg_post, bottom_sweeps, use_graph, extrapolate, fused_sweeps;
 } itokmc_tuning;
 int itokmc_set_tuning(itokmc_ctx* ctx, const itokmc_tuning* tuning);
 int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
@@ -193,8 +197,8 @@ int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
  * context's stream (off by default).  Phases: 0 push, 1 photons, 2 bin scan,
  * 3 scatter, 4 KMC, 5 coupling kernel, 6 charge-deposit kernel, 7 field solve (with
  * the field from the potential), 8 field push, 9 recount, 10 larger merge tiers,
- * 11 deposit clearing and right-hand side, 12 finest-level smoother launches (inside
- * the solve; one count per launch).  phase_times synchronises, writes accumulated
+ * 11 deposit clearing and right-hand side, 12 finest-level single-colour smoother
+ * launches, 13 finest-level fused sweeps (both inside the solve; one count per launch).  phase_times synchronises, writes accumulated
  * milliseconds and launch counts for the first n phases, and clears them if reset is
  * nonzero. */
 int itokmc_set_profiling(itokmc_ctx* ctx, int on);

@@ -432,6 +432,8 @@ int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
   out->overflow = c.overflow;
   out->particle_steps = c.pushed;
   out->merge_skipped = c.merge_skipped;
+  out->occupied_cells = c.n_occ;
+  out->queued_cells = c.n_work;
   out->solver_cycles_total = ctx->total_cycles;
   out->solves_total = ctx->total_solves;
   if (c.overflow) return set_error(ctx, ITOKMC_ECAPACITY, "capacity exceeded (flags %u)", c.overflow);
@@ -565,7 +567,7 @@ int itokmc_set_field(itokmc_ctx* ctx, const double* phi) {
 int itokmc_set_tuning(itokmc_ctx* ctx, const itokmc_tuning* t) {
   if (!ctx || !t) return ITOKMC_EINVAL;
   if (t->mg_pre < 0 || t->mg_pre > 8 || t->mg_post < 0 || t->mg_post > 8 || t->mg_pre + t->mg_post < 1 ||
-      t->bottom_sweeps < 0 || t->bottom_sweeps > 4096)
+      t->bottom_sweeps < 0 || t->bottom_sweeps > 4096 || t->fused_sweeps < 0 || t->fused_sweeps > 2)
     return set_error(ctx, ITOKMC_EINVAL, "invalid tuning");
   ctx->tune = *t;
   field_reset_graph(ctx);

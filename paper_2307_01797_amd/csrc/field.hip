@@ -40,6 +40,7 @@ struct Level {
   int nx, ny, nz;
   uint32_t n;
   void* u;    // correction
+  void* u2;   // second correction buffer for the out-of-place fused sweep
   void* f;    // right-hand side (scaled by h^2)
   void* eps;  // cell coefficient 1 + sigma dt / eps0
 };
@@ -469,22 +470,34 @@ __device__ __forceinline__ void stencil(const U* u, const E* eps, int nx, int ny
 __device__ __forceinline__ double hmean_s(double a, double b) { return 2.0 * a * b / (a + b); }
 __device__ __forceinline__ float hmean_s(float a, float b) { return __fdividef(2.0f * a * b, a + b); }
 
-template <typename T>
-__device__ __forceinline__ void stencil_s(const T* u, const T* eps, int nx, int ny, int nz, int i, int j,
-                                          int k, size_t c, T& diag, T& offsum) {
-  const T ec = eps[c];
+// Single-precision-path operator row through value accessors a(dx, dy, dz) of the
+// correction and of the coefficient at the neighbour (dx, dy, dz) of cell (i, j, k), so
+// the smoothers reading HBM and reading LDS share one arithmetic order.
+template <typename T, typename UA, typename EA>
+__device__ __forceinline__ void stencil_acc(UA ua, EA ea, int nx, int ny, int nz, int i, int j, int k,
+                                            T& diag, T& offsum) {
+  const T ec = ea(0, 0, 0);
   T d = 0, s = 0;
-  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  if (i > 0) { const T b = hmean_s(ec, eps[c - 1]); d += b; s += b * u[c - 1]; }
-  if (i < nx - 1) { const T b = hmean_s(ec, eps[c + 1]); d += b; s += b * u[c + 1]; }
-  if (j > 0) { const T b = hmean_s(ec, eps[c - sy]); d += b; s += b * u[c - sy]; }
-  if (j < ny - 1) { const T b = hmean_s(ec, eps[c + sy]); d += b; s += b * u[c + sy]; }
-  if (k > 0) { const T b = hmean_s(ec, eps[c - sz]); d += b; s += b * u[c - sz]; }
+  if (i > 0) { const T b = hmean_s(ec, ea(-1, 0, 0)); d += b; s += b * ua(-1, 0, 0); }
+  if (i < nx - 1) { const T b = hmean_s(ec, ea(1, 0, 0)); d += b; s += b * ua(1, 0, 0); }
+  if (j > 0) { const T b = hmean_s(ec, ea(0, -1, 0)); d += b; s += b * ua(0, -1, 0); }
+  if (j < ny - 1) { const T b = hmean_s(ec, ea(0, 1, 0)); d += b; s += b * ua(0, 1, 0); }
+  if (k > 0) { const T b = hmean_s(ec, ea(0, 0, -1)); d += b; s += b * ua(0, 0, -1); }
   else d += (T)2 * ec;
-  if (k < nz - 1) { const T b = hmean_s(ec, eps[c + sz]); d += b; s += b * u[c + sz]; }
+  if (k < nz - 1) { const T b = hmean_s(ec, ea(0, 0, 1)); d += b; s += b * ua(0, 0, 1); }
   else d += (T)2 * ec;
   diag = d;
   offsum = s;
+}
+
+template <typename T>
+__device__ __forceinline__ void stencil_s(const T* u, const T* eps, int nx, int ny, int nz, int i, int j,
+                                          int k, size_t c, T& diag, T& offsum) {
+  const ptrdiff_t sy = (ptrdiff_t)nx, sz = (ptrdiff_t)nx * ny;
+  auto at = [=](int dx, int dy, int dz) { return (size_t)((ptrdiff_t)c + dx + dy * sy + dz * sz); };
+  stencil_acc<T>([&](int dx, int dy, int dz) { return u[at(dx, dy, dz)]; },
+                 [&](int dx, int dy, int dz) { return eps[at(dx, dy, dz)]; }, nx, ny, nz, i, j, k, diag,
+                 offsum);
 }
 
 // Operator row for the double residual with the face coefficients computed exactly as
@@ -532,6 +545,128 @@ __global__ void __launch_bounds__(128) k_smooth_rb(T* u, const T* f, const T* ep
   T d, s;
   stencil_s<T>(u, eps, nx, ny, nz, i, j, k, c, d, s);
   u[c] = (f[c] + s) / d;
+}
+
+// One full red-black sweep in one pass (colour 0, then colour 1), out of place: a
+// workgroup takes a kFX x kFY tile (kFY = 8 or 4 rows) of zc planes and marches along z with the planes
+// p-3..p of u and the coefficient (with a two-cell ring) and p-2..p of f (one-cell ring)
+// in LDS; at plane p it updates colour 0 of plane p-1 on the tile and its ring, then
+// colour 1 of plane p-2 on the tile, and writes plane p-2.  Colour 0 reads only the
+// input (colour-1 values), colour 1 reads the updated colour-0 values, exactly as the
+// two single-colour launches; every cell's arithmetic is stencil_acc's.  Each sweep
+// reads u, the coefficient and f once and writes whole lines of u.
+constexpr int kFX = 64;
+
+template <typename T, bool kFine, int kFY>
+__global__ void __launch_bounds__(256) k_smooth_fused(const T* __restrict__ uin, T* __restrict__ uout,
+                                                     const T* __restrict__ f,
+                                                     const T* __restrict__ eps, int nx, int ny,
+                                                     int nz, int zc) {
+  constexpr int NT = 256;
+  constexpr int kFXh = kFX + 4, kFYh = kFY + 4, kFXf = kFX + 2, kFYf = kFY + 2;
+  constexpr int kPU = (kFYh * kFXh + NT - 1) / NT;  // plane values per thread (u, eps)
+  constexpr int kPF = (kFYf * kFXf + NT - 1) / NT;  // plane values per thread (f)
+  __shared__ T U[4][kFYh][kFXh];
+  __shared__ T E[4][kFYh][kFXh];
+  __shared__ T R[3][kFYf][kFXf];
+  int bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int x0 = bx * kFX, y0 = by * kFY, z0 = bz * zc;
+  const int z1 = min(z0 + zc, nz);
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const int tid = threadIdx.x;
+  // plane p's values of this thread, loaded one plane ahead (registers)
+  T pu[kPU], pe[kPU], pf[kPF];
+  auto fetch = [&](int p) {
+    if (p < 0 || p >= nz) return;
+#pragma unroll
+    for (int m = 0; m < kPU; ++m) {
+      const int t = tid + m * NT;
+      const int lj = t / kFXh, li = t - lj * kFXh;
+      const int i = x0 + li - 2, j = y0 + lj - 2;
+      if (t < kFYh * kFXh && i >= 0 && i < nx && j >= 0 && j < ny) {
+        const size_t c = (size_t)i + sy * j + sz * p;
+        pu[m] = uin[c];
+        pe[m] = eps[c];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kPF; ++m) {
+      const int t = tid + m * NT;
+      const int lj = t / kFXf, li = t - lj * kFXf;
+      const int i = x0 + li - 1, j = y0 + lj - 1;
+      if (t < kFYf * kFXf && i >= 0 && i < nx && j >= 0 && j < ny) pf[m] = f[(size_t)i + sy * j + sz * p];
+    }
+  };
+  auto stash = [&](int p) {
+    if (p < 0 || p >= nz) return;
+    const int sl = (p + 4) & 3, sf = (p + 3) % 3;
+#pragma unroll
+    for (int m = 0; m < kPU; ++m) {
+      const int t = tid + m * NT;
+      const int lj = t / kFXh, li = t - lj * kFXh;
+      const int i = x0 + li - 2, j = y0 + lj - 2;
+      if (t < kFYh * kFXh && i >= 0 && i < nx && j >= 0 && j < ny) {
+        U[sl][lj][li] = pu[m];
+        E[sl][lj][li] = pe[m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kPF; ++m) {
+      const int t = tid + m * NT;
+      const int lj = t / kFXf, li = t - lj * kFXf;
+      const int i = x0 + li - 1, j = y0 + lj - 1;
+      if (t < kFYf * kFXf && i >= 0 && i < nx && j >= 0 && j < ny) R[sf][lj][li] = pf[m];
+    }
+  };
+  fetch(z0 - 2);
+  for (int p = z0 - 2; p <= z1 + 1; ++p) {
+    stash(p);
+    if (p + 1 <= z1 + 1) fetch(p + 1);  // in flight while this plane is computed
+    __syncthreads();
+    const int k = p - 1;  // colour 0 on the tile and its one-cell ring: half of each row
+    if (k >= z0 - 1 && k <= z1 && k >= 0 && k < nz) {
+      const int sk = (k + 4) & 3, fk = (k + 3) % 3;
+      for (int t = tid; t < kFYf * (kFXf / 2); t += NT) {
+        const int lj = t / (kFXf / 2);
+        const int j = y0 + lj - 1;
+        const int li = 2 * (t - lj * (kFXf / 2)) + (((x0 - 1) + j + k) & 1);  // (i + j + k) even
+        const int i = x0 + li - 1;
+        if (i < 0 || i >= nx || j < 0 || j >= ny) continue;
+        const int ui = li + 1, uj = lj + 1;
+        T d, s;
+        stencil_acc<T>([&](int dx, int dy, int dz) { return U[(k + dz + 4) & 3][uj + dy][ui + dx]; },
+                       [&](int dx, int dy, int dz) { return E[(k + dz + 4) & 3][uj + dy][ui + dx]; },
+                       nx, ny, nz, i, j, k, d, s);
+        U[sk][uj][ui] = (R[fk][lj][li] + s) / d;
+      }
+    }
+    __syncthreads();
+    const int k2 = p - 2;  // colour 1 on the tile, then the finished plane
+    if (k2 >= z0 && k2 < z1) {
+      const int sk = (k2 + 4) & 3, fk = (k2 + 3) % 3;
+      for (int t = tid; t < kFY * (kFX / 2); t += NT) {
+        const int lj = t / (kFX / 2);
+        const int j = y0 + lj;
+        const int li = 2 * (t - lj * (kFX / 2)) + ((x0 + j + k2 + 1) & 1);  // (i + j + k2) odd
+        const int i = x0 + li;
+        if (i >= nx || j >= ny) continue;
+        const int ui = li + 2, uj = lj + 2;
+        T d, s;
+        stencil_acc<T>([&](int dx, int dy, int dz) { return U[(k2 + dz + 4) & 3][uj + dy][ui + dx]; },
+                       [&](int dx, int dy, int dz) { return E[(k2 + dz + 4) & 3][uj + dy][ui + dx]; },
+                       nx, ny, nz, i, j, k2, d, s);
+        U[sk][uj][ui] = (R[fk][lj + 1][li + 1] + s) / d;
+      }
+      __syncthreads();
+      for (int t = tid; t < kFY * kFX; t += NT) {
+        const int lj = t / kFX, li = t - lj * kFX;
+        const int i = x0 + li, j = y0 + lj;
+        if (i < nx && j < ny) uout[(size_t)i + sy * j + sz * k2] = U[sk][lj + 2][li + 2];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // r = b - A phi in double with the true boundary values (the lift is in b), 256 cells
@@ -698,6 +833,7 @@ struct FieldState {
   // each launch; while timing is on the cycle runs eagerly (not from the graph)
   static constexpr int kMaxTimed = 64;
   hipEvent_t sm_ev[2 * kMaxTimed] = {};
+  int sm_phase[kMaxTimed] = {};  // phase each pair times (single-colour or fused launch)
   int sm_n = 0;              // event pairs recorded by the cycle being enqueued
   int sm_pending = 0;        // pairs recorded by the last enqueued cycle, unread
   bool timing = false;
@@ -725,7 +861,7 @@ size_t field_bytes(const itokmc_grid_desc* d) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
   size_t total = al(n * 8) * 3 + al(n * T) * 6 + al(n * 8) * 2 + al(8 * (8 + npart));
-  for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
+  for (int l = 0; l < nl; ++l) total += 4 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
   return total;
 }
 
@@ -759,6 +895,7 @@ int field_init(itokmc_ctx* ctx, char* base) {
     L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
     L.n = (uint32_t)((size_t)L.nx * L.ny * L.nz);
     L.u = p; p += al(L.n * T);
+    L.u2 = p; p += al(L.n * T);
     L.f = p; p += al(L.n * T);
     L.eps = p; p += al(L.n * T);
   }
@@ -827,10 +964,64 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
     return;
   }
   const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
-  if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
+  if (timed) {
+    F->sm_phase[F->sm_n] = PH_SMOOTH_FINE;
+    (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
+  }
   k_smooth_rb<T, true><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
   if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n + 1], s);
   if (timed) ++F->sm_n;
+}
+
+// Levels at least this wide smooth with the fused sweep (coarser ones are launch-bound).
+constexpr int kFuseMinNx = 128;
+
+// `count` full sweeps at level l: pairs of fused out-of-place sweeps (u -> u2 -> u) on
+// wide levels, otherwise (and for an odd last sweep) two single-colour launches.  The
+// finest level's fused launches are bracketed by event pairs when timing is on.
+template <typename T>
+static void smooth_sweeps(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s, int count) {
+  Level& L = F->lev[l];
+  int it = 0;
+  if (ctx->tune.fused_sweeps && L.nx >= kFuseMinNx) {
+    const int zc = L.nz >= 256 ? 32 : 8;
+    const int fy = ctx->tune.fused_sweeps == 2 ? 4 : 8;
+    const dim3 g((unsigned)((L.nx + kFX - 1) / kFX), (unsigned)((L.ny + fy - 1) / fy),
+                 (unsigned)((L.nz + zc - 1) / zc));
+    const T* f = (const T*)L.f;
+    const T* ep = (const T*)L.eps;
+    auto launch = [&](bool fine, const T* in, T* out) {
+      if (fy == 4) {
+        if (fine) k_smooth_fused<T, true, 4><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
+        else k_smooth_fused<T, false, 4><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
+      } else {
+        if (fine) k_smooth_fused<T, true, 8><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
+        else k_smooth_fused<T, false, 8><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
+      }
+    };
+    for (; it + 2 <= count; it += 2) {
+      for (int h = 0; h < 2; ++h) {
+        const T* in = (const T*)(h ? L.u2 : L.u);
+        T* out = (T*)(h ? L.u : L.u2);
+        if (l > 0) {
+          launch(false, in, out);
+          continue;
+        }
+        const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
+        if (timed) {
+          F->sm_phase[F->sm_n] = PH_SWEEP_FINE;
+          (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
+        }
+        launch(true, in, out);
+        if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n + 1], s);
+        if (timed) ++F->sm_n;
+      }
+    }
+  }
+  for (; it < count; ++it) {
+    smooth<T>(F, l, s, 0);
+    smooth<T>(F, l, s, 1);
+  }
 }
 
 template <typename T>
@@ -847,19 +1038,13 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
     return;
   }
   Level& C = F->lev[l + 1];
-  for (int it = 0; it < ctx->tune.mg_pre; ++it) {
-    smooth<T>(F, l, s, 0);
-    smooth<T>(F, l, s, 1);
-  }
+  smooth_sweeps<T>(ctx, F, l, s, ctx->tune.mg_pre);
   k_restrict3<T><<<row_grid(C.nx, C.ny, C.nz), 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u,
                                                              C.nx, C.ny);
   vcycle<T>(ctx, F, l + 1, s);
   k_prolong3<T><<<row_grid(L.nx, L.ny, L.nz), 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny,
                                                             C.nz);
-  for (int it = 0; it < ctx->tune.mg_post; ++it) {
-    smooth<T>(F, l, s, 0);
-    smooth<T>(F, l, s, 1);
-  }
+  smooth_sweeps<T>(ctx, F, l, s, ctx->tune.mg_post);
 }
 
 // Accumulate the timed finest-level smoother launches of the last cycle (the stream
@@ -868,8 +1053,8 @@ static void collect_smooth(itokmc_ctx* ctx, FieldState* F) {
   for (int i = 0; i < F->sm_pending; ++i) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, F->sm_ev[2 * i], F->sm_ev[2 * i + 1]) == hipSuccess) {
-      ctx->phase_ms[PH_SMOOTH_FINE] += ms;
-      ctx->phase_calls[PH_SMOOTH_FINE] += 1;
+      ctx->phase_ms[F->sm_phase[i]] += ms;
+      ctx->phase_calls[F->sm_phase[i]] += 1;
     }
   }
   F->sm_pending = 0;

@@ -36,7 +36,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
            "itokmc_ensemble_last_error"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
-          "field_push", "count", "merge", "field_prep", "smooth_fine"]
+          "field_push", "count", "merge", "field_prep", "smooth_fine", "sweep_fine"]
 
 
 class GridDesc(ctypes.Structure):
@@ -60,7 +60,7 @@ class Coeffs(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("mg_pre", "mg_post", "bottom_sweeps", "use_graph",
-                                              "extrapolate", "pad0")]
+                                              "extrapolate", "fused_sweeps")]
 
 
 class SeedDesc(ctypes.Structure):
@@ -79,8 +79,8 @@ class Diag(ctypes.Structure):
                 ("merged_cells", ctypes.c_uint64), ("step", ctypes.c_uint32),
                 ("solver_cycles", ctypes.c_int32), ("solver_relres", ctypes.c_double),
                 ("rho_sum", ctypes.c_double), ("overflow", ctypes.c_uint32),
-                ("pad0", ctypes.c_uint32), ("particle_steps", ctypes.c_uint64),
-                ("merge_skipped", ctypes.c_uint32), ("pad1", ctypes.c_uint32),
+                ("occupied_cells", ctypes.c_uint32), ("particle_steps", ctypes.c_uint64),
+                ("merge_skipped", ctypes.c_uint32), ("queued_cells", ctypes.c_uint32),
                 ("solver_cycles_total", ctypes.c_uint64), ("solves_total", ctypes.c_uint64)]
 
     def as_dict(self):
@@ -357,7 +357,7 @@ class Sim:
     def tuning(self):
         t = Tuning()
         self._check(lib().itokmc_get_tuning(self.h, ctypes.byref(t)))
-        return {n: getattr(t, n) for n, _ in Tuning._fields_ if n != "pad0"}
+        return {n: getattr(t, n) for n, _ in Tuning._fields_}
 
     def set_tuning(self, **kw):
         t = Tuning()
