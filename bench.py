@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 #   deposit (per particle): read cell 4 + offsets 3S + id 8 + weight 4
 #   scatter (per particle): read cell 4 + rank 4 + offsets 3S + weight 4 + id 8, write
 #                      cell 4 + offsets 3S + weight 4 + id 8
-#   couple (per particle of a queued cell, merging on): read and write cell, offsets,
+#   couple (per particle gathered by the wavefront-per-cell coupling kernel: cells that
+#                      merge or hold many particles): read and write cell, offsets,
 #                      weight and id
 #   smooth_fine (per finest-level cell and launch of one colour): read u and eps of every
 #                      cell, f of the cells of the colour, write u of those cells: 3S
@@ -313,9 +314,7 @@ def main():
         if ph in ("smooth_fine", "sweep_fine"):
             units = ncell * launches
         elif ph == "couple":
-            if not cfg.get("n_ppc"):
-                continue  # without merging only some cells are visited
-            units = psteps_r
+            units = d2.get("couple_pieces", 0) - d1.get("couple_pieces", 0)
         else:
             units = psteps_r
         per_launch = bytes_per_unit(ph, S) * units / launches
@@ -344,7 +343,8 @@ def main():
                    "weight_end": d1["weight"], "field": cfg.get("field"),
                    "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": rc,
                    "occupied_cells_end": d2.get("occupied_cells"),
-                   "queued_cells_end": d2.get("queued_cells")},
+                   "queued_cells_end": d2.get("queued_cells"),
+                   "wavefront_coupled_cells_end": d2.get("wave_cells")},
         "profiled_window": {"ms_per_step": ms_p / args.steps, "status": rc_p,
                             "particle_steps": psteps_p},
         "phase_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},

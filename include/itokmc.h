@@ -127,6 +127,10 @@ typedef struct {
   uint32_t queued_cells;          /* cells coupled (and merged) by the last step      */
   uint64_t solver_cycles_total;   /* multigrid cycles over all field solves          */
   uint64_t solves_total;          /* field solves performed                           */
+  uint64_t couple_pieces;         /* cumulative particles gathered by the wavefront
+                                     coupling pass (cells with merging or many particles) */
+  uint32_t wave_cells;            /* cells of the last step's wavefront coupling pass  */
+  uint32_t pad2;
 } itokmc_diag;
 
 /* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid). */
@@ -195,10 +199,11 @@ int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
 
 /* Per-phase timing with HIP events recorded around each kernel phase on the
  * context's stream (off by default).  Phases: 0 push, 1 photons, 2 bin scan,
- * 3 scatter, 4 KMC, 5 coupling kernel, 6 charge-deposit kernel, 7 field solve (with
- * the field from the potential), 8 field push, 9 recount, 10 larger merge tiers,
- * 11 deposit clearing and right-hand side, 12 finest-level single-colour smoother
- * launches, 13 finest-level fused sweeps (both inside the solve; one count per launch).  phase_times synchronises, writes accumulated
+ * 3 scatter, 4 KMC, 5 coupling kernel (one wavefront per cell), 6 charge-deposit
+ * kernel, 7 field solve (with the field from the potential), 8 field push, 9 recount,
+ * 10 larger merge tiers, 11 deposit clearing and right-hand side, 12 finest-level
+ * single-colour smoother launches, 13 finest-level fused sweeps (both inside the
+ * solve; one count per launch), 14 light coupling pass (one lane per cell).  phase_times synchronises, writes accumulated
  * milliseconds and launch counts for the first n phases, and clears them if reset is
  * nonzero. */
 int itokmc_set_profiling(itokmc_ctx* ctx, int on);

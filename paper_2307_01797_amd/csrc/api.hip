@@ -165,6 +165,8 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(nc * 4);                        // 30 cells for the full KMC pass
   put(d->field_mode == ITOKMC_FIELD_POISSON ? nc * 24 : 64);  // 31 rates for the full pass
   put(nc * 4);                        // 32 huge (large merge list)
+  put(nc * 4);                        // 33 cells for the wavefront coupling pass
+  put(nc * 4);                        // 34 cells to merge after the light pass
   L->total = o;
 }
 
@@ -245,6 +247,8 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->heavy = (uint32_t*)(a + L.off[30]);
   ctx->rates = (double*)(a + L.off[31]);
   ctx->huge = (uint32_t*)(a + L.off[32]);
+  ctx->cfull = (uint32_t*)(a + L.off[33]);
+  ctx->cmerge = (uint32_t*)(a + L.off[34]);
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);
@@ -352,7 +356,7 @@ int itokmc_react(itokmc_ctx* ctx, double dt) {
   phase_begin(ctx, PH_KMC);
   if (!rc) rc = check_hip(ctx, launch_kmc_step(ctx, k, fr), "kmc");
   phase_end(ctx, PH_KMC);
-  phase_begin(ctx, PH_COUPLE);  // ended inside: coupling kernel, then the merge tiers
+  phase_begin(ctx, PH_COUPLE_LIGHT);  // ended inside: light pass, wavefront pass, merge tiers
   if (!rc) rc = check_hip(ctx, launch_couple(ctx, k), "couple");
   if (rc) return rc;
   ctx->cur = 1 - ctx->cur;
@@ -434,6 +438,8 @@ int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
   out->merge_skipped = c.merge_skipped;
   out->occupied_cells = c.n_occ;
   out->queued_cells = c.n_work;
+  out->wave_cells = c.n_cfull + c.n_cmerge;
+  out->couple_pieces = c.couple_pieces;
   out->solver_cycles_total = ctx->total_cycles;
   out->solves_total = ctx->total_solves;
   if (c.overflow) return set_error(ctx, ITOKMC_ECAPACITY, "capacity exceeded (flags %u)", c.overflow);

@@ -1,10 +1,15 @@
-// KMC-particle coupling (section "KMC-particle coupling", eq. w): one wavefront per
-// queued cell.  A net gain dN > 0 becomes min(dN, n_new) new particles of weight
-// dN div M, the remainder going to the first, placed uniformly in the cell and
-// appended to the bank; a net loss removes weight from the cell's particles in
-// ascending id order (a particle reaching weight 0 is dead and dropped by the next
-// binning).  Superparticle management (merge/split to n_ppc per cell) is applied to
-// the cell afterwards when enabled.
+// KMC-particle coupling (section "KMC-particle coupling", eq. w).  A net gain dN > 0
+// becomes min(dN, n_new) new particles of weight dN div M, the remainder going to the
+// first, placed uniformly in the cell and appended to the bank; a net loss removes
+// weight from the cell's particles in ascending id order (a particle reaching weight 0
+// is dead and dropped by the next binning).  Superparticle management (merge/split to
+// n_ppc per cell) is applied to the cell afterwards when enabled.
+//
+// Most queued cells hold a handful of particles.  A light pass takes one cell per lane:
+// it does the removal and the products of cells with at most kLightMax particles and
+// products, checks whether they need merging or splitting, and queues the cells that
+// do (merge only) and the larger cells (everything) for the wavefront-per-cell pass.
+// The arithmetic and its order are the same on both paths.
 #include <math.h>
 
 #include "device.hpp"
@@ -19,22 +24,91 @@ namespace {
 template <typename T>
 __device__ __forceinline__ T* as(void* p) { return reinterpret_cast<T*>(p); }
 
+constexpr uint32_t kLightMax = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_couple_light(Bank b, Counters* ctr, StepConst K,
+                                                     const uint32_t* work, const uint32_t* occ,
+                                                     const uint32_t* start, const int32_t* dN,
+                                                     const uint32_t* cbase, int n_new, int n_ppc,
+                                                     uint32_t* full_list, uint32_t* merge_list) {
+  __shared__ uint32_t sh[18];
+  const uint32_t nwork = ctr->n_work, n_occ = ctr->n_occ, sorted = ctr->sorted;
+  uint64_t created = 0, removed = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nwork; base += gridDim.x * blockDim.x) {
+    const uint32_t t = base + threadIdx.x;
+    bool to_full = false, to_merge = false;
+    uint32_t j = 0;
+    if (t < nwork) {
+      j = work[t];
+      const uint32_t c = occ[j];
+      const uint32_t s = start[c], e = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
+      const int32_t d = dN[j];
+      const uint32_t M = d > 0 ? ((uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new) : 0u;
+      if (e - s > kLightMax || M > kLightMax) {
+        to_full = true;
+      } else {
+        if (d < 0) removed += remove_weight_lane(b, s, e, (uint32_t)(-d));
+        uint32_t wb = 0, wr = 0, pb = 0;
+        if (M) {
+          wb = (uint32_t)d / M;
+          wr = (uint32_t)d % M;
+          pb = cbase[j];
+          for (uint32_t k = 0; k < M; ++k) {
+            const uint32_t q = pb + k;
+            if (q < K.cap) write_product<T>(b, q, c, c, k, wb, wr, K.step, K.key);
+            else atomicOr(&ctr->overflow, 1u);
+          }
+          created += M;
+        }
+        if (n_ppc > 0) {  // the merge trigger, as merge_cell evaluates it
+          uint32_t m = 0, wmax = 0;
+          for (uint32_t q = s; q < e; ++q) {
+            const uint32_t w = b.w[q];
+            if (w > 0) { ++m; wmax = w > wmax ? w : wmax; }
+          }
+          if (M) {
+            m += M;
+            const uint32_t w0 = wb + wr;
+            wmax = w0 > wmax ? w0 : wmax;
+          }
+          to_merge = m > 0 && (m > (uint32_t)n_ppc || (m < (uint32_t)n_ppc && wmax >= 2));
+        }
+      }
+    }
+    const uint32_t qf = block_append(&ctr->n_cfull, to_full ? 1u : 0u, sh);
+    if (to_full) full_list[qf] = j;
+    const uint32_t qm = block_append(&ctr->n_cmerge, to_merge ? 1u : 0u, sh);
+    if (to_merge) merge_list[qm] = j;
+  }
+  created = wave_sum64(created);
+  removed = wave_sum64(removed);
+  if (lane_id() == 0) {
+    if (created) atomicAdd(&ctr->created, (unsigned long long)created);
+    if (removed) atomicAdd(&ctr->removed, (unsigned long long)removed);
+  }
+}
+
+// One wavefront per cell: the cells of full_list (removal, products, merge) and then
+// those of merge_list (merge only; the light pass did the rest).
 template <typename T>
 __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which, StepConst K,
-                                              const uint32_t* work, const uint32_t* occ,
-                                              const uint32_t* start, const int32_t* dN,
-                                              const uint32_t* cbase, int n_new, int n_ppc,
-                                              uint32_t* big) {
-  const uint32_t nwork = ctr->n_work, n_occ = ctr->n_occ, sorted = ctr->sorted;
+                                              const uint32_t* full_list, const uint32_t* merge_list,
+                                              const uint32_t* occ, const uint32_t* start,
+                                              const int32_t* dN, const uint32_t* cbase, int n_new,
+                                              int n_ppc, uint32_t* big) {
+  const uint32_t nfull = ctr->n_cfull, nwork = nfull + ctr->n_cmerge, n_occ = ctr->n_occ,
+                 sorted = ctr->sorted;
   const int lane = lane_id();
-  uint64_t created = 0, removed = 0, merged = 0;
+  uint64_t created = 0, removed = 0, merged = 0, pieces = 0;
   for (uint32_t t = blockIdx.x; t < nwork; t += gridDim.x) {
-    const uint32_t j = work[t];
+    const bool full = t < nfull;
+    const uint32_t j = full ? full_list[t] : merge_list[t - nfull];
     const uint32_t c = occ[j];
     // the cell's sorted range ends where the next occupied cell's begins
     const uint32_t s = start[c], e = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
     const int32_t d = dN[j];
-    if (d < 0) removed += remove_weight(b, s, e, (uint32_t)(-d));
+    if (full && d < 0) removed += remove_weight(b, s, e, (uint32_t)(-d));
     uint32_t M = 0, wb = 0, wr = 0, base = 0;
     if (d > 0) {
       M = (uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new;
@@ -43,12 +117,13 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
       base = cbase[j];  // slots reserved by the KMC pass
     }
     // new particles, one per lane (n_new <= 64), into the reserved slots
-    if ((uint32_t)lane < M) {
+    if (full && (uint32_t)lane < M) {
       const uint32_t q = base + (uint32_t)lane;
       if (q < K.cap) write_product<T>(b, q, c, c, (uint32_t)lane, wb, wr, K.step, K.key);
       else atomicOr(&ctr->overflow, 1u);
     }
-    created += M;
+    if (full) created += M;
+    pieces += (e - s) + M;
     if (n_ppc > 0) {
       __syncthreads();  // removal and product stores visible before the merge gathers them
       const int r = merge_cell<T, kMergeTiny>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
@@ -59,6 +134,7 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
     if (created) atomicAdd(&ctr->created, (unsigned long long)created);
     if (removed) atomicAdd(&ctr->removed, (unsigned long long)removed);
     if (merged) atomicAdd(&ctr->merged, (unsigned long long)merged);
+    if (pieces) atomicAdd(&ctr->couple_pieces, (unsigned long long)pieces);
   }
 }
 
@@ -94,17 +170,31 @@ __global__ void __launch_bounds__(64) k_merge_tier(Bank b, Counters* ctr, int wh
 
 hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k) {
   const int dest = 1 - ctx->cur;  // coupling acts on the freshly binned bank
+  const bool f64 = ctx->d.precision == ITOKMC_FP64;
+  int gl = (int)((ctx->ncell + 255) / 256);
+  gl = gl < 1 ? 1 : (gl > 4096 ? 4096 : gl);
+  if (f64)
+    k_couple_light<double><<<gl, 256, 0, ctx->s>>>(ctx->bank[dest], ctx->ctr, k, ctx->work, ctx->occ,
+                                                   ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
+                                                   ctx->d.n_ppc, ctx->cfull, ctx->cmerge);
+  else
+    k_couple_light<float><<<gl, 256, 0, ctx->s>>>(ctx->bank[dest], ctx->ctr, k, ctx->work, ctx->occ,
+                                                  ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
+                                                  ctx->d.n_ppc, ctx->cfull, ctx->cmerge);
+  hipError_t el = hipGetLastError();
+  phase_end(ctx, PH_COUPLE_LIGHT);
+  if (el != hipSuccess) return el;
+  phase_begin(ctx, PH_COUPLE);  // the wavefront-per-cell kernel alone
   int g = (int)(ctx->ncell < 65536u ? ctx->ncell : 65536u);
   if (g < 1) g = 1;
-  const bool f64 = ctx->d.precision == ITOKMC_FP64;
   if (f64)
     k_couple<double><<<g, 64, merge_lds_bytes<double>(ctx->d.n_ppc), ctx->s>>>(
-        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN, ctx->cbase,
-        ctx->d.n_new, ctx->d.n_ppc, ctx->big);
+        ctx->bank[dest], ctx->ctr, dest, k, ctx->cfull, ctx->cmerge, ctx->occ, ctx->start, ctx->dN,
+        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ctx->big);
   else
     k_couple<float><<<g, 64, merge_lds_bytes<float>(ctx->d.n_ppc), ctx->s>>>(
-        ctx->bank[dest], ctx->ctr, dest, k, ctx->work, ctx->occ, ctx->start, ctx->dN, ctx->cbase,
-        ctx->d.n_new, ctx->d.n_ppc, ctx->big);
+        ctx->bank[dest], ctx->ctr, dest, k, ctx->cfull, ctx->cmerge, ctx->occ, ctx->start, ctx->dN,
+        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ctx->big);
   hipError_t e = hipGetLastError();
   phase_end(ctx, PH_COUPLE);
   if (e != hipSuccess || ctx->d.n_ppc == 0) return e;

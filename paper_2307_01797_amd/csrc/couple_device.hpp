@@ -42,6 +42,28 @@ __device__ inline uint64_t remove_weight(Bank b, uint32_t s, uint32_t e, uint32_
   return removed;
 }
 
+// The same removal by one lane (cells with few particles): the smallest id first.
+__device__ inline uint64_t remove_weight_lane(Bank b, uint32_t s, uint32_t e, uint32_t R) {
+  uint64_t removed = 0;
+  while (R > 0) {
+    uint64_t best = ~0ull;
+    uint32_t bi = 0xFFFFFFFFu;
+    for (uint32_t q = s; q < e; ++q) {
+      if (b.w[q] > 0) {
+        const uint64_t id = b.id[q];
+        if (id < best) { best = id; bi = q; }
+      }
+    }
+    if (bi == 0xFFFFFFFFu) break;
+    const uint32_t w = b.w[bi];
+    const uint32_t take = w < R ? w : R;
+    b.w[bi] = w - take;
+    R -= take;
+    removed += take;
+  }
+  return removed;
+}
+
 // Write the k-th of M KMC products of cell c (local index lc for ids and streams) into
 // bank slot q: offsets uniform in the cell, weight wb (+ wr for the first).
 template <typename T>

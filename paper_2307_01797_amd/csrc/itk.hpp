@@ -39,6 +39,9 @@ struct Counters {
   unsigned long long pushed;   // live particles advanced by the transport kernels
   uint32_t merge_skipped;      // cells too large for the LDS merge (left unmerged)
   uint32_t n_big;              // cells deferred to the mid-size merge staging
+  uint32_t n_cfull;            // cells for the wavefront coupling pass (everything)
+  uint32_t n_cmerge;           // cells for the wavefront coupling pass (merge only)
+  unsigned long long couple_pieces;  // particles gathered by the wavefront coupling pass
 };
 
 // Device-side copy of the per-step constants shared by the kernels.
@@ -88,6 +91,8 @@ struct itokmc_ctx {
   uint32_t* cbase = nullptr;              // first reserved bank slot of a cell's products
   uint32_t* big = nullptr;                // occupied-cell indices for the mid-size merge pass
   uint32_t* huge = nullptr;               // occupied-cell indices for the large merge pass
+  uint32_t* cfull = nullptr;              // cells for the wavefront coupling pass
+  uint32_t* cmerge = nullptr;             // cells to merge after the light coupling pass
   uint32_t* heavy = nullptr;              // occupied-cell indices for the full KMC pass
   double* rates = nullptr;                // 3 per occupied cell: rates handed to the full pass
   uint32_t* blocksums = nullptr;          // scan scratch
@@ -119,7 +124,7 @@ namespace itk {
 // phases timed when profiling is on
 enum Phase { PH_PUSH = 0, PH_PHOTON, PH_SCAN, PH_SCATTER, PH_KMC, PH_COUPLE, PH_DEPOSIT,
              PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_MERGE, PH_FIELD_PREP, PH_SMOOTH_FINE,
-             PH_SWEEP_FINE, PH_NUM };
+             PH_SWEEP_FINE, PH_COUPLE_LIGHT, PH_NUM };
 void phase_begin(itokmc_ctx* ctx, int phase);
 void phase_end(itokmc_ctx* ctx, int phase);
 int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);

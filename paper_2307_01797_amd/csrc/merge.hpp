@@ -49,6 +49,13 @@ template <> struct Bits<double> {
 // The small path also stages the sort keys of splitting leaves contiguously.
 template <int CAP> struct MergeContig { static constexpr bool value = CAP <= kMergeSmall; };
 
+// In single precision the contiguous path orders pieces by one 64-bit integer: the
+// coordinate's bit pattern (ordered like the non-negative value) above the rank of the
+// piece's id among the cell's pieces, i.e. by (coordinate, id).
+template <typename T, int CAP> struct MergePacked {
+  static constexpr bool value = MergeContig<CAP>::value && sizeof(T) == 4;
+};
+
 template <typename T, int CAP>
 constexpr size_t merge_lds_bytes_c() {
   constexpr size_t S = (size_t)CAP + kMaxMergePpc;
@@ -56,6 +63,7 @@ constexpr size_t merge_lds_bytes_c() {
   constexpr size_t U = sizeof(typename Bits<T>::U);
   return S * (8 + 3 * sizeof(T) + 4 + 2 * 2 + 3)  // store, two index buffers, three tag arrays
          + (MergeContig<CAP>::value ? S * (sizeof(T) + 8) : 0)  // contiguous keys and ids
+         + (MergePacked<T, CAP>::value ? S * 4 : 0)             // id ranks
          + NL * (6 * 4 + 3 * 4 + 6 * U + 1)        // leaf records, per-leaf scratch, extents, axis
          + 64;
 }
@@ -63,6 +71,12 @@ template <typename T>
 inline size_t merge_lds_bytes(int n_ppc) {
   return n_ppc > 0 ? merge_lds_bytes_c<T, kMergeTiny>() : 0;
 }
+
+// (coordinate, id rank) as one ordered integer (single precision; -0 folds to +0).
+__device__ __forceinline__ uint64_t packed_key(float k, uint32_t r) {
+  return ((uint64_t)__float_as_uint(k + 0.0f) << 32) | r;
+}
+__device__ __forceinline__ uint64_t packed_key(double, uint32_t) { return 0; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = lane_id();
@@ -104,9 +118,11 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   uint8_t* otag = (uint8_t*)p; p += (size_t)S;   // splitting leaf owning an ordered slot
   uint8_t* axis = (uint8_t*)p; p += NL;
   constexpr bool contig = MergeContig<CAP>::value;
+  constexpr bool packed = MergePacked<T, CAP>::value;
   p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
-  uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id of slot q (sorting leaves)
+  uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id (packed: key) of slot q
   T* kkey = (T*)p; p += contig ? (size_t)S * sizeof(T) : 0;        // key of slot q
+  uint32_t* idr = (uint32_t*)p; p += packed ? (size_t)S * 4 : 0;   // id rank of store entry
 
   // ---- gather: segment [s, e) then product slots [base, base + M) ----
   uint32_t m = 0, wmax = 0;
@@ -145,6 +161,18 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   if (m > (uint32_t)CAP) return 2;
   if (lane == 0) { Lst[0][0] = 0; Lcn[0][0] = m; LW[0][0] = (uint32_t)Wtot; }
   __syncthreads();
+  if (packed) {  // rank of every piece's id among the cell's pieces (ids are distinct here)
+    for (uint32_t q = (uint32_t)lane; q < m; q += 64) {
+      const uint64_t iq = sid[q];
+      uint32_t r = 0, t = 0;
+      for (; t + 4 <= m; t += 4)
+        r += (sid[t] < iq ? 1u : 0u) + (sid[t + 1] < iq ? 1u : 0u) + (sid[t + 2] < iq ? 1u : 0u) +
+             (sid[t + 3] < iq ? 1u : 0u);
+      for (; t < m; ++t) r += sid[t] < iq ? 1u : 0u;
+      idr[q] = r;
+    }
+    __syncthreads();
+  }
 
   // ---- breadth-first growth, all leaves of a level at once ----
   int cb = 0, nl = 1;
@@ -219,8 +247,12 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         const uint8_t L = tag[cb][q];
         if (L == kNone || !((chm >> L) & 1ull)) continue;
         const uint16_t pq = I[cb][q];
-        kkey[q] = so[axis[L]][pq];
-        kid[q] = sid[pq];
+        if (packed) {
+          kid[q] = packed_key(so[axis[L]][pq], idr[pq]);
+        } else {
+          kkey[q] = so[axis[L]][pq];
+          kid[q] = sid[pq];
+        }
       }
       __syncthreads();
     }
@@ -240,7 +272,15 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       const T kq = so[ax][pq];
       const uint64_t iq = sid[pq];
       uint32_t rank = 0;
-      if (contig) {
+      if (packed) {
+        const uint64_t cq = packed_key(kq, idr[pq]);
+        uint32_t r = Ls;
+        const uint32_t rend = Ls + Ln;
+        for (; r + 4 <= rend; r += 4)
+          rank += (kid[r] < cq ? 1u : 0u) + (kid[r + 1] < cq ? 1u : 0u) + (kid[r + 2] < cq ? 1u : 0u) +
+                  (kid[r + 3] < cq ? 1u : 0u);
+        for (; r < rend; ++r) rank += kid[r] < cq ? 1u : 0u;
+      } else if (contig) {
         uint32_t r = Ls;
         const uint32_t rend = Ls + Ln;
         for (; r + 4 <= rend; r += 4) {
@@ -335,6 +375,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       if (super) {
         const uint32_t wm = sw[pm];
         sid[np] = sid[pm];
+        if (packed) idr[np] = idr[pm];
         for (int a = 0; a < 3; ++a) so[a][np] = so[a][pm];
         sw[np] = wm - wl;
         sw[pm] = wl;

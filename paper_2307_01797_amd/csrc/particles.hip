@@ -384,6 +384,8 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* 
     ctr->n_big = 0;
     ctr->n_heavy = 0;
     ctr->n_huge = 0;
+    ctr->n_cfull = 0;
+    ctr->n_cmerge = 0;
   }
 }
 

@@ -36,7 +36,8 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
            "itokmc_ensemble_last_error"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
-          "field_push", "count", "merge", "field_prep", "smooth_fine", "sweep_fine"]
+          "field_push", "count", "merge", "field_prep", "smooth_fine", "sweep_fine",
+          "couple_light"]
 
 
 class GridDesc(ctypes.Structure):
@@ -81,7 +82,9 @@ class Diag(ctypes.Structure):
                 ("rho_sum", ctypes.c_double), ("overflow", ctypes.c_uint32),
                 ("occupied_cells", ctypes.c_uint32), ("particle_steps", ctypes.c_uint64),
                 ("merge_skipped", ctypes.c_uint32), ("queued_cells", ctypes.c_uint32),
-                ("solver_cycles_total", ctypes.c_uint64), ("solves_total", ctypes.c_uint64)]
+                ("solver_cycles_total", ctypes.c_uint64), ("solves_total", ctypes.c_uint64),
+                ("couple_pieces", ctypes.c_uint64), ("wave_cells", ctypes.c_uint32),
+                ("pad2", ctypes.c_uint32)]
 
     def as_dict(self):
         d = {}
