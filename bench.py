@@ -13,6 +13,7 @@ the FP64 oracle on a bounded sample of the same workload on one host core.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,19 +31,16 @@ HBM_PEAK_GBS = 8000.0
 #   couple (per particle gathered by the wavefront-per-cell coupling kernel: cells that
 #                      merge or hold many particles): read and write cell, offsets,
 #                      weight and id
-#   smooth_fine (per finest-level cell and launch of one colour): read u and eps of every
-#                      cell, f of the cells of the colour, write u of those cells: 3S
-#   sweep_fine (per finest-level cell and fused launch, one full red-black sweep): read
-#                      u, eps and f, write u: 4S
+#   smooth_fine (per finest-level cell and launch of one colour, split red-black order):
+#                      read u and eps of the other colour's cells, f and eps of the
+#                      colour's cells, write u of the colour's cells: 2.5 S
 KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k_field_deposit_lds",
-           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_rb<fine>",
-           "sweep_fine": "k_smooth_fused<fine>"}
+           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_split"}
 
 
 def bytes_per_unit(phase, S):
     return {"push": 24 + 6 * S, "field_push": 24 + 6 * S, "deposit": 16 + 3 * S,
-            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 3 * S,
-            "sweep_fine": 4 * S}[phase]
+            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 5 * S / 2}[phase]
 
 
 def parse():
@@ -68,22 +66,30 @@ def parse():
     return p.parse_args()
 
 
-def traffic_from_profile(kernel_file):
-    """Measured HBM bytes per launch of the dominant kernel, if a counter summary for
-    the current source of that kernel is committed; else None."""
+def traffic_from_profile(kernel_label):
+    """Measured HBM bytes per launch of a kernel from a committed counter summary
+    (profiles/*_traffic.md, lines `key: value`), or None when there is none or when a
+    source file it names has changed since the counters were taken."""
+    import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2307_01797_amd", "csrc", kernel_file)
-    if not (os.path.exists(path) and os.path.exists(src)):
-        return None
-    try:
-        t = json.load(open(path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if t.get("source_sha256") != h:
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        kv = {}
+        for line in open(path):
+            m = re.match(r"^- (\w+): (.+)$", line.strip())
+            if m:
+                kv[m.group(1)] = m.group(2).strip()
+        if kv.get("kernel") != kernel_label or "sources" not in kv:
+            continue
+        h = hashlib.sha256()
+        for rel in kv["sources"].split():
+            src = os.path.join(ROOT, rel)
+            if not os.path.exists(src):
+                return None
+            h.update(open(src, "rb").read())
+        if h.hexdigest() != kv.get("source_sha256"):
             return None
-        return t.get("bytes_per_particle")
-    except Exception:
-        return None
+        return int(kv["hbm_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(cfg, budget_s):
@@ -311,7 +317,7 @@ def main():
         tot_ms, launches = phases.get(ph, (0.0, 0))
         if not launches or tot_ms <= 0:
             continue
-        if ph in ("smooth_fine", "sweep_fine"):
+        if ph == "smooth_fine":
             units = ncell * launches
         elif ph == "couple":
             units = d2.get("couple_pieces", 0) - d1.get("couple_pieces", 0)
@@ -325,6 +331,9 @@ def main():
                      "launches": launches, "bytes_per_launch": int(per_launch),
                      "total_ms": round(tot_ms, 3)}
     roof = max(roofs.values(), key=lambda r: r["total_ms"]) if roofs else None
+    if roof is not None:
+        ph = next(p for p, r in roofs.items() if r is roof)
+        roof["traffic"] = traffic_from_profile(KERNELS[ph])
     out = {
         "metric": "particle-steps/s (push+sort+deposit+KMC)",
         "value": value,

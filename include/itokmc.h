@@ -187,12 +187,13 @@ int itokmc_set_field(itokmc_ctx* ctx, const double* phi);
  * tolerance): multigrid pre/post red-black sweeps per level (default 2/2, each 0..8,
  * sum >= 1), bottom-level sweeps (0 = automatic), capture of the refinement cycle in
  * a HIP graph (default on), linear-in-time extrapolation of the potential as the
- * initial guess (default on), fused sweeps (0 default: one launch per colour; 1 or 2:
- * levels at least 128 cells wide smooth pairs of sweeps with one out-of-place launch
- * per sweep on 8- or 4-row tiles, giving results identical to single-colour launches).
- * set_tuning copies the struct; EINVAL if out of range. */
+ * initial guess (default on), and the finest level's storage order (0 default: split
+ * red-black, each x row holding its cells of one colour in its first half and of the
+ * other colour in its second, so that a one-colour sweep moves whole lines; 1: natural
+ * order; both give identical results; a grid that cannot be coarsened always uses
+ * natural order).  set_tuning copies the struct; EINVAL if out of range. */
 typedef struct {
-  int32_t mg_pre, mg_post, bottom_sweeps, use_graph, extrapolate, fused_sweeps;
+  int32_t mg_pre, mg_post, bottom_sweeps, use_graph, extrapolate, fine_layout;
 } itokmc_tuning;
 int itokmc_set_tuning(itokmc_ctx* ctx, const itokmc_tuning* tuning);
 int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
@@ -202,8 +203,8 @@ int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
  * 3 scatter, 4 KMC, 5 coupling kernel (one wavefront per cell), 6 charge-deposit
  * kernel, 7 field solve (with the field from the potential), 8 field push, 9 recount,
  * 10 larger merge tiers, 11 deposit clearing and right-hand side, 12 finest-level
- * single-colour smoother launches, 13 finest-level fused sweeps (both inside the
- * solve; one count per launch), 14 light coupling pass (one lane per cell).  phase_times synchronises, writes accumulated
+ * smoother launches (one colour each, inside the solve; one count per launch), 13 light
+ * coupling pass (one lane per cell).  phase_times synchronises, writes accumulated
  * milliseconds and launch counts for the first n phases, and clears them if reset is
  * nonzero. */
 int itokmc_set_profiling(itokmc_ctx* ctx, int on);

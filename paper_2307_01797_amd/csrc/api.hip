@@ -573,7 +573,7 @@ int itokmc_set_field(itokmc_ctx* ctx, const double* phi) {
 int itokmc_set_tuning(itokmc_ctx* ctx, const itokmc_tuning* t) {
   if (!ctx || !t) return ITOKMC_EINVAL;
   if (t->mg_pre < 0 || t->mg_pre > 8 || t->mg_post < 0 || t->mg_post > 8 || t->mg_pre + t->mg_post < 1 ||
-      t->bottom_sweeps < 0 || t->bottom_sweeps > 4096 || t->fused_sweeps < 0 || t->fused_sweeps > 2)
+      t->bottom_sweeps < 0 || t->bottom_sweeps > 4096 || t->fine_layout < 0 || t->fine_layout > 1)
     return set_error(ctx, ITOKMC_EINVAL, "invalid tuning");
   ctx->tune = *t;
   field_reset_graph(ctx);

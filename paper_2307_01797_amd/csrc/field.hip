@@ -40,7 +40,6 @@ struct Level {
   int nx, ny, nz;
   uint32_t n;
   void* u;    // correction
-  void* u2;   // second correction buffer for the out-of-place fused sweep
   void* f;    // right-hand side (scaled by h^2)
   void* eps;  // cell coefficient 1 + sigma dt / eps0
 };
@@ -53,9 +52,6 @@ template <typename T>
 __device__ __forceinline__ T* tp(void* p) { return reinterpret_cast<T*>(p); }
 template <typename T>
 __device__ __forceinline__ const T* ctp(const void* p) { return reinterpret_cast<const T*>(p); }
-
-__device__ __forceinline__ double hmean(double a, double b) { return 2.0 * a * b / (a + b); }
-__device__ __forceinline__ float hmean(float a, float b) { return 2.0f * a * b / (a + b); }
 
 constexpr int kRedBlocks = 1024;  // fixed grid of the norm kernels: one partial per block
 
@@ -393,20 +389,62 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
 
 // ---- grid passes ------------------------------------------------------------------
 
+// Storage positions of a cell and of its face neighbours.  Natural order on every
+// level: c = i + nx (j + ny k).  Split red-black order on the finest level (nx even):
+// an x row keeps its colour-0 cells ((i + j + k) even) at positions 0 .. nx/2 - 1 and
+// its colour-1 cells at nx/2 .. nx - 1, each at i / 2.  Every face neighbour has the
+// other colour: at the same half-row position in the four neighbouring rows, and at
+// the same or the adjacent position in the cell's own row.  A sweep of one colour
+// then reads and writes whole lines of each half-row.
+struct NatAt {
+  ptrdiff_t c, sy, sz;
+  __device__ __forceinline__ size_t operator()(int dx, int dy, int dz) const {
+    return (size_t)(c + dx + dy * sy + dz * sz);
+  }
+};
+
+struct SplitAt {
+  ptrdiff_t own, oth, sy, sz;
+  int odd;  // i & 1
+  __device__ __forceinline__ size_t operator()(int dx, int dy, int dz) const {
+    if ((dx | dy | dz) == 0) return (size_t)own;
+    return (size_t)(oth + (dx < 0 ? odd - 1 : (dx > 0 ? odd : 0)) + dy * sy + dz * sz);
+  }
+};
+
+__device__ __forceinline__ NatAt nat_at(int i, int j, int k, int nx, int ny) {
+  const ptrdiff_t sy = nx, sz = (ptrdiff_t)nx * ny;
+  return NatAt{(ptrdiff_t)i + sy * j + sz * k, sy, sz};
+}
+
+__device__ __forceinline__ SplitAt split_at(int i, int j, int k, int nx, int ny) {
+  const ptrdiff_t sy = nx, sz = (ptrdiff_t)nx * ny;
+  const ptrdiff_t row = sy * j + sz * k;
+  const int h = nx >> 1, q = (i + j + k) & 1;
+  return SplitAt{row + q * h + (i >> 1), row + (1 - q) * h + (i >> 1), sy, sz, i & 1};
+}
+
+template <bool kSplit>
+__device__ __forceinline__ size_t pos_of(int i, int j, int k, int nx, int ny) {
+  if constexpr (kSplit) return (size_t)split_at(i, j, k, nx, ny).own;
+  else return (size_t)nat_at(i, j, k, nx, ny).c;
+}
+
 template <typename T>
 __global__ void k_zero(T* p, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = (T)0;
 }
 
-// Fine-level coefficient and right-hand side b = dx^2 rho / eps0 (+ the lift of the
-// anode potential on the top layer), both scaled by dx^2; accumulates ||b||^2.
+// Fine-level coefficient (at its storage position) and right-hand side
+// b = dx^2 rho / eps0 (+ the lift of the anode potential on the top layer), both
+// scaled by dx^2; accumulates ||b||^2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t* nplus,
                                                    const uint32_t* nminus,
                                                    const typename DepAcc<T>::S* ne,
                                                    const typename DepAcc<T>::S* sig,
-                                                   double sig_scale, double V, T* eps, double* b,
-                                                   double* partial) {
+                                                   double sig_scale, double V, int split, T* eps,
+                                                   double* b, double* partial) {
   const uint32_t n = K.ncell;
   const double dV = K.dx * K.dx * K.dx;
   const double qscale = K.dx * K.dx * kE / (kEps0 * dV);
@@ -416,10 +454,11 @@ __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t*
     double bb = 0.0;
     if (c < n) {
       const double e = 1.0 + sig_scale * DepAcc<T>::dec0(sig[c]);
-      eps[c] = (T)e;
+      const uint32_t row = c / (uint32_t)K.nx, k = row / (uint32_t)K.ny;
+      const int i = (int)(c - row * (uint32_t)K.nx), j = (int)(row - k * (uint32_t)K.ny);
+      eps[split ? pos_of<true>(i, j, (int)k, K.nx, K.ny) : (size_t)c] = (T)e;
       const double rho_units = (double)nplus[c] - (double)nminus[c] - DepAcc<T>::dec1(ne[c]);
       bb = qscale * rho_units;
-      const uint32_t k = c / ((uint32_t)K.nx * (uint32_t)K.ny);
       if (k == (uint32_t)K.nz - 1) bb += 2.0 * (double)(T)e * V;
       b[c] = bb;
     }
@@ -430,38 +469,17 @@ __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t*
 }
 
 template <typename T>
-__global__ void k_eps_restrict(const T* ef, int fnx, int fny, T* ec, int cnx, int cny, int cnz) {
+__global__ void k_eps_restrict(const T* ef, int fnx, int fny, int fsplit, T* ec, int cnx, int cny, int cnz) {
   const uint32_t n = (uint32_t)cnx * cny * cnz;
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     const int i = c % cnx, j = (c / cnx) % cny, k = c / (cnx * cny);
     double s = 0.0;
     for (int d = 0; d < 8; ++d) {
       const int fi = 2 * i + (d & 1), fj = 2 * j + ((d >> 1) & 1), fk = 2 * k + (d >> 2);
-      s += (double)ef[(size_t)fi + (size_t)fnx * ((size_t)fj + (size_t)fny * fk)];
+      s += (double)ef[fsplit ? pos_of<true>(fi, fj, fk, fnx, fny) : pos_of<false>(fi, fj, fk, fnx, fny)];
     }
     ec[c] = (T)(s * 0.125);
   }
-}
-
-// Operator of the scaled system at one cell (homogeneous boundary values):
-// sum over faces of beta (u_c - u_nb) plus 2 eps_c u_c on the Dirichlet faces.
-template <typename R, typename U, typename E>
-__device__ __forceinline__ void stencil(const U* u, const E* eps, int nx, int ny, int nz, int i, int j,
-                                        int k, R& diag, R& offsum) {
-  const size_t c = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
-  const R ec = (R)eps[c];
-  R d = 0, s = 0;
-  if (i > 0) { const R b = hmean(ec, (R)eps[c - 1]); d += b; s += b * (R)u[c - 1]; }
-  if (i < nx - 1) { const R b = hmean(ec, (R)eps[c + 1]); d += b; s += b * (R)u[c + 1]; }
-  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  if (j > 0) { const R b = hmean(ec, (R)eps[c - sy]); d += b; s += b * (R)u[c - sy]; }
-  if (j < ny - 1) { const R b = hmean(ec, (R)eps[c + sy]); d += b; s += b * (R)u[c + sy]; }
-  if (k > 0) { const R b = hmean(ec, (R)eps[c - sz]); d += b; s += b * (R)u[c - sz]; }
-  else d += (R)2 * ec;
-  if (k < nz - 1) { const R b = hmean(ec, (R)eps[c + sz]); d += b; s += b * (R)u[c + sz]; }
-  else d += (R)2 * ec;
-  diag = d;
-  offsum = s;
 }
 
 // Harmonic mean for the smoother: exact in double; fast reciprocal in single precision
@@ -470,53 +488,83 @@ __device__ __forceinline__ void stencil(const U* u, const E* eps, int nx, int ny
 __device__ __forceinline__ double hmean_s(double a, double b) { return 2.0 * a * b / (a + b); }
 __device__ __forceinline__ float hmean_s(float a, float b) { return __fdividef(2.0f * a * b, a + b); }
 
-// Single-precision-path operator row through value accessors a(dx, dy, dz) of the
-// correction and of the coefficient at the neighbour (dx, dy, dz) of cell (i, j, k), so
-// the smoothers reading HBM and reading LDS share one arithmetic order.
+// Operator of the scaled system at one cell (homogeneous boundary values): sum over
+// faces of beta (u_c - u_nb), beta the harmonic mean of the two cells' coefficients,
+// plus 2 eps_c u_c on the Dirichlet z faces; x and y faces are Neumann.  Returned as
+// the diagonal and the neighbour sum.  Working-precision row through value accessors
+// a(dx, dy, dz) of the correction and of the coefficient at the neighbour (dx, dy, dz)
+// of cell (i, j, k), so the smoothers reading HBM and reading LDS share one arithmetic
+// order.  All thirteen values are read before any arithmetic (offsets clamped to the
+// cell itself on the domain faces), so their loads are in flight together; a face
+// outside the domain then contributes nothing, or the Dirichlet term, in the same
+// order as the faces are listed.
 template <typename T, typename UA, typename EA>
 __device__ __forceinline__ void stencil_acc(UA ua, EA ea, int nx, int ny, int nz, int i, int j, int k,
                                             T& diag, T& offsum) {
+  const bool in[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, k > 0, k < nz - 1};
+  const int ox[6] = {in[0] ? -1 : 0, in[1] ? 1 : 0, 0, 0, 0, 0};
+  const int oy[6] = {0, 0, in[2] ? -1 : 0, in[3] ? 1 : 0, 0, 0};
+  const int oz[6] = {0, 0, 0, 0, in[4] ? -1 : 0, in[5] ? 1 : 0};
   const T ec = ea(0, 0, 0);
+  T en[6], un[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    en[q] = ea(ox[q], oy[q], oz[q]);
+    un[q] = ua(ox[q], oy[q], oz[q]);
+  }
   T d = 0, s = 0;
-  if (i > 0) { const T b = hmean_s(ec, ea(-1, 0, 0)); d += b; s += b * ua(-1, 0, 0); }
-  if (i < nx - 1) { const T b = hmean_s(ec, ea(1, 0, 0)); d += b; s += b * ua(1, 0, 0); }
-  if (j > 0) { const T b = hmean_s(ec, ea(0, -1, 0)); d += b; s += b * ua(0, -1, 0); }
-  if (j < ny - 1) { const T b = hmean_s(ec, ea(0, 1, 0)); d += b; s += b * ua(0, 1, 0); }
-  if (k > 0) { const T b = hmean_s(ec, ea(0, 0, -1)); d += b; s += b * ua(0, 0, -1); }
-  else d += (T)2 * ec;
-  if (k < nz - 1) { const T b = hmean_s(ec, ea(0, 0, 1)); d += b; s += b * ua(0, 0, 1); }
-  else d += (T)2 * ec;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const T b = hmean_s(ec, en[q]);
+    d = in[q] ? d + b : (q >= 4 ? d + (T)2 * ec : d);
+    s = in[q] ? s + b * un[q] : s;
+  }
   diag = d;
   offsum = s;
+}
+
+template <typename T, typename AT>
+__device__ __forceinline__ void stencil_at(const T* u, const T* eps, AT at, int nx, int ny, int nz, int i,
+                                           int j, int k, T& diag, T& offsum) {
+  stencil_acc<T>([&](int dx, int dy, int dz) { return u[at(dx, dy, dz)]; },
+                 [&](int dx, int dy, int dz) { return eps[at(dx, dy, dz)]; }, nx, ny, nz, i, j, k, diag,
+                 offsum);
 }
 
 template <typename T>
 __device__ __forceinline__ void stencil_s(const T* u, const T* eps, int nx, int ny, int nz, int i, int j,
                                           int k, size_t c, T& diag, T& offsum) {
   const ptrdiff_t sy = (ptrdiff_t)nx, sz = (ptrdiff_t)nx * ny;
-  auto at = [=](int dx, int dy, int dz) { return (size_t)((ptrdiff_t)c + dx + dy * sy + dz * sz); };
-  stencil_acc<T>([&](int dx, int dy, int dz) { return u[at(dx, dy, dz)]; },
-                 [&](int dx, int dy, int dz) { return eps[at(dx, dy, dz)]; }, nx, ny, nz, i, j, k, diag,
-                 offsum);
+  stencil_at<T>(u, eps, NatAt{(ptrdiff_t)c, sy, sz}, nx, ny, nz, i, j, k, diag, offsum);
 }
 
 // Operator row for the double residual with the face coefficients computed exactly as
 // the smoother computes them (single-precision harmonic means in FP32 mode, exact double
-// in FP64 mode), accumulated in double.
-template <typename T>
-__device__ __forceinline__ void stencil_r(const double* u, const T* eps, int nx, int ny, int nz, int i,
-                                          int j, int k, size_t c, double& diag, double& offsum) {
-  const T ec = eps[c];
+// in FP64 mode), accumulated in double; the potential in natural order, the
+// coefficient through its level's positions `at`.
+template <typename T, typename AT>
+__device__ __forceinline__ void stencil_r(const double* u, const T* eps, AT at, int nx, int ny, int nz,
+                                          int i, int j, int k, size_t c, double& diag, double& offsum) {
+  const ptrdiff_t sy = (ptrdiff_t)nx, sz = (ptrdiff_t)nx * ny;
+  const bool in[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, k > 0, k < nz - 1};
+  const int ox[6] = {in[0] ? -1 : 0, in[1] ? 1 : 0, 0, 0, 0, 0};
+  const int oy[6] = {0, 0, in[2] ? -1 : 0, in[3] ? 1 : 0, 0, 0};
+  const int oz[6] = {0, 0, 0, 0, in[4] ? -1 : 0, in[5] ? 1 : 0};
+  const T ec = eps[at(0, 0, 0)];
+  T en[6];
+  double un[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    en[q] = eps[at(ox[q], oy[q], oz[q])];
+    un[q] = u[(size_t)((ptrdiff_t)c + ox[q] + oy[q] * sy + oz[q] * sz)];
+  }
   double d = 0, s = 0;
-  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  if (i > 0) { const double b = (double)hmean_s(ec, eps[c - 1]); d += b; s += b * u[c - 1]; }
-  if (i < nx - 1) { const double b = (double)hmean_s(ec, eps[c + 1]); d += b; s += b * u[c + 1]; }
-  if (j > 0) { const double b = (double)hmean_s(ec, eps[c - sy]); d += b; s += b * u[c - sy]; }
-  if (j < ny - 1) { const double b = (double)hmean_s(ec, eps[c + sy]); d += b; s += b * u[c + sy]; }
-  if (k > 0) { const double b = (double)hmean_s(ec, eps[c - sz]); d += b; s += b * u[c - sz]; }
-  else d += 2.0 * (double)ec;
-  if (k < nz - 1) { const double b = (double)hmean_s(ec, eps[c + sz]); d += b; s += b * u[c + sz]; }
-  else d += 2.0 * (double)ec;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double b = (double)hmean_s(ec, en[q]);
+    d = in[q] ? d + b : (q >= 4 ? d + 2.0 * (double)ec : d);
+    s = in[q] ? s + b * un[q] : s;
+  }
   diag = d;
   offsum = s;
 }
@@ -531,9 +579,9 @@ __device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
   bz = (int)(l / (gridDim.x * gridDim.y));
 }
 
-// One colour of a red-black Gauss-Seidel sweep: grid (x: half a row, y: j, z: k),
-// every thread updates the one cell of the colour in its pair.
-// kFine marks the finest level's instantiation, so that kernel traces report it apart.
+// One colour of a red-black Gauss-Seidel sweep in natural order: grid (x: half a row,
+// y: j, z: k), every thread updates the one cell of the colour in its pair.  kFine
+// marks the finest level's instantiation, so that kernel traces report it apart.
 template <typename T, bool kFine>
 __global__ void __launch_bounds__(128) k_smooth_rb(T* u, const T* f, const T* eps, int nx, int ny, int nz,
                                                   int color) {
@@ -547,153 +595,65 @@ __global__ void __launch_bounds__(128) k_smooth_rb(T* u, const T* f, const T* ep
   u[c] = (f[c] + s) / d;
 }
 
-// One full red-black sweep in one pass (colour 0, then colour 1), out of place: a
-// workgroup takes a kFX x kFY tile (kFY = 8 or 4 rows) of zc planes and marches along z with the planes
-// p-3..p of u and the coefficient (with a two-cell ring) and p-2..p of f (one-cell ring)
-// in LDS; at plane p it updates colour 0 of plane p-1 on the tile and its ring, then
-// colour 1 of plane p-2 on the tile, and writes plane p-2.  Colour 0 reads only the
-// input (colour-1 values), colour 1 reads the updated colour-0 values, exactly as the
-// two single-colour launches; every cell's arithmetic is stencil_acc's.  Each sweep
-// reads u, the coefficient and f once and writes whole lines of u.
-constexpr int kFX = 64;
-
-template <typename T, bool kFine, int kFY>
-__global__ void __launch_bounds__(256) k_smooth_fused(const T* __restrict__ uin, T* __restrict__ uout,
-                                                     const T* __restrict__ f,
-                                                     const T* __restrict__ eps, int nx, int ny,
-                                                     int nz, int zc) {
-  constexpr int NT = 256;
-  constexpr int kFXh = kFX + 4, kFYh = kFY + 4, kFXf = kFX + 2, kFYf = kFY + 2;
-  constexpr int kPU = (kFYh * kFXh + NT - 1) / NT;  // plane values per thread (u, eps)
-  constexpr int kPF = (kFYf * kFXf + NT - 1) / NT;  // plane values per thread (f)
-  __shared__ T U[4][kFYh][kFXh];
-  __shared__ T E[4][kFYh][kFXh];
-  __shared__ T R[3][kFYf][kFXf];
-  int bx, by, bz;
-  xcd_block3(bx, by, bz);
-  const int x0 = bx * kFX, y0 = by * kFY, z0 = bz * zc;
-  const int z1 = min(z0 + zc, nz);
-  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  const int tid = threadIdx.x;
-  // plane p's values of this thread, loaded one plane ahead (registers)
-  T pu[kPU], pe[kPU], pf[kPF];
-  auto fetch = [&](int p) {
-    if (p < 0 || p >= nz) return;
-#pragma unroll
-    for (int m = 0; m < kPU; ++m) {
-      const int t = tid + m * NT;
-      const int lj = t / kFXh, li = t - lj * kFXh;
-      const int i = x0 + li - 2, j = y0 + lj - 2;
-      if (t < kFYh * kFXh && i >= 0 && i < nx && j >= 0 && j < ny) {
-        const size_t c = (size_t)i + sy * j + sz * p;
-        pu[m] = uin[c];
-        pe[m] = eps[c];
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < kPF; ++m) {
-      const int t = tid + m * NT;
-      const int lj = t / kFXf, li = t - lj * kFXf;
-      const int i = x0 + li - 1, j = y0 + lj - 1;
-      if (t < kFYf * kFXf && i >= 0 && i < nx && j >= 0 && j < ny) pf[m] = f[(size_t)i + sy * j + sz * p];
-    }
-  };
-  auto stash = [&](int p) {
-    if (p < 0 || p >= nz) return;
-    const int sl = (p + 4) & 3, sf = (p + 3) % 3;
-#pragma unroll
-    for (int m = 0; m < kPU; ++m) {
-      const int t = tid + m * NT;
-      const int lj = t / kFXh, li = t - lj * kFXh;
-      const int i = x0 + li - 2, j = y0 + lj - 2;
-      if (t < kFYh * kFXh && i >= 0 && i < nx && j >= 0 && j < ny) {
-        U[sl][lj][li] = pu[m];
-        E[sl][lj][li] = pe[m];
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < kPF; ++m) {
-      const int t = tid + m * NT;
-      const int lj = t / kFXf, li = t - lj * kFXf;
-      const int i = x0 + li - 1, j = y0 + lj - 1;
-      if (t < kFYf * kFXf && i >= 0 && i < nx && j >= 0 && j < ny) R[sf][lj][li] = pf[m];
-    }
-  };
-  fetch(z0 - 2);
-  for (int p = z0 - 2; p <= z1 + 1; ++p) {
-    stash(p);
-    if (p + 1 <= z1 + 1) fetch(p + 1);  // in flight while this plane is computed
-    __syncthreads();
-    const int k = p - 1;  // colour 0 on the tile and its one-cell ring: half of each row
-    if (k >= z0 - 1 && k <= z1 && k >= 0 && k < nz) {
-      const int sk = (k + 4) & 3, fk = (k + 3) % 3;
-      for (int t = tid; t < kFYf * (kFXf / 2); t += NT) {
-        const int lj = t / (kFXf / 2);
-        const int j = y0 + lj - 1;
-        const int li = 2 * (t - lj * (kFXf / 2)) + (((x0 - 1) + j + k) & 1);  // (i + j + k) even
-        const int i = x0 + li - 1;
-        if (i < 0 || i >= nx || j < 0 || j >= ny) continue;
-        const int ui = li + 1, uj = lj + 1;
-        T d, s;
-        stencil_acc<T>([&](int dx, int dy, int dz) { return U[(k + dz + 4) & 3][uj + dy][ui + dx]; },
-                       [&](int dx, int dy, int dz) { return E[(k + dz + 4) & 3][uj + dy][ui + dx]; },
-                       nx, ny, nz, i, j, k, d, s);
-        U[sk][uj][ui] = (R[fk][lj][li] + s) / d;
-      }
-    }
-    __syncthreads();
-    const int k2 = p - 2;  // colour 1 on the tile, then the finished plane
-    if (k2 >= z0 && k2 < z1) {
-      const int sk = (k2 + 4) & 3, fk = (k2 + 3) % 3;
-      for (int t = tid; t < kFY * (kFX / 2); t += NT) {
-        const int lj = t / (kFX / 2);
-        const int j = y0 + lj;
-        const int li = 2 * (t - lj * (kFX / 2)) + ((x0 + j + k2 + 1) & 1);  // (i + j + k2) odd
-        const int i = x0 + li;
-        if (i >= nx || j >= ny) continue;
-        const int ui = li + 2, uj = lj + 2;
-        T d, s;
-        stencil_acc<T>([&](int dx, int dy, int dz) { return U[(k2 + dz + 4) & 3][uj + dy][ui + dx]; },
-                       [&](int dx, int dy, int dz) { return E[(k2 + dz + 4) & 3][uj + dy][ui + dx]; },
-                       nx, ny, nz, i, j, k2, d, s);
-        U[sk][uj][ui] = (R[fk][lj + 1][li + 1] + s) / d;
-      }
-      __syncthreads();
-      for (int t = tid; t < kFY * kFX; t += NT) {
-        const int lj = t / kFX, li = t - lj * kFX;
-        const int i = x0 + li, j = y0 + lj;
-        if (i < nx && j < ny) uout[(size_t)i + sy * j + sz * k2] = U[sk][lj + 2][li + 2];
-      }
-    }
-    __syncthreads();
-  }
+// One colour of a red-black sweep on the finest level in split order: grid (x: half a
+// row, y: j, z: k); the thread at half-row position m updates cell
+// i = 2m + ((j + k + colour) & 1), reading its own coefficient and right-hand side and
+// the other colour's values, all as whole lines.  Same arithmetic as k_smooth_rb.
+template <typename T>
+__global__ void __launch_bounds__(128) k_smooth_split(T* u, const T* f, const T* eps, int nx, int ny,
+                                                     int nz, int color) {
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int m = (int)(bx * blockDim.x + threadIdx.x);
+  if (m >= (nx >> 1)) return;
+  const int i = 2 * m + ((j + k + color) & 1);
+  const SplitAt at = split_at(i, j, k, nx, ny);
+  T d, s;
+  stencil_at<T>(u, eps, at, nx, ny, nz, i, j, k, d, s);
+  u[at.own] = (f[at.own] + s) / d;
 }
 
-// r = b - A phi in double with the true boundary values (the lift is in b), 256 cells
-// per block; writes the working-precision right-hand side of the correction equation
-// and one partial of ||r||^2 per block.
-template <typename T>
+// r = b - A phi in double with the true boundary values (the lift is in b) over
+// 256-cell runs, a block taking every gridDim-th run (after the XCD remap); writes the
+// working-precision right-hand side of the correction equation and one partial of
+// ||r||^2 per block, summed over its runs in order.
+constexpr int kResBlocks = 8192;
+
+template <typename T, bool kSplit>
 __global__ void __launch_bounds__(256) k_residual_rows(const double* phi, const double* b, const T* eps,
                                                       int nx, int ny, int nz, T* f0, double* partial) {
   const uint32_t n = (uint32_t)nx * ny * nz;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t c = blk * 256u + threadIdx.x;
-  double rr = 0.0;
-  if (c < n) {
-    const int i = (int)(c % (uint32_t)nx), j = (int)((c / (uint32_t)nx) % (uint32_t)ny),
-              k = (int)(c / ((uint32_t)nx * (uint32_t)ny));
-    double d, s;
-    stencil_r<T>(phi, eps, nx, ny, nz, i, j, k, c, d, s);
-    rr = b[c] - (d * phi[c] - s);
-    f0[c] = (T)rr;
+  const uint32_t runs = (n + 255u) / 256u;
+  double acc = 0.0;
+  for (uint32_t run = blk; run < runs; run += gridDim.x) {
+    const uint32_t c = run * 256u + threadIdx.x;
+    double rr = 0.0;
+    if (c < n) {
+      const int i = (int)(c % (uint32_t)nx), j = (int)((c / (uint32_t)nx) % (uint32_t)ny),
+                k = (int)(c / ((uint32_t)nx * (uint32_t)ny));
+      double d, s;
+      size_t q;
+      if constexpr (kSplit) {
+        const SplitAt at = split_at(i, j, k, nx, ny);
+        stencil_r<T>(phi, eps, at, nx, ny, nz, i, j, k, c, d, s);
+        q = (size_t)at.own;
+      } else {
+        const NatAt at = nat_at(i, j, k, nx, ny);
+        stencil_r<T>(phi, eps, at, nx, ny, nz, i, j, k, c, d, s);
+        q = c;
+      }
+      rr = b[c] - (d * phi[c] - s);
+      f0[q] = (T)rr;
+    }
+    acc += block_sumd(rr * rr);
   }
-  const double acc = block_sumd(rr * rr);
   if (threadIdx.x == 0) partial[blk] = acc;
 }
 
 // Coarse right-hand side (sum of the 8 child residuals / 2) and zero coarse correction;
-// grid (x: coarse row, y: cj, z: ck).
-template <typename T>
+// grid (x: coarse row, y: cj, z: ck); the fine level in split order if kSplit.
+template <typename T, bool kSplit>
 __global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const T* eps, int nx, int ny,
                                                   int nz, T* fc, T* uc, int cnx, int cny) {
   int bx, cj, ck;
@@ -701,11 +661,20 @@ __global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const
   const int ci = bx * blockDim.x + threadIdx.x;
   if (ci >= cnx) return;
   T s8 = 0;
+#pragma unroll
   for (int d = 0; d < 8; ++d) {
     const int i = 2 * ci + (d & 1), j = 2 * cj + ((d >> 1) & 1), k = 2 * ck + (d >> 2);
-    const size_t q = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
     T dg, sm;
-    stencil_s<T>(u, eps, nx, ny, nz, i, j, k, q, dg, sm);
+    size_t q;
+    if constexpr (kSplit) {
+      const SplitAt at = split_at(i, j, k, nx, ny);
+      stencil_at<T>(u, eps, at, nx, ny, nz, i, j, k, dg, sm);
+      q = (size_t)at.own;
+    } else {
+      const NatAt at = nat_at(i, j, k, nx, ny);
+      stencil_at<T>(u, eps, at, nx, ny, nz, i, j, k, dg, sm);
+      q = (size_t)at.c;
+    }
     s8 += f[q] - (dg * u[q] - sm);
   }
   const size_t cc = (size_t)ci + (size_t)cnx * ((size_t)cj + (size_t)cny * ck);
@@ -718,13 +687,18 @@ __global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const
 // the cell on the Neumann x and y faces and negate it on the homogeneous Dirichlet z
 // faces.  (Second-order transfer: with cell-averaged restriction the transfer orders
 // then exceed the order of the operator.)
-template <typename T>
+template <typename T, bool kSplit>
 __global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, const T* uc, int cnx,
                                                  int cny, int cnz) {
   int bx, j, k;
   xcd_block3(bx, j, k);
-  const int i = bx * blockDim.x + threadIdx.x;
-  if (i >= nx) return;
+  const int p = bx * blockDim.x + threadIdx.x;  // storage position in the row
+  if (p >= nx) return;
+  int i = p;
+  if constexpr (kSplit) {
+    const int h = nx >> 1, q = p >= h ? 1 : 0;
+    i = 2 * (p - q * h) + ((j + k + q) & 1);
+  }
   const int I = i >> 1, J = j >> 1, K = k >> 1;
   const int ia[2] = {I, (i & 1) ? I + 1 : I - 1};
   const int ja[2] = {J, (j & 1) ? J + 1 : J - 1};
@@ -742,7 +716,7 @@ __global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, 
     acc += wt[c & 1] * wt[(c >> 1) & 1] * wt[c >> 2] * sg *
            uc[(size_t)a + (size_t)cnx * ((size_t)b + (size_t)cny * z)];
   }
-  u[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] += acc;
+  u[(size_t)p + (size_t)nx * ((size_t)j + (size_t)ny * k)] += acc;
 }
 
 // Coarsest level: red-black sweeps from zero inside one workgroup.
@@ -774,10 +748,21 @@ __global__ void k_extrapolate(double* phi, double* prev, uint32_t n, int have_pr
   }
 }
 
-template <typename T>
-__global__ void k_phi_update(double* phi, const T* u, uint32_t n) {
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    phi[c] += (double)u[c];
+// phi += u over the finest level; grid (x: row position, y: j, z: k), u read in its
+// storage order.
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(128) k_phi_update(double* phi, const T* u, int nx, int ny) {
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int p = bx * blockDim.x + threadIdx.x;
+  if (p >= nx) return;
+  int i = p;
+  if constexpr (kSplit) {
+    const int h = nx >> 1, q = p >= h ? 1 : 0;
+    i = 2 * (p - q * h) + ((j + k + q) & 1);
+  }
+  const size_t row = (size_t)nx * ((size_t)j + (size_t)ny * k);
+  phi[row + i] += (double)u[row + p];
 }
 
 template <typename T>
@@ -827,13 +812,13 @@ struct FieldState {
   double* host_norms = nullptr;
   double* phi_prev = nullptr;  // converged potential of the previous step
   bool have_prev = false;
+  bool split = false;  // finest level in split red-black order (nx even, more than one level)
   bool graph_failed = false;
   hipGraphExec_t graph_exec = nullptr;
   // optional timing of the finest-level smoother launches: event pairs recorded around
   // each launch; while timing is on the cycle runs eagerly (not from the graph)
   static constexpr int kMaxTimed = 64;
   hipEvent_t sm_ev[2 * kMaxTimed] = {};
-  int sm_phase[kMaxTimed] = {};  // phase each pair times (single-colour or fused launch)
   int sm_n = 0;              // event pairs recorded by the cycle being enqueued
   int sm_pending = 0;        // pairs recorded by the last enqueued cycle, unread
   bool timing = false;
@@ -861,7 +846,7 @@ size_t field_bytes(const itokmc_grid_desc* d) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
   size_t total = al(n * 8) * 3 + al(n * T) * 6 + al(n * 8) * 2 + al(8 * (8 + npart));
-  for (int l = 0; l < nl; ++l) total += 4 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
+  for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
   return total;
 }
 
@@ -895,7 +880,6 @@ int field_init(itokmc_ctx* ctx, char* base) {
     L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
     L.n = (uint32_t)((size_t)L.nx * L.ny * L.nz);
     L.u = p; p += al(L.n * T);
-    L.u2 = p; p += al(L.n * T);
     L.f = p; p += al(L.n * T);
     L.eps = p; p += al(L.n * T);
   }
@@ -950,8 +934,8 @@ static dim3 row_grid(int half_nx, int ny, int nz) {
   return dim3((unsigned)((half_nx + 127) / 128), (unsigned)ny, (unsigned)nz);
 }
 
-// One colour sweep at level l; the finest level's launches are bracketed by event
-// pairs when timing is on.
+// One colour sweep at level l (the finest level in split order when F->split); the
+// finest level's launches are bracketed by event pairs when timing is on.
 template <typename T>
 static void smooth(FieldState* F, int l, hipStream_t s, int color) {
   Level& L = F->lev[l];
@@ -964,61 +948,16 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
     return;
   }
   const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
-  if (timed) {
-    F->sm_phase[F->sm_n] = PH_SMOOTH_FINE;
-    (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
-  }
-  k_smooth_rb<T, true><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
+  if (F->split) k_smooth_split<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  else k_smooth_rb<T, true><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
   if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n + 1], s);
   if (timed) ++F->sm_n;
 }
 
-// Levels at least this wide smooth with the fused sweep (coarser ones are launch-bound).
-constexpr int kFuseMinNx = 128;
-
-// `count` full sweeps at level l: pairs of fused out-of-place sweeps (u -> u2 -> u) on
-// wide levels, otherwise (and for an odd last sweep) two single-colour launches.  The
-// finest level's fused launches are bracketed by event pairs when timing is on.
 template <typename T>
-static void smooth_sweeps(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s, int count) {
-  Level& L = F->lev[l];
-  int it = 0;
-  if (ctx->tune.fused_sweeps && L.nx >= kFuseMinNx) {
-    const int zc = L.nz >= 256 ? 32 : 8;
-    const int fy = ctx->tune.fused_sweeps == 2 ? 4 : 8;
-    const dim3 g((unsigned)((L.nx + kFX - 1) / kFX), (unsigned)((L.ny + fy - 1) / fy),
-                 (unsigned)((L.nz + zc - 1) / zc));
-    const T* f = (const T*)L.f;
-    const T* ep = (const T*)L.eps;
-    auto launch = [&](bool fine, const T* in, T* out) {
-      if (fy == 4) {
-        if (fine) k_smooth_fused<T, true, 4><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
-        else k_smooth_fused<T, false, 4><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
-      } else {
-        if (fine) k_smooth_fused<T, true, 8><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
-        else k_smooth_fused<T, false, 8><<<g, 256, 0, s>>>(in, out, f, ep, L.nx, L.ny, L.nz, zc);
-      }
-    };
-    for (; it + 2 <= count; it += 2) {
-      for (int h = 0; h < 2; ++h) {
-        const T* in = (const T*)(h ? L.u2 : L.u);
-        T* out = (T*)(h ? L.u : L.u2);
-        if (l > 0) {
-          launch(false, in, out);
-          continue;
-        }
-        const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
-        if (timed) {
-          F->sm_phase[F->sm_n] = PH_SWEEP_FINE;
-          (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
-        }
-        launch(true, in, out);
-        if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n + 1], s);
-        if (timed) ++F->sm_n;
-      }
-    }
-  }
-  for (; it < count; ++it) {
+static void smooth_sweeps(FieldState* F, int l, hipStream_t s, int count) {
+  for (int it = 0; it < count; ++it) {
     smooth<T>(F, l, s, 0);
     smooth<T>(F, l, s, 1);
   }
@@ -1038,13 +977,18 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
     return;
   }
   Level& C = F->lev[l + 1];
-  smooth_sweeps<T>(ctx, F, l, s, ctx->tune.mg_pre);
-  k_restrict3<T><<<row_grid(C.nx, C.ny, C.nz), 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u,
-                                                             C.nx, C.ny);
+  smooth_sweeps<T>(F, l, s, ctx->tune.mg_pre);
+  const dim3 gr = row_grid(C.nx, C.ny, C.nz), gp = row_grid(L.nx, L.ny, L.nz);
+  if (l == 0 && F->split)
+    k_restrict3<T, true><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx, C.ny);
+  else
+    k_restrict3<T, false><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx, C.ny);
   vcycle<T>(ctx, F, l + 1, s);
-  k_prolong3<T><<<row_grid(L.nx, L.ny, L.nz), 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny,
-                                                            C.nz);
-  smooth_sweeps<T>(ctx, F, l, s, ctx->tune.mg_post);
+  if (l == 0 && F->split)
+    k_prolong3<T, true><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
+  else
+    k_prolong3<T, false><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
+  smooth_sweeps<T>(F, l, s, ctx->tune.mg_post);
 }
 
 // Accumulate the timed finest-level smoother launches of the last cycle (the stream
@@ -1053,11 +997,27 @@ static void collect_smooth(itokmc_ctx* ctx, FieldState* F) {
   for (int i = 0; i < F->sm_pending; ++i) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, F->sm_ev[2 * i], F->sm_ev[2 * i + 1]) == hipSuccess) {
-      ctx->phase_ms[F->sm_phase[i]] += ms;
-      ctx->phase_calls[F->sm_phase[i]] += 1;
+      ctx->phase_ms[PH_SMOOTH_FINE] += ms;
+      ctx->phase_calls[PH_SMOOTH_FINE] += 1;
     }
   }
   F->sm_pending = 0;
+}
+
+// Double residual of the finest level into f (working precision) and ||r||^2 into
+// norms[1].
+template <typename T>
+static void residual(FieldState* F, hipStream_t s) {
+  Level& L0 = F->lev[0];
+  const uint32_t runs = (L0.n + 255) / 256;
+  const int rb = runs < (uint32_t)kResBlocks ? (int)runs : kResBlocks;
+  if (F->split)
+    k_residual_rows<T, true><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
+                                                (T*)L0.f, F->norms + 8);
+  else
+    k_residual_rows<T, false><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
+                                                 (T*)L0.f, F->norms + 8);
+  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
 }
 
 // One refinement cycle: correction V-cycle from zero, potential update, new double
@@ -1068,11 +1028,10 @@ static void refine_cycle(itokmc_ctx* ctx, FieldState* F, hipStream_t s) {
   F->sm_n = 0;
   k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
   vcycle<T>(ctx, F, 0, s);
-  k_phi_update<T><<<blocks(L0.n), 256, 0, s>>>(F->phi, (const T*)L0.u, L0.n);
-  const int rb = (int)((L0.n + 255) / 256);
-  k_residual_rows<T><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz, (T*)L0.f,
-                                        F->norms + 8);
-  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+  const dim3 gp = row_grid(L0.nx, L0.ny, L0.nz);
+  if (F->split) k_phi_update<T, true><<<gp, 128, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny);
+  else k_phi_update<T, false><<<gp, 128, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny);
+  residual<T>(F, s);
 }
 
 // Capture one refinement cycle into a HIP graph (on a private stream: the caller's
@@ -1109,15 +1068,13 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
   for (int l = 1; l < F->nlev; ++l) {
     Level& Fl = F->lev[l - 1];
     Level& Cl = F->lev[l];
-    k_eps_restrict<T><<<blocks(Cl.n), 256, 0, s>>>((const T*)Fl.eps, Fl.nx, Fl.ny, (T*)Cl.eps, Cl.nx,
+    k_eps_restrict<T><<<blocks(Cl.n), 256, 0, s>>>((const T*)Fl.eps, Fl.nx, Fl.ny,
+                                                   (l == 1 && F->split) ? 1 : 0, (T*)Cl.eps, Cl.nx,
                                                    Cl.ny, Cl.nz);
   }
   const int maxc = ctx->d.gmg_max_cycles > 0 ? ctx->d.gmg_max_cycles : 50;
   ctx->total_solves += 1;
-  const int rb = (int)((L0.n + 255) / 256);
-  k_residual_rows<T><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz, (T*)L0.f,
-                                        F->norms + 8);
-  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+  residual<T>(F, s);
   const bool graph = ctx->tune.use_graph && !F->timing && capture_cycle<T>(ctx, F);
   for (int cyc = 0;; ++cyc) {
     hipError_t e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
@@ -1149,6 +1106,11 @@ template <typename T>
 static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K, int mode) {
   hipStream_t s = ctx->s;
   const uint32_t n = ctx->ncell;
+  const bool split = ctx->tune.fine_layout == 0 && F->nlev > 1;
+  if (split != F->split) {
+    field_reset_graph(ctx);
+    F->split = split;
+  }
   phase_begin(ctx, PH_FIELD_PREP);
   using S = typename DepAcc<T>::S;
   k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->sig, n);
@@ -1176,7 +1138,7 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   }
   k_field_prep<T><<<kRedBlocks, 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const S*)F->ne,
                                              (const S*)F->sig, sig_scale, ctx->d.V_anode,
-                                             (T*)F->lev[0].eps, F->b, F->norms + 8);
+                                             F->split ? 1 : 0, (T*)F->lev[0].eps, F->b, F->norms + 8);
   k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms);
   phase_end(ctx, PH_FIELD_PREP);
   phase_begin(ctx, PH_SOLVE);

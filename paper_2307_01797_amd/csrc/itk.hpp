@@ -124,7 +124,7 @@ namespace itk {
 // phases timed when profiling is on
 enum Phase { PH_PUSH = 0, PH_PHOTON, PH_SCAN, PH_SCATTER, PH_KMC, PH_COUPLE, PH_DEPOSIT,
              PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_MERGE, PH_FIELD_PREP, PH_SMOOTH_FINE,
-             PH_SWEEP_FINE, PH_COUPLE_LIGHT, PH_NUM };
+             PH_COUPLE_LIGHT, PH_NUM };
 void phase_begin(itokmc_ctx* ctx, int phase);
 void phase_end(itokmc_ctx* ctx, int phase);
 int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);

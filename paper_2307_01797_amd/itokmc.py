@@ -36,8 +36,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
            "itokmc_ensemble_last_error"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
-          "field_push", "count", "merge", "field_prep", "smooth_fine", "sweep_fine",
-          "couple_light"]
+          "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light"]
 
 
 class GridDesc(ctypes.Structure):
@@ -61,7 +60,7 @@ class Coeffs(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("mg_pre", "mg_post", "bottom_sweeps", "use_graph",
-                                              "extrapolate", "fused_sweeps")]
+                                              "extrapolate", "fine_layout")]
 
 
 class SeedDesc(ctypes.Structure):

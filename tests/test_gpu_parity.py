@@ -370,23 +370,44 @@ def test_streamer_fp32_resync(itk, orc):
     assert nband <= 2
 
 
-@pytest.mark.parametrize("fused", [1, 2])
-def test_fused_sweeps_match_single_colour_launches(itk, fused):
-    """With fused sweeps, levels at least 128 cells wide smooth with one out-of-place
-    launch per red-black sweep; potential, field and particles after three
-    self-consistent FP32 steps are bit-identical to the single-colour launches."""
-    cfg = workloads.preset("streamer_64", grid=(128, 128, 128), dx=1e-3 / 128)
+def _split_vs_natural(itk, precision, grid, steps):
+    nz = grid[2]
+    cfg = workloads.preset("streamer_64", grid=grid, dx=1e-3 / nz, V_anode=18e3 * nz / 64,
+                           precision=precision,
+                           seed_centre=tuple(0.5 * g * 1e-3 / nz for g in grid))
     out = []
-    for fused in (fused, 0):
-        g = itk.Sim(cfg)
-        g.set_tuning(fused_sweeps=fused)
+    for layout in (0, 1):
+        g = itk.Sim(cfg, precision=precision)
+        g.set_tuning(fine_layout=layout)
+        assert g.tuning()["fine_layout"] == layout
         g.seed()
-        g.step(3)
-        out.append((g.field(), g.deposit("ez"), g.particles()))
+        g.step(steps)
+        out.append((g.field(), g.deposit("ez"), g.particles(), g.diagnostics()["solver_cycles_total"]))
         g.close()
-    (pa, ea, (ca, oa, wa, ia)), (pb, eb, (cb, ob, wb, ib)) = out
+    return out
+
+
+@pytest.mark.parametrize("grid", [(128, 128, 128), (48, 32, 40)])
+def test_split_order_matches_natural_order(itk, grid):
+    """The finest multigrid level stored in split red-black order (each x row holds one
+    colour's cells in its first half) and in natural order: potential, field and
+    particles after three self-consistent FP32 steps are bit-identical (every cell's
+    arithmetic and every reduction order are the same in both, and the FP32 charge
+    deposit sums fixed-point integers)."""
+    (pa, ea, (ca, oa, wa, ia), na), (pb, eb, (cb, ob, wb, ib), nb) = \
+        _split_vs_natural(itk, "fp32", grid, 3)
+    assert na == nb
     assert np.array_equal(pa, pb) and np.array_equal(ea, eb)
     ia, ca, oa, wa = by_id(ia, ca, oa, wa)
     ib, cb, ob, wb = by_id(ib, cb, ob, wb)
     assert np.array_equal(ia, ib) and np.array_equal(ca, cb) and np.array_equal(wa, wb)
     assert np.array_equal(oa, ob)
+
+
+def test_split_order_fp64_agrees(itk):
+    """In FP64 the charge deposit adds doubles with atomics in arrival order, so two runs
+    differ in the last bits whatever the order; the two storage orders agree to the
+    solver tolerance (1e-10 relative residual)."""
+    (pa, ea, _, _), (pb, eb, _, _) = _split_vs_natural(itk, "fp64", (48, 32, 40), 2)
+    assert np.abs(pa - pb).max() < 1e-8 * np.abs(pb).max()
+    assert np.abs(ea - eb).max() < 1e-7 * np.abs(eb).max()
