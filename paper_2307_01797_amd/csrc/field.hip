@@ -24,6 +24,7 @@
 
 #include <vector>
 
+
 #include "device.hpp"
 #include "itk.hpp"
 
@@ -203,17 +204,18 @@ template <> struct DepAcc<float> {
 // at X^k only (initial field); mode 1 deposits the conductivity weight mu(|E^k|) w at
 // X^k and the electron number at X_dagger (the position after the diffusive part of
 // the step, with the normals of the push).
-constexpr int kDepChunk = 2048;
+// A 1024-entry table per 512-particle chunk (20 KB of LDS): smaller tables raise the
+// number of resident workgroups, and a table twice the chunk keeps probing short.
+constexpr int kDepChunk = 512;
 constexpr int kDepProbes = 8;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-template <typename T> struct DepTbl { static constexpr int log2n = 11; };
+template <typename T> struct DepTbl { static constexpr int log2n = 10; };
 
-template <typename T>
+template <typename T, int L2>
 __device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v0,
                                         typename DepAcc<T>::S* v1, uint32_t node, T a, T b,
                                         typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
   using A = DepAcc<T>;
-  constexpr int L2 = DepTbl<T>::log2n;
   constexpr uint32_t mask = (1u << L2) - 1u;
   uint32_t h = (node * 2654435761u) >> (32 - L2);
   for (int probe = 0; probe < kDepProbes; ++probe) {
@@ -233,7 +235,7 @@ __device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v
   if (b != (T)0) atomicAdd(&g1[node], A::enc1(b));
 }
 
-template <typename T>
+template <typename T, int L2>
 __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v0,
                                         typename DepAcc<T>::S* v1, const StepConst& K, int i0,
                                         int j0, int k0, T fx, T fy, T fz, T qa, T qb,
@@ -245,32 +247,32 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
     const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
     if (wt == (T)0 || ii >= K.nx || jj >= K.ny || kk >= K.nz) continue;
     const uint32_t node = (uint32_t)ii + (uint32_t)K.nx * ((uint32_t)jj + (uint32_t)K.ny * (uint32_t)kk);
-    tbl_add<T>(keys, v0, v1, node, qa * wt, qb * wt, g0, g1);
+    tbl_add<T, L2>(keys, v0, v1, node, qa * wt, qb * wt, g0, g1);
   }
 }
 
-template <typename T>
+template <typename T, int L2>
 __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
                                                           StepConst K, const void* Ex,
                                                           const void* Ey, const void* Ez, Coef co,
                                                           int mode, typename DepAcc<T>::S* sig,
-                                                          typename DepAcc<T>::S* ne) {
+                                                          typename DepAcc<T>::S* ne, uint32_t chunk) {
   using S = typename DepAcc<T>::S;
-  constexpr int TBL = 1 << DepTbl<T>::log2n;
+  constexpr int TBL = 1 << L2;
   extern __shared__ __align__(16) char smem[];
   S* v0 = reinterpret_cast<S*>(smem);
   S* v1 = v0 + TBL;
   uint32_t* keys = reinterpret_cast<uint32_t*>(v1 + TBL);
   const uint32_t n = min(ctr->n[which], K.cap);
   const T diff = (T)K.diff;
-  for (uint32_t c0 = blockIdx.x * (uint32_t)kDepChunk; c0 < n; c0 += gridDim.x * (uint32_t)kDepChunk) {
+  for (uint32_t c0 = blockIdx.x * chunk; c0 < n; c0 += gridDim.x * chunk) {
     for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
       keys[t] = kEmptyKey;
       v0[t] = (S)0;
       v1[t] = (S)0;
     }
     __syncthreads();
-    const uint32_t c1 = min(c0 + (uint32_t)kDepChunk, n);
+    const uint32_t c1 = min(c0 + chunk, n);
     for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
       const uint32_t w = a.w[i];
       if (!w) continue;
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
       tent_axis<T>(cj, o[1], K.ny, j0, fy);
       tent_axis<T>(ck, o[2], K.nz, k0, fz);
       if (mode == 0) {
-        tbl_cic<T>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
+        tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
         continue;
       }
       const T e[3] = {cic_get<T>(ctp<T>(Ex), K, i0, j0, k0, fx, fy, fz),
@@ -292,7 +294,7 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
                       cic_get<T>(ctp<T>(Ez), K, i0, j0, k0, fx, fy, fz)};
       const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
       const T mu = Mob<T>::mu(co, Em);
-      tbl_cic<T>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, mu * (T)w, (T)0, sig, ne);
+      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, mu * (T)w, (T)0, sig, ne);
       const uint64_t id = a.id[i];
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
       T nr[3];
@@ -300,7 +302,7 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
       tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
       tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
       tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
-      tbl_cic<T>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
+      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
@@ -491,17 +493,56 @@ __device__ __forceinline__ float hmean_s(float a, float b) { return __fdividef(2
 // Operator of the scaled system at one cell (homogeneous boundary values): sum over
 // faces of beta (u_c - u_nb), beta the harmonic mean of the two cells' coefficients,
 // plus 2 eps_c u_c on the Dirichlet z faces; x and y faces are Neumann.  Returned as
-// the diagonal and the neighbour sum.  Working-precision row through value accessors
-// a(dx, dy, dz) of the correction and of the coefficient at the neighbour (dx, dy, dz)
-// of cell (i, j, k), so the smoothers reading HBM and reading LDS share one arithmetic
-// order.  All thirteen values are read before any arithmetic (offsets clamped to the
-// cell itself on the domain faces), so their loads are in flight together; a face
-// outside the domain then contributes nothing, or the Dirichlet term, in the same
-// order as the faces are listed.
+// the diagonal and the neighbour sum, from the coefficient at the cell and the
+// coefficients and values at its six face neighbours (faces ordered x-, x+, y-, y+,
+// z-, z+; in[q] false for a face on the domain boundary, whose values are not used: it
+// contributes nothing, or the Dirichlet term).  Every finest- and coarse-level kernel
+// forms its rows through op_row (working precision) or op_row_r (double accumulation
+// for the residual), so all share one arithmetic order.
+template <typename T>
+__device__ __forceinline__ void op_row(T ec, const T en[6], const T un[6], const bool in[6], T& diag,
+                                       T& offsum) {
+  T d = 0, s = 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const T b = hmean_s(ec, en[q]);
+    d = in[q] ? d + b : (q >= 4 ? d + (T)2 * ec : d);
+    s = in[q] ? s + b * un[q] : s;
+  }
+  diag = d;
+  offsum = s;
+}
+
+// Residual row: face coefficients computed exactly as the smoother computes them
+// (single-precision harmonic means in FP32 mode, exact double in FP64 mode), the
+// potential and the accumulation in double.
+template <typename T>
+__device__ __forceinline__ void op_row_r(T ec, const T en[6], const double un[6], const bool in[6],
+                                         double& diag, double& offsum) {
+  double d = 0, s = 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double b = (double)hmean_s(ec, en[q]);
+    d = in[q] ? d + b : (q >= 4 ? d + 2.0 * (double)ec : d);
+    s = in[q] ? s + b * un[q] : s;
+  }
+  diag = d;
+  offsum = s;
+}
+
+__device__ __forceinline__ void faces_in(int i, int j, int k, int nx, int ny, int nz, bool in[6]) {
+  in[0] = i > 0; in[1] = i < nx - 1; in[2] = j > 0; in[3] = j < ny - 1; in[4] = k > 0; in[5] = k < nz - 1;
+}
+
+// Operator row through value accessors a(dx, dy, dz) of the correction and of the
+// coefficient at the neighbour (dx, dy, dz) of cell (i, j, k).  All thirteen values
+// are read before any arithmetic (offsets clamped to the cell itself on the domain
+// faces), so their loads are in flight together.
 template <typename T, typename UA, typename EA>
 __device__ __forceinline__ void stencil_acc(UA ua, EA ea, int nx, int ny, int nz, int i, int j, int k,
                                             T& diag, T& offsum) {
-  const bool in[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, k > 0, k < nz - 1};
+  bool in[6];
+  faces_in(i, j, k, nx, ny, nz, in);
   const int ox[6] = {in[0] ? -1 : 0, in[1] ? 1 : 0, 0, 0, 0, 0};
   const int oy[6] = {0, 0, in[2] ? -1 : 0, in[3] ? 1 : 0, 0, 0};
   const int oz[6] = {0, 0, 0, 0, in[4] ? -1 : 0, in[5] ? 1 : 0};
@@ -512,15 +553,7 @@ __device__ __forceinline__ void stencil_acc(UA ua, EA ea, int nx, int ny, int nz
     en[q] = ea(ox[q], oy[q], oz[q]);
     un[q] = ua(ox[q], oy[q], oz[q]);
   }
-  T d = 0, s = 0;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const T b = hmean_s(ec, en[q]);
-    d = in[q] ? d + b : (q >= 4 ? d + (T)2 * ec : d);
-    s = in[q] ? s + b * un[q] : s;
-  }
-  diag = d;
-  offsum = s;
+  op_row<T>(ec, en, un, in, diag, offsum);
 }
 
 template <typename T, typename AT>
@@ -538,15 +571,14 @@ __device__ __forceinline__ void stencil_s(const T* u, const T* eps, int nx, int 
   stencil_at<T>(u, eps, NatAt{(ptrdiff_t)c, sy, sz}, nx, ny, nz, i, j, k, diag, offsum);
 }
 
-// Operator row for the double residual with the face coefficients computed exactly as
-// the smoother computes them (single-precision harmonic means in FP32 mode, exact double
-// in FP64 mode), accumulated in double; the potential in natural order, the
-// coefficient through its level's positions `at`.
+// Residual operator row: the potential in natural order, the coefficient through its
+// level's positions `at`.
 template <typename T, typename AT>
 __device__ __forceinline__ void stencil_r(const double* u, const T* eps, AT at, int nx, int ny, int nz,
                                           int i, int j, int k, size_t c, double& diag, double& offsum) {
   const ptrdiff_t sy = (ptrdiff_t)nx, sz = (ptrdiff_t)nx * ny;
-  const bool in[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, k > 0, k < nz - 1};
+  bool in[6];
+  faces_in(i, j, k, nx, ny, nz, in);
   const int ox[6] = {in[0] ? -1 : 0, in[1] ? 1 : 0, 0, 0, 0, 0};
   const int oy[6] = {0, 0, in[2] ? -1 : 0, in[3] ? 1 : 0, 0, 0};
   const int oz[6] = {0, 0, 0, 0, in[4] ? -1 : 0, in[5] ? 1 : 0};
@@ -558,15 +590,7 @@ __device__ __forceinline__ void stencil_r(const double* u, const T* eps, AT at, 
     en[q] = eps[at(ox[q], oy[q], oz[q])];
     un[q] = u[(size_t)((ptrdiff_t)c + ox[q] + oy[q] * sy + oz[q] * sz)];
   }
-  double d = 0, s = 0;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const double b = (double)hmean_s(ec, en[q]);
-    d = in[q] ? d + b : (q >= 4 ? d + 2.0 * (double)ec : d);
-    s = in[q] ? s + b * un[q] : s;
-  }
-  diag = d;
-  offsum = s;
+  op_row_r<T>(ec, en, un, in, diag, offsum);
 }
 
 // Logical (x, y, z) block of a 3-D grid after the XCD remap.
@@ -579,6 +603,16 @@ __device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
   bz = (int)(l / (gridDim.x * gridDim.y));
 }
 
+// Gauss-Seidel update of cell (i, j, k) of a level in natural order.
+template <typename T>
+__device__ __forceinline__ void smooth_cell(T* u, const T* f, const T* eps, int nx, int ny, int nz, int i,
+                                            int j, int k) {
+  const size_t c = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
+  T d, s;
+  stencil_s<T>(u, eps, nx, ny, nz, i, j, k, c, d, s);
+  u[c] = (f[c] + s) / d;
+}
+
 // One colour of a red-black Gauss-Seidel sweep in natural order: grid (x: half a row,
 // y: j, z: k), every thread updates the one cell of the colour in its pair.  kFine
 // marks the finest level's instantiation, so that kernel traces report it apart.
@@ -589,10 +623,7 @@ __global__ void __launch_bounds__(128) k_smooth_rb(T* u, const T* f, const T* ep
   xcd_block3(bx, j, k);
   const int i = 2 * (int)(bx * blockDim.x + threadIdx.x) + ((j + k + color) & 1);
   if (i >= nx) return;
-  const size_t c = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
-  T d, s;
-  stencil_s<T>(u, eps, nx, ny, nz, i, j, k, c, d, s);
-  u[c] = (f[c] + s) / d;
+  smooth_cell<T>(u, f, eps, nx, ny, nz, i, j, k);
 }
 
 // One colour of a red-black sweep on the finest level in split order: grid (x: half a
@@ -651,15 +682,12 @@ __global__ void __launch_bounds__(256) k_residual_rows(const double* phi, const 
   if (threadIdx.x == 0) partial[blk] = acc;
 }
 
-// Coarse right-hand side (sum of the 8 child residuals / 2) and zero coarse correction;
-// grid (x: coarse row, y: cj, z: ck); the fine level in split order if kSplit.
+// Coarse right-hand side at coarse cell (ci, cj, ck): the sum of its 8 child residuals
+// / 2, in the children's order (x offset, then y, then z); zero coarse correction.  The
+// fine level in split order if kSplit.
 template <typename T, bool kSplit>
-__global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const T* eps, int nx, int ny,
-                                                  int nz, T* fc, T* uc, int cnx, int cny) {
-  int bx, cj, ck;
-  xcd_block3(bx, cj, ck);
-  const int ci = bx * blockDim.x + threadIdx.x;
-  if (ci >= cnx) return;
+__device__ __forceinline__ void restrict_cell(const T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                              T* fc, T* uc, int cnx, int cny, int ci, int cj, int ck) {
   T s8 = 0;
 #pragma unroll
   for (int d = 0; d < 8; ++d) {
@@ -682,23 +710,24 @@ __global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const
   uc[cc] = (T)0;
 }
 
+// Restriction launch: grid (x: coarse row, y: cj, z: ck).
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(128) k_restrict3(const T* u, const T* f, const T* eps, int nx, int ny,
+                                                  int nz, T* fc, T* uc, int cnx, int cny) {
+  int bx, cj, ck;
+  xcd_block3(bx, cj, ck);
+  const int ci = bx * blockDim.x + threadIdx.x;
+  if (ci >= cnx) return;
+  restrict_cell<T, kSplit>(u, f, eps, nx, ny, nz, fc, uc, cnx, cny, ci, cj, ck);
+}
+
 // Trilinear prolongation of the coarse correction onto cell centres: along each axis
 // the nearer coarse centre weighs 3/4 and the farther 1/4; coarse ghost values mirror
 // the cell on the Neumann x and y faces and negate it on the homogeneous Dirichlet z
 // faces.  (Second-order transfer: with cell-averaged restriction the transfer orders
 // then exceed the order of the operator.)
-template <typename T, bool kSplit>
-__global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, const T* uc, int cnx,
-                                                 int cny, int cnz) {
-  int bx, j, k;
-  xcd_block3(bx, j, k);
-  const int p = bx * blockDim.x + threadIdx.x;  // storage position in the row
-  if (p >= nx) return;
-  int i = p;
-  if constexpr (kSplit) {
-    const int h = nx >> 1, q = p >= h ? 1 : 0;
-    i = 2 * (p - q * h) + ((j + k + q) & 1);
-  }
+template <typename T>
+__device__ __forceinline__ T prolong_value(const T* uc, int cnx, int cny, int cnz, int i, int j, int k) {
   const int I = i >> 1, J = j >> 1, K = k >> 1;
   const int ia[2] = {I, (i & 1) ? I + 1 : I - 1};
   const int ja[2] = {J, (j & 1) ? J + 1 : J - 1};
@@ -716,13 +745,28 @@ __global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, 
     acc += wt[c & 1] * wt[(c >> 1) & 1] * wt[c >> 2] * sg *
            uc[(size_t)a + (size_t)cnx * ((size_t)b + (size_t)cny * z)];
   }
-  u[(size_t)p + (size_t)nx * ((size_t)j + (size_t)ny * k)] += acc;
+  return acc;
+}
+
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, const T* uc, int cnx,
+                                                 int cny, int cnz) {
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int p = bx * blockDim.x + threadIdx.x;  // storage position in the row
+  if (p >= nx) return;
+  int i = p;
+  if constexpr (kSplit) {
+    const int h = nx >> 1, q = p >= h ? 1 : 0;
+    i = 2 * (p - q * h) + ((j + k + q) & 1);
+  }
+  u[(size_t)p + (size_t)nx * ((size_t)j + (size_t)ny * k)] += prolong_value<T>(uc, cnx, cny, cnz, i, j, k);
 }
 
 // Coarsest level: red-black sweeps from zero inside one workgroup.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps, int nx, int ny, int nz,
-                                                int sweeps) {
+__device__ __forceinline__ void bottom_sweeps(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                              int sweeps) {
   const int n = nx * ny * nz;
   for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = (T)0;
   __syncthreads();
@@ -731,12 +775,354 @@ __global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps,
       for (int c = threadIdx.x; c < n; c += blockDim.x) {
         const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
         if (((i + j + k) & 1) != color) continue;
-        T d, sm;
-        stencil_s<T>(u, eps, nx, ny, nz, i, j, k, (size_t)c, d, sm);
-        u[c] = (f[c] + sm) / d;
+        smooth_cell<T>(u, f, eps, nx, ny, nz, i, j, k);
       }
       __syncthreads();
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                                int sweeps) {
+  bottom_sweeps<T>(u, f, eps, nx, ny, nz, sweeps);
+}
+
+// ---- finest level over row segments ---------------------------------------------------
+// With nx a multiple of 8 the finest-level kernels give each thread a segment of eight
+// cells of an x row (i = 8t .. 8t+7; the smoother: four cells of one colour).  In split
+// order a segment is positions 4t .. 4t+3 of both half rows, in natural order eight
+// consecutive values, so every access to the level's arrays is a 16-byte vector.  The
+// per-cell arithmetic is op_row / op_row_r, as in the one-cell kernels, and both orders
+// run the same segment kernels (the smoother has no reduction and is order-free), so
+// their results are identical.
+
+template <typename T>
+struct V4 {
+  T a[4];
+};
+
+template <typename T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+  V4<T> v;
+  if constexpr (sizeof(T) == 4) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v.a[0] = x.x; v.a[1] = x.y; v.a[2] = x.z; v.a[3] = x.w;
+  } else {
+    const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+    v.a[0] = x.x; v.a[1] = x.y; v.a[2] = y.x; v.a[3] = y.y;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const T a0, const T a1, const T a2, const T a3) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
+  } else {
+    reinterpret_cast<double2*>(p)[0] = make_double2(a0, a1);
+    reinterpret_cast<double2*>(p)[1] = make_double2(a2, a3);
+  }
+}
+
+// Cells 8t .. 8t+7 of the finest-level row starting at rb (parity par = (j + k) & 1),
+// in natural order; h = nx / 2.  Cell 8t + 2r + e has colour (e + par) & 1 and sits at
+// position 4t + r of that colour's half row.
+template <typename T, bool kSplit>
+__device__ __forceinline__ void ld_seg(const T* a, size_t rb, int h, int t, int par, T v[8]) {
+  if constexpr (kSplit) {
+    const V4<T> c0 = ld4(a + rb + 4 * t), c1 = ld4(a + rb + h + 4 * t);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      v[2 * r] = par ? c1.a[r] : c0.a[r];
+      v[2 * r + 1] = par ? c0.a[r] : c1.a[r];
+    }
+  } else {
+    const V4<T> a0 = ld4(a + rb + 8 * t), a1 = ld4(a + rb + 8 * t + 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      v[r] = a0.a[r];
+      v[4 + r] = a1.a[r];
+    }
+  }
+}
+
+template <typename T, bool kSplit>
+__device__ __forceinline__ void st_seg(T* a, size_t rb, int h, int t, int par, const T v[8]) {
+  if constexpr (kSplit) {
+    const int e0 = par, e1 = 1 - par;  // the natural parity of the colour-0 and colour-1 cells
+    st4<T>(a + rb + 4 * t, v[e0], v[2 + e0], v[4 + e0], v[6 + e0]);
+    st4<T>(a + rb + h + 4 * t, v[e1], v[2 + e1], v[4 + e1], v[6 + e1]);
+  } else {
+    st4<T>(a + rb + 8 * t, v[0], v[1], v[2], v[3]);
+    st4<T>(a + rb + 8 * t + 4, v[4], v[5], v[6], v[7]);
+  }
+}
+
+template <typename T, bool kSplit>
+__device__ __forceinline__ T ld_cell(const T* a, size_t rb, int h, int i, int par) {
+  if constexpr (kSplit) return a[rb + (((i + par) & 1) ? (size_t)h : 0) + (size_t)(i >> 1)];
+  else return a[rb + (size_t)i];
+}
+
+// Segment g of a level with ns segments per row: row index, t, j, k, parity.
+struct Seg {
+  uint32_t row;
+  int t, j, k, par;
+};
+
+__device__ __forceinline__ Seg seg_of(uint32_t g, int ns, int ny) {
+  Seg s;
+  s.row = g / (uint32_t)ns;
+  s.t = (int)(g - s.row * (uint32_t)ns);
+  s.k = (int)(s.row / (uint32_t)ny);
+  s.j = (int)(s.row - (uint32_t)s.k * (uint32_t)ny);
+  s.par = (s.j + s.k) & 1;
+  return s;
+}
+
+// The segment's row and its four neighbouring rows (each replaced by the row itself
+// where there is none: those values are not used), with their parities.
+struct SegRows {
+  size_t rb, ym, yp, zm, zp;
+  int pym, pyp, pzm, pzp;
+};
+
+__device__ __forceinline__ SegRows seg_rows(const Seg& s, int nx, int ny, int nz) {
+  SegRows R;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  R.rb = (size_t)s.row * sy;
+  R.ym = s.j > 0 ? R.rb - sy : R.rb;
+  R.yp = s.j < ny - 1 ? R.rb + sy : R.rb;
+  R.zm = s.k > 0 ? R.rb - sz : R.rb;
+  R.zp = s.k < nz - 1 ? R.rb + sz : R.rb;
+  R.pym = s.j > 0 ? s.par ^ 1 : s.par;
+  R.pyp = s.j < ny - 1 ? s.par ^ 1 : s.par;
+  R.pzm = s.k > 0 ? s.par ^ 1 : s.par;
+  R.pzp = s.k < nz - 1 ? s.par ^ 1 : s.par;
+  return R;
+}
+
+// A segment's values of one array: the eight cells, the cells before and after it in
+// the row (clamped to the segment at the row ends), and the same eight cells of the
+// four neighbouring rows.
+template <typename T>
+struct SegVals {
+  T c[8], ym[8], yp[8], zm[8], zp[8];
+  T l, r;
+};
+
+template <typename T, bool kSplit>
+__device__ __forceinline__ void ld_seg_vals(const T* a, const SegRows& R, const Seg& s, int nx, SegVals<T>& v) {
+  const int h = nx >> 1, i0 = 8 * s.t;
+  ld_seg<T, kSplit>(a, R.rb, h, s.t, s.par, v.c);
+  ld_seg<T, kSplit>(a, R.ym, h, s.t, R.pym, v.ym);
+  ld_seg<T, kSplit>(a, R.yp, h, s.t, R.pyp, v.yp);
+  ld_seg<T, kSplit>(a, R.zm, h, s.t, R.pzm, v.zm);
+  ld_seg<T, kSplit>(a, R.zp, h, s.t, R.pzp, v.zp);
+  v.l = ld_cell<T, kSplit>(a, R.rb, h, i0 > 0 ? i0 - 1 : i0, s.par);
+  v.r = ld_cell<T, kSplit>(a, R.rb, h, i0 + 8 < nx ? i0 + 8 : i0 + 7, s.par);
+}
+
+// Face-neighbour values of cell r of the segment (faces ordered as in op_row).
+template <typename T>
+__device__ __forceinline__ void seg_faces(const SegVals<T>& v, int r, T out[6]) {
+  out[0] = r > 0 ? v.c[r - 1] : v.l;
+  out[1] = r < 7 ? v.c[r + 1] : v.r;
+  out[2] = v.ym[r];
+  out[3] = v.yp[r];
+  out[4] = v.zm[r];
+  out[5] = v.zp[r];
+}
+
+// Double residual over segments (as k_residual_rows: a block takes every gridDim-th run
+// of 256 segments; one partial of ||r||^2 per block, each thread's eight cells summed
+// in order).
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(256) k_residual_seg(const double* phi, const double* b, const T* eps,
+                                                     int nx, int ny, int nz, T* f0, double* partial) {
+  const int ns = nx >> 3, h = nx >> 1;
+  const uint32_t nseg = (uint32_t)ns * ny * nz;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t runs = (nseg + 255u) / 256u;
+  double acc = 0.0;
+  for (uint32_t run = blk; run < runs; run += gridDim.x) {
+    const uint32_t g = run * 256u + threadIdx.x;
+    double rs = 0.0;
+    if (g < nseg) {
+      const Seg s = seg_of(g, ns, ny);
+      const SegRows R = seg_rows(s, nx, ny, nz);
+      SegVals<double> P;
+      SegVals<T> E;
+      ld_seg_vals<double, false>(phi, R, s, nx, P);
+      ld_seg_vals<T, kSplit>(eps, R, s, nx, E);
+      double B[8];
+      ld_seg<double, false>(b, R.rb, h, s.t, s.par, B);
+      T F[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        bool in[6];
+        faces_in(8 * s.t + r, s.j, s.k, nx, ny, nz, in);
+        T en[6];
+        double un[6];
+        seg_faces(E, r, en);
+        seg_faces(P, r, un);
+        double d, sm;
+        op_row_r<T>(E.c[r], en, un, in, d, sm);
+        const double rr = B[r] - (d * P.c[r] - sm);
+        F[r] = (T)rr;
+        rs += rr * rr;
+      }
+      st_seg<T, kSplit>(f0, R.rb, h, s.t, s.par, F);
+    }
+    acc += block_sumd(rs);
+  }
+  if (threadIdx.x == 0) partial[blk] = acc;
+}
+
+// One colour of a red-black sweep on the split finest level, four cells of the colour
+// per thread: cells i = 2m + odd for half-row positions m = 4t .. 4t+3, odd =
+// (j + k + colour) & 1.  Their x neighbours have the other colour, at positions
+// m - 1 + odd and m + odd.
+template <typename T>
+__global__ void __launch_bounds__(256) k_smooth_seg(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                                   int color) {
+  const int ns = nx >> 3, h = nx >> 1;
+  const uint32_t g = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (g >= (uint32_t)ns * ny * nz) return;
+  const Seg s = seg_of(g, ns, ny);
+  const int odd = (s.par + color) & 1;
+  const size_t rb = (size_t)s.row * nx;
+  const size_t own = rb + (color ? (size_t)h : 0) + 4 * s.t, oth = rb + (color ? 0 : (size_t)h) + 4 * s.t;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const size_t oym = s.j > 0 ? oth - sy : oth, oyp = s.j < ny - 1 ? oth + sy : oth;
+  const size_t ozm = s.k > 0 ? oth - sz : oth, ozp = s.k < nz - 1 ? oth + sz : oth;
+  const size_t pl = s.t > 0 ? oth - 1 : oth, pr = 4 * s.t + 4 < h ? oth + 4 : oth + 3;
+  const V4<T> Fo = ld4(f + own), Eo = ld4(eps + own);
+  const V4<T> Uc = ld4(u + oth), Ec = ld4(eps + oth);
+  const V4<T> Uym = ld4(u + oym), Eym = ld4(eps + oym), Uyp = ld4(u + oyp), Eyp = ld4(eps + oyp);
+  const V4<T> Uzm = ld4(u + ozm), Ezm = ld4(eps + ozm), Uzp = ld4(u + ozp), Ezp = ld4(eps + ozp);
+  const T UL = u[pl], EL = eps[pl], UR = u[pr], ER = eps[pr];
+  T un_[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    bool in[6];
+    faces_in(2 * (4 * s.t + r) + odd, s.j, s.k, nx, ny, nz, in);
+    const T en[6] = {odd ? Ec.a[r] : (r > 0 ? Ec.a[r - 1] : EL), odd ? (r < 3 ? Ec.a[r + 1] : ER) : Ec.a[r],
+                     Eym.a[r], Eyp.a[r], Ezm.a[r], Ezp.a[r]};
+    const T un[6] = {odd ? Uc.a[r] : (r > 0 ? Uc.a[r - 1] : UL), odd ? (r < 3 ? Uc.a[r + 1] : UR) : Uc.a[r],
+                     Uym.a[r], Uyp.a[r], Uzm.a[r], Uzp.a[r]};
+    T d, sm;
+    op_row<T>(Eo.a[r], en, un, in, d, sm);
+    un_[r] = (Fo.a[r] + sm) / d;
+  }
+  st4<T>(u + own, un_[0], un_[1], un_[2], un_[3]);
+}
+
+// Restriction from the finest level over segments: a thread takes four coarse cells
+// (coarse x 4t .. 4t+3) and their children, the fine segment t of four fine rows,
+// visited in the children's order (j offset, then k offset; x offset within a row), so
+// each coarse sum adds its eight child residuals in the order of k_restrict3.
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(256) k_restrict_seg(const T* u, const T* f, const T* eps, int nx, int ny,
+                                                     int nz, T* fc, T* uc) {
+  const int ns = nx >> 3, h = nx >> 1, cnx = nx >> 1, cny = ny >> 1, cnz = nz >> 1;
+  const uint32_t g = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (g >= (uint32_t)ns * cny * cnz) return;
+  const Seg cs = seg_of(g, ns, cny);
+  T s8[4] = {0, 0, 0, 0};
+#pragma unroll 1
+  for (int dd = 0; dd < 4; ++dd) {
+    Seg s;
+    s.t = cs.t;
+    s.j = 2 * cs.j + (dd & 1);
+    s.k = 2 * cs.k + (dd >> 1);
+    s.row = (uint32_t)s.j + (uint32_t)ny * (uint32_t)s.k;
+    s.par = (s.j + s.k) & 1;
+    const SegRows R = seg_rows(s, nx, ny, nz);
+    SegVals<T> U, E;
+    ld_seg_vals<T, kSplit>(u, R, s, nx, U);
+    ld_seg_vals<T, kSplit>(eps, R, s, nx, E);
+    T F[8];
+    ld_seg<T, kSplit>(f, R.rb, h, s.t, s.par, F);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      bool in[6];
+      faces_in(8 * s.t + r, s.j, s.k, nx, ny, nz, in);
+      T en[6], un[6];
+      seg_faces(E, r, en);
+      seg_faces(U, r, un);
+      T dg, sm;
+      op_row<T>(E.c[r], en, un, in, dg, sm);
+      s8[r >> 1] += F[r] - (dg * U.c[r] - sm);
+    }
+  }
+  const size_t cc = (size_t)cs.row * cnx + 4 * cs.t;
+  st4<T>(fc + cc, s8[0] * (T)0.5, s8[1] * (T)0.5, s8[2] * (T)0.5, s8[3] * (T)0.5);
+  st4<T>(uc + cc, (T)0, (T)0, (T)0, (T)0);
+}
+
+// Trilinear prolongation onto the finest level over segments: the coarse values of
+// the eight cells come from the coarse rows (J or its neighbour toward the cell) x
+// (K or its neighbour), x from 4t-1 to 4t+4 with the clamps and Dirichlet signs of
+// k_prolong3, in the same order and arithmetic.
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(256) k_prolong_seg(T* u, int nx, int ny, int nz, const T* uc, int cnx,
+                                                    int cny, int cnz) {
+  const int ns = nx >> 3, h = nx >> 1;
+  const uint32_t g = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (g >= (uint32_t)ns * ny * nz) return;
+  const Seg s = seg_of(g, ns, ny);
+  const int J = s.j >> 1, K = s.k >> 1;
+  const int jb = (s.j & 1) ? J + 1 : J - 1, kb = (s.k & 1) ? K + 1 : K - 1;
+  const int jbc = jb < 0 ? 0 : (jb >= cny ? cny - 1 : jb);
+  const int kbc = kb < 0 ? 0 : (kb >= cnz ? cnz - 1 : kb);
+  const T sgk = (kb < 0 || kb >= cnz) ? (T)-1 : (T)1;
+  T W[2][2][6];
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+    for (int dk = 0; dk < 2; ++dk) {
+      const size_t crow = (size_t)cnx * ((size_t)(dj ? jbc : J) + (size_t)cny * (size_t)(dk ? kbc : K));
+      const V4<T> m = ld4(uc + crow + 4 * s.t);
+      W[dj][dk][0] = uc[crow + (s.t > 0 ? 4 * s.t - 1 : 0)];
+      W[dj][dk][1] = m.a[0]; W[dj][dk][2] = m.a[1]; W[dj][dk][3] = m.a[2]; W[dj][dk][4] = m.a[3];
+      W[dj][dk][5] = uc[crow + (4 * s.t + 4 < cnx ? 4 * s.t + 4 : cnx - 1)];
+    }
+  const size_t rb = (size_t)s.row * nx;
+  T V[8];
+  ld_seg<T, kSplit>(u, rb, h, s.t, s.par, V);
+  const T wt[2] = {(T)0.75, (T)0.25};
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      // x: I = 4t + r/2 sits at window index r/2 + 1; the far neighbour is I + 1 for
+      // odd i and I - 1 for even i
+      const int xa = (c & 1) ? ((r & 1) ? (r >> 1) + 2 : (r >> 1)) : (r >> 1) + 1;
+      const T sg = (c >> 2) ? sgk : (T)1;
+      acc += wt[c & 1] * wt[(c >> 1) & 1] * wt[c >> 2] * sg * W[(c >> 1) & 1][c >> 2][xa];
+    }
+    V[r] += acc;
+  }
+  st_seg<T, kSplit>(u, rb, h, s.t, s.par, V);
+}
+
+// phi += u over the finest level, a segment per thread.
+template <typename T, bool kSplit>
+__global__ void __launch_bounds__(256) k_phi_update_seg(double* phi, const T* u, int nx, int ny, int nz) {
+  const int ns = nx >> 3, h = nx >> 1;
+  const uint32_t g = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (g >= (uint32_t)ns * ny * nz) return;
+  const Seg s = seg_of(g, ns, ny);
+  const size_t rb = (size_t)s.row * nx;
+  T V[8];
+  double P[8];
+  ld_seg<T, kSplit>(u, rb, h, s.t, s.par, V);
+  ld_seg<double, false>(phi, rb, h, s.t, s.par, P);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) P[r] += (double)V[r];
+  st_seg<double, false>(phi, rb, h, s.t, s.par, P);
 }
 
 // Initial guess by linear extrapolation in time: phi <- 2 phi - prev, prev <- old phi.
@@ -813,6 +1199,7 @@ struct FieldState {
   double* phi_prev = nullptr;  // converged potential of the previous step
   bool have_prev = false;
   bool split = false;  // finest level in split red-black order (nx even, more than one level)
+  bool seg = false;    // finest-level kernels over 8-cell row segments (nx % 8 == 0, more than one level)
   bool graph_failed = false;
   hipGraphExec_t graph_exec = nullptr;
   // optional timing of the finest-level smoother launches: event pairs recorded around
@@ -875,6 +1262,7 @@ int field_init(itokmc_ctx* ctx, char* base) {
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
   F->norms = (double*)p; p += al(8 * (8 + npart));
   F->nlev = nl;
+  F->seg = nl > 1 && d->nx % 8 == 0;
   for (int l = 0; l < nl; ++l) {
     Level& L = F->lev[l];
     L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
@@ -930,6 +1318,12 @@ static Coef coef(const itokmc_ctx* ctx) {
   return Coef{ctx->c.mu_a, ctx->c.mu_E0, ctx->c.mu_b, ctx->c.E_floor, ctx->c.D};
 }
 
+// Blocks of 256 threads for one thread per 8-cell row segment of an nx x ny x nz level.
+static int seg_blocks(int nx, int ny, int nz) {
+  const uint64_t n = (uint64_t)(nx >> 3) * ny * nz;
+  return (int)((n + 255) / 256);
+}
+
 static dim3 row_grid(int half_nx, int ny, int nz) {
   return dim3((unsigned)((half_nx + 127) / 128), (unsigned)ny, (unsigned)nz);
 }
@@ -949,8 +1343,12 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
   }
   const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
   if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
-  if (F->split) k_smooth_split<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
-  else k_smooth_rb<T, true><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  if (F->split && F->seg)
+    k_smooth_seg<T><<<seg_blocks(L.nx, L.ny, L.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  else if (F->split)
+    k_smooth_split<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  else
+    k_smooth_rb<T, true><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
   if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n + 1], s);
   if (timed) ++F->sm_n;
 }
@@ -963,6 +1361,13 @@ static void smooth_sweeps(FieldState* F, int l, hipStream_t s, int count) {
   }
 }
 
+static int bottom_count(const itokmc_ctx* ctx, const Level& L) {
+  int mx = L.nx > L.ny ? L.nx : L.ny;
+  mx = mx > L.nz ? mx : L.nz;
+  return ctx->tune.bottom_sweeps > 0 ? ctx->tune.bottom_sweeps : 4 * mx + 16;
+}
+
+// V-cycle from level l.
 template <typename T>
 static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   Level& L = F->lev[l];
@@ -970,21 +1375,29 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   const T* f = (const T*)L.f;
   const T* ep = (const T*)L.eps;
   if (l == F->nlev - 1) {
-    int mx = L.nx > L.ny ? L.nx : L.ny;
-    mx = mx > L.nz ? mx : L.nz;
-    const int bs = ctx->tune.bottom_sweeps > 0 ? ctx->tune.bottom_sweeps : 4 * mx + 16;
-    k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, bs);
+    k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, bottom_count(ctx, L));
     return;
   }
   Level& C = F->lev[l + 1];
   smooth_sweeps<T>(F, l, s, ctx->tune.mg_pre);
   const dim3 gr = row_grid(C.nx, C.ny, C.nz), gp = row_grid(L.nx, L.ny, L.nz);
-  if (l == 0 && F->split)
+  const int sb = seg_blocks(L.nx, L.ny, L.nz);
+  T* fcp = (T*)C.f;
+  T* ucp = (T*)C.u;
+  if (l == 0 && F->seg && F->split)
+    k_restrict_seg<T, true><<<seg_blocks(L.nx, C.ny, C.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
+  else if (l == 0 && F->seg)
+    k_restrict_seg<T, false><<<seg_blocks(L.nx, C.ny, C.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
+  else if (l == 0 && F->split)
     k_restrict3<T, true><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx, C.ny);
   else
     k_restrict3<T, false><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx, C.ny);
   vcycle<T>(ctx, F, l + 1, s);
-  if (l == 0 && F->split)
+  if (l == 0 && F->seg && F->split)
+    k_prolong_seg<T, true><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
+  else if (l == 0 && F->seg)
+    k_prolong_seg<T, false><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
+  else if (l == 0 && F->split)
     k_prolong3<T, true><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
   else
     k_prolong3<T, false><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
@@ -1009,6 +1422,18 @@ static void collect_smooth(itokmc_ctx* ctx, FieldState* F) {
 template <typename T>
 static void residual(FieldState* F, hipStream_t s) {
   Level& L0 = F->lev[0];
+  if (F->seg) {
+    const uint32_t runs = ((L0.n >> 3) + 255) / 256;
+    const int rb = runs < (uint32_t)kResBlocks ? (int)runs : kResBlocks;
+    if (F->split)
+      k_residual_seg<T, true><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
+                                                 (T*)L0.f, F->norms + 8);
+    else
+      k_residual_seg<T, false><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
+                                                  (T*)L0.f, F->norms + 8);
+    k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+    return;
+  }
   const uint32_t runs = (L0.n + 255) / 256;
   const int rb = runs < (uint32_t)kResBlocks ? (int)runs : kResBlocks;
   if (F->split)
@@ -1029,7 +1454,12 @@ static void refine_cycle(itokmc_ctx* ctx, FieldState* F, hipStream_t s) {
   k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
   vcycle<T>(ctx, F, 0, s);
   const dim3 gp = row_grid(L0.nx, L0.ny, L0.nz);
-  if (F->split) k_phi_update<T, true><<<gp, 128, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny);
+  const int sb = seg_blocks(L0.nx, L0.ny, L0.nz);
+  if (F->seg && F->split)
+    k_phi_update_seg<T, true><<<sb, 256, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny, L0.nz);
+  else if (F->seg)
+    k_phi_update_seg<T, false><<<sb, 256, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny, L0.nz);
+  else if (F->split) k_phi_update<T, true><<<gp, 128, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny);
   else k_phi_update<T, false><<<gp, 128, 0, s>>>(F->phi, (const T*)L0.u, L0.nx, L0.ny);
   residual<T>(F, s);
 }
@@ -1119,12 +1549,13 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   void* const* Eo = F->E[F->cur];
   phase_begin(ctx, PH_DEPOSIT);  // the deposit kernel alone
   {
-    constexpr int TBL = 1 << DepTbl<T>::log2n;
-    const size_t lds = (size_t)TBL * (4 + 2 * sizeof(S));
+    constexpr int L2 = DepTbl<T>::log2n;
+    const size_t lds = (size_t)(1 << L2) * (4 + 2 * sizeof(S));
     int g = (int)((ctx->cap + kDepChunk - 1) / kDepChunk);
-    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
-    k_field_deposit_lds<T><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1],
-                                               Eo[2], coef(ctx), mode, (S*)F->sig, (S*)F->ne);
+    g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
+    k_field_deposit_lds<T, L2><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1],
+                                                   Eo[2], coef(ctx), mode, (S*)F->sig, (S*)F->ne,
+                                                   (uint32_t)kDepChunk);
   }
   phase_end(ctx, PH_DEPOSIT);
   phase_begin(ctx, PH_FIELD_PREP);

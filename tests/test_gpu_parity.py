@@ -387,15 +387,45 @@ def _split_vs_natural(itk, precision, grid, steps):
     return out
 
 
-@pytest.mark.parametrize("grid", [(128, 128, 128), (48, 32, 40)])
+@pytest.mark.parametrize("grid", [(128, 128, 128), (48, 32, 40), (44, 24, 36)])
 def test_split_order_matches_natural_order(itk, grid):
     """The finest multigrid level stored in split red-black order (each x row holds one
     colour's cells in its first half) and in natural order: potential, field and
     particles after three self-consistent FP32 steps are bit-identical (every cell's
     arithmetic and every reduction order are the same in both, and the FP32 charge
-    deposit sums fixed-point integers)."""
+    deposit sums fixed-point integers).  nx = 128 and 48 run the 8-cell row-segment
+    kernels, nx = 44 the one-cell kernels."""
     (pa, ea, (ca, oa, wa, ia), na), (pb, eb, (cb, ob, wb, ib), nb) = \
         _split_vs_natural(itk, "fp32", grid, 3)
+    assert na == nb
+    assert np.array_equal(pa, pb) and np.array_equal(ea, eb)
+    ia, ca, oa, wa = by_id(ia, ca, oa, wa)
+    ib, cb, ob, wb = by_id(ib, cb, ob, wb)
+    assert np.array_equal(ia, ib) and np.array_equal(ca, cb) and np.array_equal(wa, wb)
+    assert np.array_equal(oa, ob)
+
+
+@pytest.mark.skip(reason="the single-workgroup coarse cycle faulted on the GPU (memory aperture "
+                         "violation) although every LDS index it forms was shown in bounds on the "
+                         "CPU; no cause found, the kernel and its tuning field were removed")
+@pytest.mark.parametrize("grid", [(64, 64, 64), (48, 32, 40)])
+def test_coarse_cycle_matches_per_level_launches(itk, grid):
+    """The coarsest multigrid levels (16^3 and below at 64^3; 12 x 8 x 10 and below at
+    48 x 32 x 40) cycled by one workgroup with the levels in LDS, and by one launch per
+    sweep and level: potential, field and particles after three self-consistent FP32
+    steps are bit-identical."""
+    nz = grid[2]
+    cfg = workloads.preset("streamer_64", grid=grid, dx=1e-3 / nz, V_anode=18e3 * nz / 64,
+                           seed_centre=tuple(0.5 * g * 1e-3 / nz for g in grid))
+    out = []
+    for cc in (1, 0):
+        g = itk.Sim(cfg)
+        g.set_tuning(coarse_cycle=cc)
+        g.seed()
+        g.step(3)
+        out.append((g.field(), g.deposit("ez"), g.particles(), g.diagnostics()["solver_cycles_total"]))
+        g.close()
+    (pa, ea, (ca, oa, wa, ia), na), (pb, eb, (cb, ob, wb, ib), nb) = out
     assert na == nb
     assert np.array_equal(pa, pb) and np.array_equal(ea, eb)
     ia, ca, oa, wa = by_id(ia, ca, oa, wa)
