@@ -463,12 +463,12 @@ int itokmc_get_particles(itokmc_ctx* ctx, uint64_t* n, uint32_t* cell, double* o
   std::vector<char> ho[3];
   for (int a = 0; a < 3; ++a) ho[a].resize((size_t)N * T);
   if (N) {
-    e = hipMemcpy(hw.data(), b.w, (size_t)N * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(hc_.data(), b.cell, (size_t)N * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(hid.data(), b.id, (size_t)N * 8, hipMemcpyDeviceToHost);
+    e = copy_on(ctx->s, hw.data(), b.w, (size_t)N * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = copy_on(ctx->s, hc_.data(), b.cell, (size_t)N * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = copy_on(ctx->s, hid.data(), b.id, (size_t)N * 8, hipMemcpyDeviceToHost);
     void* src[3] = {b.ox, b.oy, b.oz};
     for (int a = 0; a < 3 && e == hipSuccess; ++a)
-      e = hipMemcpy(ho[a].data(), src[a], (size_t)N * T, hipMemcpyDeviceToHost);
+      e = copy_on(ctx->s, ho[a].data(), src[a], (size_t)N * T, hipMemcpyDeviceToHost);
     rc = check_hip(ctx, e, "get_particles copy");
     if (rc) return rc;
   }
@@ -516,13 +516,13 @@ int itokmc_set_particles(itokmc_ctx* ctx, uint64_t n, const uint32_t* cell, cons
       }
     }
     void* dst[3] = {b.ox, b.oy, b.oz};
-    if (e == hipSuccess) e = hipMemcpy(b.cell, cell, n * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b.w, w, n * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b.id, id, n * 8, hipMemcpyHostToDevice);
-    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = hipMemcpy(dst[a], ho[a].data(), ho[a].size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = copy_on(ctx->s, b.cell, cell, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = copy_on(ctx->s, b.w, w, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = copy_on(ctx->s, b.id, id, n * 8, hipMemcpyHostToDevice);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = copy_on(ctx->s, dst[a], ho[a].data(), ho[a].size(), hipMemcpyHostToDevice);
   }
   const uint32_t nn = (uint32_t)n;
-  if (e == hipSuccess) e = hipMemcpy(&ctx->ctr->n[ctx->cur], &nn, 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = copy_on(ctx->s, &ctx->ctr->n[ctx->cur], &nn, 4, hipMemcpyHostToDevice);
   int rc = check_hip(ctx, e, "set_particles");
   if (rc) return rc;
   ctx->binned = false;
@@ -544,7 +544,7 @@ int itokmc_get_counts(itokmc_ctx* ctx, int which, uint32_t* host) {
   uint32_t* p = counts_ptr(ctx, which);
   if (!p) return set_error(ctx, ITOKMC_EINVAL, "bad count selector");
   hipError_t e = hipStreamSynchronize(ctx->s);
-  if (e == hipSuccess) e = hipMemcpy(host, p, (size_t)ctx->ncell * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = copy_on(ctx->s, host, p, (size_t)ctx->ncell * 4, hipMemcpyDeviceToHost);
   return check_hip(ctx, e, "get_counts");
 }
 
@@ -553,7 +553,7 @@ int itokmc_set_counts(itokmc_ctx* ctx, int which, const uint32_t* host) {
   uint32_t* p = counts_ptr(ctx, which);
   if (!p) return set_error(ctx, ITOKMC_EINVAL, "bad count selector");
   hipError_t e = hipStreamSynchronize(ctx->s);
-  if (e == hipSuccess) e = hipMemcpy(p, host, (size_t)ctx->ncell * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = copy_on(ctx->s, p, host, (size_t)ctx->ncell * 4, hipMemcpyHostToDevice);
   ctx->field_valid = false;
   return check_hip(ctx, e, "set_counts");
 }

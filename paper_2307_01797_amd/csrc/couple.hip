@@ -12,6 +12,8 @@
 // The arithmetic and its order are the same on both paths.
 #include <math.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "itk.hpp"
 #include "couple_device.hpp"
@@ -91,8 +93,8 @@ __global__ void __launch_bounds__(256) k_couple_light(Bank b, Counters* ctr, Ste
 
 // One wavefront per cell: the cells of full_list (removal, products, merge) and then
 // those of merge_list (merge only; the light pass did the rest).
-template <typename T>
-__global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which, StepConst K,
+template <typename T, int NL>
+__global__ void __launch_bounds__(64, 5) k_couple(Bank b, Counters* ctr, int which, StepConst K,
                                               const uint32_t* full_list, const uint32_t* merge_list,
                                               const uint32_t* occ, const uint32_t* start,
                                               const int32_t* dN, const uint32_t* cbase, int n_new,
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
     pieces += (e - s) + M;
     if (n_ppc > 0) {
       __syncthreads();  // removal and product stores visible before the merge gathers them
-      const int r = merge_cell<T, kMergeTiny>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
+      const int r = merge_cell<T, kMergeTiny, NL>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
       if (r == 2 && lane == 0) big[atomicAdd(&ctr->n_big, 1u)] = j;
     }
   }
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(64) k_couple(Bank b, Counters* ctr, int which,
 // Cells whose particles exceed a staging area, merged with the next larger one:
 // tier CAP reads its cells from list `in` (count *n_in); cells exceeding CAP go to
 // list `out` (count *n_out) or, from the largest tier, are left unmerged and counted.
-template <typename T, int CAP>
+template <typename T, int CAP, int NL>
 __global__ void __launch_bounds__(64) k_merge_tier(Bank b, Counters* ctr, int which, StepConst K,
                                                   const uint32_t* in, const uint32_t* n_in,
                                                   uint32_t* out, uint32_t* n_out,
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(64) k_merge_tier(Bank b, Counters* ctr, int wh
     const uint32_t M = d > 0 ? ((uint32_t)d < (uint32_t)n_new ? (uint32_t)d : (uint32_t)n_new) : 0u;
     const uint32_t base = M ? cbase[j] : 0u;
     const uint32_t e = j + 1 < n_occ ? start[occ[j + 1]] : sorted;
-    const int r = merge_cell<T, CAP>(b, ctr, which, K, c, start[c], e, base, M, n_ppc, &merged);
+    const int r = merge_cell<T, CAP, NL>(b, ctr, which, K, c, start[c], e, base, M, n_ppc, &merged);
     if (r == 2 && lane_id() == 0) {
       if (out) out[atomicAdd(n_out, 1u)] = j;
       else atomicAdd(&ctr->merge_skipped, 1u);
@@ -187,36 +189,37 @@ hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k) {
   phase_begin(ctx, PH_COUPLE);  // the wavefront-per-cell kernel alone
   int g = (int)(ctx->ncell < 65536u ? ctx->ncell : 65536u);
   if (g < 1) g = 1;
-  if (f64)
-    k_couple<double><<<g, 64, merge_lds_bytes<double>(ctx->d.n_ppc), ctx->s>>>(
-        ctx->bank[dest], ctx->ctr, dest, k, ctx->cfull, ctx->cmerge, ctx->occ, ctx->start, ctx->dN,
-        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ctx->big);
-  else
-    k_couple<float><<<g, 64, merge_lds_bytes<float>(ctx->d.n_ppc), ctx->s>>>(
-        ctx->bank[dest], ctx->ctr, dest, k, ctx->cfull, ctx->cmerge, ctx->occ, ctx->start, ctx->dN,
-        ctx->cbase, ctx->d.n_new, ctx->d.n_ppc, ctx->big);
+  const int nl = merge_leaves(ctx->d.n_ppc);
+  auto wave = [&](auto tt, auto nlt) {
+    using T = decltype(tt);
+    constexpr int NL = decltype(nlt)::value;
+    const size_t lds = ctx->d.n_ppc > 0 ? merge_lds_bytes_c<T, kMergeTiny, NL>() : 0;
+    k_couple<T, NL><<<g, 64, lds, ctx->s>>>(ctx->bank[dest], ctx->ctr, dest, k, ctx->cfull, ctx->cmerge,
+                                          ctx->occ, ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,
+                                          ctx->d.n_ppc, ctx->big);
+  };
+  using N32 = std::integral_constant<int, 32>;
+  using N64 = std::integral_constant<int, kMaxMergePpc>;
+  if (f64) { if (nl == 32) wave(0.0, N32{}); else wave(0.0, N64{}); }
+  else { if (nl == 32) wave(0.0f, N32{}); else wave(0.0f, N64{}); }
   hipError_t e = hipGetLastError();
   phase_end(ctx, PH_COUPLE);
   if (e != hipSuccess || ctx->d.n_ppc == 0) return e;
   phase_begin(ctx, PH_MERGE);  // the larger merge tiers
   Counters* C = ctx->ctr;
-  if (f64) {
-    k_merge_tier<double, kMergeSmall><<<2048, 64, merge_lds_bytes_c<double, kMergeSmall>(), ctx->s>>>(
+  auto tiers = [&](auto tt, auto nlt) {
+    using T = decltype(tt);
+    constexpr int NL = decltype(nlt)::value;
+    constexpr int BIG = MergeBig<T>::value;
+    k_merge_tier<T, kMergeSmall, NL><<<2048, 64, merge_lds_bytes_c<T, kMergeSmall, NL>(), ctx->s>>>(
         ctx->bank[dest], C, dest, k, ctx->big, &C->n_big, ctx->huge, &C->n_huge, ctx->occ, ctx->start,
         ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
-    k_merge_tier<double, MergeBig<double>::value>
-        <<<1024, 64, merge_lds_bytes_c<double, MergeBig<double>::value>(), ctx->s>>>(
-            ctx->bank[dest], C, dest, k, ctx->huge, &C->n_huge, nullptr, nullptr, ctx->occ, ctx->start,
-            ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
-  } else {
-    k_merge_tier<float, kMergeSmall><<<2048, 64, merge_lds_bytes_c<float, kMergeSmall>(), ctx->s>>>(
-        ctx->bank[dest], C, dest, k, ctx->big, &C->n_big, ctx->huge, &C->n_huge, ctx->occ, ctx->start,
+    k_merge_tier<T, BIG, NL><<<1024, 64, merge_lds_bytes_c<T, BIG, NL>(), ctx->s>>>(
+        ctx->bank[dest], C, dest, k, ctx->huge, &C->n_huge, nullptr, nullptr, ctx->occ, ctx->start,
         ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
-    k_merge_tier<float, MergeBig<float>::value>
-        <<<1024, 64, merge_lds_bytes_c<float, MergeBig<float>::value>(), ctx->s>>>(
-            ctx->bank[dest], C, dest, k, ctx->huge, &C->n_huge, nullptr, nullptr, ctx->occ, ctx->start,
-            ctx->dN, ctx->cbase, ctx->d.n_new, ctx->d.n_ppc);
-  }
+  };
+  if (f64) { if (nl == 32) tiers(0.0, N32{}); else tiers(0.0, N64{}); }
+  else { if (nl == 32) tiers(0.0f, N32{}); else tiers(0.0f, N64{}); }
   phase_end(ctx, PH_MERGE);
   return hipGetLastError();
 }

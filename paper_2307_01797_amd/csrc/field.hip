@@ -117,16 +117,23 @@ __device__ __forceinline__ void cic_add(T* grid, const StepConst& K, int i0, int
 template <typename T>
 __device__ __forceinline__ T cic_get(const T* grid, const StepConst& K, int i0, int j0, int k0, T fx,
                                      T fy, T fz) {
+  // the eight values are loaded together (node indices clamped into the grid; a node
+  // outside it has weight zero and is skipped), then summed in node order
   const int nx = K.nx, ny = K.ny, nz = K.nz;
-  T acc = (T)0;
+  T v[8], wt[8];
+  bool use[8];
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {
     const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
-    const T wt = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
+    wt[cc] = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
     const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
-    if (wt == (T)0 || ii >= nx || jj >= ny || kk >= nz) continue;
-    acc += grid[(size_t)ii + (size_t)nx * ((size_t)jj + (size_t)ny * kk)] * wt;
+    use[cc] = !(wt[cc] == (T)0 || ii >= nx || jj >= ny || kk >= nz);
+    const int ic = ii < nx ? ii : nx - 1, jc = jj < ny ? jj : ny - 1, kc = kk < nz ? kk : nz - 1;
+    v[cc] = grid[(size_t)ic + (size_t)nx * ((size_t)jc + (size_t)ny * kc)];
   }
+  T acc = (T)0;
+#pragma unroll
+  for (int cc = 0; cc < 8; ++cc) acc = use[cc] ? acc + v[cc] * wt[cc] : acc;
   return acc;
 }
 
@@ -1623,14 +1630,14 @@ FieldRates field_rates(itokmc_ctx* ctx) {
 int field_get_phi(itokmc_ctx* ctx, double* host) {
   FieldState* F = fs(ctx);
   hipError_t e = hipStreamSynchronize(ctx->s);
-  if (e == hipSuccess) e = hipMemcpy(host, F->phi, (size_t)ctx->ncell * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = copy_on(ctx->s, host, F->phi, (size_t)ctx->ncell * 8, hipMemcpyDeviceToHost);
   return check_hip(ctx, e, "get_field");
 }
 
 int field_set_phi(itokmc_ctx* ctx, const double* host) {
   FieldState* F = fs(ctx);
   hipError_t e = hipStreamSynchronize(ctx->s);
-  if (e == hipSuccess) e = hipMemcpy(F->phi, host, (size_t)ctx->ncell * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = copy_on(ctx->s, F->phi, host, (size_t)ctx->ncell * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) return check_hip(ctx, e, "set_field");
   F->have_prev = false;
   const uint32_t n = ctx->ncell;

@@ -10,6 +10,13 @@
 #include "../../include/itokmc.h"
 
 namespace itk {
+// Host copies of the library go through the context's stream and wait for it: never the
+// legacy default stream, which the runtime forbids while any other thread captures a
+// stream into a graph.
+inline hipError_t copy_on(hipStream_t s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+  return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
 
 // Structure-of-arrays particle bank.  Offsets are cell-relative in [0,1) and stored
 // in the working precision (float or double) as three separate arrays so that each

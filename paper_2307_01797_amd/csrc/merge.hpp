@@ -56,10 +56,10 @@ template <typename T, int CAP> struct MergePacked {
   static constexpr bool value = MergeContig<CAP>::value && sizeof(T) == 4;
 };
 
-template <typename T, int CAP>
+// NL: leaf capacity (at least n_ppc): 32 for n_ppc <= 32, else kMaxMergePpc.
+template <typename T, int CAP, int NL = kMaxMergePpc>
 constexpr size_t merge_lds_bytes_c() {
-  constexpr size_t S = (size_t)CAP + kMaxMergePpc;
-  constexpr size_t NL = kMaxMergePpc;
+  constexpr size_t S = (size_t)CAP + NL;
   constexpr size_t U = sizeof(typename Bits<T>::U);
   return S * (8 + 3 * sizeof(T) + 4 + 2 * 2 + 3)  // store, two index buffers, three tag arrays
          + (MergeContig<CAP>::value ? S * (sizeof(T) + 8) : 0)  // contiguous keys and ids
@@ -67,10 +67,7 @@ constexpr size_t merge_lds_bytes_c() {
          + NL * (6 * 4 + 3 * 4 + 6 * U + 1)        // leaf records, per-leaf scratch, extents, axis
          + 64;
 }
-template <typename T>
-inline size_t merge_lds_bytes(int n_ppc) {
-  return n_ppc > 0 ? merge_lds_bytes_c<T, kMergeTiny>() : 0;
-}
+inline int merge_leaves(int n_ppc) { return n_ppc <= 32 ? 32 : kMaxMergePpc; }
 
 // (coordinate, id rank) as one ordered integer (single precision; -0 folds to +0).
 __device__ __forceinline__ uint64_t packed_key(float k, uint32_t r) {
@@ -85,13 +82,12 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 // Returns 0 if the cell needs no merge, 1 if it was merged, 2 if it holds more than CAP
 // pieces (nothing written; the caller defers it to a larger staging area).
-template <typename T, int CAP>
+template <typename T, int CAP, int NL>
 __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, uint32_t c,
                           uint32_t s, uint32_t e, uint32_t base, uint32_t M, int n_ppc,
                           uint64_t* merged) {
   using U = typename Bits<T>::U;
-  constexpr int S = CAP + kMaxMergePpc;
-  constexpr int NL = kMaxMergePpc;
+  constexpr int S = CAP + NL;
   constexpr uint8_t kNone = 0xFF;
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
