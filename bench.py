@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 #                      read u and eps of the other colour's cells, f and eps of the
 #                      colour's cells, write u of the colour's cells: 2.5 S
 KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k_field_deposit_lds",
-           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_split"}
+           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_seg"}
 
 
 def bytes_per_unit(phase, S):
@@ -55,7 +55,7 @@ def parse():
     p.add_argument("--realizations", type=int, default=256)
     p.add_argument("--rate", type=float, default=200.0)
     p.add_argument("--duration", type=float, default=60.0)
-    p.add_argument("--poisson-frac", type=float, default=0.1)
+    p.add_argument("--poisson-frac", type=float, default=0.004)
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--drain", type=float, default=60.0)
     p.add_argument("--poisson-workers", type=int, default=4)
