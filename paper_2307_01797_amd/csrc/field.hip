@@ -770,13 +770,12 @@ __global__ void __launch_bounds__(128) k_prolong3(T* u, int nx, int ny, int nz, 
   u[(size_t)p + (size_t)nx * ((size_t)j + (size_t)ny * k)] += prolong_value<T>(uc, cnx, cny, cnz, i, j, k);
 }
 
-// Coarsest level: red-black sweeps from zero inside one workgroup.
+// `sweeps` red-black sweeps of a small level inside one workgroup (a barrier between
+// colours), the cell updates of the one-colour launches.
 template <typename T>
-__device__ __forceinline__ void bottom_sweeps(T* u, const T* f, const T* eps, int nx, int ny, int nz,
-                                              int sweeps) {
+__device__ __forceinline__ void rb_sweeps(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                          int sweeps) {
   const int n = nx * ny * nz;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = (T)0;
-  __syncthreads();
   for (int s = 0; s < sweeps; ++s)
     for (int color = 0; color < 2; ++color) {
       for (int c = threadIdx.x; c < n; c += blockDim.x) {
@@ -788,10 +787,23 @@ __device__ __forceinline__ void bottom_sweeps(T* u, const T* f, const T* eps, in
     }
 }
 
+// Levels of at most kSmallLevel cells: all pre- or post-sweeps in one launch.
+constexpr uint32_t kSmallLevel = 4096;
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_sweeps_small(T* u, const T* f, const T* eps, int nx, int ny,
+                                                      int nz, int sweeps) {
+  rb_sweeps<T>(u, f, eps, nx, ny, nz, sweeps);
+}
+
+// Coarsest level: red-black sweeps from zero inside one workgroup.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps, int nx, int ny, int nz,
                                                 int sweeps) {
-  bottom_sweeps<T>(u, f, eps, nx, ny, nz, sweeps);
+  const int n = nx * ny * nz;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = (T)0;
+  __syncthreads();
+  rb_sweeps<T>(u, f, eps, nx, ny, nz, sweeps);
 }
 
 // ---- finest level over row segments ---------------------------------------------------
@@ -1362,6 +1374,12 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
 
 template <typename T>
 static void smooth_sweeps(FieldState* F, int l, hipStream_t s, int count) {
+  Level& L = F->lev[l];
+  if (l > 0 && L.n <= kSmallLevel) {
+    if (count > 0)
+      k_sweeps_small<T><<<1, 1024, 0, s>>>((T*)L.u, (const T*)L.f, (const T*)L.eps, L.nx, L.ny, L.nz, count);
+    return;
+  }
   for (int it = 0; it < count; ++it) {
     smooth<T>(F, l, s, 0);
     smooth<T>(F, l, s, 1);

@@ -173,7 +173,9 @@ __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int whi
 // computational photons; each is emitted uniformly in the cell, isotropically, and
 // travels an exponential distance whose mean is log-uniform in [l1, l2].  Absorbed
 // photons make one electron of the photon's weight plus as many positive ions in the
-// absorbing cell; photons leaving the domain are removed.  Geometry in double.
+// absorbing cell; photons leaving the domain are removed.  Geometry in double.  The
+// grid stride runs over wavefront-uniform bases, so that every lane takes part in the
+// reservation of its cell's photon slots.
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int which,
@@ -184,12 +186,15 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
   const double two_pi = 6.283185307179586476925286766559;
   const double lr = l2 / l1;
   uint64_t absorbed = 0, lost = 0;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < k.ncell;
-       c += gridDim.x * blockDim.x) {
-    const uint32_t ng = ngamma[c];
+  for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < k.ncell; c0 += gridDim.x * blockDim.x) {
+    const uint32_t c = c0 + threadIdx.x;
+    const uint32_t ng = c < k.ncell ? ngamma[c] : 0u;
+    const uint32_t M = ng < (uint32_t)n_new ? ng : (uint32_t)n_new;
+    // one atomic per wavefront reserves every photon's slot; a photon that leaves the
+    // domain leaves its slot dead (weight 0), which the scatter skips
+    const uint32_t slot0 = wave_append(&ctr->n[which], M);
     if (ng == 0) continue;
     ngamma[c] = 0;
-    const uint32_t M = ng < (uint32_t)n_new ? ng : (uint32_t)n_new;
     const uint32_t wb = ng / M, wr = ng % M;
     const double ci = (double)(c % (uint32_t)k.nx), cj = (double)((c / (uint32_t)k.nx) % (uint32_t)k.ny),
                  ck = (double)(c / ((uint32_t)k.nx * (uint32_t)k.ny));
@@ -206,11 +211,15 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
                            ck + u24(A.z) + rg * cth};
       const bool in = y[0] >= 0.0 && y[0] < k.nx && y[1] >= 0.0 && y[1] < k.ny && y[2] >= 0.0 &&
                       y[2] < k.nz;
-      if (!in) { lost += w; continue; }
+      const uint32_t q = slot0 + s;
+      if (!in) {
+        lost += w;
+        if (q < k.cap) a.w[q] = 0u;
+        continue;
+      }
       const double f[3] = {floor(y[0]), floor(y[1]), floor(y[2])};
       const uint32_t cell =
           (uint32_t)f[0] + (uint32_t)k.nx * ((uint32_t)f[1] + (uint32_t)k.ny * (uint32_t)f[2]);
-      const uint32_t q = atomicAdd(&ctr->n[which], 1u);
       if (q >= k.cap) { atomicOr(&ctr->overflow, 1u); continue; }
       put<T>(a, q, cell, to_off<T>(y[0] - f[0]), to_off<T>(y[1] - f[1]), to_off<T>(y[2] - f[2]), w,
              make_id(KIND_PHOTO, k.step, c, s));
