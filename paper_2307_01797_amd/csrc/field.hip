@@ -54,6 +54,36 @@ __device__ __forceinline__ T* tp(void* p) { return reinterpret_cast<T*>(p); }
 template <typename T>
 __device__ __forceinline__ const T* ctp(const void* p) { return reinterpret_cast<const T*>(p); }
 
+// Four values of T as one 16- (float) or two 16-byte (double) accesses.
+template <typename T>
+struct V4 {
+  T a[4];
+};
+
+template <typename T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+  V4<T> v;
+  if constexpr (sizeof(T) == 4) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v.a[0] = x.x; v.a[1] = x.y; v.a[2] = x.z; v.a[3] = x.w;
+  } else {
+    const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+    v.a[0] = x.x; v.a[1] = x.y; v.a[2] = y.x; v.a[3] = y.y;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const T a0, const T a1, const T a2, const T a3) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
+  } else {
+    reinterpret_cast<double2*>(p)[0] = make_double2(a0, a1);
+    reinterpret_cast<double2*>(p)[1] = make_double2(a2, a3);
+  }
+}
+
+
 constexpr int kRedBlocks = 1024;  // fixed grid of the norm kernels: one partial per block
 
 // Block-wide sum of a double (256 threads), valid in thread 0.
@@ -114,13 +144,16 @@ __device__ __forceinline__ void cic_add(T* grid, const StepConst& K, int i0, int
   }
 }
 
+// The field at a particle (CIC interpolation, section "Charge deposition &
+// interpolation") from the packed (Ex, Ey, Ez, 0) array: the eight nodes' vectors are
+// loaded together (node indices clamped into the grid; a node outside it has weight
+// zero and is skipped), then each component is summed in node order.
 template <typename T>
-__device__ __forceinline__ T cic_get(const T* grid, const StepConst& K, int i0, int j0, int k0, T fx,
-                                     T fy, T fz) {
-  // the eight values are loaded together (node indices clamped into the grid; a node
-  // outside it has weight zero and is skipped), then summed in node order
+__device__ __forceinline__ void cic_get3(const T* E4, const StepConst& K, int i0, int j0, int k0, T fx,
+                                         T fy, T fz, T out[3]) {
   const int nx = K.nx, ny = K.ny, nz = K.nz;
-  T v[8], wt[8];
+  V4<T> v[8];
+  T wt[8];
   bool use[8];
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {
@@ -129,12 +162,15 @@ __device__ __forceinline__ T cic_get(const T* grid, const StepConst& K, int i0, 
     const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
     use[cc] = !(wt[cc] == (T)0 || ii >= nx || jj >= ny || kk >= nz);
     const int ic = ii < nx ? ii : nx - 1, jc = jj < ny ? jj : ny - 1, kc = kk < nz ? kk : nz - 1;
-    v[cc] = grid[(size_t)ic + (size_t)nx * ((size_t)jc + (size_t)ny * kc)];
+    v[cc] = ld4(E4 + 4 * ((size_t)ic + (size_t)nx * ((size_t)jc + (size_t)ny * kc)));
   }
-  T acc = (T)0;
 #pragma unroll
-  for (int cc = 0; cc < 8; ++cc) acc = use[cc] ? acc + v[cc] * wt[cc] : acc;
-  return acc;
+  for (int a = 0; a < 3; ++a) {
+    T acc = (T)0;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) acc = use[cc] ? acc + v[cc].a[a] * wt[cc] : acc;
+    out[a] = acc;
+  }
 }
 
 template <typename T> struct Mob;
@@ -260,8 +296,7 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
 
 template <typename T, int L2>
 __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
-                                                          StepConst K, const void* Ex,
-                                                          const void* Ey, const void* Ez, Coef co,
+                                                          StepConst K, const void* E4, Coef co,
                                                           int mode, typename DepAcc<T>::S* sig,
                                                           typename DepAcc<T>::S* ne, uint32_t chunk) {
   using S = typename DepAcc<T>::S;
@@ -296,9 +331,8 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
         tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
         continue;
       }
-      const T e[3] = {cic_get<T>(ctp<T>(Ex), K, i0, j0, k0, fx, fy, fz),
-                      cic_get<T>(ctp<T>(Ey), K, i0, j0, k0, fx, fy, fz),
-                      cic_get<T>(ctp<T>(Ez), K, i0, j0, k0, fx, fy, fz)};
+      T e[3];
+      cic_get3<T>(ctp<T>(E4), K, i0, j0, k0, fx, fy, fz, e);
       const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
       const T mu = Mob<T>::mu(co, Em);
       tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, mu * (T)w, (T)0, sig, ne);
@@ -327,9 +361,7 @@ __global__ void __launch_bounds__(256) k_field_deposit_lds(Bank a, const Counter
 template <typename T>
 __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int which,
                                                    unsigned long long* cellacc, uint32_t* tiles,
-                                                   StepConst K,
-                                                   const void* Eox, const void* Eoy, const void* Eoz,
-                                                   const void* Enx, const void* Eny, const void* Enz,
+                                                   StepConst K, const void* Eo4, const void* En4,
                                                    Coef co) {
   const uint32_t n = min(ctr->n[which], K.cap);
   const T diff = (T)K.diff;
@@ -350,12 +382,9 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
       tent_axis<T>(ci[0], o[0], K.nx, i0, fx);
       tent_axis<T>(ci[1], o[1], K.ny, j0, fy);
       tent_axis<T>(ci[2], o[2], K.nz, k0, fz);
-      const T eo[3] = {cic_get<T>(ctp<T>(Eox), K, i0, j0, k0, fx, fy, fz),
-                       cic_get<T>(ctp<T>(Eoy), K, i0, j0, k0, fx, fy, fz),
-                       cic_get<T>(ctp<T>(Eoz), K, i0, j0, k0, fx, fy, fz)};
-      const T en[3] = {cic_get<T>(ctp<T>(Enx), K, i0, j0, k0, fx, fy, fz),
-                       cic_get<T>(ctp<T>(Eny), K, i0, j0, k0, fx, fy, fz),
-                       cic_get<T>(ctp<T>(Enz), K, i0, j0, k0, fx, fy, fz)};
+      T eo[3], en[3];
+      cic_get3<T>(ctp<T>(Eo4), K, i0, j0, k0, fx, fy, fz, eo);
+      cic_get3<T>(ctp<T>(En4), K, i0, j0, k0, fx, fy, fz, en);
       const T mu = Mob<T>::mu(co, sqrt(eo[0] * eo[0] + eo[1] * eo[1] + eo[2] * eo[2]));
       const uint64_t id = a.id[i];
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
@@ -815,34 +844,6 @@ __global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps,
 // run the same segment kernels (the smoother has no reduction and is order-free), so
 // their results are identical.
 
-template <typename T>
-struct V4 {
-  T a[4];
-};
-
-template <typename T>
-__device__ __forceinline__ V4<T> ld4(const T* p) {
-  V4<T> v;
-  if constexpr (sizeof(T) == 4) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    v.a[0] = x.x; v.a[1] = x.y; v.a[2] = x.z; v.a[3] = x.w;
-  } else {
-    const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
-    v.a[0] = x.x; v.a[1] = x.y; v.a[2] = y.x; v.a[3] = y.y;
-  }
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ void st4(T* p, const T a0, const T a1, const T a2, const T a3) {
-  if constexpr (sizeof(T) == 4) {
-    *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
-  } else {
-    reinterpret_cast<double2*>(p)[0] = make_double2(a0, a1);
-    reinterpret_cast<double2*>(p)[1] = make_double2(a2, a3);
-  }
-}
-
 // Cells 8t .. 8t+7 of the finest-level row starting at rb (parity par = (j + k) & 1),
 // in natural order; h = nx / 2.  Cell 8t + 2r + e has colour (e + par) & 1 and sits at
 // position 4t + r of that colour's half row.
@@ -1170,9 +1171,9 @@ __global__ void __launch_bounds__(128) k_phi_update(double* phi, const T* u, int
   phi[row + i] += (double)u[row + p];
 }
 
+// E = -grad phi at cell centres into the packed (Ex, Ey, Ez, 0) array.
 template <typename T>
-__global__ void k_efield(const double* phi, int nx, int ny, int nz, double V, double inv2h, T* Ex, T* Ey,
-                         T* Ez) {
+__global__ void k_efield(const double* phi, int nx, int ny, int nz, double V, double inv2h, T* E4) {
   const uint32_t n = (uint32_t)nx * ny * nz;
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
@@ -1181,16 +1182,16 @@ __global__ void k_efield(const double* phi, int nx, int ny, int nz, double V, do
     const double xm = i > 0 ? phi[c - 1] : pc, xp = i < nx - 1 ? phi[c + 1] : pc;
     const double ym = j > 0 ? phi[c - sy] : pc, yp = j < ny - 1 ? phi[c + sy] : pc;
     const double zm = k > 0 ? phi[c - sz] : -pc, zp = k < nz - 1 ? phi[c + sz] : 2.0 * V - pc;
-    Ex[c] = (T)(-(xp - xm) * inv2h);
-    Ey[c] = (T)(-(yp - ym) * inv2h);
-    Ez[c] = (T)(-(zp - zm) * inv2h);
+    st4<T>(E4 + 4 * (size_t)c, (T)(-(xp - xm) * inv2h), (T)(-(yp - ym) * inv2h), (T)(-(zp - zm) * inv2h),
+           (T)0);
   }
 }
 
+// One component of the packed field, as double.
 template <typename T>
-__global__ void k_to_double(const T* a, double* out, uint32_t n) {
+__global__ void k_component(const T* E4, int a, double* out, uint32_t n) {
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    out[c] = (double)a[c];
+    out[c] = (double)E4[4 * (size_t)c + a];
 }
 
 inline int blocks(uint64_t n, int max_blocks = 16384) {
@@ -1209,7 +1210,7 @@ struct FieldState {
   Level lev[kMaxLevels];
   double* phi = nullptr;
   double* b = nullptr;
-  void* E[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  void* E[2] = {nullptr, nullptr};  // packed (Ex, Ey, Ez, 0) per cell; E[cur] holds the latest
   int cur = 0;        // E[cur] holds the latest field
   void* sig = nullptr;
   void* ne = nullptr;
@@ -1251,7 +1252,7 @@ size_t field_bytes(const itokmc_grid_desc* d) {
   const int nl = build_levels(d, dims);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
-  size_t total = al(n * 8) * 3 + al(n * T) * 6 + al(n * 8) * 2 + al(8 * (8 + npart));
+  size_t total = al(n * 8) * 3 + al(n * 4 * T) * 2 + al(n * 8) * 2 + al(8 * (8 + npart));
   for (int l = 0; l < nl; ++l) total += 3 * al((size_t)dims[l][0] * dims[l][1] * dims[l][2] * T);
   return total;
 }
@@ -1275,7 +1276,7 @@ int field_init(itokmc_ctx* ctx, char* base) {
   F->b = (double*)p; p += al(n * 8);
   F->phi_prev = (double*)p; p += al(n * 8);
   for (int s = 0; s < 2; ++s)
-    for (int a = 0; a < 3; ++a) { F->E[s][a] = p; p += al(n * T); }
+    { F->E[s] = p; p += al(n * 4 * T); }
   F->sig = p; p += al(n * 8);  // deposit accumulators (8 bytes in either precision)
   F->ne = p; p += al(n * 8);
   const size_t npart = (size_t)kRedBlocks > (n + 255) / 256 ? (size_t)kRedBlocks : (n + 255) / 256;
@@ -1293,7 +1294,7 @@ int field_init(itokmc_ctx* ctx, char* base) {
   hipError_t e = hipHostMalloc((void**)&F->host_norms, 64, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(F->phi, 0, n * 8, ctx->s);
   for (int s = 0; s < 2 && e == hipSuccess; ++s)
-    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = hipMemsetAsync(F->E[s][a], 0, n * T, ctx->s);
+    e = hipMemsetAsync(F->E[s], 0, n * 4 * T, ctx->s);
   if (e != hipSuccess) {
     delete F;
     return check_hip(ctx, e, "field init");
@@ -1571,15 +1572,15 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->sig, n);
   k_zero<S><<<blocks(n), 256, 0, s>>>((S*)F->ne, n);
   phase_end(ctx, PH_FIELD_PREP);
-  void* const* Eo = F->E[F->cur];
+  const void* Eo = F->E[F->cur];
   phase_begin(ctx, PH_DEPOSIT);  // the deposit kernel alone
   {
     constexpr int L2 = DepTbl<T>::log2n;
     const size_t lds = (size_t)(1 << L2) * (4 + 2 * sizeof(S));
     int g = (int)((ctx->cap + kDepChunk - 1) / kDepChunk);
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
-    k_field_deposit_lds<T, L2><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo[0], Eo[1],
-                                                   Eo[2], coef(ctx), mode, (S*)F->sig, (S*)F->ne,
+    k_field_deposit_lds<T, L2><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo,
+                                                   coef(ctx), mode, (S*)F->sig, (S*)F->ne,
                                                    (uint32_t)kDepChunk);
   }
   phase_end(ctx, PH_DEPOSIT);
@@ -1601,8 +1602,7 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   const int rc = solve<T>(ctx, F);
   const int nxt = 1 - F->cur;
   k_efield<T><<<blocks(n), 256, 0, s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz, ctx->d.V_anode,
-                                        1.0 / (2.0 * ctx->d.dx), (T*)F->E[nxt][0], (T*)F->E[nxt][1],
-                                        (T*)F->E[nxt][2]);
+                                        1.0 / (2.0 * ctx->d.dx), (T*)F->E[nxt]);
   phase_end(ctx, PH_SOLVE);
   return rc ? rc : check_hip(ctx, hipGetLastError(), "field");
 }
@@ -1622,8 +1622,7 @@ static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
   const int nxt = 1 - F->cur;
   phase_begin(ctx, PH_FIELD_PUSH);
   k_push_field<T><<<blocks(ctx->cap, 4096), 256, 0, ctx->s>>>(
-      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, F->E[F->cur][0], F->E[F->cur][1],
-      F->E[F->cur][2], F->E[nxt][0], F->E[nxt][1], F->E[nxt][2], coef(ctx));
+      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, F->E[F->cur], F->E[nxt], coef(ctx));
   phase_end(ctx, PH_FIELD_PUSH);
   F->cur = nxt;  // E^{k+1} becomes the field of the next step
   return check_hip(ctx, hipGetLastError(), "field push");
@@ -1637,7 +1636,7 @@ FieldRates field_rates(itokmc_ctx* ctx) {
   FieldState* F = fs(ctx);
   FieldRates r{};
   if (!F) return r;
-  for (int a = 0; a < 3; ++a) r.E[a] = F->E[F->cur][a];
+  r.E4 = F->E[F->cur];
   r.is_double = ctx->d.precision == ITOKMC_FP64 ? 1 : 0;
   r.mu_a = ctx->c.mu_a; r.mu_E0 = ctx->c.mu_E0; r.mu_b = ctx->c.mu_b; r.E_floor = ctx->c.E_floor;
   r.alpha_A = ctx->c.alpha_A; r.alpha_B = ctx->c.alpha_B; r.eta = ctx->c.eta;
@@ -1662,13 +1661,11 @@ int field_set_phi(itokmc_ctx* ctx, const double* host) {
   if (ctx->d.precision == ITOKMC_FP64)
     k_efield<double><<<blocks(n), 256, 0, ctx->s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz,
                                                     ctx->d.V_anode, 1.0 / (2.0 * ctx->d.dx),
-                                                    (double*)F->E[F->cur][0], (double*)F->E[F->cur][1],
-                                                    (double*)F->E[F->cur][2]);
+                                                    (double*)F->E[F->cur]);
   else
     k_efield<float><<<blocks(n), 256, 0, ctx->s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz,
                                                    ctx->d.V_anode, 1.0 / (2.0 * ctx->d.dx),
-                                                   (float*)F->E[F->cur][0], (float*)F->E[F->cur][1],
-                                                   (float*)F->E[F->cur][2]);
+                                                   (float*)F->E[F->cur]);
   ctx->field_valid = true;
   return check_hip(ctx, hipGetLastError(), "set_field");
 }
@@ -1681,9 +1678,9 @@ int field_deposit(itokmc_ctx* ctx, int what, void* dev_out) {
                      "deposit phi");
   const int a = what - ITOKMC_Q_EX;
   if (ctx->d.precision == ITOKMC_FP64)
-    k_to_double<double><<<blocks(n), 256, 0, ctx->s>>>((const double*)F->E[F->cur][a], (double*)dev_out, n);
+    k_component<double><<<blocks(n), 256, 0, ctx->s>>>((const double*)F->E[F->cur], a, (double*)dev_out, n);
   else
-    k_to_double<float><<<blocks(n), 256, 0, ctx->s>>>((const float*)F->E[F->cur][a], (double*)dev_out, n);
+    k_component<float><<<blocks(n), 256, 0, ctx->s>>>((const float*)F->E[F->cur], a, (double*)dev_out, n);
   return check_hip(ctx, hipGetLastError(), "deposit E");
 }
 

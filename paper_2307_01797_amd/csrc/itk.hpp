@@ -64,10 +64,11 @@ struct StepConst {
   double k[3];       // uniform mode rates (1/s)
 };
 
-// Field view for per-cell KMC rates (Poisson mode): E at cell centres and the
-// coefficient forms; E[0] == nullptr means the prescribed uniform field.
+// Field view for per-cell KMC rates (Poisson mode): E at cell centres, packed
+// (Ex, Ey, Ez, 0) per cell, and the coefficient forms; E4 == nullptr means the
+// prescribed uniform field.
 struct FieldRates {
-  const void* E[3];
+  const void* E4;
   int is_double;
   double mu_a, mu_E0, mu_b, E_floor, alpha_A, alpha_B, eta, kgamma_ratio;
 };

@@ -24,8 +24,8 @@ namespace {
 __device__ void rates_at(const FieldRates& fr, uint32_t c, double k[3]) {
   double e[3];
   for (int a = 0; a < 3; ++a)
-    e[a] = fr.is_double ? reinterpret_cast<const double*>(fr.E[a])[c]
-                        : (double)reinterpret_cast<const float*>(fr.E[a])[c];
+    e[a] = fr.is_double ? reinterpret_cast<const double*>(fr.E4)[4 * (size_t)c + a]
+                        : (double)reinterpret_cast<const float*>(fr.E4)[4 * (size_t)c + a];
   const double Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
   const double Ec = Em > fr.E_floor ? Em : fr.E_floor;
   const double mu = fr.mu_a * pow(Ec / fr.mu_E0, fr.mu_b);
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) k_kmc_step(
       const uint32_t Xe = (uint32_t)cellacc[c];
       State X{(int64_t)Xe, (int64_t)nplus[c], (int64_t)nminus[c], 0};
       double k[3];
-      if (!fr.E[0]) { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
+      if (!fr.E4) { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
       else if (kFast) rates_at(fr, c, k);
       else { k[0] = rates[3 * (size_t)j]; k[1] = rates[3 * (size_t)j + 1]; k[2] = rates[3 * (size_t)j + 2]; }
       CellStream st;
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) k_kmc_step(
       if (kFast) {
         if (!advance_fast(P, X, k, K.dt, st, f)) {
           fl[r] = 2; ++nd;
-          if (fr.E[0]) {
+          if (fr.E4) {
             rates[3 * (size_t)j] = k[0]; rates[3 * (size_t)j + 1] = k[1]; rates[3 * (size_t)j + 2] = k[2];
           }
           continue;
