@@ -25,7 +25,7 @@
 namespace itk {
 
 constexpr int kMaxMergePpc = 64;
-constexpr int kMergeTiny = 96;    // pieces staged by the common path (smallest LDS)
+constexpr int kMergeTiny = 128;   // pieces staged by the common path (smallest LDS)
 constexpr int kMergeSmall = 256;  // pieces staged by the mid-size path
 template <typename T> struct MergeBig;
 template <> struct MergeBig<float> { static constexpr int value = 1536; };
