@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 #                      read u and eps of the other colour's cells, f and eps of the
 #                      colour's cells, write u of the colour's cells: 2.5 S
 KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k_field_deposit_lds",
-           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_seg"}
+           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_seg<fine>"}
 
 
 def bytes_per_unit(phase, S):

@@ -507,7 +507,8 @@ __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t*
 }
 
 template <typename T>
-__global__ void k_eps_restrict(const T* ef, int fnx, int fny, int fsplit, T* ec, int cnx, int cny, int cnz) {
+__global__ void k_eps_restrict(const T* ef, int fnx, int fny, int fsplit, T* ec, int cnx, int cny, int cnz,
+                               int csplit) {
   const uint32_t n = (uint32_t)cnx * cny * cnz;
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     const int i = c % cnx, j = (c / cnx) % cny, k = c / (cnx * cny);
@@ -516,7 +517,7 @@ __global__ void k_eps_restrict(const T* ef, int fnx, int fny, int fsplit, T* ec,
       const int fi = 2 * i + (d & 1), fj = 2 * j + ((d >> 1) & 1), fk = 2 * k + (d >> 2);
       s += (double)ef[fsplit ? pos_of<true>(fi, fj, fk, fnx, fny) : pos_of<false>(fi, fj, fk, fnx, fny)];
     }
-    ec[c] = (T)(s * 0.125);
+    ec[csplit ? pos_of<true>(i, j, k, cnx, cny) : (size_t)c] = (T)(s * 0.125);
   }
 }
 
@@ -999,11 +1000,11 @@ __global__ void __launch_bounds__(256) k_residual_seg(const double* phi, const d
   if (threadIdx.x == 0) partial[blk] = acc;
 }
 
-// One colour of a red-black sweep on the split finest level, four cells of the colour
-// per thread: cells i = 2m + odd for half-row positions m = 4t .. 4t+3, odd =
+// One colour of a red-black sweep on a split segment level, four cells of the colour
+// per thread (kFine marks the finest level's instantiation for kernel traces): cells i = 2m + odd for half-row positions m = 4t .. 4t+3, odd =
 // (j + k + colour) & 1.  Their x neighbours have the other colour, at positions
 // m - 1 + odd and m + odd.
-template <typename T>
+template <typename T, bool kFine>
 __global__ void __launch_bounds__(256) k_smooth_seg(T* u, const T* f, const T* eps, int nx, int ny, int nz,
                                                    int color) {
   const int ns = nx >> 3, h = nx >> 1;
@@ -1038,11 +1039,13 @@ __global__ void __launch_bounds__(256) k_smooth_seg(T* u, const T* f, const T* e
   st4<T>(u + own, un_[0], un_[1], un_[2], un_[3]);
 }
 
-// Restriction from the finest level over segments: a thread takes four coarse cells
-// (coarse x 4t .. 4t+3) and their children, the fine segment t of four fine rows,
-// visited in the children's order (j offset, then k offset; x offset within a row), so
-// each coarse sum adds its eight child residuals in the order of k_restrict3.
-template <typename T, bool kSplit>
+// Restriction from a segment level: a thread takes four coarse cells (coarse x
+// 4t .. 4t+3) and their children, the fine segment t of four fine rows, visited in the
+// children's order (j offset, then k offset; x offset within a row), so each coarse
+// sum adds its eight child residuals in the order of k_restrict3.  The fine level in
+// split order if kSplit, the coarse one if kCSplit (coarse cells 4t, 4t+1 sit at
+// half-row position 2t, 4t+2 and 4t+3 at 2t+1, one of each pair in each half).
+template <typename T, bool kSplit, bool kCSplit>
 __global__ void __launch_bounds__(256) k_restrict_seg(const T* u, const T* f, const T* eps, int nx, int ny,
                                                      int nz, T* fc, T* uc) {
   const int ns = nx >> 3, h = nx >> 1, cnx = nx >> 1, cny = ny >> 1, cnz = nz >> 1;
@@ -1076,16 +1079,27 @@ __global__ void __launch_bounds__(256) k_restrict_seg(const T* u, const T* f, co
       s8[r >> 1] += F[r] - (dg * U.c[r] - sm);
     }
   }
-  const size_t cc = (size_t)cs.row * cnx + 4 * cs.t;
-  st4<T>(fc + cc, s8[0] * (T)0.5, s8[1] * (T)0.5, s8[2] * (T)0.5, s8[3] * (T)0.5);
-  st4<T>(uc + cc, (T)0, (T)0, (T)0, (T)0);
+  const size_t cb = (size_t)cs.row * cnx;
+  if constexpr (kCSplit) {
+    const int ch = cnx >> 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ci = 4 * cs.t + r;
+      const size_t q = cb + (((ci + cs.par) & 1) ? (size_t)ch : 0) + (size_t)(ci >> 1);
+      fc[q] = s8[r] * (T)0.5;
+      uc[q] = (T)0;
+    }
+  } else {
+    st4<T>(fc + cb + 4 * cs.t, s8[0] * (T)0.5, s8[1] * (T)0.5, s8[2] * (T)0.5, s8[3] * (T)0.5);
+    st4<T>(uc + cb + 4 * cs.t, (T)0, (T)0, (T)0, (T)0);
+  }
 }
 
 // Trilinear prolongation onto the finest level over segments: the coarse values of
 // the eight cells come from the coarse rows (J or its neighbour toward the cell) x
 // (K or its neighbour), x from 4t-1 to 4t+4 with the clamps and Dirichlet signs of
 // k_prolong3, in the same order and arithmetic.
-template <typename T, bool kSplit>
+template <typename T, bool kSplit, bool kCSplit>
 __global__ void __launch_bounds__(256) k_prolong_seg(T* u, int nx, int ny, int nz, const T* uc, int cnx,
                                                     int cny, int cnz) {
   const int ns = nx >> 3, h = nx >> 1;
@@ -1102,11 +1116,22 @@ __global__ void __launch_bounds__(256) k_prolong_seg(T* u, int nx, int ny, int n
   for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
     for (int dk = 0; dk < 2; ++dk) {
-      const size_t crow = (size_t)cnx * ((size_t)(dj ? jbc : J) + (size_t)cny * (size_t)(dk ? kbc : K));
-      const V4<T> m = ld4(uc + crow + 4 * s.t);
-      W[dj][dk][0] = uc[crow + (s.t > 0 ? 4 * s.t - 1 : 0)];
-      W[dj][dk][1] = m.a[0]; W[dj][dk][2] = m.a[1]; W[dj][dk][3] = m.a[2]; W[dj][dk][4] = m.a[3];
-      W[dj][dk][5] = uc[crow + (4 * s.t + 4 < cnx ? 4 * s.t + 4 : cnx - 1)];
+      const int rj = dj ? jbc : J, rk = dk ? kbc : K;
+      const size_t crow = (size_t)cnx * ((size_t)rj + (size_t)cny * (size_t)rk);
+      const int xl = s.t > 0 ? 4 * s.t - 1 : 0, xr = 4 * s.t + 4 < cnx ? 4 * s.t + 4 : cnx - 1;
+      if constexpr (kCSplit) {
+        const int ch = cnx >> 1, cp = (rj + rk) & 1;
+        auto cv = [&](int x) { return uc[crow + (((x + cp) & 1) ? (size_t)ch : 0) + (size_t)(x >> 1)]; };
+        W[dj][dk][0] = cv(xl);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W[dj][dk][1 + q] = cv(4 * s.t + q);
+        W[dj][dk][5] = cv(xr);
+      } else {
+        const V4<T> m = ld4(uc + crow + 4 * s.t);
+        W[dj][dk][0] = uc[crow + xl];
+        W[dj][dk][1] = m.a[0]; W[dj][dk][2] = m.a[1]; W[dj][dk][3] = m.a[2]; W[dj][dk][4] = m.a[3];
+        W[dj][dk][5] = uc[crow + xr];
+      }
     }
   const size_t rb = (size_t)s.row * nx;
   T V[8];
@@ -1220,6 +1245,11 @@ struct FieldState {
   bool have_prev = false;
   bool split = false;  // finest level in split red-black order (nx even, more than one level)
   bool seg = false;    // finest-level kernels over 8-cell row segments (nx % 8 == 0, more than one level)
+  // per level: split red-black order, and 8-cell row-segment kernels.  The finest level
+  // as above; a coarser level (not the coarsest) with nx % 8 == 0 and more than
+  // kSmallLevel cells takes both when the finest level is split.
+  bool lsplit[kMaxLevels] = {};
+  bool lseg[kMaxLevels] = {};
   bool graph_failed = false;
   hipGraphExec_t graph_exec = nullptr;
   // optional timing of the finest-level smoother launches: event pairs recorded around
@@ -1358,13 +1388,16 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
   const T* f = (const T*)L.f;
   const T* ep = (const T*)L.eps;
   if (l > 0) {
-    k_smooth_rb<T, false><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+    if (F->lsplit[l])
+      k_smooth_seg<T, false><<<seg_blocks(L.nx, L.ny, L.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+    else
+      k_smooth_rb<T, false><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
     return;
   }
   const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
   if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
   if (F->split && F->seg)
-    k_smooth_seg<T><<<seg_blocks(L.nx, L.ny, L.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+    k_smooth_seg<T, true><<<seg_blocks(L.nx, L.ny, L.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
   else if (F->split)
     k_smooth_split<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
   else
@@ -1410,23 +1443,28 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   const int sb = seg_blocks(L.nx, L.ny, L.nz);
   T* fcp = (T*)C.f;
   T* ucp = (T*)C.u;
-  if (l == 0 && F->seg && F->split)
-    k_restrict_seg<T, true><<<seg_blocks(L.nx, C.ny, C.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
-  else if (l == 0 && F->seg)
-    k_restrict_seg<T, false><<<seg_blocks(L.nx, C.ny, C.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
-  else if (l == 0 && F->split)
-    k_restrict3<T, true><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx, C.ny);
-  else
-    k_restrict3<T, false><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, (T*)C.f, (T*)C.u, C.nx, C.ny);
+  const int rg = seg_blocks(L.nx, C.ny, C.nz);
+  const bool fs = F->lsplit[l], csp = F->lsplit[l + 1];
+  if (F->lseg[l]) {
+    if (fs && csp) k_restrict_seg<T, true, true><<<rg, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
+    else if (fs) k_restrict_seg<T, true, false><<<rg, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
+    else k_restrict_seg<T, false, false><<<rg, 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp);
+  } else if (fs) {
+    k_restrict3<T, true><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp, C.nx, C.ny);
+  } else {
+    k_restrict3<T, false><<<gr, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, fcp, ucp, C.nx, C.ny);
+  }
   vcycle<T>(ctx, F, l + 1, s);
-  if (l == 0 && F->seg && F->split)
-    k_prolong_seg<T, true><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
-  else if (l == 0 && F->seg)
-    k_prolong_seg<T, false><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
-  else if (l == 0 && F->split)
-    k_prolong3<T, true><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
-  else
-    k_prolong3<T, false><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, (const T*)C.u, C.nx, C.ny, C.nz);
+  const T* ucc = (const T*)C.u;
+  if (F->lseg[l]) {
+    if (fs && csp) k_prolong_seg<T, true, true><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, ucc, C.nx, C.ny, C.nz);
+    else if (fs) k_prolong_seg<T, true, false><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, ucc, C.nx, C.ny, C.nz);
+    else k_prolong_seg<T, false, false><<<sb, 256, 0, s>>>(u, L.nx, L.ny, L.nz, ucc, C.nx, C.ny, C.nz);
+  } else if (fs) {
+    k_prolong3<T, true><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, ucc, C.nx, C.ny, C.nz);
+  } else {
+    k_prolong3<T, false><<<gp, 128, 0, s>>>(u, L.nx, L.ny, L.nz, ucc, C.nx, C.ny, C.nz);
+  }
   smooth_sweeps<T>(F, l, s, ctx->tune.mg_post);
 }
 
@@ -1524,9 +1562,8 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
   for (int l = 1; l < F->nlev; ++l) {
     Level& Fl = F->lev[l - 1];
     Level& Cl = F->lev[l];
-    k_eps_restrict<T><<<blocks(Cl.n), 256, 0, s>>>((const T*)Fl.eps, Fl.nx, Fl.ny,
-                                                   (l == 1 && F->split) ? 1 : 0, (T*)Cl.eps, Cl.nx,
-                                                   Cl.ny, Cl.nz);
+    k_eps_restrict<T><<<blocks(Cl.n), 256, 0, s>>>((const T*)Fl.eps, Fl.nx, Fl.ny, F->lsplit[l - 1] ? 1 : 0,
+                                                   (T*)Cl.eps, Cl.nx, Cl.ny, Cl.nz, F->lsplit[l] ? 1 : 0);
   }
   const int maxc = ctx->d.gmg_max_cycles > 0 ? ctx->d.gmg_max_cycles : 50;
   ctx->total_solves += 1;
@@ -1566,6 +1603,15 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   if (split != F->split) {
     field_reset_graph(ctx);
     F->split = split;
+  }
+  for (int l = 0; l < F->nlev; ++l) {
+    const Level& L = F->lev[l];
+    if (l == 0) {
+      F->lsplit[0] = F->split;
+      F->lseg[0] = F->seg;
+    } else {
+      F->lseg[l] = F->lsplit[l] = F->split && l < F->nlev - 1 && L.nx % 8 == 0 && L.n > kSmallLevel;
+    }
   }
   phase_begin(ctx, PH_FIELD_PREP);
   using S = typename DepAcc<T>::S;
