@@ -1004,7 +1004,7 @@ __global__ void __launch_bounds__(256) k_residual_seg(const double* phi, const d
 // per thread (kFine marks the finest level's instantiation for kernel traces): cells i = 2m + odd for half-row positions m = 4t .. 4t+3, odd =
 // (j + k + colour) & 1.  Their x neighbours have the other colour, at positions
 // m - 1 + odd and m + odd.
-template <typename T, bool kFine>
+template <typename T, bool kFine, bool kZero = false>
 __global__ void __launch_bounds__(256) k_smooth_seg(T* u, const T* f, const T* eps, int nx, int ny, int nz,
                                                    int color) {
   const int ns = nx >> 3, h = nx >> 1;
@@ -1019,10 +1019,16 @@ __global__ void __launch_bounds__(256) k_smooth_seg(T* u, const T* f, const T* e
   const size_t ozm = s.k > 0 ? oth - sz : oth, ozp = s.k < nz - 1 ? oth + sz : oth;
   const size_t pl = s.t > 0 ? oth - 1 : oth, pr = 4 * s.t + 4 < h ? oth + 4 : oth + 3;
   const V4<T> Fo = ld4(f + own), Eo = ld4(eps + own);
-  const V4<T> Uc = ld4(u + oth), Ec = ld4(eps + oth);
-  const V4<T> Uym = ld4(u + oym), Eym = ld4(eps + oym), Uyp = ld4(u + oyp), Eyp = ld4(eps + oyp);
-  const V4<T> Uzm = ld4(u + ozm), Ezm = ld4(eps + ozm), Uzp = ld4(u + ozp), Ezp = ld4(eps + ozp);
-  const T UL = u[pl], EL = eps[pl], UR = u[pr], ER = eps[pr];
+  const V4<T> Ec = ld4(eps + oth);
+  const V4<T> Eym = ld4(eps + oym), Eyp = ld4(eps + oyp), Ezm = ld4(eps + ozm), Ezp = ld4(eps + ozp);
+  const T EL = eps[pl], ER = eps[pr];
+  // kZero: the first colour-0 sweep of a cycle, from u = 0 (the neighbours' values are
+  // zeros, not read)
+  const V4<T> zero = {{(T)0, (T)0, (T)0, (T)0}};
+  const V4<T> Uc = kZero ? zero : ld4(u + oth);
+  const V4<T> Uym = kZero ? zero : ld4(u + oym), Uyp = kZero ? zero : ld4(u + oyp);
+  const V4<T> Uzm = kZero ? zero : ld4(u + ozm), Uzp = kZero ? zero : ld4(u + ozp);
+  const T UL = kZero ? (T)0 : u[pl], UR = kZero ? (T)0 : u[pr];
   T un_[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -1381,7 +1387,7 @@ static dim3 row_grid(int half_nx, int ny, int nz) {
 // One colour sweep at level l (the finest level in split order when F->split); the
 // finest level's launches are bracketed by event pairs when timing is on.
 template <typename T>
-static void smooth(FieldState* F, int l, hipStream_t s, int color) {
+static void smooth(FieldState* F, int l, hipStream_t s, int color, bool from_zero = false) {
   Level& L = F->lev[l];
   const dim3 gs = row_grid((L.nx + 1) / 2, L.ny, L.nz);
   T* u = (T*)L.u;
@@ -1396,7 +1402,9 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
   }
   const bool timed = F->timing && F->sm_n < FieldState::kMaxTimed;  // eager cycles only
   if (timed) (void)hipEventRecord(F->sm_ev[2 * F->sm_n], s);
-  if (F->split && F->seg)
+  if (F->split && F->seg && from_zero)
+    k_smooth_seg<T, true, true><<<seg_blocks(L.nx, L.ny, L.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
+  else if (F->split && F->seg)
     k_smooth_seg<T, true><<<seg_blocks(L.nx, L.ny, L.nz), 256, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
   else if (F->split)
     k_smooth_split<T><<<gs, 128, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, color);
@@ -1406,8 +1414,10 @@ static void smooth(FieldState* F, int l, hipStream_t s, int color) {
   if (timed) ++F->sm_n;
 }
 
+// from_zero: the level's correction is zero on entry and not stored (first sweeps of a
+// refinement cycle on the finest level with the row-segment smoother).
 template <typename T>
-static void smooth_sweeps(FieldState* F, int l, hipStream_t s, int count) {
+static void smooth_sweeps(FieldState* F, int l, hipStream_t s, int count, bool from_zero = false) {
   Level& L = F->lev[l];
   if (l > 0 && L.n <= kSmallLevel) {
     if (count > 0)
@@ -1415,9 +1425,13 @@ static void smooth_sweeps(FieldState* F, int l, hipStream_t s, int count) {
     return;
   }
   for (int it = 0; it < count; ++it) {
-    smooth<T>(F, l, s, 0);
+    smooth<T>(F, l, s, 0, from_zero && it == 0);
     smooth<T>(F, l, s, 1);
   }
+}
+
+static bool zero_free_start(const itokmc_ctx* ctx, const FieldState* F) {
+  return F->split && F->seg && ctx->tune.mg_pre >= 1;
 }
 
 static int bottom_count(const itokmc_ctx* ctx, const Level& L) {
@@ -1438,7 +1452,7 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
     return;
   }
   Level& C = F->lev[l + 1];
-  smooth_sweeps<T>(F, l, s, ctx->tune.mg_pre);
+  smooth_sweeps<T>(F, l, s, ctx->tune.mg_pre, l == 0 && zero_free_start(ctx, F));
   const dim3 gr = row_grid(C.nx, C.ny, C.nz), gp = row_grid(L.nx, L.ny, L.nz);
   const int sb = seg_blocks(L.nx, L.ny, L.nz);
   T* fcp = (T*)C.f;
@@ -1515,7 +1529,9 @@ template <typename T>
 static void refine_cycle(itokmc_ctx* ctx, FieldState* F, hipStream_t s) {
   Level& L0 = F->lev[0];
   F->sm_n = 0;
-  k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
+  // the correction starts at zero; the first colour-0 sweep can assume it instead (the
+  // colour-1 sweep that follows writes the rest of the level before anything reads it)
+  if (!zero_free_start(ctx, F)) k_zero<T><<<blocks(L0.n), 256, 0, s>>>((T*)L0.u, L0.n);
   vcycle<T>(ctx, F, 0, s);
   const dim3 gp = row_grid(L0.nx, L0.ny, L0.nz);
   const int sb = seg_blocks(L0.nx, L0.ny, L0.nz);
