@@ -819,6 +819,11 @@ __device__ __forceinline__ void rb_sweeps(T* u, const T* f, const T* eps, int nx
 
 // Levels of at most kSmallLevel cells: all pre- or post-sweeps in one launch.
 constexpr uint32_t kSmallLevel = 4096;
+// LDS that one small-level launch may stage: correction, right-hand side and
+// coefficient of the level (3 n values).
+constexpr size_t kSmallLds = 65536;
+template <typename T>
+inline bool small_fits_lds(uint32_t n) { return 3 * (size_t)n * sizeof(T) <= kSmallLds; }
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_sweeps_small(T* u, const T* f, const T* eps, int nx, int ny,
@@ -826,7 +831,156 @@ __global__ void __launch_bounds__(1024) k_sweeps_small(T* u, const T* f, const T
   rb_sweeps<T>(u, f, eps, nx, ny, nz, sweeps);
 }
 
-// Coarsest level: red-black sweeps from zero inside one workgroup.
+// Launch shapes of the LDS form, threads x cells per thread: levels of up to 64 cells
+// run in one wavefront (its barriers cost little), larger ones in 1024 threads x 4
+// cells (single precision) or 512 x 8 (double precision, which keeps the registers of
+// a thread's cells within its waves' budget).
+template <typename T> constexpr int kSmallThreads = sizeof(T) == 8 ? 512 : 1024;
+template <typename T> constexpr int kSmallCells = (int)kSmallLevel / kSmallThreads<T>;
+
+// Red-black sweeps of a small level held in LDS, single precision: each of the NT
+// threads owns the cells t + r NT (r < NC) and keeps their face coefficients, diagonal
+// and right-hand side in registers, so that a sweep reads only the six neighbour
+// values.  The coefficients and the update are those of op_row and smooth_cell, in the
+// same order (same values).
+template <typename T, int NT, int NC>
+__device__ __forceinline__ void small_sweeps_cached(T* su, const T* sf, const T* se, int nx, int ny, int nz,
+                                                    int sweeps) {
+  const int n = nx * ny * nz, sy = nx, sz = nx * ny;
+  T bq[NC][6], dg[NC], fr[NC];
+  int cr[NC];
+  uint32_t meta[NC];  // bits 0-5: face q inside; bit 6: colour; bit 7: owned cell
+#pragma unroll
+  for (int r = 0; r < NC; ++r) {
+    const int c = (int)threadIdx.x + r * NT;
+    cr[r] = c < n ? c : 0;
+    meta[r] = 0;
+    dg[r] = (T)1;
+    fr[r] = (T)0;
+    if (c < n) {
+      const int i = c % nx, j = (c / nx) % ny, k = c / sz;
+      bool in[6];
+      faces_in(i, j, k, nx, ny, nz, in);
+      const int off[6] = {in[0] ? -1 : 0, in[1] ? 1 : 0, in[2] ? -sy : 0,
+                          in[3] ? sy : 0, in[4] ? -sz : 0, in[5] ? sz : 0};
+      const T ec = se[c];
+      T d = 0;
+      uint32_t m = 0x80u | ((uint32_t)((i + j + k) & 1) << 6);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const T b = hmean_s(ec, se[c + off[q]]);
+        bq[r][q] = b;
+        d = in[q] ? d + b : (q >= 4 ? d + (T)2 * ec : d);
+        m |= in[q] ? (1u << q) : 0u;
+      }
+      dg[r] = d;
+      fr[r] = sf[c];
+      meta[r] = m;
+    }
+  }
+  for (int it = 0; it < sweeps; ++it)
+    for (int color = 0; color < 2; ++color) {
+      const uint32_t want = 0x80u | ((uint32_t)color << 6);
+#pragma unroll
+      for (int r = 0; r < NC; ++r) {
+        if ((meta[r] & 0xC0u) != want) continue;
+        const int c = cr[r];
+        const uint32_t m = meta[r];
+        const int off[6] = {(m & 1u) ? -1 : 0, (m & 2u) ? 1 : 0, (m & 4u) ? -sy : 0,
+                            (m & 8u) ? sy : 0, (m & 16u) ? -sz : 0, (m & 32u) ? sz : 0};
+        T un[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) un[q] = su[c + off[q]];
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc = ((m >> q) & 1u) ? acc + bq[r][q] * un[q] : acc;
+        su[c] = (fr[r] + acc) / dg[r];
+      }
+      __syncthreads();
+    }
+}
+
+// A small level staged in LDS by NT threads, NC cells each (the host checks
+// small_fits_lds and n <= NT NC): the level's coefficient and right-hand side and its
+// correction (plus the prolonged coarse correction if uc_in, zero if zero_u) are
+// loaded once, all loads of a thread in flight together; every sweep runs on the LDS
+// copies with the cell updates of the one-colour launches (same values), and the
+// correction is stored back; with fc_out the level's residual is then restricted to
+// the next coarser level (its correction zeroed), as the restriction launch does.
+template <typename T, int NT, int NC>
+__global__ void __launch_bounds__(NT) k_small_lds(T* u, const T* f, const T* eps, int nx, int ny, int nz,
+                                                 int sweeps, bool zero_u, const T* uc_in, T* fc_out,
+                                                 T* uc_out, int cnx, int cny, int cnz) {
+  extern __shared__ __align__(16) char smem[];
+  const int n = nx * ny * nz;
+  T* su = reinterpret_cast<T*>(smem);
+  T* sf = su + n;
+  T* se = sf + n;
+  T vu[NC], vf[NC], ve[NC];
+#pragma unroll
+  for (int r = 0; r < NC; ++r) {
+    const int c = (int)threadIdx.x + r * NT;
+    vu[r] = vf[r] = ve[r] = (T)0;
+    if (c < n) {
+      vu[r] = zero_u ? (T)0 : u[c];
+      vf[r] = f[c];
+      ve[r] = eps[c];
+    }
+  }
+  if (uc_in) {
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+      const int c = (int)threadIdx.x + r * NT;
+      if (c < n) {
+        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        vu[r] = vu[r] + prolong_value<T>(uc_in, cnx, cny, cnz, i, j, k);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NC; ++r) {
+    const int c = (int)threadIdx.x + r * NT;
+    if (c < n) {
+      su[c] = vu[r];
+      sf[c] = vf[r];
+      se[c] = ve[r];
+    }
+  }
+  __syncthreads();
+  if constexpr (sizeof(T) == 4)
+    small_sweeps_cached<T, NT, NC>(su, sf, se, nx, ny, nz, sweeps);
+  else
+    rb_sweeps<T>(su, sf, se, nx, ny, nz, sweeps);
+#pragma unroll
+  for (int r = 0; r < NC; ++r) {
+    const int c = (int)threadIdx.x + r * NT;
+    if (c < n) u[c] = su[c];
+  }
+  if (fc_out) {
+    const int cn = cnx * cny * cnz;
+    for (int q = threadIdx.x; q < cn; q += NT) {
+      const int ci = q % cnx, cj = (q / cnx) % cny, ck = q / (cnx * cny);
+      restrict_cell<T, false>(su, sf, se, nx, ny, nz, fc_out, uc_out, cnx, cny, ci, cj, ck);
+    }
+  }
+}
+
+// Launch of the LDS form on a level of n cells (n <= kSmallLevel, small_fits_lds).
+template <typename T>
+static void launch_small_lds(hipStream_t s, uint32_t n, T* u, const T* f, const T* eps, int nx, int ny,
+                             int nz, int sweeps, bool zero_u, const T* uc_in, T* fc_out, T* uc_out, int cnx,
+                             int cny, int cnz) {
+  const size_t lds = 3 * (size_t)n * sizeof(T);
+  if (n <= 64)
+    k_small_lds<T, 64, 1><<<1, 64, lds, s>>>(u, f, eps, nx, ny, nz, sweeps, zero_u, uc_in, fc_out, uc_out,
+                                             cnx, cny, cnz);
+  else
+    k_small_lds<T, kSmallThreads<T>, kSmallCells<T>><<<1, kSmallThreads<T>, lds, s>>>(
+        u, f, eps, nx, ny, nz, sweeps, zero_u, uc_in, fc_out, uc_out, cnx, cny, cnz);
+}
+
+// Coarsest level: red-black sweeps from zero inside one workgroup (levels too large
+// for the LDS form).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_bottom(T* u, const T* f, const T* eps, int nx, int ny, int nz,
                                                 int sweeps) {
@@ -1448,10 +1602,25 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   const T* f = (const T*)L.f;
   const T* ep = (const T*)L.eps;
   if (l == F->nlev - 1) {
-    k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, bottom_count(ctx, L));
+    if (small_fits_lds<T>(L.n))
+      launch_small_lds<T>(s, L.n, u, f, ep, L.nx, L.ny, L.nz, bottom_count(ctx, L), true, nullptr, nullptr,
+                          nullptr, 0, 0, 0);
+    else
+      k_bottom<T><<<1, 1024, 0, s>>>(u, f, ep, L.nx, L.ny, L.nz, bottom_count(ctx, L));
     return;
   }
   Level& C = F->lev[l + 1];
+  if (l > 0 && L.n <= kSmallLevel && small_fits_lds<T>(L.n)) {
+    // natural order (small levels are never split): smoothing from the zero
+    // correction that every restriction leaves, and restriction; the coarser cycle;
+    // prolongation and smoothing
+    launch_small_lds<T>(s, L.n, u, f, ep, L.nx, L.ny, L.nz, ctx->tune.mg_pre, true, nullptr, (T*)C.f,
+                        (T*)C.u, C.nx, C.ny, C.nz);
+    vcycle<T>(ctx, F, l + 1, s);
+    launch_small_lds<T>(s, L.n, u, f, ep, L.nx, L.ny, L.nz, ctx->tune.mg_post, false, (const T*)C.u,
+                        nullptr, nullptr, C.nx, C.ny, C.nz);
+    return;
+  }
   smooth_sweeps<T>(F, l, s, ctx->tune.mg_pre, l == 0 && zero_free_start(ctx, F));
   const dim3 gr = row_grid(C.nx, C.ny, C.nz), gp = row_grid(L.nx, L.ny, L.nz);
   const int sb = seg_blocks(L.nx, L.ny, L.nz);
