@@ -75,6 +75,11 @@ __device__ __forceinline__ uint64_t packed_key(float k, uint32_t r) {
 }
 __device__ __forceinline__ uint64_t packed_key(double, uint32_t) { return 0; }
 
+__device__ __forceinline__ uint32_t shfl_up_u(uint32_t v, int d) { return __shfl_up(v, d, 64); }
+__device__ __forceinline__ unsigned long long shfl_up_u(unsigned long long v, int d) {
+  return shfl_up64(v, d);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -216,15 +221,42 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     }
     for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) { tag[ncb][q] = kNone; otag[q] = kNone; }
     __syncthreads();
-    // (i) extents of the splitting leaves
-    for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
-      const uint8_t L = tag[cb][q];
-      if (L == kNone || !((chm >> L) & 1ull)) continue;
-      const uint16_t pq = I[cb][q];
-      for (int a = 0; a < 3; ++a) {
-        const U v = Bits<T>::of(so[a][pq]);
-        atomicMin(&lo[3 * L + a], v);
-        atomicMax(&hi[3 * L + a], v);
+    // (i) extents of the splitting leaves: a segmented min/max over each 64-slot chunk
+    // of the buffer (a leaf's slots are contiguous), then one LDS atomic per leaf
+    // segment and bound (LDS atomics of many lanes on one address serialise)
+    for (uint32_t q0 = 0; q0 < extent; q0 += 64) {
+      const uint32_t q = q0 + (uint32_t)lane;
+      const uint8_t L = q < extent ? tag[cb][q] : kNone;
+      const bool part = L != kNone && ((chm >> L) & 1ull);
+      const uint32_t key = part ? (uint32_t)L : 0xFFFFFFFFu;
+      U mn[3], mx[3];
+      if (part) {
+        const uint16_t pq = I[cb][q];
+        for (int a = 0; a < 3; ++a) mn[a] = mx[a] = Bits<T>::of(so[a][pq]);
+      } else {
+        for (int a = 0; a < 3; ++a) { mn[a] = Bits<T>::lo_init; mx[a] = 0; }
+      }
+      const uint32_t prev = __shfl_up(key, 1, 64);
+      const uint64_t heads = __ballot(lane == 0 || prev != key);
+      const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const int seg_start = 63 - __clzll(heads & upto);
+      for (int d = 1; d < 64; d <<= 1) {
+        if (__ballot(lane - d >= seg_start) == 0ull) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const U y = shfl_up_u(mn[a], d), z = shfl_up_u(mx[a], d);
+          if (lane - d >= seg_start) {
+            mn[a] = y < mn[a] ? y : mn[a];
+            mx[a] = z > mx[a] ? z : mx[a];
+          }
+        }
+      }
+      const uint32_t next = __shfl_down(key, 1, 64);
+      if (part && (lane == 63 || next != key)) {
+        for (int a = 0; a < 3; ++a) {
+          atomicMin(&lo[3 * L + a], mn[a]);
+          atomicMax(&hi[3 * L + a], mx[a]);
+        }
       }
     }
     __syncthreads();
