@@ -191,7 +191,7 @@ template <> struct Mob<float> {
 
 template <typename T> struct NormalsF;
 template <> struct NormalsF<double> {
-  __device__ static void get(uint4 r, double n[3]) {
+  __device__ __forceinline__ static void get(uint4 r, double n[3]) {
     const double two_pi = 6.283185307179586476925286766559;
     const double r0 = sqrt(-2.0 * log(u_oc(r.x)));
     const double t0 = two_pi * u_co(r.y);
@@ -203,7 +203,7 @@ template <> struct NormalsF<double> {
   }
 };
 template <> struct NormalsF<float> {
-  __device__ static void get(uint4 r, float n[3]) {
+  __device__ __forceinline__ static void get(uint4 r, float n[3]) {
     const float m2ln2 = -1.3862943611198906f;
     const float r0 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.x)));
     const float r1 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u_ocf(r.z)));

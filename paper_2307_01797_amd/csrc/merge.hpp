@@ -100,27 +100,27 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   uint64_t* sid = (uint64_t*)p; p += (size_t)S * 8;
   U* lo = (U*)p; p += (size_t)NL * 3 * sizeof(U);
   U* hi = (U*)p; p += (size_t)NL * 3 * sizeof(U);
-  T* so[3];
-  for (int a = 0; a < 3; ++a) { so[a] = (T*)p; p += (size_t)S * sizeof(T); }
+  // Arrays selected by a run-time index (axis, buffer) are addressed from one base, so
+  // that every access stays an LDS instruction.
+  T* const soB = (T*)p; p += (size_t)3 * S * sizeof(T);
+  auto so = [soB](int a) { return soB + (size_t)a * S; };
   uint32_t* sw = (uint32_t*)p; p += (size_t)S * 4;
-  uint32_t* Lst[2]; uint32_t* Lcn[2]; uint32_t* LW[2];
-  for (int k = 0; k < 2; ++k) {
-    Lst[k] = (uint32_t*)p; p += NL * 4;
-    Lcn[k] = (uint32_t*)p; p += NL * 4;
-    LW[k] = (uint32_t*)p; p += NL * 4;
-  }
+  uint32_t* const LB = (uint32_t*)p; p += (size_t)6 * NL * 4;   // per buffer: start, count, weight
+  auto Lst = [LB](int k) { return LB + (size_t)k * 3 * NL; };
+  auto Lcn = [LB](int k) { return LB + (size_t)k * 3 * NL + NL; };
+  auto LW = [LB](int k) { return LB + (size_t)k * 3 * NL + 2 * NL; };
   uint32_t* Rg = (uint32_t*)p; p += NL * 4;     // region of each old leaf in the new buffer
   uint32_t* medp = (uint32_t*)p; p += NL * 4;   // median position inside the ordered leaf
   uint32_t* medWl = (uint32_t*)p; p += NL * 4;  // weight ordered before the median
-  uint16_t* I[2];
-  for (int k = 0; k < 2; ++k) { I[k] = (uint16_t*)p; p += (size_t)S * 2; }
-  uint8_t* tag[2];                               // leaf of each slot of I[k]
-  for (int k = 0; k < 2; ++k) { tag[k] = (uint8_t*)p; p += (size_t)S; }
+  uint16_t* const IB = (uint16_t*)p; p += (size_t)2 * S * 2;
+  auto I = [IB](int k) { return IB + (size_t)k * S; };
+  uint8_t* const tagB = (uint8_t*)p; p += (size_t)2 * S;   // leaf of each slot of I(k)
+  auto tag = [tagB](int k) { return tagB + (size_t)k * S; };
   uint8_t* otag = (uint8_t*)p; p += (size_t)S;   // splitting leaf owning an ordered slot
   uint8_t* axis = (uint8_t*)p; p += NL;
   constexpr bool contig = MergeContig<CAP>::value;
   constexpr bool packed = MergePacked<T, CAP>::value;
-  p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+  p = smem + ((size_t)(p - smem) + 15) / 16 * 16;  // stays an LDS address (LDS instructions)
   uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id (packed: key) of slot q
   T* kkey = (T*)p; p += contig ? (size_t)S * sizeof(T) : 0;        // key of slot q
   uint32_t* idr = (uint32_t*)p; p += packed ? (size_t)S * 4 : 0;   // id rank of store entry
@@ -139,12 +139,12 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     if (alive) {
       if (pos < (uint32_t)CAP) {
         sid[pos] = b.id[q];
-        so[0][pos] = reinterpret_cast<const T*>(b.ox)[q];
-        so[1][pos] = reinterpret_cast<const T*>(b.oy)[q];
-        so[2][pos] = reinterpret_cast<const T*>(b.oz)[q];
+        so(0)[pos] = reinterpret_cast<const T*>(b.ox)[q];
+        so(1)[pos] = reinterpret_cast<const T*>(b.oy)[q];
+        so(2)[pos] = reinterpret_cast<const T*>(b.oz)[q];
         sw[pos] = w;
-        I[0][pos] = (uint16_t)pos;
-        tag[0][pos] = 0;
+        I(0)[pos] = (uint16_t)pos;
+        tag(0)[pos] = 0;
       }
       wmax = w > wmax ? w : wmax;
       Wtot += w;
@@ -160,7 +160,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   const bool trigger = m > (uint32_t)n_ppc || (m < (uint32_t)n_ppc && wmax >= 2);
   if (!trigger || m == 0) return 0;
   if (m > (uint32_t)CAP) return 2;
-  if (lane == 0) { Lst[0][0] = 0; Lcn[0][0] = m; LW[0][0] = (uint32_t)Wtot; }
+  if (lane == 0) { Lst(0)[0] = 0; Lcn(0)[0] = m; LW(0)[0] = (uint32_t)Wtot; }
   __syncthreads();
   if (packed) {  // rank of every piece's id among the cell's pieces (ids are distinct here)
     for (uint32_t q = (uint32_t)lane; q < m; q += 64) {
@@ -177,12 +177,12 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
 
   // ---- breadth-first growth, all leaves of a level at once ----
   int cb = 0, nl = 1;
-  uint32_t extent = m;   // slots in use in I[cb]
+  uint32_t extent = m;   // slots in use in I(cb)
   uint32_t nstore = m;   // next free store entry
   for (int level = 0; level < 64 && nl < n_ppc; ++level) {
     const int ncb = 1 - cb;
     // leaves to split this level
-    const uint32_t Wi = lane < nl ? LW[cb][lane] : 0u;
+    const uint32_t Wi = lane < nl ? LW(cb)[lane] : 0u;
     const bool cand = lane < nl && Wi >= 2;
     const uint64_t cmask = __ballot(cand);
     const int ncand = __popcll(cmask);
@@ -198,7 +198,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       chosen = cand && rank < budget;
     }
     const uint64_t chm = __ballot(chosen);
-    const uint32_t n_i = lane < nl ? Lcn[cb][lane] : 0u;
+    const uint32_t n_i = lane < nl ? Lcn(cb)[lane] : 0u;
     // new leaf index and region of each old leaf (a splitting leaf gets a spare slot)
     const uint32_t widx = lane < nl ? (chosen ? 2u : 1u) : 0u;
     const uint32_t wreg = n_i + (chosen ? 1u : 0u);
@@ -216,23 +216,23 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       if (chosen) {
         for (int a = 0; a < 3; ++a) { lo[3 * lane + a] = Bits<T>::lo_init; hi[3 * lane + a] = 0; }
       } else {
-        Lst[ncb][newidx] = R; Lcn[ncb][newidx] = n_i; LW[ncb][newidx] = Wi;
+        Lst(ncb)[newidx] = R; Lcn(ncb)[newidx] = n_i; LW(ncb)[newidx] = Wi;
       }
     }
-    for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) { tag[ncb][q] = kNone; otag[q] = kNone; }
+    for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) { tag(ncb)[q] = kNone; otag[q] = kNone; }
     __syncthreads();
     // (i) extents of the splitting leaves: a segmented min/max over each 64-slot chunk
     // of the buffer (a leaf's slots are contiguous), then one LDS atomic per leaf
     // segment and bound (LDS atomics of many lanes on one address serialise)
     for (uint32_t q0 = 0; q0 < extent; q0 += 64) {
       const uint32_t q = q0 + (uint32_t)lane;
-      const uint8_t L = q < extent ? tag[cb][q] : kNone;
+      const uint8_t L = q < extent ? tag(cb)[q] : kNone;
       const bool part = L != kNone && ((chm >> L) & 1ull);
       const uint32_t key = part ? (uint32_t)L : 0xFFFFFFFFu;
       U mn[3], mx[3];
       if (part) {
-        const uint16_t pq = I[cb][q];
-        for (int a = 0; a < 3; ++a) mn[a] = mx[a] = Bits<T>::of(so[a][pq]);
+        const uint16_t pq = I(cb)[q];
+        for (int a = 0; a < 3; ++a) mn[a] = mx[a] = Bits<T>::of(so(a)[pq]);
       } else {
         for (int a = 0; a < 3; ++a) { mn[a] = Bits<T>::lo_init; mx[a] = 0; }
       }
@@ -272,13 +272,13 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     __syncthreads();
     if (contig) {
       for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
-        const uint8_t L = tag[cb][q];
+        const uint8_t L = tag(cb)[q];
         if (L == kNone || !((chm >> L) & 1ull)) continue;
-        const uint16_t pq = I[cb][q];
+        const uint16_t pq = I(cb)[q];
         if (packed) {
-          kid[q] = packed_key(so[axis[L]][pq], idr[pq]);
+          kid[q] = packed_key(so(axis[L])[pq], idr[pq]);
         } else {
-          kkey[q] = so[axis[L]][pq];
+          kkey[q] = so(axis[L])[pq];
           kid[q] = sid[pq];
         }
       }
@@ -286,18 +286,18 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     }
     // (ii) order each splitting leaf by (coordinate, id); copy the other leaves
     for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
-      const uint8_t L = tag[cb][q];
+      const uint8_t L = tag(cb)[q];
       if (L == kNone) continue;
-      const uint32_t Ls = Lst[cb][L], Ln = Lcn[cb][L], RL = Rg[L];
-      const uint16_t pq = I[cb][q];
+      const uint32_t Ls = Lst(cb)[L], Ln = Lcn(cb)[L], RL = Rg[L];
+      const uint16_t pq = I(cb)[q];
       if (!((chm >> L) & 1ull)) {
         const uint32_t ni = (uint32_t)L + (uint32_t)__popcll(chm & ((1ull << L) - 1ull));
-        I[ncb][RL + (q - Ls)] = pq;
-        tag[ncb][RL + (q - Ls)] = (uint8_t)ni;
+        I(ncb)[RL + (q - Ls)] = pq;
+        tag(ncb)[RL + (q - Ls)] = (uint8_t)ni;
         continue;
       }
       const int ax = axis[L];
-      const T kq = so[ax][pq];
+      const T kq = so(ax)[pq];
       const uint64_t iq = sid[pq];
       uint32_t rank = 0;
       if (packed) {
@@ -325,12 +325,12 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         }
       } else {
         for (uint32_t r = Ls; r < Ls + Ln; ++r) {
-          const uint16_t pr = I[cb][r];
-          const T kr = so[ax][pr];
+          const uint16_t pr = I(cb)[r];
+          const T kr = so(ax)[pr];
           rank += (kr < kq || (kr == kq && sid[pr] < iq)) ? 1u : 0u;
         }
       }
-      I[ncb][RL + rank] = pq;
+      I(ncb)[RL + rank] = pq;
       otag[RL + rank] = L;
     }
     __syncthreads();
@@ -343,7 +343,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       const uint8_t t8 = q < new_extent ? otag[q] : kNone;
       const bool valid = t8 != kNone;
       const uint32_t vkey = valid ? (uint32_t)t8 : 0xFFFFFFFFu;
-      const uint64_t w = valid ? (uint64_t)sw[I[ncb][q]] : 0ull;
+      const uint64_t w = valid ? (uint64_t)sw[I(ncb)[q]] : 0ull;
       const uint32_t prev = __shfl_up(vkey, 1, 64);
       const bool head = lane == 0 || prev != vkey;
       const uint64_t heads = __ballot(head);
@@ -356,7 +356,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         if (lane - d >= seg_start) x += y;
       }
       if (seg_start == 0 && vkey == carry_key) x += carry;
-      const bool hit = valid && 2ull * x > (uint64_t)LW[cb][vkey & 63u];
+      const bool hit = valid && 2ull * x > (uint64_t)LW(cb)[vkey & 63u];
       const bool up_hit = __shfl_up(hit ? 1 : 0, 1, 64) != 0;
       const bool prev_same = lane > 0 ? prev == vkey : vkey == carry_key;
       const bool prev_hit = lane > 0 ? up_hit : carry_hit;
@@ -375,7 +375,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     if (lane < nl && chosen) {
       mu = medp[lane];
       const uint32_t Wl = medWl[lane];
-      pm = I[ncb][R + mu];
+      pm = I(ncb)[R + mu];
       const uint32_t wm = sw[pm];
       const uint32_t Wr = Wi - Wl - wm;
       if (wm == 1) {
@@ -404,13 +404,13 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         const uint32_t wm = sw[pm];
         sid[np] = sid[pm];
         if (packed) idr[np] = idr[pm];
-        for (int a = 0; a < 3; ++a) so[a][np] = so[a][pm];
+        for (int a = 0; a < 3; ++a) so(a)[np] = so(a)[pm];
         sw[np] = wm - wl;
         sw[pm] = wl;
-        I[ncb][R + n_i] = (uint16_t)np;
+        I(ncb)[R + n_i] = (uint16_t)np;
       }
-      Lst[ncb][newidx] = R; Lcn[ncb][newidx] = lcnt; LW[ncb][newidx] = WLn;
-      Lst[ncb][newidx + 1] = R + rst; Lcn[ncb][newidx + 1] = rcnt; LW[ncb][newidx + 1] = WRn;
+      Lst(ncb)[newidx] = R; Lcn(ncb)[newidx] = lcnt; LW(ncb)[newidx] = WLn;
+      Lst(ncb)[newidx + 1] = R + rst; Lcn(ncb)[newidx + 1] = rcnt; LW(ncb)[newidx + 1] = WRn;
     }
     __syncthreads();
     // leaf tags of the split regions (ordered slots plus the spare slot)
@@ -419,16 +419,16 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       if (L == kNone) {
         if (q == 0 || otag[q - 1] == kNone) continue;
         const uint8_t Lp = otag[q - 1];
-        if (q != Rg[Lp] + Lcn[cb][Lp]) continue;
+        if (q != Rg[Lp] + Lcn(cb)[Lp]) continue;
         L = Lp;  // the spare slot that follows an ordered range
       }
       const uint32_t ni = (uint32_t)L + (uint32_t)__popcll(chm & ((1ull << L) - 1ull));
       const uint32_t off = q - Rg[L];
-      const uint32_t lc = Lcn[ncb][ni], rs = Lst[ncb][ni + 1] - Rg[L], rc = Lcn[ncb][ni + 1];
+      const uint32_t lc = Lcn(ncb)[ni], rs = Lst(ncb)[ni + 1] - Rg[L], rc = Lcn(ncb)[ni + 1];
       uint8_t t = kNone;
       if (off < lc) t = (uint8_t)ni;
       else if (off >= rs && off < rs + rc) t = (uint8_t)(ni + 1);
-      tag[ncb][q] = t;
+      tag(ncb)[q] = t;
     }
     __syncthreads();
     cb = ncb;
@@ -440,14 +440,14 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   double my_o[3] = {0.0, 0.0, 0.0};
   uint32_t my_w = 0;
   if (lane < nl) {
-    const uint32_t st = Lst[cb][lane], n = Lcn[cb][lane];
+    const uint32_t st = Lst(cb)[lane], n = Lcn(cb)[lane];
     double acc[3] = {0.0, 0.0, 0.0};
     for (uint32_t q = st; q < st + n; ++q) {
-      const uint16_t pq = I[cb][q];
+      const uint16_t pq = I(cb)[q];
       const double w = (double)sw[pq];
-      for (int a = 0; a < 3; ++a) acc[a] += w * (double)so[a][pq];
+      for (int a = 0; a < 3; ++a) acc[a] += w * (double)so(a)[pq];
     }
-    my_w = LW[cb][lane];
+    my_w = LW(cb)[lane];
     for (int a = 0; a < 3; ++a) my_o[a] = acc[a] / (double)my_w;
   }
   uint32_t extra_base = 0;
