@@ -1,9 +1,10 @@
-"""The self-consistent streamer at its full size (256^3 cells, about 6.3 million seed
-particles, FP32, 50 million particle slots), built and stepped exactly as the benchmark
-builds and times it (default tuning: split red-black multigrid, one HIP graph per
-refinement cycle).  The oracle cannot run this size step by step, so the tests check
-what holds at any size, and outputs that the oracle computes independently from state
-the GPU returns:
+"""The workloads at their full size, built and stepped exactly as the benchmark builds
+and times them: the self-consistent streamer (256^3 cells, about 6.3 million seed
+particles, FP32, 50 million particle slots; default tuning: split red-black multigrid,
+one HIP graph per refinement cycle) and the prescribed-field avalanche (256^3 cells,
+5e7 particles).  The oracle cannot run these sizes step by step, so the tests check
+what holds at any size, and outputs that the oracle computes independently, one
+sampled particle or cell at a time, from state the GPU returns:
 
 * exact integer invariants: charge changes only by outflow, the NGP deposit sums to the
   live weight, no negative ion counts, every cell at most N_ppc particles after the
@@ -11,12 +12,15 @@ the GPU returns:
 * the field solve reached its tolerance, and E = -grad(Phi) of the returned potential
   equals the oracle's central differences (with its boundary rules) at every cell, to
   the rounding of the single-precision field;
-* two runs from the same descriptor agree bit for bit.
+* two runs from the same descriptor agree bit for bit;
+* avalanche: 1e5 sampled particles pushed again by the oracle from the GPU's state,
+  and 2000 sampled occupied cells reacted again by the oracle (KMC, products,
+  removals) from the GPU's post-transport state.
 """
 import numpy as np
 import pytest
 
-from helpers import by_id
+from helpers import by_id, gpu_xi, xi_to_cell_off
 from paper_2307_01797_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -96,3 +100,93 @@ def test_fullsize_reproducible(itk, run):
     for a, b in zip(first, second):
         assert np.array_equal(a, b)
     assert np.array_equal(phi_first, g2.field())
+
+
+# ---- prescribed-field avalanche at full size (256^3 cells, 5e7 particles) ----------
+
+SAMPLE_PARTICLES = 100_000
+SAMPLE_CELLS = 2_000
+
+
+def _aval(itk):
+    """A fresh full-size avalanche after two steps (as the benchmark builds it)."""
+    cfg = workloads.preset("avalanche_256")
+    g = itk.Sim(cfg)
+    g.seed()
+    g.step(2)
+    return cfg, g
+
+
+def _subset(cell, off, w, ids, mask):
+    return cell[mask], off[mask], w[mask], ids[mask]
+
+
+def test_fullsize_avalanche_push_sampled(itk, orc):
+    """One full-size transport (push, binning, counting sort over all particles); a
+    random sample of the particles pushed again by the oracle from the same start:
+    the same particles survive, cells agree outside the 1e-5 tie band and positions
+    agree to 1e-5 cells (single-precision state)."""
+    cfg, g = _aval(itk)
+    cell, off, w, ids = g.particles()
+    assert len(ids) > 40_000_000
+    rng = np.random.default_rng(7)
+    pick = rng.choice(len(ids), SAMPLE_PARTICLES, replace=False)
+    step = g.diagnostics()["step"]
+    o = orc.Sim(cfg, capacity=4 * SAMPLE_PARTICLES)
+    o.set_particles(gpu_xi(cell[pick], off[pick], cfg["grid"]), w[pick].astype(np.uint64), ids[pick])
+    o.set_step(step)
+    del cell, off, w
+    g.transport()
+    o.transport(cfg["dt"])
+    cell2, off2, w2, ids2 = g.particles()
+    keep = np.isin(ids2, ids[pick])
+    ids_g, cell_g, off_g = by_id(ids2[keep], cell2[keep], off2[keep])
+    xi_o, w_o, id_o = o.particles()
+    id_o, xi_o = by_id(id_o, xi_o)
+    assert np.array_equal(ids_g, id_o)   # the same particles left the domain
+    co, _ = xi_to_cell_off(xi_o, cfg["grid"])
+    mism = co != cell_g
+    if mism.any():
+        face = np.abs(xi_o[mism] - np.round(xi_o[mism]))
+        assert np.all(np.any(face < 1e-5, axis=1))
+    err = np.abs(gpu_xi(cell_g, off_g, cfg["grid"]) - xi_o)
+    assert err[~mism].max(initial=0.0) < 1e-5
+    assert mism.sum() <= 5
+
+
+def test_fullsize_avalanche_react_sampled(itk, orc):
+    """One full-size reaction pass (per-cell KMC over every occupied cell, products and
+    removals); a random sample of occupied cells reacted again by the oracle from the
+    same post-transport state: every integer of those cells agrees (particle ids,
+    weights and cells, ion counts, fires), product offsets to 1e-6."""
+    cfg, g = _aval(itk)
+    g.transport()
+    cell, off, w, ids = g.particles()
+    rng = np.random.default_rng(11)
+    occ = np.unique(cell)
+    sel = np.sort(rng.choice(occ, SAMPLE_CELLS, replace=False))
+    m = np.isin(cell, sel)
+    c_s, o_s, w_s, i_s = _subset(cell, off, w, ids, m)
+    del cell, off, w, ids
+    o = orc.Sim(cfg, capacity=4_000_000)
+    o.set_particles(gpu_xi(c_s, o_s, cfg["grid"]), w_s.astype(np.uint64), i_s)
+    for which in ("plus", "minus", "gamma"):
+        v = np.zeros(o.ncell, dtype=np.int64)
+        v[sel] = g.counts(which).astype(np.int64)[sel]
+        o.set_counts(which, v)
+    o.set_step(g.diagnostics()["step"])
+    g.react()
+    o.react(cfg["dt"])
+    cell2, off2, w2, ids2 = g.particles()
+    m2 = np.isin(cell2, sel)
+    ids_g, cell_g, off_g, w_g = by_id(ids2[m2], cell2[m2], off2[m2], w2[m2])
+    xi_o, w_o, id_o = o.particles()
+    id_o, xi_o, w_o = by_id(id_o, xi_o, w_o)
+    assert np.array_equal(ids_g, id_o)
+    assert np.array_equal(w_g.astype(np.uint64), w_o)
+    co, _ = xi_to_cell_off(xi_o, cfg["grid"])
+    assert np.array_equal(co, cell_g)
+    assert np.abs(gpu_xi(cell_g, off_g, cfg["grid"]) - xi_o).max(initial=0.0) < 1e-6
+    for which in ("plus", "minus"):
+        assert np.array_equal(g.counts(which).astype(np.int64)[sel], o.counts(which)[sel]), which
+    assert np.array_equal(g.deposit("fires").astype(np.int64)[sel], o.fires()[sel])
