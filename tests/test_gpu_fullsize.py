@@ -13,6 +13,8 @@ sampled particle or cell at a time, from state the GPU returns:
   equals the oracle's central differences (with its boundary rules) at every cell, to
   the rounding of the single-precision field;
 * two runs from the same descriptor agree bit for bit;
+* streamer: 2000 sampled occupied cells reacted again by the oracle (KMC, photon
+  absorption, products, removals, merge/split) from the GPU's post-transport state;
 * avalanche: 1e5 sampled particles pushed again by the oracle from the GPU's state,
   and 2000 sampled occupied cells reacted again by the oracle (KMC, products,
   removals) from the GPU's post-transport state.
@@ -187,6 +189,48 @@ def test_fullsize_avalanche_react_sampled(itk, orc):
     co, _ = xi_to_cell_off(xi_o, cfg["grid"])
     assert np.array_equal(co, cell_g)
     assert np.abs(gpu_xi(cell_g, off_g, cfg["grid"]) - xi_o).max(initial=0.0) < 1e-6
+    for which in ("plus", "minus"):
+        assert np.array_equal(g.counts(which).astype(np.int64)[sel], o.counts(which)[sel]), which
+    assert np.array_equal(g.deposit("fires").astype(np.int64)[sel], o.fires()[sel])
+
+
+def test_fullsize_streamer_react_sampled(itk, orc):
+    """The streamer's full-size reaction pass (KMC in every occupied cell, photon
+    absorption, products, removals, superparticle merge/split to N_ppc); 2000 sampled
+    occupied cells reacted again by the oracle from the GPU's post-transport state, with
+    the GPU's field and every cell's pending photons: the particles of those cells agree
+    in id, weight and cell, positions to 2e-6 cells (merge centroids rounded to single
+    precision), and their ion counts and fires are exact."""
+    cfg, g, _ = _run(itk)
+    g.transport()
+    cell, off, w, ids = g.particles()
+    rng = np.random.default_rng(13)
+    sel = np.sort(rng.choice(np.unique(cell), SAMPLE_CELLS, replace=False))
+    m = np.isin(cell, sel)
+    o = orc.Sim(cfg, capacity=4_000_000)
+    o.set_particles(gpu_xi(cell[m], off[m], cfg["grid"]), w[m].astype(np.uint64), ids[m])
+    del cell, off, w, ids
+    for which in ("plus", "minus"):
+        v = np.zeros(o.ncell, dtype=np.int64)
+        v[sel] = g.counts(which).astype(np.int64)[sel]
+        o.set_counts(which, v)
+    o.set_counts("gamma", g.counts("gamma").astype(np.int64))   # photons land anywhere
+    o.set_efield(g.deposit("ex"), g.deposit("ey"), g.deposit("ez"))
+    o.set_step(g.diagnostics()["step"])
+    g.react()
+    o.react(cfg["dt"])
+    cell2, off2, w2, ids2 = g.particles()
+    m2 = np.isin(cell2, sel)
+    ids_g, cell_g, off_g, w_g = by_id(ids2[m2], cell2[m2], off2[m2], w2[m2])
+    xi_o, w_o, id_o = o.particles()
+    co, _ = xi_to_cell_off(xi_o, cfg["grid"])
+    mo = np.isin(co, sel)
+    id_o, xi_o, w_o, co = by_id(id_o[mo], xi_o[mo], w_o[mo], co[mo])
+    assert len(ids_g) > 0 and np.array_equal(ids_g, id_o)
+    assert np.array_equal(w_g.astype(np.uint64), w_o)
+    assert np.array_equal(co, cell_g)
+    assert np.abs(gpu_xi(cell_g, off_g, cfg["grid"]) - xi_o).max() < 2e-6
+    assert np.bincount(cell_g.astype(np.int64)).max() <= cfg["n_ppc"]
     for which in ("plus", "minus"):
         assert np.array_equal(g.counts(which).astype(np.int64)[sel], o.counts(which)[sel]), which
     assert np.array_equal(g.deposit("fires").astype(np.int64)[sel], o.fires()[sel])
