@@ -245,9 +245,10 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
 // only) and the ascending list of occupied cells (down).  Scratch layout (u32):
 // tile counts [2 nb] | tile prefixes within the group [2 nb] | group prefixes [2 ng + 2].
 
-constexpr int kScanPer = 8;                     // cells per thread
+constexpr int kScanPer = 8;                     // cells per thread (k_scan_down unpacks two uint4)
 constexpr int kScanTile = kBlock * kScanPer;    // cells per tile (1 << kTileShift)
 static_assert(kScanTile == (1 << kTileShift), "scan tile and tile flags disagree");
+static_assert(kScanPer == 8, "k_scan_down reads a thread's counts as two uint4");
 constexpr int kScanGroup = 1024;                // tiles per mid-level group
 
 template <int NT>
@@ -295,11 +296,12 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(const unsigned long long
       if (threadIdx.x == 0) { cnt[2 * t] = 0u; cnt[2 * t + 1] = 0u; }
       continue;
     }
-    const uint32_t c0 = t * kScanTile + threadIdx.x * kScanPer;
+    // only the tile totals are needed here: cells read in coalesced order
+    const uint32_t c0 = t * kScanTile + threadIdx.x;
     uint32_t n = 0, oc = 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      const uint32_t c = c0 + j;
+      const uint32_t c = c0 + j * kBlock;
       if (c < ncell) {
         const uint32_t k = (uint32_t)(cellacc[c] >> 32);
         n += k;
@@ -355,17 +357,29 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* 
                                                      const uint32_t* grp, uint32_t* start,
                                                      uint32_t* occ, Counters* ctr, int dest) {
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
+  __shared__ __align__(16) uint32_t tile_n[kScanTile];
   const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
   const uint32_t nb = scan_tiles(ncell);
   for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
     if (cnt[2 * t] == 0u) continue;  // empty tile: no start entries, no occupied cells
-    const uint32_t c0 = t * kScanTile + threadIdx.x * kScanPer;
-    uint32_t n[kScanPer];
-    uint32_t k = 0, oc = 0;
+    // counts read in coalesced order through LDS; each thread then takes eight
+    // consecutive cells (the scan follows cell order)
+    const uint32_t tb = t * kScanTile;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      const uint32_t c = c0 + j;
-      n[j] = c < ncell ? (uint32_t)(cellacc[c] >> 32) : 0u;
+      const uint32_t i = (uint32_t)j * kBlock + threadIdx.x;
+      tile_n[i] = tb + i < ncell ? (uint32_t)(cellacc[tb + i] >> 32) : 0u;
+    }
+    __syncthreads();
+    const uint32_t c0 = tb + threadIdx.x * kScanPer;
+    uint32_t n[kScanPer];
+    uint32_t k = 0, oc = 0;
+    const uint4 a0 = *reinterpret_cast<const uint4*>(tile_n + threadIdx.x * kScanPer);
+    const uint4 a1 = *reinterpret_cast<const uint4*>(tile_n + threadIdx.x * kScanPer + 4);
+    n[0] = a0.x; n[1] = a0.y; n[2] = a0.z; n[3] = a0.w;
+    n[4] = a1.x; n[5] = a1.y; n[6] = a1.z; n[7] = a1.w;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
       k += n[j];
       oc += n[j] ? 1u : 0u;
     }
