@@ -525,7 +525,9 @@ __global__ void k_eps_restrict(const T* ef, int fnx, int fny, int fsplit, T* ec,
 // (the smoother only has to reduce the error; the double residual of the refinement
 // loop defines the solution).
 __device__ __forceinline__ double hmean_s(double a, double b) { return 2.0 * a * b / (a + b); }
-__device__ __forceinline__ float hmean_s(float a, float b) { return __fdividef(2.0f * a * b, a + b); }
+__device__ __forceinline__ float hmean_s(float a, float b) {
+  return (2.0f * a * b) * __builtin_amdgcn_rcpf(a + b);  // v_rcp_f32 (1 ulp), not a full division
+}
 
 // Operator of the scaled system at one cell (homogeneous boundary values): sum over
 // faces of beta (u_c - u_nb), beta the harmonic mean of the two cells' coefficients,
