@@ -528,6 +528,10 @@ __device__ __forceinline__ double hmean_s(double a, double b) { return 2.0 * a *
 __device__ __forceinline__ float hmean_s(float a, float b) {
   return (2.0f * a * b) * __builtin_amdgcn_rcpf(a + b);  // v_rcp_f32 (1 ulp), not a full division
 }
+// The smoother's cell update (f + offsum) / diag, in every smoother form: a division in
+// double, the hardware reciprocal in single precision.
+__device__ __forceinline__ double smooth_div(double num, double d) { return num / d; }
+__device__ __forceinline__ float smooth_div(float num, float d) { return num * __builtin_amdgcn_rcpf(d); }
 
 // Operator of the scaled system at one cell (homogeneous boundary values): sum over
 // faces of beta (u_c - u_nb), beta the harmonic mean of the two cells' coefficients,
@@ -649,7 +653,7 @@ __device__ __forceinline__ void smooth_cell(T* u, const T* f, const T* eps, int 
   const size_t c = (size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k);
   T d, s;
   stencil_s<T>(u, eps, nx, ny, nz, i, j, k, c, d, s);
-  u[c] = (f[c] + s) / d;
+  u[c] = smooth_div(f[c] + s, d);
 }
 
 // One colour of a red-black Gauss-Seidel sweep in natural order: grid (x: half a row,
@@ -680,7 +684,7 @@ __global__ void __launch_bounds__(128) k_smooth_split(T* u, const T* f, const T*
   const SplitAt at = split_at(i, j, k, nx, ny);
   T d, s;
   stencil_at<T>(u, eps, at, nx, ny, nz, i, j, k, d, s);
-  u[at.own] = (f[at.own] + s) / d;
+  u[at.own] = smooth_div(f[at.own] + s, d);
 }
 
 // r = b - A phi in double with the true boundary values (the lift is in b) over
@@ -896,7 +900,7 @@ __device__ __forceinline__ void small_sweeps_cached(T* su, const T* sf, const T*
         T acc = 0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) acc = ((m >> q) & 1u) ? acc + bq[r][q] * un[q] : acc;
-        su[c] = (fr[r] + acc) / dg[r];
+        su[c] = smooth_div(fr[r] + acc, dg[r]);
       }
       __syncthreads();
     }
@@ -1134,6 +1138,9 @@ __global__ void __launch_bounds__(256) k_residual_seg(const double* phi, const d
       ld_seg_vals<T, kSplit>(eps, R, s, nx, E);
       double B[8];
       ld_seg<double, false>(b, R.rb, h, s.t, s.par, B);
+      // every load above is issued before the arithmetic below (the scheduler would
+      // otherwise interleave them to save registers and wait on each)
+      __builtin_amdgcn_sched_barrier(0);
       T F[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -1173,30 +1180,34 @@ __global__ void __launch_bounds__(256) k_smooth_seg(T* u, const T* f, const T* e
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
   const size_t oym = s.j > 0 ? oth - sy : oth, oyp = s.j < ny - 1 ? oth + sy : oth;
   const size_t ozm = s.k > 0 ? oth - sz : oth, ozp = s.k < nz - 1 ? oth + sz : oth;
-  const size_t pl = s.t > 0 ? oth - 1 : oth, pr = 4 * s.t + 4 < h ? oth + 4 : oth + 3;
+  // the one x neighbour outside the segment's other-colour values: on the left of the
+  // first cell (odd = 0) or on the right of the last (odd = 1); a single unconditional
+  // load, so that it joins the others in flight
+  const size_t pe = odd ? (4 * s.t + 4 < h ? oth + 4 : oth + 3) : (s.t > 0 ? oth - 1 : oth);
   const V4<T> Fo = ld4(f + own), Eo = ld4(eps + own);
   const V4<T> Ec = ld4(eps + oth);
   const V4<T> Eym = ld4(eps + oym), Eyp = ld4(eps + oyp), Ezm = ld4(eps + ozm), Ezp = ld4(eps + ozp);
-  const T EL = eps[pl], ER = eps[pr];
+  const T EX = eps[pe];
   // kZero: the first colour-0 sweep of a cycle, from u = 0 (the neighbours' values are
   // zeros, not read)
   const V4<T> zero = {{(T)0, (T)0, (T)0, (T)0}};
   const V4<T> Uc = kZero ? zero : ld4(u + oth);
   const V4<T> Uym = kZero ? zero : ld4(u + oym), Uyp = kZero ? zero : ld4(u + oyp);
   const V4<T> Uzm = kZero ? zero : ld4(u + ozm), Uzp = kZero ? zero : ld4(u + ozp);
-  const T UL = kZero ? (T)0 : u[pl], UR = kZero ? (T)0 : u[pr];
+  const T UX = kZero ? (T)0 : u[pe];
+  __builtin_amdgcn_sched_barrier(0);  // all loads issued before the arithmetic
   T un_[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     bool in[6];
     faces_in(2 * (4 * s.t + r) + odd, s.j, s.k, nx, ny, nz, in);
-    const T en[6] = {odd ? Ec.a[r] : (r > 0 ? Ec.a[r - 1] : EL), odd ? (r < 3 ? Ec.a[r + 1] : ER) : Ec.a[r],
+    const T en[6] = {odd ? Ec.a[r] : (r > 0 ? Ec.a[r - 1] : EX), odd ? (r < 3 ? Ec.a[r + 1] : EX) : Ec.a[r],
                      Eym.a[r], Eyp.a[r], Ezm.a[r], Ezp.a[r]};
-    const T un[6] = {odd ? Uc.a[r] : (r > 0 ? Uc.a[r - 1] : UL), odd ? (r < 3 ? Uc.a[r + 1] : UR) : Uc.a[r],
+    const T un[6] = {odd ? Uc.a[r] : (r > 0 ? Uc.a[r - 1] : UX), odd ? (r < 3 ? Uc.a[r + 1] : UX) : Uc.a[r],
                      Uym.a[r], Uyp.a[r], Uzm.a[r], Uzp.a[r]};
     T d, sm;
     op_row<T>(Eo.a[r], en, un, in, d, sm);
-    un_[r] = (Fo.a[r] + sm) / d;
+    un_[r] = smooth_div(Fo.a[r] + sm, d);
   }
   st4<T>(u + own, un_[0], un_[1], un_[2], un_[3]);
 }
