@@ -148,29 +148,44 @@ __device__ __forceinline__ void cic_add(T* grid, const StepConst& K, int i0, int
 // interpolation") from the packed (Ex, Ey, Ez, 0) array: the eight nodes' vectors are
 // loaded together (node indices clamped into the grid; a node outside it has weight
 // zero and is skipped), then each component is summed in node order.
+// The eight node values of a CIC gather (loads only; the weights and the masks of nodes
+// outside the grid or of zero weight), then their weighted sums in node order.
 template <typename T>
-__device__ __forceinline__ void cic_get3(const T* E4, const StepConst& K, int i0, int j0, int k0, T fx,
-                                         T fy, T fz, T out[3]) {
-  const int nx = K.nx, ny = K.ny, nz = K.nz;
+struct CicNodes {
   V4<T> v[8];
   T wt[8];
   bool use[8];
+};
+template <typename T>
+__device__ __forceinline__ void cic_load(const T* E4, const StepConst& K, int i0, int j0, int k0, T fx, T fy,
+                                         T fz, CicNodes<T>& g) {
+  const int nx = K.nx, ny = K.ny, nz = K.nz;
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {
     const int di = cc & 1, dj = (cc >> 1) & 1, dk = (cc >> 2) & 1;
-    wt[cc] = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
+    g.wt[cc] = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
     const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
-    use[cc] = !(wt[cc] == (T)0 || ii >= nx || jj >= ny || kk >= nz);
+    g.use[cc] = !(g.wt[cc] == (T)0 || ii >= nx || jj >= ny || kk >= nz);
     const int ic = ii < nx ? ii : nx - 1, jc = jj < ny ? jj : ny - 1, kc = kk < nz ? kk : nz - 1;
-    v[cc] = ld4(E4 + 4 * ((size_t)ic + (size_t)nx * ((size_t)jc + (size_t)ny * kc)));
+    g.v[cc] = ld4(E4 + 4 * ((size_t)ic + (size_t)nx * ((size_t)jc + (size_t)ny * kc)));
   }
+}
+template <typename T>
+__device__ __forceinline__ void cic_sum(const CicNodes<T>& g, T out[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     T acc = (T)0;
 #pragma unroll
-    for (int cc = 0; cc < 8; ++cc) acc = use[cc] ? acc + v[cc].a[a] * wt[cc] : acc;
+    for (int cc = 0; cc < 8; ++cc) acc = g.use[cc] ? acc + g.v[cc].a[a] * g.wt[cc] : acc;
     out[a] = acc;
   }
+}
+template <typename T>
+__device__ __forceinline__ void cic_get3(const T* E4, const StepConst& K, int i0, int j0, int k0, T fx,
+                                         T fy, T fz, T out[3]) {
+  CicNodes<T> g;
+  cic_load<T>(E4, K, i0, j0, k0, fx, fy, fz, g);
+  cic_sum<T>(g, out);
 }
 
 template <typename T> struct Mob;
@@ -370,23 +385,38 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     uint32_t key = kInvalidCell, w = 0;
-    if (i < n) w = a.w[i];
+    // the particle's own words are read before its weight is tested (one round trip)
+    uint32_t cell0 = 0;
+    T o0[3] = {(T)0, (T)0, (T)0};
+    uint64_t id0 = 0;
+    if (i < n) {
+      w = a.w[i];
+      cell0 = a.cell[i];
+      o0[0] = tp<T>(a.ox)[i];
+      o0[1] = tp<T>(a.oy)[i];
+      o0[2] = tp<T>(a.oz)[i];
+      id0 = a.id[i];
+    }
     if (w > 0) {
       ++pushed;
-      const uint32_t cell = a.cell[i];
+      const uint32_t cell = cell0;
       int ci[3] = {(int)(cell % (uint32_t)K.nx), (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
                    (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny))};
-      T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
+      T o[3] = {o0[0], o0[1], o0[2]};
       int i0, j0, k0;
       T fx, fy, fz;
       tent_axis<T>(ci[0], o[0], K.nx, i0, fx);
       tent_axis<T>(ci[1], o[1], K.ny, j0, fy);
       tent_axis<T>(ci[2], o[2], K.nz, k0, fz);
       T eo[3], en[3];
-      cic_get3<T>(ctp<T>(Eo4), K, i0, j0, k0, fx, fy, fz, eo);
-      cic_get3<T>(ctp<T>(En4), K, i0, j0, k0, fx, fy, fz, en);
+      CicNodes<T> go, gn;
+      cic_load<T>(ctp<T>(Eo4), K, i0, j0, k0, fx, fy, fz, go);
+      cic_load<T>(ctp<T>(En4), K, i0, j0, k0, fx, fy, fz, gn);
+      __builtin_amdgcn_sched_barrier(0);  // the sixteen gathers in flight together
+      cic_sum<T>(go, eo);
+      cic_sum<T>(gn, en);
       const T mu = Mob<T>::mu(co, sqrt(eo[0] * eo[0] + eo[1] * eo[1] + eo[2] * eo[2]));
-      const uint64_t id = a.id[i];
+      const uint64_t id = id0;
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
       T nr[3];
       NormalsF<T>::get(r, nr);
@@ -1240,6 +1270,7 @@ __global__ void __launch_bounds__(256) k_restrict_seg(const T* u, const T* f, co
     ld_seg_vals<T, kSplit>(eps, R, s, nx, E);
     T F[8];
     ld_seg<T, kSplit>(f, R.rb, h, s.t, s.par, F);
+    __builtin_amdgcn_sched_barrier(0);  // the row's loads in flight together
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       bool in[6];
