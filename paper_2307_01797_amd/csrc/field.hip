@@ -1407,10 +1407,14 @@ __global__ void k_efield(const double* phi, int nx, int ny, int nz, double V, do
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    // neighbour indices clamped to the cell itself on the faces, so the seven loads are
+    // unconditional and in flight together (the clamped value is the Neumann one)
     const double pc = phi[c];
-    const double xm = i > 0 ? phi[c - 1] : pc, xp = i < nx - 1 ? phi[c + 1] : pc;
-    const double ym = j > 0 ? phi[c - sy] : pc, yp = j < ny - 1 ? phi[c + sy] : pc;
-    const double zm = k > 0 ? phi[c - sz] : -pc, zp = k < nz - 1 ? phi[c + sz] : 2.0 * V - pc;
+    const double xm = phi[i > 0 ? c - 1 : c], xp = phi[i < nx - 1 ? c + 1 : c];
+    const double ym = phi[j > 0 ? c - sy : c], yp = phi[j < ny - 1 ? c + sy : c];
+    const double vzm = phi[k > 0 ? c - sz : c], vzp = phi[k < nz - 1 ? c + sz : c];
+    __builtin_amdgcn_sched_barrier(0);
+    const double zm = k > 0 ? vzm : -pc, zp = k < nz - 1 ? vzp : 2.0 * V - pc;
     st4<T>(E4 + 4 * (size_t)c, (T)(-(xp - xm) * inv2h), (T)(-(yp - ym) * inv2h), (T)(-(zp - zm) * inv2h),
            (T)0);
   }

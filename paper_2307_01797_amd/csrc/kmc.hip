@@ -21,11 +21,7 @@ namespace itk {
 namespace {
 
 // Rates from |E| at the cell centre (local field approximation).
-__device__ void rates_at(const FieldRates& fr, uint32_t c, double k[3]) {
-  double e[3];
-  for (int a = 0; a < 3; ++a)
-    e[a] = fr.is_double ? reinterpret_cast<const double*>(fr.E4)[4 * (size_t)c + a]
-                        : (double)reinterpret_cast<const float*>(fr.E4)[4 * (size_t)c + a];
+__device__ void rates_from_field(const FieldRates& fr, const double e[3], double k[3]) {
   const double Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
   const double Ec = Em > fr.E_floor ? Em : fr.E_floor;
   const double mu = fr.mu_a * pow(Ec / fr.mu_E0, fr.mu_b);
@@ -59,20 +55,53 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) k_kmc_step(
   for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
     uint32_t js[kKmcPer], Ms[kKmcPer], fl[kKmcPer];  // fl: 1 queue, 2 defer
     uint32_t nq = 0, nd = 0, nm = 0;
+    // the words of the thread's cells are read first, all in flight together: the
+    // cell indices, then each cell's counts and field (or the rates kept for it)
+    // (indices past the end are clamped to the last cell, whose words are then unused,
+    // so that no load is conditional)
+    uint32_t cs[kKmcPer], xe0[kKmcPer], xp0[kKmcPer], xm0[kKmcPer];
+    double kv[kKmcPer][3];
 #pragma unroll
     for (int r = 0; r < kKmcPer; ++r) {
       const uint32_t jj = base + (uint32_t)r * blockDim.x + threadIdx.x;
-      js[r] = 0; Ms[r] = 0; fl[r] = 0;
+      const uint32_t jc = jj < n ? jj : n - 1;
+      js[r] = kFast ? jc : heavy[jc];
+    }
+#pragma unroll
+    for (int r = 0; r < kKmcPer; ++r) cs[r] = occ[js[r]];
+#pragma unroll
+    for (int r = 0; r < kKmcPer; ++r) {
+      xe0[r] = (uint32_t)cellacc[cs[r]];
+      xp0[r] = nplus[cs[r]];
+      xm0[r] = nminus[cs[r]];
+    }
+    if (fr.E4 && kFast && fr.is_double) {
+#pragma unroll
+      for (int r = 0; r < kKmcPer; ++r)
+        for (int a = 0; a < 3; ++a) kv[r][a] = reinterpret_cast<const double*>(fr.E4)[4 * (size_t)cs[r] + a];
+    } else if (fr.E4 && kFast) {
+#pragma unroll
+      for (int r = 0; r < kKmcPer; ++r)
+        for (int a = 0; a < 3; ++a) kv[r][a] = (double)reinterpret_cast<const float*>(fr.E4)[4 * (size_t)cs[r] + a];
+    } else if (fr.E4) {
+#pragma unroll
+      for (int r = 0; r < kKmcPer; ++r)
+        for (int a = 0; a < 3; ++a) kv[r][a] = rates[3 * (size_t)js[r] + a];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < kKmcPer; ++r) {
+      const uint32_t jj = base + (uint32_t)r * blockDim.x + threadIdx.x;
+      Ms[r] = 0; fl[r] = 0;
       if (jj >= n) continue;
-      const uint32_t j = kFast ? jj : heavy[jj];
-      js[r] = j;
-      const uint32_t c = occ[j];
-      const uint32_t Xe = (uint32_t)cellacc[c];
-      State X{(int64_t)Xe, (int64_t)nplus[c], (int64_t)nminus[c], 0};
+      const uint32_t j = js[r];
+      const uint32_t c = cs[r];
+      const uint32_t Xe = xe0[r];
+      State X{(int64_t)Xe, (int64_t)xp0[r], (int64_t)xm0[r], 0};
       double k[3];
       if (!fr.E4) { k[0] = K.k[0]; k[1] = K.k[1]; k[2] = K.k[2]; }
-      else if (kFast) rates_at(fr, c, k);
-      else { k[0] = rates[3 * (size_t)j]; k[1] = rates[3 * (size_t)j + 1]; k[2] = rates[3 * (size_t)j + 2]; }
+      else if (kFast) rates_from_field(fr, kv[r], k);
+      else { k[0] = kv[r][0]; k[1] = kv[r][1]; k[2] = kv[r][2]; }
       CellStream st;
       st.init(c, K.step, TAG_KMC, 0, K.key);
       int64_t f[3];
