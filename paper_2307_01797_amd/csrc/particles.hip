@@ -186,22 +186,47 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
   const double two_pi = 6.283185307179586476925286766559;
   const double lr = l2 / l1;
   uint64_t absorbed = 0, lost = 0;
+  const int lane = lane_id();
   for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < k.ncell; c0 += gridDim.x * blockDim.x) {
     const uint32_t c = c0 + threadIdx.x;
     const uint32_t ng = c < k.ncell ? ngamma[c] : 0u;
     const uint32_t M = ng < (uint32_t)n_new ? ng : (uint32_t)n_new;
-    // one atomic per wavefront reserves every photon's slot; a photon that leaves the
-    // domain leaves its slot dead (weight 0), which the scatter skips
-    const uint32_t slot0 = wave_append(&ctr->n[which], M);
-    if (ng == 0) continue;
-    ngamma[c] = 0;
-    const uint32_t wb = ng / M, wr = ng % M;
-    const double ci = (double)(c % (uint32_t)k.nx), cj = (double)((c / (uint32_t)k.nx) % (uint32_t)k.ny),
-                 ck = (double)(c / ((uint32_t)k.nx * (uint32_t)k.ny));
-    for (uint32_t s = 0; s < M; ++s) {
-      const uint32_t w = wb + (s == 0 ? wr : 0u);
-      const uint4 A = philox_block(c, s, k.step, TAG_PHOTON, 0, k.key);
-      const uint4 B = philox_block(c, s, k.step, TAG_PHOTON, 1, k.key);
+    if (__ballot(M > 0) == 0ull) continue;  // no photons in this wavefront's cells
+    if (ng) ngamma[c] = 0;
+    // one atomic per wavefront reserves the slots of all its photons: cell lane L owns
+    // slots [incl_L - M_L, incl_L) after the wavefront's base (incl: inclusive prefix
+    // of M over the lanes); a photon that leaves the domain leaves its slot dead
+    // (weight 0), which the scatter skips
+    uint32_t incl = M;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    const uint32_t tot = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if (lane == 63) base = atomicAdd(&ctr->n[which], tot);
+    base = __shfl(base, 63, 64);
+    const uint32_t cw = c0 + (threadIdx.x & ~63u);  // the wavefront's first cell
+    // the wavefront's photons spread over its lanes: photon p (slot base + p) belongs to
+    // the first lane L with incl_L > p
+    for (uint32_t p0 = 0; p0 < tot; p0 += 64) {
+      const uint32_t pp = p0 + (uint32_t)lane;
+      int L = 0;
+#pragma unroll
+      for (int st = 32; st >= 1; st >>= 1) {
+        const uint32_t v = __shfl(incl, L + st - 1, 64);
+        if (v <= pp) L += st;
+      }
+      const uint32_t inclL = __shfl(incl, L, 64), ngL = __shfl(ng, L, 64);
+      if (pp >= tot) continue;
+      const uint32_t ML = ngL < (uint32_t)n_new ? ngL : (uint32_t)n_new;
+      const uint32_t sidx = pp - (inclL - ML), cc = cw + (uint32_t)L;
+      const uint32_t w = ngL / ML + (sidx == 0 ? ngL % ML : 0u);
+      const double ci = (double)(cc % (uint32_t)k.nx), cj = (double)((cc / (uint32_t)k.nx) % (uint32_t)k.ny),
+                   ck = (double)(cc / ((uint32_t)k.nx * (uint32_t)k.ny));
+      const uint4 A = philox_block(cc, sidx, k.step, TAG_PHOTON, 0, k.key);
+      const uint4 B = philox_block(cc, sidx, k.step, TAG_PHOTON, 1, k.key);
       const double cth = 2.0 * u_co(A.w) - 1.0;
       const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
       const double ph = two_pi * u_co(B.x);
@@ -211,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
                            ck + u24(A.z) + rg * cth};
       const bool in = y[0] >= 0.0 && y[0] < k.nx && y[1] >= 0.0 && y[1] < k.ny && y[2] >= 0.0 &&
                       y[2] < k.nz;
-      const uint32_t q = slot0 + s;
+      const uint32_t q = base + pp;
       if (!in) {
         lost += w;
         if (q < k.cap) a.w[q] = 0u;
@@ -222,7 +247,7 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
           (uint32_t)f[0] + (uint32_t)k.nx * ((uint32_t)f[1] + (uint32_t)k.ny * (uint32_t)f[2]);
       if (q >= k.cap) { atomicOr(&ctr->overflow, 1u); continue; }
       put<T>(a, q, cell, to_off<T>(y[0] - f[0]), to_off<T>(y[1] - f[1]), to_off<T>(y[2] - f[2]), w,
-             make_id(KIND_PHOTO, k.step, c, s));
+             make_id(KIND_PHOTO, k.step, cc, sidx));
       const unsigned long long old = atomicAdd(&cellacc[cell], (1ull << 32) | (unsigned long long)w);
       mark_tile(tiles, cell, old);
       a.rank[q] = (uint32_t)(old >> 32);
