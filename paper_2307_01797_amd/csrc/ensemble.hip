@@ -203,10 +203,24 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
   for (uint32_t base = b0; base < b1; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     uint32_t key = kInvalidCell, w = 0;
-    if (i < b1) w = a.w[i];
+    // two rounds of loads instead of a chain: the particle's words (kept ahead of the
+    // weight test by the empty asm), then its block's slot and local block
+    uint32_t g = 0;
+    T o0[3] = {(T)0, (T)0, (T)0};
+    uint64_t id0 = 0;
+    if (i < b1) {
+      w = a.w[i];
+      g = a.cell[i];
+      o0[0] = as<T>(a.ox)[i];
+      o0[1] = as<T>(a.oy)[i];
+      o0[2] = as<T>(a.oz)[i];
+      id0 = a.id[i];
+    }
+    asm volatile("" ::"v"(w), "v"(g), "v"(o0[0]), "v"(o0[1]), "v"(o0[2]), "v"(id0));
     if (w > 0) {
-      const uint32_t g = a.cell[i];
       const int s = blk_slot[g >> kBlkShift];
+      const uint32_t lblk = blk_local[g >> kBlkShift];
+      asm volatile("" ::"v"(s), "v"(lblk));
       if (s < 0) {
         a.w[i] = 0;  // realization released
       } else if (sc[s].state != ITOKMC_SLOT_ACTIVE) {
@@ -222,13 +236,13 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
           cur = (uint32_t)s;
           live = left = outw = 0;
         }
-        const uint32_t c = to_local(g, blk_local);
-        T o[3] = {as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i]};
+        const uint32_t c = (lblk << kBlkShift) | (g & kBlkMask);  // the local cell index
+        T o[3] = {o0[0], o0[1], o0[2]};
         int ci[3] = {(int)(c % (uint32_t)S.nx), (int)((c / (uint32_t)S.nx) % (uint32_t)S.ny),
                      (int)(c / ((uint32_t)S.nx * (uint32_t)S.ny))};
         const int lim[3] = {S.nx, S.ny, S.nz};
         const T drift[3] = {(T)S.drift[0], (T)S.drift[1], (T)S.drift[2]};
-        const bool inside = push_uniform<T>(a.id[i], S.step, S.key, drift, (T)S.diff, lim, ci, o);
+        const bool inside = push_uniform<T>(id0, S.step, S.key, drift, (T)S.diff, lim, ci, o);
         ++live;
         if (inside) {
           const uint32_t lc =
