@@ -113,6 +113,32 @@ __global__ void __launch_bounds__(1024) k_sum_partials(const double* part, int n
   }
 }
 
+// The residual's norm as k_sum_partials computes it, also written with ||b||^2 into
+// mapped host memory, followed by a sequence number (after a system-scope fence), so
+// that the host can wait for it by polling instead of a copy and a stream
+// synchronisation.
+__global__ void __launch_bounds__(1024) k_sum_notify(const double* part, int n, double* out,
+                                                     const double* bn2, double* host,
+                                                     unsigned long long* seq) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) v += part[i];
+  v = wave_sumd(v);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += sh[i];
+    *out = s;
+    host[0] = *bn2;
+    host[1] = s;
+    __threadfence_system();
+    const unsigned long long q = atomicAdd(seq, 1ull) + 1ull;
+    reinterpret_cast<volatile unsigned long long*>(host)[2] = q;
+    __threadfence_system();
+  }
+}
+
 // ---- CIC helpers ------------------------------------------------------------------
 
 // Lower tent node and weight of the upper node along one axis for a particle in cell c
@@ -1448,7 +1474,9 @@ struct FieldState {
   void* sig = nullptr;
   void* ne = nullptr;
   double* norms = nullptr;   // device: ||b||^2, ||r||^2, then per-block partials
-  double* host_norms = nullptr;
+  double* host_norms = nullptr;    // mapped pinned host memory: ||b||^2, ||r||^2, sequence
+  double* host_norms_dev = nullptr;  // its device address
+  unsigned long long seq_expect = 0;  // notifications the host has waited for
   double* phi_prev = nullptr;  // converged potential of the previous step
   bool have_prev = false;
   bool split = false;  // finest level in split red-black order (nx even, more than one level)
@@ -1529,7 +1557,12 @@ int field_init(itokmc_ctx* ctx, char* base) {
     L.f = p; p += al(L.n * T);
     L.eps = p; p += al(L.n * T);
   }
-  hipError_t e = hipHostMalloc((void**)&F->host_norms, 64, hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&F->host_norms, 64, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    for (int i = 0; i < 8; ++i) F->host_norms[i] = 0.0;
+    e = hipHostGetDevicePointer((void**)&F->host_norms_dev, F->host_norms, 0);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(F->norms, 0, 8 * sizeof(double), ctx->s);
   if (e == hipSuccess) e = hipMemsetAsync(F->phi, 0, n * 8, ctx->s);
   for (int s = 0; s < 2 && e == hipSuccess; ++s)
     e = hipMemsetAsync(F->E[s], 0, n * 4 * T, ctx->s);
@@ -1699,6 +1732,25 @@ static void vcycle(itokmc_ctx* ctx, FieldState* F, int l, hipStream_t s) {
   smooth_sweeps<T>(F, l, s, ctx->tune.mg_post);
 }
 
+// Wait for the next residual-norm notification (k_sum_notify) by polling the mapped
+// host word; after a fraction of a second without it (a failed launch), synchronise the stream,
+// which reports the error.  While the smoother is being timed the stream is
+// synchronised instead (its events are read right after).
+static hipError_t wait_norms(FieldState* F, hipStream_t s) {
+  const unsigned long long want = ++F->seq_expect;
+  if (F->timing) return hipStreamSynchronize(s);
+  volatile unsigned long long* q = reinterpret_cast<volatile unsigned long long*>(F->host_norms) + 2;
+  for (long spin = 0; *q < want; ++spin) {
+    if (spin > (1L << 26)) {
+      const hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      if (*q < want) return hipErrorUnknown;
+      break;
+    }
+  }
+  return hipSuccess;
+}
+
 // Accumulate the timed finest-level smoother launches of the last cycle (the stream
 // has been synchronised).
 static void collect_smooth(itokmc_ctx* ctx, FieldState* F) {
@@ -1726,7 +1778,8 @@ static void residual(FieldState* F, hipStream_t s) {
     else
       k_residual_seg<T, false><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
                                                   (T*)L0.f, F->norms + 8);
-    k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+    k_sum_notify<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1, F->norms, F->host_norms_dev,
+                                    reinterpret_cast<unsigned long long*>(F->norms + 2));
     return;
   }
   const uint32_t runs = (L0.n + 255) / 256;
@@ -1737,7 +1790,8 @@ static void residual(FieldState* F, hipStream_t s) {
   else
     k_residual_rows<T, false><<<rb, 256, 0, s>>>(F->phi, F->b, (const T*)L0.eps, L0.nx, L0.ny, L0.nz,
                                                  (T*)L0.f, F->norms + 8);
-  k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1);
+  k_sum_notify<<<1, 1024, 0, s>>>(F->norms + 8, rb, F->norms + 1, F->norms, F->host_norms_dev,
+                                  reinterpret_cast<unsigned long long*>(F->norms + 2));
 }
 
 // One refinement cycle: correction V-cycle from zero, potential update, new double
@@ -1803,8 +1857,8 @@ static int solve(itokmc_ctx* ctx, FieldState* F) {
   residual<T>(F, s);
   const bool graph = ctx->tune.use_graph && !F->timing && capture_cycle<T>(ctx, F);
   for (int cyc = 0;; ++cyc) {
-    hipError_t e = hipMemcpyAsync(F->host_norms, F->norms, 16, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // every residual launch ends with one notification: wait for this one
+    hipError_t e = wait_norms(F, s);
     if (e != hipSuccess) return check_hip(ctx, e, "solve residual");
     collect_smooth(ctx, F);
     const double bn2 = F->host_norms[0], rn2 = F->host_norms[1];
