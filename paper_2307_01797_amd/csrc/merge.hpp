@@ -132,7 +132,8 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   for (uint32_t q0 = 0; q0 < nseg + M; q0 += 64) {
     const uint32_t qi = q0 + (uint32_t)lane;
     const uint32_t q = qi < nseg ? s + qi : base + (qi - nseg);
-    const uint32_t w = qi < nseg + M ? b.w[q] : 0u;
+    // product slots past the bank's capacity were never written (overflow is flagged)
+    const uint32_t w = qi < nseg + M && q < K.cap ? b.w[q] : 0u;
     const bool alive = w > 0;
     const uint64_t mask = __ballot(alive);
     const uint32_t pos = m + (uint32_t)__popcll(mask & lanemask_lt());
