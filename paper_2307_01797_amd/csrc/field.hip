@@ -297,11 +297,10 @@ template <typename T> struct DepTbl { static constexpr int log2n = 10; };
 
 template <typename T, int L2>
 __device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v0,
-                                        typename DepAcc<T>::S* v1, uint32_t node, T a, T b,
+                                        typename DepAcc<T>::S* v1, uint32_t node, uint32_t h, T a, T b,
                                         typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
   using A = DepAcc<T>;
   constexpr uint32_t mask = (1u << L2) - 1u;
-  uint32_t h = (node * 2654435761u) >> (32 - L2);
   for (int probe = 0; probe < kDepProbes; ++probe) {
     uint32_t k = keys[h];
     if (k == kEmptyKey) {
@@ -330,8 +329,12 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
     const T wt = (di ? fx : (T)1 - fx) * (dj ? fy : (T)1 - fy) * (dk ? fz : (T)1 - fz);
     const int ii = i0 + di, jj = j0 + dj, kk = k0 + dk;
     if (wt == (T)0 || ii >= K.nx || jj >= K.ny || kk >= K.nz) continue;
-    const uint32_t node = (uint32_t)ii + (uint32_t)K.nx * ((uint32_t)jj + (uint32_t)K.ny * (uint32_t)kk);
-    tbl_add<T, L2>(keys, v0, v1, node, qa * wt, qb * wt, g0, g1);
+    const uint32_t row = (uint32_t)jj + (uint32_t)K.ny * (uint32_t)kk;
+    const uint32_t node = (uint32_t)ii + (uint32_t)K.nx * row;
+    // table slot: the row hashed, x kept in order, so that a row's nodes sit in
+    // consecutive slots and the flush's atomics of neighbouring lanes share lines
+    const uint32_t h = ((uint32_t)ii + ((row * 2654435761u) >> (32 - L2))) & ((1u << L2) - 1u);
+    tbl_add<T, L2>(keys, v0, v1, node, h, qa * wt, qb * wt, g0, g1);
   }
 }
 
