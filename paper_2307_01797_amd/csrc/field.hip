@@ -288,9 +288,10 @@ template <> struct DepAcc<float> {
 // at X^k only (initial field); mode 1 deposits the conductivity weight mu(|E^k|) w at
 // X^k and the electron number at X_dagger (the position after the diffusive part of
 // the step, with the normals of the push).
-// A 1024-entry table per 512-particle chunk (20 KB of LDS): smaller tables raise the
-// number of resident workgroups, and a table twice the chunk keeps probing short.
-constexpr int kDepChunk = 512;
+// A 1024-entry table per 256-particle chunk, one particle per thread (20 KB of LDS):
+// small tables raise the number of resident workgroups, a table four times the chunk
+// keeps probing short, and with the row-ordered slots a chunk's nodes rarely collide.
+constexpr int kDepChunk = 256;
 constexpr int kDepProbes = 8;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 template <typename T> struct DepTbl { static constexpr int log2n = 10; };
