@@ -1192,27 +1192,66 @@ __global__ void __launch_bounds__(256) k_residual_seg(const double* phi, const d
     if (g < nseg) {
       const Seg s = seg_of(g, ns, ny);
       const SegRows R = seg_rows(s, nx, ny, nz);
-      SegVals<double> P;
-      SegVals<T> E;
-      ld_seg_vals<double, false>(phi, R, s, nx, P);
-      ld_seg_vals<T, kSplit>(eps, R, s, nx, E);
-      double B[8];
+      const int i0 = 8 * s.t;
+      // two rounds of loads, each issued together before its arithmetic: the segment's
+      // row with its x and y neighbours (faces 0-3), then the z neighbour rows (faces
+      // 4-5); the face sums continue in the operator's face order (same values), and
+      // the y rows are dead before the z rows arrive (fewer registers, more waves)
+      double Pc[8], Pym[8], Pyp[8], B[8];
+      T Ec[8], Eym[8], Eyp[8];
+      ld_seg<double, false>(phi, R.rb, h, s.t, s.par, Pc);
+      ld_seg<double, false>(phi, R.ym, h, s.t, R.pym, Pym);
+      ld_seg<double, false>(phi, R.yp, h, s.t, R.pyp, Pyp);
+      const double Pl = ld_cell<double, false>(phi, R.rb, h, i0 > 0 ? i0 - 1 : i0, s.par);
+      const double Pr = ld_cell<double, false>(phi, R.rb, h, i0 + 8 < nx ? i0 + 8 : i0 + 7, s.par);
+      ld_seg<T, kSplit>(eps, R.rb, h, s.t, s.par, Ec);
+      ld_seg<T, kSplit>(eps, R.ym, h, s.t, R.pym, Eym);
+      ld_seg<T, kSplit>(eps, R.yp, h, s.t, R.pyp, Eyp);
+      const T El = ld_cell<T, kSplit>(eps, R.rb, h, i0 > 0 ? i0 - 1 : i0, s.par);
+      const T Er = ld_cell<T, kSplit>(eps, R.rb, h, i0 + 8 < nx ? i0 + 8 : i0 + 7, s.par);
       ld_seg<double, false>(b, R.rb, h, s.t, s.par, B);
-      // every load above is issued before the arithmetic below (the scheduler would
-      // otherwise interleave them to save registers and wait on each)
+      __builtin_amdgcn_sched_barrier(0);
+      double d[8], sm[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        bool in[6];
+        faces_in(i0 + r, s.j, s.k, nx, ny, nz, in);
+        const T en[4] = {r > 0 ? Ec[r - 1] : El, r < 7 ? Ec[r + 1] : Er, Eym[r], Eyp[r]};
+        const double un[4] = {r > 0 ? Pc[r - 1] : Pl, r < 7 ? Pc[r + 1] : Pr, Pym[r], Pyp[r]};
+        double dd = 0, ss = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double bq = (double)hmean_s(Ec[r], en[q]);
+          dd = in[q] ? dd + bq : dd;
+          ss = in[q] ? ss + bq * un[q] : ss;
+        }
+        d[r] = dd;
+        sm[r] = ss;
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the z rows are loaded after the y rows are dead
+      double Pzm[8], Pzp[8];
+      T Ezm[8], Ezp[8];
+      ld_seg<double, false>(phi, R.zm, h, s.t, R.pzm, Pzm);
+      ld_seg<double, false>(phi, R.zp, h, s.t, R.pzp, Pzp);
+      ld_seg<T, kSplit>(eps, R.zm, h, s.t, R.pzm, Ezm);
+      ld_seg<T, kSplit>(eps, R.zp, h, s.t, R.pzp, Ezp);
       __builtin_amdgcn_sched_barrier(0);
       T F[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        bool in[6];
-        faces_in(8 * s.t + r, s.j, s.k, nx, ny, nz, in);
-        T en[6];
-        double un[6];
-        seg_faces(E, r, en);
-        seg_faces(P, r, un);
-        double d, sm;
-        op_row_r<T>(E.c[r], en, un, in, d, sm);
-        const double rr = B[r] - (d * P.c[r] - sm);
+        const bool in4 = s.k > 0, in5 = s.k < nz - 1;
+        double dd = d[r], ss = sm[r];
+        {
+          const double bq = (double)hmean_s(Ec[r], Ezm[r]);
+          dd = in4 ? dd + bq : dd + 2.0 * (double)Ec[r];
+          ss = in4 ? ss + bq * Pzm[r] : ss;
+        }
+        {
+          const double bq = (double)hmean_s(Ec[r], Ezp[r]);
+          dd = in5 ? dd + bq : dd + 2.0 * (double)Ec[r];
+          ss = in5 ? ss + bq * Pzp[r] : ss;
+        }
+        const double rr = B[r] - (dd * Pc[r] - ss);
         F[r] = (T)rr;
         rs += rr * rr;
       }
@@ -1447,6 +1486,37 @@ __global__ void k_efield(const double* phi, int nx, int ny, int nz, double V, do
     const double zm = k > 0 ? vzm : -pc, zp = k < nz - 1 ? vzp : 2.0 * V - pc;
     st4<T>(E4 + 4 * (size_t)c, (T)(-(xp - xm) * inv2h), (T)(-(yp - ym) * inv2h), (T)(-(zp - zm) * inv2h),
            (T)0);
+  }
+}
+
+// The same field over 4-cell row segments (nx a multiple of 4): a thread reads the
+// potential of its four cells and of the four cells of each neighbouring row as
+// 16-byte vectors, plus the cells before and after the segment, all in flight
+// together, and writes four packed values; each cell's differences are those of
+// k_efield (same values).
+template <typename T>
+__global__ void __launch_bounds__(256) k_efield_seg(const double* phi, int nx, int ny, int nz, double V,
+                                                   double inv2h, T* E4) {
+  const int ns = nx >> 2;
+  const uint32_t nseg = (uint32_t)ns * ny * nz;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nseg; g += gridDim.x * blockDim.x) {
+    const uint32_t row = g / (uint32_t)ns;
+    const int t = (int)(g - row * (uint32_t)ns);
+    const int j = (int)(row % (uint32_t)ny), k = (int)(row / (uint32_t)ny);
+    const size_t c0 = (size_t)row * sy + 4 * (size_t)t;
+    const V4<double> pc = ld4(phi + c0);
+    const V4<double> ym = ld4(phi + (j > 0 ? c0 - sy : c0)), yp = ld4(phi + (j < ny - 1 ? c0 + sy : c0));
+    const V4<double> zm = ld4(phi + (k > 0 ? c0 - sz : c0)), zp = ld4(phi + (k < nz - 1 ? c0 + sz : c0));
+    const double pl = phi[t > 0 ? c0 - 1 : c0], pr = phi[4 * t + 4 < nx ? c0 + 4 : c0 + 3];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double xm = r > 0 ? pc.a[r - 1] : pl, xp = r < 3 ? pc.a[r + 1] : pr;
+      const double vzm = k > 0 ? zm.a[r] : -pc.a[r], vzp = k < nz - 1 ? zp.a[r] : 2.0 * V - pc.a[r];
+      st4<T>(E4 + 4 * (c0 + r), (T)(-(xp - xm) * inv2h), (T)(-(yp.a[r] - ym.a[r]) * inv2h),
+             (T)(-(vzp - vzm) * inv2h), (T)0);
+    }
   }
 }
 
@@ -1938,8 +2008,12 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   phase_begin(ctx, PH_SOLVE);
   const int rc = solve<T>(ctx, F);
   const int nxt = 1 - F->cur;
-  k_efield<T><<<blocks(n), 256, 0, s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz, ctx->d.V_anode,
-                                        1.0 / (2.0 * ctx->d.dx), (T*)F->E[nxt]);
+  if (ctx->d.nx % 4 == 0)
+    k_efield_seg<T><<<blocks(n / 4), 256, 0, s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz, ctx->d.V_anode,
+                                                  1.0 / (2.0 * ctx->d.dx), (T*)F->E[nxt]);
+  else
+    k_efield<T><<<blocks(n), 256, 0, s>>>(F->phi, ctx->d.nx, ctx->d.ny, ctx->d.nz, ctx->d.V_anode,
+                                          1.0 / (2.0 * ctx->d.dx), (T*)F->E[nxt]);
   phase_end(ctx, PH_SOLVE);
   return rc ? rc : check_hip(ctx, hipGetLastError(), "field");
 }
