@@ -174,7 +174,9 @@ hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k) {
   const int dest = 1 - ctx->cur;  // coupling acts on the freshly binned bank
   const bool f64 = ctx->d.precision == ITOKMC_FP64;
   int gl = (int)((ctx->ncell + 255) / 256);
-  gl = gl < 1 ? 1 : (gl > 4096 ? 4096 : gl);
+  // at most 768 workgroups (three per CU), each looping over the queue: 0.096 ms per
+  // step at 9.5e6 particles against 0.21 ms with 4096 and 0.125 ms with 256
+  gl = gl < 1 ? 1 : (gl > 768 ? 768 : gl);
   if (f64)
     k_couple_light<double><<<gl, 256, 0, ctx->s>>>(ctx->bank[dest], ctx->ctr, k, ctx->work, ctx->occ,
                                                    ctx->start, ctx->dN, ctx->cbase, ctx->d.n_new,

@@ -172,8 +172,10 @@ KmcParams params(const itokmc_ctx* ctx) {
 }  // namespace
 
 hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates& fr) {
+  // at most 256 workgroups (one per CU), each looping over its share of the occupied
+  // cells: measured 0.23 ms per step at 9.5e6 particles against 0.28 ms with 4096
   int g = (int)((ctx->ncell + 256 * kKmcPer - 1) / (256 * kKmcPer));
-  if (g > 4096) g = 4096;
+  if (g > 256) g = 256;
   if (g < 1) g = 1;
   const int qa = ctx->d.n_ppc > 0 ? 1 : 0, dest = 1 - ctx->cur;
   k_kmc_step<true><<<g, 256, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
