@@ -339,10 +339,12 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
   }
 }
 
-// (at least 7 waves per SIMD: 72 VGPRs, no spills; 0.684 against 0.704 ms at 9.5e6
-// particles with the compiler's 75 VGPRs and 6 waves; 8 waves spill and are slower)
+// Single precision: at least 7 waves per SIMD (72 VGPRs, no spills; 0.684 against
+// 0.704 ms at 9.5e6 particles with the compiler's 75 VGPRs and 6 waves; 8 waves spill and
+// are slower).  Double precision keeps the compiler's choice (a 72-VGPR bound spills).
+template <typename T> constexpr int kDepMinWaves = sizeof(T) == 4 ? 7 : 1;
 template <typename T, int L2>
-__global__ void __launch_bounds__(256, 7) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
+__global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
                                                           StepConst K, const void* E4, Coef co,
                                                           int mode, typename DepAcc<T>::S* sig,
                                                           typename DepAcc<T>::S* ne, uint32_t chunk) {
