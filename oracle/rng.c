@@ -12,10 +12,9 @@
  *   - the Box-Muller transform (Box and Muller, 1958);
  *   - Poisson deviates by sequential CDF inversion for small means and by the
  *     transformed-rejection method PTRS of Hormann (1993) for means >= 10.
- * Pins: statistical tests (uniformity, normality, Poisson pmf) and bit agreement
- * with the independent GPU implementation.  Published known-answer vectors for
- * Philox are not available here, so the generator words are "parity unpinned"
- * against a third source.
+ * Pins: statistical tests (uniformity, normality, Poisson pmf); the generator words
+ * against a third implementation, PyTorch's header-only CPU Philox engine, compiled
+ * on the host by the tests (every counter and key word, 206 blocks).
  */
 #include "or_internal.h"
 #include <math.h>
