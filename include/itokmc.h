@@ -57,7 +57,17 @@ enum {
   ITOKMC_Q_CIC_DENSITY = 4,/* double per cell: electron density (m^-3), CIC           */
   ITOKMC_Q_PHI = 5,        /* double per cell: potential (V), field mode POISSON      */
   ITOKMC_Q_EX = 6, ITOKMC_Q_EY = 7, ITOKMC_Q_EZ = 8, /* double per cell: E (V/m)     */
-  ITOKMC_Q_FIRES = 9       /* uint32 per cell x 3: reaction fires of the last step    */
+  ITOKMC_Q_FIRES = 9,      /* uint32 per cell x 3: reaction fires of the last step    */
+  ITOKMC_Q_RHO = 10        /* double per cell: space charge e((n+ - n-)/dV - n_e) with
+                              n_e the CIC density of the current particles (C/m^3)   */
+};
+/* itokmc_diag.overflow flags (any set flag makes itokmc_diagnostics return ECAPACITY) */
+enum {
+  ITOKMC_OVF_PARTICLES = 1, /* a particle bank was full: particles that did not fit
+                               were dropped                                         */
+  ITOKMC_OVF_MERGE = 2      /* a cell held more particles than the largest merge
+                               staging (1536 in FP32, 1024 in FP64): it was left
+                               unmerged (merge_skipped counts such cells)            */
 };
 
 typedef struct itokmc_ctx itokmc_ctx;
@@ -133,19 +143,39 @@ typedef struct {
   uint32_t pad2;
 } itokmc_diag;
 
-/* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid). */
+/* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid).
+ * Host-only: no device call.  The arena holds two particle banks of max_particles
+ * (structure of arrays), the per-cell arrays and, in POISSON mode, the multigrid
+ * levels (section "Computer implementation"). */
 size_t itokmc_arena_bytes(const itokmc_grid_desc* desc);
 
-/* Create a context.  arena: device pointer of at least itokmc_arena_bytes(desc)
+/* Create a context for one realization on a uniform grid with planar electrodes
+ * (the paper's problem statement, eq. ito_poisson, on the grid of section "Computer
+ * implementation").  arena: device pointer of at least itokmc_arena_bytes(desc)
  * bytes, 256-byte aligned, owned by the caller.  stream: hipStream_t (may be NULL).
- * Errors: EINVAL (bad descriptor), ENOMEM (arena too small), EHIP. */
+ * The context starts with no particles, zero ion counts and step 0.
+ * Errors: EINVAL (bad descriptor or null arena), ENOMEM (arena too small), EHIP. */
 int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena,
                      size_t arena_bytes, void* stream);
 
-/* Set the coefficient set (copied).  EINVAL on NaN or negative D/mobility. */
+/* Set the coefficient set (copied): the field-dependent mobility, diffusion and rate
+ * coefficients of the local field approximation (section "Particle transport", the
+ * rates k_r of section "Kinetic Monte Carlo") and the photon absorption lengths
+ * (eq. photon_transport).  EINVAL on a non-finite or negative coefficient (the
+ * previous set stays in force). */
 int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* coeffs);
+/* The same validation without a context (host-only, no device call): ITOKMC_OK or
+ * ITOKMC_EINVAL. */
+int itokmc_check_coefficients(const itokmc_coeffs* coeffs);
 
-/* Seed particles (appends to the current state; step counter unchanged). */
+/* Seed particles (appends to the current state; step counter unchanged).  GAUSSIAN:
+ * n0 weight-1 electrons at centre + sigma N(0,1)^3 (the initial electrons of the
+ * paper's streamer runs, section "Simulation conditions"; draws outside the domain are
+ * discarded).  NEUTRAL: per cell a Poisson number of electron-ion pairs of mean
+ * n(x_c) dV, the electrons made by the coupling rule of eq. w (weights N div M,
+ * remainder on the first, uniform in the cell) and as many positive ions.
+ * Enqueued on the context's stream.  Errors: EINVAL (sigma <= 0, unknown kind); a full
+ * bank drops the rest and is reported as ECAPACITY by itokmc_diagnostics. */
 int itokmc_seed_particles(itokmc_ctx* ctx, const itokmc_seed_desc* seed);
 
 /* Advance nsteps full steps of length dt (final algorithm, steps 1-8).  Returns
@@ -160,26 +190,45 @@ int itokmc_transport(itokmc_ctx* ctx, double dt);
 int itokmc_react(itokmc_ctx* ctx, double dt);
 
 /* Write a per-cell quantity (selector ITOKMC_Q_*) to the device buffer dev_out of
- * ncell (x3 for FIRES) elements of the stated type.  NGP weights and CIC density are
- * computed from the current particles. */
+ * ncell (x3 for FIRES) elements of the stated type, enqueued on the context's stream.
+ * NGP weights (the reaction network's electron count of section "KMC-particle
+ * coupling"), the CIC density and RHO (section "Charge deposition & interpolation",
+ * cell-centred tent weights, clouds folded into the wall cells) are computed from the
+ * current particles; PHI and E are the last field solve's (eq. poisson_simp).
+ * dev_out is owned by the caller.  Errors: EINVAL (unknown selector; PHI/E in UNIFORM
+ * mode), EHIP. */
 int itokmc_deposit(itokmc_ctx* ctx, int what, void* dev_out);
 
-/* Reductions and tallies; synchronises the stream. */
+/* Reductions and tallies (the integer charge sum(n+ - n_e - n-) in units of e is
+ * conserved by every reaction of the paper's air table, so it changes only by
+ * outflow); synchronises the stream.  Returns ECAPACITY when an overflow flag
+ * (ITOKMC_OVF_*) is set, after filling host_out; EHIP for an earlier asynchronous
+ * failure. */
 int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* host_out);
 
-/* Particle state exchange with host memory (checkpoint, parity resynchronisation).
- * get: *n receives the count; arrays (each may be NULL) must hold n entries
- * (offsets: 3 n doubles, x y z interleaved).  Call with all arrays NULL to query n.
- * set: replaces all particles; w must be >= 1, offsets in [0,1), cells valid. */
+/* Particle state exchange with host memory (checkpoint, parity resynchronisation):
+ * the computational particles of section "Ito diffusion", each a cell, an offset in
+ * [0,1)^3 inside it, an integer weight (physical electrons) and a 64-bit id.
+ * get: *n receives the count of live particles; arrays (each may be NULL) must hold n
+ * entries (offsets: 3 n doubles, x y z interleaved).  Call with all arrays NULL to
+ * query n.  set: replaces all particles (a host copy, synchronous); w must be >= 1,
+ * offsets in [0,1), cells valid (EINVAL otherwise, state unchanged); ECAPACITY if n
+ * exceeds max_particles.  Both synchronise the stream. */
 int itokmc_get_particles(itokmc_ctx* ctx, uint64_t* n, uint32_t* cell, double* off,
                          uint32_t* w, uint64_t* id);
 int itokmc_set_particles(itokmc_ctx* ctx, uint64_t n, const uint32_t* cell,
                          const double* off, const uint32_t* w, const uint64_t* id);
-/* Per-cell counts (which = ITOKMC_Q_NPLUS, NMINUS or NGAMMA), host uint32 arrays. */
+/* Per-cell counts (which = ITOKMC_Q_NPLUS, NMINUS or NGAMMA), host uint32 arrays of
+ * ncell entries: the ion species of the air table (section "Numerical tests") as
+ * immobile counts at the cell centres, and the photons awaiting transport in the next
+ * step (final algorithm, step 6).  EINVAL for another selector.  Synchronous. */
 int itokmc_get_counts(itokmc_ctx* ctx, int which, uint32_t* host);
 int itokmc_set_counts(itokmc_ctx* ctx, int which, const uint32_t* host);
+/* Step counter k (a component of every random stream's counter). */
 int itokmc_set_step(itokmc_ctx* ctx, uint32_t step);
-/* Potential (host doubles, ncell); set_field also recomputes E. Poisson mode only. */
+/* Potential of eq. poisson_simp (host doubles, ncell, V); set_field also recomputes
+ * E = -grad phi at the cell centres.  POISSON mode only (EINVAL otherwise).
+ * Synchronous. */
 int itokmc_get_field(itokmc_ctx* ctx, double* phi);
 int itokmc_set_field(itokmc_ctx* ctx, const double* phi);
 

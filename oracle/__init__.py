@@ -84,6 +84,7 @@ def lib():
         L.or_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
         L.or_ngp_weight.argtypes = [P, P]
         L.or_cic_density.argtypes = [P, P]
+        L.or_charge_density.argtypes = [P, P]
         L.or_get_fires.argtypes = [P, P]
         L.or_get_field.argtypes = [P, P, P, P, P]
         L.or_set_field.argtypes = [P, P]
@@ -337,6 +338,11 @@ class Sim:
     def cic_density(self):
         v = np.zeros(self.ncell)
         lib().or_cic_density(self.h, _p(v))
+        return v
+
+    def charge_density(self):
+        v = np.zeros(self.ncell)
+        lib().or_charge_density(self.h, _p(v))
         return v
 
     def fires(self):

@@ -128,6 +128,8 @@ void or_diagnostics(const or_sim* s, or_diag* out);
 void or_ngp_weight(const or_sim* s, int64_t* out);
 /* CIC electron number density (m^-3) of the current particles */
 void or_cic_density(const or_sim* s, double* out);
+/* space charge (C/m^3) of the current state: e (n+ - n-) / dV - e n_e(CIC) */
+void or_charge_density(const or_sim* s, double* out);
 /* last per-cell fire counts (3 per cell) of the most recent react phase */
 void or_get_fires(const or_sim* s, int64_t* out);
 

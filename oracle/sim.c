@@ -241,6 +241,12 @@ static void charge_density(const or_sim* s, const double* xi, double* rho) {
   free(q);
 }
 
+void or_charge_density(const or_sim* s, double* out) {
+  double* xi = xi_array(s);
+  charge_density(s, xi, out);
+  free(xi);
+}
+
 static int solve_field(or_sim* s, const double* rho, const double* eps_r) {
   double rr = 0.0;
   int it = or_solve_poisson(&s->d, rho, eps_r, s->phi, s->d.poisson_rtol, 100000, &rr);

@@ -283,6 +283,12 @@ int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* c) {
   return ITOKMC_OK;
 }
 
+int itokmc_check_coefficients(const itokmc_coeffs* c) {
+  if (!c) return ITOKMC_EINVAL;
+  std::string why;
+  return check_coeffs(c, &why);
+}
+
 static int mark_unbinned(itokmc_ctx* ctx) {
   // the bin accumulator must be all zero between steps; recount before reacting
   return check_hip(ctx, hipMemsetAsync(ctx->cellacc, 0, (size_t)ctx->ncell * 8, ctx->s), "memset");
@@ -393,6 +399,7 @@ int itokmc_deposit(itokmc_ctx* ctx, int what, void* dev_out) {
     case ITOKMC_Q_NGAMMA: e = hipMemcpyAsync(dev_out, ctx->ngamma, nb * 4, hipMemcpyDeviceToDevice, ctx->s); break;
     case ITOKMC_Q_FIRES: e = launch_fires_dense(ctx, (uint32_t*)dev_out); break;
     case ITOKMC_Q_CIC_DENSITY: e = launch_cic_density(ctx, (double*)dev_out); break;
+    case ITOKMC_Q_RHO: e = launch_rho(ctx, (double*)dev_out); break;
     case ITOKMC_Q_PHI: case ITOKMC_Q_EX: case ITOKMC_Q_EY: case ITOKMC_Q_EZ:
       if (ctx->d.field_mode != ITOKMC_FIELD_POISSON)
         return set_error(ctx, ITOKMC_EINVAL, "no field in uniform mode");

@@ -162,7 +162,10 @@ __global__ void __launch_bounds__(64) k_merge_tier(Bank b, Counters* ctr, int wh
     const int r = merge_cell<T, CAP, NL>(b, ctr, which, K, c, start[c], e, base, M, n_ppc, &merged);
     if (r == 2 && lane_id() == 0) {
       if (out) out[atomicAdd(n_out, 1u)] = j;
-      else atomicAdd(&ctr->merge_skipped, 1u);
+      else {  // larger than every staging: left unmerged, reported as ECAPACITY
+        atomicAdd(&ctr->merge_skipped, 1u);
+        atomicOr(&ctr->overflow, (uint32_t)ITOKMC_OVF_MERGE);
+      }
     }
   }
   if (lane_id() == 0 && merged) atomicAdd(&ctr->merged, (unsigned long long)merged);

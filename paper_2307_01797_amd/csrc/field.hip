@@ -261,9 +261,13 @@ template <> struct NormalsF<float> {
 // Deposit accumulators.  In single precision the node sums are fixed-point integers
 // (conductivity weight mu w in units of 2^-32, electron number in units of 2^-28,
 // 64-bit), so a sum does not depend on the order of its atomic additions and the field
-// of a realization is bit-reproducible; each single-precision contribution converts
-// exactly or to within half a unit.  Ranges: 2^31 and 2^35 per node.  Double precision
-// sums doubles.
+// of a realization is bit-reproducible.  A contribution is the product of the
+// single-precision tent weight and the particle's integer weight (times the mobility
+// for the conductivity), formed in double: the integer weight is not rounded to 24
+// bits, so a node that receives all of a particle's charge receives it exactly (a
+// quasi-neutral plasma of heavy particles would otherwise carry a spurious charge of
+// 2^-24 of its density).  Ranges: 2^31 and 2^35 per node.  Double precision sums
+// doubles.
 template <typename T> struct DepAcc;
 template <> struct DepAcc<double> {
   using S = double;
@@ -274,8 +278,8 @@ template <> struct DepAcc<double> {
 };
 template <> struct DepAcc<float> {
   using S = unsigned long long;
-  __device__ static S enc0(float a) { return (S)rintf(a * 0x1p32f); }
-  __device__ static S enc1(float a) { return (S)rintf(a * 0x1p28f); }
+  __device__ static S enc0(double a) { return (S)rint(a * 0x1p32); }
+  __device__ static S enc1(double a) { return (S)rint(a * 0x1p28); }
   __device__ static double dec0(S v) { return (double)v * 0x1p-32; }
   __device__ static double dec1(S v) { return (double)v * 0x1p-28; }
 };
@@ -298,8 +302,8 @@ template <typename T> struct DepTbl { static constexpr int log2n = 10; };
 
 template <typename T, int L2>
 __device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v0,
-                                        typename DepAcc<T>::S* v1, uint32_t node, uint32_t h, T a, T b,
-                                        typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
+                                        typename DepAcc<T>::S* v1, uint32_t node, uint32_t h, double a,
+                                        double b, typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
   using A = DepAcc<T>;
   constexpr uint32_t mask = (1u << L2) - 1u;
   for (int probe = 0; probe < kDepProbes; ++probe) {
@@ -309,20 +313,20 @@ __device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v
       k = prev == kEmptyKey ? node : prev;
     }
     if (k == node) {
-      if (a != (T)0) atomicAdd(&v0[h], A::enc0(a));
-      if (b != (T)0) atomicAdd(&v1[h], A::enc1(b));
+      if (a != 0.0) atomicAdd(&v0[h], A::enc0(a));
+      if (b != 0.0) atomicAdd(&v1[h], A::enc1(b));
       return;
     }
     h = (h + 1u) & mask;
   }
-  if (a != (T)0) atomicAdd(&g0[node], A::enc0(a));
-  if (b != (T)0) atomicAdd(&g1[node], A::enc1(b));
+  if (a != 0.0) atomicAdd(&g0[node], A::enc0(a));
+  if (b != 0.0) atomicAdd(&g1[node], A::enc1(b));
 }
 
 template <typename T, int L2>
 __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v0,
                                         typename DepAcc<T>::S* v1, const StepConst& K, int i0,
-                                        int j0, int k0, T fx, T fy, T fz, T qa, T qb,
+                                        int j0, int k0, T fx, T fy, T fz, double qa, double qb,
                                         typename DepAcc<T>::S* g0, typename DepAcc<T>::S* g1) {
 #pragma unroll
   for (int cc = 0; cc < 8; ++cc) {
@@ -335,7 +339,7 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
     // table slot: the row hashed, x kept in order, so that a row's nodes sit in
     // consecutive slots and the flush's atomics of neighbouring lanes share lines
     const uint32_t h = ((uint32_t)ii + ((row * 2654435761u) >> (32 - L2))) & ((1u << L2) - 1u);
-    tbl_add<T, L2>(keys, v0, v1, node, h, qa * wt, qb * wt, g0, g1);
+    tbl_add<T, L2>(keys, v0, v1, node, h, qa * (double)wt, qb * (double)wt, g0, g1);
   }
 }
 
@@ -377,14 +381,14 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
       tent_axis<T>(cj, o[1], K.ny, j0, fy);
       tent_axis<T>(ck, o[2], K.nz, k0, fz);
       if (mode == 0) {
-        tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
+        tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, 0.0, (double)w, sig, ne);
         continue;
       }
       T e[3];
       cic_get3<T>(ctp<T>(E4), K, i0, j0, k0, fx, fy, fz, e);
       const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
       const T mu = Mob<T>::mu(co, Em);
-      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, mu * (T)w, (T)0, sig, ne);
+      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (double)mu * (double)w, 0.0, sig, ne);
       const uint64_t id = a.id[i];
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
       T nr[3];
@@ -392,7 +396,7 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
       tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
       tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
       tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
-      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (T)0, (T)w, sig, ne);
+      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, 0.0, (double)w, sig, ne);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
@@ -2130,6 +2134,24 @@ hipError_t launch_cic_density(itokmc_ctx* ctx, double* out) {
     k_cic_density<double><<<2048, 256, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, inv_dV, out);
   else
     k_cic_density<float><<<2048, 256, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, inv_dV, out);
+  return hipGetLastError();
+}
+
+// Space charge of the current state (deposit query): e ((n+ - n-) / dV - n_e) with n_e
+// the CIC density written into out by launch_cic_density.
+namespace {
+__global__ void k_rho_from_density(double* out, const uint32_t* np, const uint32_t* nm, uint32_t n,
+                                   double inv_dV) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = kE * (((double)np[i] - (double)nm[i]) * inv_dV - out[i]);
+}
+}  // namespace
+
+hipError_t launch_rho(itokmc_ctx* ctx, double* out) {
+  hipError_t e = launch_cic_density(ctx, out);
+  if (e != hipSuccess) return e;
+  const double inv_dV = 1.0 / (ctx->d.dx * ctx->d.dx * ctx->d.dx);
+  k_rho_from_density<<<blocks(ctx->ncell), 256, 0, ctx->s>>>(out, ctx->nplus, ctx->nminus, ctx->ncell, inv_dV);
   return hipGetLastError();
 }
 

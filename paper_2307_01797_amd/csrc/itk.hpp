@@ -34,7 +34,8 @@ struct Bank {
 // Device-resident counters and tallies (one 256-byte block of the arena).
 struct Counters {
   uint32_t n[2];          // particles per bank (including dead slots, w == 0)
-  uint32_t overflow;      // bit 0: particle capacity, bit 1: merge scratch
+  uint32_t overflow;      // ITOKMC_OVF_*: bit 0 particle capacity, bit 1 a cell too
+                          // large for every merge staging (left unmerged)
   uint32_t n_occ;         // occupied cells after binning
   uint32_t n_work;        // cells needing coupling / merge
   uint32_t sorted;        // particles placed by the last counting sort
@@ -184,4 +185,5 @@ int field_get_phi(itokmc_ctx* ctx, double* host);
 int field_set_phi(itokmc_ctx* ctx, const double* host);
 int field_deposit(itokmc_ctx* ctx, int what, void* dev_out);
 hipError_t launch_cic_density(itokmc_ctx* ctx, double* out);
+hipError_t launch_rho(itokmc_ctx* ctx, double* out);
 }  // namespace itk

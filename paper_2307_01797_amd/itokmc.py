@@ -19,9 +19,12 @@ FP32, FP64 = 0, 1
 FIELD_UNIFORM, FIELD_POISSON = 0, 1
 KMC_HYBRID, KMC_PURE_TAU = 0, 1
 SEED_GAUSSIAN, SEED_NEUTRAL = 0, 1
-Q_NGP_WEIGHT, Q_NPLUS, Q_NMINUS, Q_NGAMMA, Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ, Q_FIRES = range(10)
+(Q_NGP_WEIGHT, Q_NPLUS, Q_NMINUS, Q_NGAMMA, Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ, Q_FIRES,
+ Q_RHO) = range(11)
+OVF_PARTICLES, OVF_MERGE = 1, 2
 
 EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
+           "itokmc_check_coefficients",
            "itokmc_seed_particles", "itokmc_step", "itokmc_transport", "itokmc_react",
            "itokmc_deposit", "itokmc_diagnostics", "itokmc_get_particles",
            "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
@@ -144,6 +147,7 @@ def lib():
         L.itokmc_init_grid.argtypes = [ctypes.POINTER(P), ctypes.POINTER(GridDesc), P,
                                        ctypes.c_size_t, P]
         L.itokmc_set_coefficients.argtypes = [P, ctypes.POINTER(Coeffs)]
+        L.itokmc_check_coefficients.argtypes = [ctypes.POINTER(Coeffs)]
         L.itokmc_seed_particles.argtypes = [P, ctypes.POINTER(SeedDesc)]
         L.itokmc_step.argtypes = [P, U32, D]
         L.itokmc_transport.argtypes = [P, D]
@@ -340,8 +344,8 @@ class Sim:
         torch = self.torch
         q = {"ngp": Q_NGP_WEIGHT, "plus": Q_NPLUS, "minus": Q_NMINUS, "gamma": Q_NGAMMA,
              "cic": Q_CIC_DENSITY, "phi": Q_PHI, "ex": Q_EX, "ey": Q_EY, "ez": Q_EZ,
-             "fires": Q_FIRES}[what]
-        if q in (Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ):
+             "fires": Q_FIRES, "rho": Q_RHO}[what]
+        if q in (Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ, Q_RHO):
             out = torch.empty(self.ncell, dtype=torch.float64, device=self.device)
         elif q == Q_FIRES:
             out = torch.empty(self.ncell * 3, dtype=torch.int32, device=self.device)

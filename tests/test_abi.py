@@ -71,3 +71,24 @@ def test_ensemble_descriptor_validation():
     h = ctypes.c_void_p()
     assert L.itokmc_ensemble_create(ctypes.byref(h), ctypes.byref(ok), None, n, None) == itokmc.EINVAL
     assert L.itokmc_ensemble_step(None, 1) == itokmc.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_coefficient_validation_on_host():
+    import math
+
+    from paper_2307_01797_amd import itokmc, workloads
+    L = itokmc.lib()
+    good = itokmc.make_coeffs(workloads.preset("streamer_64"))
+    assert L.itokmc_check_coefficients(ctypes.byref(good)) == itokmc.OK
+    for name, bad in (("D", math.nan), ("mu_a", math.inf), ("eta", -1.0), ("alpha_B", math.nan),
+                      ("mu_E0", 0.0), ("E_floor", -5.0), ("photon_l1", math.nan)):
+        c = itokmc.make_coeffs(workloads.preset("streamer_64"))
+        setattr(c, name, bad)
+        assert L.itokmc_check_coefficients(ctypes.byref(c)) == itokmc.EINVAL, name
+    # photon lengths must be ordered when photons are emitted
+    c = itokmc.make_coeffs(workloads.preset("streamer_64"))
+    c.photon_l1, c.photon_l2 = 2e-3, 30e-6
+    assert L.itokmc_check_coefficients(ctypes.byref(c)) == itokmc.EINVAL
+    assert L.itokmc_check_coefficients(None) == itokmc.EINVAL
+    assert L.itokmc_set_coefficients(None, ctypes.byref(good)) == itokmc.EINVAL

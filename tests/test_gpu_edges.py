@@ -188,3 +188,88 @@ def test_ensemble_empty_and_ragged(itk):
     i2, c2, o2, w2 = by_id(i2, c2, o2, w2)
     assert np.array_equal(i1, i2) and np.array_equal(c1, c2) and np.array_equal(w1, w2)
     assert np.array_equal(o1, o2)
+
+
+def test_rho_selector_matches_oracle(itk, orc):
+    """ITOKMC_Q_RHO: e (n+ - n-)/dV - e n_e(CIC) of the current state, against the
+    oracle's charge density of the same particles and ion counts."""
+    cfg = workloads.preset("streamer_64", grid=(20, 18, 24), dx=1e-3 / 64)
+    rng = np.random.default_rng(12)
+    n = 5000
+    xi = rng.random((n, 3)) * np.array(cfg["grid"])
+    w = rng.integers(1, 3000, size=n).astype(np.uint64)
+    ids = np.arange(n, dtype=np.uint64) * np.uint64(3) + np.uint64(11)
+    ncell = int(np.prod(cfg["grid"]))
+    npl = rng.integers(0, 4000, ncell)
+    nmi = rng.integers(0, 300, ncell)
+    cell, off = xi_to_cell_off(xi, cfg["grid"])
+    o = orc.Sim(cfg)
+    o.set_particles(xi, w, ids)
+    o.set_counts("plus", npl)
+    o.set_counts("minus", nmi)
+    want = o.charge_density()
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        g = itk.Sim(cfg, precision=prec, max_particles=2 * n)
+        g.set_particles(cell, off, w.astype(np.uint32), ids)
+        g.set_counts("plus", npl.astype(np.uint32))
+        g.set_counts("minus", nmi.astype(np.uint32))
+        got = g.deposit("rho")
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= tol * scale, (prec, np.abs(got - want).max() / scale)
+        g.close()
+
+
+def test_solver_nonconvergence_reported(itk):
+    """A field solve limited to one multigrid cycle misses the 1e-10 tolerance: the
+    step returns ENOCONV and the state stays usable (the best potential is kept)."""
+    cfg = workloads.preset("streamer_64", grid=(32, 32, 32), dx=1e-3 / 32, gmg_max_cycles=1)
+    g = itk.Sim(cfg, max_particles=500_000)
+    g.seed()
+    rc = g.step_rc(1)
+    assert rc == itk.ENOCONV, rc
+    d = g.diagnostics(check=False)
+    assert d["solver_cycles"] == 1 and d["solver_relres"] > 1e-10
+    phi = g.field()
+    assert np.all(np.isfinite(phi))
+    g.close()
+
+
+def test_nan_coefficients_rejected(itk):
+    """set_coefficients keeps the previous set and returns EINVAL for a NaN."""
+    import ctypes
+    import math
+    cfg = workloads.preset("avalanche_32", seed_n0=500)
+    g = itk.Sim(cfg, max_particles=10_000)
+    c = itk.make_coeffs(cfg)
+    c.D = math.nan
+    assert itk.lib().itokmc_set_coefficients(g.h, ctypes.byref(c)) == itk.EINVAL
+    g.seed()
+    g.step(2)                      # the earlier coefficients are still in force
+    assert g.diagnostics()["step"] == 2
+    g.close()
+
+
+def test_oversized_cell_reported_as_capacity(itk):
+    """A cell holding more particles than the largest merge staging is left unmerged
+    and flagged (ITOKMC_OVF_MERGE): diagnostics returns ECAPACITY and counts the cell;
+    the other cells are merged as usual."""
+    cfg = workloads.preset("avalanche_32", grid=(8, 8, 8), n_ppc=32, E=(0.0, 0.0, 1.0),
+                           coeffs=dict(alpha_A=0.0, eta=0.0, D=0.0), precision="fp32")
+    rng = np.random.default_rng(3)
+    big, small = 2000, 100
+    cell = np.concatenate([np.full(big, 100), np.full(small, 300)]).astype(np.uint32)
+    off = rng.random((big + small, 3)) * 0.98 + 0.01
+    w = np.ones(big + small, dtype=np.uint32)
+    ids = np.arange(big + small, dtype=np.uint64) + np.uint64(1)
+    g = itk.Sim(cfg, max_particles=20_000)
+    g.set_particles(cell, off, w, ids)
+    g.step(1)
+    with pytest.raises(itk.ItokmcError) as err:
+        g.diagnostics()
+    assert err.value.code == itk.ECAPACITY
+    d = g.diagnostics(check=False)
+    assert d["overflow"] & itk.OVF_MERGE and d["merge_skipped"] == 1
+    c2, _, w2, _ = g.particles()
+    assert np.sum(c2 == 100) == big and np.sum(c2 == 300) == 32
+    assert int(w2.sum()) == big + small
+    g.close()

@@ -73,3 +73,33 @@ def test_two_layer_dielectric(orc):
     z = (np.arange(n) + 0.5) * h
     exact = np.where(z < L / 2, El * z, El * L / 2 + Eh * (z - L / 2))
     assert np.allclose(phi.reshape(n, 4, 4)[:, 0, 0], exact, rtol=1e-9)
+
+
+def test_charge_density_sums_to_integer_charge(orc):
+    # CIC folds clouds into the wall cells, so sum(rho) dV is e times the integer charge
+    import numpy as np
+    from paper_2307_01797_amd import workloads
+    cfg = workloads.preset("streamer_64", grid=(12, 10, 14), dx=1e-3 / 64)
+    rng = np.random.default_rng(4)
+    sim = orc.Sim(cfg)
+    n = 3000
+    xi = rng.random((n, 3)) * np.array(cfg["grid"])
+    xi[:50] = rng.random((50, 3)) * 0.4          # clouds reaching past the walls
+    w = rng.integers(1, 1000, size=n).astype(np.uint64)
+    sim.set_particles(xi, w, np.arange(n, dtype=np.uint64) + 7)
+    ncell = int(np.prod(cfg["grid"]))
+    sim.set_counts("plus", rng.integers(0, 500, ncell))
+    sim.set_counts("minus", rng.integers(0, 50, ncell))
+    rho = sim.charge_density()
+    dV = cfg["dx"] ** 3
+    q = sim.diagnostics()["charge"]
+    assert q == sim.counts("plus").sum() - int(w.sum()) - sim.counts("minus").sum()
+    assert rho.sum() * dV == pytest.approx(1.602176634e-19 * q, rel=1e-12)
+    # a single electron at a cell centre deposits all of its charge in that cell
+    sim.set_particles(np.array([[3.5, 4.5, 5.5]]), np.array([9], dtype=np.uint64), np.array([1], dtype=np.uint64))
+    sim.set_counts("plus", np.zeros(ncell, dtype=np.int64))
+    sim.set_counts("minus", np.zeros(ncell, dtype=np.int64))
+    rho = sim.charge_density()
+    c = 3 + 12 * (4 + 10 * 5)
+    assert rho[c] == pytest.approx(-9 * 1.602176634e-19 / dV, rel=1e-15)
+    assert np.count_nonzero(rho) == 1
