@@ -85,6 +85,13 @@ def lib():
         L.or_ngp_weight.argtypes = [P, P]
         L.or_cic_density.argtypes = [P, P]
         L.or_charge_density.argtypes = [P, P]
+        L.or_poisson_relres.restype = ctypes.c_double
+        L.or_poisson_relres.argtypes = [ctypes.POINTER(Desc), P, P, P]
+        L.or_semi_implicit_residual.restype = ctypes.c_double
+        L.or_semi_implicit_residual.argtypes = [P, ctypes.c_double, P]
+        L.or_push_with_fields.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Coeffs),
+                                          ctypes.c_uint64, P, P, ctypes.c_uint32,
+                                          ctypes.c_double] + [P] * 7
         L.or_get_fires.argtypes = [P, P]
         L.or_get_field.argtypes = [P, P, P, P, P]
         L.or_set_field.argtypes = [P, P]
@@ -345,6 +352,11 @@ class Sim:
         lib().or_charge_density(self.h, _p(v))
         return v
 
+    def semi_implicit_residual(self, dt, phi):
+        """||b - A phi|| / ||b|| in the system this state's transport would solve."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        return lib().or_semi_implicit_residual(self.h, float(dt), _p(phi))
+
     def fires(self):
         v = np.zeros((self.ncell, 3), dtype=np.int64)
         lib().or_get_fires(self.h, _p(v))
@@ -378,3 +390,23 @@ def photon_sample(cfg, cell, slot, step):
                                    ctypes.c_void_p, ctypes.c_void_p]
     L.or_photon_sample(ctypes.byref(d), ctypes.byref(c), cell, slot, step, _p(y0), _p(dr), _p(r))
     return y0, dr, float(r[0])
+
+
+def poisson_relres(cfg, rho, eps_r, phi):
+    d = make_desc(cfg)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (rho, eps_r, phi)]
+    return lib().or_poisson_relres(ctypes.byref(d), *[_p(x) for x in a])
+
+
+def push_with_fields(cfg, xi, ids, step, dt, Ek, Ek1):
+    """Semi-implicit update of particles xi (grid units) with given cell-centred fields
+    Ek = (Ex, Ey, Ez) at step k and Ek1 at step k+1."""
+    d = make_desc(cfg)
+    c = make_coeffs(cfg)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    F = [np.ascontiguousarray(a, dtype=np.float64) for a in list(Ek) + list(Ek1)]
+    out = np.zeros_like(xi)
+    lib().or_push_with_fields(ctypes.byref(d), ctypes.byref(c), xi.shape[0], _p(xi), _p(ids),
+                              step, float(dt), *[_p(a) for a in F], _p(out))
+    return out

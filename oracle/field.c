@@ -98,6 +98,27 @@ int or_solve_poisson(const or_desc* d, const double* rho, const double* eps_r, d
   return it;
 }
 
+/* ||b - A phi||_2 / ||b||_2 of the system or_solve_poisson solves (same b, same A). */
+double or_poisson_relres(const or_desc* d, const double* rho, const double* eps_r,
+                         const double* phi) {
+  int64_t n = (int64_t)d->nx * d->ny * d->nz;
+  double h2 = d->dx * d->dx;
+  double* Ap = (double*)malloc(sizeof(double) * (size_t)n);
+  apply_A(d, eps_r, phi, Ap);
+  double bb = 0.0, rr = 0.0;
+  for (int k = 0; k < d->nz; ++k)
+    for (int j = 0; j < d->ny; ++j)
+      for (int i = 0; i < d->nx; ++i) {
+        int64_t c = IDX(d, i, j, k);
+        double b = h2 * rho[c] / OR_EPS0;
+        if (k == d->nz - 1) b += 2.0 * eps_r[c] * d->V_anode;
+        bb += b * b;
+        rr += (b - Ap[c]) * (b - Ap[c]);
+      }
+  free(Ap);
+  return bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+}
+
 void or_efield(const or_desc* d, const double* phi, double* Ex, double* Ey, double* Ez) {
   int nx = d->nx, ny = d->ny, nz = d->nz;
   double inv2h = 1.0 / (2.0 * d->dx);

@@ -146,6 +146,18 @@ void or_get_field(const or_sim* s, double* phi, double* Ex, double* Ey, double* 
 void or_set_field(or_sim* s, const double* phi);
 /* Set the cell-centred field used by the next transport (as E^k) and reactions. */
 void or_set_efield(or_sim* s, const double* Ex, const double* Ey, const double* Ez);
+/* ||b - A phi|| / ||b|| of the system or_solve_poisson solves. */
+double or_poisson_relres(const or_desc* d, const double* rho, const double* eps_r,
+                         const double* phi);
+/* Relative residual of phi in the semi-implicit system (eqs. conductivity and
+ * poisson_simp) built from the simulation's particles X^k, ion counts, field E^k and
+ * step k, as or_transport builds it; the state is unchanged. */
+double or_semi_implicit_residual(const or_sim* s, double dt, const double* phi);
+/* Semi-implicit update of n particles with given cell-centred E^k and E^{k+1}. */
+void or_push_with_fields(const or_desc* d, const or_coeffs* c, uint64_t n, const double* xi,
+                         const uint64_t* id, uint32_t step, double dt, const double* Ekx,
+                         const double* Eky, const double* Ekz, const double* E1x,
+                         const double* E1y, const double* E1z, double* out);
 
 /* CIC helpers on an arbitrary point set (grid units). */
 void or_cic_deposit(const or_desc* d, uint64_t n, const double* xi, const double* q,

@@ -370,6 +370,69 @@ int or_transport(or_sim* s, double dt) {
   return 0;
 }
 
+/* Relative residual of a potential phi in the semi-implicit system built from the
+ * simulation's state (particles X^k, ion counts, field E^k as set by or_set_efield,
+ * step counter k): steps 1-3 of or_transport (sigma^k of eq. conductivity at X^k, the
+ * diffusive advance X_dagger, rho_dagger, eq. poisson_simp) without solving.  The state
+ * is not changed. */
+double or_semi_implicit_residual(const or_sim* s, double dt, const double* phi) {
+  const or_desc* d = &s->d;
+  const or_coeffs* c = &s->c;
+  uint64_t np = s->np;
+  double dV = d->dx * d->dx * d->dx;
+  double diff = sqrt(2.0 * c->D * dt) / d->dx;
+  double* xk = xi_array(s);
+  double* ex = (double*)malloc(sizeof(double) * (np ? np : 1));
+  double* ey = (double*)malloc(sizeof(double) * (np ? np : 1));
+  double* ez = (double*)malloc(sizeof(double) * (np ? np : 1));
+  double* q = (double*)malloc(sizeof(double) * (np ? np : 1));
+  or_cic_interp(d, s->Ex, np, xk, ex);
+  or_cic_interp(d, s->Ey, np, xk, ey);
+  or_cic_interp(d, s->Ez, np, xk, ez);
+  for (uint64_t i = 0; i < np; ++i) {
+    double mu = or_mobility(c, sqrt(ex[i] * ex[i] + ey[i] * ey[i] + ez[i] * ez[i]));
+    q[i] = OR_E_CHARGE * mu * (double)s->p[i].w / dV;
+  }
+  double* sigma = (double*)calloc((size_t)s->ncell, sizeof(double));
+  or_cic_deposit(d, np, xk, q, sigma);
+  double* xd = (double*)malloc(sizeof(double) * 3 * (np ? np : 1));
+  for (uint64_t i = 0; i < np; ++i) {
+    double n[3];
+    or_normals3(s->p[i].id, s->step, d->seed, d->realization, n);
+    for (int a = 0; a < 3; ++a) xd[3 * i + a] = xk[3 * i + a] + diff * n[a];
+  }
+  double* rho = (double*)malloc(sizeof(double) * (size_t)s->ncell);
+  double* eps = (double*)malloc(sizeof(double) * (size_t)s->ncell);
+  charge_density(s, xd, rho);
+  for (int64_t cc = 0; cc < s->ncell; ++cc) eps[cc] = 1.0 + sigma[cc] * dt / OR_EPS0;
+  double rr = or_poisson_relres(d, rho, eps, phi);
+  free(xk); free(ex); free(ey); free(ez); free(q); free(sigma); free(xd); free(rho); free(eps);
+  return rr;
+}
+
+/* The semi-implicit update of final-algorithm steps 2, 4 and 5 for n particles with
+ * given cell-centred fields E^k and E^{k+1} (three arrays each):
+ * X^{k+1} = X^k + sqrt(2 D dt) N(id, k) - mu(|E^k(X^k)|) E^{k+1}(X^k) dt (grid units). */
+void or_push_with_fields(const or_desc* d, const or_coeffs* c, uint64_t n, const double* xi,
+                         const uint64_t* id, uint32_t step, double dt, const double* Ekx,
+                         const double* Eky, const double* Ekz, const double* E1x,
+                         const double* E1y, const double* E1z, double* out) {
+  double diff = sqrt(2.0 * c->D * dt) / d->dx;
+  for (uint64_t i = 0; i < n; ++i) {
+    const double* x = xi + 3 * i;
+    double ek[3], e1[3], nrm[3];
+    or_cic_interp(d, Ekx, 1, x, &ek[0]);
+    or_cic_interp(d, Eky, 1, x, &ek[1]);
+    or_cic_interp(d, Ekz, 1, x, &ek[2]);
+    or_cic_interp(d, E1x, 1, x, &e1[0]);
+    or_cic_interp(d, E1y, 1, x, &e1[1]);
+    or_cic_interp(d, E1z, 1, x, &e1[2]);
+    double mu = or_mobility(c, sqrt(ek[0] * ek[0] + ek[1] * ek[1] + ek[2] * ek[2]));
+    or_normals3(id[i], step, d->seed, d->realization, nrm);
+    for (int a = 0; a < 3; ++a) out[3 * i + a] = (x[a] + diff * nrm[a]) + (-mu * e1[a] * dt / d->dx);
+  }
+}
+
 /* ---- photons (final algorithm step 6) ------------------------------------------ */
 
 void or_photon_sample(const or_desc* d, const or_coeffs* c, uint32_t cell, uint32_t slot,

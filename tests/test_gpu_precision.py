@@ -14,6 +14,17 @@ weights, ion counts, reaction fires).  A particle whose oracle position lies wit
 1e-5 cells of a face may be binned differently by the single-precision push (the
 decision is taken in the other precision); such tie-band particles, and the KMC of the
 cells they make differ, are counted and reported, and every other integer must agree.
+In single precision every integer difference must be certified.  The step is split:
+  * transport: the FP32 GPU and the oracle advance the same state; a particle may bin
+    into another cell only if the oracle's position lies within 1e-5 of a cell face
+    (the decision is taken in the other precision);
+  * react: the oracle reacts from the GPU's own post-transport state (particles, counts,
+    field), so every integer decision (KMC fires, products, removals, photon
+    absorption, merge groupings) has the same inputs and must agree exactly; merge
+    extents and keys are single-precision values on both sides.
+The first step at which a free-running FP32 run's integer state departs from the FP64
+oracle's is reported (a stochastic trajectory; c.f. the paper's remark that numerical
+convergence tests were not possible).
 The measured errors are printed as one JSON line (pytest -s shows it).
 """
 import json
@@ -95,12 +106,76 @@ def _errors(g, o, cfg, fires0):
     }
 
 
+def _oracle_from_gpu(orc, cfg, g):
+    o = orc.Sim(cfg)
+    cell, off, w, ids = g.particles()
+    o.set_particles(gpu_xi(cell, off, cfg["grid"]), w.astype(np.uint64), ids)
+    for k in ("plus", "minus", "gamma"):
+        o.set_counts(k, g.counts(k).astype(np.int64))
+    o.set_efield(g.deposit("ex"), g.deposit("ey"), g.deposit("ez"))
+    o.set_step(g.diagnostics()["step"])
+    return o
+
+
+def _transport_check(g, o, cfg):
+    """FP32 GPU transport against the oracle's from the same state: cells equal except
+    inside the tie band; returns (tie-band count, max position error in cells)."""
+    cell, off, w, ids = g.particles()
+    ids, cell, off, w = by_id(ids, cell, off, w)
+    xi_o, w_o, id_o = o.particles()
+    id_o, xi_o, w_o = by_id(id_o, xi_o, w_o)
+    assert np.array_equal(ids, id_o) and np.array_equal(w.astype(np.uint64), w_o)
+    co, _ = xi_to_cell_off(xi_o, cfg["grid"])
+    mism = co != cell
+    face = np.abs(xi_o - np.round(xi_o)).min(axis=1)
+    assert np.all(face[mism] < 1e-5), "uncertified cell mismatch after transport"
+    err = np.abs(gpu_xi(cell, off, cfg["grid"]) - xi_o).max(axis=1)
+    return int(mism.sum()), float(err[~mism].max(initial=0.0))
+
+
+def _react_exact(g, o, cfg):
+    """After both react from the same post-transport state: every integer agrees."""
+    cell, off, w, ids = g.particles()
+    ids, cell, off, w = by_id(ids, cell, off, w)
+    xi_o, w_o, id_o = o.particles()
+    id_o, xi_o, w_o = by_id(id_o, xi_o, w_o)
+    assert np.array_equal(ids, id_o), "ids differ after react"
+    assert np.array_equal(w.astype(np.uint64), w_o), "weights differ after react"
+    co, _ = xi_to_cell_off(xi_o, cfg["grid"])
+    assert np.array_equal(co, cell), "cells differ after react"
+    for k in ("plus", "minus", "gamma"):
+        assert np.array_equal(g.counts(k).astype(np.int64), o.counts(k)), k
+    assert np.array_equal(g.deposit("fires").astype(np.int64), o.fires())
+    return float(np.abs(gpu_xi(cell, off, cfg["grid"]) - xi_o).max(initial=0.0))
+
+
+def _first_divergence(itk, orc, cfg, steps):
+    """Free-running FP32 GPU against the FP64 oracle from the same seed: the first step
+    whose integer state (particles, weight, ions, fires) differs, or None."""
+    g = itk.Sim(cfg, precision="fp32")
+    g.seed()
+    o = orc.Sim(cfg)
+    o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+    first = None
+    for k in range(1, steps + 1):
+        g.step(1)
+        o.step(cfg["dt"], 1)
+        dg, do = g.diagnostics(), o.diagnostics()
+        same = all(dg[q] == do[q] for q in ("n_particles", "weight", "n_plus", "n_minus")) and \
+            dg["fires"] == do["fires"]
+        if not same:
+            first = k
+            break
+    g.close()
+    return first
+
+
 def test_precision_study_64(itk, orc):
     cfg = workloads.preset("streamer_64")
     o = orc.Sim(cfg)
     o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
     o.step(cfg["dt"], 4)
-    report = {"fp64": [], "fp32": []}
+    report = {"fp64": [], "fp32": [], "fp32_split": []}
     for _ in range(2):
         xi, w, ids = o.particles()
         state = (xi, w, ids, {k: o.counts(k) for k in ("plus", "minus", "gamma")},
@@ -109,10 +184,30 @@ def test_precision_study_64(itk, orc):
         gs = {p: _load(itk, cfg, p, state) for p in ("fp64", "fp32")}
         for g in gs.values():
             g.step(1)
+        # the split FP32 step: transport against the oracle's transport, then react
+        # against the oracle reacting from the GPU's post-transport state
+        gsplit = _load(itk, cfg, "fp32", state)
+        ot = orc.Sim(cfg)
+        ot.set_particles(xi, w, ids)
+        for k, v in state[3].items():
+            ot.set_counts(k, v)
+        ot.set_step(state[4])
+        ot.set_field(state[5])
+        gsplit.transport()
+        ot.transport(cfg["dt"])
+        nband, pos_t = _transport_check(gsplit, ot, cfg)
+        orr = _oracle_from_gpu(orc, cfg, gsplit)
+        gsplit.react()
+        orr.react(cfg["dt"])
+        pos_r = _react_exact(gsplit, orr, cfg)
+        report["fp32_split"].append({"transport_tie_band": nband, "transport_pos_max_cells": pos_t,
+                                     "react_pos_max_cells": pos_r})
+        gsplit.close()
         o.step(cfg["dt"], 1)
         for p, g in gs.items():
             report[p].append(_errors(g, o, cfg, fires0))
             g.close()
+    report["fp32_first_divergence_step"] = _first_divergence(itk, orc, cfg, 8)
     print("PRECISION_STUDY " + json.dumps(report))
     for r in report["fp64"]:
         # both solves stop at a relative residual of 1e-10; the central difference of
@@ -127,8 +222,9 @@ def test_precision_study_64(itk, orc):
         assert r["phi_max_rel"] < 1e-6 and r["E_max_rel"] < 1e-5
         assert r["ne_l2_rel"] < 1e-5
         assert r["pos_max_cells"] < 1e-5
-        assert r["leaves_regrouped"] <= max(2, r["leaves"] // 1000)
         assert r["cell_mismatch_outside_band"] == 0
         assert r["solver_relres"] <= 1e-10
-        # integer results differ only through tie-band particles (a few cells' KMC)
-        assert r["ids_only_one_side"] <= 64 * max(1, r["cell_mismatch"]) * 2
+    for r in report["fp32_split"]:
+        assert r["transport_pos_max_cells"] < 1e-5
+        # merge centroids are computed in double and rounded to single precision
+        assert r["react_pos_max_cells"] < 2e-6

@@ -51,3 +51,39 @@ def test_two_layer_mistakes_are_visible(orc):
     assert abs(c["E_h"] - c["E_l"]) > 0.5 * c["E_l"]  # E^k instead of E^{k+1}
     mu_b = c["cfg"]["coeffs"]["mu_b"]
     assert abs((c["E_l"] / V_L) ** mu_b - 1.0) > 0.1  # mobility at E^{k+1} instead of E^k
+
+
+def test_residual_and_field_push_entries_reproduce_transport(orc):
+    """The oracle entries that check GPU states at full size: the residual of the
+    oracle's own solution in the system rebuilt from the pre-transport state is at the
+    solver's tolerance (and a perturbed potential is not), and the push with the two
+    given fields reproduces the transport's positions bit for bit."""
+    cfg = workloads.preset("streamer_64", grid=(16, 16, 16), dx=1e-3 / 64,
+                           seed_centre=(125e-6, 125e-6, 125e-6), seed_sigma=30e-6,
+                           V_anode=18e3 * 0.25)
+    a = orc.Sim(cfg)
+    a.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+    a.step(cfg["dt"], 3)
+    xi, w, ids = a.particles()
+    counts = {k: a.counts(k) for k in ("plus", "minus", "gamma")}
+    phi_k, ex, ey, ez = a.field()
+    step = a.diagnostics()["step"]
+    b = orc.Sim(cfg)
+    b.set_particles(xi, w, ids)
+    for k, v in counts.items():
+        b.set_counts(k, v)
+    b.set_field(phi_k)
+    b.set_step(step)
+    a.transport(cfg["dt"])
+    phi1, e1x, e1y, e1z = a.field()
+    assert b.semi_implicit_residual(cfg["dt"], phi1) < 1e-12
+    bad = phi1.copy()
+    bad[len(bad) // 2] *= 1.0 + 1e-6
+    assert b.semi_implicit_residual(cfg["dt"], bad) > 1e-8
+    assert b.semi_implicit_residual(cfg["dt"], phi_k) > 1e-6   # the old potential
+    x1 = orc.push_with_fields(cfg, xi, ids, step, cfg["dt"], (ex, ey, ez), (e1x, e1y, e1z))
+    xa, _, ida = a.particles()
+    o1, o2 = np.argsort(ids), np.argsort(ida)
+    inside = np.all((x1[o1] >= 0) & (x1[o1] < 16), axis=1)
+    assert np.array_equal(ids[o1][inside], ida[o2])
+    assert np.array_equal(x1[o1][inside], xa[o2])
