@@ -380,6 +380,26 @@ int itokmc_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* dev_cell_ids,
                      int64_t* dev_X, const double* dev_k, double dt, uint32_t step,
                      int64_t* dev_fires);
 
+/* Counting sort of n particles by cell (the binning of particles into per-cell lists
+ * that the reactions and superparticle management of the final algorithm, steps 7-8,
+ * work on).  Inputs (device, n entries each): cell (u32), offsets ox, oy, oz (float for
+ * ITOKMC_FP32, double for ITOKMC_FP64), weight w (u32; w == 0 marks a dead slot), id
+ * (u64).  Outputs (device, capacity n each): the live particles (w > 0 and cell < ncell;
+ * others are dropped) grouped by ascending cell, cell c occupying
+ * [start[c], start[c+1]) with start of ncell + 1 u32; within a cell the order is
+ * unspecified.  *n_out (device u32) receives the number of live particles.  Inputs and
+ * outputs must not overlap.  workspace: device memory of at least
+ * itokmc_sort_workspace_bytes(n, ncell) bytes, owned by the caller, unused after the
+ * call's kernels finish.  Everything is enqueued on stream (a hipStream_t); nothing
+ * synchronises.  Errors: EINVAL (null pointer, precision, ncell outside [1, 2^24], n >
+ * 2^31 - 1), ENOMEM (workspace too small), EHIP. */
+size_t itokmc_sort_workspace_bytes(uint64_t n, uint32_t ncell);
+int itokmc_sort_by_cell(int precision, uint64_t n, uint32_t ncell, const uint32_t* cell,
+                        const void* ox, const void* oy, const void* oz, const uint32_t* w,
+                        const uint64_t* id, uint32_t* cell_out, void* ox_out, void* oy_out,
+                        void* oz_out, uint32_t* w_out, uint64_t* id_out, uint32_t* start,
+                        uint32_t* n_out, void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,7 +37,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_particles", "itokmc_ensemble_get_counts",
            "itokmc_ensemble_release", "itokmc_ensemble_info", "itokmc_ensemble_set_tuning",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
-           "itokmc_ensemble_last_error"]
+           "itokmc_ensemble_last_error", "itokmc_sort_workspace_bytes", "itokmc_sort_by_cell"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
           "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light"]
 
@@ -195,6 +195,9 @@ def lib():
         L.itokmc_ensemble_destroy.restype = None
         L.itokmc_ensemble_last_error.argtypes = [P]
         L.itokmc_ensemble_last_error.restype = ctypes.c_char_p
+        L.itokmc_sort_workspace_bytes.restype = ctypes.c_size_t
+        L.itokmc_sort_workspace_bytes.argtypes = [U64, U32]
+        L.itokmc_sort_by_cell.argtypes = [I32, U64, U32] + [P] * 14 + [P, ctypes.c_size_t, P]
         _lib = L
     return _lib
 
@@ -584,3 +587,48 @@ def philox_fill(c0, c1, c2, c3, k0, k1, n, device="cuda:0"):
         raise ItokmcError(rc, "philox_fill")
     torch.cuda.synchronize(device)
     return out.cpu().numpy().view(np.uint32).reshape(n, 4)
+
+
+def _sort_tensors(cell, off, w, ids, precision, device):
+    import torch
+    ft = torch.float64 if precision == "fp64" else torch.float32
+    dev = torch.device(device)
+    t = {"cell": torch.from_numpy(np.ascontiguousarray(cell, dtype=np.uint32).view(np.int32)).to(dev),
+         "w": torch.from_numpy(np.ascontiguousarray(w, dtype=np.uint32).view(np.int32)).to(dev),
+         "id": torch.from_numpy(np.ascontiguousarray(ids, dtype=np.uint64).view(np.int64)).to(dev)}
+    off = np.asarray(off, dtype=np.float64).reshape(-1, 3)
+    for a, k in enumerate(("ox", "oy", "oz")):
+        t[k] = torch.from_numpy(np.ascontiguousarray(off[:, a])).to(dev, ft)
+    return t
+
+
+def sort_by_cell(cell, off, w, ids, ncell, precision="fp32", device="cuda:0", noalloc=False):
+    """Counting sort of particles by cell through the C ABI (kernel-level entry point).
+    Returns (start[ncell+1], cell, off (n, 3), w, ids) of the live particles, grouped by
+    cell, as numpy arrays."""
+    import torch
+    L = lib()
+    n = len(w)
+    t = _sort_tensors(cell, off, w, ids, precision, device)
+    o = {k: torch.empty_like(v) for k, v in t.items()}
+    start = torch.empty(ncell + 1, dtype=torch.int32, device=device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=device)
+    stream = torch.cuda.current_stream(torch.device(device))
+    prec = FP64 if precision == "fp64" else FP32
+    args = [prec, n, ncell] + [ctypes.c_void_p(t[k].data_ptr()) for k in ("cell", "ox", "oy", "oz", "w", "id")] + \
+        [ctypes.c_void_p(o[k].data_ptr()) for k in ("cell", "ox", "oy", "oz", "w", "id")] + \
+        [ctypes.c_void_p(start.data_ptr()), ctypes.c_void_p(n_out.data_ptr())]
+    if noalloc:
+        rc = L.itokmc_sort_by_cell_noalloc(*args, ctypes.c_void_p(stream.cuda_stream))
+    else:
+        nb = L.itokmc_sort_workspace_bytes(n, ncell)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+        rc = L.itokmc_sort_by_cell(*args, ctypes.c_void_p(ws.data_ptr()), nb,
+                                   ctypes.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise ItokmcError(rc, "sort_by_cell failed")
+    stream.synchronize()
+    m = int(n_out.cpu().item())
+    offs = np.stack([o[k][:m].double().cpu().numpy() for k in ("ox", "oy", "oz")], axis=1)
+    return (start.cpu().numpy().view(np.uint32), o["cell"][:m].cpu().numpy().view(np.uint32), offs,
+            o["w"][:m].cpu().numpy().view(np.uint32), o["id"][:m].cpu().numpy().view(np.uint64))
