@@ -399,6 +399,22 @@ int itokmc_sort_by_cell(int precision, uint64_t n, uint32_t ncell, const uint32_
                         const uint64_t* id, uint32_t* cell_out, void* ox_out, void* oy_out,
                         void* oz_out, uint32_t* w_out, uint64_t* id_out, uint32_t* start,
                         uint32_t* n_out, void* workspace, size_t workspace_bytes, void* stream);
+/* The same sort without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the scratch is a file-scope device array of 32 MiB per GPU, so the call
+ * performs no allocation of any kind.  It accepts sizes whose
+ * itokmc_sort_workspace_bytes(n, ncell) is at most 32 MiB (for example 2^20 cells with
+ * 7e6 particles) and returns ECAPACITY beyond that.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (on several streams or host threads) race
+ * and must be serialised by the caller.  The first call on a device resolves the
+ * array's address there (EHIP if that fails).  Other arguments and errors as
+ * itokmc_sort_by_cell. */
+int itokmc_sort_by_cell_noalloc(int precision, uint64_t n, uint32_t ncell,
+                                const uint32_t* cell, const void* ox, const void* oy,
+                                const void* oz, const uint32_t* w, const uint64_t* id,
+                                uint32_t* cell_out, void* ox_out, void* oy_out, void* oz_out,
+                                uint32_t* w_out, uint64_t* id_out, uint32_t* start,
+                                uint32_t* n_out, void* stream);
 
 #ifdef __cplusplus
 }

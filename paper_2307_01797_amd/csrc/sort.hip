@@ -9,9 +9,13 @@
 // Within a cell the order is that of the counting atomics (unspecified).
 //
 // Scratch (32-bit words): the per-cell counters [ncell], the ranks [n] and the scan's
-// block partials, taken from a caller workspace.
+// block partials.  itokmc_sort_by_cell takes it from a caller workspace;
+// itokmc_sort_by_cell_noalloc from a file-scope device array (one per GPU, resolved once
+// per device with hipGetSymbolAddress), for callers that cannot allocate.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <mutex>
 
 #include "device.hpp"
 #include "itk.hpp"
@@ -243,6 +247,32 @@ bool sort_args_ok(int precision, uint64_t n, uint32_t ncell, const void* const* 
   return true;
 }
 
+// ---- file-scope scratch for the no-allocation entry point --------------------------
+constexpr uint64_t kNoAllocScratchBytes = 32ull << 20;
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchBytes / 4];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The device address of this GPU's scratch array, resolved once per device with that
+// device current (each GPU holds its own copy at its own address).
+hipError_t scratch_for_current_device(uint32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (uint32_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 }  // namespace itk
 
@@ -265,6 +295,20 @@ int itokmc_sort_by_cell(int precision, uint64_t n, uint32_t ncell, const uint32_
   if (workspace_bytes < (size_t)sort_words(n, ncell) * 4) return ITOKMC_ENOMEM;
   return sort_run(precision, n, ncell, cell, ox, oy, oz, w, id, cell_out, ox_out, oy_out, oz_out, w_out,
                   id_out, start, n_out, (uint32_t*)workspace, (hipStream_t)stream);
+}
+
+int itokmc_sort_by_cell_noalloc(int precision, uint64_t n, uint32_t ncell, const uint32_t* cell,
+                                const void* ox, const void* oy, const void* oz, const uint32_t* w,
+                                const uint64_t* id, uint32_t* cell_out, void* ox_out, void* oy_out,
+                                void* oz_out, uint32_t* w_out, uint64_t* id_out, uint32_t* start,
+                                uint32_t* n_out, void* stream) {
+  const void* p[] = {cell, ox, oy, oz, w, id, cell_out, ox_out, oy_out, oz_out, w_out, id_out, start, n_out};
+  if (!sort_args_ok(precision, n, ncell, p, 14)) return ITOKMC_EINVAL;
+  if ((uint64_t)sort_words(n, ncell) * 4 > kNoAllocScratchBytes) return ITOKMC_ECAPACITY;
+  uint32_t* sp = nullptr;
+  if (scratch_for_current_device(&sp) != hipSuccess) return ITOKMC_EHIP;
+  return sort_run(precision, n, ncell, cell, ox, oy, oz, w, id, cell_out, ox_out, oy_out, oz_out, w_out,
+                  id_out, start, n_out, sp, (hipStream_t)stream);
 }
 
 }  // extern "C"

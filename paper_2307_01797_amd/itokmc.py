@@ -37,7 +37,8 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_particles", "itokmc_ensemble_get_counts",
            "itokmc_ensemble_release", "itokmc_ensemble_info", "itokmc_ensemble_set_tuning",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
-           "itokmc_ensemble_last_error", "itokmc_sort_workspace_bytes", "itokmc_sort_by_cell"]
+           "itokmc_ensemble_last_error", "itokmc_sort_workspace_bytes", "itokmc_sort_by_cell",
+           "itokmc_sort_by_cell_noalloc"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
           "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light"]
 
@@ -198,6 +199,7 @@ def lib():
         L.itokmc_sort_workspace_bytes.restype = ctypes.c_size_t
         L.itokmc_sort_workspace_bytes.argtypes = [U64, U32]
         L.itokmc_sort_by_cell.argtypes = [I32, U64, U32] + [P] * 14 + [P, ctypes.c_size_t, P]
+        L.itokmc_sort_by_cell_noalloc.argtypes = [I32, U64, U32] + [P] * 14 + [P]
         _lib = L
     return _lib
 
