@@ -47,7 +47,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--workload", default="streamer_256")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -63,6 +63,11 @@ def parse():
                    help="first copy 1 GiB device to device (a known-size kernel for "
                         "scaling hardware traffic counters)")
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-scale-window", action="store_true",
+                   help="skip the second timed window near the particle cap")
+    p.add_argument("--scale-steps", type=int, default=8)
+    p.add_argument("--cpu-workers", type=int, default=16,
+                   help="oracle processes of the multi-core host baseline (0: skip)")
     return p.parse_args()
 
 
@@ -124,6 +129,47 @@ def cpu_baseline(cfg, budget_s):
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# One oracle process of the multi-core host baseline: the streamer sample of
+# cpu_baseline with realization r, stepped for a time budget; prints particle-steps and
+# seconds.
+_CPU_WORKER = r"""
+import sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2307_01797_amd import workloads
+r, budget = int(sys.argv[2]), float(sys.argv[3])
+cfg = workloads.preset("streamer_64", realization=r)
+o = oracle.Sim(cfg)
+o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+ps, t0, k = 0, time.perf_counter(), 0
+while time.perf_counter() - t0 < budget and k < 50:
+    ps += o.diagnostics()["n_particles"]
+    o.step(cfg["dt"], 1)
+    k += 1
+print(ps, time.perf_counter() - t0, k)
+"""
+
+
+def cpu_baseline_parallel(workers, budget_s):
+    """The oracle as it stands on several host cores at once: one single-threaded
+    process per core, each a different realization of the streamer sample of
+    cpu_baseline, started as child processes; the aggregate particle-steps/s."""
+    import subprocess
+    procs = [subprocess.Popen([sys.executable, "-c", _CPU_WORKER, ROOT, str(r), str(budget_s)],
+                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
+             for r in range(workers)]
+    rate, steps = 0.0, []
+    for pr in procs:
+        out, _ = pr.communicate()
+        ps, el, k = out.split()
+        rate += int(ps) / float(el)
+        steps.append(int(k))
+    return {"value": rate, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} processes (one per core), each the streamer workload on the "
+                      f"64^3 grid with its own realization, {min(steps)}-{max(steps)} steps in "
+                      f"about {budget_s:.0f} s"}
 
 
 def cpu_baseline_ensemble(cfgs, budget_s):
@@ -277,26 +323,94 @@ def main():
     sim.seed()
     sim.step(args.warmup)
     torch.cuda.synchronize(dev)
+    w = timed_windows(sim, cfg, args.steps, dev)
+    roof = max(w["roofs"].values(), key=lambda r: r["total_ms"]) if w["roofs"] else None
+    if roof is not None:
+        ph = next(p for p, r in w["roofs"].items() if r is roof)
+        roof["traffic"] = traffic_from_profile(KERNELS[ph])
+    d0, d1, d2 = w["diag"]
+    out = {
+        "metric": "particle-steps/s (push+sort+deposit+KMC)",
+        "value": w["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": w["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if cfg.get("precision") == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": list(cfg["grid"]), "dx_m": cfg["dx"],
+                   "particles_start": d0["n_particles"], "particles_end": d1["n_particles"],
+                   "weight_end": d1["weight"], "field": cfg.get("field"),
+                   "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": w["rc"],
+                   "occupied_cells_end": d2.get("occupied_cells"),
+                   "queued_cells_end": d2.get("queued_cells"),
+                   "wavefront_coupled_cells_end": d2.get("wave_cells")},
+        "profiled_window": {"ms_per_step": w["ms_p"] / args.steps, "status": w["rc_p"],
+                            "particle_steps": w["psteps_p"]},
+        "phase_ms_per_step": w["phase_ms_per_step"],
+        "solver_cycles_per_step": w["cycles"] / args.steps,
+        "roofline": roof,
+        "roofline_by_kernel": w["roofs"],
+    }
+    if "push_deposit" in w:
+        out["push_deposit"] = w["push_deposit"]
+    del sim
+    torch.cuda.synchronize(dev)
+    if cfg["name"] == "streamer_256" and not args.no_scale_window:
+        out["scale_window"] = scale_window(args, dev)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        if args.cpu_workers > 0:
+            out["cpu_baseline_parallel"] = cpu_baseline_parallel(args.cpu_workers, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+def push_deposit_roofline(roofs, psteps, S):
+    """The particle push with its fused NGP binning and the charge deposit together:
+    44 B per particle-step for the push (read cell 4 + offsets 3 x 4 + id 8 + weight 4,
+    write cell 4 + offsets 3 x 4) and, in the self-consistent step, 28 B for the
+    deposit pass (read cell, offsets, weight and id), over the two kernels' time."""
+    push = roofs.get("field_push") or roofs.get("push")
+    if push is None:
+        return None
+    dep = roofs.get("deposit")
+    per = (20 + 6 * S) + (16 + 3 * S if dep else 0)
+    t_ms = push["total_ms"] + (dep["total_ms"] if dep else 0.0)
+    achieved = per * psteps / (t_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_particle_step": per,
+            "kernels": [push["kernel"]] + ([dep["kernel"]] if dep else []),
+            "ms": round(t_ms, 3), "particle_steps": psteps,
+            "particle_steps_per_s": psteps / (t_ms / 1e3)}
+
+
+def timed_windows(sim, cfg, steps, dev):
+    """K timed steps (HIP events on the library's stream), then K profiled steps (HIP
+    events around every kernel phase): the rate, the per-phase times, the roofline of
+    each single-kernel phase."""
+    import torch
     stream = sim.stream
-    # timed window: K steps, HIP events on the library's stream
     d0 = sim.diagnostics()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize(dev)
     ev0.record(stream)
-    rc = sim.step_rc(args.steps)
+    rc = sim.step_rc(steps)
     ev1.record(stream)
     torch.cuda.synchronize(dev)
     ms = ev0.elapsed_time(ev1)
     d1 = sim.diagnostics(check=False)
     psteps = d1["particle_steps"] - d0["particle_steps"]
-    value = psteps / (ms / 1e3)
     # profiled window: the next K steps with HIP events around every kernel phase (and
     # around each finest-level smoother launch, whose cycles then run without the graph)
     sim.set_profiling(True)
     sim.phase_times(reset=True)
     ev0.record(stream)
-    rc_p = sim.step_rc(args.steps)
+    rc_p = sim.step_rc(steps)
     ev1.record(stream)
     torch.cuda.synchronize(dev)
     ms_p = ev0.elapsed_time(ev1)
@@ -304,15 +418,11 @@ def main():
     sim.set_profiling(False)
     d2 = sim.diagnostics(check=False)
     psteps_p = d2["particle_steps"] - d1["particle_steps"]
-
-    # roofline of the dominant kernel: algorithmic bytes per launch / average launch
     ncell = 1
     for v in cfg["grid"]:
         ncell *= v
     S = 8 if cfg.get("precision") == "fp64" else 4
-    cycles = d1.get("solver_cycles_total", 0) - d0.get("solver_cycles_total", 0)
     roofs = {}
-    psteps_r = psteps_p
     for ph, kname in KERNELS.items():
         tot_ms, launches = phases.get(ph, (0.0, 0))
         if not launches or tot_ms <= 0:
@@ -322,7 +432,7 @@ def main():
         elif ph == "couple":
             units = d2.get("couple_pieces", 0) - d1.get("couple_pieces", 0)
         else:
-            units = psteps_r
+            units = psteps_p
         per_launch = bytes_per_unit(ph, S) * units / launches
         achieved = per_launch / (tot_ms / launches / 1e3) / 1e9
         roofs[ph] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -330,40 +440,41 @@ def main():
                      "kernel": kname, "avg_launch_ms": round(tot_ms / launches, 4),
                      "launches": launches, "bytes_per_launch": int(per_launch),
                      "total_ms": round(tot_ms, 3)}
-    roof = max(roofs.values(), key=lambda r: r["total_ms"]) if roofs else None
-    if roof is not None:
-        ph = next(p for p, r in roofs.items() if r is roof)
-        roof["traffic"] = traffic_from_profile(KERNELS[ph])
-    out = {
-        "metric": "particle-steps/s (push+sort+deposit+KMC)",
-        "value": value,
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if cfg.get("precision") == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": cfg["name"], "grid": list(cfg["grid"]), "dx_m": cfg["dx"],
-                   "particles_start": d0["n_particles"], "particles_end": d1["n_particles"],
-                   "weight_end": d1["weight"], "field": cfg.get("field"),
-                   "n_ppc": cfg.get("n_ppc", 0), "dt_s": cfg["dt"], "status": rc,
-                   "occupied_cells_end": d2.get("occupied_cells"),
-                   "queued_cells_end": d2.get("queued_cells"),
-                   "wavefront_coupled_cells_end": d2.get("wave_cells")},
-        "profiled_window": {"ms_per_step": ms_p / args.steps, "status": rc_p,
-                            "particle_steps": psteps_p},
-        "phase_ms_per_step": {p: round(v[0] / args.steps, 4) for p, v in phases.items() if v[1]},
-        "solver_cycles_per_step": cycles / args.steps,
-        "roofline": roof,
-        "roofline_by_kernel": roofs,
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
-    print(json.dumps(out))
+    out = {"value": psteps / (ms / 1e3), "ms": ms, "rc": rc, "ms_p": ms_p, "rc_p": rc_p,
+           "psteps": psteps, "psteps_p": psteps_p, "diag": (d0, d1, d2), "roofs": roofs,
+           "phase_ms_per_step": {p: round(v[0] / steps, 4) for p, v in phases.items() if v[1]},
+           "cycles": d1.get("solver_cycles_total", 0) - d0.get("solver_cycles_total", 0)}
+    pd = push_deposit_roofline(roofs, psteps_p, S)
+    if pd is not None:
+        out["push_deposit"] = pd
+    return out
+
+
+def scale_window(args, dev):
+    """The self-consistent streamer near the configuration's particle cap (the denser
+    seed of workloads.STREAMER_256_DENSE, about 4.4e7 particles after the first
+    superparticle pass): two warm-up steps, then a timed and a profiled window."""
+    import torch
+
+    from paper_2307_01797_amd import itokmc, workloads
+    cfg = workloads.preset("streamer_256_dense")
+    sim = itokmc.Sim(cfg, device=dev)
+    sim.seed()
+    sim.step(2)
+    torch.cuda.synchronize(dev)
+    w = timed_windows(sim, cfg, args.scale_steps, dev)
+    d0, d1, _ = w["diag"]
+    res = {"workload": cfg["name"], "steps": args.scale_steps, "warmup": 2,
+           "particles_start": d0["n_particles"], "particles_end": d1["n_particles"],
+           "value": w["value"], "unit": "particle-steps/s",
+           "ms_per_step": w["ms"] / args.scale_steps, "status": w["rc"],
+           "phase_ms_per_step": w["phase_ms_per_step"],
+           "roofline_by_kernel": w["roofs"]}
+    if "push_deposit" in w:
+        res["push_deposit"] = w["push_deposit"]
+    del sim
+    torch.cuda.synchronize(dev)
+    return res
 
 
 if __name__ == "__main__":

@@ -87,6 +87,8 @@ void uniform_consts(const itokmc_grid_desc& d, const itokmc_coeffs& c, double dt
 StepConst make_const(const itokmc_ctx* ctx, double dt) {
   StepConst k{};
   k.nx = ctx->d.nx; k.ny = ctx->d.ny; k.nz = ctx->d.nz;
+  div_magic((uint32_t)k.nx, &k.mdx, &k.sdx);
+  div_magic((uint32_t)k.ny, &k.mdy, &k.sdy);
   k.ncell = ctx->ncell;
   k.cap = (uint32_t)ctx->cap;
   k.step = ctx->step;

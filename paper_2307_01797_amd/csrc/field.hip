@@ -372,8 +372,8 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
       const uint32_t w = a.w[i];
       if (!w) continue;
       const uint32_t cell = a.cell[i];
-      const int ci = (int)(cell % (uint32_t)K.nx), cj = (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
-                ck = (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny));
+      int ci, cj, ck;
+      cell_ijk(cell, K, ci, cj, ck);
       const T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
       int i0, j0, k0;
       T fx, fy, fz;
@@ -438,8 +438,8 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
     if (w > 0) {
       ++pushed;
       const uint32_t cell = cell0;
-      int ci[3] = {(int)(cell % (uint32_t)K.nx), (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny),
-                   (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny))};
+      int ci[3];
+      cell_ijk(cell, K, ci[0], ci[1], ci[2]);
       T o[3] = {o0[0], o0[1], o0[2]};
       int i0, j0, k0;
       T fx, fy, fz;

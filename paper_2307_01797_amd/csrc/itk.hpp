@@ -63,7 +63,27 @@ struct StepConst {
   double drift[3];   // uniform mode: -mu E dt / dx per axis (grid units)
   double diff;       // sqrt(2 D dt) / dx (grid units per unit normal)
   double k[3];       // uniform mode rates (1/s)
+  // multiply-shift division by nx and by ny: floor(c / d) = (c * m) >> s for every
+  // c < 2^24, with s = 24 + ceil(log2 d) and m = ceil(2^s / d) (< 2^25)
+  uint32_t mdx, sdx, mdy, sdy;
 };
+
+// Cell indices (i, j, k) of a cell number c = i + nx (j + ny k), by multiply-shift
+// division (StepConst.mdx/sdx/mdy/sdy).
+__device__ __forceinline__ void cell_ijk(uint32_t c, const StepConst& K, int& i, int& j, int& k) {
+  const uint32_t row = (uint32_t)(((uint64_t)c * K.mdx) >> K.sdx);
+  i = (int)(c - row * (uint32_t)K.nx);
+  const uint32_t kk = (uint32_t)(((uint64_t)row * K.mdy) >> K.sdy);
+  j = (int)(row - kk * (uint32_t)K.ny);
+  k = (int)kk;
+}
+// Host: the multiply-shift constants of a divisor d in [1, 2^24].
+inline void div_magic(uint32_t d, uint32_t* m, uint32_t* s) {
+  uint32_t l = 0;
+  while ((1u << l) < d) ++l;
+  *s = 24 + l;
+  *m = (uint32_t)(((1ull << *s) + d - 1) / d);
+}
 
 // Field view for per-cell KMC rates (Poisson mode): E at cell centres, packed
 // (Ex, Ey, Ez, 0) per cell, and the coefficient forms; E4 == nullptr means the

@@ -116,15 +116,22 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     uint32_t key = kInvalidCell;
-    uint32_t w = 0;
-    if (i < n) w = a.w[i];
+    // all of the particle's words in one round trip, before its weight is tested
+    uint32_t w = 0, cell = 0;
+    uint64_t id = 0;
+    T o[3] = {(T)0, (T)0, (T)0};
+    if (i < n) {
+      w = a.w[i];
+      cell = a.cell[i];
+      id = a.id[i];
+      o[0] = as<T>(a.ox)[i];
+      o[1] = as<T>(a.oy)[i];
+      o[2] = as<T>(a.oz)[i];
+    }
     if (w > 0) {
       ++pushed;
-      const uint32_t cell = a.cell[i];
-      const uint64_t id = a.id[i];
-      T o[3] = {as<T>(a.ox)[i], as<T>(a.oy)[i], as<T>(a.oz)[i]};
-      int ci[3] = {(int)(cell % (uint32_t)k.nx), (int)((cell / (uint32_t)k.nx) % (uint32_t)k.ny),
-                   (int)(cell / ((uint32_t)k.nx * (uint32_t)k.ny))};
+      int ci[3];
+      cell_ijk(cell, k, ci[0], ci[1], ci[2]);
       const int lim[3] = {k.nx, k.ny, k.nz};
       const bool inside = push_uniform<T>(id, k.step, k.key, drift, diff, lim, ci, o);
       if (inside) {

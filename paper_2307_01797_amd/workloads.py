@@ -41,6 +41,15 @@ STREAMER_256 = dict(
     gmg_rtol=1e-10,
 )
 
+# The same streamer at the particle cap: a denser, wider seed (peak 1e21 m^-3,
+# sigma = 65 um) at the centre of the gap makes about 7.7e7 computational particles
+# (at most 64 per cell), and the first superparticle pass leaves about 4.4e7 (32 per
+# cell where the count allows).  The bank holds the seed and, before that first pass,
+# the reactions' products (up to 64 per cell): 1.6e8 slots.
+STREAMER_256_DENSE = dict(STREAMER_256, name="streamer_256_dense", seed_peak=1e21,
+                          seed_centre=(0.5e-3, 0.5e-3, 0.5e-3), seed_sigma=65e-6,
+                          max_particles=160_000_000)
+
 # The same gap at 64^3 (dx = 15.6 um), 200 steps: precision study size.
 STREAMER_64 = dict(STREAMER_256, name="streamer_64", grid=(64, 64, 64), dx=1e-3 / 64,
                    steps=200, max_particles=4_000_000)
@@ -59,7 +68,8 @@ AVALANCHE_256 = dict(
 
 def preset(name, **overrides):
     base = {"avalanche_32": AVALANCHE_32, "streamer_256": STREAMER_256,
-            "streamer_64": STREAMER_64, "avalanche_256": AVALANCHE_256}[name]
+            "streamer_64": STREAMER_64, "avalanche_256": AVALANCHE_256,
+            "streamer_256_dense": STREAMER_256_DENSE}[name]
     cfg = copy.deepcopy(base)
     for k, v in overrides.items():
         if k == "coeffs":
