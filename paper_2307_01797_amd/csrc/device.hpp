@@ -123,6 +123,46 @@ __device__ __forceinline__ uint64_t run_add(unsigned long long* acc, uint32_t ke
   return old + x - (active ? val : 0ull);
 }
 
+// Inclusive prefix sum across the wavefront (32-bit, wrapping) with DPP: shifts by 1,
+// 2, 4 and 8 lanes inside each 16-lane row (lanes shifted in from outside the row add
+// 0), then the last lane of row 0 added to rows 1 and 3 and the last lane of row 1 (by
+// then the total of rows 0-1) to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_prefix_dpp(uint32_t x) {
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xF, 0xF, true);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xF, 0xF, true);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xF, 0xF, true);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xF, 0xF, true);   // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
+// Binning of one particle per lane into acc[key] = (count << 32) | weight (inactive
+// lanes use kInvalidCell): one 64-bit atomic per run of equal consecutive keys, as
+// run_add, but only the count is returned: each active lane's rank in its cell (0 for
+// the cell's first particle of the step).  A run's weight is the difference of two
+// wavefront prefix sums of 32-bit weights; it is exact because a cell's total weight
+// is below 2^32.
+__device__ __forceinline__ uint32_t bin_add(unsigned long long* acc, uint32_t key, uint32_t w) {
+  const int lane = lane_id();
+  const bool active = key != kInvalidCell;
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const bool head = (lane == 0) || (prev != key);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int seg_start = 63 - __clzll(heads & upto);
+  const uint64_t after = heads & ~upto;
+  const int seg_end = after ? (__ffsll((long long)after) - 2) : 63;
+  const uint32_t P = wave_prefix_dpp(active ? w : 0u);
+  const uint32_t Pb = __shfl(P, seg_start > 0 ? seg_start - 1 : 0, 64);
+  const uint32_t wsum = P - (seg_start > 0 ? Pb : 0u);
+  uint32_t old = 0;
+  if (active && lane == seg_end)
+    old = (uint32_t)(atomicAdd(&acc[key], ((unsigned long long)(seg_end - seg_start + 1) << 32) |
+                                              (unsigned long long)wsum) >> 32);
+  return __shfl(old, seg_end, 64) + (uint32_t)(lane - seg_start);
+}
+
 // Scan tiles of 2048 cells.  The binning kernels flag the tile of every cell that
 // receives its first particle of the step; the counting-sort scan visits flagged tiles
 // only (and clears the flags).

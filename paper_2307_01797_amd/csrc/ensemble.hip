@@ -259,9 +259,9 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
         }
       }
     }
-    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
-    mark_tile(tiles, key, old);
-    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+    const uint32_t rank = bin_add(cellacc, key, w);
+    mark_tile(tiles, key, (uint64_t)rank << 32);
+    if (key != kInvalidCell) a.rank[i] = rank;
   }
   uint64_t tot;
   if (run_total(cur, live, &tot) && tot) atomicAdd(&st[S_LIVE * ms + cur], (unsigned long long)tot);

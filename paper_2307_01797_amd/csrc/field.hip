@@ -481,9 +481,9 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
         a.w[i] = 0;
       }
     }
-    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
-    mark_tile(tiles, key, old);
-    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+    const uint32_t rank = bin_add(cellacc, key, w);
+    mark_tile(tiles, key, (uint64_t)rank << 32);
+    if (key != kInvalidCell) a.rank[i] = rank;
   }
   out_w = wave_sum64(out_w);
   pushed = wave_sum64(pushed);

@@ -145,9 +145,9 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
         a.w[i] = 0;  // removed at the domain face
       }
     }
-    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
-    mark_tile(tiles, key, old);
-    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+    const uint32_t rank = bin_add(cellacc, key, w);
+    mark_tile(tiles, key, (uint64_t)rank << 32);
+    if (key != kInvalidCell) a.rank[i] = rank;
   }
   out_w = wave_sum64(out_w);
   pushed = wave_sum64(pushed);
@@ -169,9 +169,9 @@ __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int whi
       w = a.w[i];
       if (w > 0) key = a.cell[i];
     }
-    const uint64_t old = run_add(cellacc, key, key != kInvalidCell ? ((1ull << 32) | w) : 0ull);
-    mark_tile(tiles, key, old);
-    if (key != kInvalidCell) a.rank[i] = (uint32_t)(old >> 32);
+    const uint32_t rank = bin_add(cellacc, key, w);
+    mark_tile(tiles, key, (uint64_t)rank << 32);
+    if (key != kInvalidCell) a.rank[i] = rank;
   }
 }
 
