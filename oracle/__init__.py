@@ -34,14 +34,20 @@ class Coeffs(ctypes.Structure):
                 ("E_floor", ctypes.c_double), ("D", ctypes.c_double),
                 ("alpha_A", ctypes.c_double), ("alpha_B", ctypes.c_double),
                 ("eta", ctypes.c_double), ("kgamma_ratio", ctypes.c_double),
-                ("photon_l1", ctypes.c_double), ("photon_l2", ctypes.c_double)]
+                ("photon_l1", ctypes.c_double), ("photon_l2", ctypes.c_double),
+                ("beta_ep", ctypes.c_double), ("beta_ep_b", ctypes.c_double),
+                ("Te_a", ctypes.c_double), ("Te_b", ctypes.c_double),
+                ("beta_np", ctypes.c_double)]
+
+# recombination coefficients are optional in a coefficient set (absent: reaction off)
+RECOMB_FIELDS = ("beta_ep", "beta_ep_b", "Te_a", "Te_b", "beta_np")
 
 
 class Diag(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_uint64), ("weight", ctypes.c_uint64),
                 ("n_plus", ctypes.c_int64), ("n_minus", ctypes.c_int64),
                 ("charge", ctypes.c_int64), ("outflow_weight", ctypes.c_uint64),
-                ("fires", ctypes.c_uint64 * 3), ("photons_emitted", ctypes.c_uint64),
+                ("fires", ctypes.c_uint64 * 5), ("photons_emitted", ctypes.c_uint64),
                 ("photons_absorbed", ctypes.c_uint64), ("photons_lost", ctypes.c_uint64),
                 ("created", ctypes.c_uint64), ("removed_weight", ctypes.c_uint64),
                 ("merged_cells", ctypes.c_uint64), ("step", ctypes.c_uint32),
@@ -103,7 +109,9 @@ def lib():
                                       ctypes.c_uint32, ctypes.c_uint32, P]
         L.or_mobility.restype = ctypes.c_double
         L.or_mobility.argtypes = [ctypes.POINTER(Coeffs), ctypes.c_double]
-        L.or_rates.argtypes = [ctypes.POINTER(Coeffs), ctypes.c_double, P]
+        L.or_rates.argtypes = [ctypes.POINTER(Coeffs), ctypes.c_double, ctypes.c_double, P]
+        L.or_kmc_leap_bound.argtypes = [ctypes.POINTER(Desc), P, P]
+        L.or_kmc_leap_bound.restype = ctypes.c_double
         L.or_kmc_cells.argtypes = [ctypes.POINTER(Desc), ctypes.c_int64, P, P, P,
                                    ctypes.c_double, ctypes.c_uint32, P]
         L.or_merge_cell.restype = ctypes.c_int32
@@ -151,7 +159,7 @@ def make_coeffs(cfg) -> Coeffs:
     c = Coeffs()
     co = cfg["coeffs"]
     for name, _ in Coeffs._fields_:
-        setattr(c, name, co[name])
+        setattr(c, name, co.get(name, 0.0) if name in RECOMB_FIELDS else co[name])
     return c
 
 
@@ -192,24 +200,41 @@ def mobility(cfg, E):
 
 
 def rates(cfg, E):
+    """(k_alpha, k_eta, k_gamma, k_ep, k_np) at field magnitude E in one cell of cfg."""
     c = make_coeffs(cfg)
-    k = np.zeros(3)
-    lib().or_rates(ctypes.byref(c), float(E), _p(k))
+    k = np.zeros(5)
+    lib().or_rates(ctypes.byref(c), float(E), float(cfg["dx"]) ** 3, _p(k))
     return k
 
 
+def _rates5(k, n):
+    k = np.asarray(k, dtype=np.float64).reshape(n, -1)
+    out = np.zeros((n, 5))
+    out[:, :k.shape[1]] = k
+    return out
+
+
 def kmc_cells(cfg, X, k, dt, step, cell_ids=None):
-    """One KMC step on independent cells. X: (n,4) int64, k: (n,3). Returns (X, fires)."""
+    """One KMC step on independent cells. X: (n,4) int64, k: (n,3) or (n,5) (missing
+    recombination rates are zero). Returns (X, fires (n,5))."""
     d = make_desc(cfg)
     X = np.ascontiguousarray(X, dtype=np.int64).copy()
-    k = np.ascontiguousarray(k, dtype=np.float64)
     n = X.shape[0]
+    k = np.ascontiguousarray(_rates5(k, n))
     if cell_ids is None:
         cell_ids = np.arange(n, dtype=np.uint32)
     cell_ids = np.ascontiguousarray(cell_ids, dtype=np.uint32)
-    f = np.zeros((n, 3), dtype=np.int64)
+    f = np.zeros((n, 5), dtype=np.int64)
     lib().or_kmc_cells(ctypes.byref(d), n, _p(cell_ids), _p(X), _p(k), float(dt), step, _p(f))
     return X, f
+
+
+def kmc_leap_bound(cfg, X, k):
+    """Step 4's non-critical leap bound for one state X (4) and rates k (3 or 5)."""
+    d = make_desc(cfg)
+    X = np.ascontiguousarray(X, dtype=np.int64)
+    k = np.ascontiguousarray(_rates5(k, 1)[0])
+    return lib().or_kmc_leap_bound(ctypes.byref(d), _p(X), _p(k))
 
 
 def merge_cell(n_ppc, off, w, ids, cell=0, step=0):

@@ -45,9 +45,9 @@ void or_stream_init(or_stream* s, uint32_t cell, uint32_t step, uint32_t tag, ui
 uint32_t or_stream_next(or_stream* s);
 int64_t or_poisson(double lambda, or_stream* s);
 
-/* KMC on one cell: X[4] in/out, k[3], returns fires[3] */
-void or_kmc_advance(const or_desc* d, int64_t X[4], const double k[3], double dt,
-                    or_stream* s, int64_t fires[3]);
+/* KMC on one cell: X[4] in/out, k[5], returns fires[5] */
+void or_kmc_advance(const or_desc* d, int64_t X[4], const double k[5], double dt,
+                    or_stream* s, int64_t fires[5]);
 
 uint64_t or_make_id(int kind, uint32_t step, uint32_t cell, uint32_t slot);
 /* split N physical particles into at most n_new computational ones: returns M,

@@ -60,6 +60,10 @@ typedef struct {
   double eta;                 /* attachment coefficient, 1/m                    */
   double kgamma_ratio;        /* k_gamma = kgamma_ratio * k_alpha               */
   double photon_l1, photon_l2;/* absorption length log-uniform in [l1, l2], m   */
+  /* recombination (0 disables each reaction):
+   *   k_ep = beta_ep * T_e^beta_ep_b / dV with T_e = max(300 K, Te_a (E/mu_E0)^Te_b) K,
+   *   k_np = beta_np / dV (beta_np at the gas temperature, 300 K)                 */
+  double beta_ep, beta_ep_b, Te_a, Te_b, beta_np;
 } or_coeffs;
 
 typedef struct {
@@ -67,7 +71,8 @@ typedef struct {
   int64_t n_plus, n_minus;          /* total ion counts                          */
   int64_t charge;                   /* sum(n+ - n_e - n-) in units of e          */
   uint64_t outflow_weight;          /* electron weight lost through domain faces */
-  uint64_t fires[3];                /* cumulative fires: ionization, attachment, photon emission */
+  uint64_t fires[5];                /* cumulative fires: ionization, attachment, photon
+                                       emission, electron-ion and ion-ion recombination */
   uint64_t photons_emitted, photons_absorbed, photons_lost; /* physical photons */
   uint64_t created, removed_weight; /* coupling tallies                          */
   uint64_t merged_cells;            /* cells rebuilt by merge/split              */
@@ -88,13 +93,17 @@ int64_t or_poisson_draw(double lambda, uint32_t cell, uint32_t step, uint32_t se
 
 /* ---- coefficients -------------------------------------------------------- */
 double or_mobility(const or_coeffs* c, double Emag);
-void or_rates(const or_coeffs* c, double Emag, double k[3]);
+/* k = (k_alpha, k_eta, k_gamma, k_ep, k_np) at field magnitude Emag in a cell of
+ * volume dV */
+void or_rates(const or_coeffs* c, double Emag, double dV, double k[5]);
 
 /* ---- KMC on independent cells (0-D) --------------------------------------- */
-/* X: n_cells x 4 (e, M+, M-, gamma) in/out; k: n_cells x 3 rates (1/s);
- * fires: n_cells x 3 out.  Cell c draws from stream (cell_ids[c], step). */
+/* X: n_cells x 4 (e, M+, M-, gamma) in/out; k: n_cells x 5 rates (1/s);
+ * fires: n_cells x 5 out.  Cell c draws from stream (cell_ids[c], step). */
 void or_kmc_cells(const or_desc* d, int64_t n_cells, const uint32_t* cell_ids,
                   int64_t* X, const double* k, double dt, uint32_t step, int64_t* fires);
+/* Step 4's non-critical leap bound dtau_nc for state X (e, M+, M-, gamma), rates k[5]. */
+double or_kmc_leap_bound(const or_desc* d, const int64_t X[4], const double k[5]);
 
 /* ---- merge/split of one cell ----------------------------------------------
  * off: m x 3 cell-relative offsets in [0,1); w, id: m.  Output leaves written to

@@ -54,13 +54,25 @@ double or_mobility(const or_coeffs* c, double Emag) {
   return c->mu_a * pow(E / c->mu_E0, c->mu_b);
 }
 
-void or_rates(const or_coeffs* c, double Emag, double k[3]) {
+/* Rates of the air-chemistry table: k_alpha = alpha mu E, k_eta = eta mu E,
+ * k_gamma = ratio k_alpha; the recombination rates of the section on the chemistry,
+ * k_ep = beta_ep(T_e) / dV and k_np = beta_np / dV, with the synthetic electron
+ * temperature T_e(E) = max(300 K, Te_a (max(E, E_floor) / mu_E0)^Te_b) standing in for
+ * the tabulated one. */
+void or_rates(const or_coeffs* c, double Emag, double dV, double k[5]) {
   double mu = or_mobility(c, Emag);
   double alpha = Emag > 0.0 ? c->alpha_A * exp(-c->alpha_B / Emag) : 0.0;
   double v = mu * Emag;
   k[0] = alpha * v;
   k[1] = c->eta * v;
   k[2] = c->kgamma_ratio * k[0];
+  k[3] = 0.0;
+  if (c->beta_ep > 0.0) {
+    double E = Emag > c->E_floor ? Emag : c->E_floor;
+    double Te = fmax(300.0, c->Te_a * pow(E / c->mu_E0, c->Te_b));
+    k[3] = c->beta_ep * pow(Te, c->beta_ep_b) / dV;
+  }
+  k[4] = c->beta_np > 0.0 ? c->beta_np / dV : 0.0;
 }
 
 int64_t or_cell_of(const or_desc* d, const double xi[3]) {
@@ -533,10 +545,11 @@ int or_react(or_sim* s, double dt) {
   free(fill);
 
   /* rates: prescribed field, or |E^{k+1}| at the cell centre */
-  double kuni[3];
+  const double dV = d->dx * d->dx * d->dx;
+  double kuni[5];
   if (d->field_mode == OR_FIELD_UNIFORM) {
     const double* E = d->E_uniform;
-    or_rates(c, sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]), kuni);
+    or_rates(c, sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]), dV, kuni);
   }
   memset(s->fires, 0, sizeof(int64_t) * 3 * (size_t)ncell);
   uint64_t np_before = s->np;
@@ -547,22 +560,25 @@ int or_react(or_sim* s, double dt) {
 
   for (int64_t cc = 0; cc < ncell; ++cc) {
     int64_t b = start[cc], e = start[cc + 1];
-    if (e == b) continue;
+    /* step 7 acts on every cell where a reaction can fire: one holding electrons, or
+     * (ion-ion recombination) one holding ions of both signs */
+    if (e == b && !(c->beta_np > 0.0 && s->nplus[cc] > 0 && s->nminus[cc] > 0)) continue;
     /* step 7: reactions on the NGP state of the cell */
     int64_t Xe = 0;
     for (int64_t q = b; q < e; ++q) Xe += (int64_t)s->p[order[q].idx].w;
     int64_t X[4] = {Xe, s->nplus[cc], s->nminus[cc], 0};
-    double k[3];
-    if (d->field_mode == OR_FIELD_UNIFORM) { k[0] = kuni[0]; k[1] = kuni[1]; k[2] = kuni[2]; }
+    double k[5];
+    if (d->field_mode == OR_FIELD_UNIFORM) memcpy(k, kuni, sizeof(k));
     else {
       double Ex = s->Ex[cc], Ey = s->Ey[cc], Ez = s->Ez[cc];
-      or_rates(c, sqrt(Ex * Ex + Ey * Ey + Ez * Ez), k);
+      or_rates(c, sqrt(Ex * Ex + Ey * Ey + Ez * Ez), dV, k);
     }
     or_stream st;
     or_stream_init(&st, (uint32_t)cc, step, OR_TAG_KMC, 0, d->seed, d->realization);
-    int64_t f[3];
+    int64_t f[5];
     or_kmc_advance(d, X, k, dt, &st, f);
-    for (int r = 0; r < 3; ++r) { s->fires[3 * cc + r] = f[r]; s->diag.fires[r] += (uint64_t)f[r]; }
+    for (int r = 0; r < 3; ++r) s->fires[3 * cc + r] = f[r];
+    for (int r = 0; r < 5; ++r) s->diag.fires[r] += (uint64_t)f[r];
     s->nplus[cc] = X[1];
     s->nminus[cc] = X[2];
     s->ngamma[cc] = X[3];

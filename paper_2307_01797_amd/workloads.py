@@ -19,6 +19,13 @@ AIR = dict(mu_a=0.0372, mu_E0=1.0e6, mu_b=-0.25, E_floor=1.0e4, D=0.1,
            alpha_A=4.332e5, alpha_B=1.91e7, eta=2000.0, kgamma_ratio=0.0,
            photon_l1=30e-6, photon_l2=2e-3)
 
+# Recombination rows of the air chemistry, with the paper's rate coefficients
+# beta_ep = 1.138e-11 T_e^-0.7 m^3/s and beta_np = 2e-13 m^3/s (gas at 300 K) and a
+# synthetic electron temperature T_e = max(300 K, 1e4 K (E / 1 MV/m)^0.5) (about 2.7 eV
+# at 10 MV/m) in place of the tabulated T_e(E).  Off in every preset above unless merged
+# in (coefficients absent count as zero).
+RECOMBINATION = dict(beta_ep=1.138e-11, beta_ep_b=-0.7, Te_a=1.0e4, Te_b=0.5, beta_np=2.0e-13)
+
 # Plain avalanche: 32^3 grid, dx = 10 um, uniform 10 MV/m along z, 1e4 electrons of
 # weight 1 in a Gaussian blob (sigma = 50 um) at the centre, dt = 1 ps, 200 steps,
 # NGP deposit, hybrid KMC for ionization and attachment, seed 1, FP64.

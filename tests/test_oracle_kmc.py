@@ -40,7 +40,7 @@ def _run_cells(orc, cfg, X0, nsteps, n, E=1e7, k=None):
     if k is None:
         k = orc.rates(cfg, E)
     K = np.tile(k, (n, 1))
-    F = np.zeros((n, 3), dtype=np.int64)
+    F = np.zeros((n, 5), dtype=np.int64)
     for s in range(nsteps):
         X, f = orc.kmc_cells(cfg, X, K, DT, s)
         F += f
