@@ -71,10 +71,10 @@ def parse():
     return p.parse_args()
 
 
-def traffic_from_profile(kernel_label):
-    """Measured HBM bytes per launch of a kernel from a committed counter summary
-    (profiles/*_traffic.md, lines `key: value`), or None when there is none or when a
-    source file it names has changed since the counters were taken."""
+def traffic_from_profile(kernel_label, workload):
+    """Measured HBM bytes per launch of a kernel on a workload from a committed counter
+    summary (profiles/*_traffic.md, lines `key: value`), or None when there is none or
+    when a source file it names has changed since the counters were taken."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
@@ -83,7 +83,7 @@ def traffic_from_profile(kernel_label):
             m = re.match(r"^- (\w+): (.+)$", line.strip())
             if m:
                 kv[m.group(1)] = m.group(2).strip()
-        if kv.get("kernel") != kernel_label or "sources" not in kv:
+        if kv.get("kernel") != kernel_label or kv.get("workload") != workload or "sources" not in kv:
             continue
         h = hashlib.sha256()
         for rel in kv["sources"].split():
@@ -324,10 +324,9 @@ def main():
     sim.step(args.warmup)
     torch.cuda.synchronize(dev)
     w = timed_windows(sim, cfg, args.steps, dev)
+    for ph, r in w["roofs"].items():
+        r["traffic"] = traffic_from_profile(KERNELS[ph], cfg["name"])
     roof = max(w["roofs"].values(), key=lambda r: r["total_ms"]) if w["roofs"] else None
-    if roof is not None:
-        ph = next(p for p, r in w["roofs"].items() if r is roof)
-        roof["traffic"] = traffic_from_profile(KERNELS[ph])
     d0, d1, d2 = w["diag"]
     out = {
         "metric": "particle-steps/s (push+sort+deposit+KMC)",

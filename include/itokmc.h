@@ -57,7 +57,8 @@ enum {
   ITOKMC_Q_CIC_DENSITY = 4,/* double per cell: electron density (m^-3), CIC           */
   ITOKMC_Q_PHI = 5,        /* double per cell: potential (V), field mode POISSON      */
   ITOKMC_Q_EX = 6, ITOKMC_Q_EY = 7, ITOKMC_Q_EZ = 8, /* double per cell: E (V/m)     */
-  ITOKMC_Q_FIRES = 9,      /* uint32 per cell x 3: reaction fires of the last step    */
+  ITOKMC_Q_FIRES = 9,      /* uint32 per cell x 3: ionization, attachment and emission
+                              fires of the last step (recombination: totals only)    */
   ITOKMC_Q_RHO = 10        /* double per cell: space charge e((n+ - n-)/dV - n_e) with
                               n_e the CIC density of the current particles (C/m^3)   */
 };
@@ -100,10 +101,17 @@ typedef struct {
  * section "Particle transport"): mu(E) = mu_a (max(E,E_floor)/mu_E0)^mu_b, constant
  * D, alpha(E) = alpha_A exp(-alpha_B/E), eta constant; k_alpha = alpha mu E,
  * k_eta = eta mu E, k_gamma = kgamma_ratio k_alpha; photon mean absorption length
- * log-uniform in [photon_l1, photon_l2]. */
+ * log-uniform in [photon_l1, photon_l2].
+ * Recombination (the electron-ion and ion-ion rows of the air-chemistry table, rates of
+ * the section "Simulation conditions"; each reaction is off when its coefficient is 0):
+ * k_ep = beta_ep T_e^beta_ep_b / dV with the electron temperature
+ * T_e = max(300 K, Te_a (max(E,E_floor)/mu_E0)^Te_b) (a synthetic stand-in for the
+ * tabulated T_e(E)), k_np = beta_np / dV; propensities k_ep X_e X_M+ and
+ * k_np X_M+ X_M-.  The batched ensemble does not take recombination (EINVAL). */
 typedef struct {
   double mu_a, mu_E0, mu_b, E_floor, D, alpha_A, alpha_B, eta, kgamma_ratio;
   double photon_l1, photon_l2;
+  double beta_ep, beta_ep_b, Te_a, Te_b, beta_np;
 } itokmc_coeffs;
 
 /* Initial particles.  GAUSSIAN: n0 electrons of weight 1 at centre + sigma N(0,1)^3,
@@ -123,7 +131,8 @@ typedef struct {
   int64_t n_plus, n_minus;
   int64_t charge;                 /* sum(n+ - n_e - n-), units of e                  */
   uint64_t outflow_weight;
-  uint64_t fires[3];              /* cumulative: ionization, attachment, emission    */
+  uint64_t fires[5];              /* cumulative: ionization, attachment, emission,
+                                     electron-ion and ion-ion recombination          */
   uint64_t photons_emitted, photons_absorbed, photons_lost;
   uint64_t created, removed_weight, merged_cells;
   uint32_t step;
@@ -373,9 +382,10 @@ const char* itokmc_ensemble_last_error(const itokmc_ens* ens);
  * i < n, key (k0, k1): out is 4 n uint32. */
 int itokmc_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                        uint32_t k1, uint64_t n, uint32_t* dev_out, void* stream);
-/* One KMC step on n independent cells with the context's method parameters:
- * X (n x 4 int64: e, M+, M-, gamma; in/out), k (n x 3 double rates, 1/s), cell ids
- * (n uint32, stream keys), fires (n x 3 int64 out); all device pointers. */
+/* One KMC step on n independent cells with the context's method parameters (section
+ * "Reaction algorithm outline"): X (n x 4 int64: e, M+, M-, gamma; in/out), k (n x 5
+ * double rates, 1/s: k_alpha, k_eta, k_gamma, k_ep, k_np), cell ids (n uint32, stream
+ * keys), fires (n x 5 int64 out); all device pointers. */
 int itokmc_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* dev_cell_ids,
                      int64_t* dev_X, const double* dev_k, double dt, uint32_t step,
                      int64_t* dev_fires);

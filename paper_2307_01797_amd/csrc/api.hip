@@ -70,8 +70,22 @@ static void phase_collect(itokmc_ctx* ctx) {
   ctx->ev_used.clear();
 }
 
+// Electron-ion and ion-ion recombination rates in a cell of edge dx at field magnitude
+// Em: k_ep = beta_ep T_e^beta_ep_b / dV with T_e = max(300 K, Te_a (max(Em,
+// E_floor)/mu_E0)^Te_b), k_np = beta_np / dV (0 when the coefficient is 0).
+void recomb_rates(const itokmc_coeffs& c, double Em, double dx, double k[2]) {
+  const double dV = dx * dx * dx;
+  k[0] = 0.0;
+  if (c.beta_ep > 0.0) {
+    const double E = Em > c.E_floor ? Em : c.E_floor;
+    const double Te = fmax(300.0, c.Te_a * pow(E / c.mu_E0, c.Te_b));
+    k[0] = c.beta_ep * pow(Te, c.beta_ep_b) / dV;
+  }
+  k[1] = c.beta_np > 0.0 ? c.beta_np / dV : 0.0;
+}
+
 void uniform_consts(const itokmc_grid_desc& d, const itokmc_coeffs& c, double dt,
-                    double drift[3], double* diff, double k[3]) {
+                    double drift[3], double* diff, double k[5]) {
   *diff = sqrt(2.0 * c.D * dt) / d.dx;
   const double* E = d.E_uniform;
   const double Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
@@ -82,6 +96,7 @@ void uniform_consts(const itokmc_grid_desc& d, const itokmc_coeffs& c, double dt
   k[0] = alpha * v;
   k[1] = c.eta * v;
   k[2] = c.kgamma_ratio * k[0];
+  recomb_rates(c, Em, d.dx, k + 3);
 }
 
 StepConst make_const(const itokmc_ctx* ctx, double dt) {
@@ -174,11 +189,12 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
 
 int check_coeffs(const itokmc_coeffs* c, std::string* why) {
   const double v[] = {c->mu_a, c->mu_E0, c->mu_b, c->E_floor, c->D, c->alpha_A, c->alpha_B,
-                      c->eta, c->kgamma_ratio, c->photon_l1, c->photon_l2};
+                      c->eta, c->kgamma_ratio, c->photon_l1, c->photon_l2, c->beta_ep,
+                      c->beta_ep_b, c->Te_a, c->Te_b, c->beta_np};
   for (double x : v)
     if (!isfinite(x)) { *why = "non-finite coefficient"; return ITOKMC_EINVAL; }
   if (c->mu_a < 0 || !(c->mu_E0 > 0) || !(c->E_floor > 0) || c->D < 0 || c->alpha_A < 0 ||
-      c->eta < 0 || c->kgamma_ratio < 0) {
+      c->eta < 0 || c->kgamma_ratio < 0 || c->beta_ep < 0 || c->Te_a < 0 || c->beta_np < 0) {
     *why = "negative transport or rate coefficient";
     return ITOKMC_EINVAL;
   }
@@ -431,7 +447,7 @@ int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
   out->n_minus = (int64_t)host[3];
   out->charge = (int64_t)host[2] - (int64_t)host[1] - (int64_t)host[3];
   out->outflow_weight = c.outflow;
-  for (int r = 0; r < 3; ++r) out->fires[r] = c.fires[r];
+  for (int r = 0; r < 5; ++r) out->fires[r] = c.fires[r];
   out->photons_emitted = c.ph_emitted;
   out->photons_absorbed = c.ph_absorbed;
   out->photons_lost = c.ph_lost;

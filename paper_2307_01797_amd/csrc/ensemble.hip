@@ -319,19 +319,20 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
     for (int r = 0; r < kEnsKmcPer; ++r) {
       const uint32_t jj = base + (uint32_t)r * blockDim.x + threadIdx.x;
       js[r] = 0; Ms[r] = 0; fl[r] = 0;
-      uint32_t skey = kInvalidCell, M = 0, j = 0;
+      uint32_t skey = kInvalidCell, M = 0, j = 0, g = 0;
       int64_t d = 0;
       int64_t f[3] = {0, 0, 0};
+      State X{0, 0, 0, 0};
       bool defer = false;
       if (jj < n) {
         j = kFast ? jj : heavy[jj];
-        const uint32_t g = occ[j];
+        g = occ[j];
         const uint32_t Xe = (uint32_t)cellacc[g];
         const int s = blk_slot[g >> kBlkShift];
         if (s >= 0 && sc[s].state == ITOKMC_SLOT_ACTIVE) {
           const SlotConst& S = sc[s];
           const uint32_t c = to_local(g, blk_local);
-          State X{(int64_t)Xe, (int64_t)nplus[g], (int64_t)nminus[g], 0};
+          X = State{(int64_t)Xe, (int64_t)nplus[g], (int64_t)nminus[g], 0};
           const double k[3] = {S.k[0], S.k[1], S.k[2]};
           CellStream cs;
           cs.init(c, S.step, TAG_KMC, 0, S.key);
@@ -339,8 +340,6 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
           else advance(S.kp, X, k, S.dt, cs, f);
           if (!defer) {
             skey = (uint32_t)s;
-            nplus[g] = (uint32_t)X.p;
-            nminus[g] = (uint32_t)X.m;
             d = X.e - (int64_t)Xe;
             if (d > 0) M = d < (int64_t)S.n_new ? (uint32_t)d : S.n_new;
           }
@@ -349,13 +348,23 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
       }
       // quota: live particles kept by the push plus products reserved so far
       const uint64_t before = run_add(st + S_PROD * ms, M ? skey : kInvalidCell, M);
+      bool apply = skey != kInvalidCell;
       if (M) {
         const uint64_t kept = st[S_LIVE * ms + skey] - st[S_LEFT * ms + skey];
         if (kept + before + M > (uint64_t)sc[skey].quota) {
+          // products dropped: the realization is capped and stops after this step.  The
+          // cell keeps its state from before the reactions (ions, electrons and tallies
+          // together), so that the realization's charge stays exact.
           M = 0;
-          d = 0;  // products dropped: the realization is capped and stops after this step
+          d = 0;
+          f[0] = f[1] = f[2] = 0;
+          apply = false;
           atomicOr(&st[S_CAPPED * ms + skey], 1ull);
         }
+      }
+      if (apply) {
+        nplus[g] = (uint32_t)X.p;
+        nminus[g] = (uint32_t)X.m;
       }
       if (jj < n && !defer) {
         dN[j] = (int32_t)d;
@@ -877,6 +886,8 @@ int itokmc_ensemble_admit(itokmc_ens* e, const itokmc_grid_desc* d, const itokmc
                      "ensemble realizations need a uniform field, n_ppc 0 and the ensemble's precision");
   std::string why;
   if (check_coeffs(c, &why)) return ens_error(e, ITOKMC_EINVAL, "%s", why.c_str());
+  if (c->beta_ep > 0.0 || c->beta_np > 0.0)
+    return ens_error(e, ITOKMC_EINVAL, "the ensemble does not take recombination");
   if (c->kgamma_ratio != 0.0) return ens_error(e, ITOKMC_EINVAL, "ensemble realizations carry no photons");
   if (sd->kind != ITOKMC_SEED_GAUSSIAN || !(sd->sigma > 0.0))
     return ens_error(e, ITOKMC_EINVAL, "ensemble seeds are Gaussian electrons with sigma > 0");
@@ -920,7 +931,9 @@ int itokmc_ensemble_admit(itokmc_ens* e, const itokmc_grid_desc* d, const itokmc
   v.stop = r->stop_particles;
   v.kp = KmcParams{d->kmc_mode, d->kmc_nc, d->kmc_nssa, d->kmc_eps};
   v.dt = r->dt;
-  uniform_consts(*d, *c, r->dt, v.drift, &v.diff, v.k);
+  double k5[5];
+  uniform_consts(*d, *c, r->dt, v.drift, &v.diff, k5);
+  for (int i = 0; i < 3; ++i) v.k[i] = k5[i];
   hipError_t h = update_hw(e);
   if (h == hipSuccess) {
     e_set_slot<<<1, 64, 0, e->s>>>(v, s, e->sc, e->st, e->stat2, e->ms);

@@ -2062,6 +2062,9 @@ FieldRates field_rates(itokmc_ctx* ctx) {
   r.mu_a = ctx->c.mu_a; r.mu_E0 = ctx->c.mu_E0; r.mu_b = ctx->c.mu_b; r.E_floor = ctx->c.E_floor;
   r.alpha_A = ctx->c.alpha_A; r.alpha_B = ctx->c.alpha_B; r.eta = ctx->c.eta;
   r.kgamma_ratio = ctx->c.kgamma_ratio;
+  r.beta_ep = ctx->c.beta_ep; r.beta_ep_b = ctx->c.beta_ep_b; r.Te_a = ctx->c.Te_a;
+  r.Te_b = ctx->c.Te_b; r.beta_np = ctx->c.beta_np;
+  r.dV = ctx->d.dx * ctx->d.dx * ctx->d.dx;
   return r;
 }
 

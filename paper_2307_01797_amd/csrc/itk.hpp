@@ -42,7 +42,7 @@ struct Counters {
   uint32_t n_heavy;       // occupied cells left to the full KMC pass
   uint32_t n_huge;        // cells deferred past the mid-size merge staging
   unsigned long long outflow, created, removed, merged;
-  unsigned long long fires[3];
+  unsigned long long fires[5];  // ionization, attachment, emission, e-ion, ion-ion
   unsigned long long ph_emitted, ph_absorbed, ph_lost;
   unsigned long long pushed;   // live particles advanced by the transport kernels
   uint32_t merge_skipped;      // cells too large for the LDS merge (left unmerged)
@@ -62,7 +62,7 @@ struct StepConst {
   double dx, dt;
   double drift[3];   // uniform mode: -mu E dt / dx per axis (grid units)
   double diff;       // sqrt(2 D dt) / dx (grid units per unit normal)
-  double k[3];       // uniform mode rates (1/s)
+  double k[5];       // uniform mode rates (1/s): k_alpha, k_eta, k_gamma, k_ep, k_np
   // multiply-shift division by nx and by ny: floor(c / d) = (c * m) >> s for every
   // c < 2^24, with s = 24 + ceil(log2 d) and m = ceil(2^s / d) (< 2^25)
   uint32_t mdx, sdx, mdy, sdy;
@@ -92,6 +92,7 @@ struct FieldRates {
   const void* E4;
   int is_double;
   double mu_a, mu_E0, mu_b, E_floor, alpha_A, alpha_B, eta, kgamma_ratio;
+  double beta_ep, beta_ep_b, Te_a, Te_b, beta_np, dV;  // recombination (0: off)
 };
 
 }  // namespace itk
@@ -162,7 +163,12 @@ int check_hip(itokmc_ctx* ctx, hipError_t e, const char* what);
 StepConst make_const(const itokmc_ctx* ctx, double dt);
 // Uniform-field drift and diffusion per step (grid units) and rates (1/s).
 void uniform_consts(const itokmc_grid_desc& d, const itokmc_coeffs& c, double dt,
-                    double drift[3], double* diff, double k[3]);
+                    double drift[3], double* diff, double k[5]);
+void recomb_rates(const itokmc_coeffs& c, double Em, double dx, double k[2]);
+// Recombination (electron-ion or ion-ion) is part of the context's network.
+inline bool recombination(const itokmc_ctx* ctx) {
+  return ctx->c.beta_ep > 0.0 || ctx->c.beta_np > 0.0;
+}
 bool valid_desc(const itokmc_grid_desc* d);
 int check_coeffs(const itokmc_coeffs* c, std::string* why);
 // particles.hip

@@ -113,41 +113,51 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
   const T drift[3] = {(T)k.drift[0], (T)k.drift[1], (T)k.drift[2]};
   const T diff = (T)k.diff;
   uint64_t out_w = 0, pushed = 0;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    uint32_t key = kInvalidCell;
-    // all of the particle's words in one round trip, before its weight is tested
-    uint32_t w = 0, cell = 0;
-    uint64_t id = 0;
-    T o[3] = {(T)0, (T)0, (T)0};
-    if (i < n) {
-      w = a.w[i];
-      cell = a.cell[i];
-      id = a.id[i];
-      o[0] = as<T>(a.ox)[i];
-      o[1] = as<T>(a.oy)[i];
-      o[2] = as<T>(a.oz)[i];
-    }
-    if (w > 0) {
-      ++pushed;
-      int ci[3];
-      cell_ijk(cell, k, ci[0], ci[1], ci[2]);
-      const int lim[3] = {k.nx, k.ny, k.nz};
-      const bool inside = push_uniform<T>(id, k.step, k.key, drift, diff, lim, ci, o);
-      if (inside) {
-        key = (uint32_t)ci[0] + (uint32_t)k.nx * ((uint32_t)ci[1] + (uint32_t)k.ny * (uint32_t)ci[2]);
-        a.cell[i] = key;
-        as<T>(a.ox)[i] = o[0];
-        as<T>(a.oy)[i] = o[1];
-        as<T>(a.oz)[i] = o[2];
-      } else {
-        out_w += w;
-        a.w[i] = 0;  // removed at the domain face
+  const int lim[3] = {k.nx, k.ny, k.nz};
+  // two particles per thread (a workgroup-sized stride apart, so that loads stay
+  // coalesced): both particles' words are requested before either is pushed
+  for (uint32_t base = blockIdx.x * blockDim.x * 2u; base < n; base += gridDim.x * blockDim.x * 2u) {
+    uint32_t ii[2] = {base + threadIdx.x, base + blockDim.x + threadIdx.x};
+    uint32_t w[2] = {0, 0}, cell[2] = {0, 0};
+    uint64_t id[2] = {0, 0};
+    T o[2][3] = {{(T)0, (T)0, (T)0}, {(T)0, (T)0, (T)0}};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (ii[q] < n) {
+        w[q] = a.w[ii[q]];
+        cell[q] = a.cell[ii[q]];
+        id[q] = a.id[ii[q]];
+        o[q][0] = as<T>(a.ox)[ii[q]];
+        o[q][1] = as<T>(a.oy)[ii[q]];
+        o[q][2] = as<T>(a.oz)[ii[q]];
       }
     }
-    const uint32_t rank = bin_add(cellacc, key, w);
-    mark_tile(tiles, key, (uint64_t)rank << 32);
-    if (key != kInvalidCell) a.rank[i] = rank;
+    uint32_t key[2] = {kInvalidCell, kInvalidCell};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (w[q] > 0) {
+        ++pushed;
+        int ci[3];
+        cell_ijk(cell[q], k, ci[0], ci[1], ci[2]);
+        const bool inside = push_uniform<T>(id[q], k.step, k.key, drift, diff, lim, ci, o[q]);
+        if (inside) {
+          key[q] = (uint32_t)ci[0] + (uint32_t)k.nx * ((uint32_t)ci[1] + (uint32_t)k.ny * (uint32_t)ci[2]);
+          a.cell[ii[q]] = key[q];
+          as<T>(a.ox)[ii[q]] = o[q][0];
+          as<T>(a.oy)[ii[q]] = o[q][1];
+          as<T>(a.oz)[ii[q]] = o[q][2];
+        } else {
+          out_w += w[q];
+          a.w[ii[q]] = 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t rank = bin_add(cellacc, key[q], w[q]);
+      mark_tile(tiles, key[q], (uint64_t)rank << 32);
+      if (key[q] != kInvalidCell) a.rank[ii[q]] = rank;
+    }
   }
   out_w = wave_sum64(out_w);
   pushed = wave_sum64(pushed);

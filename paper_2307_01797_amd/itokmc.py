@@ -59,7 +59,12 @@ class GridDesc(ctypes.Structure):
 class Coeffs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("mu_a", "mu_E0", "mu_b", "E_floor", "D", "alpha_A",
                                                "alpha_B", "eta", "kgamma_ratio", "photon_l1",
-                                               "photon_l2")]
+                                               "photon_l2", "beta_ep", "beta_ep_b", "Te_a", "Te_b",
+                                               "beta_np")]
+
+
+# recombination coefficients are optional in a coefficient set (absent: reaction off)
+RECOMB_FIELDS = ("beta_ep", "beta_ep_b", "Te_a", "Te_b", "beta_np")
 
 
 class Tuning(ctypes.Structure):
@@ -77,7 +82,7 @@ class Diag(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_uint64), ("weight", ctypes.c_uint64),
                 ("n_plus", ctypes.c_int64), ("n_minus", ctypes.c_int64),
                 ("charge", ctypes.c_int64), ("outflow_weight", ctypes.c_uint64),
-                ("fires", ctypes.c_uint64 * 3), ("photons_emitted", ctypes.c_uint64),
+                ("fires", ctypes.c_uint64 * 5), ("photons_emitted", ctypes.c_uint64),
                 ("photons_absorbed", ctypes.c_uint64), ("photons_lost", ctypes.c_uint64),
                 ("created", ctypes.c_uint64), ("removed_weight", ctypes.c_uint64),
                 ("merged_cells", ctypes.c_uint64), ("step", ctypes.c_uint32),
@@ -239,7 +244,7 @@ def arena_bytes(cfg, precision=None, max_particles=None):
 def make_coeffs(cfg):
     c = Coeffs()
     for n, _ in Coeffs._fields_:
-        setattr(c, n, cfg["coeffs"][n])
+        setattr(c, n, cfg["coeffs"].get(n, 0.0) if n in RECOMB_FIELDS else cfg["coeffs"][n])
     return c
 
 
@@ -398,15 +403,19 @@ class Sim:
         return self._check(lib().itokmc_set_field(self.h, _np(phi)))
 
     def kmc_cells(self, X, k, dt, step, cell_ids=None):
-        """One KMC step on independent cells (kernel-level entry point)."""
+        """One KMC step on independent cells (kernel-level entry point).  k: (n,3) or
+        (n,5) rates (missing recombination rates are zero); returns X and fires (n,5)."""
         torch = self.torch
         X = np.ascontiguousarray(X, dtype=np.int64)
         n = X.shape[0]
         ids = np.arange(n, dtype=np.uint32) if cell_ids is None else np.asarray(cell_ids, np.uint32)
+        k = np.asarray(k, dtype=np.float64).reshape(n, -1)
+        k5 = np.zeros((n, 5))
+        k5[:, :k.shape[1]] = k
         dX = torch.from_numpy(X.copy()).to(self.device)
-        dk = torch.from_numpy(np.ascontiguousarray(k, dtype=np.float64)).to(self.device)
+        dk = torch.from_numpy(k5).to(self.device)
         di = torch.from_numpy(ids.astype(np.int32)).to(self.device)
-        df = torch.zeros((n, 3), dtype=torch.int64, device=self.device)
+        df = torch.zeros((n, 5), dtype=torch.int64, device=self.device)
         self.stream.synchronize()
         self._check(lib().itokmc_kmc_cells(self.h, n, ctypes.c_void_p(di.data_ptr()),
                                            ctypes.c_void_p(dX.data_ptr()),

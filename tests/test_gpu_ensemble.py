@@ -226,7 +226,19 @@ def test_capped_realization_stops(itk):
     done = _drain(ens)
     assert done[s0][0] == itk.SLOT_CAPPED and done[s0][2] < 120
     assert done[s1][0] == itk.SLOT_DONE
-    assert ens.result(s0)["overflow"] == 1
+    r0 = ens.result(s0)
+    assert r0["overflow"] == 1
+    # the capped step drops whole cells (their reactions with their products), so the
+    # charge identity of the reaction table still holds exactly
+    g0 = itk.Sim(cfgs[0], max_particles=cfgs[0]["max_particles"])
+    g0.seed()
+    w0 = g0.diagnostics()["weight"]
+    _, _, w, _ = ens.particles(s0)
+    plus = ens.counts(s0, "plus").astype(np.int64).sum()
+    minus = ens.counts(s0, "minus").astype(np.int64).sum()
+    assert int(w.astype(np.int64).sum()) == r0["weight"]
+    assert plus - minus - r0["weight"] == -w0 + r0["outflow_weight"]
+    assert r0["n_plus"] == plus and r0["n_minus"] == minus
     _assert_same(_ens_state(ens, s1, cfgs[1]["grid"]), _plain_state(_run_plain(itk, cfgs[1])))
 
 

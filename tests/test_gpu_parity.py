@@ -441,3 +441,87 @@ def test_split_order_fp64_agrees(itk):
     (pa, ea, _, _), (pb, eb, _, _) = _split_vs_natural(itk, "fp64", (48, 32, 40), 2)
     assert np.abs(pa - pb).max() < 1e-8 * np.abs(pb).max()
     assert np.abs(ea - eb).max() < 1e-7 * np.abs(eb).max()
+
+
+# ---- recombination (rows 3 and 4 of the air table) ------------------------------------
+
+def _recomb(scale, **kw):
+    c = dict(workloads.RECOMBINATION, **kw)
+    c["beta_ep"] *= scale
+    c["beta_np"] *= scale
+    return c
+
+
+@pytest.mark.parametrize("mode,eps", [("hybrid", np.inf), ("pure_tau", np.inf), ("hybrid", 0.03)])
+def test_kmc_cells_recombination_bit_exact(itk, orc, mode, eps):
+    """The five-reaction code on independent cells: SSA, critical and leap regimes of
+    both second-order reactions (small, medium and large populations, cells without
+    electrons), every fire count and population equal to the oracle's."""
+    cfg = workloads.preset("avalanche_32", kmc=mode, kmc_eps=eps,
+                           coeffs=dict(kgamma_ratio=0.06, **workloads.RECOMBINATION))
+    g = itk.Sim(cfg, precision="fp64", max_particles=1024)
+    rng = np.random.default_rng(11)
+    n = 30000
+    t = n // 4
+    X = np.zeros((n, 4), dtype=np.int64)
+    X[:, 0] = np.concatenate([rng.integers(0, 8, t), rng.integers(8, 300, t),
+                              rng.integers(300, 200000, t), np.zeros(n - 3 * t, np.int64)])
+    X[:, 1] = np.concatenate([rng.integers(0, 10, t), rng.integers(0, 3000, n - t)])
+    X[:, 2] = np.concatenate([rng.integers(0, 10, t), rng.integers(0, 3000, n - t)])
+    rng.shuffle(X)
+    E = 10 ** rng.uniform(6.0, 7.6, n)
+    k = np.array([orc.rates(cfg, e) for e in E])
+    k[:, 3] = 10 ** rng.uniform(-2, 7, n)
+    k[:, 4] = np.where(rng.random(n) < 0.2, 0.0, 10 ** rng.uniform(-2, 8, n))
+    for step, dt in ((0, 1e-12), (9, 3e-12)):
+        gX, gf = g.kmc_cells(X, k, dt, step)
+        oX, of = orc.kmc_cells(cfg, X, k, dt, step)
+        assert np.array_equal(gf, of), np.argwhere(gf != of)[:5]
+        assert np.array_equal(gX, oX)
+        assert of[:, 3].sum() > 0 and of[:, 4].sum() > 0
+
+
+def test_avalanche_recombination_fp64(itk, orc):
+    """The plain avalanche with (scaled) electron-ion and ion-ion recombination, FP64,
+    free-running: every integer agrees, including the cells that hold only ions."""
+    cfg = workloads.preset("avalanche_32", coeffs=_recomb(1e7), seed_n0=3000)
+    g = itk.Sim(cfg, precision="fp64", max_particles=400_000)
+    g.seed()
+    o = orc.Sim(cfg)
+    o.seed_gaussian(cfg["seed_n0"], cfg["seed_centre"], cfg["seed_sigma"])
+    done = 0
+    for target in (1, 5, 20, 60):
+        g.step(target - done)
+        o.step(cfg["dt"], target - done)
+        done = target
+        assert _compare(g, o, cfg, 1e-9) == 0
+        _compare_tallies(g, o)
+    d = g.diagnostics()
+    assert d["fires"][3] > 0 and d["fires"][4] > 0
+    assert d["charge"] == o.diagnostics()["charge"]
+
+
+def test_streamer_recombination_fp64(itk, orc):
+    """The self-consistent streamer seed (16^3, semi-implicit field, photons, merging)
+    with recombination rates from the field at each cell centre, FP64, free-running."""
+    cfg = _streamer_small(coeffs=_recomb(1e7))
+    g = itk.Sim(cfg, precision="fp64")
+    g.seed()
+    o = orc.Sim(cfg)
+    o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+    for target in (1, 3, 6):
+        n = target - g.diagnostics()["step"]
+        g.step(n)
+        o.step(cfg["dt"], n)
+        assert _compare(g, o, cfg, 1e-9) == 0
+        _compare_tallies(g, o)
+    assert g.diagnostics()["fires"][3] > 0
+
+
+def test_ensemble_rejects_recombination(itk):
+    cfg = workloads.ensemble_realization(0)
+    cfg["coeffs"].update(workloads.RECOMBINATION)
+    ens = itk.Ensemble(2, 1 << 20, 1_000_000)
+    with pytest.raises(itk.ItokmcError) as e:
+        ens.admit(cfg)
+    assert e.value.code == itk.EINVAL and "recombination" in str(e.value)
