@@ -24,8 +24,10 @@ HBM_PEAK_GBS = 8000.0
 # Single-kernel phases timed with HIP events (library profiling mode), the kernel each
 # one is, and its algorithmic HBM bytes per unit (S = 4 in single, 8 in double precision):
 #   push / field_push (per live particle): read cell 4 + offsets 3S + id 8 + weight 4,
-#                      write cell 4 + offsets 3S + rank 4
-#   deposit (per particle): read cell 4 + offsets 3S + id 8 + weight 4
+#                      write cell 4 + offsets 3S + rank 4; field_push also reads the
+#                      particle's mobility (S) that the deposit kept
+#   deposit (per particle): read cell 4 + offsets 3S + id 8 + weight 4, write the
+#                      particle's mobility S
 #   scatter (per particle): read cell 4 + rank 4 + offsets 3S + weight 4 + id 8, write
 #                      cell 4 + offsets 3S + weight 4 + id 8
 #   couple (per particle gathered by the wavefront-per-cell coupling kernel: cells that
@@ -39,7 +41,7 @@ KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k
 
 
 def bytes_per_unit(phase, S):
-    return {"push": 24 + 6 * S, "field_push": 24 + 6 * S, "deposit": 16 + 3 * S,
+    return {"push": 24 + 6 * S, "field_push": 24 + 7 * S, "deposit": 16 + 4 * S,
             "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 5 * S / 2}[phase]
 
 
@@ -372,12 +374,13 @@ def push_deposit_roofline(roofs, psteps, S):
     """The particle push with its fused NGP binning and the charge deposit together:
     44 B per particle-step for the push (read cell 4 + offsets 3 x 4 + id 8 + weight 4,
     write cell 4 + offsets 3 x 4) and, in the self-consistent step, 28 B for the
-    deposit pass (read cell, offsets, weight and id), over the two kernels' time."""
+    deposit pass (read cell, offsets, weight and id) plus the particle's mobility that
+    the deposit writes and the push reads (2 x 4 B), over the two kernels' time."""
     push = roofs.get("field_push") or roofs.get("push")
     if push is None:
         return None
     dep = roofs.get("deposit")
-    per = (20 + 6 * S) + (16 + 3 * S if dep else 0)
+    per = (20 + 6 * S) + (16 + 3 * S + 2 * S if dep else 0)
     t_ms = push["total_ms"] + (dep["total_ms"] if dep else 0.0)
     achieved = per * psteps / (t_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -184,6 +184,7 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(nc * 4);                        // 32 huge (large merge list)
   put(nc * 4);                        // 33 cells for the wavefront coupling pass
   put(nc * 4);                        // 34 cells to merge after the light pass
+  put(d->field_mode == ITOKMC_FIELD_POISSON ? cap * T : 64);  // 35 mobility per particle
   L->total = o;
 }
 
@@ -267,6 +268,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->huge = (uint32_t*)(a + L.off[32]);
   ctx->cfull = (uint32_t*)(a + L.off[33]);
   ctx->cmerge = (uint32_t*)(a + L.off[34]);
+  ctx->mu_p = a + L.off[35];
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);

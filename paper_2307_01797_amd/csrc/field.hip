@@ -291,7 +291,8 @@ template <> struct DepAcc<float> {
 // one global atomic per touched node and field.  Mode 0 deposits the electron number
 // at X^k only (initial field); mode 1 deposits the conductivity weight mu(|E^k|) w at
 // X^k and the electron number at X_dagger (the position after the diffusive part of
-// the step, with the normals of the push).
+// the step, with the normals of the push), and keeps each particle's mobility mu^k for
+// the push, which then reads it instead of interpolating E^k again.
 // A 1024-entry table per 256-particle chunk, one particle per thread (20 KB of LDS):
 // small tables raise the number of resident workgroups, a table four times the chunk
 // keeps probing short, and with the row-ordered slots a chunk's nodes rarely collide.
@@ -351,7 +352,8 @@ template <typename T, int L2>
 __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
                                                           StepConst K, const void* E4, Coef co,
                                                           int mode, typename DepAcc<T>::S* sig,
-                                                          typename DepAcc<T>::S* ne, uint32_t chunk) {
+                                                          typename DepAcc<T>::S* ne, uint32_t chunk,
+                                                          T* mu_out) {
   using S = typename DepAcc<T>::S;
   constexpr int TBL = 1 << L2;
   extern __shared__ __align__(16) char smem[];
@@ -388,6 +390,7 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
       cic_get3<T>(ctp<T>(E4), K, i0, j0, k0, fx, fy, fz, e);
       const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
       const T mu = Mob<T>::mu(co, Em);
+      mu_out[i] = mu;
       tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (double)mu * (double)w, 0.0, sig, ne);
       const uint64_t id = a.id[i];
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
@@ -414,8 +417,7 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
 template <typename T>
 __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int which,
                                                    unsigned long long* cellacc, uint32_t* tiles,
-                                                   StepConst K, const void* Eo4, const void* En4,
-                                                   Coef co) {
+                                                   StepConst K, const T* mu_in, const void* En4) {
   const uint32_t n = min(ctr->n[which], K.cap);
   const T diff = (T)K.diff;
   const T dtdx = (T)(K.dt / K.dx);
@@ -427,6 +429,7 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
     uint32_t cell0 = 0;
     T o0[3] = {(T)0, (T)0, (T)0};
     uint64_t id0 = 0;
+    T mu0 = (T)0;
     if (i < n) {
       w = a.w[i];
       cell0 = a.cell[i];
@@ -434,6 +437,7 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
       o0[1] = tp<T>(a.oy)[i];
       o0[2] = tp<T>(a.oz)[i];
       id0 = a.id[i];
+      mu0 = mu_in[i];
     }
     if (w > 0) {
       ++pushed;
@@ -446,14 +450,12 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
       tent_axis<T>(ci[0], o[0], K.nx, i0, fx);
       tent_axis<T>(ci[1], o[1], K.ny, j0, fy);
       tent_axis<T>(ci[2], o[2], K.nz, k0, fz);
-      T eo[3], en[3];
-      CicNodes<T> go, gn;
-      cic_load<T>(ctp<T>(Eo4), K, i0, j0, k0, fx, fy, fz, go);
+      T en[3];
+      CicNodes<T> gn;
       cic_load<T>(ctp<T>(En4), K, i0, j0, k0, fx, fy, fz, gn);
-      __builtin_amdgcn_sched_barrier(0);  // the sixteen gathers in flight together
-      cic_sum<T>(go, eo);
+      __builtin_amdgcn_sched_barrier(0);  // the eight gathers in flight together
       cic_sum<T>(gn, en);
-      const T mu = Mob<T>::mu(co, sqrt(eo[0] * eo[0] + eo[1] * eo[1] + eo[2] * eo[2]));
+      const T mu = mu0;  // mu(|E^k(X^k)|), kept by this step's deposit
       const uint64_t id = id0;
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
       T nr[3];
@@ -1996,7 +1998,7 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
     k_field_deposit_lds<T, L2><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo,
                                                    coef(ctx), mode, (S*)F->sig, (S*)F->ne,
-                                                   (uint32_t)kDepChunk);
+                                                   (uint32_t)kDepChunk, (T*)ctx->mu_p);
   }
   phase_end(ctx, PH_DEPOSIT);
   phase_begin(ctx, PH_FIELD_PREP);
@@ -2043,7 +2045,7 @@ static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
   // at most 1024 workgroups looping over the particles: 0.375 ms per step at 9.5e6
   // particles against 0.405 ms with 4096 and 0.45 ms with 512
   k_push_field<T><<<blocks(ctx->cap, 1024), 256, 0, ctx->s>>>(
-      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, F->E[F->cur], F->E[nxt], coef(ctx));
+      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, (const T*)ctx->mu_p, F->E[nxt]);
   phase_end(ctx, PH_FIELD_PUSH);
   F->cur = nxt;  // E^{k+1} becomes the field of the next step
   return check_hip(ctx, hipGetLastError(), "field push");

@@ -123,6 +123,8 @@ struct itokmc_ctx {
   uint32_t* huge = nullptr;               // occupied-cell indices for the large merge pass
   uint32_t* cfull = nullptr;              // cells for the wavefront coupling pass
   uint32_t* cmerge = nullptr;             // cells to merge after the light coupling pass
+  void* mu_p = nullptr;                   // per particle (self-consistent mode): mu(|E^k(X^k)|)
+                                          // written by the deposit, read by the push
   uint32_t* heavy = nullptr;              // occupied-cell indices for the full KMC pass
   double* rates = nullptr;                // 3 per occupied cell: rates handed to the full pass
   uint32_t* blocksums = nullptr;          // scan scratch
