@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 #                      cell 4 + offsets 3S + weight 4 + id 8
 #   couple (per particle gathered by the wavefront-per-cell coupling kernel: cells that
 #                      merge or hold many particles): read and write cell, offsets,
-#                      weight and id
+#                      weight and id; without merging (n_ppc = 0) the kernel only removes
+#                      weight, reading each gathered particle's weight and id (12 B)
 #   smooth_fine (per finest-level cell and launch of one colour, split red-black order):
 #                      read u and eps of the other colour's cells, f and eps of the
 #                      colour's cells, write u of the colour's cells: 2.5 S
@@ -435,7 +436,10 @@ def timed_windows(sim, cfg, steps, dev):
             units = d2.get("couple_pieces", 0) - d1.get("couple_pieces", 0)
         else:
             units = psteps_p
-        per_launch = bytes_per_unit(ph, S) * units / launches
+        per_unit = bytes_per_unit(ph, S)
+        if ph == "couple" and not cfg.get("n_ppc", 0):
+            per_unit = 12
+        per_launch = per_unit * units / launches
         achieved = per_launch / (tot_ms / launches / 1e3) / 1e9
         roofs[ph] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
