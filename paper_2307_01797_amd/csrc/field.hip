@@ -344,9 +344,10 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
   }
 }
 
-// Single precision: at least 7 waves per SIMD (72 VGPRs, no spills; 0.684 against
-// 0.704 ms at 9.5e6 particles with the compiler's 75 VGPRs and 6 waves; 8 waves spill and
-// are slower).  Double precision keeps the compiler's choice (a 72-VGPR bound spills).
+// Single precision: at least 7 waves per SIMD (72 VGPRs, no spills), which measured about
+// 3% faster than the compiler's 75 VGPRs and 6 waves in a side-by-side run on the same
+// state; 8 waves spill and are slower.  Double precision keeps the compiler's choice (a
+// 72-VGPR bound spills).
 template <typename T> constexpr int kDepMinWaves = sizeof(T) == 4 ? 7 : 1;
 template <typename T, int L2>
 __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
