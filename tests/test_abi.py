@@ -92,3 +92,68 @@ def test_coefficient_validation_on_host():
     assert L.itokmc_check_coefficients(ctypes.byref(c)) == itokmc.EINVAL
     assert L.itokmc_check_coefficients(None) == itokmc.EINVAL
     assert L.itokmc_set_coefficients(None, ctypes.byref(good)) == itokmc.EINVAL
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets that the C
+    compiler gives the header's struct (a field added on one side only fails here)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_2307_01797_amd import itokmc as b
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    pairs = {"itokmc_grid_desc": b.GridDesc, "itokmc_coeffs": b.Coeffs,
+             "itokmc_seed_desc": b.SeedDesc, "itokmc_diag": b.Diag, "itokmc_tuning": b.Tuning,
+             "itokmc_ens_desc": b.EnsDesc, "itokmc_run_desc": b.RunDesc,
+             "itokmc_slot_event": b.SlotEvent, "itokmc_ens_info": b.EnsInfo,
+             "itokmc_ens_tuning": b.EnsTuning}
+    lines = ['#include <stdio.h>', '#include "itokmc.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_oracle_binding_structs_match_header_layout(tmp_path):
+    """The oracle's ctypes structures against its C header, as above."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    import oracle as o
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    pairs = {"or_desc": o.Desc, "or_coeffs": o.Coeffs, "or_diag": o.Diag}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "oracle.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "oracle"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
