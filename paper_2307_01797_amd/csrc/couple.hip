@@ -127,7 +127,10 @@ __global__ void __launch_bounds__(64, 5) k_couple(Bank b, Counters* ctr, int whi
     if (full) created += M;
     pieces += (e - s) + M;
     if (n_ppc > 0) {
-      __syncthreads();  // removal and product stores visible before the merge gathers them
+      // removal and product stores visible before the merge gathers them (nothing to
+      // wait for otherwise: the previous cell's leaf stores are to other slots)
+      if (full && (d < 0 || M > 0)) __syncthreads();
+      else wave_lds_sync();
       const int r = merge_cell<T, kMergeTiny, NL>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
       if (r == 2 && lane == 0) big[atomicAdd(&ctr->n_big, 1u)] = j;
     }

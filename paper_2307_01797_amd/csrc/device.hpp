@@ -86,6 +86,16 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
 
 // ---- wavefront helpers (64 lanes) ------------------------------------------------
 
+// Ordering point between LDS accesses of different lanes inside a workgroup that is one
+// wavefront: its lanes run in lockstep and the LDS serves a wavefront's operations in
+// issue order, so only the compiler's reordering has to be stopped.  Unlike
+// __syncthreads() it does not wait for the wavefront's outstanding global stores.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 __device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {

@@ -18,6 +18,10 @@
 // Leaves are written back into the cell's segment slots, then into its product slots,
 // then (splits of small cells only) into slots appended with one atomic; slots left
 // over are marked dead (weight 0).
+//
+// Run by workgroups of exactly one wavefront: the LDS phases are ordered with
+// wave_lds_sync(), so the leaf stores of one cell stay in flight while the wavefront
+// gathers its next cell.
 #pragma once
 #include "device.hpp"
 #include "itk.hpp"
@@ -132,17 +136,25 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   for (uint32_t q0 = 0; q0 < nseg + M; q0 += 64) {
     const uint32_t qi = q0 + (uint32_t)lane;
     const uint32_t q = qi < nseg ? s + qi : base + (qi - nseg);
-    // product slots past the bank's capacity were never written (overflow is flagged)
-    const uint32_t w = qi < nseg + M && q < K.cap ? b.w[q] : 0u;
+    // product slots past the bank's capacity were never written (overflow is flagged);
+    // every word is requested at once (lanes out of range read slot 0, unused)
+    const bool inr = qi < nseg + M && q < K.cap;
+    const uint32_t qc = inr ? q : 0u;
+    const uint32_t wq = b.w[qc];
+    const uint64_t iq = b.id[qc];
+    const T x0 = reinterpret_cast<const T*>(b.ox)[qc];
+    const T x1 = reinterpret_cast<const T*>(b.oy)[qc];
+    const T x2 = reinterpret_cast<const T*>(b.oz)[qc];
+    const uint32_t w = inr ? wq : 0u;
     const bool alive = w > 0;
     const uint64_t mask = __ballot(alive);
     const uint32_t pos = m + (uint32_t)__popcll(mask & lanemask_lt());
     if (alive) {
       if (pos < (uint32_t)CAP) {
-        sid[pos] = b.id[q];
-        so(0)[pos] = reinterpret_cast<const T*>(b.ox)[q];
-        so(1)[pos] = reinterpret_cast<const T*>(b.oy)[q];
-        so(2)[pos] = reinterpret_cast<const T*>(b.oz)[q];
+        sid[pos] = iq;
+        so(0)[pos] = x0;
+        so(1)[pos] = x1;
+        so(2)[pos] = x2;
         sw[pos] = w;
         I(0)[pos] = (uint16_t)pos;
         tag(0)[pos] = 0;
@@ -162,7 +174,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   if (!trigger || m == 0) return 0;
   if (m > (uint32_t)CAP) return 2;
   if (lane == 0) { Lst(0)[0] = 0; Lcn(0)[0] = m; LW(0)[0] = (uint32_t)Wtot; }
-  __syncthreads();
+  wave_lds_sync();
   if (packed) {  // rank of every piece's id among the cell's pieces (ids are distinct here)
     for (uint32_t q = (uint32_t)lane; q < m; q += 64) {
       const uint64_t iq = sid[q];
@@ -173,7 +185,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       for (; t < m; ++t) r += sid[t] < iq ? 1u : 0u;
       idr[q] = r;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
 
   // ---- breadth-first growth, all leaves of a level at once ----
@@ -221,7 +233,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       }
     }
     for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) { tag(ncb)[q] = kNone; otag[q] = kNone; }
-    __syncthreads();
+    wave_lds_sync();
     // (i) extents of the splitting leaves: a segmented min/max over each 64-slot chunk
     // of the buffer (a leaf's slots are contiguous), then one LDS atomic per leaf
     // segment and bound (LDS atomics of many lanes on one address serialise)
@@ -260,7 +272,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     if (lane < nl && chosen) {
       float ext[3];
       for (int a = 0; a < 3; ++a)
@@ -270,7 +282,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       if (ext[2] > ext[ax]) ax = 2;
       axis[lane] = (uint8_t)ax;
     }
-    __syncthreads();
+    wave_lds_sync();
     if (contig) {
       for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
         const uint8_t L = tag(cb)[q];
@@ -283,7 +295,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
           kid[q] = sid[pq];
         }
       }
-      __syncthreads();
+      wave_lds_sync();
     }
     // (ii) order each splitting leaf by (coordinate, id); copy the other leaves
     for (uint32_t q = (uint32_t)lane; q < extent; q += 64) {
@@ -334,7 +346,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       I(ncb)[RL + rank] = pq;
       otag[RL + rank] = L;
     }
-    __syncthreads();
+    wave_lds_sync();
     // (iii) weight median of every splitting leaf: one segmented scan over the buffer
     uint64_t carry = 0;
     uint32_t carry_key = 0xFFFFFFFFu;
@@ -369,7 +381,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       carry_key = __shfl(vkey, 63, 64);
       carry_hit = __shfl(hit ? 1 : 0, 63, 64) != 0;
     }
-    __syncthreads();
+    wave_lds_sync();
     // (iv)-(v) children of every splitting leaf, one lane per leaf
     uint32_t lcnt = 0, rst = 0, rcnt = 0, WLn = 0, WRn = 0, wl = 0, pm = 0, mu = 0;
     bool super = false;
@@ -413,7 +425,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       Lst(ncb)[newidx] = R; Lcn(ncb)[newidx] = lcnt; LW(ncb)[newidx] = WLn;
       Lst(ncb)[newidx + 1] = R + rst; Lcn(ncb)[newidx + 1] = rcnt; LW(ncb)[newidx + 1] = WRn;
     }
-    __syncthreads();
+    wave_lds_sync();
     // leaf tags of the split regions (ordered slots plus the spare slot)
     for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) {
       uint8_t L = otag[q];
@@ -431,7 +443,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       else if (off >= rs && off < rs + rc) t = (uint8_t)(ni + 1);
       tag(ncb)[q] = t;
     }
-    __syncthreads();
+    wave_lds_sync();
     cb = ncb;
     nl = nl_new;
     extent = new_extent;
@@ -488,7 +500,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     if (q < K.cap) b.w[q] = 0;
   }
   if (lane == 0) *merged += 1;
-  __syncthreads();
+  wave_lds_sync();
   return 1;
 }
 
