@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--drain", type=float, default=60.0)
     p.add_argument("--poisson-workers", type=int, default=4)
+    p.add_argument("--reactor-frac", type=float, default=0.0,
+                   help="served workload: share of zero-dimensional reactor requests")
     p.add_argument("--copy-calibration", action="store_true",
                    help="first copy 1 GiB device to device (a known-size kernel for "
                         "scaling hardware traffic counters)")
@@ -273,7 +275,7 @@ def bench_served(args):
 
     from paper_2307_01797_amd import serve, workloads
     trace = workloads.request_trace(rate=args.rate, duration=args.duration,
-                                    poisson_frac=args.poisson_frac)
+                                    poisson_frac=args.poisson_frac, reactor_frac=args.reactor_frac)
     srv = serve.Server(budget_bytes=args.budget_gb * 1e9, poisson_workers=args.poisson_workers)
     # warm-up: a few requests through both lanes (graph capture, allocator)
     warm = [(0.0, -1 - i, c) for i, (_, _, c) in enumerate(trace[:8])]
@@ -287,7 +289,8 @@ def bench_served(args):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "served", "rate_req_s": args.rate, "duration_s": args.duration,
-                   "poisson_frac": args.poisson_frac, "budget_gb": args.budget_gb,
+                   "poisson_frac": args.poisson_frac, "reactor_frac": args.reactor_frac,
+                   "budget_gb": args.budget_gb,
                    "poisson_workers": args.poisson_workers,
                    "drain_limit_s": args.drain},
         "served": summary,
@@ -300,6 +303,75 @@ def bench_served(args):
     print(json.dumps(out))
 
 
+def bench_reactors(args):
+    """Zero-dimensional reactors (the paper's comparison of the reaction algorithm with
+    the rate equation): the above-breakdown case, 10^6 reactors of one starting electron
+    at 10 MV/m for 50 steps of 1 ps, in one launch of the reactor entry point (inputs
+    resident in HBM; HIP events on the context's stream).  Reports reactor-steps/s, the
+    ensemble's mean and extinct fraction beside the rate equation's mean and the
+    birth-death extinction probability, and the oracle on one host core."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2307_01797_amd import itokmc, serve, workloads
+    cfg = workloads.preset("reactor_a")
+    dev = torch.device("cuda:0")
+    sim = serve.reactor_context()
+    n, steps, dt = cfg["n_reactors"], cfg["steps"], cfg["dt"]
+    k = itokmc.rates(cfg, cfg["E_field"])
+    dK = torch.from_numpy(np.tile(k, (n, 1))).to(dev)
+    dI = torch.arange(n, dtype=torch.int32, device=dev)
+    dF = torch.zeros((n, 5), dtype=torch.int64, device=dev)
+    X0 = torch.zeros((n, 4), dtype=torch.int64, device=dev)
+    X0[:, 0] = cfg["X0"]
+    ms = []
+    for rep in range(args.warmup + args.steps):
+        dX = X0.clone()
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.kmc_run_device(dI, dX, dK, dt, 100 * rep, steps, dF)
+        e1.record(sim.stream)
+        torch.cuda.synchronize(dev)
+        if rep >= args.warmup:
+            ms.append(e0.elapsed_time(e1))
+    xe = dX[:, 0].cpu().numpy()
+    ka, ke = k[0], k[1]
+    r = ka - ke
+    g = math.exp(r * steps * dt)
+    p0 = ke * (g - 1.0) / (ka * g - ke)
+    t_ms = sum(ms) / len(ms)
+    out = {
+        "metric": "reactor-steps/s (zero-dimensional KMC)",
+        "value": n * steps / (t_ms / 1e3), "unit": "reactor-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "reactor_a", "reactors": n, "kmc_steps": steps, "dt_s": dt,
+                   "E_V_per_m": cfg["E_field"], "X0": cfg["X0"]},
+        "statistics": {"mean_e": float(xe.mean()), "rate_equation_mean": cfg["X0"] * g,
+                       "extinct_fraction": float((xe == 0).mean()),
+                       "birth_death_extinction": p0 ** cfg["X0"]},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        m = 2_000_000
+        X = np.zeros((m, 4), dtype=np.int64)
+        X[:, 0] = cfg["X0"]
+        K = np.tile(oracle.rates(cfg, cfg["E_field"]), (m, 1))
+        t0 = time.perf_counter()
+        for s_ in range(steps):
+            X, _ = oracle.kmc_cells(cfg, X, K, dt, s_)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m * steps / el, "unit": "reactor-steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{m} reactors x {steps} steps in {el:.1f} s"}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -308,6 +380,8 @@ def main():
         sys.exit(2)
     if args.workload.startswith("ensemble"):
         return bench_ensemble(args)
+    if args.workload == "reactors":
+        return bench_reactors(args)
     if args.workload == "served":
         return bench_served(args)
     import torch

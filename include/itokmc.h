@@ -176,6 +176,12 @@ int itokmc_set_coefficients(itokmc_ctx* ctx, const itokmc_coeffs* coeffs);
 /* The same validation without a context (host-only, no device call): ITOKMC_OK or
  * ITOKMC_EINVAL. */
 int itokmc_check_coefficients(const itokmc_coeffs* coeffs);
+/* Rate constants (1/s) at field magnitude E (V/m) in a cell of edge dx (m), host-only:
+ * out[5] = k_alpha = alpha mu E, k_eta = eta mu E, k_gamma = kgamma_ratio k_alpha (the
+ * local field approximation of the section "Particle transport" and the air-chemistry
+ * table), k_ep and k_np (section "Simulation conditions"; 0 when off).  EINVAL on
+ * invalid coefficients, E < 0 or dx <= 0. */
+int itokmc_rates(const itokmc_coeffs* coeffs, double E, double dx, double* out);
 
 /* Seed particles (appends to the current state; step counter unchanged).  GAUSSIAN:
  * n0 weight-1 electrons at centre + sigma N(0,1)^3 (the initial electrons of the
@@ -389,6 +395,21 @@ int itokmc_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint3
 int itokmc_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* dev_cell_ids,
                      int64_t* dev_X, const double* dev_k, double dt, uint32_t step,
                      int64_t* dev_fires);
+/* Zero-dimensional reactors (section "Comparing reaction algorithms": a single cell's
+ * reactions with no transport): nsteps consecutive KMC steps of length dt on each of n
+ * independent reactors, in one launch.  Reactor i takes the steps step0 .. step0 +
+ * nsteps - 1 of the stream (dev_cell_ids[i], step, KMC) under the key (context seed,
+ * dev_realization[i]) (dev_realization may be NULL: the context's realization for all),
+ * so its result does not depend on the other reactors of the call.  dev_nsteps (may be
+ * NULL: nsteps for all) gives reactor i its own step count (steps past the 32-bit step
+ * counter are not taken).  X (n x 4 int64: e, M+, M-, photons; in/out), k (n x 5 rates,
+ * as itokmc_kmc_cells), fires (n x 5 int64 out: totals over the reactor's steps); all
+ * device pointers.  Enqueued on the context's stream.  EINVAL on null arrays with
+ * n > 0, dt <= 0, or step0 + nsteps beyond 2^32. */
+int itokmc_kmc_run(itokmc_ctx* ctx, uint64_t n, const uint32_t* dev_cell_ids,
+                   const uint32_t* dev_realization, const uint32_t* dev_nsteps, int64_t* dev_X,
+                   const double* dev_k, double dt, uint32_t step0, uint32_t nsteps,
+                   int64_t* dev_fires);
 
 /* Counting sort of n particles by cell (the binning of particles into per-cell lists
  * that the reactions and superparticle management of the final algorithm, steps 7-8,

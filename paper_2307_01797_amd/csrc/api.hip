@@ -661,4 +661,28 @@ int itokmc_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, int64_t* 
   return check_hip(ctx, launch_kmc_cells(ctx, n, ids, X, k, dt, step, fires), "kmc_cells");
 }
 
+int itokmc_rates(const itokmc_coeffs* c, double E, double dx, double* out) {
+  std::string why;
+  if (!c || !out || !(E >= 0.0) || !(dx > 0.0) || check_coeffs(c, &why)) return ITOKMC_EINVAL;
+  const double mu = mobility(*c, E);
+  const double alpha = E > 0.0 ? c->alpha_A * exp(-c->alpha_B / E) : 0.0;
+  const double v = mu * E;
+  out[0] = alpha * v;
+  out[1] = c->eta * v;
+  out[2] = c->kgamma_ratio * out[0];
+  recomb_rates(*c, E, dx, out + 3);
+  return ITOKMC_OK;
+}
+
+int itokmc_kmc_run(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, const uint32_t* real,
+                   const uint32_t* nst, int64_t* X, const double* k, double dt, uint32_t step0,
+                   uint32_t nsteps, int64_t* fires) {
+  if (!ctx || (n && (!ids || !X || !k || !fires))) return ITOKMC_EINVAL;
+  if (!(dt > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "dt must be positive");
+  if ((uint64_t)step0 + nsteps > 0x100000000ull)
+    return set_error(ctx, ITOKMC_EINVAL, "step0 + nsteps exceeds the 32-bit step counter");
+  if (n == 0 || (nsteps == 0 && !nst)) return ITOKMC_OK;
+  return check_hip(ctx, launch_kmc_run(ctx, n, ids, real, nst, X, k, dt, step0, nsteps, fires), "kmc_run");
+}
+
 }  // extern "C"

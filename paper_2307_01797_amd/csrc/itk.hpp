@@ -197,6 +197,9 @@ hipError_t launch_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
                               uint32_t k1, uint64_t n, uint32_t* out, hipStream_t s);
 // kmc.hip
 hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates& fr);
+hipError_t launch_kmc_run(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, const uint32_t* real,
+                          const uint32_t* nst, int64_t* X, const double* k, double dt, uint32_t step0,
+                          uint32_t nsteps, int64_t* fires);
 hipError_t launch_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, int64_t* X,
                             const double* k, double dt, uint32_t step, int64_t* fires);
 // couple.hip

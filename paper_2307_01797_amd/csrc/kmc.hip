@@ -299,6 +299,46 @@ int blocks_for(uint64_t n, int per_block, int max_blocks) {
   return (int)b;
 }
 
+// Zero-dimensional reactors: nsteps steps per reactor in one launch, each reactor with
+// its own key (seed, realization) and stream cell id; X stays in registers.
+__global__ void k_kmc_run(KmcParams P, uint32_t seed, uint32_t real0, uint64_t n, const uint32_t* ids,
+                          const uint32_t* real, const uint32_t* nst, int64_t* Xa, const double* ka,
+                          double dt, uint32_t step0, uint32_t nsteps0, int64_t* fa) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const Key key{seed, real ? real[i] : real0};
+    const uint32_t id = ids[i];
+    const uint64_t want = nst ? nst[i] : nsteps0;
+    const uint32_t nsteps = (uint32_t)(want < 0x100000000ull - step0 ? want : 0x100000000ull - step0);
+    int64_t F[5] = {0, 0, 0, 0, 0};
+    if (ka[5 * i + 3] == 0.0 && ka[5 * i + 4] == 0.0) {
+      State X{Xa[4 * i], Xa[4 * i + 1], Xa[4 * i + 2], Xa[4 * i + 3]};
+      const double k[3] = {ka[5 * i], ka[5 * i + 1], ka[5 * i + 2]};
+      for (uint32_t s = 0; s < nsteps; ++s) {
+        CellStream st;
+        st.init(id, step0 + s, TAG_KMC, 0, key);
+        int64_t f[3];
+        advance(P, X, k, dt, st, f);
+        F[0] += f[0]; F[1] += f[1]; F[2] += f[2];
+      }
+      Xa[4 * i] = X.e; Xa[4 * i + 1] = X.p; Xa[4 * i + 2] = X.m; Xa[4 * i + 3] = X.g;
+    } else {
+      State5 X{{Xa[4 * i], Xa[4 * i + 1], Xa[4 * i + 2], Xa[4 * i + 3]}};
+      double k[5];
+      for (int r = 0; r < 5; ++r) k[r] = ka[5 * i + r];
+      for (uint32_t s = 0; s < nsteps; ++s) {
+        CellStream st;
+        st.init(id, step0 + s, TAG_KMC, 0, key);
+        int64_t f[5];
+        advance5(P, X, k, dt, st, f);
+        for (int r = 0; r < 5; ++r) F[r] += f[r];
+      }
+      for (int a = 0; a < 4; ++a) Xa[4 * i + a] = X.x[a];
+    }
+    for (int r = 0; r < 5; ++r) fa[5 * i + r] = F[r];
+  }
+}
+
 KmcParams params(const itokmc_ctx* ctx) {
   return KmcParams{ctx->d.kmc_mode, ctx->d.kmc_nc, ctx->d.kmc_nssa, ctx->d.kmc_eps};
 }
@@ -336,6 +376,15 @@ hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates
   k_kmc_step<false><<<gh, 64, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
                                            ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
                                            ctx->cbase, ctx->heavy, ctx->rates, fr, qa, ctx->d.n_new, dest);
+  return hipGetLastError();
+}
+
+hipError_t launch_kmc_run(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, const uint32_t* real,
+                          const uint32_t* nst, int64_t* X, const double* k, double dt, uint32_t step0,
+                          uint32_t nsteps, int64_t* fires) {
+  k_kmc_run<<<blocks_for(n, 256, 8192), 256, 0, ctx->s>>>(params(ctx), ctx->d.seed, ctx->d.realization,
+                                                         n, ids, real, nst, X, k, dt, step0, nsteps,
+                                                         fires);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_deposit", "itokmc_diagnostics", "itokmc_get_particles",
            "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
            "itokmc_get_field", "itokmc_set_field", "itokmc_destroy", "itokmc_last_error",
-           "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_set_profiling",
+           "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_kmc_run", "itokmc_rates", "itokmc_set_profiling",
            "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning",
            "itokmc_ensemble_arena_bytes", "itokmc_ensemble_create", "itokmc_ensemble_admit",
            "itokmc_ensemble_step", "itokmc_ensemble_poll", "itokmc_ensemble_result",
@@ -173,6 +173,8 @@ def lib():
         L.itokmc_last_error.restype = ctypes.c_char_p
         L.itokmc_philox_fill.argtypes = [U32, U32, U32, U32, U32, U32, U64, P, P]
         L.itokmc_kmc_cells.argtypes = [P, U64, P, P, P, D, U32, P]
+        L.itokmc_kmc_run.argtypes = [P, U64, P, P, P, P, P, D, U32, U32, P]
+        L.itokmc_rates.argtypes = [ctypes.POINTER(Coeffs), D, D, P]
         L.itokmc_set_profiling.argtypes = [P, I32]
         L.itokmc_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.itokmc_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -423,6 +425,51 @@ class Sim:
                                            ctypes.c_void_p(df.data_ptr())))
         self.stream.synchronize()
         return dX.cpu().numpy(), df.cpu().numpy()
+
+
+    def kmc_run_device(self, ids, X, k, dt, step0, nsteps, fires, realization=None,
+                       steps=None):
+        """Zero-dimensional reactors on device tensors (kernel-level entry point):
+        ids (n,) int32, X (n,4) int64 in/out, k (n,5) float64, fires (n,5) int64 out,
+        realization and steps (n,) int32 or None.  Enqueued on the context's stream."""
+        n = X.shape[0]
+        rp = ctypes.c_void_p(realization.data_ptr()) if realization is not None else None
+        sp = ctypes.c_void_p(steps.data_ptr()) if steps is not None else None
+        return self._check(lib().itokmc_kmc_run(self.h, n, ctypes.c_void_p(ids.data_ptr()), rp, sp,
+                                                ctypes.c_void_p(X.data_ptr()),
+                                                ctypes.c_void_p(k.data_ptr()), dt, step0, nsteps,
+                                                ctypes.c_void_p(fires.data_ptr())))
+
+    def kmc_run(self, X, k, dt, step0, nsteps, cell_ids=None, realization=None):
+        """Host-array form of kmc_run_device; returns X and the fire totals (n,5)."""
+        torch = self.torch
+        X = np.ascontiguousarray(X, dtype=np.int64)
+        n = X.shape[0]
+        ids = np.arange(n, dtype=np.uint32) if cell_ids is None else np.asarray(cell_ids, np.uint32)
+        k = np.asarray(k, dtype=np.float64).reshape(n, -1)
+        k5 = np.zeros((n, 5))
+        k5[:, :k.shape[1]] = k
+        dX = torch.from_numpy(X.copy()).to(self.device)
+        dk = torch.from_numpy(k5).to(self.device)
+        di = torch.from_numpy(ids.astype(np.int32)).to(self.device)
+        dr = None
+        if realization is not None:
+            dr = torch.from_numpy(np.asarray(realization, np.uint32).astype(np.int32)).to(self.device)
+        df = torch.zeros((n, 5), dtype=torch.int64, device=self.device)
+        self.stream.synchronize()
+        self.kmc_run_device(di, dX, dk, dt, step0, nsteps, df, dr)
+        self.stream.synchronize()
+        return dX.cpu().numpy(), df.cpu().numpy()
+
+
+def rates(cfg, E):
+    """The library's rate constants (k_alpha, k_eta, k_gamma, k_ep, k_np) in 1/s at field
+    magnitude E in one cell of cfg (host computation, no device)."""
+    out = (ctypes.c_double * 5)()
+    rc = lib().itokmc_rates(ctypes.byref(make_coeffs(cfg)), float(E), float(cfg["dx"]), out)
+    if rc != OK:
+        raise ItokmcError(rc, "invalid coefficients or field")
+    return np.array(list(out))
 
 
 def make_seed(cfg):

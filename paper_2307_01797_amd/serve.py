@@ -11,6 +11,11 @@
   new ones join.  Self-consistent (Poisson) requests run in single contexts on worker
   threads with streams of their own, admitted against the remaining budget, so their
   kernels overlap the ensemble's on the device.
+* Zero-dimensional reactor requests (ensembles of independent reactors, the paper's
+  comparison of the reaction algorithm with the rate equation) are gathered between
+  ensemble steps and run together in one launch of the library's reactor entry point
+  on a stream of their own; each reactor keeps its request's key and its own stream,
+  so a request's result does not depend on what it was batched with.
 * serve_plain: the same request stream handled first-come first-served, one request
   at a time in single contexts.
 
@@ -119,6 +124,60 @@ def run_batched(cfgs, ens=None, steps_per_poll=2, device="cuda:0"):
                 particle_steps=sum(r["particle_steps"] for r in results))
 
 
+def reactor_context(device="cuda:0", stream=None):
+    """A small context whose method parameters (hybrid KMC, seed 1) the reactor lane
+    uses; each reactor brings its own realization (key) and rates."""
+    from . import workloads
+    return itokmc.Sim(workloads.REACTOR_A, device=device, stream=stream, max_particles=1024)
+
+
+def run_reactors(sim, cfgs, keep=False):
+    """Run reactor requests (equal dt) in one launch: reactor j of request r starts with
+    X0 electrons, takes the request's rates at its field and its step count, under the
+    key (seed, r) and stream cell id j.  Returns per request the mean and the number
+    of extinct final electron counts, the fire totals, and (keep) the final counts."""
+    torch = sim.torch
+    dt = cfgs[0]["dt"]
+    assert all(c["dt"] == dt for c in cfgs)
+    n = [int(c["n_reactors"]) for c in cfgs]
+    N = sum(n)
+    X = np.zeros((N, 4), dtype=np.int64)
+    K = np.zeros((N, 5))
+    ids = np.zeros(N, dtype=np.int32)
+    real = np.zeros(N, dtype=np.int32)
+    steps = np.zeros(N, dtype=np.int32)
+    o = 0
+    for c, m in zip(cfgs, n):
+        X[o:o + m, 0] = c["X0"]
+        K[o:o + m] = itokmc.rates(c, c["E_field"])
+        ids[o:o + m] = np.arange(m, dtype=np.int32)
+        real[o:o + m] = np.int32(np.uint32(c["realization"]).view(np.int32))
+        steps[o:o + m] = c["steps"]
+        o += m
+    dev = sim.device
+    dX = torch.from_numpy(X).to(dev)
+    dK = torch.from_numpy(K).to(dev)
+    dI = torch.from_numpy(ids).to(dev)
+    dR = torch.from_numpy(real).to(dev)
+    dS = torch.from_numpy(steps).to(dev)
+    dF = torch.zeros((N, 5), dtype=torch.int64, device=dev)
+    sim.stream.synchronize()
+    sim.kmc_run_device(dI, dX, dK, dt, 0, 0, dF, realization=dR, steps=dS)
+    sim.stream.synchronize()
+    Xh = dX.cpu().numpy()
+    Fh = dF.cpu().numpy()
+    out = []
+    o = 0
+    for c, m in zip(cfgs, n):
+        xe = Xh[o:o + m, 0]
+        out.append(dict(n=m, mean_e=float(xe.mean()), extinct=int((xe == 0).sum()),
+                        fires=[int(v) for v in Fh[o:o + m].sum(axis=0)],
+                        reactor_steps=m * int(c["steps"]),
+                        final=Xh[o:o + m].copy() if keep else None))
+        o += m
+    return out
+
+
 def _percentiles(lat):
     if not lat:
         return None, None
@@ -153,6 +212,8 @@ class Server:
         self.keep = set(keep)
         self.cv = threading.Condition()
         self._cancel = threading.Event()
+        self.reactor_stream = torch.cuda.Stream(self.device)
+        self.reactors = reactor_context(device, self.reactor_stream)
 
     # -- self-consistent lane -------------------------------------------------------
     def _poisson_worker(self, q, results, t0, stream, errors):
@@ -214,6 +275,7 @@ class Server:
         end_arrivals = trace[-1][0] if trace else 0.0
         i = 0
         pending = collections.deque()
+        rq = []   # reactor requests waiting for the next batch
         active = {}
         batched_steps = 0
         max_active = 0
@@ -228,7 +290,9 @@ class Server:
             while i < len(trace) and trace[i][0] <= now:
                 item = trace[i]
                 i += 1
-                if item[2].get("field") == "poisson":
+                if item[2].get("kind") == "reactor":
+                    rq.append(item)
+                elif item[2].get("field") == "poisson":
                     pq.put(item)
                 else:
                     pending.append(item)
@@ -249,6 +313,23 @@ class Server:
                 pending.popleft()
                 active[slot] = (rid, t_arr, now)
             max_active = max(max_active, len(active))
+            if rq:
+                # reactor requests: one launch per time step length, overlapping the
+                # ensemble's queued work on the device
+                t_adm = time.perf_counter() - t0
+                by_dt = collections.defaultdict(list)
+                for item in rq:
+                    by_dt[item[2]["dt"]].append(item)
+                rq = []
+                for items in by_dt.values():
+                    outs = run_reactors(self.reactors, [c for _, _, c in items],
+                                        keep=any(rid in self.keep for _, rid, _ in items))
+                    tf = time.perf_counter() - t0
+                    for (t_arr, rid, cfg), res in zip(items, outs):
+                        if rid not in self.keep:
+                            res["final"] = None
+                        results[rid] = dict(kind="reactor", arrival=t_arr, admitted=t_adm,
+                                            finished=tf, reactor=res)
             if active:
                 ens.step(steps_per_poll)
                 batched_steps += steps_per_poll
@@ -262,7 +343,7 @@ class Server:
                     results[rid] = dict(kind="batched", arrival=t_arr, admitted=t_adm,
                                         finished=tf, state=state, steps=steps, diag=d,
                                         particles=parts)
-            elif i >= len(trace) and not pending:
+            elif i >= len(trace) and not pending and not rq:
                 break
             elif i < len(trace):
                 time.sleep(max(0.0, min(0.002, trace[i][0] - now)))
@@ -288,8 +369,9 @@ class Server:
         return self._summary(trace, results, wall, batched_steps, max_active), results
 
     def _summary(self, trace, results, wall, batched_steps, max_active):
-        lat_all, lat_b, lat_p = [], [], []
+        lat_all, lat_b, lat_p, lat_r = [], [], [], []
         psteps = 0
+        rsteps = 0
         done = 0
         unfinished_poisson = 0
         for t, rid, cfg in trace:
@@ -301,18 +383,25 @@ class Server:
             done += 1
             lat = r["finished"] - r["arrival"]
             lat_all.append(lat)
+            if r["kind"] == "reactor":
+                lat_r.append(lat)
+                rsteps += r["reactor"]["reactor_steps"]
+                continue
             (lat_p if r["kind"] == "poisson" else lat_b).append(lat)
             psteps += r["diag"]["particle_steps"]
         p50, p99 = _percentiles(lat_all)
         b50, b99 = _percentiles(lat_b)
         q50, q99 = _percentiles(lat_p)
+        r50, r99 = _percentiles(lat_r)
         n = len(trace)
         return dict(requests=n, completed=done, unfinished=n - done,
                     unfinished_poisson=unfinished_poisson, wall_s=wall,
                     throughput_req_s=done / wall if wall > 0 else 0.0,
                     particle_steps_per_s=psteps / wall if wall > 0 else 0.0,
                     p50_s=p50, p99_s=p99, batched_p50_s=b50, batched_p99_s=b99,
-                    poisson_p50_s=q50, poisson_p99_s=q99, slots=self.slots,
+                    poisson_p50_s=q50, poisson_p99_s=q99, reactor_p50_s=r50,
+                    reactor_p99_s=r99, reactor_requests=len(lat_r),
+                    reactor_steps_per_s=rsteps / wall if wall > 0 else 0.0, slots=self.slots,
                     max_resident=max_active, ensemble_steps=batched_steps,
                     admission_waits=self.admission_waits,
                     ensemble_arena_gb=self.ens.arena_bytes / 1e9)
@@ -328,6 +417,7 @@ def serve_plain(trace, time_limit_s, device="cuda:0", keep=(), log=None):
     results = {}
     psteps = 0
     next_log = 10.0
+    reactors = None
     for t_arr, rid, cfg in trace:
         now = time.perf_counter() - t0
         if now > time_limit_s:
@@ -338,6 +428,13 @@ def serve_plain(trace, time_limit_s, device="cuda:0", keep=(), log=None):
         if t_arr > now:
             time.sleep(t_arr - now)
         t_adm = time.perf_counter() - t0
+        if cfg.get("kind") == "reactor":
+            if reactors is None:
+                reactors = reactor_context(device)
+            res = run_reactors(reactors, [cfg], keep=rid in keep)[0]
+            results[rid] = dict(kind="reactor", arrival=t_arr, admitted=t_adm,
+                                finished=time.perf_counter() - t0, reactor=res)
+            continue
         d, parts = run_plain_one(cfg, device, keep_particles=rid in keep)
         results[rid] = dict(kind=cfg.get("field", "uniform"), arrival=t_arr, admitted=t_adm,
                             finished=time.perf_counter() - t0, diag=d, particles=parts)

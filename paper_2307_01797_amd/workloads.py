@@ -73,10 +73,25 @@ AVALANCHE_256 = dict(
 )
 
 
+# Zero-dimensional reactors (the paper's comparison of the reaction algorithm with the
+# rate equation): electron-impact ionization and attachment only, no transport, the
+# synthetic air coefficients at a fixed field.  After the paper's two cases: (a) above
+# breakdown, E = 10 MV/m, one starting electron, 50 ps (50 steps of 1 ps); (b) below
+# breakdown, E = 1.7 MV/m, five starting electrons, 50 ns (500 steps of 100 ps).  A
+# reactor ensemble holds n_reactors independent reactors (stream cell ids 0 .. n-1) at
+# the field magnitude E_field (V/m).
+REACTOR_A = dict(name="reactor_a", kind="reactor", coeffs=dict(AIR), kmc="hybrid", seed=1,
+                 realization=0, E_field=1.0e7, X0=1, n_reactors=1_000_000, dt=1e-12, steps=50,
+                 dx=10e-6, grid=(8, 8, 8), field="uniform", precision="fp64")
+REACTOR_B = dict(REACTOR_A, name="reactor_b", E_field=1.7e6, X0=5, n_reactors=200_000, dt=1e-10,
+                 steps=500)
+
+
 def preset(name, **overrides):
     base = {"avalanche_32": AVALANCHE_32, "streamer_256": STREAMER_256,
             "streamer_64": STREAMER_64, "avalanche_256": AVALANCHE_256,
-            "streamer_256_dense": STREAMER_256_DENSE}[name]
+            "streamer_256_dense": STREAMER_256_DENSE, "reactor_a": REACTOR_A,
+            "reactor_b": REACTOR_B}[name]
     cfg = copy.deepcopy(base)
     for k, v in overrides.items():
         if k == "coeffs":
@@ -131,9 +146,22 @@ def poisson_request(r, seed=1):
         seed_sigma=0.156 * L)
 
 
-def request_trace(rate=200.0, duration=60.0, poisson_frac=0.1, seed=1):
+def reactor_request(r, seed=1):
+    """Served zero-dimensional request r: an ensemble of 4096 reactors (as REACTOR_A) with
+    the field log-uniform in [1.7, 12] MV/m, the starting electrons log-uniform in
+    [1, 100] and 50 to 500 steps of 1 ps; the key (seed, r)."""
+    rng = np.random.default_rng([seed, r, 0])
+    E = float(10 ** rng.uniform(math.log10(1.7e6), math.log10(1.2e7)))
+    X0 = int(round(10 ** rng.uniform(0, 2)))
+    steps = int(rng.integers(50, 501))
+    return dict(REACTOR_A, coeffs=dict(AIR), name=f"reactor_{r}", E_field=E, X0=X0,
+                n_reactors=4096, steps=steps, seed=seed, realization=r)
+
+
+def request_trace(rate=200.0, duration=60.0, poisson_frac=0.1, seed=1, reactor_frac=0.0):
     """Served workload: Poisson arrivals at `rate` requests/s over `duration` s; each
-    request is a self-consistent 128^3 request with probability poisson_frac, else a
+    request is a self-consistent 128^3 request with probability poisson_frac, a
+    zero-dimensional reactor ensemble with probability reactor_frac, else a
     batched-avalanche realization.  Returns [(arrival_s, request_id, cfg)]."""
     rng = np.random.default_rng([seed, 5])
     out = []
@@ -143,8 +171,13 @@ def request_trace(rate=200.0, duration=60.0, poisson_frac=0.1, seed=1):
         t += rng.exponential(1.0 / rate)
         if t >= duration:
             return out
-        kind = rng.random() < poisson_frac
-        cfg = poisson_request(r, seed) if kind else ensemble_realization(r, seed)
+        u = rng.random()
+        if u < poisson_frac:
+            cfg = poisson_request(r, seed)
+        elif reactor_frac > 0.0 and u < poisson_frac + reactor_frac:
+            cfg = reactor_request(r, seed)
+        else:
+            cfg = ensemble_realization(r, seed)
         out.append((t, r, cfg))
         r += 1
 
