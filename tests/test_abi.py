@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -157,3 +158,18 @@ def test_oracle_binding_structs_match_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_library_rates_equal_oracle_rates_on_host():
+    """itokmc_rates is host code: it runs without a GPU and equals the oracle's rates
+    bit for bit (fields below, at and above the mobility floor; with and without
+    recombination)."""
+    import oracle
+
+    from paper_2307_01797_amd import itokmc, workloads
+    for coeffs in ({}, dict(workloads.RECOMBINATION), dict(kgamma_ratio=0.06)):
+        cfg = workloads.preset("avalanche_32", coeffs=coeffs)
+        for E in (0.0, 5e3, 1e4, 1.7e6, 1e7, 3.3e7):
+            assert np.array_equal(itokmc.rates(cfg, E), oracle.rates(cfg, E)), (coeffs, E)
+    with pytest.raises(itokmc.ItokmcError):
+        itokmc.rates(workloads.preset("avalanche_32"), -1.0)
