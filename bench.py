@@ -76,10 +76,11 @@ def parse():
     return p.parse_args()
 
 
-def traffic_from_profile(kernel_label, workload):
-    """Measured HBM bytes per launch of a kernel on a workload from a committed counter
-    summary (profiles/*_traffic.md, lines `key: value`), or None when there is none or
-    when a source file it names has changed since the counters were taken."""
+def traffic_from_profile(kernel_label, workload, key="hbm_bytes_per_launch"):
+    """Measured HBM bytes per launch (or another recorded quantity, e.g.
+    valu_busy_pct) of a kernel on a workload from a committed counter summary
+    (profiles/*_traffic.md, lines `key: value`), or None when there is none or when a
+    source file it names has changed since the counters were taken."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
@@ -96,9 +97,9 @@ def traffic_from_profile(kernel_label, workload):
             if not os.path.exists(src):
                 return None
             h.update(open(src, "rb").read())
-        if h.hexdigest() != kv.get("source_sha256"):
+        if h.hexdigest() != kv.get("source_sha256") or key not in kv:
             return None
-        return int(kv["hbm_bytes_per_launch"])
+        return float(kv[key]) if "." in kv[key] else int(kv[key])
     return None
 
 
@@ -403,6 +404,7 @@ def main():
     w = timed_windows(sim, cfg, args.steps, dev)
     for ph, r in w["roofs"].items():
         r["traffic"] = traffic_from_profile(KERNELS[ph], cfg["name"])
+        r["valu_busy_pct"] = traffic_from_profile(KERNELS[ph], cfg["name"], "valu_busy_pct")
     roof = max(w["roofs"].values(), key=lambda r: r["total_ms"]) if w["roofs"] else None
     d0, d1, d2 = w["diag"]
     out = {
