@@ -402,6 +402,40 @@ int itokmc_step(itokmc_ctx* ctx, uint32_t nsteps, double dt) {
   return ITOKMC_OK;
 }
 
+int itokmc_step_until(itokmc_ctx* ctx, uint32_t nsteps, double dt, uint64_t stop_particles,
+                      uint32_t* steps_done) {
+  if (!ctx || !steps_done) return ITOKMC_EINVAL;
+  if (ctx->d.field_mode != ITOKMC_FIELD_UNIFORM)
+    return set_error(ctx, ITOKMC_EINVAL, "the device-side stop rule needs the prescribed-field mode");
+  if (!ctx->have_coeffs) return set_error(ctx, ITOKMC_EINVAL, "coefficients not set");
+  if (!(dt > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "dt must be positive");
+  *steps_done = 0;
+  if (nsteps == 0) return ITOKMC_OK;
+  const uint32_t step0 = ctx->step;
+  const int cur0 = ctx->cur;
+  int rc = check_hip(ctx, launch_stop_begin(ctx), "stop rule");
+  // every step is enqueued; once the rule has stopped the run on the device, the
+  // kernels of the remaining steps return at entry
+  for (uint32_t i = 0; i < nsteps && !rc; ++i) {
+    rc = itokmc_transport(ctx, dt);
+    if (!rc) rc = itokmc_react(ctx, dt);
+    if (!rc) rc = check_hip(ctx, launch_stop_step(ctx, stop_particles), "stop rule");
+  }
+  uint32_t done = 0;
+  hipError_t e = hipMemcpyAsync(&done, &ctx->ctr->steps_done, sizeof(done), hipMemcpyDeviceToHost, ctx->s);
+  if (e == hipSuccess) e = launch_stop_end(ctx);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->s);
+  const int rc2 = check_hip(ctx, e, "stop rule");
+  if (rc) return rc;
+  if (rc2) return rc2;
+  // the host enqueued nsteps steps; the state is that of the steps taken
+  ctx->step = step0 + done;
+  ctx->cur = (done & 1u) ? 1 - cur0 : cur0;
+  ctx->binned = false;
+  *steps_done = done;
+  return ITOKMC_OK;
+}
+
 int itokmc_set_step(itokmc_ctx* ctx, uint32_t step) {
   if (!ctx) return ITOKMC_EINVAL;
   ctx->step = step;

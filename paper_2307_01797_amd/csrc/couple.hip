@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(256) k_couple_light(Bank b, Counters* ctr, Ste
                                                      const uint32_t* start, const int32_t* dN,
                                                      const uint32_t* cbase, int n_new, int n_ppc,
                                                      uint32_t* full_list, uint32_t* merge_list) {
+  if (ctr->halt) return;
   __shared__ uint32_t sh[18];
   const uint32_t nwork = ctr->n_work, n_occ = ctr->n_occ, sorted = ctr->sorted;
   uint64_t created = 0, removed = 0;
@@ -99,6 +100,7 @@ __global__ void __launch_bounds__(64, 5) k_couple(Bank b, Counters* ctr, int whi
                                               const uint32_t* occ, const uint32_t* start,
                                               const int32_t* dN, const uint32_t* cbase, int n_new,
                                               int n_ppc, uint32_t* big) {
+  if (ctr->halt) return;
   const uint32_t nfull = ctr->n_cfull, nwork = nfull + ctr->n_cmerge, n_occ = ctr->n_occ,
                  sorted = ctr->sorted;
   const int lane = lane_id();
@@ -153,6 +155,7 @@ __global__ void __launch_bounds__(64) k_merge_tier(Bank b, Counters* ctr, int wh
                                                   const uint32_t* occ, const uint32_t* start,
                                                   const int32_t* dN, const uint32_t* cbase,
                                                   int n_new, int n_ppc) {
+  if (ctr->halt) return;
   const uint32_t nin = *n_in, n_occ = ctr->n_occ, sorted = ctr->sorted;
   uint64_t merged = 0;
   for (uint32_t t = blockIdx.x; t < nin; t += gridDim.x) {

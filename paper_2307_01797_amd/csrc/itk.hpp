@@ -50,6 +50,11 @@ struct Counters {
   uint32_t n_cfull;            // cells for the wavefront coupling pass (everything)
   uint32_t n_cmerge;           // cells for the wavefront coupling pass (merge only)
   unsigned long long couple_pieces;  // particles gathered by the wavefront coupling pass
+  // device-side stop rule (itokmc_step_until): once halt is set, every kernel of the
+  // step path returns at entry, so the state stays that of the last step taken
+  uint32_t halt;
+  uint32_t steps_done;
+  unsigned long long pushed_mark;    // `pushed` at the start of the current step
 };
 
 // Device-side copy of the per-step constants shared by the kernels.
@@ -197,6 +202,9 @@ hipError_t launch_philox_fill(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
                               uint32_t k1, uint64_t n, uint32_t* out, hipStream_t s);
 // kmc.hip
 hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates& fr);
+hipError_t launch_stop_begin(itokmc_ctx* ctx);
+hipError_t launch_stop_step(itokmc_ctx* ctx, uint64_t stop_particles);
+hipError_t launch_stop_end(itokmc_ctx* ctx);
 hipError_t launch_kmc_run(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, const uint32_t* real,
                           const uint32_t* nst, int64_t* X, const double* k, double dt, uint32_t step0,
                           uint32_t nsteps, int64_t* fires);

@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) k_kmc_step(
     uint32_t* nplus, uint32_t* nminus, uint32_t* ngamma, uint32_t* occ_fires, int32_t* dN,
     uint32_t* work, uint32_t* cbase, uint32_t* heavy, double* rates, FieldRates fr,
     int queue_all, int n_new, int dest) {
+  if (ctr->halt) return;
   __shared__ uint32_t sh[18];
   const uint32_t n = kFast ? ctr->n_occ : ctr->n_heavy;
   const uint32_t span = blockDim.x * kKmcPer;
@@ -185,6 +186,7 @@ __global__ void __launch_bounds__(64) k_kmc_step_rec(
     KmcParams P, StepConst K, Counters* ctr, const uint32_t* occ, unsigned long long* cellacc,
     uint32_t* nplus, uint32_t* nminus, uint32_t* ngamma, uint32_t* occ_fires, int32_t* dN,
     uint32_t* work, uint32_t* cbase, FieldRates fr, int queue_all, int n_new, int dest) {
+  if (ctr->halt) return;
   __shared__ uint32_t sh[18];
   const uint32_t n = ctr->n_occ;
   uint64_t t[5] = {0, 0, 0, 0, 0};
@@ -240,6 +242,7 @@ __global__ void __launch_bounds__(64) k_kmc_step_rec(
 __global__ void __launch_bounds__(256) k_kmc_ions(KmcParams P, StepConst K, Counters* ctr,
                                                   const unsigned long long* cellacc, uint32_t* nplus,
                                                   uint32_t* nminus, FieldRates fr) {
+  if (ctr->halt) return;
   uint64_t t4 = 0;
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < K.ncell; c += gridDim.x * blockDim.x) {
     const uint32_t p0 = nplus[c], m0 = nminus[c];
@@ -339,6 +342,22 @@ __global__ void k_kmc_run(KmcParams P, uint32_t seed, uint32_t real0, uint64_t n
   }
 }
 
+// Device-side stop rule of a run (itokmc_step_until): a run stops after the first step
+// that began with at least stop_particles live particles (the push counts them).
+__global__ void k_stop_begin(Counters* ctr) {
+  ctr->halt = 0u;
+  ctr->steps_done = 0u;
+  ctr->pushed_mark = ctr->pushed;
+}
+__global__ void k_stop_step(Counters* ctr, uint64_t stop_particles) {
+  if (ctr->halt) return;
+  ctr->steps_done += 1u;
+  const unsigned long long live = ctr->pushed - ctr->pushed_mark;
+  ctr->pushed_mark = ctr->pushed;
+  if (stop_particles && live >= stop_particles) ctr->halt = 1u;
+}
+__global__ void k_stop_end(Counters* ctr) { ctr->halt = 0u; }
+
 KmcParams params(const itokmc_ctx* ctx) {
   return KmcParams{ctx->d.kmc_mode, ctx->d.kmc_nc, ctx->d.kmc_nssa, ctx->d.kmc_eps};
 }
@@ -376,6 +395,19 @@ hipError_t launch_kmc_step(itokmc_ctx* ctx, const StepConst& k, const FieldRates
   k_kmc_step<false><<<gh, 64, 0, ctx->s>>>(params(ctx), k, ctx->ctr, ctx->occ, ctx->cellacc, ctx->nplus,
                                            ctx->nminus, ctx->ngamma, ctx->occ_fires, ctx->dN, ctx->work,
                                            ctx->cbase, ctx->heavy, ctx->rates, fr, qa, ctx->d.n_new, dest);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop_begin(itokmc_ctx* ctx) {
+  k_stop_begin<<<1, 1, 0, ctx->s>>>(ctx->ctr);
+  return hipGetLastError();
+}
+hipError_t launch_stop_step(itokmc_ctx* ctx, uint64_t stop_particles) {
+  k_stop_step<<<1, 1, 0, ctx->s>>>(ctx->ctr, stop_particles);
+  return hipGetLastError();
+}
+hipError_t launch_stop_end(itokmc_ctx* ctx) {
+  k_stop_end<<<1, 1, 0, ctx->s>>>(ctx->ctr);
   return hipGetLastError();
 }
 

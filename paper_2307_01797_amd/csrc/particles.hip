@@ -109,6 +109,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, int which,
                                                         unsigned long long* cellacc,
                                                         uint32_t* tiles, StepConst k) {
+  if (ctr->halt) return;
   const uint32_t n = min(ctr->n[which], k.cap);
   const T drift[3] = {(T)k.drift[0], (T)k.drift[1], (T)k.drift[2]};
   const T diff = (T)k.diff;
@@ -171,6 +172,7 @@ __global__ void __launch_bounds__(kBlock) k_push_uniform(Bank a, Counters* ctr, 
 __global__ void __launch_bounds__(kBlock) k_count(Bank a, Counters* ctr, int which,
                                                  unsigned long long* cellacc, uint32_t* tiles,
                                                  uint32_t cap) {
+  if (ctr->halt) return;
   const uint32_t n = min(ctr->n[which], cap);
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t i = base + threadIdx.x;
@@ -200,6 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_photons(Bank a, Counters* ctr, int w
                                                    uint32_t* ngamma,
                                                    uint32_t* nplus, StepConst k, int n_new,
                                                    double l1, double l2) {
+  if (ctr->halt) return;
   const double two_pi = 6.283185307179586476925286766559;
   const double lr = l2 / l1;
   uint64_t absorbed = 0, lost = 0;
@@ -398,6 +401,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* 
                                                      const uint32_t* cnt, const uint32_t* pre,
                                                      const uint32_t* grp, uint32_t* start,
                                                      uint32_t* occ, Counters* ctr, int dest) {
+  if (ctr->halt) return;
   __shared__ uint32_t sh[2][kBlock / 64 + 1];
   __shared__ __align__(16) uint32_t tile_n[kScanTile];
   const uint32_t ncell = scan_cells(ncell_arg, ncell_dev);
@@ -457,6 +461,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const unsigned long long* 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_scatter(Bank a, Bank b, Counters* ctr, int which,
                                                    const uint32_t* start, uint32_t cap) {
+  if (ctr->halt) return;
   const uint32_t n = min(ctr->n[which], cap);
   if (n <= 2u * gridDim.x * blockDim.x) {
     // at most two passes of the grid: one particle per thread and pass (0.22 ms at

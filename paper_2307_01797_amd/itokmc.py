@@ -29,7 +29,8 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_deposit", "itokmc_diagnostics", "itokmc_get_particles",
            "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
            "itokmc_get_field", "itokmc_set_field", "itokmc_destroy", "itokmc_last_error",
-           "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_kmc_run", "itokmc_rates", "itokmc_set_profiling",
+           "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_kmc_run", "itokmc_rates",
+           "itokmc_step_until", "itokmc_set_profiling",
            "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning",
            "itokmc_ensemble_arena_bytes", "itokmc_ensemble_create", "itokmc_ensemble_admit",
            "itokmc_ensemble_step", "itokmc_ensemble_poll", "itokmc_ensemble_result",
@@ -156,6 +157,7 @@ def lib():
         L.itokmc_check_coefficients.argtypes = [ctypes.POINTER(Coeffs)]
         L.itokmc_seed_particles.argtypes = [P, ctypes.POINTER(SeedDesc)]
         L.itokmc_step.argtypes = [P, U32, D]
+        L.itokmc_step_until.argtypes = [P, U32, D, U64, P]
         L.itokmc_transport.argtypes = [P, D]
         L.itokmc_react.argtypes = [P, D]
         L.itokmc_deposit.argtypes = [P, I32, P]
@@ -299,6 +301,14 @@ class Sim:
     # -- stepping ------------------------------------------------------------------
     def step(self, n=1, dt=None):
         return self._check(lib().itokmc_step(self.h, n, dt or self.cfg["dt"]))
+
+    def step_until(self, n, stop_particles=0, dt=None):
+        """Up to n steps under the device-side stop rule (prescribed-field mode); returns
+        the number of steps taken (synchronises once)."""
+        done = ctypes.c_uint32(0)
+        self._check(lib().itokmc_step_until(self.h, n, dt or self.cfg["dt"], int(stop_particles),
+                                             ctypes.byref(done)))
+        return done.value
 
     def step_rc(self, n=1, dt=None):
         return lib().itokmc_step(self.h, n, dt or self.cfg["dt"])

@@ -38,8 +38,14 @@ CELL_BYTES = 36            # ensemble per-cell arrays
 
 def _stop_rule_run(sim, cfg, cancelled=None):
     """Step a single context under the stop rule; returns steps run, or None if
-    cancelled() became true first."""
+    cancelled() became true first.  In the prescribed-field mode the rule runs on the
+    device (one call, one synchronisation); the self-consistent mode checks it on the
+    host before each step."""
     stop = int(cfg.get("stop_particles", 0))
+    if cfg.get("field") != "poisson":
+        if cancelled is not None and cancelled():
+            return None
+        return sim.step_until(int(cfg["steps"]), stop)
     steps = 0
     for _ in range(int(cfg["steps"])):
         if cancelled is not None and cancelled():

@@ -255,3 +255,35 @@ def test_autotune_keeps_results(itk):
     _drain(ens)
     for cfg, s in zip(cfgs, slots):
         _assert_same(_ens_state(ens, s, cfg["grid"]), _plain_state(_run_plain(itk, cfg)))
+
+
+def test_device_stop_rule_matches_host_rule(itk):
+    """itokmc_step_until (the rule evaluated on the device, one synchronisation) takes
+    the same steps and leaves the same state as the rule checked on the host before
+    each step: runs stopped after an odd and an even number of steps, at the first
+    step, and not at all."""
+    cfgs = _small_realizations(4, steps=60, seed=29)
+    cases = []
+    for c in cfgs[:2]:
+        g = _run_plain(itk, dict(c, stop_particles=0))
+        w = g.diagnostics()["n_particles"]
+        cases.append(dict(c, stop_particles=max(2, w // 2)))   # stops part-way
+    cases.append(dict(cfgs[2], stop_particles=1))              # stops after the first step
+    cases.append(dict(cfgs[3], stop_particles=0))              # runs every step
+    parities = set()
+    for c in cases:
+        host = _run_plain(itk, c)
+        dev = itk.Sim(c, max_particles=c["max_particles"])
+        dev.seed()
+        n = dev.step_until(c["steps"], c["stop_particles"])
+        dh, dd = host.diagnostics(), dev.diagnostics()
+        assert n == dh["step"] == dd["step"]
+        for k in TALLIES:
+            assert dd[k] == dh[k], (c["name"], k)
+        _assert_same(_plain_state(dev), _plain_state(host))
+        parities.add(n % 2)
+        # the context keeps stepping normally afterwards
+        host.step(2)
+        dev.step(2)
+        _assert_same(_plain_state(dev), _plain_state(host))
+    assert parities == {0, 1}
