@@ -61,6 +61,17 @@ class Diag(ctypes.Structure):
         return out
 
 
+class DtRule(ctypes.Structure):
+    _fields_ = [("dt_max", ctypes.c_double), ("c_drift", ctypes.c_double),
+                ("c_diff", ctypes.c_double), ("c_ion", ctypes.c_double)]
+
+
+def make_dt_rule(rule) -> DtRule:
+    """rule: dict with dt_max and any of c_drift, c_diff, c_ion (absent = off)."""
+    return DtRule(float(rule["dt_max"]), float(rule.get("c_drift", 0.0)),
+                  float(rule.get("c_diff", 0.0)), float(rule.get("c_ion", 0.0)))
+
+
 _lib = None
 
 
@@ -127,6 +138,11 @@ def lib():
         L.or_photons_cell.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Coeffs),
                                       ctypes.c_uint32, ctypes.c_int64, ctypes.c_uint32,
                                       P, P, P, P]
+        L.or_field_max.restype = ctypes.c_double
+        L.or_field_max.argtypes = [P]
+        L.or_stable_dt.restype = ctypes.c_double
+        L.or_stable_dt.argtypes = [P, ctypes.POINTER(DtRule), P]
+        L.or_step_adaptive.argtypes = [P, ctypes.POINTER(DtRule), ctypes.c_uint32, P]
         _lib = L
     return _lib
 
@@ -361,6 +377,24 @@ class Sim:
         dg = Diag()
         lib().or_diagnostics(self.h, ctypes.byref(dg))
         return dg.as_dict()
+
+    def field_max(self):
+        return float(lib().or_field_max(self.h))
+
+    def stable_dt(self, rule):
+        """(dt, Emax) of the dynamic time-step rule for the next step."""
+        r = make_dt_rule(rule)
+        em = np.zeros(1)
+        dt = lib().or_stable_dt(self.h, ctypes.byref(r), _p(em))
+        return float(dt), float(em[0])
+
+    def step_adaptive(self, rule, n):
+        r = make_dt_rule(rule)
+        dts = np.zeros(max(int(n), 1))
+        rc = lib().or_step_adaptive(self.h, ctypes.byref(r), int(n), _p(dts))
+        if rc:
+            raise RuntimeError("oracle adaptive step failed")
+        return dts[:int(n)]
 
     def ngp_weight(self):
         v = np.zeros(self.ncell, dtype=np.int64)

@@ -133,6 +133,22 @@ int or_transport(or_sim* s, double dt);
 int or_react(or_sim* s, double dt);
 int or_step(or_sim* s, double dt, uint32_t nsteps);
 void or_diagnostics(const or_sim* s, or_diag* out);
+
+/* ---- dynamic time step (see sim.c) ---------------------------------------------- */
+typedef struct {
+  double dt_max;   /* upper bound, s (> 0)                                           */
+  double c_drift;  /* dt <= c_drift dx / v(Emax); off when <= 0                      */
+  double c_diff;   /* dt <= c_diff dx^2 / (2 D); off when <= 0 or D == 0             */
+  double c_ion;    /* dt <= c_ion / (alpha(Emax) v(Emax)); off when <= 0 or no rate   */
+} or_dt_rule;
+/* Largest |E| over the cell centres of the field the next step starts from (uniform
+ * mode: |E_uniform|); in the Poisson mode the initial field is computed first when
+ * there is none yet (the same solve the first transport would make). */
+double or_field_max(or_sim* s);
+/* The next step's dt under rule r; Emax (may be NULL) receives the field bound. */
+double or_stable_dt(or_sim* s, const or_dt_rule* r, double* Emax);
+/* nsteps steps, each with the dt of or_stable_dt; dts (may be NULL) receives them. */
+int or_step_adaptive(or_sim* s, const or_dt_rule* r, uint32_t nsteps, double* dts);
 /* per-cell electron weight (NGP) of the current particles, int64 per cell */
 void or_ngp_weight(const or_sim* s, int64_t* out);
 /* CIC electron number density (m^-3) of the current particles */

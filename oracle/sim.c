@@ -697,6 +697,58 @@ int or_step(or_sim* s, double dt, uint32_t nsteps) {
   return 0;
 }
 
+/* ---- dynamic time step ---------------------------------------------------------
+ * The paper runs fixed steps and names CFL- or physics-based stepping as the next step
+ * (section Final algorithm, closing paragraph).  Reading taken here: the step is the
+ * smallest of
+ *   dt_max,
+ *   c_drift dx / v(Emax)          (drift CFL: no particle drifts more than c_drift cells),
+ *   c_diff dx^2 / (2 D)           (no axis's diffusive spread exceeds sqrt(c_diff) cells),
+ *   c_ion / (alpha(Emax) v(Emax)) (at most c_ion expected ionizations per electron),
+ * with v(E) = mu(E) E and Emax the largest |E^k| over the cell centres (uniform mode:
+ * |E_uniform|).  A CIC-interpolated field is a convex combination of cell-centre values,
+ * so no particle sees a field above Emax; v and alpha v grow with E (mu_b >= -1), so
+ * the limits hold for every particle.  A limit whose factor is <= 0, or whose rate is
+ * zero, is not applied. */
+double or_field_max(or_sim* s) {
+  const or_desc* d = &s->d;
+  if (d->field_mode == OR_FIELD_UNIFORM) {
+    const double* E = d->E_uniform;
+    return sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+  }
+  if (!s->field_valid) initial_field(s);
+  double m2 = 0.0;
+  for (int64_t c = 0; c < s->ncell; ++c) {
+    double e2 = s->Ex[c] * s->Ex[c] + s->Ey[c] * s->Ey[c] + s->Ez[c] * s->Ez[c];
+    if (e2 > m2) m2 = e2;
+  }
+  return sqrt(m2);
+}
+
+double or_stable_dt(or_sim* s, const or_dt_rule* r, double* Emax_out) {
+  const or_coeffs* c = &s->c;
+  const double dx = s->d.dx;
+  const double Em = or_field_max(s);
+  if (Emax_out) *Emax_out = Em;
+  double dt = r->dt_max;
+  const double v = or_mobility(c, Em) * Em;
+  if (r->c_drift > 0.0 && v > 0.0) dt = fmin(dt, r->c_drift * dx / v);
+  if (r->c_diff > 0.0 && c->D > 0.0) dt = fmin(dt, r->c_diff * dx * dx / (2.0 * c->D));
+  const double nu = Em > 0.0 ? c->alpha_A * exp(-c->alpha_B / Em) * v : 0.0;
+  if (r->c_ion > 0.0 && nu > 0.0) dt = fmin(dt, r->c_ion / nu);
+  return dt;
+}
+
+int or_step_adaptive(or_sim* s, const or_dt_rule* r, uint32_t nsteps, double* dts) {
+  for (uint32_t i = 0; i < nsteps; ++i) {
+    const double dt = or_stable_dt(s, r, NULL);
+    if (dts) dts[i] = dt;
+    if (or_transport(s, dt)) return -1;
+    if (or_react(s, dt)) return -1;
+  }
+  return 0;
+}
+
 void or_diagnostics(const or_sim* s, or_diag* out) {
   *out = s->diag;
   out->n_particles = s->np;
