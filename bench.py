@@ -436,6 +436,8 @@ def main():
     }
     if "push_deposit" in w:
         out["push_deposit"] = w["push_deposit"]
+    if cfg.get("field") == "poisson":
+        out["dt_rule"] = dt_rule_probe(sim, cfg)
     del sim
     torch.cuda.synchronize(dev)
     if cfg["name"] == "streamer_256" and not args.no_scale_window:
@@ -445,6 +447,31 @@ def main():
         if args.cpu_workers > 0:
             out["cpu_baseline_parallel"] = cpu_baseline_parallel(args.cpu_workers, args.cpu_seconds)
     print(json.dumps(out))
+
+
+def dt_rule_probe(sim, cfg, queries=10):
+    """The dynamic time-step rule's field bound on the state the timed windows left:
+    `queries` queries (the state is not changed), the per-cell pass timed with HIP
+    events; algorithmic bytes per launch = the packed field, 4 S per cell."""
+    rule = {"dt_max": cfg["dt"], "c_drift": 0.5, "c_ion": 0.1}
+    sim.set_profiling(True)
+    sim.phase_times(reset=True)
+    for _ in range(queries):
+        dt, em = sim.stable_dt(rule)
+    tot_ms, launches = sim.phase_times(reset=True)["emax"]
+    sim.set_profiling(False)
+    ncell = 1
+    for v in cfg["grid"]:
+        ncell *= v
+    S = 8 if cfg.get("precision") == "fp64" else 4
+    per_launch = 4 * S * ncell
+    achieved = per_launch / (tot_ms / launches / 1e3) / 1e9
+    return {"rule": rule, "dt_s": dt, "Emax_V_per_m": em,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": traffic_from_profile("k_emax_partial", cfg["name"]),
+                         "kernel": "k_emax_partial", "avg_launch_ms": round(tot_ms / launches, 4),
+                         "launches": launches, "bytes_per_launch": per_launch}}
 
 
 def push_deposit_roofline(roofs, psteps, S):

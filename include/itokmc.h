@@ -213,6 +213,41 @@ int itokmc_step_until(itokmc_ctx* ctx, uint32_t nsteps, double dt, uint64_t stop
 int itokmc_transport(itokmc_ctx* ctx, double dt);
 int itokmc_react(itokmc_ctx* ctx, double dt);
 
+/* Dynamic time step.  The paper runs fixed steps and names CFL- or physics-based
+ * stepping as its next step (section "Final algorithm", closing paragraph).  The rule
+ * here takes the smallest of
+ *   dt_max,
+ *   c_drift dx / v(Emax)          drift CFL: no electron drifts more than c_drift cells,
+ *   c_diff dx^2 / (2 D)           diffusive spread of sqrt(c_diff) cells per axis,
+ *   c_ion / (alpha(Emax) v(Emax)) at most c_ion expected ionizations per electron,
+ * with v(E) = mu(E) E and Emax the largest |E| over the cell centres of the field the
+ * next step starts from (E^k; |E_uniform| in the prescribed-field mode).  A limit whose
+ * factor is 0, or whose rate is zero, is off.  Emax bounds every particle's field (a
+ * CIC interpolation is a convex combination of cell-centre values), so the drift and
+ * ionization limits hold for every particle when v and alpha v grow with E, which
+ * needs mu_b >= -1.  In the self-consistent mode the advection uses E^{k+1}, known only
+ * after the step's solve, so there the drift limit is the CFL number of E^k. */
+typedef struct {
+  double dt_max;          /* upper bound (s), > 0                                   */
+  double c_drift;         /* drift limit factor (cells), 0 = off                    */
+  double c_diff;          /* diffusion limit factor (cells^2), 0 = off              */
+  double c_ion;           /* ionization limit factor (per electron), 0 = off        */
+} itokmc_dt_rule;
+
+/* out[0] = dt of the next step, out[1] = Emax (V/m) (host array of 2).  In the
+ * self-consistent mode before the first step, computes the initial field first: the
+ * solve the first transport would make, which it then skips, so the step is the same
+ * as without the query.  Synchronises the stream.  Errors: EINVAL (no coefficients,
+ * dt_max <= 0, a negative or non-finite factor, mu_b < -1 with the drift or
+ * ionization limit on), ENOCONV (initial solve), EHIP. */
+int itokmc_stable_dt(itokmc_ctx* ctx, const itokmc_dt_rule* rule, double* out);
+
+/* nsteps steps, each of the dt that itokmc_stable_dt gives at its start; dts (host
+ * array of nsteps, may be NULL) receives them.  One synchronisation per step (the
+ * query).  Errors as itokmc_stable_dt and itokmc_step. */
+int itokmc_step_adaptive(itokmc_ctx* ctx, const itokmc_dt_rule* rule, uint32_t nsteps,
+                         double* dts);
+
 /* Write a per-cell quantity (selector ITOKMC_Q_*) to the device buffer dev_out of
  * ncell (x3 for FIRES) elements of the stated type, enqueued on the context's stream.
  * NGP weights (the reaction network's electron count of section "KMC-particle
@@ -277,7 +312,8 @@ int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
  * kernel, 7 field solve (with the field from the potential), 8 field push, 9 recount,
  * 10 larger merge tiers, 11 deposit clearing and right-hand side, 12 finest-level
  * smoother launches (one colour each, inside the solve; one count per launch), 13 light
- * coupling pass (one lane per cell).  phase_times synchronises, writes accumulated
+ * coupling pass (one lane per cell), 14 per-cell pass of the time-step rule's field bound
+ * (one count per query).  phase_times synchronises, writes accumulated
  * milliseconds and launch counts for the first n phases, and clears them if reset is
  * nonzero. */
 int itokmc_set_profiling(itokmc_ctx* ctx, int on);

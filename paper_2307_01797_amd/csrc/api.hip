@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <vector>
 
 #include "device.hpp"
@@ -433,6 +434,51 @@ int itokmc_step_until(itokmc_ctx* ctx, uint32_t nsteps, double dt, uint64_t stop
   ctx->cur = (done & 1u) ? 1 - cur0 : cur0;
   ctx->binned = false;
   *steps_done = done;
+  return ITOKMC_OK;
+}
+
+int itokmc_stable_dt(itokmc_ctx* ctx, const itokmc_dt_rule* r, double* out) {
+  if (!ctx || !r || !out) return ITOKMC_EINVAL;
+  if (!ctx->have_coeffs) return set_error(ctx, ITOKMC_EINVAL, "coefficients not set");
+  const auto bad = [](double f) { return !(f >= 0.0) || !std::isfinite(f); };
+  if (!(r->dt_max > 0.0) || !std::isfinite(r->dt_max) || bad(r->c_drift) || bad(r->c_diff) ||
+      bad(r->c_ion))
+    return set_error(ctx, ITOKMC_EINVAL, "time-step rule: dt_max > 0 and finite factors >= 0");
+  const itokmc_coeffs& c = ctx->c;
+  if ((r->c_drift > 0.0 || r->c_ion > 0.0) && c.mu_b < -1.0)
+    return set_error(ctx, ITOKMC_EINVAL, "time-step rule: the field bound needs mu_b >= -1");
+  double Em = 0.0;
+  if (ctx->d.field_mode == ITOKMC_FIELD_UNIFORM) {
+    const double* E = ctx->d.E_uniform;
+    Em = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+  } else {
+    const int rc = field_max(ctx, &Em);
+    if (rc) return rc;
+  }
+  const double dx = ctx->d.dx;
+  const double v = mobility(c, Em) * Em;
+  double dt = r->dt_max;
+  if (r->c_drift > 0.0 && v > 0.0) dt = fmin(dt, r->c_drift * dx / v);
+  if (r->c_diff > 0.0 && c.D > 0.0) dt = fmin(dt, r->c_diff * dx * dx / (2.0 * c.D));
+  const double nu = Em > 0.0 ? c.alpha_A * exp(-c.alpha_B / Em) * v : 0.0;
+  if (r->c_ion > 0.0 && nu > 0.0) dt = fmin(dt, r->c_ion / nu);
+  out[0] = dt;
+  out[1] = Em;
+  return ITOKMC_OK;
+}
+
+int itokmc_step_adaptive(itokmc_ctx* ctx, const itokmc_dt_rule* r, uint32_t nsteps, double* dts) {
+  if (!ctx) return ITOKMC_EINVAL;
+  for (uint32_t i = 0; i < nsteps; ++i) {
+    double q[2];
+    int rc = itokmc_stable_dt(ctx, r, q);
+    if (rc) return rc;
+    if (dts) dts[i] = q[0];
+    rc = itokmc_transport(ctx, q[0]);
+    if (rc) return rc;
+    rc = itokmc_react(ctx, q[0]);
+    if (rc) return rc;
+  }
   return ITOKMC_OK;
 }
 

@@ -2029,17 +2029,24 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   return rc ? rc : check_hip(ctx, hipGetLastError(), "field");
 }
 
+// Initial field: the solution for the present charge with sigma = 0 (the deposit's mode
+// 0 uses neither dt nor the diffusion of K).
+template <typename T>
+static int ensure_field(itokmc_ctx* ctx, FieldState* F, const StepConst& K) {
+  if (ctx->field_valid) return 0;
+  const int rc = deposit_and_solve<T>(ctx, F, K, 0);
+  if (rc) return rc;
+  F->cur = 1 - F->cur;
+  ctx->field_valid = true;
+  return 0;
+}
+
 template <typename T>
 static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
   FieldState* F = fs(ctx);
-  if (!ctx->field_valid) {
-    // initial field: the solution for the present charge with sigma = 0
-    const int rc = deposit_and_solve<T>(ctx, F, K, 0);
-    if (rc) return rc;
-    F->cur = 1 - F->cur;
-    ctx->field_valid = true;
-  }
-  const int rc = deposit_and_solve<T>(ctx, F, K, 1);
+  int rc = ensure_field<T>(ctx, F, K);
+  if (rc) return rc;
+  rc = deposit_and_solve<T>(ctx, F, K, 1);
   if (rc) return rc;
   const int nxt = 1 - F->cur;
   phase_begin(ctx, PH_FIELD_PUSH);
@@ -2054,6 +2061,70 @@ static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
 
 int field_transport(itokmc_ctx* ctx, const StepConst& K) {
   return ctx->d.precision == ITOKMC_FP64 ? transport_t<double>(ctx, K) : transport_t<float>(ctx, K);
+}
+
+// Largest |E|^2 over the cell centres of the packed (Ex, Ey, Ez, 0) field: one partial
+// per workgroup, squares summed in double from the stored components (exact for
+// single-precision fields), then the largest partial.  Non-negative doubles order as
+// their bit patterns, but plain comparisons suffice here: no atomics.
+template <typename T>
+__global__ void __launch_bounds__(256) k_emax_partial(const T* E4, uint32_t n, double* part) {
+  __shared__ double sh[4];
+  double m = 0.0;
+#pragma unroll 4
+  for (uint32_t c = blockIdx.x * 256u + threadIdx.x; c < n; c += gridDim.x * 256u) {
+    const V4<T> e = ld4(E4 + 4 * (size_t)c);
+    const double x = (double)e.a[0], y = (double)e.a[1], z = (double)e.a[2];
+    m = fmax(m, x * x + y * y + z * z);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ void __launch_bounds__(1024) k_max_partials(const double* part, int n, double* out) {
+  __shared__ double sh[16];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) m = fmax(m, part[i]);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int i = 0; i < 16; ++i) r = fmax(r, sh[i]);
+    *out = r;
+  }
+}
+
+template <typename T>
+static int field_max_t(itokmc_ctx* ctx, double* Emax) {
+  FieldState* F = fs(ctx);
+  int rc = ensure_field<T>(ctx, F, make_const(ctx, 0.0));
+  if (rc) return rc;
+  const uint32_t n = ctx->ncell;
+  // at most 2048 workgroups (one resident round of 32 waves per CU); the partials
+  // buffer holds max(kRedBlocks, blocks(n)) entries
+  const int nb = (int)std::min<size_t>(2048, blocks(n));
+  hipStream_t s = ctx->s;
+  phase_begin(ctx, PH_EMAX);  // the per-cell pass alone
+  k_emax_partial<T><<<nb, 256, 0, s>>>((const T*)F->E[F->cur], n, F->norms + 8);
+  phase_end(ctx, PH_EMAX);
+  k_max_partials<<<1, 1024, 0, s>>>(F->norms + 8, nb, F->norms + 3);
+  double m2 = 0.0;
+  hipError_t e = hipMemcpyAsync(&m2, F->norms + 3, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  rc = check_hip(ctx, e, "field max");
+  if (rc) return rc;
+  *Emax = sqrt(m2);
+  return ITOKMC_OK;
+}
+
+int field_max(itokmc_ctx* ctx, double* Emax) {
+  if (!fs(ctx)) return set_error(ctx, ITOKMC_EINVAL, "no field state");
+  return ctx->d.precision == ITOKMC_FP64 ? field_max_t<double>(ctx, Emax) : field_max_t<float>(ctx, Emax);
 }
 
 FieldRates field_rates(itokmc_ctx* ctx) {

@@ -161,7 +161,7 @@ namespace itk {
 // phases timed when profiling is on
 enum Phase { PH_PUSH = 0, PH_PHOTON, PH_SCAN, PH_SCATTER, PH_KMC, PH_COUPLE, PH_DEPOSIT,
              PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_MERGE, PH_FIELD_PREP, PH_SMOOTH_FINE,
-             PH_COUPLE_LIGHT, PH_NUM };
+             PH_COUPLE_LIGHT, PH_EMAX, PH_NUM };
 void phase_begin(itokmc_ctx* ctx, int phase);
 void phase_end(itokmc_ctx* ctx, int phase);
 int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);
@@ -216,6 +216,8 @@ hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k);
 size_t field_bytes(const itokmc_grid_desc* d);
 int field_init(itokmc_ctx* ctx, char* base);
 int field_transport(itokmc_ctx* ctx, const StepConst& k);
+// Largest |E| over the cell centres of E^k (computes the initial field if there is none).
+int field_max(itokmc_ctx* ctx, double* Emax);
 FieldRates field_rates(itokmc_ctx* ctx);  // E view for the KMC rates
 void field_destroy(itokmc_ctx* ctx);
 void field_reset_graph(itokmc_ctx* ctx);

@@ -30,7 +30,8 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_set_particles", "itokmc_get_counts", "itokmc_set_counts", "itokmc_set_step",
            "itokmc_get_field", "itokmc_set_field", "itokmc_destroy", "itokmc_last_error",
            "itokmc_philox_fill", "itokmc_kmc_cells", "itokmc_kmc_run", "itokmc_rates",
-           "itokmc_step_until", "itokmc_set_profiling",
+           "itokmc_step_until", "itokmc_stable_dt", "itokmc_step_adaptive",
+           "itokmc_set_profiling",
            "itokmc_phase_times", "itokmc_set_tuning", "itokmc_get_tuning",
            "itokmc_ensemble_arena_bytes", "itokmc_ensemble_create", "itokmc_ensemble_admit",
            "itokmc_ensemble_step", "itokmc_ensemble_poll", "itokmc_ensemble_result",
@@ -41,7 +42,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_last_error", "itokmc_sort_workspace_bytes", "itokmc_sort_by_cell",
            "itokmc_sort_by_cell_noalloc"]
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
-          "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light"]
+          "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light", "emax"]
 
 
 class GridDesc(ctypes.Structure):
@@ -55,6 +56,17 @@ class GridDesc(ctypes.Structure):
                 ("realization", ctypes.c_uint32), ("max_particles", ctypes.c_uint64),
                 ("gmg_max_cycles", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("gmg_rtol", ctypes.c_double)]
+
+
+class DtRule(ctypes.Structure):
+    _fields_ = [("dt_max", ctypes.c_double), ("c_drift", ctypes.c_double),
+                ("c_diff", ctypes.c_double), ("c_ion", ctypes.c_double)]
+
+
+def make_dt_rule(rule) -> DtRule:
+    """rule: dict with dt_max and any of c_drift, c_diff, c_ion (absent = off)."""
+    return DtRule(float(rule["dt_max"]), float(rule.get("c_drift", 0.0)),
+                  float(rule.get("c_diff", 0.0)), float(rule.get("c_ion", 0.0)))
 
 
 class Coeffs(ctypes.Structure):
@@ -158,6 +170,8 @@ def lib():
         L.itokmc_seed_particles.argtypes = [P, ctypes.POINTER(SeedDesc)]
         L.itokmc_step.argtypes = [P, U32, D]
         L.itokmc_step_until.argtypes = [P, U32, D, U64, P]
+        L.itokmc_stable_dt.argtypes = [P, ctypes.POINTER(DtRule), P]
+        L.itokmc_step_adaptive.argtypes = [P, ctypes.POINTER(DtRule), U32, P]
         L.itokmc_transport.argtypes = [P, D]
         L.itokmc_react.argtypes = [P, D]
         L.itokmc_deposit.argtypes = [P, I32, P]
@@ -301,6 +315,20 @@ class Sim:
     # -- stepping ------------------------------------------------------------------
     def step(self, n=1, dt=None):
         return self._check(lib().itokmc_step(self.h, n, dt or self.cfg["dt"]))
+
+    def stable_dt(self, rule):
+        """(dt, Emax) of the dynamic time-step rule for the next step (synchronises)."""
+        r = make_dt_rule(rule)
+        out = np.zeros(2)
+        self._check(lib().itokmc_stable_dt(self.h, ctypes.byref(r), _np(out)))
+        return float(out[0]), float(out[1])
+
+    def step_adaptive(self, rule, n):
+        """n steps, each of the rule's dt at its start; returns the dts."""
+        r = make_dt_rule(rule)
+        dts = np.zeros(max(int(n), 1))
+        self._check(lib().itokmc_step_adaptive(self.h, ctypes.byref(r), int(n), _np(dts)))
+        return dts[:int(n)]
 
     def step_until(self, n, stop_particles=0, dt=None):
         """Up to n steps under the device-side stop rule (prescribed-field mode); returns

@@ -109,7 +109,7 @@ def test_binding_structs_match_header_layout(tmp_path):
              "itokmc_seed_desc": b.SeedDesc, "itokmc_diag": b.Diag, "itokmc_tuning": b.Tuning,
              "itokmc_ens_desc": b.EnsDesc, "itokmc_run_desc": b.RunDesc,
              "itokmc_slot_event": b.SlotEvent, "itokmc_ens_info": b.EnsInfo,
-             "itokmc_ens_tuning": b.EnsTuning}
+             "itokmc_ens_tuning": b.EnsTuning, "itokmc_dt_rule": b.DtRule}
     lines = ['#include <stdio.h>', '#include "itokmc.h"', "int main(void) {"]
     for cname, cls in pairs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -139,7 +139,7 @@ def test_oracle_binding_structs_match_header_layout(tmp_path):
     import oracle as o
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
-    pairs = {"or_desc": o.Desc, "or_coeffs": o.Coeffs, "or_diag": o.Diag}
+    pairs = {"or_desc": o.Desc, "or_coeffs": o.Coeffs, "or_diag": o.Diag, "or_dt_rule": o.DtRule}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "oracle.h"', "int main(void) {"]
     for cname, cls in pairs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
