@@ -14,6 +14,7 @@ LIBPATH = os.path.join(HERE, "liboracle.so")
 
 FIELD_UNIFORM, FIELD_POISSON = 0, 1
 KMC_HYBRID, KMC_PURE_TAU = 0, 1
+SHAPES = {"cic": 0, "tsc": 1}
 TAG_PUSH, TAG_SEED, TAG_KMC, TAG_CREATE, TAG_PHOTON = 1, 2, 3, 4, 5
 KIND_SEED, KIND_KMC, KIND_PHOTO, KIND_MERGE = 0, 1, 2, 3
 
@@ -24,7 +25,7 @@ class Desc(ctypes.Structure):
                 ("E_uniform", ctypes.c_double * 3), ("V_anode", ctypes.c_double),
                 ("kmc_mode", ctypes.c_int32), ("n_ppc", ctypes.c_int32),
                 ("n_new", ctypes.c_int32), ("kmc_nc", ctypes.c_int32),
-                ("kmc_nssa", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("kmc_nssa", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("kmc_eps", ctypes.c_double), ("seed", ctypes.c_uint32),
                 ("realization", ctypes.c_uint32), ("poisson_rtol", ctypes.c_double)]
 
@@ -134,6 +135,8 @@ def lib():
         L.or_efield.argtypes = [ctypes.POINTER(Desc), P, P, P, P]
         L.or_cic_deposit.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint64, P, P, P]
         L.or_cic_interp.argtypes = [ctypes.POINTER(Desc), P, ctypes.c_uint64, P, P]
+        L.or_tsc_deposit.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint64, P, P, P]
+        L.or_tsc_interp.argtypes = [ctypes.POINTER(Desc), P, ctypes.c_uint64, P, P]
         L.or_photons_cell.restype = ctypes.c_int32
         L.or_photons_cell.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Coeffs),
                                       ctypes.c_uint32, ctypes.c_int64, ctypes.c_uint32,
@@ -168,6 +171,7 @@ def make_desc(cfg) -> Desc:
     d.seed = cfg.get("seed", 1)
     d.realization = cfg.get("realization", 0)
     d.poisson_rtol = cfg.get("oracle_rtol", 1e-13)
+    d.shape = SHAPES[cfg.get("shape", "cic")]
     return d
 
 
@@ -300,6 +304,30 @@ def cic_interp(cfg, grid, xi):
     out = np.zeros(xi.shape[0])
     lib().or_cic_interp(ctypes.byref(d), _p(grid), xi.shape[0], _p(xi), _p(out))
     return out
+
+
+def tsc_deposit(cfg, xi, q):
+    d = make_desc(cfg)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    nx, ny, nz = cfg["grid"]
+    g = np.zeros(nx * ny * nz)
+    lib().or_tsc_deposit(ctypes.byref(d), q.shape[0], _p(xi), _p(q), _p(g))
+    return g
+
+
+def tsc_interp(cfg, grid, xi):
+    d = make_desc(cfg)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    out = np.zeros(xi.shape[0])
+    lib().or_tsc_interp(ctypes.byref(d), _p(grid), xi.shape[0], _p(xi), _p(out))
+    return out
+
+
+def cloud_interp(cfg, grid, xi):
+    """Interpolation with cfg's particle shape (CIC unless cfg['shape'] == 'tsc')."""
+    return tsc_interp(cfg, grid, xi) if cfg.get("shape", "cic") == "tsc" else cic_interp(cfg, grid, xi)
 
 
 def photons_cell(cfg, cell, n_gamma, step):

@@ -18,7 +18,8 @@
  * interpolation", with cell centres at (i + 1/2) dx.  The part of a cloud that lies
  * beyond the outermost cell centres is folded back into the wall cell (the paper's
  * embedded boundaries do not exist here), which conserves the deposited total;
- * interpolation uses the same weights.
+ * interpolation uses the same weights.  A workload may select the quadratic B-spline
+ * (TSC) shape instead (or_tsc_*, below), with the same conventions.
  * Pins (tests): rho = 0 gives the linear potential and the uniform field V/L;
  * manufactured solutions converge at second order; a constant coefficient scales
  * the solution; single-particle CIC weights; total deposited weight.
@@ -189,4 +190,78 @@ void or_cic_interp(const or_desc* d, const double* grid, uint64_t n, const doubl
     }
     out[p] = acc;
   }
+}
+
+/* TSC: the quadratic B-spline cloud (a unit box convolved with the CIC tent), one of
+ * the higher-order particle shapes the paper's future-work section points to.  Along an
+ * axis with cell centres at j + 1/2, a particle at xi has its nearest centre j =
+ * floor(xi), offset d = xi - j - 1/2 in [-1/2, 1/2), and weights (1/2 - d)^2 / 2,
+ * 3/4 - d^2 and (1/2 + d)^2 / 2 on the centres j - 1, j, j + 1.  A centre outside the
+ * grid hands its weight to the wall cell (clamped index), which conserves the total and
+ * keeps the weights a convex combination; interpolation uses the same weights.  Its
+ * moments pin it: the weights sum to 1, reproduce xi as the first moment and xi^2 + 1/4
+ * as the second (inside the grid), and equal the CIC weights averaged over a unit box
+ * centred on the particle. */
+static void tsc_axis(double xi, int n, int idx[3], double w[3]) {
+  const double j = floor(xi);
+  const double dd = xi - j - 0.5;
+  w[0] = 0.5 * (0.5 - dd) * (0.5 - dd);
+  w[1] = 0.75 - dd * dd;
+  w[2] = 0.5 * (0.5 + dd) * (0.5 + dd);
+  for (int a = 0; a < 3; ++a) {
+    double t = j - 1.0 + (double)a;
+    if (t < 0.0) t = 0.0;
+    if (t > (double)(n - 1)) t = (double)(n - 1);
+    idx[a] = (int)t;
+  }
+}
+
+void or_tsc_deposit(const or_desc* d, uint64_t n, const double* xi, const double* q,
+                    double* grid) {
+  for (uint64_t p = 0; p < n; ++p) {
+    int ix[3], iy[3], iz[3];
+    double wx[3], wy[3], wz[3];
+    tsc_axis(xi[3 * p + 0], d->nx, ix, wx);
+    tsc_axis(xi[3 * p + 1], d->ny, iy, wy);
+    tsc_axis(xi[3 * p + 2], d->nz, iz, wz);
+    for (int c = 0; c < 3; ++c)
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+          double wgt = wx[a] * wy[b] * wz[c];
+          if (wgt == 0.0) continue;
+          grid[IDX(d, ix[a], iy[b], iz[c])] += q[p] * wgt;
+        }
+  }
+}
+
+void or_tsc_interp(const or_desc* d, const double* grid, uint64_t n, const double* xi,
+                   double* out) {
+  for (uint64_t p = 0; p < n; ++p) {
+    int ix[3], iy[3], iz[3];
+    double wx[3], wy[3], wz[3];
+    tsc_axis(xi[3 * p + 0], d->nx, ix, wx);
+    tsc_axis(xi[3 * p + 1], d->ny, iy, wy);
+    tsc_axis(xi[3 * p + 2], d->nz, iz, wz);
+    double acc = 0.0;
+    for (int c = 0; c < 3; ++c)
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+          double wgt = wx[a] * wy[b] * wz[c];
+          if (wgt == 0.0) continue;
+          acc += grid[IDX(d, ix[a], iy[b], iz[c])] * wgt;
+        }
+    out[p] = acc;
+  }
+}
+
+void or_cloud_deposit(const or_desc* d, uint64_t n, const double* xi, const double* q,
+                      double* grid) {
+  if (d->shape == OR_SHAPE_TSC) or_tsc_deposit(d, n, xi, q, grid);
+  else or_cic_deposit(d, n, xi, q, grid);
+}
+
+void or_cloud_interp(const or_desc* d, const double* grid, uint64_t n, const double* xi,
+                     double* out) {
+  if (d->shape == OR_SHAPE_TSC) or_tsc_interp(d, grid, n, xi, out);
+  else or_cic_interp(d, grid, n, xi, out);
 }

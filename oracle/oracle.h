@@ -34,6 +34,8 @@ enum { OR_KIND_SEED = 0, OR_KIND_KMC = 1, OR_KIND_PHOTO = 2, OR_KIND_MERGE = 3 }
 
 enum { OR_FIELD_UNIFORM = 0, OR_FIELD_POISSON = 1 };
 enum { OR_KMC_HYBRID = 0, OR_KMC_PURE_TAU = 1 };
+/* Particle shape for the field coupling (deposit and interpolation alike). */
+enum { OR_SHAPE_CIC = 0, OR_SHAPE_TSC = 1 };
 
 typedef struct {
   int32_t nx, ny, nz;      /* cells per axis                                   */
@@ -46,7 +48,7 @@ typedef struct {
   int32_t n_new;           /* max new computational particles per cell (64)    */
   int32_t kmc_nc;          /* critical threshold N_c (5)                       */
   int32_t kmc_nssa;        /* max SSA steps in the SSA exception (10)          */
-  int32_t pad0;
+  int32_t shape;           /* OR_SHAPE_CIC | OR_SHAPE_TSC (Poisson mode)       */
   double kmc_eps;          /* accuracy factor; INFINITY = accept any leap      */
   uint32_t seed, realization; /* Philox key                                    */
   double poisson_rtol;     /* linear-solve relative residual target            */
@@ -151,7 +153,8 @@ double or_stable_dt(or_sim* s, const or_dt_rule* r, double* Emax);
 int or_step_adaptive(or_sim* s, const or_dt_rule* r, uint32_t nsteps, double* dts);
 /* per-cell electron weight (NGP) of the current particles, int64 per cell */
 void or_ngp_weight(const or_sim* s, int64_t* out);
-/* CIC electron number density (m^-3) of the current particles */
+/* electron number density (m^-3) of the current particles with the descriptor's shape
+ * (CIC unless d->shape is TSC) */
 void or_cic_density(const or_sim* s, double* out);
 /* space charge (C/m^3) of the current state: e (n+ - n-) / dV - e n_e(CIC) */
 void or_charge_density(const or_sim* s, double* out);
@@ -189,6 +192,16 @@ void or_cic_deposit(const or_desc* d, uint64_t n, const double* xi, const double
                     double* grid);
 void or_cic_interp(const or_desc* d, const double* grid, uint64_t n, const double* xi,
                    double* out);
+/* TSC (quadratic B-spline) helpers, same conventions (see field.c). */
+void or_tsc_deposit(const or_desc* d, uint64_t n, const double* xi, const double* q,
+                    double* grid);
+void or_tsc_interp(const or_desc* d, const double* grid, uint64_t n, const double* xi,
+                   double* out);
+/* The descriptor's shape (d->shape): CIC or TSC. */
+void or_cloud_deposit(const or_desc* d, uint64_t n, const double* xi, const double* q,
+                      double* grid);
+void or_cloud_interp(const or_desc* d, const double* grid, uint64_t n, const double* xi,
+                     double* out);
 
 /* photon transport of one cell's pending photons; returns absorbed count and fills
  * positions (grid units) and weights of the photo-electrons. */

@@ -27,7 +27,10 @@
  *     weight >= 2;
  *   - the initial field (Poisson mode) is the solution for the present charge with
  *     sigma = 0;
- *   - the mobility formula is evaluated at max(|E|, E_floor).
+ *   - the mobility formula is evaluated at max(|E|, E_floor);
+ *   - with the TSC shape (a higher-order deposit, future work in the paper) the ions,
+ *     point charges at their cell centres, are deposited with the same shape as the
+ *     electrons, so a plasma of both on the same centres stays neutral.
  * Counter-based random streams (Philox key = (seed, realization)):
  *   push normals (id, step, PUSH); KMC (cell, step, KMC) sequential; creation
  *   (cell, slot, step, CREATE); photons (cell, slot, step, PHOTON sub 0/1); seeds
@@ -233,22 +236,45 @@ void or_cic_density(const or_sim* s, double* out) {
   double* xi = xi_array(s);
   double* q = (double*)malloc(sizeof(double) * (s->np ? s->np : 1));
   for (uint64_t i = 0; i < s->np; ++i) q[i] = (double)s->p[i].w / dV;
-  or_cic_deposit(&s->d, s->np, xi, q, out);
+  or_cloud_deposit(&s->d, s->np, xi, q, out);
   free(xi);
   free(q);
 }
 
 /* ---- field (Poisson mode) -------------------------------------------------------- */
 
-/* rho at cell centres from electron positions xi (CIC) and the ion counts (NGP) */
+/* rho at cell centres from electron positions xi and the ion counts.  The ions are
+ * point charges at their cell centres, deposited with the particles' shape: with CIC
+ * that is their own cell (NGP); with TSC they spread over the 27 nearest centres like
+ * any particle sitting on a centre. */
 static void charge_density(const or_sim* s, const double* xi, double* rho) {
   double dV = s->d.dx * s->d.dx * s->d.dx;
   double* ne = (double*)calloc((size_t)s->ncell, sizeof(double));
   double* q = (double*)malloc(sizeof(double) * (s->np ? s->np : 1));
-  for (uint64_t i = 0; i < s->np; ++i) q[i] = (double)s->p[i].w / dV;
-  or_cic_deposit(&s->d, s->np, xi, q, ne);
-  for (int64_t c = 0; c < s->ncell; ++c)
-    rho[c] = OR_E_CHARGE * ((double)(s->nplus[c] - s->nminus[c]) / dV - ne[c]);
+  if (s->d.shape != OR_SHAPE_TSC) {
+    for (uint64_t i = 0; i < s->np; ++i) q[i] = (double)s->p[i].w / dV;
+    or_cic_deposit(&s->d, s->np, xi, q, ne);
+    for (int64_t c = 0; c < s->ncell; ++c)
+      rho[c] = OR_E_CHARGE * ((double)(s->nplus[c] - s->nminus[c]) / dV - ne[c]);
+  } else {
+    /* counts in physical particles (integer charges times dyadic weights: the ion
+     * sums are exact), scaled by the cell volume at the end */
+    for (uint64_t i = 0; i < s->np; ++i) q[i] = (double)s->p[i].w;
+    or_tsc_deposit(&s->d, s->np, xi, q, ne);
+    double* ion = (double*)calloc((size_t)s->ncell, sizeof(double));
+    double* pts = (double*)malloc(sizeof(double) * 3 * (size_t)s->ncell);
+    double* qi = (double*)malloc(sizeof(double) * (size_t)s->ncell);
+    for (int64_t c = 0; c < s->ncell; ++c) {
+      const int64_t i = c % s->d.nx, j = (c / s->d.nx) % s->d.ny, k = c / ((int64_t)s->d.nx * s->d.ny);
+      pts[3 * c + 0] = (double)i + 0.5;
+      pts[3 * c + 1] = (double)j + 0.5;
+      pts[3 * c + 2] = (double)k + 0.5;
+      qi[c] = (double)(s->nplus[c] - s->nminus[c]);
+    }
+    or_tsc_deposit(&s->d, (uint64_t)s->ncell, pts, qi, ion);
+    for (int64_t c = 0; c < s->ncell; ++c) rho[c] = OR_E_CHARGE * (ion[c] - ne[c]) / dV;
+    free(ion); free(pts); free(qi);
+  }
   free(ne);
   free(q);
 }
@@ -344,16 +370,16 @@ int or_transport(or_sim* s, double dt) {
   double* ez = (double*)malloc(sizeof(double) * (np ? np : 1));
   double* mu = (double*)malloc(sizeof(double) * (np ? np : 1));
   /* step 1: sigma^k = e sum_p mu_p w_p W / dV with mu_p = mu(|E^k(X_p^k)|) */
-  or_cic_interp(d, s->Ex, np, xk, ex);
-  or_cic_interp(d, s->Ey, np, xk, ey);
-  or_cic_interp(d, s->Ez, np, xk, ez);
+  or_cloud_interp(d, s->Ex, np, xk, ex);
+  or_cloud_interp(d, s->Ey, np, xk, ey);
+  or_cloud_interp(d, s->Ez, np, xk, ez);
   double* q = (double*)malloc(sizeof(double) * (np ? np : 1));
   for (uint64_t i = 0; i < np; ++i) {
     mu[i] = or_mobility(c, sqrt(ex[i] * ex[i] + ey[i] * ey[i] + ez[i] * ez[i]));
     q[i] = OR_E_CHARGE * mu[i] * (double)s->p[i].w / dV;
   }
   double* sigma = (double*)calloc((size_t)s->ncell, sizeof(double));
-  or_cic_deposit(d, np, xk, q, sigma);
+  or_cloud_deposit(d, np, xk, q, sigma);
   /* step 2: X_dagger = X^k + sqrt(2 D dt) N */
   for (uint64_t i = 0; i < np; ++i) {
     double n[3];
@@ -368,9 +394,9 @@ int or_transport(or_sim* s, double dt) {
   for (int64_t cc = 0; cc < s->ncell; ++cc) eps[cc] = 1.0 + sigma[cc] * dt / OR_EPS0;
   solve_field(s, rho, eps);
   /* steps 4-5: V^{k+1} = -mu^k E^{k+1}(X^k); X^{k+1} = X_dagger + V dt */
-  or_cic_interp(d, s->Ex, np, xk, ex);
-  or_cic_interp(d, s->Ey, np, xk, ey);
-  or_cic_interp(d, s->Ez, np, xk, ez);
+  or_cloud_interp(d, s->Ex, np, xk, ex);
+  or_cloud_interp(d, s->Ey, np, xk, ey);
+  or_cloud_interp(d, s->Ez, np, xk, ez);
   for (uint64_t i = 0; i < np; ++i) {
     s->p[i].xi[0] += -mu[i] * ex[i] * dt / d->dx;
     s->p[i].xi[1] += -mu[i] * ey[i] * dt / d->dx;
@@ -398,15 +424,15 @@ double or_semi_implicit_residual(const or_sim* s, double dt, const double* phi) 
   double* ey = (double*)malloc(sizeof(double) * (np ? np : 1));
   double* ez = (double*)malloc(sizeof(double) * (np ? np : 1));
   double* q = (double*)malloc(sizeof(double) * (np ? np : 1));
-  or_cic_interp(d, s->Ex, np, xk, ex);
-  or_cic_interp(d, s->Ey, np, xk, ey);
-  or_cic_interp(d, s->Ez, np, xk, ez);
+  or_cloud_interp(d, s->Ex, np, xk, ex);
+  or_cloud_interp(d, s->Ey, np, xk, ey);
+  or_cloud_interp(d, s->Ez, np, xk, ez);
   for (uint64_t i = 0; i < np; ++i) {
     double mu = or_mobility(c, sqrt(ex[i] * ex[i] + ey[i] * ey[i] + ez[i] * ez[i]));
     q[i] = OR_E_CHARGE * mu * (double)s->p[i].w / dV;
   }
   double* sigma = (double*)calloc((size_t)s->ncell, sizeof(double));
-  or_cic_deposit(d, np, xk, q, sigma);
+  or_cloud_deposit(d, np, xk, q, sigma);
   double* xd = (double*)malloc(sizeof(double) * 3 * (np ? np : 1));
   for (uint64_t i = 0; i < np; ++i) {
     double n[3];
@@ -433,12 +459,12 @@ void or_push_with_fields(const or_desc* d, const or_coeffs* c, uint64_t n, const
   for (uint64_t i = 0; i < n; ++i) {
     const double* x = xi + 3 * i;
     double ek[3], e1[3], nrm[3];
-    or_cic_interp(d, Ekx, 1, x, &ek[0]);
-    or_cic_interp(d, Eky, 1, x, &ek[1]);
-    or_cic_interp(d, Ekz, 1, x, &ek[2]);
-    or_cic_interp(d, E1x, 1, x, &e1[0]);
-    or_cic_interp(d, E1y, 1, x, &e1[1]);
-    or_cic_interp(d, E1z, 1, x, &e1[2]);
+    or_cloud_interp(d, Ekx, 1, x, &ek[0]);
+    or_cloud_interp(d, Eky, 1, x, &ek[1]);
+    or_cloud_interp(d, Ekz, 1, x, &ek[2]);
+    or_cloud_interp(d, E1x, 1, x, &e1[0]);
+    or_cloud_interp(d, E1y, 1, x, &e1[1]);
+    or_cloud_interp(d, E1z, 1, x, &e1[2]);
     double mu = or_mobility(c, sqrt(ek[0] * ek[0] + ek[1] * ek[1] + ek[2] * ek[2]));
     or_normals3(id[i], step, d->seed, d->realization, nrm);
     for (int a = 0; a < 3; ++a) out[3 * i + a] = (x[a] + diff * nrm[a]) + (-mu * e1[a] * dt / d->dx);
