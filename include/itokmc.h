@@ -47,6 +47,16 @@ enum {
 enum { ITOKMC_FP32 = 0, ITOKMC_FP64 = 1 };
 enum { ITOKMC_FIELD_UNIFORM = 0, ITOKMC_FIELD_POISSON = 1 };
 enum { ITOKMC_KMC_HYBRID = 0, ITOKMC_KMC_PURE_TAU = 1 };
+/* Particle shape of the field coupling: the conductivity and charge deposits and the
+ * field interpolation of the self-consistent mode, and the density and charge queries
+ * in either mode, all use it.  CIC: the tent of the section
+ * "Charge deposition & interpolation".  TSC: the quadratic B-spline (the tent averaged
+ * over a unit box, 27 cells), one of the higher-order deposits of the section "Future
+ * work"; along an axis with centres at j + 1/2, nearest centre j, offset d in
+ * [-1/2, 1/2): weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2; a centre outside the
+ * grid hands its weight to the wall cell; the immobile ions, point charges at their
+ * cell centres, take the same shape. */
+enum { ITOKMC_SHAPE_CIC = 0, ITOKMC_SHAPE_TSC = 1 };
 enum { ITOKMC_SEED_GAUSSIAN = 0, ITOKMC_SEED_NEUTRAL = 1 };
 /* itokmc_deposit / counts selectors */
 enum {
@@ -54,13 +64,15 @@ enum {
   ITOKMC_Q_NPLUS = 1,      /* uint32 per cell: positive ions                          */
   ITOKMC_Q_NMINUS = 2,     /* uint32 per cell: negative ions                          */
   ITOKMC_Q_NGAMMA = 3,     /* uint32 per cell: photons pending transport              */
-  ITOKMC_Q_CIC_DENSITY = 4,/* double per cell: electron density (m^-3), CIC           */
+  ITOKMC_Q_CIC_DENSITY = 4,/* double per cell: electron density (m^-3) with the grid's
+                              shape (CIC, or TSC when selected)                      */
   ITOKMC_Q_PHI = 5,        /* double per cell: potential (V), field mode POISSON      */
   ITOKMC_Q_EX = 6, ITOKMC_Q_EY = 7, ITOKMC_Q_EZ = 8, /* double per cell: E (V/m)     */
   ITOKMC_Q_FIRES = 9,      /* uint32 per cell x 3: ionization, attachment and emission
                               fires of the last step (recombination: totals only)    */
   ITOKMC_Q_RHO = 10        /* double per cell: space charge e((n+ - n-)/dV - n_e) with
-                              n_e the CIC density of the current particles (C/m^3)   */
+                              n_e the density of the current particles and the ions
+                              deposited with the grid's shape (C/m^3)                */
 };
 /* itokmc_diag.overflow flags (any set flag makes itokmc_diagnostics return ECAPACITY) */
 enum {
@@ -93,7 +105,7 @@ typedef struct {
   uint32_t seed, realization; /* key of every random stream                          */
   uint64_t max_particles;  /* particle capacity (per bank)                           */
   int32_t gmg_max_cycles;  /* max multigrid cycles per solve                          */
-  int32_t pad0;
+  int32_t shape;           /* ITOKMC_SHAPE_CIC | ITOKMC_SHAPE_TSC                     */
   double gmg_rtol;         /* relative residual target of the field solve            */
 } itokmc_grid_desc;
 

@@ -139,6 +139,7 @@ bool valid_desc(const itokmc_grid_desc* d) {
   if (d->precision != ITOKMC_FP32 && d->precision != ITOKMC_FP64) return false;
   if (d->field_mode != ITOKMC_FIELD_UNIFORM && d->field_mode != ITOKMC_FIELD_POISSON) return false;
   if (d->kmc_mode != ITOKMC_KMC_HYBRID && d->kmc_mode != ITOKMC_KMC_PURE_TAU) return false;
+  if (d->shape != ITOKMC_SHAPE_CIC && d->shape != ITOKMC_SHAPE_TSC) return false;
   if (d->n_new < 1 || d->n_new > 64) return false;
   if (d->n_ppc < 0 || d->n_ppc > 64) return false;
   if (d->kmc_nc < 0 || d->kmc_nssa < 1) return false;

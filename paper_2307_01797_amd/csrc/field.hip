@@ -214,6 +214,96 @@ __device__ __forceinline__ void cic_get3(const T* E4, const StepConst& K, int i0
   cic_sum<T>(g, out);
 }
 
+// ---- TSC (quadratic B-spline) helpers ---------------------------------------------
+
+// Along one axis, for a particle in cell c with offset t from the cell's lower face (t
+// may leave [0,1) for X_dagger): nearest cell centre j = c + floor(t), d = t - floor(t)
+// - 1/2, weights (1/2 - d)^2 / 2, 3/4 - d^2 and (1/2 + d)^2 / 2 on the centres j - 1, j
+// and j + 1; a centre outside the grid hands its weight to the wall cell (the index is
+// clamped), so the weights stay a convex combination that sums to one.
+template <typename T>
+struct Tsc {
+  int ix[3], iy[3], iz[3];
+  T wx[3], wy[3], wz[3];
+};
+template <typename T>
+__device__ __forceinline__ void tsc_axis(int c, T t, int n, int idx[3], T w[3]) {
+  const T fl = floor(t);
+  const T d = t - fl - (T)0.5;
+  const T lo = (T)0.5 - d, hi = (T)0.5 + d;
+  w[0] = (T)0.5 * lo * lo;
+  w[1] = (T)0.75 - d * d;
+  w[2] = (T)0.5 * hi * hi;
+  const int j = c + (int)fl;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int x = j - 1 + q;
+    idx[q] = x < 0 ? 0 : (x > n - 1 ? n - 1 : x);
+  }
+}
+template <typename T>
+__device__ __forceinline__ Tsc<T> tsc_at(const StepConst& K, int ci, int cj, int ck, T tx, T ty, T tz) {
+  Tsc<T> s;
+  tsc_axis<T>(ci, tx, K.nx, s.ix, s.wx);
+  tsc_axis<T>(cj, ty, K.ny, s.iy, s.wy);
+  tsc_axis<T>(ck, tz, K.nz, s.iz, s.wz);
+  return s;
+}
+// The field at a particle from the packed (Ex, Ey, Ez, 0) array: one z plane's nine
+// node vectors loaded together, then each component summed in node order (z, y, x),
+// weight (wx wy) wz, nodes of zero weight skipped.
+template <typename T>
+__device__ __forceinline__ void tsc_get3(const T* E4, const StepConst& K, const Tsc<T>& s, T out[3]) {
+  const size_t nx = (size_t)K.nx, ny = (size_t)K.ny;
+  T acc[3] = {(T)0, (T)0, (T)0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V4<T> v[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      v[q] = ld4(E4 + 4 * ((size_t)s.ix[q % 3] + nx * ((size_t)s.iy[q / 3] + ny * (size_t)s.iz[c])));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const T wt = (s.wx[q % 3] * s.wy[q / 3]) * s.wz[c];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc[a] = wt != (T)0 ? acc[a] + v[q].a[a] * wt : acc[a];
+    }
+  }
+  out[0] = acc[0];
+  out[1] = acc[1];
+  out[2] = acc[2];
+}
+
+// Ion charge (units of e) that cell (i, j, k) receives with the TSC shape: the immobile
+// ions are point charges at their cell centres, so along each axis a cell keeps 3/4 of
+// its own and takes 1/8 of each neighbour's, and a wall cell also keeps the 1/8 that
+// would fall outside.  Every term is an integer times a multiple of 1/512: the sum is
+// exact in double, in any order.
+__device__ __forceinline__ double tsc_keep(int i, int n) {
+  return 0.75 + (i == 0 ? 0.125 : 0.0) + (i == n - 1 ? 0.125 : 0.0);
+}
+__device__ __forceinline__ double ion_tsc(const uint32_t* np, const uint32_t* nm, int i, int j, int k,
+                                          int nx, int ny, int nz) {
+  double acc = 0.0;
+  for (int dk = -1; dk <= 1; ++dk) {
+    const int kk = k + dk;
+    if (kk < 0 || kk >= nz) continue;
+    const double wz = dk ? 0.125 : tsc_keep(k, nz);
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= ny) continue;
+      const double wyz = (dj ? 0.125 : tsc_keep(j, ny)) * wz;
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= nx) continue;
+        const size_t c = (size_t)ii + (size_t)nx * ((size_t)jj + (size_t)ny * kk);
+        acc += ((double)np[c] - (double)nm[c]) * ((di ? 0.125 : tsc_keep(i, nx)) * wyz);
+      }
+    }
+  }
+  return acc;
+}
+
 template <typename T> struct Mob;
 template <> struct Mob<double> {
   __device__ static double mu(const Coef& c, double E) {
@@ -344,13 +434,39 @@ __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v
   }
 }
 
+// The 27 TSC contributions of one particle into the table (clamped wall nodes repeat
+// and simply add), with the same slot rule.
+template <typename T, int L2>
+__device__ __forceinline__ void tbl_tsc(uint32_t* keys, typename DepAcc<T>::S* v0,
+                                        typename DepAcc<T>::S* v1, const StepConst& K, const Tsc<T>& s,
+                                        double qa, double qb, typename DepAcc<T>::S* g0,
+                                        typename DepAcc<T>::S* g1) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const uint32_t row = (uint32_t)s.iy[b] + (uint32_t)K.ny * (uint32_t)s.iz[c];
+      const uint32_t hr = (row * 2654435761u) >> (32 - L2);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T wt = (s.wx[a] * s.wy[b]) * s.wz[c];
+        if (wt == (T)0) continue;
+        const uint32_t node = (uint32_t)s.ix[a] + (uint32_t)K.nx * row;
+        const uint32_t h = ((uint32_t)s.ix[a] + hr) & ((1u << L2) - 1u);
+        tbl_add<T, L2>(keys, v0, v1, node, h, qa * (double)wt, qb * (double)wt, g0, g1);
+      }
+    }
+  }
+}
+
 // Single precision: at least 7 waves per SIMD (72 VGPRs, no spills), which measured about
 // 3% faster than the compiler's 75 VGPRs and 6 waves in a side-by-side run on the same
 // state; 8 waves spill and are slower.  Double precision keeps the compiler's choice (a
 // 72-VGPR bound spills).
+// The TSC form (SH = 1: 27 nodes per deposit and gather) keeps the compiler's choice.
 template <typename T> constexpr int kDepMinWaves = sizeof(T) == 4 ? 7 : 1;
-template <typename T, int L2>
-__global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
+template <typename T, int L2, int SH>
+__global__ void __launch_bounds__(256, SH == 0 ? kDepMinWaves<T> : 1) k_field_deposit_lds(Bank a, const Counters* ctr, int which,
                                                           StepConst K, const void* E4, Coef co,
                                                           int mode, typename DepAcc<T>::S* sig,
                                                           typename DepAcc<T>::S* ne, uint32_t chunk,
@@ -378,29 +494,49 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
       int ci, cj, ck;
       cell_ijk(cell, K, ci, cj, ck);
       const T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
-      int i0, j0, k0;
-      T fx, fy, fz;
-      tent_axis<T>(ci, o[0], K.nx, i0, fx);
-      tent_axis<T>(cj, o[1], K.ny, j0, fy);
-      tent_axis<T>(ck, o[2], K.nz, k0, fz);
-      if (mode == 0) {
+      if constexpr (SH == 0) {
+        int i0, j0, k0;
+        T fx, fy, fz;
+        tent_axis<T>(ci, o[0], K.nx, i0, fx);
+        tent_axis<T>(cj, o[1], K.ny, j0, fy);
+        tent_axis<T>(ck, o[2], K.nz, k0, fz);
+        if (mode == 0) {
+          tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, 0.0, (double)w, sig, ne);
+          continue;
+        }
+        T e[3];
+        cic_get3<T>(ctp<T>(E4), K, i0, j0, k0, fx, fy, fz, e);
+        const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        const T mu = Mob<T>::mu(co, Em);
+        mu_out[i] = mu;
+        tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (double)mu * (double)w, 0.0, sig, ne);
+        const uint64_t id = a.id[i];
+        const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
+        T nr[3];
+        NormalsF<T>::get(r, nr);
+        tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
+        tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
+        tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
         tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, 0.0, (double)w, sig, ne);
-        continue;
+      } else {
+        const Tsc<T> sk = tsc_at<T>(K, ci, cj, ck, o[0], o[1], o[2]);
+        if (mode == 0) {
+          tbl_tsc<T, L2>(keys, v0, v1, K, sk, 0.0, (double)w, sig, ne);
+          continue;
+        }
+        T e[3];
+        tsc_get3<T>(ctp<T>(E4), K, sk, e);
+        const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        const T mu = Mob<T>::mu(co, Em);
+        mu_out[i] = mu;
+        tbl_tsc<T, L2>(keys, v0, v1, K, sk, (double)mu * (double)w, 0.0, sig, ne);
+        const uint64_t id = a.id[i];
+        const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
+        T nr[3];
+        NormalsF<T>::get(r, nr);
+        const Tsc<T> sd = tsc_at<T>(K, ci, cj, ck, o[0] + diff * nr[0], o[1] + diff * nr[1], o[2] + diff * nr[2]);
+        tbl_tsc<T, L2>(keys, v0, v1, K, sd, 0.0, (double)w, sig, ne);
       }
-      T e[3];
-      cic_get3<T>(ctp<T>(E4), K, i0, j0, k0, fx, fy, fz, e);
-      const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-      const T mu = Mob<T>::mu(co, Em);
-      mu_out[i] = mu;
-      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, (double)mu * (double)w, 0.0, sig, ne);
-      const uint64_t id = a.id[i];
-      const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
-      T nr[3];
-      NormalsF<T>::get(r, nr);
-      tent_axis<T>(ci, o[0] + diff * nr[0], K.nx, i0, fx);
-      tent_axis<T>(cj, o[1] + diff * nr[1], K.ny, j0, fy);
-      tent_axis<T>(ck, o[2] + diff * nr[2], K.nz, k0, fz);
-      tbl_cic<T, L2>(keys, v0, v1, K, i0, j0, k0, fx, fy, fz, 0.0, (double)w, sig, ne);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < TBL; t += blockDim.x) {
@@ -415,7 +551,7 @@ __global__ void __launch_bounds__(256, kDepMinWaves<T>) k_field_deposit_lds(Bank
 
 // Semi-implicit push: X^{k+1} = X^k + sqrt(2 D dt) N - mu(|E^k(X^k)|) E^{k+1}(X^k) dt,
 // then binning exactly as the uniform push.
-template <typename T>
+template <typename T, int SH>
 __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int which,
                                                    unsigned long long* cellacc, uint32_t* tiles,
                                                    StepConst K, const T* mu_in, const void* En4) {
@@ -446,16 +582,20 @@ __global__ void __launch_bounds__(256) k_push_field(Bank a, Counters* ctr, int w
       int ci[3];
       cell_ijk(cell, K, ci[0], ci[1], ci[2]);
       T o[3] = {o0[0], o0[1], o0[2]};
-      int i0, j0, k0;
-      T fx, fy, fz;
-      tent_axis<T>(ci[0], o[0], K.nx, i0, fx);
-      tent_axis<T>(ci[1], o[1], K.ny, j0, fy);
-      tent_axis<T>(ci[2], o[2], K.nz, k0, fz);
       T en[3];
-      CicNodes<T> gn;
-      cic_load<T>(ctp<T>(En4), K, i0, j0, k0, fx, fy, fz, gn);
-      __builtin_amdgcn_sched_barrier(0);  // the eight gathers in flight together
-      cic_sum<T>(gn, en);
+      if constexpr (SH == 0) {
+        int i0, j0, k0;
+        T fx, fy, fz;
+        tent_axis<T>(ci[0], o[0], K.nx, i0, fx);
+        tent_axis<T>(ci[1], o[1], K.ny, j0, fy);
+        tent_axis<T>(ci[2], o[2], K.nz, k0, fz);
+        CicNodes<T> gn;
+        cic_load<T>(ctp<T>(En4), K, i0, j0, k0, fx, fy, fz, gn);
+        __builtin_amdgcn_sched_barrier(0);  // the eight gathers in flight together
+        cic_sum<T>(gn, en);
+      } else {
+        tsc_get3<T>(ctp<T>(En4), K, tsc_at<T>(K, ci[0], ci[1], ci[2], o[0], o[1], o[2]), en);
+      }
       const T mu = mu0;  // mu(|E^k(X^k)|), kept by this step's deposit
       const uint64_t id = id0;
       const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
@@ -552,8 +692,8 @@ __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t*
                                                    const uint32_t* nminus,
                                                    const typename DepAcc<T>::S* ne,
                                                    const typename DepAcc<T>::S* sig,
-                                                   double sig_scale, double V, int split, T* eps,
-                                                   double* b, double* partial) {
+                                                   double sig_scale, double V, int split, int tsc,
+                                                   T* eps, double* b, double* partial) {
   const uint32_t n = K.ncell;
   const double dV = K.dx * K.dx * K.dx;
   const double qscale = K.dx * K.dx * kE / (kEps0 * dV);
@@ -566,7 +706,9 @@ __global__ void __launch_bounds__(256) k_field_prep(StepConst K, const uint32_t*
       const uint32_t row = c / (uint32_t)K.nx, k = row / (uint32_t)K.ny;
       const int i = (int)(c - row * (uint32_t)K.nx), j = (int)(row - k * (uint32_t)K.ny);
       eps[split ? pos_of<true>(i, j, (int)k, K.nx, K.ny) : (size_t)c] = (T)e;
-      const double rho_units = (double)nplus[c] - (double)nminus[c] - DepAcc<T>::dec1(ne[c]);
+      const double ions = tsc ? ion_tsc(nplus, nminus, i, j, (int)k, K.nx, K.ny, K.nz)
+                              : (double)nplus[c] - (double)nminus[c];
+      const double rho_units = ions - DepAcc<T>::dec1(ne[c]);
       bb = qscale * rho_units;
       if (k == (uint32_t)K.nz - 1) bb += 2.0 * (double)(T)e * V;
       b[c] = bb;
@@ -1997,9 +2139,14 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
     const size_t lds = (size_t)(1 << L2) * (4 + 2 * sizeof(S));
     int g = (int)((ctx->cap + kDepChunk - 1) / kDepChunk);
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
-    k_field_deposit_lds<T, L2><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo,
-                                                   coef(ctx), mode, (S*)F->sig, (S*)F->ne,
-                                                   (uint32_t)kDepChunk, (T*)ctx->mu_p);
+    if (ctx->d.shape == ITOKMC_SHAPE_TSC)
+      k_field_deposit_lds<T, L2, 1><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo,
+                                                        coef(ctx), mode, (S*)F->sig, (S*)F->ne,
+                                                        (uint32_t)kDepChunk, (T*)ctx->mu_p);
+    else
+      k_field_deposit_lds<T, L2, 0><<<g, 256, lds, s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, Eo,
+                                                        coef(ctx), mode, (S*)F->sig, (S*)F->ne,
+                                                        (uint32_t)kDepChunk, (T*)ctx->mu_p);
   }
   phase_end(ctx, PH_DEPOSIT);
   phase_begin(ctx, PH_FIELD_PREP);
@@ -2013,7 +2160,8 @@ static int deposit_and_solve(itokmc_ctx* ctx, FieldState* F, const StepConst& K,
   }
   k_field_prep<T><<<kRedBlocks, 256, 0, s>>>(K, ctx->nplus, ctx->nminus, (const S*)F->ne,
                                              (const S*)F->sig, sig_scale, ctx->d.V_anode,
-                                             F->split ? 1 : 0, (T*)F->lev[0].eps, F->b, F->norms + 8);
+                                             F->split ? 1 : 0, ctx->d.shape == ITOKMC_SHAPE_TSC ? 1 : 0,
+                                             (T*)F->lev[0].eps, F->b, F->norms + 8);
   k_sum_partials<<<1, 1024, 0, s>>>(F->norms + 8, kRedBlocks, F->norms);
   phase_end(ctx, PH_FIELD_PREP);
   phase_begin(ctx, PH_SOLVE);
@@ -2052,8 +2200,12 @@ static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
   phase_begin(ctx, PH_FIELD_PUSH);
   // at most 1024 workgroups looping over the particles: 0.375 ms per step at 9.5e6
   // particles against 0.405 ms with 4096 and 0.45 ms with 512
-  k_push_field<T><<<blocks(ctx->cap, 1024), 256, 0, ctx->s>>>(
-      ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, (const T*)ctx->mu_p, F->E[nxt]);
+  if (ctx->d.shape == ITOKMC_SHAPE_TSC)
+    k_push_field<T, 1><<<blocks(ctx->cap, 1024), 256, 0, ctx->s>>>(
+        ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, (const T*)ctx->mu_p, F->E[nxt]);
+  else
+    k_push_field<T, 0><<<blocks(ctx->cap, 1024), 256, 0, ctx->s>>>(
+        ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, (const T*)ctx->mu_p, F->E[nxt]);
   phase_end(ctx, PH_FIELD_PUSH);
   F->cur = nxt;  // E^{k+1} becomes the field of the next step
   return check_hip(ctx, hipGetLastError(), "field push");
@@ -2184,7 +2336,7 @@ int field_deposit(itokmc_ctx* ctx, int what, void* dev_out) {
 
 // CIC electron density of the current particles (diagnostic query), double atomics.
 namespace {
-template <typename T>
+template <typename T, int SH>
 __global__ void k_cic_density(Bank a, const Counters* ctr, int which, StepConst K, double inv_dV,
                               double* out) {
   const uint32_t n = min(ctr->n[which], K.cap);
@@ -2192,12 +2344,27 @@ __global__ void k_cic_density(Bank a, const Counters* ctr, int which, StepConst 
     const uint32_t w = a.w[i];
     if (!w) continue;
     const uint32_t cell = a.cell[i];
-    int i0, j0, k0;
-    double fx, fy, fz;
-    tent_axis<double>((int)(cell % (uint32_t)K.nx), (double)ctp<T>(a.ox)[i], K.nx, i0, fx);
-    tent_axis<double>((int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny), (double)ctp<T>(a.oy)[i], K.ny, j0, fy);
-    tent_axis<double>((int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny)), (double)ctp<T>(a.oz)[i], K.nz, k0, fz);
-    cic_add<double>(out, K, i0, j0, k0, fx, fy, fz, (double)w * inv_dV);
+    const int ci = (int)(cell % (uint32_t)K.nx), cj = (int)((cell / (uint32_t)K.nx) % (uint32_t)K.ny);
+    const int ck = (int)(cell / ((uint32_t)K.nx * (uint32_t)K.ny));
+    const double ox = (double)ctp<T>(a.ox)[i], oy = (double)ctp<T>(a.oy)[i], oz = (double)ctp<T>(a.oz)[i];
+    const double q = (double)w * inv_dV;
+    if constexpr (SH == 0) {
+      int i0, j0, k0;
+      double fx, fy, fz;
+      tent_axis<double>(ci, ox, K.nx, i0, fx);
+      tent_axis<double>(cj, oy, K.ny, j0, fy);
+      tent_axis<double>(ck, oz, K.nz, k0, fz);
+      cic_add<double>(out, K, i0, j0, k0, fx, fy, fz, q);
+    } else {
+      const Tsc<double> s = tsc_at<double>(K, ci, cj, ck, ox, oy, oz);
+      for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+          for (int aa = 0; aa < 3; ++aa) {
+            const double wt = (s.wx[aa] * s.wy[b]) * s.wz[c];
+            if (wt == 0.0) continue;
+            atomicAdd(&out[(size_t)s.ix[aa] + (size_t)K.nx * ((size_t)s.iy[b] + (size_t)K.ny * s.iz[c])], q * wt);
+          }
+    }
   }
 }
 }  // namespace
@@ -2207,20 +2374,33 @@ hipError_t launch_cic_density(itokmc_ctx* ctx, double* out) {
   if (e != hipSuccess) return e;
   StepConst K = make_const(ctx, 0.0);
   const double inv_dV = 1.0 / (ctx->d.dx * ctx->d.dx * ctx->d.dx);
-  if (ctx->d.precision == ITOKMC_FP64)
-    k_cic_density<double><<<2048, 256, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, inv_dV, out);
-  else
-    k_cic_density<float><<<2048, 256, 0, ctx->s>>>(ctx->bank[ctx->cur], ctx->ctr, ctx->cur, K, inv_dV, out);
+  const bool tsc = ctx->d.shape == ITOKMC_SHAPE_TSC;
+  Bank b = ctx->bank[ctx->cur];
+  if (ctx->d.precision == ITOKMC_FP64) {
+    if (tsc) k_cic_density<double, 1><<<2048, 256, 0, ctx->s>>>(b, ctx->ctr, ctx->cur, K, inv_dV, out);
+    else k_cic_density<double, 0><<<2048, 256, 0, ctx->s>>>(b, ctx->ctr, ctx->cur, K, inv_dV, out);
+  } else {
+    if (tsc) k_cic_density<float, 1><<<2048, 256, 0, ctx->s>>>(b, ctx->ctr, ctx->cur, K, inv_dV, out);
+    else k_cic_density<float, 0><<<2048, 256, 0, ctx->s>>>(b, ctx->ctr, ctx->cur, K, inv_dV, out);
+  }
   return hipGetLastError();
 }
 
 // Space charge of the current state (deposit query): e ((n+ - n-) / dV - n_e) with n_e
 // the CIC density written into out by launch_cic_density.
 namespace {
-__global__ void k_rho_from_density(double* out, const uint32_t* np, const uint32_t* nm, uint32_t n,
-                                   double inv_dV) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    out[i] = kE * (((double)np[i] - (double)nm[i]) * inv_dV - out[i]);
+__global__ void k_rho_from_density(double* out, const uint32_t* np, const uint32_t* nm, StepConst K,
+                                   int tsc, double inv_dV) {
+  const uint32_t n = K.ncell;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    double ions = (double)np[c] - (double)nm[c];
+    if (tsc) {
+      const uint32_t row = c / (uint32_t)K.nx, k = row / (uint32_t)K.ny;
+      ions = ion_tsc(np, nm, (int)(c - row * (uint32_t)K.nx), (int)(row - k * (uint32_t)K.ny), (int)k, K.nx,
+                     K.ny, K.nz);
+    }
+    out[c] = kE * (ions * inv_dV - out[c]);
+  }
 }
 }  // namespace
 
@@ -2228,7 +2408,9 @@ hipError_t launch_rho(itokmc_ctx* ctx, double* out) {
   hipError_t e = launch_cic_density(ctx, out);
   if (e != hipSuccess) return e;
   const double inv_dV = 1.0 / (ctx->d.dx * ctx->d.dx * ctx->d.dx);
-  k_rho_from_density<<<blocks(ctx->ncell), 256, 0, ctx->s>>>(out, ctx->nplus, ctx->nminus, ctx->ncell, inv_dV);
+  const int tsc = ctx->d.shape == ITOKMC_SHAPE_TSC ? 1 : 0;
+  k_rho_from_density<<<blocks(ctx->ncell), 256, 0, ctx->s>>>(out, ctx->nplus, ctx->nminus, make_const(ctx, 0.0),
+                                                            tsc, inv_dV);
   return hipGetLastError();
 }
 

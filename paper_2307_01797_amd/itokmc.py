@@ -41,6 +41,7 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_ensemble_get_tuning", "itokmc_ensemble_autotune", "itokmc_ensemble_destroy",
            "itokmc_ensemble_last_error", "itokmc_sort_workspace_bytes", "itokmc_sort_by_cell",
            "itokmc_sort_by_cell_noalloc"]
+SHAPES = {"cic": 0, "tsc": 1}
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
           "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light", "emax"]
 
@@ -54,7 +55,7 @@ class GridDesc(ctypes.Structure):
                 ("kmc_nc", ctypes.c_int32), ("kmc_nssa", ctypes.c_int32),
                 ("kmc_eps", ctypes.c_double), ("seed", ctypes.c_uint32),
                 ("realization", ctypes.c_uint32), ("max_particles", ctypes.c_uint64),
-                ("gmg_max_cycles", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("gmg_max_cycles", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("gmg_rtol", ctypes.c_double)]
 
 
@@ -251,6 +252,7 @@ def make_desc(cfg, precision=None, max_particles=None):
     d.max_particles = int(max_particles or cfg.get("max_particles", 4_000_000))
     d.gmg_max_cycles = cfg.get("gmg_max_cycles", 50)
     d.gmg_rtol = cfg.get("gmg_rtol", 1e-10)
+    d.shape = SHAPES[cfg.get("shape", "cic")]
     return d
 
 

@@ -57,6 +57,10 @@ STREAMER_256_DENSE = dict(STREAMER_256, name="streamer_256_dense", seed_peak=1e2
                           seed_centre=(0.5e-3, 0.5e-3, 0.5e-3), seed_sigma=65e-6,
                           max_particles=160_000_000)
 
+# The 256^3 streamer with the quadratic B-spline (TSC) shape for the conductivity and
+# charge deposits and the field interpolation (27 cells per particle instead of 8).
+STREAMER_256_TSC = dict(STREAMER_256, name="streamer_256_tsc", shape="tsc")
+
 # The same gap at 64^3 (dx = 15.6 um), 200 steps: precision study size.
 STREAMER_64 = dict(STREAMER_256, name="streamer_64", grid=(64, 64, 64), dx=1e-3 / 64,
                    steps=200, max_particles=4_000_000)
@@ -90,7 +94,8 @@ REACTOR_B = dict(REACTOR_A, name="reactor_b", E_field=1.7e6, X0=5, n_reactors=20
 def preset(name, **overrides):
     base = {"avalanche_32": AVALANCHE_32, "streamer_256": STREAMER_256,
             "streamer_64": STREAMER_64, "avalanche_256": AVALANCHE_256,
-            "streamer_256_dense": STREAMER_256_DENSE, "reactor_a": REACTOR_A,
+            "streamer_256_dense": STREAMER_256_DENSE, "streamer_256_tsc": STREAMER_256_TSC,
+            "reactor_a": REACTOR_A,
             "reactor_b": REACTOR_B}[name]
     cfg = copy.deepcopy(base)
     for k, v in overrides.items():
