@@ -38,10 +38,14 @@ class Coeffs(ctypes.Structure):
                 ("photon_l1", ctypes.c_double), ("photon_l2", ctypes.c_double),
                 ("beta_ep", ctypes.c_double), ("beta_ep_b", ctypes.c_double),
                 ("Te_a", ctypes.c_double), ("Te_b", ctypes.c_double),
-                ("beta_np", ctypes.c_double)]
+                ("beta_np", ctypes.c_double), ("mu_ion", ctypes.c_double),
+                ("D_ion", ctypes.c_double)]
 
-# recombination coefficients are optional in a coefficient set (absent: reaction off)
+# recombination coefficients are optional in a coefficient set (absent: reaction off),
+# and so are the ion transport coefficients (absent: immobile ions)
 RECOMB_FIELDS = ("beta_ep", "beta_ep_b", "Te_a", "Te_b", "beta_np")
+ION_FIELDS = ("mu_ion", "D_ion")
+OPTIONAL_FIELDS = RECOMB_FIELDS + ION_FIELDS
 
 
 class Diag(ctypes.Structure):
@@ -52,7 +56,8 @@ class Diag(ctypes.Structure):
                 ("photons_absorbed", ctypes.c_uint64), ("photons_lost", ctypes.c_uint64),
                 ("created", ctypes.c_uint64), ("removed_weight", ctypes.c_uint64),
                 ("merged_cells", ctypes.c_uint64), ("step", ctypes.c_uint32),
-                ("solver_iters", ctypes.c_int32), ("solver_relres", ctypes.c_double)]
+                ("solver_iters", ctypes.c_int32), ("solver_relres", ctypes.c_double),
+                ("ion_outflow_plus", ctypes.c_uint64), ("ion_outflow_minus", ctypes.c_uint64)]
 
     def as_dict(self):
         out = {}
@@ -179,7 +184,7 @@ def make_coeffs(cfg) -> Coeffs:
     c = Coeffs()
     co = cfg["coeffs"]
     for name, _ in Coeffs._fields_:
-        setattr(c, name, co.get(name, 0.0) if name in RECOMB_FIELDS else co[name])
+        setattr(c, name, co.get(name, 0.0) if name in OPTIONAL_FIELDS else co[name])
     return c
 
 

@@ -26,7 +26,7 @@ extern "C" {
 /* Philox4x32-10 counter tags (top byte of counter word 3). */
 enum {
   OR_TAG_PUSH = 1, OR_TAG_SEED = 2, OR_TAG_KMC = 3, OR_TAG_CREATE = 4,
-  OR_TAG_PHOTON = 5, OR_TAG_CONFIG = 7, OR_TAG_ARRIVAL = 8
+  OR_TAG_PHOTON = 5, OR_TAG_ION = 6, OR_TAG_CONFIG = 7, OR_TAG_ARRIVAL = 8
 };
 
 /* Particle id kinds (bits 63:62). */
@@ -66,6 +66,9 @@ typedef struct {
    *   k_ep = beta_ep * T_e^beta_ep_b / dV with T_e = max(300 K, Te_a (E/mu_E0)^Te_b) K,
    *   k_np = beta_np / dV (beta_np at the gas temperature, 300 K)                 */
   double beta_ep, beta_ep_b, Te_a, Te_b, beta_np;
+  /* ion transport (0 and 0: immobile ions): ion mobility, m^2/(V s), and ion
+   * diffusion coefficient, m^2/s; positive ions drift along E, negative against */
+  double mu_ion, D_ion;
 } or_coeffs;
 
 typedef struct {
@@ -81,6 +84,7 @@ typedef struct {
   uint32_t step;
   int32_t solver_iters;             /* last linear solve                          */
   double solver_relres;             /* last linear solve                          */
+  uint64_t ion_outflow_plus, ion_outflow_minus; /* ions lost through domain faces */
 } or_diag;
 
 typedef struct or_sim or_sim;

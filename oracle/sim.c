@@ -12,8 +12,10 @@
  * sgn(Z) = -1).
  *
  * Readings where the text is silent:
- *   - ions are immobile per-cell counts located at cell centres (the paper moves
- *     them as particles; their mobility is not given);
+ *   - ions are per-cell counts located at cell centres (the paper moves them as
+ *     particles; their mobility is not given): immobile unless an ion mobility or
+ *     diffusion coefficient is set, when they move on the grid as a lattice jump
+ *     process (move_ions);
  *   - particles that leave any domain face are removed and their weight tallied;
  *   - mobility inside eq. Vk1 is mu^k = mu(|E^k(X^k)|); D is constant;
  *   - photons counted by the reactions of step k are transported in step k+1
@@ -38,6 +40,21 @@
  */
 #include "or_internal.h"
 #include <stdio.h>
+
+static inline int64_t IDXS(const or_desc* d, int i, int j, int k) {
+  return (int64_t)i + (int64_t)d->nx * ((int64_t)j + (int64_t)d->ny * k);
+}
+
+/* cell-centre field of cell c: the step's solved field, or the prescribed one */
+static void field_at(const or_sim* s, int64_t c, double E[3]) {
+  if (s->d.field_mode == OR_FIELD_UNIFORM) {
+    for (int a = 0; a < 3; ++a) E[a] = s->d.E_uniform[a];
+  } else {
+    E[0] = s->Ex[c];
+    E[1] = s->Ey[c];
+    E[2] = s->Ez[c];
+  }
+}
 
 uint64_t or_make_id(int kind, uint32_t step, uint32_t cell, uint32_t slot) {
   return ((uint64_t)kind << 62) | ((uint64_t)(step & 0x3FFFFFu) << 40) |
@@ -332,6 +349,79 @@ void or_set_field(or_sim* s, const double* phi) {
 
 /* ---- transport ------------------------------------------------------------------- */
 
+/* ---- ion transport -----------------------------------------------------------------
+ * The paper moves ions as Ito particles (eq. Vk1 with sgn(Z) = +1 for positive ions)
+ * and, in its future-work section, proposes treating heavy species as a continuum.
+ * Reading taken: the ions stay per-cell integer counts (the reaction network's
+ * populations) and drift and diffuse on the grid as a lattice jump process, the
+ * first-order upwind finite-volume form of the drift-diffusion equation realised with
+ * integer jumps.  An ion of sign q in a cell crosses the face towards its neighbour
+ * along axis a in direction d (-1 or +1) at the rate
+ *     max(0, d q mu_ion E_face,a) / dx + D_ion / dx^2,
+ * with E_face the mean of the two cell-centre fields (the cell's own on a domain face).
+ * Over a step the rates are frozen and each face's count is Poisson(n rate dt), n the
+ * cell's count at the start of the move (tau leaping of the jump process), drawn for M+
+ * then M- in the face order -x, +x, -y, +y, -z, +z from the cell's stream (cell, step,
+ * ION), each capped at the ions not yet moved; ions crossing a domain face leave and are
+ * tallied.  The field is the step's E^{k+1} (the uniform field in the prescribed mode):
+ * the ions move explicitly, their dielectric relaxation time being far above dt. */
+static void move_ions(or_sim* s, double dt) {
+  const or_desc* d = &s->d;
+  const or_coeffs* c = &s->c;
+  if (!(c->mu_ion > 0.0) && !(c->D_ion > 0.0)) return;
+  const int n3[3] = {d->nx, d->ny, d->nz};
+  const double inv_dx = 1.0 / d->dx;
+  const double dr = c->D_ion / (d->dx * d->dx);
+  int64_t* nxt[2];
+  nxt[0] = (int64_t*)calloc((size_t)s->ncell, sizeof(int64_t));
+  nxt[1] = (int64_t*)calloc((size_t)s->ncell, sizeof(int64_t));
+  const int64_t* cur[2] = {s->nplus, s->nminus};
+  uint64_t out[2] = {0, 0};
+  for (int k = 0; k < d->nz; ++k)
+    for (int j = 0; j < d->ny; ++j)
+      for (int i = 0; i < d->nx; ++i) {
+        const int64_t c0 = IDXS(d, i, j, k);
+        if (cur[0][c0] == 0 && cur[1][c0] == 0) continue;
+        double Ec[3];
+        field_at(s, c0, Ec);
+        or_stream st;
+        or_stream_init(&st, (uint32_t)c0, s->step, OR_TAG_ION, 0, d->seed, d->realization);
+        for (int sp = 0; sp < 2; ++sp) {
+          const int64_t n0 = cur[sp][c0];
+          const double q = sp == 0 ? 1.0 : -1.0;
+          int64_t left = n0;
+          for (int f = 0; f < 6; ++f) {
+            const int a = f / 2, dir = (f & 1) ? 1 : -1;
+            int ijk[3] = {i, j, k};
+            ijk[a] += dir;
+            const int inside = ijk[a] >= 0 && ijk[a] < n3[a];
+            double Ef = Ec[a];
+            int64_t nb = -1;
+            if (inside) {
+              double En[3];
+              nb = IDXS(d, ijk[0], ijk[1], ijk[2]);
+              field_at(s, nb, En);
+              Ef = 0.5 * (Ec[a] + En[a]);
+            }
+            const double v = q * c->mu_ion * Ef;
+            const double rate = fmax(0.0, (double)dir * v) * inv_dx + dr;
+            int64_t K = or_poisson((double)n0 * rate * dt, &st);
+            if (K > left) K = left;
+            left -= K;
+            if (inside) nxt[sp][nb] += K;
+            else out[sp] += (uint64_t)K;
+          }
+          nxt[sp][c0] += left;
+        }
+      }
+  memcpy(s->nplus, nxt[0], sizeof(int64_t) * (size_t)s->ncell);
+  memcpy(s->nminus, nxt[1], sizeof(int64_t) * (size_t)s->ncell);
+  s->diag.ion_outflow_plus += out[0];
+  s->diag.ion_outflow_minus += out[1];
+  free(nxt[0]);
+  free(nxt[1]);
+}
+
 static void remove_outside(or_sim* s) {
   uint64_t keep = 0;
   for (uint64_t i = 0; i < s->np; ++i) {
@@ -357,6 +447,7 @@ int or_transport(or_sim* s, double dt) {
       or_normals3(s->p[i].id, s->step, d->seed, d->realization, n);
       for (int a = 0; a < 3; ++a) s->p[i].xi[a] += (-mu * E[a] * dt) / d->dx + diff * n[a];
     }
+    move_ions(s, dt);
     remove_outside(s);
     return 0;
   }
@@ -404,6 +495,7 @@ int or_transport(or_sim* s, double dt) {
   }
   free(xk); free(ex); free(ey); free(ez); free(mu); free(q); free(sigma);
   free(xd); free(rho); free(eps);
+  move_ions(s, dt);
   remove_outside(s);
   return 0;
 }
