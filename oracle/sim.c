@@ -361,8 +361,10 @@ void or_set_field(or_sim* s, const double* phi) {
  * with E_face the mean of the two cell-centre fields (the cell's own on a domain face).
  * Over a step the rates are frozen and each face's count is Poisson(n rate dt), n the
  * cell's count at the start of the move (tau leaping of the jump process), drawn for M+
- * then M- in the face order -x, +x, -y, +y, -z, +z from the cell's stream (cell, step,
- * ION), each capped at the ions not yet moved; ions crossing a domain face leave and are
+ * then M- in the face order -x, +x, -y, +y, -z, +z, each from its own stream (cell,
+ * step, ION, sub = 6 species + face) so that a face whose rate is zero on one side of a
+ * comparison and a rounding error on the other shifts no other face's draws; each count
+ * is capped at the ions not yet moved; ions crossing a domain face leave and are
  * tallied.  The field is the step's E^{k+1} (the uniform field in the prescribed mode):
  * the ions move explicitly, their dielectric relaxation time being far above dt. */
 static void move_ions(or_sim* s, double dt) {
@@ -384,8 +386,6 @@ static void move_ions(or_sim* s, double dt) {
         if (cur[0][c0] == 0 && cur[1][c0] == 0) continue;
         double Ec[3];
         field_at(s, c0, Ec);
-        or_stream st;
-        or_stream_init(&st, (uint32_t)c0, s->step, OR_TAG_ION, 0, d->seed, d->realization);
         for (int sp = 0; sp < 2; ++sp) {
           const int64_t n0 = cur[sp][c0];
           const double q = sp == 0 ? 1.0 : -1.0;
@@ -405,6 +405,9 @@ static void move_ions(or_sim* s, double dt) {
             }
             const double v = q * c->mu_ion * Ef;
             const double rate = fmax(0.0, (double)dir * v) * inv_dx + dr;
+            or_stream st;
+            or_stream_init(&st, (uint32_t)c0, s->step, OR_TAG_ION, (uint32_t)(6 * sp + f), d->seed,
+                           d->realization);
             int64_t K = or_poisson((double)n0 * rate * dt, &st);
             if (K > left) K = left;
             left -= K;
