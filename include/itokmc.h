@@ -119,11 +119,24 @@ typedef struct {
  * k_ep = beta_ep T_e^beta_ep_b / dV with the electron temperature
  * T_e = max(300 K, Te_a (max(E,E_floor)/mu_E0)^Te_b) (a synthetic stand-in for the
  * tabulated T_e(E)), k_np = beta_np / dV; propensities k_ep X_e X_M+ and
- * k_np X_M+ X_M-.  The batched ensemble does not take recombination (EINVAL). */
+ * k_np X_M+ X_M-.  The batched ensemble does not take recombination (EINVAL).
+ * Ion transport (the paper moves ions as Ito particles and proposes heavy species as a
+ * continuum in the section "Future work"): the ion counts stay per cell and move, once
+ * per transport with the step's field E^{k+1} (the prescribed field in the uniform
+ * mode), as a lattice jump process: an ion of sign q crosses the face towards its
+ * neighbour along an axis in direction d = -1, +1 at the rate
+ * max(0, d q mu_ion E_face) / dx + D_ion / dx^2 (E_face: mean of the two cell-centre
+ * fields, the cell's own on a domain face); per step each face's count is
+ * Poisson(n rate dt), n the count before the move, drawn for M+ then M- in the order
+ * -x, +x, -y, +y, -z, +z, each from its own stream (cell, step, ION, sub = 6 species +
+ * face), each capped at the ions not yet moved; ions leaving the domain are tallied in
+ * itokmc_diag.  The batched
+ * ensemble does not take mobile ions (EINVAL). */
 typedef struct {
   double mu_a, mu_E0, mu_b, E_floor, D, alpha_A, alpha_B, eta, kgamma_ratio;
   double photon_l1, photon_l2;
   double beta_ep, beta_ep_b, Te_a, Te_b, beta_np;
+  double mu_ion, D_ion;   /* ion transport (see below); both 0: immobile ions          */
 } itokmc_coeffs;
 
 /* Initial particles.  GAUSSIAN: n0 electrons of weight 1 at centre + sigma N(0,1)^3,
@@ -162,6 +175,8 @@ typedef struct {
                                      coupling pass (cells with merging or many particles) */
   uint32_t wave_cells;            /* cells of the last step's wavefront coupling pass  */
   uint32_t pad2;
+  uint64_t ion_outflow_plus;      /* cumulative positive and negative ions lost      */
+  uint64_t ion_outflow_minus;     /* through domain faces (mobile ions)              */
 } itokmc_diag;
 
 /* Bytes of device arena needed for a descriptor (0 if the descriptor is invalid).
@@ -325,7 +340,7 @@ int itokmc_get_tuning(itokmc_ctx* ctx, itokmc_tuning* tuning);
  * 10 larger merge tiers, 11 deposit clearing and right-hand side, 12 finest-level
  * smoother launches (one colour each, inside the solve; one count per launch), 13 light
  * coupling pass (one lane per cell), 14 per-cell pass of the time-step rule's field bound
- * (one count per query).  phase_times synchronises, writes accumulated
+ * (one count per query), 15 ion transport (its three passes).  phase_times synchronises, writes accumulated
  * milliseconds and launch counts for the first n phases, and clears them if reset is
  * nonzero. */
 int itokmc_set_profiling(itokmc_ctx* ctx, int on);

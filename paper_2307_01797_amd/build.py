@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libitokmc.so")
-SOURCES = ["api.hip", "particles.hip", "kmc.hip", "couple.hip", "field.hip", "ensemble.hip", "sort.hip"]
+SOURCES = ["api.hip", "particles.hip", "kmc.hip", "couple.hip", "field.hip", "ensemble.hip", "sort.hip",
+           "ions.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

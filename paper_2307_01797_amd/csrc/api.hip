@@ -187,17 +187,20 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(nc * 4);                        // 33 cells for the wavefront coupling pass
   put(nc * 4);                        // 34 cells to merge after the light pass
   put(d->field_mode == ITOKMC_FIELD_POISSON ? cap * T : 64);  // 35 mobility per particle
+  put(nc * 4);                        // 36 positive ions after a transport move
+  put(nc * 4);                        // 37 negative ions after a transport move
   L->total = o;
 }
 
 int check_coeffs(const itokmc_coeffs* c, std::string* why) {
   const double v[] = {c->mu_a, c->mu_E0, c->mu_b, c->E_floor, c->D, c->alpha_A, c->alpha_B,
                       c->eta, c->kgamma_ratio, c->photon_l1, c->photon_l2, c->beta_ep,
-                      c->beta_ep_b, c->Te_a, c->Te_b, c->beta_np};
+                      c->beta_ep_b, c->Te_a, c->Te_b, c->beta_np, c->mu_ion, c->D_ion};
   for (double x : v)
     if (!isfinite(x)) { *why = "non-finite coefficient"; return ITOKMC_EINVAL; }
   if (c->mu_a < 0 || !(c->mu_E0 > 0) || !(c->E_floor > 0) || c->D < 0 || c->alpha_A < 0 ||
-      c->eta < 0 || c->kgamma_ratio < 0 || c->beta_ep < 0 || c->Te_a < 0 || c->beta_np < 0) {
+      c->eta < 0 || c->kgamma_ratio < 0 || c->beta_ep < 0 || c->Te_a < 0 || c->beta_np < 0 ||
+      c->mu_ion < 0 || c->D_ion < 0) {
     *why = "negative transport or rate coefficient";
     return ITOKMC_EINVAL;
   }
@@ -271,6 +274,8 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->cfull = (uint32_t*)(a + L.off[33]);
   ctx->cmerge = (uint32_t*)(a + L.off[34]);
   ctx->mu_p = a + L.off[35];
+  ctx->ion_next[0] = (uint32_t*)(a + L.off[36]);
+  ctx->ion_next[1] = (uint32_t*)(a + L.off[37]);
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);
@@ -346,6 +351,7 @@ int itokmc_transport(itokmc_ctx* ctx, double dt) {
     phase_begin(ctx, PH_PUSH);
     rc = check_hip(ctx, launch_push_uniform(ctx, k), "push");
     phase_end(ctx, PH_PUSH);
+    if (!rc && mobile_ions(ctx)) rc = check_hip(ctx, launch_ion_move(ctx, k, nullptr), "ions");
   } else {
     if (ctx->binned) {
       rc = mark_unbinned(ctx);
@@ -547,6 +553,8 @@ int itokmc_diagnostics(itokmc_ctx* ctx, itokmc_diag* out) {
   out->occupied_cells = c.n_occ;
   out->queued_cells = c.n_work;
   out->wave_cells = c.n_cfull + c.n_cmerge;
+  out->ion_outflow_plus = c.ion_out[0];
+  out->ion_outflow_minus = c.ion_out[1];
   out->couple_pieces = c.couple_pieces;
   out->solver_cycles_total = ctx->total_cycles;
   out->solves_total = ctx->total_solves;

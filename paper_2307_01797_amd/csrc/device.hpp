@@ -7,7 +7,7 @@
 namespace itk {
 
 // Philox counter tags (top byte of counter word 3) and particle-id kinds.
-enum : uint32_t { TAG_PUSH = 1, TAG_SEED = 2, TAG_KMC = 3, TAG_CREATE = 4, TAG_PHOTON = 5 };
+enum : uint32_t { TAG_PUSH = 1, TAG_SEED = 2, TAG_KMC = 3, TAG_CREATE = 4, TAG_PHOTON = 5, TAG_ION = 6 };
 enum : uint32_t { KIND_SEED = 0, KIND_KMC = 1, KIND_PHOTO = 2, KIND_MERGE = 3 };
 
 constexpr uint32_t kInvalidCell = 0xFFFFFFFFu;

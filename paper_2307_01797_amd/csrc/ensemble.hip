@@ -888,6 +888,8 @@ int itokmc_ensemble_admit(itokmc_ens* e, const itokmc_grid_desc* d, const itokmc
   if (check_coeffs(c, &why)) return ens_error(e, ITOKMC_EINVAL, "%s", why.c_str());
   if (c->beta_ep > 0.0 || c->beta_np > 0.0)
     return ens_error(e, ITOKMC_EINVAL, "the ensemble does not take recombination");
+  if (c->mu_ion > 0.0 || c->D_ion > 0.0)
+    return ens_error(e, ITOKMC_EINVAL, "the ensemble does not take mobile ions");
   if (c->kgamma_ratio != 0.0) return ens_error(e, ITOKMC_EINVAL, "ensemble realizations carry no photons");
   if (sd->kind != ITOKMC_SEED_GAUSSIAN || !(sd->sigma > 0.0))
     return ens_error(e, ITOKMC_EINVAL, "ensemble seeds are Gaussian electrons with sigma > 0");

@@ -2208,6 +2208,10 @@ static int transport_t(itokmc_ctx* ctx, const StepConst& K) {
         ctx->bank[ctx->cur], ctx->ctr, ctx->cur, ctx->cellacc, ctx->tiles, K, (const T*)ctx->mu_p, F->E[nxt]);
   phase_end(ctx, PH_FIELD_PUSH);
   F->cur = nxt;  // E^{k+1} becomes the field of the next step
+  if (mobile_ions(ctx)) {
+    const hipError_t e = launch_ion_move(ctx, K, F->E[nxt]);
+    if (e != hipSuccess) return check_hip(ctx, e, "ions");
+  }
   return check_hip(ctx, hipGetLastError(), "field push");
 }
 

@@ -55,6 +55,7 @@ struct Counters {
   uint32_t halt;
   uint32_t steps_done;
   unsigned long long pushed_mark;    // `pushed` at the start of the current step
+  unsigned long long ion_out[2];     // positive and negative ions lost through domain faces
 };
 
 // Device-side copy of the per-step constants shared by the kernels.
@@ -128,6 +129,7 @@ struct itokmc_ctx {
   uint32_t* huge = nullptr;               // occupied-cell indices for the large merge pass
   uint32_t* cfull = nullptr;              // cells for the wavefront coupling pass
   uint32_t* cmerge = nullptr;             // cells to merge after the light coupling pass
+  uint32_t* ion_next[2] = {nullptr, nullptr};  // ion counts after a transport move (M+, M-)
   void* mu_p = nullptr;                   // per particle (self-consistent mode): mu(|E^k(X^k)|)
                                           // written by the deposit, read by the push
   uint32_t* heavy = nullptr;              // occupied-cell indices for the full KMC pass
@@ -161,7 +163,7 @@ namespace itk {
 // phases timed when profiling is on
 enum Phase { PH_PUSH = 0, PH_PHOTON, PH_SCAN, PH_SCATTER, PH_KMC, PH_COUPLE, PH_DEPOSIT,
              PH_SOLVE, PH_FIELD_PUSH, PH_COUNT, PH_MERGE, PH_FIELD_PREP, PH_SMOOTH_FINE,
-             PH_COUPLE_LIGHT, PH_EMAX, PH_NUM };
+             PH_COUPLE_LIGHT, PH_EMAX, PH_IONS, PH_NUM };
 void phase_begin(itokmc_ctx* ctx, int phase);
 void phase_end(itokmc_ctx* ctx, int phase);
 int set_error(itokmc_ctx* ctx, int code, const char* fmt, ...);
@@ -212,6 +214,11 @@ hipError_t launch_kmc_cells(itokmc_ctx* ctx, uint64_t n, const uint32_t* ids, in
                             const double* k, double dt, uint32_t step, int64_t* fires);
 // couple.hip
 hipError_t launch_couple(itokmc_ctx* ctx, const StepConst& k);
+// ions.hip: move the ion counts with the step's field (E4: packed cell-centre field of
+// the precision's type, or null for the prescribed uniform field); no-op without ion
+// transport coefficients
+inline bool mobile_ions(const itokmc_ctx* ctx) { return ctx->c.mu_ion > 0.0 || ctx->c.D_ion > 0.0; }
+hipError_t launch_ion_move(itokmc_ctx* ctx, const StepConst& k, const void* E4);
 // field.hip (Poisson mode)
 size_t field_bytes(const itokmc_grid_desc* d);
 int field_init(itokmc_ctx* ctx, char* base);

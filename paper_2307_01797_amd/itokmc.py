@@ -43,7 +43,8 @@ EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_sort_by_cell_noalloc"]
 SHAPES = {"cic": 0, "tsc": 1}
 PHASES = ["push", "photons", "scan", "scatter", "kmc", "couple", "deposit", "solve",
-          "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light", "emax"]
+          "field_push", "count", "merge", "field_prep", "smooth_fine", "couple_light", "emax",
+          "ions"]
 
 
 class GridDesc(ctypes.Structure):
@@ -74,11 +75,13 @@ class Coeffs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("mu_a", "mu_E0", "mu_b", "E_floor", "D", "alpha_A",
                                                "alpha_B", "eta", "kgamma_ratio", "photon_l1",
                                                "photon_l2", "beta_ep", "beta_ep_b", "Te_a", "Te_b",
-                                               "beta_np")]
+                                               "beta_np", "mu_ion", "D_ion")]
 
 
 # recombination coefficients are optional in a coefficient set (absent: reaction off)
 RECOMB_FIELDS = ("beta_ep", "beta_ep_b", "Te_a", "Te_b", "beta_np")
+ION_FIELDS = ("mu_ion", "D_ion")
+OPTIONAL_FIELDS = RECOMB_FIELDS + ION_FIELDS
 
 
 class Tuning(ctypes.Structure):
@@ -106,7 +109,8 @@ class Diag(ctypes.Structure):
                 ("merge_skipped", ctypes.c_uint32), ("queued_cells", ctypes.c_uint32),
                 ("solver_cycles_total", ctypes.c_uint64), ("solves_total", ctypes.c_uint64),
                 ("couple_pieces", ctypes.c_uint64), ("wave_cells", ctypes.c_uint32),
-                ("pad2", ctypes.c_uint32)]
+                ("pad2", ctypes.c_uint32), ("ion_outflow_plus", ctypes.c_uint64),
+                ("ion_outflow_minus", ctypes.c_uint64)]
 
     def as_dict(self):
         d = {}
@@ -264,7 +268,7 @@ def arena_bytes(cfg, precision=None, max_particles=None):
 def make_coeffs(cfg):
     c = Coeffs()
     for n, _ in Coeffs._fields_:
-        setattr(c, n, cfg["coeffs"].get(n, 0.0) if n in RECOMB_FIELDS else cfg["coeffs"][n])
+        setattr(c, n, cfg["coeffs"].get(n, 0.0) if n in OPTIONAL_FIELDS else cfg["coeffs"][n])
     return c
 
 
