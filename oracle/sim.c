@@ -359,14 +359,21 @@ void or_set_field(or_sim* s, const double* phi) {
  * along axis a in direction d (-1 or +1) at the rate
  *     max(0, d q mu_ion E_face,a) / dx + D_ion / dx^2,
  * with E_face the mean of the two cell-centre fields (the cell's own on a domain face).
- * Over a step the rates are frozen and each face's count is Poisson(n rate dt), n the
- * cell's count at the start of the move (tau leaping of the jump process), drawn for M+
- * then M- in the face order -x, +x, -y, +y, -z, +z, each from its own stream (cell,
- * step, ION, sub = 6 species + face) so that a face whose rate is zero on one side of a
- * comparison and a rounding error on the other shifts no other face's draws; each count
- * is capped at the ions not yet moved; ions crossing a domain face leave and are
- * tallied.  The field is the step's E^{k+1} (the uniform field in the prescribed mode):
- * the ions move explicitly, their dielectric relaxation time being far above dt. */
+ * Over a step the rates are frozen: with n the count before the move, face f (order
+ * -x, +x, -y, +y, -z, +z) has the mean lambda_f = n rate_f dt, and the faces' counts are
+ * independent Poisson(lambda_f) (tau leaping of the jump process).  They are drawn per
+ * species (M+ then M-) in one of two equivalent ways, chosen by the total mean
+ * Lambda = sum lambda_f (summed in face order):
+ *   Lambda < 10: the number of movers N ~ Poisson(Lambda), capped at n, from the stream
+ *     (cell, step, ION, sub = species); each mover then picks its face with one more
+ *     uniform u from that stream, the first face whose running sum of lambda exceeds
+ *     u Lambda (a Poisson total split multinomially gives independent Poisson faces);
+ *   otherwise: each face's Poisson(lambda_f) from its own stream (cell, step, ION,
+ *     sub = 2 + 6 species + face), each capped at the ions not yet moved.
+ * Most cells hold a few ions with a tiny Lambda: the first way costs them one block of
+ * random words instead of six.  Ions crossing a domain face leave and are tallied.  The
+ * field is the step's E^{k+1} (the uniform field in the prescribed mode): the ions move
+ * explicitly, their dielectric relaxation time being far above dt. */
 static void move_ions(or_sim* s, double dt) {
   const or_desc* d = &s->d;
   const or_coeffs* c = &s->c;
@@ -386,35 +393,67 @@ static void move_ions(or_sim* s, double dt) {
         if (cur[0][c0] == 0 && cur[1][c0] == 0) continue;
         double Ec[3];
         field_at(s, c0, Ec);
+        int64_t nb[6];
+        double Ef[6];
+        for (int f = 0; f < 6; ++f) {
+          const int a = f / 2, dir = (f & 1) ? 1 : -1;
+          int ijk[3] = {i, j, k};
+          ijk[a] += dir;
+          nb[f] = -1;
+          Ef[f] = Ec[a];
+          if (ijk[a] >= 0 && ijk[a] < n3[a]) {
+            double En[3];
+            nb[f] = IDXS(d, ijk[0], ijk[1], ijk[2]);
+            field_at(s, nb[f], En);
+            Ef[f] = 0.5 * (Ec[a] + En[a]);
+          }
+        }
         for (int sp = 0; sp < 2; ++sp) {
           const int64_t n0 = cur[sp][c0];
+          if (n0 == 0) continue;
           const double q = sp == 0 ? 1.0 : -1.0;
-          int64_t left = n0;
+          double lam[6], L = 0.0;
           for (int f = 0; f < 6; ++f) {
-            const int a = f / 2, dir = (f & 1) ? 1 : -1;
-            int ijk[3] = {i, j, k};
-            ijk[a] += dir;
-            const int inside = ijk[a] >= 0 && ijk[a] < n3[a];
-            double Ef = Ec[a];
-            int64_t nb = -1;
-            if (inside) {
-              double En[3];
-              nb = IDXS(d, ijk[0], ijk[1], ijk[2]);
-              field_at(s, nb, En);
-              Ef = 0.5 * (Ec[a] + En[a]);
-            }
-            const double v = q * c->mu_ion * Ef;
-            const double rate = fmax(0.0, (double)dir * v) * inv_dx + dr;
-            or_stream st;
-            or_stream_init(&st, (uint32_t)c0, s->step, OR_TAG_ION, (uint32_t)(6 * sp + f), d->seed,
-                           d->realization);
-            int64_t K = or_poisson((double)n0 * rate * dt, &st);
-            if (K > left) K = left;
-            left -= K;
-            if (inside) nxt[sp][nb] += K;
-            else out[sp] += (uint64_t)K;
+            const double dir = (f & 1) ? 1.0 : -1.0;
+            const double v = q * c->mu_ion * Ef[f];
+            const double rate = fmax(0.0, dir * v) * inv_dx + dr;
+            lam[f] = (double)n0 * rate * dt;
+            L += lam[f];
           }
-          nxt[sp][c0] += left;
+          int64_t K[6] = {0, 0, 0, 0, 0, 0};
+          if (!(L > 0.0)) {
+            /* no movers */
+          } else if (L < 10.0) {
+            or_stream st;
+            or_stream_init(&st, (uint32_t)c0, s->step, OR_TAG_ION, (uint32_t)sp, d->seed, d->realization);
+            int64_t N = or_poisson(L, &st);
+            if (N > n0) N = n0;
+            for (int64_t m = 0; m < N; ++m) {
+              const double t = or_u_co(or_stream_next(&st)) * L;
+              int f = 0;
+              double acc = lam[0];
+              while (f < 5 && t >= acc) acc += lam[++f];
+              K[f] += 1;
+            }
+          } else {
+            int64_t left = n0;
+            for (int f = 0; f < 6; ++f) {
+              or_stream st;
+              or_stream_init(&st, (uint32_t)c0, s->step, OR_TAG_ION, (uint32_t)(2 + 6 * sp + f), d->seed,
+                             d->realization);
+              int64_t kf = or_poisson(lam[f], &st);
+              if (kf > left) kf = left;
+              left -= kf;
+              K[f] = kf;
+            }
+          }
+          int64_t moved = 0;
+          for (int f = 0; f < 6; ++f) {
+            moved += K[f];
+            if (nb[f] >= 0) nxt[sp][nb[f]] += K[f];
+            else out[sp] += (uint64_t)K[f];
+          }
+          nxt[sp][c0] += n0 - moved;
         }
       }
   memcpy(s->nplus, nxt[0], sizeof(int64_t) * (size_t)s->ncell);
