@@ -37,13 +37,19 @@ HBM_PEAK_GBS = 8000.0
 #   smooth_fine (per finest-level cell and launch of one colour, split red-black order):
 #                      read u and eps of the other colour's cells, f and eps of the
 #                      colour's cells, write u of the colour's cells: 2.5 S
+#   ions (per cell and move, mobile ions only; the three passes together): clear the
+#                      next counts (write 8), read the counts (8), copy back (read 8,
+#                      write 8): 32; the field and the atomics of ion-holding cells are
+#                      not counted
 KERNELS = {"push": "k_push_uniform", "field_push": "k_push_field", "deposit": "k_field_deposit_lds",
-           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_seg<fine>"}
+           "scatter": "k_scatter", "couple": "k_couple", "smooth_fine": "k_smooth_seg<fine>",
+           "ions": "k_ion_move"}
 
 
 def bytes_per_unit(phase, S):
     return {"push": 24 + 6 * S, "field_push": 24 + 7 * S, "deposit": 16 + 4 * S,
-            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 5 * S / 2}[phase]
+            "scatter": 36 + 6 * S, "couple": 32 + 6 * S, "smooth_fine": 5 * S / 2,
+            "ions": 32}[phase]
 
 
 def parse():
@@ -533,7 +539,7 @@ def timed_windows(sim, cfg, steps, dev):
         tot_ms, launches = phases.get(ph, (0.0, 0))
         if not launches or tot_ms <= 0:
             continue
-        if ph == "smooth_fine":
+        if ph in ("smooth_fine", "ions"):
             units = ncell * launches
         elif ph == "couple":
             units = d2.get("couple_pieces", 0) - d1.get("couple_pieces", 0)
@@ -546,7 +552,8 @@ def timed_windows(sim, cfg, steps, dev):
         achieved = per_launch / (tot_ms / launches / 1e3) / 1e9
         roofs[ph] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": kname, "avg_launch_ms": round(tot_ms / launches, 4),
+                     "kernel": kname if ph != "ions" else "k_ion_clear, k_ion_move, k_ion_commit",
+                     "avg_launch_ms": round(tot_ms / launches, 4),
                      "launches": launches, "bytes_per_launch": int(per_launch),
                      "total_ms": round(tot_ms, 3)}
     out = {"value": psteps / (ms / 1e3), "ms": ms, "rc": rc, "ms_p": ms_p, "rc_p": rc_p,

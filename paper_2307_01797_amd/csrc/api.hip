@@ -189,6 +189,7 @@ static void layout(const itokmc_grid_desc* d, Layout* L) {
   put(d->field_mode == ITOKMC_FIELD_POISSON ? cap * T : 64);  // 35 mobility per particle
   put(nc * 4);                        // 36 positive ions after a transport move
   put(nc * 4);                        // 37 negative ions after a transport move
+  put(nc * 8);                        // 38 ion species of large total mean (two per cell)
   L->total = o;
 }
 
@@ -276,6 +277,7 @@ int itokmc_init_grid(itokmc_ctx** out, const itokmc_grid_desc* desc, void* arena
   ctx->mu_p = a + L.off[35];
   ctx->ion_next[0] = (uint32_t*)(a + L.off[36]);
   ctx->ion_next[1] = (uint32_t*)(a + L.off[37]);
+  ctx->ion_big = (uint32_t*)(a + L.off[38]);
   const size_t nb = ctx->ncell;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemsetAsync(ctx->cellacc, 0, nb * 8, ctx->s);

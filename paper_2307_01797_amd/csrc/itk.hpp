@@ -56,6 +56,8 @@ struct Counters {
   uint32_t steps_done;
   unsigned long long pushed_mark;    // `pushed` at the start of the current step
   unsigned long long ion_out[2];     // positive and negative ions lost through domain faces
+  uint32_t n_ionbig;                 // ion species of large total mean left to the second pass
+  uint32_t pad_ion;
 };
 
 // Device-side copy of the per-step constants shared by the kernels.
@@ -130,6 +132,7 @@ struct itokmc_ctx {
   uint32_t* cfull = nullptr;              // cells for the wavefront coupling pass
   uint32_t* cmerge = nullptr;             // cells to merge after the light coupling pass
   uint32_t* ion_next[2] = {nullptr, nullptr};  // ion counts after a transport move (M+, M-)
+  uint32_t* ion_big = nullptr;            // (cell << 1 | species) of large total mean, 2 ncell
   void* mu_p = nullptr;                   // per particle (self-consistent mode): mu(|E^k(X^k)|)
                                           // written by the deposit, read by the push
   uint32_t* heavy = nullptr;              // occupied-cell indices for the full KMC pass

@@ -7,20 +7,22 @@
 
 namespace itk {
 
-__device__ inline int64_t poisson_draw(double lam, CellStream& st) {
-  if (!(lam > 0.0)) return 0;
-  if (lam < 10.0) {
-    const double u = u_co(st.next());
-    double term = exp(-lam);
-    double cdf = term;
-    int64_t k = 0;
-    while (u >= cdf && k < 1000) {
-      ++k;
-      term *= lam / (double)k;
-      cdf += term;
-    }
-    return k;
+// Mean in (0, 10): sequential CDF inversion.
+__device__ inline int64_t poisson_small(double lam, CellStream& st) {
+  const double u = u_co(st.next());
+  double term = exp(-lam);
+  double cdf = term;
+  int64_t k = 0;
+  while (u >= cdf && k < 1000) {
+    ++k;
+    term *= lam / (double)k;
+    cdf += term;
   }
+  return k;
+}
+
+// Mean >= 10: PTRS.
+__device__ inline int64_t poisson_ptrs(double lam, CellStream& st) {
   const double sl = sqrt(lam);
   const double ll = log(lam);
   const double b = 0.931 + 2.53 * sl;
@@ -39,6 +41,11 @@ __device__ inline int64_t poisson_draw(double lam, CellStream& st) {
     if (lhs <= rhs) return (int64_t)kd;
   }
   return (int64_t)floor(lam);  // unreachable in practice; bounds the loop
+}
+
+__device__ inline int64_t poisson_draw(double lam, CellStream& st) {
+  if (!(lam > 0.0)) return 0;
+  return lam < 10.0 ? poisson_small(lam, st) : poisson_ptrs(lam, st);
 }
 
 }  // namespace itk

@@ -61,6 +61,12 @@ STREAMER_256_DENSE = dict(STREAMER_256, name="streamer_256_dense", seed_peak=1e2
 # charge deposits and the field interpolation (27 cells per particle instead of 8).
 STREAMER_256_TSC = dict(STREAMER_256, name="streamer_256_tsc", shape="tsc")
 
+# The 256^3 streamer with mobile ions: ion mobility 2e-4 m^2/(V s) (of the order of
+# atmospheric-pressure N2+/O2- mobilities) and the Einstein diffusion coefficient at 300 K,
+# mu_ion k T / e = 5.2e-6 m^2/s.
+IONS = dict(mu_ion=2e-4, D_ion=5.2e-6)
+STREAMER_256_IONS = dict(STREAMER_256, name="streamer_256_ions", coeffs=dict(STREAMER_256["coeffs"], **IONS))
+
 # The same gap at 64^3 (dx = 15.6 um), 200 steps: precision study size.
 STREAMER_64 = dict(STREAMER_256, name="streamer_64", grid=(64, 64, 64), dx=1e-3 / 64,
                    steps=200, max_particles=4_000_000)
@@ -95,6 +101,7 @@ def preset(name, **overrides):
     base = {"avalanche_32": AVALANCHE_32, "streamer_256": STREAMER_256,
             "streamer_64": STREAMER_64, "avalanche_256": AVALANCHE_256,
             "streamer_256_dense": STREAMER_256_DENSE, "streamer_256_tsc": STREAMER_256_TSC,
+            "streamer_256_ions": STREAMER_256_IONS,
             "reactor_a": REACTOR_A,
             "reactor_b": REACTOR_B}[name]
     cfg = copy.deepcopy(base)
