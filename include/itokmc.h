@@ -225,13 +225,16 @@ int itokmc_seed_particles(itokmc_ctx* ctx, const itokmc_seed_desc* seed);
  * the particles that do not fit, sets a device flag and is reported as ECAPACITY by
  * itokmc_diagnostics (the state stays consistent but incomplete). */
 int itokmc_step(itokmc_ctx* ctx, uint32_t nsteps, double dt);
-/* The same steps under a stop rule evaluated on the device (prescribed-field mode):
- * at most nsteps steps, the run ending after the first step that began with at least
- * stop_particles live particles (0: no particle rule), with no host synchronisation
- * between steps.  All nsteps steps are enqueued; once the rule has ended the run, the
- * kernels of the remaining steps return at entry.  Synchronises once at the end and
- * writes the number of steps taken to *steps_done (the context's step counter and bank
- * follow it).  EINVAL in the self-consistent mode, without coefficients or for dt <= 0. */
+/* The same steps under a stop rule evaluated on the device: at most nsteps steps, the
+ * run ending after the first step that began with at least stop_particles live
+ * particles (0: no particle rule).  Prescribed-field mode: no host synchronisation
+ * between steps; all nsteps steps are enqueued and, once the rule has ended the run,
+ * the kernels of the remaining steps return at entry; one synchronisation at the end.
+ * Self-consistent mode (whose field solve synchronises every refinement cycle anyway):
+ * the steps run one at a time and the host reads the device's 4-byte decision after
+ * each, so no reduction of the state is needed.  Writes the number of steps taken to
+ * *steps_done (the context's step counter and bank follow it).  EINVAL without
+ * coefficients or for dt <= 0; errors of itokmc_step. */
 int itokmc_step_until(itokmc_ctx* ctx, uint32_t nsteps, double dt, uint64_t stop_particles,
                       uint32_t* steps_done);
 

@@ -412,15 +412,40 @@ int itokmc_step(itokmc_ctx* ctx, uint32_t nsteps, double dt) {
   return ITOKMC_OK;
 }
 
+// Self-consistent form of the stop rule: the field solve already synchronises with the
+// host every refinement cycle, so the steps run one at a time and the host reads the
+// device's decision (4 bytes) after each; no step is enqueued past the one that stops.
+static int step_until_field(itokmc_ctx* ctx, uint32_t nsteps, double dt, uint64_t stop_particles,
+                            uint32_t* steps_done) {
+  int rc = check_hip(ctx, launch_stop_begin(ctx), "stop rule");
+  uint32_t done = 0;
+  uint32_t* halt = &ctx->host_ctr->halt;
+  while (!rc && done < nsteps) {
+    rc = itokmc_transport(ctx, dt);
+    if (!rc) rc = itokmc_react(ctx, dt);
+    if (!rc) rc = check_hip(ctx, launch_stop_step(ctx, stop_particles), "stop rule");
+    if (rc) break;
+    ++done;
+    hipError_t e = hipMemcpyAsync(halt, &ctx->ctr->halt, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->s);
+    rc = check_hip(ctx, e, "stop rule");
+    if (!rc && *halt) break;
+  }
+  hipError_t e = launch_stop_end(ctx);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->s);
+  const int rc2 = check_hip(ctx, e, "stop rule");
+  *steps_done = done;
+  return rc ? rc : rc2;
+}
+
 int itokmc_step_until(itokmc_ctx* ctx, uint32_t nsteps, double dt, uint64_t stop_particles,
                       uint32_t* steps_done) {
   if (!ctx || !steps_done) return ITOKMC_EINVAL;
-  if (ctx->d.field_mode != ITOKMC_FIELD_UNIFORM)
-    return set_error(ctx, ITOKMC_EINVAL, "the device-side stop rule needs the prescribed-field mode");
   if (!ctx->have_coeffs) return set_error(ctx, ITOKMC_EINVAL, "coefficients not set");
   if (!(dt > 0.0)) return set_error(ctx, ITOKMC_EINVAL, "dt must be positive");
   *steps_done = 0;
   if (nsteps == 0) return ITOKMC_OK;
+  if (ctx->d.field_mode == ITOKMC_FIELD_POISSON) return step_until_field(ctx, nsteps, dt, stop_particles, steps_done);
   const uint32_t step0 = ctx->step;
   const int cur0 = ctx->cur;
   int rc = check_hip(ctx, launch_stop_begin(ctx), "stop rule");

@@ -337,8 +337,9 @@ class Sim:
         return dts[:int(n)]
 
     def step_until(self, n, stop_particles=0, dt=None):
-        """Up to n steps under the device-side stop rule (prescribed-field mode); returns
-        the number of steps taken (synchronises once)."""
+        """Up to n steps under the device-side stop rule; returns the number of steps
+        taken (prescribed-field mode: one synchronisation; self-consistent mode: the
+        host reads the rule's decision after each step)."""
         done = ctypes.c_uint32(0)
         self._check(lib().itokmc_step_until(self.h, n, dt or self.cfg["dt"], int(stop_particles),
                                              ctypes.byref(done)))

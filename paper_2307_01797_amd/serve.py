@@ -37,25 +37,13 @@ CELL_BYTES = 36            # ensemble per-cell arrays
 
 
 def _stop_rule_run(sim, cfg, cancelled=None):
-    """Step a single context under the stop rule; returns steps run, or None if
-    cancelled() became true first.  In the prescribed-field mode the rule runs on the
-    device (one call, one synchronisation); the self-consistent mode checks it on the
-    host before each step."""
-    stop = int(cfg.get("stop_particles", 0))
-    if cfg.get("field") != "poisson":
-        if cancelled is not None and cancelled():
-            return None
-        return sim.step_until(int(cfg["steps"]), stop)
-    steps = 0
-    for _ in range(int(cfg["steps"])):
-        if cancelled is not None and cancelled():
-            return None
-        live = sim.diagnostics()["n_particles"] if stop else 0
-        sim.step(1)
-        steps += 1
-        if stop and live >= stop:
-            break
-    return steps
+    """Step a single context under the stop rule, evaluated on the device
+    (itokmc_step_until: one call; in the self-consistent mode the host reads the
+    device's decision after each step, whose field solve synchronises anyway); returns
+    steps run, or None if cancelled() was already true."""
+    if cancelled is not None and cancelled():
+        return None
+    return sim.step_until(int(cfg["steps"]), int(cfg.get("stop_particles", 0)))
 
 
 def run_plain_one(cfg, device="cuda:0", stream=None, keep_particles=False, cancelled=None):

@@ -287,3 +287,37 @@ def test_device_stop_rule_matches_host_rule(itk):
         dev.step(2)
         _assert_same(_plain_state(dev), _plain_state(host))
     assert parities == {0, 1}
+
+
+def test_device_stop_rule_self_consistent(itk):
+    """The stop rule in the self-consistent mode (steps one at a time, the host reading
+    the device's decision after each) takes the same steps and leaves the same state as
+    the rule checked on the host with a full reduction before each step."""
+    from test_gpu_parity import _streamer_small
+    base = _streamer_small(precision="fp32", gmg_rtol=1e-10)
+    probe = itk.Sim(base, precision="fp32")
+    probe.seed()
+    n0 = probe.diagnostics()["n_particles"]
+    probe.step(3)
+    n3 = probe.diagnostics()["n_particles"]
+    for stop, steps in ((0, 4), (1, 4), ((n0 + n3) // 2 if n3 > n0 else n0 + 1, 8)):
+        cfg = dict(base, steps=steps, stop_particles=stop)
+        host = itk.Sim(cfg, precision="fp32")
+        host.seed()
+        taken = 0
+        for _ in range(steps):
+            live = host.diagnostics()["n_particles"]
+            host.step(1)
+            taken += 1
+            if stop and live >= stop:
+                break
+        dev = itk.Sim(cfg, precision="fp32")
+        dev.seed()
+        n = dev.step_until(steps, stop)
+        assert n == taken == dev.diagnostics()["step"], (stop, n, taken)
+        for k in TALLIES:
+            assert dev.diagnostics()[k] == host.diagnostics()[k], (stop, k)
+        a, b = dev.particles(), host.particles()
+        for u, v in zip(by_id(a[3], *a[:3]), by_id(b[3], *b[:3])):
+            assert np.array_equal(u, v)
+        assert np.array_equal(dev.field(), host.field())
