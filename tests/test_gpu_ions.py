@@ -143,3 +143,50 @@ def test_ensemble_rejects_mobile_ions(itk):
     with pytest.raises(itk.ItokmcError) as e:
         ens.admit(cfg)
     assert e.value.code == itk.EINVAL and "mobile ions" in str(e.value)
+
+
+def test_ragged_grid_ion_cloud(itk, orc):
+    """Mobile ions on a 37 x 29 x 23 grid (no dimension a multiple of any tile), ions on
+    every face of the box, FP32: counts and tallies exact."""
+    cfg = workloads.preset("avalanche_32", grid=(37, 29, 23), E=(-3e6, 4e6, 1.2e7), precision="fp32",
+                           coeffs=FAST_IONS)
+    rng = np.random.default_rng(17)
+    n = 37 * 29 * 23
+    p = rng.integers(0, 400, n)
+    m = rng.integers(0, 40, n)
+    g = itk.Sim(cfg, precision="fp32", max_particles=1000)
+    g.set_particles(np.zeros(0), np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.uint64))
+    g.set_counts("plus", p.astype(np.uint32))
+    g.set_counts("minus", m.astype(np.uint32))
+    o = orc.Sim(cfg)
+    o.set_counts("plus", p)
+    o.set_counts("minus", m)
+    for _ in range(3):
+        g.step(1, dt=5e-11)
+        o.step(5e-11)
+        for which in ("plus", "minus"):
+            assert np.array_equal(g.counts(which).astype(np.int64), o.counts(which)), which
+        _tallies(g, o)
+
+
+def test_next_step_features_together_fp64(itk, orc):
+    """The 16^3 self-consistent streamer with the TSC shape, recombination, mobile ions
+    and the dynamic time step at once, FP64, free-running: every integer exact, the step
+    sizes within 1e-9, positions within 1e-9 cells."""
+    from test_gpu_parity import _recomb
+    coeffs = dict(_recomb(1e7), **FAST_IONS)
+    cfg = _streamer_small(shape="tsc", coeffs=coeffs)
+    rule = {"dt_max": 1e-12, "c_drift": 0.2, "c_ion": 0.05}
+    g = itk.Sim(cfg, precision="fp64")
+    g.seed()
+    o = orc.Sim(cfg)
+    o.seed_neutral(cfg["seed_peak"], cfg["seed_centre"], cfg["seed_sigma"])
+    for n in (1, 2, 2):
+        dg = g.step_adaptive(rule, n)
+        do = o.step_adaptive(rule, n)
+        assert np.allclose(dg, do, rtol=1e-9, atol=0)
+        assert _compare(g, o, cfg, 1e-9) == 0
+        _compare_tallies(g, o)
+        _tallies(g, o)
+    d = g.diagnostics()
+    assert d["fires"][3] > 0 and d["step"] == 5
