@@ -147,6 +147,62 @@ __device__ __forceinline__ uint32_t wave_prefix_dpp(uint32_t x) {
   return x;
 }
 
+// Lane moves across the whole wavefront (DPP wave_shr:1 and wave_shl:1): lane i receives
+// lane i - 1 (resp. i + 1); the lane with no source receives `fill`.
+__device__ __forceinline__ uint32_t dpp_from_prev(uint32_t x, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t dpp_from_next(uint32_t x, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, 0x130, 0xF, 0xF, false);
+}
+
+// One step of a segmented inclusive scan with DPP (control ctrl, rows row_mask): the
+// (head flag, value) pair of the source lane combined with the lane's own, keeping the
+// lane's value after a head inside its range and applying op otherwise.  The pair
+// operator is associative, so the shifts of wave_prefix_dpp (row_shr 1, 2, 4, 8, then
+// row_bcast 15 and 31) give the scan of each segment; lanes without a source see the
+// identity and no head.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x, uint64_t fill) {
+  const uint32_t lo = dpp_u32<CTRL, ROWS>((uint32_t)x, (uint32_t)fill);
+  const uint32_t hi = dpp_u32<CTRL, ROWS>((uint32_t)(x >> 32), (uint32_t)(fill >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL, int ROWS, typename U>
+__device__ __forceinline__ U dpp_move(U x, U fill) {
+  if constexpr (sizeof(U) == 8) return (U)dpp_u64<CTRL, ROWS>((uint64_t)x, (uint64_t)fill);
+  else return (U)dpp_u32<CTRL, ROWS>((uint32_t)x, (uint32_t)fill);
+}
+
+// Segmented inclusive scans over the wavefront.  `head` (0/1) marks the first lane of
+// a segment; lane 0 always starts one.  Returns the scanned values in place and, in
+// `seen`, whether a head lies in lanes 1..i (0: the lane continues lane 0's segment).
+template <int CTRL, int ROWS, typename U, int N, typename Op>
+__device__ __forceinline__ void seg_step(U (&v)[N], uint32_t& f, const U (&id)[N], Op op) {
+  const uint32_t fs = dpp_u32<CTRL, ROWS>(f, 0u);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const U vs = dpp_move<CTRL, ROWS, U>(v[k], id[k]);
+    v[k] = f ? v[k] : op(k, vs, v[k]);
+  }
+  f |= fs;
+}
+template <typename U, int N, typename Op>
+__device__ __forceinline__ uint32_t seg_scan(U (&v)[N], uint32_t head, const U (&id)[N], Op op) {
+  uint32_t f = lane_id() == 0 ? 0u : head;
+  seg_step<0x111, 0xF>(v, f, id, op);   // row_shr:1
+  seg_step<0x112, 0xF>(v, f, id, op);   // row_shr:2
+  seg_step<0x114, 0xF>(v, f, id, op);   // row_shr:4
+  seg_step<0x118, 0xF>(v, f, id, op);   // row_shr:8
+  seg_step<0x142, 0xA>(v, f, id, op);   // row_bcast:15
+  seg_step<0x143, 0xC>(v, f, id, op);   // row_bcast:31
+  return f;
+}
+
 // Binning of one particle per lane into acc[key] = (count << 32) | weight (inactive
 // lanes use kInvalidCell): one 64-bit atomic per run of equal consecutive keys, as
 // run_add, but only the count is returned: each active lane's rank in its cell (0 for

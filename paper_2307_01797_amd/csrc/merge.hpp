@@ -79,10 +79,6 @@ __device__ __forceinline__ uint64_t packed_key(float k, uint32_t r) {
 }
 __device__ __forceinline__ uint64_t packed_key(double, uint32_t) { return 0; }
 
-__device__ __forceinline__ uint32_t shfl_up_u(uint32_t v, int d) { return __shfl_up(v, d, 64); }
-__device__ __forceinline__ unsigned long long shfl_up_u(unsigned long long v, int d) {
-  return shfl_up64(v, d);
-}
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = lane_id();
@@ -215,12 +211,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     // new leaf index and region of each old leaf (a splitting leaf gets a spare slot)
     const uint32_t widx = lane < nl ? (chosen ? 2u : 1u) : 0u;
     const uint32_t wreg = n_i + (chosen ? 1u : 0u);
-    uint32_t xi = widx, xr = wreg;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t yi = __shfl_up(xi, d, 64), yr = __shfl_up(xr, d, 64);
-      if (lane >= d) { xi += yi; xr += yr; }
-    }
+    const uint32_t xi = wave_prefix_dpp(widx), xr = wave_prefix_dpp(wreg);
     const uint32_t newidx = xi - widx, R = xr - wreg;
     const int nl_new = (int)__shfl(xi, 63, 64);
     const uint32_t new_extent = __shfl(xr, 63, 64);
@@ -249,22 +240,15 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       } else {
         for (int a = 0; a < 3; ++a) { mn[a] = Bits<T>::lo_init; mx[a] = 0; }
       }
-      const uint32_t prev = __shfl_up(key, 1, 64);
-      const uint64_t heads = __ballot(lane == 0 || prev != key);
-      const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-      const int seg_start = 63 - __clzll(heads & upto);
-      for (int d = 1; d < 64; d <<= 1) {
-        if (__ballot(lane - d >= seg_start) == 0ull) break;
+      // segmented min and max of each axis over the chunk (DPP moves, no LDS)
+      const uint32_t prev = dpp_from_prev(key, ~key);
+      U ext[6] = {mn[0], mn[1], mn[2], mx[0], mx[1], mx[2]};
+      const U eid[6] = {Bits<T>::lo_init, Bits<T>::lo_init, Bits<T>::lo_init, 0, 0, 0};
+      seg_scan(ext, prev != key ? 1u : 0u, eid,
+               [](int k, U a, U b) { return k < 3 ? (a < b ? a : b) : (a > b ? a : b); });
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const U y = shfl_up_u(mn[a], d), z = shfl_up_u(mx[a], d);
-          if (lane - d >= seg_start) {
-            mn[a] = y < mn[a] ? y : mn[a];
-            mx[a] = z > mx[a] ? z : mx[a];
-          }
-        }
-      }
-      const uint32_t next = __shfl_down(key, 1, 64);
+      for (int a = 0; a < 3; ++a) { mn[a] = ext[a]; mx[a] = ext[3 + a]; }
+      const uint32_t next = dpp_from_next(key, ~key);
       if (part && (lane == 63 || next != key)) {
         for (int a = 0; a < 3; ++a) {
           atomicMin(&lo[3 * L + a], mn[a]);
@@ -357,20 +341,16 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       const bool valid = t8 != kNone;
       const uint32_t vkey = valid ? (uint32_t)t8 : 0xFFFFFFFFu;
       const uint64_t w = valid ? (uint64_t)sw[I(ncb)[q]] : 0ull;
-      const uint32_t prev = __shfl_up(vkey, 1, 64);
-      const bool head = lane == 0 || prev != vkey;
-      const uint64_t heads = __ballot(head);
-      const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-      const int seg_start = 63 - __clzll(heads & upto);
-      uint64_t x = w;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t y = shfl_up64(x, d);
-        if (lane - d >= seg_start) x += y;
-      }
-      if (seg_start == 0 && vkey == carry_key) x += carry;
+      // segmented prefix sums of the weights over the chunk (DPP moves, no LDS)
+      const uint32_t prev = dpp_from_prev(vkey, ~vkey);
+      uint64_t xs[1] = {w};
+      const uint64_t zid[1] = {0ull};
+      const uint32_t seen = seg_scan(xs, prev != vkey ? 1u : 0u, zid,
+                                     [](int, uint64_t a, uint64_t b) { return a + b; });
+      uint64_t x = xs[0];
+      if (!seen && vkey == carry_key) x += carry;
       const bool hit = valid && 2ull * x > (uint64_t)LW(cb)[vkey & 63u];
-      const bool up_hit = __shfl_up(hit ? 1 : 0, 1, 64) != 0;
+      const bool up_hit = dpp_from_prev(hit ? 1u : 0u, 0u) != 0u;
       const bool prev_same = lane > 0 ? prev == vkey : vkey == carry_key;
       const bool prev_hit = lane > 0 ? up_hit : carry_hit;
       if (hit && !(prev_same && prev_hit)) {
@@ -404,12 +384,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     }
     // store entries for the right pieces of split superparticle medians
     const uint32_t sx = super ? 1u : 0u;
-    uint32_t sp = sx;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(sp, d, 64);
-      if (lane >= d) sp += y;
-    }
+    const uint32_t sp = wave_prefix_dpp(sx);
     const uint32_t np = nstore + sp - sx;
     nstore += __shfl(sp, 63, 64);
     if (lane < nl && chosen) {
