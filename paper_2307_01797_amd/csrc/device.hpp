@@ -105,6 +105,15 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   return (uint64_t)__shfl((unsigned long long)v, src, 64);
 }
 
+// Lane moves across the whole wavefront (DPP wave_shr:1 and wave_shl:1): lane i receives
+// lane i - 1 (resp. i + 1); the lane with no source receives `fill`.
+__device__ __forceinline__ uint32_t dpp_from_prev(uint32_t x, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t dpp_from_next(uint32_t x, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, 0x130, 0xF, 0xF, false);
+}
+
 // Run-aggregated atomic add.  Lanes whose keys form a run of equal consecutive values
 // (inactive lanes use kInvalidCell) add their values to acc[key] with a single atomic
 // per run; each active lane receives the value acc[key] had before its own
@@ -114,7 +123,7 @@ __device__ __forceinline__ uint64_t run_add(unsigned long long* acc, uint32_t ke
                                             uint64_t val) {
   const int lane = lane_id();
   const bool active = key != kInvalidCell;
-  const uint32_t prev = __shfl_up(key, 1, 64);
+  const uint32_t prev = dpp_from_prev(key, ~key);
   const bool head = (lane == 0) || (prev != key);
   const uint64_t heads = __ballot(head);
   const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
@@ -145,15 +154,6 @@ __device__ __forceinline__ uint32_t wave_prefix_dpp(uint32_t x) {
   x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
   x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
   return x;
-}
-
-// Lane moves across the whole wavefront (DPP wave_shr:1 and wave_shl:1): lane i receives
-// lane i - 1 (resp. i + 1); the lane with no source receives `fill`.
-__device__ __forceinline__ uint32_t dpp_from_prev(uint32_t x, uint32_t fill) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, 0x138, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t dpp_from_next(uint32_t x, uint32_t fill) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)x, 0x130, 0xF, 0xF, false);
 }
 
 // One step of a segmented inclusive scan with DPP (control ctrl, rows row_mask): the
@@ -203,6 +203,30 @@ __device__ __forceinline__ uint32_t seg_scan(U (&v)[N], uint32_t head, const U (
   return f;
 }
 
+// The value of one lane (a wave-uniform lane index), read by the scalar unit.
+__device__ __forceinline__ uint32_t lane_u32(uint32_t x, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int lane) {
+  return ((uint64_t)lane_u32((uint32_t)(x >> 32), lane) << 32) | lane_u32((uint32_t)x, lane);
+}
+
+// Wavefront sum and maximum with DPP moves (every lane active); the result is uniform.
+__device__ __forceinline__ uint64_t wave_sum64_dpp(uint64_t v) {
+  uint64_t x[1] = {v};
+  const uint64_t id[1] = {0ull};
+  (void)seg_scan(x, 0u, id, [](int, uint64_t a, uint64_t b) { return a + b; });
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x[0], 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x[0] >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t wave_max_u32_dpp(uint32_t v) {
+  uint32_t x[1] = {v};
+  const uint32_t id[1] = {0u};
+  (void)seg_scan(x, 0u, id, [](int, uint32_t a, uint32_t b) { return a > b ? a : b; });
+  return (uint32_t)__builtin_amdgcn_readlane((int)x[0], 63);
+}
+
 // Binning of one particle per lane into acc[key] = (count << 32) | weight (inactive
 // lanes use kInvalidCell): one 64-bit atomic per run of equal consecutive keys, as
 // run_add, but only the count is returned: each active lane's rank in its cell (0 for
@@ -212,7 +236,7 @@ __device__ __forceinline__ uint32_t seg_scan(U (&v)[N], uint32_t head, const U (
 __device__ __forceinline__ uint32_t bin_add(unsigned long long* acc, uint32_t key, uint32_t w) {
   const int lane = lane_id();
   const bool active = key != kInvalidCell;
-  const uint32_t prev = __shfl_up(key, 1, 64);
+  const uint32_t prev = dpp_from_prev(key, ~key);
   const bool head = (lane == 0) || (prev != key);
   const uint64_t heads = __ballot(head);
   const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);

@@ -160,12 +160,8 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     }
     m += (uint32_t)__popcll(mask);
   }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint32_t o = __shfl_xor(wmax, d, 64);
-    wmax = o > wmax ? o : wmax;
-  }
-  Wtot = wave_sum64(Wtot);
+  wmax = wave_max_u32_dpp(wmax);
+  Wtot = wave_sum64_dpp(Wtot);
   const bool trigger = m > (uint32_t)n_ppc || (m < (uint32_t)n_ppc && wmax >= 2);
   if (!trigger || m == 0) return 0;
   if (m > (uint32_t)CAP) return 2;
@@ -201,7 +197,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     if (ncand > budget) {
       int rank = 0;
       for (int j = 0; j < nl; ++j) {
-        const uint32_t Wj = __shfl(Wi, j, 64);
+        const uint32_t Wj = lane_u32(Wi, j);
         if (((cmask >> j) & 1ull) && (Wj > Wi || (Wj == Wi && j < lane))) ++rank;
       }
       chosen = cand && rank < budget;
@@ -213,8 +209,8 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     const uint32_t wreg = n_i + (chosen ? 1u : 0u);
     const uint32_t xi = wave_prefix_dpp(widx), xr = wave_prefix_dpp(wreg);
     const uint32_t newidx = xi - widx, R = xr - wreg;
-    const int nl_new = (int)__shfl(xi, 63, 64);
-    const uint32_t new_extent = __shfl(xr, 63, 64);
+    const int nl_new = (int)lane_u32(xi, 63);
+    const uint32_t new_extent = lane_u32(xr, 63);
     if (lane < nl) {
       Rg[lane] = R;
       if (chosen) {
@@ -357,9 +353,9 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         medp[vkey] = q - Rg[vkey];
         medWl[vkey] = (uint32_t)(x - w);
       }
-      carry = shfl64(x, 63);
-      carry_key = __shfl(vkey, 63, 64);
-      carry_hit = __shfl(hit ? 1 : 0, 63, 64) != 0;
+      carry = lane_u64(x, 63);
+      carry_key = lane_u32(vkey, 63);
+      carry_hit = lane_u32(hit ? 1u : 0u, 63) != 0u;
     }
     wave_lds_sync();
     // (iv)-(v) children of every splitting leaf, one lane per leaf
@@ -386,7 +382,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     const uint32_t sx = super ? 1u : 0u;
     const uint32_t sp = wave_prefix_dpp(sx);
     const uint32_t np = nstore + sp - sx;
-    nstore += __shfl(sp, 63, 64);
+    nstore += lane_u32(sp, 63);
     if (lane < nl && chosen) {
       if (super) {
         const uint32_t wm = sw[pm];
@@ -442,7 +438,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   const int extra = nl - (int)nseg - (int)M;
   if (extra > 0) {
     if (lane == 0) extra_base = atomicAdd(&ctr->n[which], (uint32_t)extra);
-    extra_base = __shfl(extra_base, 0, 64);
+    extra_base = lane_u32(extra_base, 0);
   }
   if (lane < nl) {
     const uint32_t i = (uint32_t)lane;
