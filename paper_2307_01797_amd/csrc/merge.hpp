@@ -23,6 +23,8 @@
 // wave_lds_sync(), so the leaf stores of one cell stay in flight while the wavefront
 // gathers its next cell.
 #pragma once
+#include <type_traits>
+
 #include "device.hpp"
 #include "itk.hpp"
 
@@ -60,13 +62,21 @@ template <typename T, int CAP> struct MergePacked {
   static constexpr bool value = MergeContig<CAP>::value && sizeof(T) == 4;
 };
 
+// Index of a store entry in the two index buffers: one byte when the store has at most
+// 256 entries (the common staging), else two.
+template <int CAP, int NL> struct MergeIdx {
+  using type = std::conditional_t<(CAP + NL <= 256), uint8_t, uint16_t>;
+};
+
 // NL: leaf capacity (at least n_ppc): 32 for n_ppc <= 32, else kMaxMergePpc.
 template <typename T, int CAP, int NL = kMaxMergePpc>
 constexpr size_t merge_lds_bytes_c() {
   constexpr size_t S = (size_t)CAP + NL;
   constexpr size_t U = sizeof(typename Bits<T>::U);
-  return S * (8 + 3 * sizeof(T) + 4 + 2 * 2 + 3)  // store, two index buffers, three tag arrays
-         + (MergeContig<CAP>::value ? S * (sizeof(T) + 8) : 0)  // contiguous keys and ids
+  return S * (8 + 3 * sizeof(T) + 4 + 2 * sizeof(typename MergeIdx<CAP, NL>::type) + 3)
+                                                    // store, two index buffers, three tag arrays
+         + (MergeContig<CAP>::value ? S * 8 : 0)               // contiguous ids (packed: keys)
+         + (MergeContig<CAP>::value && !MergePacked<T, CAP>::value ? S * sizeof(T) : 0)  // keys
          + (MergePacked<T, CAP>::value ? S * 4 : 0)             // id ranks
          + NL * (6 * 4 + 3 * 4 + 6 * U + 1)        // leaf records, per-leaf scratch, extents, axis
          + 64;
@@ -112,7 +122,8 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   uint32_t* Rg = (uint32_t*)p; p += NL * 4;     // region of each old leaf in the new buffer
   uint32_t* medp = (uint32_t*)p; p += NL * 4;   // median position inside the ordered leaf
   uint32_t* medWl = (uint32_t*)p; p += NL * 4;  // weight ordered before the median
-  uint16_t* const IB = (uint16_t*)p; p += (size_t)2 * S * 2;
+  using Ix = typename MergeIdx<CAP, NL>::type;
+  Ix* const IB = (Ix*)p; p += (size_t)2 * S * sizeof(Ix);
   auto I = [IB](int k) { return IB + (size_t)k * S; };
   uint8_t* const tagB = (uint8_t*)p; p += (size_t)2 * S;   // leaf of each slot of I(k)
   auto tag = [tagB](int k) { return tagB + (size_t)k * S; };
@@ -122,7 +133,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   constexpr bool packed = MergePacked<T, CAP>::value;
   p = smem + ((size_t)(p - smem) + 15) / 16 * 16;  // stays an LDS address (LDS instructions)
   uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id (packed: key) of slot q
-  T* kkey = (T*)p; p += contig ? (size_t)S * sizeof(T) : 0;        // key of slot q
+  T* kkey = (T*)p; p += contig && !packed ? (size_t)S * sizeof(T) : 0;  // key of slot q
   uint32_t* idr = (uint32_t*)p; p += packed ? (size_t)S * 4 : 0;   // id rank of store entry
 
   // ---- gather: segment [s, e) then product slots [base, base + M) ----
@@ -152,7 +163,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         so(1)[pos] = x1;
         so(2)[pos] = x2;
         sw[pos] = w;
-        I(0)[pos] = (uint16_t)pos;
+        I(0)[pos] = (Ix)pos;
         tag(0)[pos] = 0;
       }
       wmax = w > wmax ? w : wmax;
@@ -285,7 +296,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       const uint16_t pq = I(cb)[q];
       if (!((chm >> L) & 1ull)) {
         const uint32_t ni = (uint32_t)L + (uint32_t)__popcll(chm & ((1ull << L) - 1ull));
-        I(ncb)[RL + (q - Ls)] = pq;
+        I(ncb)[RL + (q - Ls)] = (Ix)pq;
         tag(ncb)[RL + (q - Ls)] = (uint8_t)ni;
         continue;
       }
@@ -323,7 +334,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
           rank += (kr < kq || (kr == kq && sid[pr] < iq)) ? 1u : 0u;
         }
       }
-      I(ncb)[RL + rank] = pq;
+      I(ncb)[RL + rank] = (Ix)pq;
       otag[RL + rank] = L;
     }
     wave_lds_sync();
@@ -391,7 +402,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
         for (int a = 0; a < 3; ++a) so(a)[np] = so(a)[pm];
         sw[np] = wm - wl;
         sw[pm] = wl;
-        I(ncb)[R + n_i] = (uint16_t)np;
+        I(ncb)[R + n_i] = (Ix)np;
       }
       Lst(ncb)[newidx] = R; Lcn(ncb)[newidx] = lcnt; LW(ncb)[newidx] = WLn;
       Lst(ncb)[newidx + 1] = R + rst; Lcn(ncb)[newidx + 1] = rcnt; LW(ncb)[newidx + 1] = WRn;
