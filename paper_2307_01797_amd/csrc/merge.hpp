@@ -73,8 +73,10 @@ template <typename T, int CAP, int NL = kMaxMergePpc>
 constexpr size_t merge_lds_bytes_c() {
   constexpr size_t S = (size_t)CAP + NL;
   constexpr size_t U = sizeof(typename Bits<T>::U);
-  return S * (8 + 3 * sizeof(T) + 4 + 2 * sizeof(typename MergeIdx<CAP, NL>::type) + 3)
-                                                    // store, two index buffers, three tag arrays
+  return S * ((MergePacked<T, CAP>::value ? 0 : 8) + 3 * sizeof(T) + 4 +
+              2 * sizeof(typename MergeIdx<CAP, NL>::type) + 3)
+                            // store (ids in the contiguous array when packed), two index buffers,
+                            // three tag arrays
          + (MergeContig<CAP>::value ? S * 8 : 0)               // contiguous ids (packed: keys)
          + (MergeContig<CAP>::value && !MergePacked<T, CAP>::value ? S * sizeof(T) : 0)  // keys
          + (MergePacked<T, CAP>::value ? S * 4 : 0)             // id ranks
@@ -107,7 +109,11 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   char* p = smem;
-  uint64_t* sid = (uint64_t*)p; p += (size_t)S * 8;
+  constexpr bool contig = MergeContig<CAP>::value;
+  constexpr bool packed = MergePacked<T, CAP>::value;
+  // piece ids: needed by the packed path only until the id ranks are known, so there
+  // they live in the contiguous key array, which is filled later
+  uint64_t* sid_own = (uint64_t*)p; p += packed ? 0 : (size_t)S * 8;
   U* lo = (U*)p; p += (size_t)NL * 3 * sizeof(U);
   U* hi = (U*)p; p += (size_t)NL * 3 * sizeof(U);
   // Arrays selected by a run-time index (axis, buffer) are addressed from one base, so
@@ -129,10 +135,9 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   auto tag = [tagB](int k) { return tagB + (size_t)k * S; };
   uint8_t* otag = (uint8_t*)p; p += (size_t)S;   // splitting leaf owning an ordered slot
   uint8_t* axis = (uint8_t*)p; p += NL;
-  constexpr bool contig = MergeContig<CAP>::value;
-  constexpr bool packed = MergePacked<T, CAP>::value;
   p = smem + ((size_t)(p - smem) + 15) / 16 * 16;  // stays an LDS address (LDS instructions)
   uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id (packed: key) of slot q
+  uint64_t* const sid = packed ? kid : sid_own;
   T* kkey = (T*)p; p += contig && !packed ? (size_t)S * sizeof(T) : 0;  // key of slot q
   uint32_t* idr = (uint32_t*)p; p += packed ? (size_t)S * 4 : 0;   // id rank of store entry
 
@@ -302,7 +307,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       }
       const int ax = axis[L];
       const T kq = so(ax)[pq];
-      const uint64_t iq = sid[pq];
+      const uint64_t iq = packed ? 0ull : sid[pq];
       uint32_t rank = 0;
       if (packed) {
         const uint64_t cq = packed_key(kq, idr[pq]);
@@ -397,8 +402,8 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     if (lane < nl && chosen) {
       if (super) {
         const uint32_t wm = sw[pm];
-        sid[np] = sid[pm];
         if (packed) idr[np] = idr[pm];
+        else sid[np] = sid[pm];
         for (int a = 0; a < 3; ++a) so(a)[np] = so(a)[pm];
         sw[np] = wm - wl;
         sw[pm] = wl;
