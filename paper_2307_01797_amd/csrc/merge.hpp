@@ -79,8 +79,10 @@ constexpr size_t merge_lds_bytes_c() {
                             // three tag arrays
          + (MergeContig<CAP>::value ? S * 8 : 0)               // contiguous ids (packed: keys)
          + (MergeContig<CAP>::value && !MergePacked<T, CAP>::value ? S * sizeof(T) : 0)  // keys
-         + (MergePacked<T, CAP>::value ? S * 4 : 0)             // id ranks
-         + NL * (6 * 4 + 3 * 4 + 6 * U + 1)        // leaf records, per-leaf scratch, extents, axis
+         + (MergePacked<T, CAP>::value ? S * sizeof(typename MergeIdx<CAP, NL>::type) : 0)  // id ranks
+         + NL * (2 * 4 + 4 + 6 * U + 1 +                           // weights, extents, axis
+                 6 * sizeof(typename MergeIdx<CAP, NL>::type))      // starts, counts, regions,
+                                                                    // median positions
          + 64;
 }
 inline int merge_leaves(int n_ppc) { return n_ppc <= 32 ? 32 : kMaxMergePpc; }
@@ -121,14 +123,16 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   T* const soB = (T*)p; p += (size_t)3 * S * sizeof(T);
   auto so = [soB](int a) { return soB + (size_t)a * S; };
   uint32_t* sw = (uint32_t*)p; p += (size_t)S * 4;
-  uint32_t* const LB = (uint32_t*)p; p += (size_t)6 * NL * 4;   // per buffer: start, count, weight
-  auto Lst = [LB](int k) { return LB + (size_t)k * 3 * NL; };
-  auto Lcn = [LB](int k) { return LB + (size_t)k * 3 * NL + NL; };
-  auto LW = [LB](int k) { return LB + (size_t)k * 3 * NL + 2 * NL; };
-  uint32_t* Rg = (uint32_t*)p; p += NL * 4;     // region of each old leaf in the new buffer
-  uint32_t* medp = (uint32_t*)p; p += NL * 4;   // median position inside the ordered leaf
+  // leaf records per buffer: weight (u32), start and count (store indices)
+  uint32_t* const LWB = (uint32_t*)p; p += (size_t)2 * NL * 4;
+  auto LW = [LWB](int k) { return LWB + (size_t)k * NL; };
   uint32_t* medWl = (uint32_t*)p; p += NL * 4;  // weight ordered before the median
   using Ix = typename MergeIdx<CAP, NL>::type;
+  Ix* const LSB = (Ix*)p; p += (size_t)4 * NL * sizeof(Ix);
+  auto Lst = [LSB](int k) { return LSB + (size_t)k * 2 * NL; };
+  auto Lcn = [LSB](int k) { return LSB + (size_t)k * 2 * NL + NL; };
+  Ix* Rg = (Ix*)p; p += NL * sizeof(Ix);     // region of each old leaf in the new buffer
+  Ix* medp = (Ix*)p; p += NL * sizeof(Ix);   // median position inside the ordered leaf
   Ix* const IB = (Ix*)p; p += (size_t)2 * S * sizeof(Ix);
   auto I = [IB](int k) { return IB + (size_t)k * S; };
   uint8_t* const tagB = (uint8_t*)p; p += (size_t)2 * S;   // leaf of each slot of I(k)
@@ -139,7 +143,7 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
   uint64_t* kid = (uint64_t*)p; p += contig ? (size_t)S * 8 : 0;   // id (packed: key) of slot q
   uint64_t* const sid = packed ? kid : sid_own;
   T* kkey = (T*)p; p += contig && !packed ? (size_t)S * sizeof(T) : 0;  // key of slot q
-  uint32_t* idr = (uint32_t*)p; p += packed ? (size_t)S * 4 : 0;   // id rank of store entry
+  Ix* idr = (Ix*)p; p += packed ? (size_t)S * sizeof(Ix) : 0;   // id rank of store entry
 
   // ---- gather: segment [s, e) then product slots [base, base + M) ----
   uint32_t m = 0, wmax = 0;
