@@ -220,6 +220,30 @@ def cpu_baseline_ensemble(cfgs, budget_s):
 BYTES_EXPLICIT_STEP = 48 + 60   # push with binning + scatter, per particle-step
 
 
+def step_forms(ens, best, rounds=2, per=3):
+    """Mean step time of the ensemble step as its kernel sequence and as the persistent
+    fused kernel at each register budget (1, 2, 4 workgroups per CU), interleaved over
+    rounds on the warm-up ensemble; the autotuned shapes are restored afterwards."""
+    import torch
+    forms = [0, 1, 2, 4]
+    tot = dict.fromkeys(forms, 0.0)
+    for k in forms:                    # capture each form's graphs outside the timing
+        ens.set_tuning(fused_per_cu=k)
+        ens.step(1)
+    for _ in range(rounds):
+        for k in forms:
+            ens.set_tuning(fused_per_cu=k)
+            ens.step(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ens.step(per)
+            ens.poll()
+            tot[k] += time.perf_counter() - t0
+    ens.set_tuning(**best)
+    names = {0: "sequence", 1: "fused_1", 2: "fused_2", 4: "fused_4"}
+    return {names[k]: round(1e3 * tot[k] / (rounds * per), 4) for k in forms}
+
+
 def bench_ensemble(args):
     """Batched form: every realization in one ensemble, stepped together to the end,
     against the plain form (each realization alone in a single context)."""
@@ -233,6 +257,7 @@ def bench_ensemble(args):
         ens.admit(c, tag=i)
     ens.step(max(1, args.warmup))
     tune, tune_ms = ens.autotune(rounds=2)
+    forms_ms = step_forms(ens, tune)
     ens.poll()
     for s in list(ens.ncell):
         ens.release(s)
@@ -253,7 +278,7 @@ def bench_ensemble(args):
                    "steps_max": 500, "stop_particles": 1_000_000,
                    "capped": sum(1 for r in rb["results"] if r["state"] != 2),
                    "particle_steps": rb["particle_steps"], "seconds": rb["seconds"],
-                   "tuning": tune, "autotune_step_ms": tune_ms,
+                   "tuning": tune, "autotune_step_ms": tune_ms, "step_forms_ms": forms_ms,
                    "arena_gb": ens.arena_bytes / 1e9},
         "step_bandwidth": {"bytes_per_particle_step": BYTES_EXPLICIT_STEP,
                            "achieved_gbs": BYTES_EXPLICIT_STEP * value / 1e9,

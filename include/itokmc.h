@@ -78,9 +78,12 @@ enum {
 enum {
   ITOKMC_OVF_PARTICLES = 1, /* a particle bank was full: particles that did not fit
                                were dropped                                         */
-  ITOKMC_OVF_MERGE = 2      /* a cell held more particles than the largest merge
+  ITOKMC_OVF_MERGE = 2,     /* a cell held more particles than the largest merge
                                staging (1536 in FP32, 1024 in FP64): it was left
                                unmerged (merge_skipped counts such cells)            */
+  ITOKMC_OVF_BARRIER = 4    /* ensemble, fused step: a device-wide barrier gave up
+                               waiting (its grid was not resident at once); that step
+                               did not complete and the ensemble's state is not valid */
 };
 
 typedef struct itokmc_ctx itokmc_ctx;
@@ -411,9 +414,17 @@ typedef struct {
 /* Launch shapes of the ensemble step (results do not depend on them): threads per
  * block of the particle kernels (64..1024, multiple of 64) and their blocks per
  * compute unit (1..64), threads per block of the KMC kernel, coupling wavefronts per
- * compute unit (1..256), HIP graph replay (default on). */
+ * compute unit (1..256), HIP graph replay (default on), and fused_per_cu: 0 runs the
+ * step as its sequence of kernels; k = 1, 2 or 4 runs it as one persistent fused
+ * kernel (push, counting sort, scatter, KMC, coupling and end of step separated by
+ * device-wide barriers with bounded waits) of k 256-thread workgroups per compute unit,
+ * compiled for the register budget that keeps all of them resident at once (set_tuning
+ * returns EINVAL if the device cannot).  A barrier gives up after 4 s (the environment
+ * variable ITOKMC_FUSED_WAIT_US, read at ensemble creation, sets another limit in
+ * microseconds); the step then ends early, ITOKMC_OVF_BARRIER is raised and the next
+ * poll returns EHIP. */
 typedef struct {
-  int32_t push_block, push_blocks_per_cu, kmc_block, couple_per_cu, use_graph, pad0;
+  int32_t push_block, push_blocks_per_cu, kmc_block, couple_per_cu, use_graph, fused_per_cu;
 } itokmc_ens_tuning;
 
 size_t itokmc_ensemble_arena_bytes(const itokmc_ens_desc* desc);

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -188,16 +189,17 @@ __global__ void __launch_bounds__(256) e_seed_gaussian(Bank b, Counters* ctr, in
 // contiguous chunk of the bank (whose particles mostly share a realization), and each
 // thread keeps its realization's tallies in registers, flushing them when it moves to
 // another realization and, wave-aggregated, at the end.
+// bid, nblk: this workgroup's index and the number of workgroups taking part.
 template <typename T>
-__global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
-                                              unsigned long long* cellacc, uint32_t* tiles,
-                                              const SlotConst* sc,
-                                              const int32_t* blk_slot, const uint32_t* blk_local,
-                                              const uint32_t* map, unsigned long long* st,
-                                              uint32_t ms, uint32_t cap) {
+__device__ __forceinline__ void push_phase(Bank a, Counters* ctr, int which,
+                                           unsigned long long* cellacc, uint32_t* tiles,
+                                           const SlotConst* sc, const int32_t* blk_slot,
+                                           const uint32_t* blk_local, const uint32_t* map,
+                                           unsigned long long* st, uint32_t ms, uint32_t cap,
+                                           uint32_t bid, uint32_t nblk) {
   const uint32_t n = min(ctr->n[which], cap);
-  const uint32_t per = ((n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
-  const uint32_t b0 = blockIdx.x * per, b1 = min(n, b0 + per);
+  const uint32_t per = ((n + nblk - 1) / nblk + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const uint32_t b0 = bid * per, b1 = min(n, b0 + per);
   uint32_t cur = kInvalidCell;
   uint64_t live = 0, left = 0, outw = 0;
   for (uint32_t base = b0; base < b1; base += blockDim.x) {
@@ -269,6 +271,17 @@ __global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
   if (run_total(cur, outw, &tot) && tot) atomicAdd(&st[S_OUTW * ms + cur], (unsigned long long)tot);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(1024) e_push(Bank a, Counters* ctr, int which,
+                                              unsigned long long* cellacc, uint32_t* tiles,
+                                              const SlotConst* sc,
+                                              const int32_t* blk_slot, const uint32_t* blk_local,
+                                              const uint32_t* map, unsigned long long* st,
+                                              uint32_t ms, uint32_t cap) {
+  push_phase<T>(a, ctr, which, cellacc, tiles, sc, blk_slot, blk_local, map, st, ms, cap,
+                blockIdx.x, gridDim.x);
+}
+
 // Per-slot tallies of one thread, flushed to the slot's counters when the thread moves
 // to another slot and, wave-aggregated, at the end.
 struct SlotTally {
@@ -302,17 +315,17 @@ struct SlotTally {
 // workgroup-aggregated appends.
 constexpr int kEnsKmcPer = 4;
 
+// sh: 18 words of LDS (block_append).
 template <bool kFast>
-__global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
+__device__ __forceinline__ void kmc_phase(
     Counters* ctr, const uint32_t* occ, unsigned long long* cellacc, uint32_t* nplus,
     uint32_t* nminus, int32_t* dN, uint32_t* work, uint32_t* cbase, uint32_t* heavy,
     const SlotConst* sc, const int32_t* blk_slot, const uint32_t* blk_local,
-    unsigned long long* st, uint32_t ms, int dest) {
-  __shared__ uint32_t sh[18];
+    unsigned long long* st, uint32_t ms, int dest, uint32_t* sh, uint32_t bid, uint32_t nblk) {
   const uint32_t n = kFast ? ctr->n_occ : ctr->n_heavy;
   const uint32_t span = blockDim.x * kEnsKmcPer;
   SlotTally tally;
-  for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+  for (uint32_t base = bid * span; base < n; base += nblk * span) {
     uint32_t js[kEnsKmcPer], Ms[kEnsKmcPer], fl[kEnsKmcPer];  // fl: 1 queue, 2 defer
     uint32_t nq = 0, nd = 0, nm = 0;
 #pragma unroll
@@ -394,16 +407,29 @@ __global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
   tally.flush_wave(st, ms);
 }
 
+template <bool kFast>
+__global__ void __launch_bounds__(kFast ? 256 : 64) e_kmc(
+    Counters* ctr, const uint32_t* occ, unsigned long long* cellacc, uint32_t* nplus,
+    uint32_t* nminus, int32_t* dN, uint32_t* work, uint32_t* cbase, uint32_t* heavy,
+    const SlotConst* sc, const int32_t* blk_slot, const uint32_t* blk_local,
+    unsigned long long* st, uint32_t ms, int dest) {
+  __shared__ uint32_t sh[18];
+  kmc_phase<kFast>(ctr, occ, cellacc, nplus, nminus, dN, work, cbase, heavy, sc, blk_slot,
+                   blk_local, st, ms, dest, sh, blockIdx.x, gridDim.x);
+}
+
 // Coupling of eq. w, one wavefront per queued cell (no merge in the ensemble).
+// wid, nwaves: this wavefront's index and the number of wavefronts taking part.
 template <typename T>
-__global__ void __launch_bounds__(64) e_couple(Bank b, Counters* ctr, const uint32_t* work,
-                                              const uint32_t* occ, const uint32_t* start,
-                                              const int32_t* dN, const uint32_t* cbase,
-                                              const SlotConst* sc, const int32_t* blk_slot,
-                                              const uint32_t* blk_local, uint32_t cap) {
+__device__ __forceinline__ void couple_phase(Bank b, Counters* ctr, const uint32_t* work,
+                                             const uint32_t* occ, const uint32_t* start,
+                                             const int32_t* dN, const uint32_t* cbase,
+                                             const SlotConst* sc, const int32_t* blk_slot,
+                                             const uint32_t* blk_local, uint32_t cap, uint32_t wid,
+                                             uint32_t nwaves) {
   const uint32_t nwork = ctr->n_work, n_occ = ctr->n_occ, sorted = ctr->sorted;
   const int lane = lane_id();
-  for (uint32_t t = blockIdx.x; t < nwork; t += gridDim.x) {
+  for (uint32_t t = wid; t < nwork; t += nwaves) {
     const uint32_t j = work[t];
     const uint32_t g = occ[j];
     const int32_t d = dN[j];
@@ -427,9 +453,21 @@ __global__ void __launch_bounds__(64) e_couple(Bank b, Counters* ctr, const uint
   }
 }
 
-// Per-slot end of step: advance the step counter and apply the stop rule.
-__global__ void e_finish(SlotConst* sc, unsigned long long* st, uint32_t* stat2, uint32_t ms) {
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ms; s += gridDim.x * blockDim.x) {
+template <typename T>
+__global__ void __launch_bounds__(64) e_couple(Bank b, Counters* ctr, const uint32_t* work,
+                                              const uint32_t* occ, const uint32_t* start,
+                                              const int32_t* dN, const uint32_t* cbase,
+                                              const SlotConst* sc, const int32_t* blk_slot,
+                                              const uint32_t* blk_local, uint32_t cap) {
+  couple_phase<T>(b, ctr, work, occ, start, dN, cbase, sc, blk_slot, blk_local, cap, blockIdx.x,
+                  gridDim.x);
+}
+
+// Per-slot end of step: advance the step counter and apply the stop rule (thread t of
+// nthr threads takes slots t, t + nthr, ...).
+__device__ __forceinline__ void finish_phase(SlotConst* sc, unsigned long long* st, uint32_t* stat2,
+                                             uint32_t ms, uint32_t t, uint32_t nthr) {
+  for (uint32_t s = t; s < ms; s += nthr) {
     if (sc[s].state != ITOKMC_SLOT_ACTIVE) continue;
     const uint64_t live = st[S_LIVE * ms + s];
     st[S_PUSHED * ms + s] += live;
@@ -445,6 +483,300 @@ __global__ void e_finish(SlotConst* sc, unsigned long long* st, uint32_t* stat2,
     stat2[2 * s] = state;
     stat2[2 * s + 1] = step;
   }
+}
+
+__global__ void e_finish(SlotConst* sc, unsigned long long* st, uint32_t* stat2, uint32_t ms) {
+  finish_phase(sc, st, stat2, ms, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// ---- persistent fused step ---------------------------------------------------------------
+// The step above in one launch: a grid of kFuseBlock-thread workgroups that are all
+// resident together (the host sizes it from the kernel's occupancy) runs every phase,
+// with a device-wide barrier between consecutive phases.  A barrier waits a bounded
+// time: a workgroup that gives up raises the grid's failure word and the overflow flag
+// ITOKMC_OVF_BARRIER and returns, and the others return at their next wait once they see
+// the word, so the launch always ends.  The counting sort takes a form suited to a
+// resident grid: each workgroup counts one contiguous range of scan tiles, and after one
+// barrier adds the totals of the ranges before its own to place its cells, so that the
+// tile totals need no scan launches of their own.
+
+constexpr int kFuseBlock = 256;
+constexpr int kFuseMaxPerCu = 4;                          // register budgets: 1, 2 or 4 workgroups per CU
+constexpr uint32_t kFuseMaxGrid = 1024u * kFuseMaxPerCu;  // workgroups (any compute-unit count up to 1024)
+constexpr uint32_t kScanCells = 1u << kTileShift;         // cells per scan tile
+
+// Barrier words, each on a 64-byte line of its own: one arrival count per group of
+// workgroups (group g: the workgroups whose index is g modulo kBarGroups; the hardware
+// deals consecutive workgroups to the eight XCDs in turn), the count of groups arrived,
+// the number of barriers completed, and the failure word.
+constexpr uint32_t kBarGroups = 8;
+struct GridBar {
+  uint32_t group[kBarGroups][16];
+  uint32_t top[16];
+  uint32_t gen[16];
+  uint32_t fail[16];
+};
+
+// Device-wide barrier of the nblk workgroups of the grid; false once the grid has given
+// up.  limit: the longest wait, in wall-clock ticks.  flag: one word of LDS.  A
+// workgroup arrives at its group's count; the last of a group arrives at the top count,
+// and the last group's arrival completes the barrier, so that no single word takes one
+// atomic per workgroup.
+__device__ bool grid_barrier(GridBar* bar, Counters* ctr, uint32_t nblk, uint64_t limit,
+                             uint32_t* flag) {
+  // every wavefront waits for its own stores of this phase to reach the L2; thread 0's
+  // release fence then writes the L2's dirty lines back for the whole workgroup (the
+  // workgroups of the grid sit on different XCDs, each with its own L2)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // the barrier words are read and counted with device-coherent relaxed atomics, so
+    // the wait does not invalidate the caches that other workgroups are still using;
+    // the acquire fence after the wait orders the reads of the next phase
+    uint32_t ok = 1u;
+    const uint32_t g = blockIdx.x % kBarGroups;
+    const uint32_t ngroups = min(nblk, kBarGroups);
+    const uint32_t gsize = (nblk - g + kBarGroups - 1u) / kBarGroups;  // workgroups of group g
+    const uint32_t g0 = __hip_atomic_load(&bar->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    if (__hip_atomic_fetch_add(&bar->group[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gsize) {
+      // the group's last arrival takes over the group's writes (acquire), resets the
+      // group count and passes both on with its arrival at the top count (release)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(&bar->group[g][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(&bar->top[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == ngroups) {
+        __hip_atomic_store(&bar->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&bar->gen[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&bar->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        if (__hip_atomic_load(&bar->fail[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0u; break; }
+        if ((uint64_t)(wall_clock64() - t0) > limit) {
+          __hip_atomic_fetch_or(&bar->fail[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          atomicOr(&ctr->overflow, (uint32_t)ITOKMC_OVF_BARRIER);
+          ok = 0u;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    *flag = ok;
+  }
+  __syncthreads();
+  // every wavefront: its later reads see the other workgroups' writes of this phase
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *flag != 0u;
+}
+
+// Sums of two values over the workgroup (valid in every thread); sh: 2 * waves + 2 words.
+__device__ __forceinline__ void block_sum2(uint32_t a, uint32_t b, uint32_t* sh, uint32_t* sa,
+                                           uint32_t* sb) {
+  const int lane = lane_id(), wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += (uint32_t)__shfl_xor((int)a, d, 64);
+    b += (uint32_t)__shfl_xor((int)b, d, 64);
+  }
+  if (lane == 0) { sh[2 * wid] = a; sh[2 * wid + 1] = b; }
+  __syncthreads();
+  uint32_t x = 0, y = 0;
+  for (int i = 0; i < nw; ++i) { x += sh[2 * i]; y += sh[2 * i + 1]; }
+  *sa = x;
+  *sb = y;
+  __syncthreads();
+}
+
+// The scan tiles [t0, t1) of workgroup bid's range.
+__device__ __forceinline__ void fuse_range(uint32_t ncell, uint32_t bid, uint32_t nblk,
+                                           uint32_t* t0, uint32_t* t1) {
+  const uint32_t nb = (ncell + kScanCells - 1) / kScanCells;
+  const uint32_t per = (nb + nblk - 1) / nblk;
+  *t0 = min(nb, bid * per);
+  *t1 = min(nb, *t0 + per);
+}
+
+// Counting sort, first half: the particle and occupied-cell counts of every flagged
+// tile of the range (flags cleared), and the range's totals in wgt[2 bid ..].
+__device__ void fuse_count(const unsigned long long* cellacc, uint32_t ncell, uint32_t* tiles,
+                           uint32_t* cnt, uint32_t* wgt, uint32_t* sh, uint32_t bid,
+                           uint32_t nblk) {
+  uint32_t t0, t1;
+  fuse_range(ncell, bid, nblk, &t0, &t1);
+  uint32_t tot0 = 0, tot1 = 0;
+  for (uint32_t t = t0; t < t1; ++t) {
+    uint32_t n = 0, oc = 0;
+    if (tiles[t] != 0u) {  // uniform: one word per tile
+      for (uint32_t c = t * kScanCells + threadIdx.x; c < min(ncell, (t + 1) * kScanCells); c += blockDim.x) {
+        const uint32_t k = (uint32_t)(cellacc[c] >> 32);
+        n += k;
+        oc += k ? 1u : 0u;
+      }
+    }
+    uint32_t sn, so;
+    block_sum2(n, oc, sh, &sn, &so);
+    if (threadIdx.x == 0) {
+      cnt[2 * t] = sn;
+      cnt[2 * t + 1] = so;
+      tiles[t] = 0u;
+    }
+    tot0 += sn;
+    tot1 += so;
+  }
+  if (threadIdx.x == 0) {
+    wgt[2 * bid] = tot0;
+    wgt[2 * bid + 1] = tot1;
+  }
+}
+
+// Counting sort, second half: the first bank slot of every occupied cell of the range
+// (start) and the ascending list of occupied cells (occ), offset by the totals of the
+// ranges before this one; the last workgroup writes the grand totals and resets the
+// step's append counters.  sh: kScanCells + 2 * waves + 2 words.
+__device__ void fuse_place(const unsigned long long* cellacc, uint32_t ncell, const uint32_t* cnt,
+                           const uint32_t* wgt, uint32_t* start, uint32_t* occ, Counters* ctr,
+                           int dest, uint32_t* sh, uint32_t bid, uint32_t nblk) {
+  uint32_t* red = sh + kScanCells;
+  uint32_t b0 = 0, b1 = 0;
+  for (uint32_t i = threadIdx.x; i < bid; i += blockDim.x) {
+    b0 += wgt[2 * i];
+    b1 += wgt[2 * i + 1];
+  }
+  uint32_t base0, base1;
+  block_sum2(b0, b1, red, &base0, &base1);
+  uint32_t t0, t1;
+  fuse_range(ncell, bid, nblk, &t0, &t1);
+  if (bid + 1u == nblk && threadIdx.x == 0) {
+    const uint32_t total = base0 + wgt[2 * bid], tocc = base1 + wgt[2 * bid + 1];
+    start[ncell] = total;
+    ctr->sorted = total;
+    ctr->n_occ = tocc;
+    ctr->n[dest] = total;
+    ctr->n_work = 0;
+    ctr->n_big = 0;
+    ctr->n_heavy = 0;
+    ctr->n_huge = 0;
+    ctr->n_cfull = 0;
+    ctr->n_cmerge = 0;
+  }
+  const uint32_t per = kScanCells / blockDim.x;  // consecutive cells per thread
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t c0t = cnt[2 * t], c1t = cnt[2 * t + 1];
+    if (c0t == 0u) continue;  // uniform
+    const uint32_t tb = t * kScanCells;
+    for (uint32_t i = threadIdx.x; i < kScanCells; i += blockDim.x)
+      sh[i] = tb + i < ncell ? (uint32_t)(cellacc[tb + i] >> 32) : 0u;
+    __syncthreads();
+    uint32_t k = 0, oc = 0;
+    for (uint32_t j = 0; j < per; ++j) {
+      const uint32_t v = sh[threadIdx.x * per + j];
+      k += v;
+      oc += v ? 1u : 0u;
+    }
+    // exclusive prefix over the workgroup's threads, in cell order
+    const int lane = lane_id(), wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+    uint32_t x = k, y = oc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t xs = (uint32_t)__shfl_up((int)x, d, 64), ys = (uint32_t)__shfl_up((int)y, d, 64);
+      if (lane >= d) { x += xs; y += ys; }
+    }
+    if (lane == 63) { red[2 * wid] = x; red[2 * wid + 1] = y; }
+    __syncthreads();
+    uint32_t p0 = base0 + x - k, p1 = base1 + y - oc;
+    for (int i = 0; i < wid; ++i) { p0 += red[2 * i]; p1 += red[2 * i + 1]; }
+    for (uint32_t j = 0; j < per; ++j) {
+      const uint32_t v = sh[threadIdx.x * per + j];
+      if (v) {
+        const uint32_t c = tb + threadIdx.x * per + j;
+        start[c] = p0;
+        occ[p1++] = c;
+        p0 += v;
+      }
+    }
+    __syncthreads();  // sh and red are reused by the next tile
+    base0 += c0t;
+    base1 += c1t;
+    (void)nw;
+  }
+}
+
+// Scatter into the destination bank at start[cell] + rank (thread t of nthr threads).
+template <typename T>
+__device__ __forceinline__ void fuse_scatter(Bank a, Bank b, const Counters* ctr, int which,
+                                             const uint32_t* start, uint32_t cap, uint32_t t,
+                                             uint32_t nthr) {
+  const uint32_t n = min(ctr->n[which], cap);
+  for (uint32_t i = t; i < n; i += nthr) {
+    const uint32_t w = a.w[i];
+    if (w == 0u) continue;
+    const uint32_t cell = a.cell[i];
+    const uint32_t q = start[cell] + a.rank[i];
+    b.cell[q] = cell;
+    as<T>(b.ox)[q] = as<T>(a.ox)[i];
+    as<T>(b.oy)[q] = as<T>(a.oy)[i];
+    as<T>(b.oz)[q] = as<T>(a.oz)[i];
+    b.w[q] = w;
+    b.id[q] = a.id[i];
+  }
+}
+
+struct FuseArgs {
+  Bank a, b;  // source and destination banks
+  Counters* ctr;
+  int cur;
+  unsigned long long* cellacc;
+  uint32_t* tiles;
+  const uint32_t* ncell;  // pool cells to scan (device word)
+  uint32_t *cnt, *wgt;
+  GridBar* bar;
+  uint32_t *start, *occ, *nplus, *nminus;
+  int32_t* dN;
+  uint32_t *work, *cbase, *heavy;
+  SlotConst* sc;
+  unsigned long long* st;
+  uint32_t* stat2;
+  const int32_t* blk_slot;
+  const uint32_t *blk_local, *map;
+  uint32_t ms, cap;
+  uint64_t limit;
+};
+
+// W: resident workgroups per compute unit that the register budget is cut for (W waves
+// per SIMD).  The full KMC pass needs about 256 registers per lane without spilling, so
+// W = 1 keeps every phase in registers while W = 2 and 4 buy the push and the scatter
+// more wavefronts in flight for spills in the KMC passes; the autotuner chooses.
+template <typename T, int W>
+__global__ void __launch_bounds__(kFuseBlock, W) e_step_fused(FuseArgs A) {
+  __shared__ __align__(16) uint32_t sh[kScanCells + 2 * (kFuseBlock / 64) + 2];
+  __shared__ uint32_t flag;
+  const uint32_t bid = blockIdx.x, G = gridDim.x;
+  const uint32_t tid = bid * blockDim.x + threadIdx.x, nthr = G * blockDim.x;
+  const uint32_t nwv = blockDim.x >> 6;
+  const int dest = 1 - A.cur;
+  push_phase<T>(A.a, A.ctr, A.cur, A.cellacc, A.tiles, A.sc, A.blk_slot, A.blk_local, A.map, A.st,
+                A.ms, A.cap, bid, G);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  const uint32_t ncell = *A.ncell;
+  fuse_count(A.cellacc, ncell, A.tiles, A.cnt, A.wgt, sh, bid, G);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  fuse_place(A.cellacc, ncell, A.cnt, A.wgt, A.start, A.occ, A.ctr, dest, sh, bid, G);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  fuse_scatter<T>(A.a, A.b, A.ctr, A.cur, A.start, A.cap, tid, nthr);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  kmc_phase<true>(A.ctr, A.occ, A.cellacc, A.nplus, A.nminus, A.dN, A.work, A.cbase, A.heavy, A.sc,
+                  A.blk_slot, A.blk_local, A.st, A.ms, dest, sh, bid, G);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  kmc_phase<false>(A.ctr, A.occ, A.cellacc, A.nplus, A.nminus, A.dN, A.work, A.cbase, A.heavy, A.sc,
+                   A.blk_slot, A.blk_local, A.st, A.ms, dest, sh, bid, G);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  couple_phase<T>(A.b, A.ctr, A.work, A.occ, A.start, A.dN, A.cbase, A.sc, A.blk_slot, A.blk_local,
+                  A.cap, bid * nwv + (threadIdx.x >> 6), G * nwv);
+  if (!grid_barrier(A.bar, A.ctr, G, A.limit, &flag)) return;
+  finish_phase(A.sc, A.st, A.stat2, A.ms, tid, nthr);
 }
 
 // ---- queries ------------------------------------------------------------------------------
@@ -583,6 +915,11 @@ struct itokmc_ens {
   unsigned long long* slot_red = nullptr;  // 4 per slot: count, weight (pool), n+, n-
   uint32_t* tiles = nullptr;                // scan tile flags
   uint32_t* heavy = nullptr;                // cells for the full KMC pass
+  GridBar* bar = nullptr;                   // fused step: device-wide barrier words
+  uint32_t* wgt = nullptr;                  // fused step: per-workgroup range totals
+  int n_cu = 0;                             // compute units of the device
+  int fuse_occ = 0;                         // fused kernel: resident workgroups per CU
+  uint64_t fuse_limit = 0;                  // fused kernel: longest barrier wait (ticks)
   // host bookkeeping
   std::vector<SlotHost> slots;
   std::set<uint32_t> free_blocks, used_blocks;
@@ -592,7 +929,7 @@ struct itokmc_ens {
   uint64_t quota_free = 0, pending_quota = 0;
   uint32_t hw_blocks = 0;
   uint64_t steps = 0;
-  itokmc_ens_tuning tune{256, 8, 256, 64, 1, 0};
+  itokmc_ens_tuning tune{256, 8, 256, 64, 1, 0};  // fused_per_cu 0: the kernel sequence
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   bool graph_failed = false;
   uint32_t* host_stat = nullptr;
@@ -669,6 +1006,7 @@ void ens_layout(const itokmc_ens_desc* d, EnsLayout* L) {
   put(ms * 4 * 8);                     // 32 per-slot result reductions
   put((nc / 2048 + 2) * 4);            // 33 scan tile flags
   put(nc * 4);                         // 34 cells for the full KMC pass
+  put(sizeof(GridBar) + 2 * kFuseMaxGrid * 4);  // 35 fused step: barrier words, range totals
   L->total = o;
 }
 
@@ -681,8 +1019,83 @@ int grid_particles(const itokmc_ens* e) {
   return g;
 }
 
+template <typename T, int W>
+hipError_t fuse_launch(const FuseArgs& A, uint32_t grid, hipStream_t s) {
+  e_step_fused<T, W><<<grid, kFuseBlock, 0, s>>>(A);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fuse_occupancy(int w, int* occ) {
+  if (w == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, e_step_fused<T, 1>, kFuseBlock, 0);
+  if (w == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, e_step_fused<T, 2>, kFuseBlock, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, e_step_fused<T, 4>, kFuseBlock, 0);
+}
+
+// The device's compute units, the fused budgets that keep their W workgroups per
+// compute unit resident (a bit mask over W = 1, 2, 4) and the barrier time limit: 4 s of
+// the device's constant-rate wall clock, or ITOKMC_FUSED_WAIT_US microseconds when that
+// environment variable is set (tests shorten it to exercise the failure report).
+hipError_t fuse_setup(itokmc_ens* e) {
+  int dev = 0, rate_khz = 0;
+  hipError_t h = hipGetDevice(&dev);
+  if (h == hipSuccess) h = hipDeviceGetAttribute(&e->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (h == hipSuccess) h = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+  e->fuse_occ = 0;
+  for (int w : {1, 2, 4}) {
+    int occ = 0;
+    if (h == hipSuccess) h = f64(e) ? fuse_occupancy<double>(w, &occ) : fuse_occupancy<float>(w, &occ);
+    if (h == hipSuccess && occ >= w) e->fuse_occ |= w;
+  }
+  if (h != hipSuccess) return h;
+  if ((uint64_t)e->n_cu * kFuseMaxPerCu > kFuseMaxGrid) e->fuse_occ = 0;  // range totals would not fit
+  uint64_t wait_us = 4000000ull;
+  if (const char* v = getenv("ITOKMC_FUSED_WAIT_US")) wait_us = strtoull(v, nullptr, 10);
+  e->fuse_limit = (uint64_t)std::max(rate_khz, 1) * wait_us / 1000ull;
+  return hipSuccess;
+}
+
+hipError_t enqueue_fused(itokmc_ens* e, int cur, hipStream_t s) {
+  FuseArgs A;
+  A.a = e->bank[cur];
+  A.b = e->bank[1 - cur];
+  A.ctr = e->ctr;
+  A.cur = cur;
+  A.cellacc = e->cellacc;
+  A.tiles = e->tiles;
+  A.ncell = e->misc;
+  A.cnt = e->blocksums;
+  A.wgt = e->wgt;
+  A.bar = e->bar;
+  A.start = e->start;
+  A.occ = e->occ;
+  A.nplus = e->nplus;
+  A.nminus = e->nminus;
+  A.dN = e->dN;
+  A.work = e->work;
+  A.cbase = e->cbase;
+  A.heavy = e->heavy;
+  A.sc = e->sc;
+  A.st = e->st;
+  A.stat2 = e->stat2;
+  A.blk_slot = e->blk_slot;
+  A.blk_local = e->blk_local;
+  A.map = e->map;
+  A.ms = e->ms;
+  A.cap = e->cap;
+  A.limit = e->fuse_limit;
+  const int w = e->tune.fused_per_cu;
+  const uint32_t G = (uint32_t)(e->n_cu * w);  // exactly the resident workgroups
+  if (f64(e))
+    return w == 1 ? fuse_launch<double, 1>(A, G, s) : w == 2 ? fuse_launch<double, 2>(A, G, s)
+                                                             : fuse_launch<double, 4>(A, G, s);
+  return w == 1 ? fuse_launch<float, 1>(A, G, s) : w == 2 ? fuse_launch<float, 2>(A, G, s)
+                                                          : fuse_launch<float, 4>(A, G, s);
+}
+
 // Enqueue one ensemble step for bank parity cur on stream s.
 hipError_t enqueue_step(itokmc_ens* e, int cur, hipStream_t s) {
+  if (e->tune.fused_per_cu > 0) return enqueue_fused(e, cur, s);
   const int dest = 1 - cur;
   const int gp = grid_particles(e);
   if (f64(e))
@@ -848,7 +1261,9 @@ int itokmc_ensemble_create(itokmc_ens** out, const itokmc_ens_desc* desc, void* 
   e->slot_red = (unsigned long long*)(a + L.off[32]);
   e->tiles = (uint32_t*)(a + L.off[33]);
   e->heavy = (uint32_t*)(a + L.off[34]);
-  hipError_t h = hipSuccess;
+  e->bar = (GridBar*)(a + L.off[35]);
+  e->wgt = (uint32_t*)(a + L.off[35] + sizeof(GridBar));
+  hipError_t h = fuse_setup(e);
   if (h == hipSuccess) h = hipMemsetAsync(e->cellacc, 0, (size_t)e->max_cells * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->ctr, 0, sizeof(Counters), e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->misc, 0, 64, e->s);
@@ -857,6 +1272,7 @@ int itokmc_ensemble_create(itokmc_ens** out, const itokmc_ens_desc* desc, void* 
   if (h == hipSuccess) h = hipMemsetAsync(e->st, 0, (size_t)e->ms * S_NUM * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->stat2, 0, (size_t)e->ms * 8, e->s);
   if (h == hipSuccess) h = hipMemsetAsync(e->blk_slot, 0xFF, (size_t)e->nblk * 4, e->s);
+  if (h == hipSuccess) h = hipMemsetAsync(e->bar, 0, sizeof(GridBar), e->s);
   if (h == hipSuccess) h = hipHostMalloc((void**)&e->host_stat, (size_t)e->ms * 8, hipHostMallocDefault);
   if (h == hipSuccess) h = hipHostMalloc((void**)&e->host_ctr, sizeof(Counters), hipHostMallocDefault);
   if (h == hipSuccess) h = hipHostMalloc((void**)&e->host_red, 64, hipHostMallocDefault);
@@ -1012,6 +1428,9 @@ int itokmc_ensemble_poll(itokmc_ens* e, itokmc_slot_event* ev, int32_t max, int3
     ++k;
   }
   *n_ev = k;
+  if (e->host_ctr->overflow & ITOKMC_OVF_BARRIER)
+    return ens_error(e, ITOKMC_EHIP,
+                     "fused ensemble step: a device-wide barrier timed out; the ensemble's state is not valid");
   if (e->host_ctr->overflow)
     return ens_error(e, ITOKMC_ECAPACITY, "ensemble pool overflow (flags %u)", e->host_ctr->overflow);
   return ITOKMC_OK;
@@ -1204,10 +1623,14 @@ int itokmc_ensemble_set_tuning(itokmc_ens* e, const itokmc_ens_tuning* t) {
   if (t->push_block < 64 || t->push_block > 1024 || t->push_block % 64 ||
       t->push_blocks_per_cu < 1 || t->push_blocks_per_cu > 64 ||
       (t->kmc_block != 64 && t->kmc_block != 128 && t->kmc_block != 256) ||
-      t->couple_per_cu < 1 || t->couple_per_cu > 256)
+      t->couple_per_cu < 1 || t->couple_per_cu > 256 ||
+      (t->fused_per_cu != 0 && t->fused_per_cu != 1 && t->fused_per_cu != 2 && t->fused_per_cu != 4))
     return ens_error(e, ITOKMC_EINVAL, "tuning out of range");
+  if (t->fused_per_cu && !(e->fuse_occ & t->fused_per_cu))
+    return ens_error(e, ITOKMC_EINVAL,
+                     "fused step: %d workgroups per compute unit do not stay resident on this device",
+                     t->fused_per_cu);
   e->tune = *t;
-  e->tune.pad0 = 0;
   drop_graphs(e);
   return ITOKMC_OK;
 }
@@ -1272,6 +1695,19 @@ int itokmc_ensemble_autotune(itokmc_ens* e, uint32_t rounds, itokmc_ens_tuning* 
     for (int cc : {16, 64, 256}) { itokmc_ens_tuning t = cur; t.couple_per_cu = cc; c3.push_back(t); }
     rc = measure(c3, &arg, &cur_ms);
     if (!rc) cur = c3[arg];
+  }
+  if (!rc) {
+    // the form of the step: the kernel sequence (with the shapes found above) against
+    // the persistent fused kernel at each resident grid size
+    std::vector<itokmc_ens_tuning> c4;
+    for (int k : {0, 1, 2, 4}) {
+      if (k && !(e->fuse_occ & k)) continue;
+      itokmc_ens_tuning t = cur;
+      t.fused_per_cu = k;
+      c4.push_back(t);
+    }
+    rc = measure(c4, &arg, &cur_ms);
+    if (!rc) cur = c4[arg];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -145,7 +145,7 @@ class EnsInfo(ctypes.Structure):
 
 class EnsTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("push_block", "push_blocks_per_cu", "kmc_block",
-                                              "couple_per_cu", "use_graph", "pad0")]
+                                              "couple_per_cu", "use_graph", "fused_per_cu")]
 
 
 class ItokmcError(RuntimeError):
@@ -664,7 +664,7 @@ class Ensemble:
     def tuning(self):
         t = EnsTuning()
         self._check(lib().itokmc_ensemble_get_tuning(self.h, ctypes.byref(t)))
-        return {n: getattr(t, n) for n, _ in EnsTuning._fields_ if n != "pad0"}
+        return {n: getattr(t, n) for n, _ in EnsTuning._fields_}
 
     def set_tuning(self, **kw):
         t = EnsTuning()
@@ -678,7 +678,7 @@ class Ensemble:
         ms = ctypes.c_double()
         self._check(lib().itokmc_ensemble_autotune(self.h, rounds, ctypes.byref(t),
                                                    ctypes.byref(ms)))
-        return {n: getattr(t, n) for n, _ in EnsTuning._fields_ if n != "pad0"}, ms.value
+        return {n: getattr(t, n) for n, _ in EnsTuning._fields_}, ms.value
 
 
 def philox_fill(c0, c1, c2, c3, k0, k1, n, device="cuda:0"):
