@@ -120,22 +120,24 @@ __global__ void __launch_bounds__(64, 5) k_couple(Bank b, Counters* ctr, int whi
       wr = (uint32_t)d % M;
       base = cbase[j];  // slots reserved by the KMC pass
     }
-    // new particles, one per lane (n_new <= 64), into the reserved slots
-    if (full && (uint32_t)lane < M) {
-      const uint32_t q = base + (uint32_t)lane;
-      if (q < K.cap) write_product<T>(b, q, c, c, (uint32_t)lane, wb, wr, K.step, K.key);
-      else atomicOr(&ctr->overflow, 1u);
-    }
+    // new particles, one per lane (n_new <= 64), for the reserved slots; slots past the
+    // bank's capacity are flagged
+    const bool mine = full && (uint32_t)lane < M;
+    const uint32_t q = base + (uint32_t)lane;
+    if (mine && q >= K.cap) atomicOr(&ctr->overflow, 1u);
     if (full) created += M;
     pieces += (e - s) + M;
+    int r = 0;
     if (n_ppc > 0) {
-      // removal and product stores visible before the merge gathers them (nothing to
-      // wait for otherwise: the previous cell's leaf stores are to other slots)
-      if (full && (d < 0 || M > 0)) __syncthreads();
+      // removal stores visible before the merge gathers the cell (nothing to wait for
+      // otherwise: the previous cell's leaf stores are to other slots); the products
+      // are made by the gather itself and stored only if the cell is not merged here
+      if (full && d < 0) __syncthreads();
       else wave_lds_sync();
-      const int r = merge_cell<T, kMergeTiny, NL>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged);
+      r = merge_cell<T, kMergeTiny, NL>(b, ctr, which, K, c, s, e, base, M, n_ppc, &merged, full, wb, wr);
       if (r == 2 && lane == 0) big[atomicAdd(&ctr->n_big, 1u)] = j;
     }
+    if (mine && r != 1 && q < K.cap) write_product<T>(b, q, c, c, (uint32_t)lane, wb, wr, K.step, K.key);
   }
   if (lane == 0) {
     if (created) atomicAdd(&ctr->created, (unsigned long long)created);

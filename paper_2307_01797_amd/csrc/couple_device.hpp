@@ -64,19 +64,39 @@ __device__ inline uint64_t remove_weight_lane(Bank b, uint32_t s, uint32_t e, ui
   return removed;
 }
 
-// Write the k-th of M KMC products of cell c (local index lc for ids and streams) into
-// bank slot q: offsets uniform in the cell, weight wb (+ wr for the first).
+// The k-th of M KMC products of a cell (local index lc for ids and streams): offsets
+// uniform in the cell, weight wb (+ wr for the first), id.
+template <typename T>
+struct Product {
+  T o[3];
+  uint32_t w;
+  uint64_t id;
+};
+template <typename T>
+__device__ __forceinline__ Product<T> make_product(uint32_t lc, uint32_t k, uint32_t wb, uint32_t wr,
+                                                   uint32_t step, Key key) {
+  const uint4 r = philox_block(lc, k, step, TAG_CREATE, 0, key);
+  Product<T> p;
+  p.o[0] = (T)u24(r.x);
+  p.o[1] = (T)u24(r.y);
+  p.o[2] = (T)u24(r.z);
+  p.w = wb + (k == 0 ? wr : 0u);
+  p.id = make_id(KIND_KMC, step, lc, k);
+  return p;
+}
+
+// Write that product into bank slot q of global cell gcell.
 template <typename T>
 __device__ __forceinline__ void write_product(Bank b, uint32_t q, uint32_t gcell, uint32_t lc,
                                               uint32_t k, uint32_t wb, uint32_t wr, uint32_t step,
                                               Key key) {
-  const uint4 r = philox_block(lc, k, step, TAG_CREATE, 0, key);
+  const Product<T> p = make_product<T>(lc, k, wb, wr, step, key);
   b.cell[q] = gcell;
-  reinterpret_cast<T*>(b.ox)[q] = (T)u24(r.x);
-  reinterpret_cast<T*>(b.oy)[q] = (T)u24(r.y);
-  reinterpret_cast<T*>(b.oz)[q] = (T)u24(r.z);
-  b.w[q] = wb + (k == 0 ? wr : 0u);
-  b.id[q] = make_id(KIND_KMC, step, lc, k);
+  reinterpret_cast<T*>(b.ox)[q] = p.o[0];
+  reinterpret_cast<T*>(b.oy)[q] = p.o[1];
+  reinterpret_cast<T*>(b.oz)[q] = p.o[2];
+  b.w[q] = p.w;
+  b.id[q] = p.id;
 }
 
 }  // namespace itk

@@ -25,6 +25,7 @@
 #pragma once
 #include <type_traits>
 
+#include "couple_device.hpp"
 #include "device.hpp"
 #include "itk.hpp"
 
@@ -100,11 +101,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 // Returns 0 if the cell needs no merge, 1 if it was merged, 2 if it holds more than CAP
-// pieces (nothing written; the caller defers it to a larger staging area).
+// pieces (nothing written; the caller defers it to a larger staging area).  gen: the
+// cell's M KMC products (weights wb, wb + wr for the first) have not been written to
+// their slots [base, base + M) yet; the gather makes them in place (the same values
+// write_product stores), and a merged cell's leaves then take those slots directly.
 template <typename T, int CAP, int NL>
 __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, uint32_t c,
                           uint32_t s, uint32_t e, uint32_t base, uint32_t M, int n_ppc,
-                          uint64_t* merged) {
+                          uint64_t* merged, bool gen = false, uint32_t wb = 0, uint32_t wr = 0) {
   using U = typename Bits<T>::U;
   constexpr int S = CAP + NL;
   constexpr uint8_t kNone = 0xFF;
@@ -155,12 +159,21 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
     // product slots past the bank's capacity were never written (overflow is flagged);
     // every word is requested at once (lanes out of range read slot 0, unused)
     const bool inr = qi < nseg + M && q < K.cap;
-    const uint32_t qc = inr ? q : 0u;
-    const uint32_t wq = b.w[qc];
-    const uint64_t iq = b.id[qc];
-    const T x0 = reinterpret_cast<const T*>(b.ox)[qc];
-    const T x1 = reinterpret_cast<const T*>(b.oy)[qc];
-    const T x2 = reinterpret_cast<const T*>(b.oz)[qc];
+    const bool made = gen && qi >= nseg;  // a product made here, not read
+    const uint32_t qc = inr && !made ? q : 0u;
+    uint32_t wq = b.w[qc];
+    uint64_t iq = b.id[qc];
+    T x0 = reinterpret_cast<const T*>(b.ox)[qc];
+    T x1 = reinterpret_cast<const T*>(b.oy)[qc];
+    T x2 = reinterpret_cast<const T*>(b.oz)[qc];
+    if (made && inr) {
+      const Product<T> pr = make_product<T>(c, qi - nseg, wb, wr, K.step, K.key);
+      wq = pr.w;
+      iq = pr.id;
+      x0 = pr.o[0];
+      x1 = pr.o[1];
+      x2 = pr.o[2];
+    }
     const uint32_t w = inr ? wq : 0u;
     const bool alive = w > 0;
     const uint64_t mask = __ballot(alive);
@@ -347,8 +360,13 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       otag[RL + rank] = L;
     }
     wave_lds_sync();
-    // (iii) weight median of every splitting leaf: one segmented scan over the buffer
-    uint64_t carry = 0;
+    // (iii) weight median of every splitting leaf: one segmented scan over the buffer.
+    // A leaf's weight is below 2^32 (LW), so its prefix sums are exact in 32 bits.  The
+    // pieces of a leaf all weigh at least 1, so its prefix x rises strictly: a slot
+    // lies left of the median if 2x <= W, right of it if 2(x - w) > W, and is the
+    // median otherwise; the first two get their child's tag here, the median (and a
+    // split superparticle's spare slot) with the children below.
+    uint32_t carry = 0;
     uint32_t carry_key = 0xFFFFFFFFu;
     bool carry_hit = false;
     for (uint32_t q0 = 0; q0 < new_extent; q0 += 64) {
@@ -356,24 +374,30 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       const uint8_t t8 = q < new_extent ? otag[q] : kNone;
       const bool valid = t8 != kNone;
       const uint32_t vkey = valid ? (uint32_t)t8 : 0xFFFFFFFFu;
-      const uint64_t w = valid ? (uint64_t)sw[I(ncb)[q]] : 0ull;
+      const uint32_t w = valid ? sw[I(ncb)[q]] : 0u;
       // segmented prefix sums of the weights over the chunk (DPP moves, no LDS)
       const uint32_t prev = dpp_from_prev(vkey, ~vkey);
-      uint64_t xs[1] = {w};
-      const uint64_t zid[1] = {0ull};
+      uint32_t xs[1] = {w};
+      const uint32_t zid[1] = {0u};
       const uint32_t seen = seg_scan(xs, prev != vkey ? 1u : 0u, zid,
-                                     [](int, uint64_t a, uint64_t b) { return a + b; });
-      uint64_t x = xs[0];
+                                     [](int, uint32_t a, uint32_t b) { return a + b; });
+      uint32_t x = xs[0];
       if (!seen && vkey == carry_key) x += carry;
-      const bool hit = valid && 2ull * x > (uint64_t)LW(cb)[vkey & 63u];
+      const uint32_t Wv = valid ? LW(cb)[vkey & 63u] : 0u;
+      const bool hit = valid && x > Wv - x;  // 2x > W
       const bool up_hit = dpp_from_prev(hit ? 1u : 0u, 0u) != 0u;
       const bool prev_same = lane > 0 ? prev == vkey : vkey == carry_key;
       const bool prev_hit = lane > 0 ? up_hit : carry_hit;
       if (hit && !(prev_same && prev_hit)) {
         medp[vkey] = q - Rg[vkey];
-        medWl[vkey] = (uint32_t)(x - w);
+        medWl[vkey] = x - w;
       }
-      carry = lane_u64(x, 63);
+      if (valid) {
+        const uint32_t ni = vkey + (uint32_t)__popcll(chm & ((1ull << vkey) - 1ull));
+        const uint32_t xe = x - w;
+        tag(ncb)[q] = !hit ? (uint8_t)ni : (xe > Wv - xe ? (uint8_t)(ni + 1u) : kNone);
+      }
+      carry = lane_u32(x, 63);
       carry_key = lane_u32(vkey, 63);
       carry_hit = lane_u32(hit ? 1u : 0u, 63) != 0u;
     }
@@ -415,24 +439,12 @@ __device__ int merge_cell(Bank b, Counters* ctr, int which, const StepConst& K, 
       }
       Lst(ncb)[newidx] = R; Lcn(ncb)[newidx] = lcnt; LW(ncb)[newidx] = WLn;
       Lst(ncb)[newidx + 1] = R + rst; Lcn(ncb)[newidx + 1] = rcnt; LW(ncb)[newidx + 1] = WRn;
-    }
-    wave_lds_sync();
-    // leaf tags of the split regions (ordered slots plus the spare slot)
-    for (uint32_t q = (uint32_t)lane; q < new_extent; q += 64) {
-      uint8_t L = otag[q];
-      if (L == kNone) {
-        if (q == 0 || otag[q - 1] == kNone) continue;
-        const uint8_t Lp = otag[q - 1];
-        if (q != Rg[Lp] + Lcn(cb)[Lp]) continue;
-        L = Lp;  // the spare slot that follows an ordered range
-      }
-      const uint32_t ni = (uint32_t)L + (uint32_t)__popcll(chm & ((1ull << L) - 1ull));
-      const uint32_t off = q - Rg[L];
-      const uint32_t lc = Lcn(ncb)[ni], rs = Lst(ncb)[ni + 1] - Rg[L], rc = Lcn(ncb)[ni + 1];
-      uint8_t t = kNone;
-      if (off < lc) t = (uint8_t)ni;
-      else if (off >= rs && off < rs + rc) t = (uint8_t)(ni + 1);
-      tag(ncb)[q] = t;
+      // the median slot joins the left child if the left count covers it, else the
+      // right one (a unit median) or none (a split superparticle whose left part is
+      // empty); a split superparticle's right part, in the spare slot, closes the
+      // right child
+      tag(ncb)[R + mu] = lcnt > mu ? (uint8_t)newidx : (super ? kNone : (uint8_t)(newidx + 1u));
+      if (super) tag(ncb)[R + n_i] = (uint8_t)(newidx + 1u);
     }
     wave_lds_sync();
     cb = ncb;
