@@ -156,6 +156,31 @@ def test_capacity_reported_and_state_valid(itk):
     assert len(np.unique(ids)) == len(ids)
 
 
+def test_capacity_with_merging_state_valid(itk):
+    """The self-consistent streamer (merging on) in a bank only a little larger than its
+    seed: KMC products that find no slot are flagged, the coupling still merges the
+    cells whose products it makes itself, and every particle left is valid (cells in
+    range, offsets in [0,1), positive weights, unique ids)."""
+    from test_gpu_parity import _streamer_small
+    cfg = _streamer_small(precision="fp32", gmg_rtol=1e-10)
+    probe = itk.Sim(cfg, precision="fp32")
+    probe.seed()
+    n0 = probe.diagnostics()["n_particles"]
+    del probe
+    g = itk.Sim(cfg, precision="fp32", max_particles=n0 + 400)
+    g.seed()
+    assert g.step_rc(12) == itk.OK
+    with pytest.raises(itk.ItokmcError) as err:
+        g.diagnostics()
+    assert err.value.code == itk.ECAPACITY
+    d = g.diagnostics(check=False)
+    assert d["overflow"] & 1 and d["merged_cells"] > 0
+    cell, off, w, ids = g.particles()
+    assert len(cell) > 0 and cell.max() < np.prod(cfg["grid"])
+    assert np.all(off >= 0) and np.all(off < 1) and np.all(w > 0)
+    assert len(np.unique(ids)) == len(ids)
+
+
 def test_ensemble_empty_and_ragged(itk):
     """An ensemble step with no realizations; a realization with no electrons; a ragged
     grid (33 x 17 x 9 = 5049 cells: one full 4096-cell block and a partial one) alone
