@@ -60,10 +60,26 @@ def test_fused_matches_kernel_sequence_fp32(itk, fused):
     _assert_same(_ens_state(ens, slots[2], cfgs[2]["grid"]), _plain_state(_run_plain(itk, cfgs[2])))
 
 
-def test_fused_matches_kernel_sequence_fp64(itk):
-    print("fused fp64 W=1", flush=True)
+@pytest.mark.parametrize("fused", (1, 4))
+def test_fused_matches_kernel_sequence_fp64(itk, fused):
+    print(f"fused fp64 W={fused}", flush=True)
     cfgs = _small_realizations(4, steps=30, seed=9, precision="fp64")
-    _same_runs(_run(itk, cfgs, 0, precision="fp64"), _run(itk, cfgs, 1, precision="fp64"), cfgs)
+    _same_runs(_run(itk, cfgs, 0, precision="fp64"), _run(itk, cfgs, fused, precision="fp64"), cfgs)
+
+
+def test_fused_empty_pool_then_admission(itk):
+    """Fused steps of an ensemble with no realizations (nothing to push, no scan tiles),
+    then a realization admitted into it runs as its plain context does."""
+    print("fused empty pool W=2", flush=True)
+    ens = _new_ensemble(itk, slots=2, cells=1 << 20, particles=400_000)
+    ens.set_tuning(fused_per_cu=2)
+    ens.step(3)
+    assert ens.poll() == []
+    cfg = _small_realizations(1, steps=25, seed=41)[0]
+    s = ens.admit(cfg)
+    done = _drain(ens)
+    assert done[s][2] == 25
+    _assert_same(_ens_state(ens, s, cfg["grid"]), _plain_state(_run_plain(itk, cfg)))
 
 
 def test_fused_without_graph(itk):
