@@ -67,7 +67,7 @@ def parse():
     p.add_argument("--poisson-frac", type=float, default=0.004)
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--drain", type=float, default=60.0)
-    p.add_argument("--poisson-workers", type=int, default=4)
+    p.add_argument("--poisson-workers", type=int, default=8)
     p.add_argument("--reactor-frac", type=float, default=0.0,
                    help="served workload: share of zero-dimensional reactor requests")
     p.add_argument("--copy-calibration", action="store_true",
