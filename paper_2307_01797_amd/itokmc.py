@@ -21,7 +21,7 @@ KMC_HYBRID, KMC_PURE_TAU = 0, 1
 SEED_GAUSSIAN, SEED_NEUTRAL = 0, 1
 (Q_NGP_WEIGHT, Q_NPLUS, Q_NMINUS, Q_NGAMMA, Q_CIC_DENSITY, Q_PHI, Q_EX, Q_EY, Q_EZ, Q_FIRES,
  Q_RHO) = range(11)
-OVF_PARTICLES, OVF_MERGE = 1, 2
+OVF_PARTICLES, OVF_MERGE, OVF_BARRIER = 1, 2, 4
 
 EXPORTS = ["itokmc_arena_bytes", "itokmc_init_grid", "itokmc_set_coefficients",
            "itokmc_check_coefficients",
