@@ -414,6 +414,27 @@ __device__ __forceinline__ void tbl_add(uint32_t* keys, typename DepAcc<T>::S* v
   if (b != 0.0) atomicAdd(&g1[node], A::enc1(b));
 }
 
+// tbl_add for one field and an already encoded (fixed-point) value.
+template <int F, int L2>
+__device__ __forceinline__ void tbl_add_enc(uint32_t* keys, unsigned long long* v,
+                                            uint32_t node, uint32_t h, unsigned long long e,
+                                            unsigned long long* g) {
+  constexpr uint32_t mask = (1u << L2) - 1u;
+  for (int probe = 0; probe < kDepProbes; ++probe) {
+    uint32_t k = keys[h];
+    if (k == kEmptyKey) {
+      const uint32_t prev = atomicCAS(&keys[h], kEmptyKey, node);
+      k = prev == kEmptyKey ? node : prev;
+    }
+    if (k == node) {
+      atomicAdd(&v[h], e);
+      return;
+    }
+    h = (h + 1u) & mask;
+  }
+  atomicAdd(&g[node], e);
+}
+
 template <typename T, int L2>
 __device__ __forceinline__ void tbl_cic(uint32_t* keys, typename DepAcc<T>::S* v0,
                                         typename DepAcc<T>::S* v1, const StepConst& K, int i0,
@@ -459,6 +480,56 @@ __device__ __forceinline__ void tbl_tsc(uint32_t* keys, typename DepAcc<T>::S* v
   }
 }
 
+// Single precision, TSC shape, one particle per lane (all lanes present; inactive lanes
+// contribute nothing).  The lanes of a wavefront hold consecutive, cell-sorted
+// particles, and the 27 nodes of a particle depend only on its cell indices j (before
+// wall clamping) along the three axes, so the lanes of a run of equal j share them.
+// Each node's fixed-point contributions (exact integers: their sum does not depend on
+// the order) are summed over every run with a segmented scan, and only the run's last
+// lane inserts the sum: a third of the table atomics when cells hold three particles.
+// F: 0 conductivity (enc0, v0/g0), 1 electron number (enc1, v1/g1).
+template <int F, int L2>
+__device__ __forceinline__ void tbl_tsc_runs(uint32_t* keys, unsigned long long* v0,
+                                             unsigned long long* v1, const StepConst& K,
+                                             const Tsc<float>& s, bool active, int jx, int jy,
+                                             int jz, double q, unsigned long long* g0,
+                                             unsigned long long* g1) {
+  using A = DepAcc<float>;
+  const int lane = lane_id();
+  // run key: the three cell indices, each biased into 21 bits (an index off the grid by
+  // up to 2^20 cells still has a key of its own); inactive lanes all differ from it
+  const uint64_t key = active ? ((uint64_t)(uint32_t)(jx + (1 << 20)) << 42) |
+                                    ((uint64_t)(uint32_t)(jy + (1 << 20)) << 21) |
+                                    (uint64_t)(uint32_t)(jz + (1 << 20))
+                              : ~0ull;
+  const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+  const uint32_t plo = dpp_from_prev(klo, ~klo), phi = dpp_from_prev(khi, ~khi);
+  const uint32_t nlo = dpp_from_next(klo, ~klo), nhi = dpp_from_next(khi, ~khi);
+  const uint32_t head = (plo != klo || phi != khi) ? 1u : 0u;
+  const bool tail = active && (lane == 63 || nlo != klo || nhi != khi);
+  const uint64_t zid[1] = {0ull};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const uint32_t row = (uint32_t)s.iy[b] + (uint32_t)K.ny * (uint32_t)s.iz[c];
+      const uint32_t hr = (row * 2654435761u) >> (32 - L2);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float wt = (s.wx[a] * s.wy[b]) * s.wz[c];
+        const double x = q * (double)wt;
+        uint64_t v[1] = {active && x != 0.0 ? (F == 0 ? A::enc0(x) : A::enc1(x)) : 0ull};
+        (void)seg_scan(v, head, zid, [](int, uint64_t u, uint64_t w) { return u + w; });
+        if (tail && v[0] != 0ull) {
+          const uint32_t node = (uint32_t)s.ix[a] + (uint32_t)K.nx * row;
+          const uint32_t h = ((uint32_t)s.ix[a] + hr) & ((1u << L2) - 1u);
+          tbl_add_enc<F, L2>(keys, F == 0 ? v0 : v1, node, h, v[0], F == 0 ? g0 : g1);
+        }
+      }
+    }
+  }
+}
+
 // Single precision: at least 7 waves per SIMD (72 VGPRs, no spills), which measured about
 // 3% faster than the compiler's 75 VGPRs and 6 waves in a side-by-side run on the same
 // state; 8 waves spill and are slower.  Double precision keeps the compiler's choice (a
@@ -487,8 +558,46 @@ __global__ void __launch_bounds__(256, SH == 0 ? kDepMinWaves<T> : 1) k_field_de
     }
     __syncthreads();
     const uint32_t c1 = min(c0 + chunk, n);
-    for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-      const uint32_t w = a.w[i];
+    for (uint32_t ib = c0; ib < c1; ib += blockDim.x) {  // the same trip count in every thread
+      const uint32_t i = ib + threadIdx.x;
+      const uint32_t w = i < c1 ? a.w[i] : 0u;
+      if constexpr (SH == 1 && sizeof(T) == 4) {
+        // every lane takes part in the run sums (inactive: weight 0)
+        const bool act = w != 0u;
+        Tsc<T> sk{}, sd{};
+        int jk[3] = {0, 0, 0}, jd[3] = {0, 0, 0};
+        double qa = 0.0;
+        if (act) {
+          const uint32_t cell = a.cell[i];
+          int ci, cj, ck;
+          cell_ijk(cell, K, ci, cj, ck);
+          const T o[3] = {tp<T>(a.ox)[i], tp<T>(a.oy)[i], tp<T>(a.oz)[i]};
+          sk = tsc_at<T>(K, ci, cj, ck, o[0], o[1], o[2]);
+          jk[0] = ci; jk[1] = cj; jk[2] = ck;
+          if (mode != 0) {
+            T e[3];
+            tsc_get3<T>(ctp<T>(E4), K, sk, e);
+            const T Em = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+            const T mu = Mob<T>::mu(co, Em);
+            mu_out[i] = mu;
+            qa = (double)mu * (double)w;
+            const uint64_t id = a.id[i];
+            const uint4 r = philox_block((uint32_t)id, (uint32_t)(id >> 32), K.step, TAG_PUSH, 0, K.key);
+            T nr[3];
+            NormalsF<T>::get(r, nr);
+            const T t[3] = {o[0] + diff * nr[0], o[1] + diff * nr[1], o[2] + diff * nr[2]};
+            sd = tsc_at<T>(K, ci, cj, ck, t[0], t[1], t[2]);
+            jd[0] = ci + (int)floor(t[0]); jd[1] = cj + (int)floor(t[1]); jd[2] = ck + (int)floor(t[2]);
+          }
+        }
+        if (mode == 0) {
+          tbl_tsc_runs<1, L2>(keys, v0, v1, K, sk, act, jk[0], jk[1], jk[2], (double)w, sig, ne);
+        } else {
+          tbl_tsc_runs<0, L2>(keys, v0, v1, K, sk, act, jk[0], jk[1], jk[2], qa, sig, ne);
+          tbl_tsc_runs<1, L2>(keys, v0, v1, K, sd, act, jd[0], jd[1], jd[2], (double)w, sig, ne);
+        }
+        continue;
+      }
       if (!w) continue;
       const uint32_t cell = a.cell[i];
       int ci, cj, ck;
