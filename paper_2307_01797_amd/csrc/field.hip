@@ -274,34 +274,44 @@ __device__ __forceinline__ void tsc_get3(const T* E4, const StepConst& K, const 
   out[2] = acc[2];
 }
 
-// Ion charge (units of e) that cell (i, j, k) receives with the TSC shape: the immobile
-// ions are point charges at their cell centres, so along each axis a cell keeps 3/4 of
-// its own and takes 1/8 of each neighbour's, and a wall cell also keeps the 1/8 that
-// would fall outside.  Every term is an integer times a multiple of 1/512: the sum is
-// exact in double, in any order.
-__device__ __forceinline__ double tsc_keep(int i, int n) {
-  return 0.75 + (i == 0 ? 0.125 : 0.0) + (i == n - 1 ? 0.125 : 0.0);
+// Ion charge (units of e) that cell (i, j, k) receives with the TSC shape: the ions are
+// point charges at their cell centres, so along each axis a cell keeps 3/4 of its own
+// and takes 1/8 of each neighbour's, and a wall cell also keeps the 1/8 that would fall
+// outside.  Every weight is a multiple of 1/512, so the sum is formed in integers: per
+// axis the weights in eighths (the cell 6, plus 1 for each wall it touches; each
+// neighbour 1, or 0 past a wall), summed along x for each of the nine rows and the rows
+// then weighted by y and z.  The total is exact (|total| < 2^53) and so is its scaling
+// by 2^-9: the same double as the 27-term sum in any order.
+__device__ __forceinline__ void tsc_ion_axis(int c, int n, int w[3], int idx[3]) {
+  w[0] = c > 0 ? 1 : 0;
+  w[1] = 6 + (c == 0 ? 1 : 0) + (c == n - 1 ? 1 : 0);
+  w[2] = c < n - 1 ? 1 : 0;
+  idx[0] = c > 0 ? c - 1 : c;  // a tap past the wall reads the cell itself, weight 0
+  idx[1] = c;
+  idx[2] = c < n - 1 ? c + 1 : c;
 }
 __device__ __forceinline__ double ion_tsc(const uint32_t* np, const uint32_t* nm, int i, int j, int k,
                                           int nx, int ny, int nz) {
-  double acc = 0.0;
-  for (int dk = -1; dk <= 1; ++dk) {
-    const int kk = k + dk;
-    if (kk < 0 || kk >= nz) continue;
-    const double wz = dk ? 0.125 : tsc_keep(k, nz);
-    for (int dj = -1; dj <= 1; ++dj) {
-      const int jj = j + dj;
-      if (jj < 0 || jj >= ny) continue;
-      const double wyz = (dj ? 0.125 : tsc_keep(j, ny)) * wz;
-      for (int di = -1; di <= 1; ++di) {
-        const int ii = i + di;
-        if (ii < 0 || ii >= nx) continue;
-        const size_t c = (size_t)ii + (size_t)nx * ((size_t)jj + (size_t)ny * kk);
-        acc += ((double)np[c] - (double)nm[c]) * ((di ? 0.125 : tsc_keep(i, nx)) * wyz);
+  int wx[3], wy[3], wz[3], xi[3], yj[3], zk[3];
+  tsc_ion_axis(i, nx, wx, xi);
+  tsc_ion_axis(j, ny, wy, yj);
+  tsc_ion_axis(k, nz, wz, zk);
+  int64_t acc = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const size_t row = (size_t)nx * ((size_t)yj[b] + (size_t)ny * (size_t)zk[c]);
+      int64_t r = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t q = row + (size_t)xi[a];
+        r += (int64_t)wx[a] * ((int64_t)np[q] - (int64_t)nm[q]);
       }
+      acc += (int64_t)(wy[b] * wz[c]) * r;
     }
   }
-  return acc;
+  return (double)acc * 0x1p-9;
 }
 
 template <typename T> struct Mob;
