@@ -517,6 +517,9 @@ __device__ __forceinline__ void tbl_tsc_runs(uint32_t* keys, unsigned long long*
   const uint32_t nlo = dpp_from_next(klo, ~klo), nhi = dpp_from_next(khi, ~khi);
   const uint32_t head = (plo != klo || phi != khi) ? 1u : 0u;
   const bool tail = active && (lane == 63 || nlo != klo || nhi != khi);
+  // no run of two or more in the wavefront (sparse cells): every lane inserts its own
+  // contributions, as without the run sums, and the scans are skipped
+  const bool runs = __ballot(active && lane > 0 && head == 0u) != 0ull;
   const uint64_t zid[1] = {0ull};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -529,7 +532,7 @@ __device__ __forceinline__ void tbl_tsc_runs(uint32_t* keys, unsigned long long*
         const float wt = (s.wx[a] * s.wy[b]) * s.wz[c];
         const double x = q * (double)wt;
         uint64_t v[1] = {active && x != 0.0 ? (F == 0 ? A::enc0(x) : A::enc1(x)) : 0ull};
-        (void)seg_scan(v, head, zid, [](int, uint64_t u, uint64_t w) { return u + w; });
+        if (runs) (void)seg_scan(v, head, zid, [](int, uint64_t u, uint64_t w) { return u + w; });
         if (tail && v[0] != 0ull) {
           const uint32_t node = (uint32_t)s.ix[a] + (uint32_t)K.nx * row;
           const uint32_t h = ((uint32_t)s.ix[a] + hr) & ((1u << L2) - 1u);
