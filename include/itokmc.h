@@ -463,7 +463,10 @@ int itokmc_ensemble_set_tuning(itokmc_ens* ens, const itokmc_ens_tuning* tuning)
 int itokmc_ensemble_get_tuning(itokmc_ens* ens, itokmc_ens_tuning* tuning);
 /* Pick the launch shapes by timing candidate shapes on the live ensemble: each trial
  * is a real ensemble step (results are unchanged), candidates are interleaved over
- * rounds; the fastest is kept.  best_ms: its mean step time. */
+ * rounds; the fastest is kept.  Coordinates in turn: the particle kernels' block and
+ * blocks per compute unit, the KMC block, the coupling grid, then the form of the step
+ * (the kernel sequence, or the fused kernel at each budget the device keeps resident).
+ * best_ms: the kept shape's mean step time. */
 int itokmc_ensemble_autotune(itokmc_ens* ens, uint32_t rounds, itokmc_ens_tuning* best,
                              double* best_ms);
 void itokmc_ensemble_destroy(itokmc_ens* ens);
