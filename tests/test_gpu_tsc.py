@@ -127,3 +127,40 @@ def test_tsc_run_is_reproducible(itk):
         out.append(by_id(ids, cell, off, w) + (g.field(),))
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-6)])
+def test_ragged_walls_many_per_cell(itk, orc, prec, tol):
+    """TSC on a 13 x 11 x 9 grid with clusters of particles in cells on every wall and
+    corner (runs of equal cells in the wavefronts, clamped and folded nodes) and random
+    ion counts: one transport, the potential against the oracle's from the same state,
+    and the charge-density query exact to rounding."""
+    grid = (13, 11, 9)
+    cfg = _streamer_small(grid=grid, shape="tsc", precision=prec, n_ppc=0, gmg_rtol=1e-12)
+    rng = np.random.default_rng(29)
+    nx, ny, nz = grid
+    cells = []
+    for i in (0, nx // 2, nx - 1):
+        for j in (0, ny // 2, ny - 1):
+            for k in (0, nz // 2, nz - 1):
+                cells += [i + nx * (j + ny * k)] * int(rng.integers(1, 9))
+    cells = np.sort(np.array(cells, dtype=np.int64))
+    n = len(cells)
+    off = rng.random((n, 3))
+    w = rng.integers(1, 2000, n).astype(np.uint32)
+    ids = np.arange(1, n + 1, dtype=np.uint64) * 7919
+    g = itk.Sim(cfg, precision=prec, max_particles=4 * n)
+    g.set_particles(cells, off, w, ids)
+    nc = nx * ny * nz
+    p = rng.integers(0, 3000, nc) * (rng.random(nc) < 0.3)
+    m = rng.integers(0, 300, nc) * (rng.random(nc) < 0.3)
+    g.set_counts("plus", p.astype(np.uint32))
+    g.set_counts("minus", m.astype(np.uint32))
+    o = _oracle_from_gpu(orc, cfg, g)
+    rho_o = o.charge_density()
+    scale = 1.602176634e-19 * np.abs(o.cic_density()).max()
+    assert np.abs(g.deposit("rho") - rho_o).max() <= 1e-12 * max(scale, np.abs(rho_o).max())
+    g.transport(cfg["dt"])
+    o.transport(cfg["dt"])
+    phi_g, phi_o = g.field(), o.field()[0]
+    assert np.abs(phi_g - phi_o).max() <= tol * np.abs(phi_o).max()
